@@ -1,0 +1,153 @@
+"""FP64 CPU oracle for the contrast-maximization loss and its gradient.
+
+TEST INFRASTRUCTURE ONLY.  Imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg; never by the product path.  The arithmetic lives
+in ``cm_oracle.c`` (plain C, FP64, no code shared with the GPU library); this
+module builds and loads it and marshals numpy arrays.
+
+Paper: Sec. 3.1 (iterative warp, Eq. 1, bilinear splatting, active-pixel
+normalisation and out-of-image masking), Sec. 3.2 (Eq. 2, flow from depth and
+ego-motion), Sec. 3.3 (per-event forward, analytic backward).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cm_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libcm_oracle.so")
+_lib = None
+
+# -O2, no fast-math, no FMA contraction: every FP64 operation is the one written.
+GCC_FLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def build() -> str:
+    """Compile the oracle library in place (always recompiles)."""
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc"] + GCC_FLAGS + [_SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    lib.cmo_flow_field.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P]
+    lib.cmo_flow_field.restype = ctypes.c_int
+    lib.cmo_forward.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double,
+                                ctypes.c_int64, P, P, P, P, P, P, P, P, P, P]
+    lib.cmo_forward.restype = ctypes.c_int
+    lib.cmo_backward.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double,
+                                 ctypes.c_int64, P, P, P, P, P, P, ctypes.c_double, P, P, P]
+    lib.cmo_backward.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    """Widen to FP64 (exact for FP32 data)."""
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _window_args(win, rho=None, theta=None):
+    """The window's arrays as the oracle takes them.  FP32 fields (the form the
+    GPU library reads) widen exactly; FP64 arrays pass through unchanged so
+    that finite-difference tests can perturb below FP32 resolution."""
+    rho = _f64(win.rho if rho is None else rho)
+    theta = _f64(win.theta if theta is None else theta)
+    K = _f64([_as_f(win.fx), _as_f(win.fy), _as_f(win.cx), _as_f(win.cy)])
+    refs = _f64(win.refs)
+    x, y, t = _f64(win.x), _f64(win.y), _f64(win.t)
+    p = np.ascontiguousarray(np.asarray(win.p, dtype=np.int8))
+    return K, refs, x, y, t, p, rho, theta
+
+
+def _as_f(v):
+    """Scalars of the window descriptor are FP32 on the GPU side."""
+    return float(np.float32(v)) if not isinstance(v, np.float64) else float(v)
+
+
+def _eps(win):
+    return ctypes.c_double(_as_f(win.eps))
+
+
+def flow_field(width, height, K, rho, theta) -> np.ndarray:
+    """Eq. 2 (first order): flow [H, W, 2] in px per window."""
+    lib = _load()
+    K = _f64(K)
+    rho = _f64(rho)
+    theta = _f64(theta)
+    u = np.empty((height, width, 2), dtype=np.float64)
+    st = lib.cmo_flow_field(width, height, _ptr(K), _ptr(rho), _ptr(theta), _ptr(u))
+    if st != 0:
+        raise ValueError(f"cmo_flow_field failed ({st})")
+    return u
+
+
+def forward(win, rho=None, theta=None, images=False, valid=False, positions=False) -> dict:
+    """Loss and per-reference terms of Eq. 1 for one window.
+
+    Returns dict(loss, num[R], nact[R]) and optionally
+    images [R, 2 pol, 2 (C,S), H, W], valid [n] bool, positions [n, R, 2]."""
+    lib = _load()
+    K, refs, x, y, t, p, rho, theta = _window_args(win, rho, theta)
+    R = refs.shape[0]
+    n = x.shape[0]
+    out = np.zeros(1 + 2 * R, dtype=np.float64)
+    img = np.zeros((R, 2, 2, win.height, win.width), dtype=np.float64) if images else None
+    val = np.zeros(n, dtype=np.uint8) if valid else None
+    pos = np.zeros((n, R, 2), dtype=np.float64) if positions else None
+    st = lib.cmo_forward(win.width, win.height, _ptr(K), R, _ptr(refs), _eps(win),
+                         n, _ptr(x), _ptr(y), _ptr(t), _ptr(p), _ptr(rho), _ptr(theta), _ptr(out),
+                         _ptr(img), _ptr(val), _ptr(pos))
+    if st != 0:
+        raise ValueError(f"cmo_forward failed ({st})")
+    res = dict(loss=float(out[0]), num=out[1:1 + R].copy(), nact=out[1 + R:].copy())
+    if images:
+        res["images"] = img
+    if valid:
+        res["valid"] = val.astype(bool)
+    if positions:
+        res["positions"] = pos
+    return res
+
+
+def loss(win, rho=None, theta=None) -> float:
+    return forward(win, rho, theta)["loss"]
+
+
+def backward(win, rho=None, theta=None, grad_loss: float = 1.0, flow_grad=False) -> dict:
+    """Gradient of the loss: dict(drho [H, W], dtheta [6]) (+ dflow [H, W, 2])."""
+    lib = _load()
+    K, refs, x, y, t, p, rho, theta = _window_args(win, rho, theta)
+    R = refs.shape[0]
+    n = x.shape[0]
+    drho = np.zeros((win.height, win.width), dtype=np.float64)
+    dth = np.zeros(6, dtype=np.float64)
+    dflow = np.zeros((win.height, win.width, 2), dtype=np.float64) if flow_grad else None
+    st = lib.cmo_backward(win.width, win.height, _ptr(K), R, _ptr(refs), _eps(win),
+                          n, _ptr(x), _ptr(y), _ptr(t), _ptr(p), _ptr(rho), _ptr(theta),
+                          ctypes.c_double(grad_loss), _ptr(drho), _ptr(dth), _ptr(dflow))
+    if st != 0:
+        raise ValueError(f"cmo_backward failed ({st})")
+    res = dict(drho=drho, dtheta=dth)
+    if flow_grad:
+        res["dflow"] = dflow
+    return res
