@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Throughput of the contrast-maximization loss forward + backward on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c5]
+
+One step is one pass of the whole path over one window: forward (clear, warp +
+splat, reduce, loss) and backward (clear, recompute + adjoint, d ego), through
+the C ABI with buffers allocated once; inputs are resident in HBM before the
+timed region.  Prints one JSON line.  Inputs are seeded synthetic windows
+(edge maps under rigid camera motion, see eventgen).
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "events/sec for CM loss fwd+bwd (batched vs plain); p50/p99 per-window latency"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "c1": "c1: 64x64 f=50, 2k uniform events, refs {1}, fwd+bwd",
+    "c2": "c2: 640x480 f=300, 100k edge-map events (50 segments), refs {0,0.5,1}, fwd+bwd",
+    "c5": "c5: 1280x720 f=600, 2M edge-map events (400 segments), 8 refs in [0,1], fwd+bwd",
+}
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2412_06359_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(phase: str, n: int, HW: int, R: int) -> float:
+    """Bytes a phase must move at minimum for one window.
+
+    events: 13 B each (x, y, t FP32 + p int8); rho: 4 B per pixel; splat images:
+    C and S FP64 per pixel, polarity and reference (32 R B per pixel); d rho 4 B
+    per pixel."""
+    ev = 13.0 * n
+    rho = 4.0 * HW
+    img = 32.0 * R * HW
+    return {
+        "zero": img,
+        "splat": ev + rho + img,
+        "reduce": img,
+        "finalize": 0.0,
+        "grad_zero": 4.0 * HW,
+        "adjoint": ev + rho + img + 4.0 * HW,
+        "grad_finalize": 0.0,
+    }[phase]
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha") != kernel_source_sha():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(win, seconds: float) -> dict:
+    import oracle
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.forward(win)
+        oracle.backward(win)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": reps * win.n / el, "unit": "events/s", "cores": 1, "kind": "oracle",
+            "sample": f"{win.name} window ({win.n} events, R={len(win.refs)}), FP64 oracle "
+                      f"forward+backward, {reps} repetitions in {el:.1f} s, single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); windows are "
+              f"independent and shard across GPUs with no exchange, see the design notes",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import eventgen
+    import paper_2412_06359_amd as cm
+
+    cm.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    win = eventgen.make_window(args.workload)
+    desc = cm.WindowDesc.from_window(win)
+    f32 = lambda a: torch.as_tensor(a, dtype=torch.float32).contiguous().to(dev)
+    x, y, t = f32(win.x), f32(win.y), f32(win.t)
+    p = torch.as_tensor(win.p, dtype=torch.int8).contiguous().to(dev)
+    rho, ego = f32(win.rho), f32(win.theta)
+    state = torch.empty(cm.state_bytes(desc), dtype=torch.uint8, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    g_loss = torch.ones(1, dtype=torch.float32, device=dev)
+    g_rho = torch.empty_like(rho)
+    g_ego = torch.empty(6, dtype=torch.float32, device=dev)
+
+    def step():
+        cm.forward(desc, x, y, t, p, rho, ego, state=state, loss=loss)
+        cm.backward(desc, x, y, t, p, rho, ego, state, g_loss, grad_rho=g_rho, grad_ego=g_ego)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = e0.elapsed_time(e1) / args.steps
+    n_valid = cm.diagnostics(desc, state)["n_valid"]
+
+    # second timed region with per-kernel HIP events on the launch stream
+    cm.profile_enable(0, True)
+    cm.profile_read(0)
+    for _ in range(args.steps):
+        step()
+    phases = cm.profile_read(0)
+    cm.profile_enable(0, False)
+    per_launch = {k: (ms / max(c, 1), c) for k, (ms, c) in phases.items()}
+    dom = max(per_launch, key=lambda k: per_launch[k][0])
+    dom_ms = per_launch[dom][0]
+    HW = win.width * win.height
+    R = len(win.refs)
+    alg = algorithmic_bytes(dom, win.n, HW, R)
+    achieved = alg / (dom_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, dom)
+
+    out = {
+        "metric": METRIC,
+        "value": win.n / (ms_per_step * 1e-3),
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "path": "plain (one window per call)",
+                   "sensor": f"{win.width}x{win.height}", "n_events": win.n, "refs": R,
+                   "valid_fraction": n_valid / max(win.n, 1), "mode": "atomic",
+                   "inputs": "FP32 events/rho/ego, FP64 warp and splat images"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": alg, "avg_launch_ms": dom_ms},
+        "phases_ms_per_launch": {k: v[0] for k, v in per_launch.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(win, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,156 @@
+/*
+ * cmloss.h -- C ABI of the MI355X (gfx950) contrast-maximization loss library.
+ *
+ * The library computes the multi-reference contrast-maximization (CM) loss of
+ * one or many windows of events and its gradient with respect to per-pixel
+ * inverse depth and 6-DoF ego-motion, entirely in HIP kernels.
+ *
+ * Paper (arXiv 2412.06359): the loss is Eq. 1 of Sec. 3.1 (iterative warp of
+ * every event to all reference times, bilinear splatting into per-polarity
+ * images of warped events, active-pixel normalisation, masking of events that
+ * leave the image); the flow comes from inverse depth and ego-motion through
+ * Eq. 2 of Sec. 3.2 (taken in its first-order, motion-field form); the
+ * gradient is the analytic backward of Sec. 3.3.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pixel centres sit at integer coordinates; the image domain is the closed
+ *    box [0, width-1] x [0, height-1].  Row-major images: pixel (x, y) is at
+ *    index y * width + x.
+ *  - Events are structure-of-arrays in device memory: x, y, t float32, p int8
+ *    (p > 0 positive polarity, anything else negative).  t is the timestamp
+ *    normalised to the window, expected in [0, 1].
+ *  - inv_depth: float32 [height * width] device array, rho = 1/depth (any
+ *    common scale, Eq. 2 fixes depth only up to scale).
+ *  - ego: float32 [6] device array (v_x, v_y, v_z, w_x, w_y, w_z): translation
+ *    and rotation (exponential coordinates) of the camera over the window;
+ *    flow is in pixels per window.
+ *  - Loss: L = (1/R) sum_r [sum_x sum_p (S_p/(C_p+eps))^2] / (N_r + eps), with
+ *    C_p / S_p the bilinear splat of the surviving events' weights / weights
+ *    times (1 - |r - t_k|), and N_r the number of pixels with C_+ + C_- > 0.
+ *  - Memory: the caller allocates every buffer (device memory for all arrays
+ *    unless stated otherwise); the library never frees caller memory.  The
+ *    handle owns nothing that a call writes, so calls on different streams
+ *    with different state buffers may overlap.
+ *  - Streams: every call is asynchronous on `stream` (a hipStream_t; NULL is
+ *    the null stream).  No host synchronisation happens inside a call.
+ *  - Errors: every function returns a cm_status and never aborts.  Invalid
+ *    arguments detected on the host return CM_ERR_INVALID_ARG with nothing
+ *    enqueued.  Data errors in device arrays are not reported: an event with a
+ *    non-finite coordinate, a timestamp outside [0, 1] or a start position off
+ *    the image is masked like an event that leaves the image.
+ */
+#ifndef CMLOSS_H
+#define CMLOSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cm_handle_s* cm_handle;
+
+typedef enum {
+    CM_OK = 0,
+    CM_ERR_INVALID_ARG = -1,
+    CM_ERR_OOM = -2,
+    CM_ERR_HIP = -3,
+    CM_ERR_UNSUPPORTED = -4,
+    CM_ERR_BUDGET = -5
+} cm_status;
+
+/* Splat modes.  ATOMIC: floating-point atomics, results vary in the last bits
+ * from run to run.  DETERMINISTIC: a sort of the splat contributions by pixel
+ * followed by a fixed-order reduction; bit-identical from run to run. */
+enum { CM_MODE_ATOMIC = 0, CM_MODE_DETERMINISTIC = 1 };
+
+#define CM_MAX_REFS 16
+
+/* One window's geometry and loss settings (host memory). */
+typedef struct {
+    int32_t width, height;          /* sensor size, > 0 */
+    float fx, fy, cx, cy;           /* pinhole intrinsics, fx, fy > 0 */
+    int32_t n_refs;                 /* R, 1 <= R <= CM_MAX_REFS */
+    float refs[CM_MAX_REFS];        /* reference times, strictly increasing, in [0, 1] */
+    int32_t mode;                   /* CM_MODE_* */
+    float eps;                      /* regulariser of Eq. 1's ratios, finite and > 0 (1e-9 by default) */
+} cm_window_desc;
+
+/* Create a handle bound to HIP device `device`.  *h receives the handle. */
+cm_status cm_create(cm_handle* h, int device);
+
+/* Destroy a handle (NULL is accepted).  No call may be in flight on it. */
+cm_status cm_destroy(cm_handle h);
+
+/* Human-readable name of a status code (static string). */
+const char* cm_status_string(cm_status s);
+
+/* Bytes of the per-window `state` buffer: the splatted images C and S per
+ * reference and polarity (32 * R * width * height bytes, FP64) plus
+ * per-reference sums and the reduction scratch.  0 if `d` is invalid. */
+size_t cm_state_bytes(const cm_window_desc* d);
+
+/* Forward (paper Sec. 3.1 Eq. 1 with Sec. 3.2 Eq. 2; Sec. 3.3 per-event
+ * forward).
+ *   ev_x, ev_y, ev_t, ev_p : n_events events (device; may be NULL if n_events == 0)
+ *   inv_depth, ego         : as above (device)
+ *   loss                   : float32 [1] (device), receives L
+ *   state                  : cm_state_bytes(d) bytes (device), written; the
+ *                            backward reads it, so keep it and the inputs
+ *                            unchanged until the backward has run.
+ * n_events == 0 gives L = 0. */
+cm_status cm_loss_forward(cm_handle h, const cm_window_desc* d,
+                          const float* ev_x, const float* ev_y, const float* ev_t,
+                          const int8_t* ev_p, int64_t n_events,
+                          const float* inv_depth, const float* ego,
+                          float* loss, void* state, void* stream);
+
+/* Backward (paper Sec. 3.3: analytic gradient; here the exact adjoint of the
+ * forward with the active-pixel count and the event mask held fixed, computed
+ * by re-running each event's warp instead of storing it).
+ *   state          : the buffer the forward wrote for the same inputs; its
+ *                    scratch tail is overwritten, the images are only read.
+ *   grad_loss      : float32 [1] (device), dOut/dL from the caller
+ *   grad_inv_depth : float32 [height * width] (device), overwritten with
+ *                    grad_loss * dL/d(inv_depth)
+ *   grad_ego       : float32 [6] (device), overwritten with grad_loss * dL/d(ego) */
+cm_status cm_loss_backward(cm_handle h, const cm_window_desc* d,
+                           const float* ev_x, const float* ev_y, const float* ev_t,
+                           const int8_t* ev_p, int64_t n_events,
+                           const float* inv_depth, const float* ego,
+                           void* state, const float* grad_loss,
+                           float* grad_inv_depth, float* grad_ego, void* stream);
+
+/* Diagnostics of the last forward on `state` (device -> host copy; this call
+ * synchronises `stream`).  out[0] = loss (FP64), out[1] = number of valid
+ * (unmasked) events, out[2 + r] = numerator of reference r, out[2 + R + r] =
+ * N_r.  `out` is host memory of 2 + 2R doubles. */
+cm_status cm_state_diagnostics(const cm_window_desc* d, const void* state, double* out,
+                               void* stream);
+
+/* Phase timing (diagnostics, not part of the method).  While enabled on a
+ * handle, each call records a pair of HIP events on its stream around every
+ * kernel it launches.  cm_profile_read waits for the recorded events, writes
+ * the accumulated milliseconds and launch counts per phase (host arrays of
+ * CM_N_PHASES entries) and clears them.  A handle that profiles must be used
+ * from one host thread at a time. */
+enum {
+    CM_PHASE_ZERO = 0,          /* clear the splat images (forward) */
+    CM_PHASE_SPLAT = 1,         /* warp + splat (forward) */
+    CM_PHASE_REDUCE = 2,        /* per-reference sums (forward) */
+    CM_PHASE_FINALIZE = 3,      /* loss (forward) */
+    CM_PHASE_GRAD_ZERO = 4,     /* clear d inv_depth (backward) */
+    CM_PHASE_ADJOINT = 5,       /* recompute warp + adjoint sweep (backward) */
+    CM_PHASE_GRAD_FINALIZE = 6, /* d ego (backward) */
+    CM_N_PHASES = 7
+};
+cm_status cm_profile_enable(cm_handle h, int enable);
+cm_status cm_profile_read(cm_handle h, double* ms, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CMLOSS_H */

@@ -1,0 +1,13 @@
+"""MI355X-native contrast-maximization loss (arXiv 2412.06359, Secs. 3.1-3.3).
+
+The loss and its gradient run in HIP kernels for gfx950 behind the C ABI of
+include/cmloss.h (libcmloss.so); this package is the thin Python binding.
+"""
+
+from .binding import (CM_MODE_ATOMIC, CM_MODE_DETERMINISTIC, PHASES, CMError, CMLoss, WindowDesc,
+                      backward, cm_loss, diagnostics, forward, handle, load, profile_enable,
+                      profile_read, state_bytes)
+
+__all__ = ["CM_MODE_ATOMIC", "CM_MODE_DETERMINISTIC", "CMError", "CMLoss", "WindowDesc",
+           "backward", "cm_loss", "diagnostics", "forward", "handle", "load", "profile_enable",
+           "profile_read", "state_bytes", "PHASES"]

@@ -1,0 +1,260 @@
+"""ctypes binding of libcmloss.so (include/cmloss.h) for torch tensors.
+
+Argument marshalling only: every step of the loss and its gradient runs in
+the library's HIP kernels.  PyTorch supplies device memory and the stream.
+There is no fallback: if the library is missing, every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import Optional, Sequence
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcmloss.so")
+
+CM_MAX_REFS = 16
+CM_MODE_ATOMIC = 0
+CM_MODE_DETERMINISTIC = 1
+
+_STATUS = {0: "CM_OK", -1: "CM_ERR_INVALID_ARG", -2: "CM_ERR_OOM", -3: "CM_ERR_HIP",
+           -4: "CM_ERR_UNSUPPORTED", -5: "CM_ERR_BUDGET"}
+
+
+class CMError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {_STATUS.get(status, status)}")
+        self.status = status
+
+
+class WindowDesc(ctypes.Structure):
+    """cm_window_desc: sensor, intrinsics, reference times, mode, eps."""
+
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("n_refs", ctypes.c_int32), ("refs", ctypes.c_float * CM_MAX_REFS),
+                ("mode", ctypes.c_int32), ("eps", ctypes.c_float)]
+
+    @classmethod
+    def make(cls, width: int, height: int, fx: float, fy: float, cx: float, cy: float,
+             refs: Sequence[float], mode: int = CM_MODE_ATOMIC, eps: float = 1e-9) -> "WindowDesc":
+        refs = [float(r) for r in refs]
+        if not 1 <= len(refs) <= CM_MAX_REFS:
+            raise ValueError(f"need 1..{CM_MAX_REFS} reference times, got {len(refs)}")
+        d = cls()
+        d.width, d.height = int(width), int(height)
+        d.fx, d.fy, d.cx, d.cy = fx, fy, cx, cy
+        d.n_refs = len(refs)
+        for i, r in enumerate(refs):
+            d.refs[i] = r
+        d.mode = int(mode)
+        d.eps = eps
+        return d
+
+    @classmethod
+    def from_window(cls, win, mode: int = CM_MODE_ATOMIC) -> "WindowDesc":
+        """From an object with width, height, fx, fy, cx, cy, refs, eps."""
+        return cls.make(win.width, win.height, win.fx, win.fy, win.cx, win.cy, list(win.refs),
+                        mode, getattr(win, "eps", 1e-9))
+
+    @property
+    def R(self) -> int:
+        return int(self.n_refs)
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def load() -> ctypes.CDLL:
+    """Load libcmloss.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2412_06359_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        D = ctypes.POINTER(WindowDesc)
+        i64 = ctypes.c_int64
+        lib.cm_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+        lib.cm_create.restype = ctypes.c_int
+        lib.cm_destroy.argtypes = [P]
+        lib.cm_destroy.restype = ctypes.c_int
+        lib.cm_status_string.argtypes = [ctypes.c_int]
+        lib.cm_status_string.restype = ctypes.c_char_p
+        lib.cm_state_bytes.argtypes = [D]
+        lib.cm_state_bytes.restype = ctypes.c_size_t
+        lib.cm_loss_forward.argtypes = [P, D, P, P, P, P, i64, P, P, P, P, P]
+        lib.cm_loss_forward.restype = ctypes.c_int
+        lib.cm_loss_backward.argtypes = [P, D, P, P, P, P, i64, P, P, P, P, P, P, P]
+        lib.cm_loss_backward.restype = ctypes.c_int
+        lib.cm_state_diagnostics.argtypes = [D, P, P, P]
+        lib.cm_state_diagnostics.restype = ctypes.c_int
+        lib.cm_profile_enable.argtypes = [P, ctypes.c_int]
+        lib.cm_profile_enable.restype = ctypes.c_int
+        lib.cm_profile_read.argtypes = [P, P, P]
+        lib.cm_profile_read.restype = ctypes.c_int
+        _lib = lib
+        return lib
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise CMError(status, what)
+
+
+_handles = {}
+
+
+def handle(device: int) -> ctypes.c_void_p:
+    """The library handle of a device (created once per process)."""
+    h = _handles.get(device)
+    if h is None:
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.cm_create(ctypes.byref(h), device), "cm_create")
+        _handles[device] = h
+    return h
+
+
+def state_bytes(desc: WindowDesc) -> int:
+    n = load().cm_state_bytes(ctypes.byref(desc))
+    if n == 0:
+        raise CMError(-1, "cm_state_bytes (invalid descriptor)")
+    return int(n)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_events(x, y, t, p):
+    n = x.numel()
+    for name, a, dt in (("x", x, torch.float32), ("y", y, torch.float32), ("t", t, torch.float32),
+                        ("p", p, torch.int8)):
+        if a.dtype != dt or a.dim() != 1 or a.numel() != n or not a.is_contiguous():
+            raise ValueError(f"event array {name}: need contiguous 1-D {dt} of length {n}")
+        if not a.is_cuda:
+            raise ValueError(f"event array {name} must be on a GPU")
+    return n
+
+
+def _check_params(desc, rho, ego):
+    if rho.dtype != torch.float32 or rho.numel() != desc.width * desc.height or \
+            not rho.is_contiguous() or not rho.is_cuda:
+        raise ValueError(f"inv_depth: need contiguous float32 GPU tensor of "
+                         f"{desc.height}x{desc.width} elements")
+    if ego.dtype != torch.float32 or ego.numel() != 6 or not ego.is_contiguous() or not ego.is_cuda:
+        raise ValueError("ego: need contiguous float32 GPU tensor of 6 elements")
+
+
+def forward(desc: WindowDesc, x, y, t, p, rho, ego, state: Optional[torch.Tensor] = None,
+            loss: Optional[torch.Tensor] = None):
+    """cm_loss_forward on torch's current stream.  Returns (loss [1], state)."""
+    n = _check_events(x, y, t, p)
+    _check_params(desc, rho, ego)
+    dev = rho.device
+    nbytes = state_bytes(desc)
+    if state is None:
+        state = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    elif state.numel() * state.element_size() < nbytes or not state.is_contiguous():
+        raise ValueError(f"state: need {nbytes} contiguous bytes")
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+    lib = load()
+    st = lib.cm_loss_forward(handle(dev.index), ctypes.byref(desc), _ptr(x), _ptr(y), _ptr(t),
+                             _ptr(p), n, _ptr(rho), _ptr(ego), _ptr(loss), _ptr(state),
+                             _stream(dev))
+    _check(st, "cm_loss_forward")
+    return loss, state
+
+
+def backward(desc: WindowDesc, x, y, t, p, rho, ego, state, grad_loss,
+             grad_rho: Optional[torch.Tensor] = None, grad_ego: Optional[torch.Tensor] = None):
+    """cm_loss_backward on torch's current stream.  Returns (grad_rho, grad_ego)."""
+    n = _check_events(x, y, t, p)
+    _check_params(desc, rho, ego)
+    dev = rho.device
+    if state.numel() * state.element_size() < state_bytes(desc):
+        raise ValueError("state buffer too small")
+    gl = grad_loss.reshape(1).to(device=dev, dtype=torch.float32).contiguous()
+    if grad_rho is None:
+        grad_rho = torch.empty_like(rho)
+    if grad_ego is None:
+        grad_ego = torch.empty(6, dtype=torch.float32, device=dev)
+    lib = load()
+    st = lib.cm_loss_backward(handle(dev.index), ctypes.byref(desc), _ptr(x), _ptr(y), _ptr(t),
+                              _ptr(p), n, _ptr(rho), _ptr(ego), _ptr(state), _ptr(gl),
+                              _ptr(grad_rho), _ptr(grad_ego), _stream(dev))
+    _check(st, "cm_loss_backward")
+    return grad_rho, grad_ego
+
+
+def diagnostics(desc: WindowDesc, state: torch.Tensor) -> dict:
+    """Per-window sums of the last forward (synchronises the stream)."""
+    R = desc.R
+    out = (ctypes.c_double * (2 + 2 * R))()
+    st = load().cm_state_diagnostics(ctypes.byref(desc), _ptr(state), out, _stream(state.device))
+    _check(st, "cm_state_diagnostics")
+    vals = list(out)
+    return dict(loss=vals[0], n_valid=int(vals[1]), num=vals[2:2 + R], nact=vals[2 + R:])
+
+
+PHASES = ("zero", "splat", "reduce", "finalize", "grad_zero", "adjoint", "grad_finalize")
+
+
+def profile_enable(device: int, enable: bool = True):
+    """Record HIP events around every kernel launched through this device's handle."""
+    _check(load().cm_profile_enable(handle(device), int(enable)), "cm_profile_enable")
+
+
+def profile_read(device: int) -> dict:
+    """{phase: (total_ms, launches)} since the last read (waits for the events)."""
+    n = len(PHASES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    _check(load().cm_profile_read(handle(device), ms, cnt), "cm_profile_read")
+    return {PHASES[i]: (ms[i], int(cnt[i])) for i in range(n)}
+
+
+class CMLoss(torch.autograd.Function):
+    """Contrast-maximization loss of one window; differentiable in inv_depth and ego.
+
+    forward(x, y, t, p, inv_depth, ego, desc) -> 0-d loss tensor
+    backward -> (None, None, None, None, d inv_depth, d ego, None), computed by
+    the library's adjoint kernels (the warp is recomputed, not stored).
+    """
+
+    @staticmethod
+    def forward(ctx, x, y, t, p, rho, ego, desc):
+        rho_c = rho.detach().contiguous()
+        ego_c = ego.detach().contiguous()
+        loss, state = forward(desc, x, y, t, p, rho_c, ego_c)
+        ctx.desc = desc
+        ctx.save_for_backward(x, y, t, p, rho_c, ego_c, state)
+        return loss.reshape(())
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        x, y, t, p, rho, ego, state = ctx.saved_tensors
+        g_rho, g_ego = backward(ctx.desc, x, y, t, p, rho, ego, state, grad_out)
+        return None, None, None, None, g_rho.reshape(rho.shape), g_ego.reshape(ego.shape), None
+
+
+def cm_loss(x, y, t, p, inv_depth, ego, desc: WindowDesc) -> torch.Tensor:
+    """Differentiable CM loss (see CMLoss)."""
+    return CMLoss.apply(x, y, t, p, inv_depth, ego, desc)

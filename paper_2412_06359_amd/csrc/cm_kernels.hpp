@@ -1,0 +1,109 @@
+// cm_kernels.hpp -- internal interface between the C ABI and the kernels.
+#pragma once
+
+#include <algorithm>
+#include <vector>
+#include <stdint.h>
+
+#include "cm_device.hpp"
+
+namespace cm {
+
+// Per-window sums written by the forward (device memory, inside `state`).
+struct StateHeader {
+    double loss;
+    unsigned long long n_valid;
+    double num[kMaxRefs];
+    double nact[kMaxRefs];
+};
+
+constexpr int kReduceBlocks = 256;     // reduce blocks per reference (max)
+constexpr int kBackwardBlocks = 4096;  // backward grid (max), grid-stride beyond
+constexpr size_t kScratchDoubles =
+    std::max<size_t>((size_t)kReduceBlocks * kMaxRefs * 2, (size_t)kBackwardBlocks * 6);
+
+struct EventPtrs {
+    const float* x;
+    const float* y;
+    const float* t;
+    const int8_t* p;
+    int64_t n;
+};
+
+struct StatePtrs {
+    double* img;           // [R][2][H*W][2] FP64
+    StateHeader* hdr;
+    double* scratch;       // kScratchDoubles
+    size_t zero_floats;    // floats to clear before a forward (images + header)
+};
+
+// Optional per-phase timing: HIP events recorded on the launch stream around
+// each kernel (see cm_profile_enable in include/cmloss.h).
+class Profiler {
+public:
+    bool enabled = false;
+    void begin(int phase, hipStream_t s)
+    {
+        Rec r{phase, get(), get()};
+        (void)hipEventRecord(r.a, s);
+        recs_.push_back(r);
+    }
+    void end(hipStream_t s) { (void)hipEventRecord(recs_.back().b, s); }
+    // Accumulates elapsed ms and counts per phase, then recycles the events.
+    hipError_t read(double* ms, int64_t* count, int n_phases)
+    {
+        for (int i = 0; i < n_phases; ++i) { ms[i] = 0.0; count[i] = 0; }
+        hipError_t err = hipSuccess;
+        for (const Rec& r : recs_) {
+            float t = 0.f;
+            hipError_t e = hipEventSynchronize(r.b);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+            if (e != hipSuccess) err = e;
+            if (r.phase >= 0 && r.phase < n_phases) { ms[r.phase] += t; count[r.phase] += 1; }
+            pool_.push_back(r.a);
+            pool_.push_back(r.b);
+        }
+        recs_.clear();
+        return err;
+    }
+    ~Profiler()
+    {
+        for (const Rec& r : recs_) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
+    }
+
+private:
+    struct Rec { int phase; hipEvent_t a, b; };
+    hipEvent_t get()
+    {
+        if (!pool_.empty()) { hipEvent_t e = pool_.back(); pool_.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    std::vector<Rec> recs_;
+    std::vector<hipEvent_t> pool_;
+};
+
+// Records a phase around the kernels launched in its scope (no-op without a profiler).
+struct PhaseScope {
+    PhaseScope(Profiler* p, int phase, hipStream_t s) : p_(p), s_(s) { if (p_) p_->begin(phase, s_); }
+    ~PhaseScope() { if (p_) p_->end(s_); }
+    Profiler* p_;
+    hipStream_t s_;
+};
+
+enum Phase { kPhZero = 0, kPhSplat, kPhReduce, kPhFinalize, kPhGradZero, kPhAdjoint, kPhGradFinalize };
+
+int reduce_blocks(const WinParams& P);
+int backward_blocks(int64_t n);
+
+hipError_t launch_fill_zero(float* p, size_t n_floats, hipStream_t s);
+hipError_t launch_forward(const WinParams& P, const EventPtrs& ev, const float* rho,
+                          const float* ego, float* loss, const StatePtrs& st, hipStream_t s,
+                          Profiler* prof);
+hipError_t launch_backward(const WinParams& P, const EventPtrs& ev, const float* rho,
+                           const float* ego, const StatePtrs& st, const float* grad_loss,
+                           float* grad_rho, float* grad_ego, hipStream_t s, Profiler* prof);
+
+}  // namespace cm

@@ -1,0 +1,93 @@
+"""CPU checks of the C ABI: the library builds, loads, exports every symbol the
+header declares, and rejects invalid arguments on the host (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2412_06359_amd as cm
+from paper_2412_06359_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cmloss.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cm_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return cm.load()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "cm_loss_forward" in names and "cm_loss_backward" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code, name in binding._STATUS.items():
+        assert lib.cm_status_string(code).decode() == name
+
+
+def _desc(**kw):
+    base = dict(width=64, height=48, fx=50.0, fy=50.0, cx=31.5, cy=23.5, refs=[0.0, 0.5, 1.0])
+    base.update(kw)
+    return cm.WindowDesc.make(**base)
+
+
+def test_state_bytes_formula(lib):
+    d = _desc()
+    n = cm.state_bytes(d)
+    assert n >= 32 * 3 * 64 * 48
+    assert n - 32 * 3 * 64 * 48 < 1 << 20
+
+
+@pytest.mark.parametrize("bad", [
+    dict(width=0), dict(height=-3), dict(fx=0.0), dict(fy=-1.0), dict(fx=float("nan")),
+    dict(refs=[0.5, 0.5]), dict(refs=[0.7, 0.2]), dict(refs=[-0.1, 1.0]), dict(refs=[0.0, 1.5]),
+    dict(mode=7), dict(eps=0.0), dict(eps=float("inf")),
+])
+def test_invalid_descriptors_rejected(lib, bad):
+    d = _desc(**bad)
+    assert lib.cm_state_bytes(ctypes.byref(d)) == 0
+    # a null handle or invalid descriptor returns CM_ERR_INVALID_ARG before any HIP call
+    st = lib.cm_loss_forward(None, ctypes.byref(d), None, None, None, None, 0, None, None, None,
+                             None, None)
+    assert st == -1
+
+
+def test_too_many_refs_rejected(lib):
+    d = _desc()
+    d.n_refs = 17
+    assert lib.cm_state_bytes(ctypes.byref(d)) == 0
+    d.n_refs = 0
+    assert lib.cm_state_bytes(ctypes.byref(d)) == 0
+
+
+def test_null_arguments_rejected(lib):
+    d = _desc()
+    assert lib.cm_create(None, 0) == -1
+    fake = ctypes.c_void_p(1)
+    # n_events > 0 with null event pointers
+    st = lib.cm_loss_forward(fake, ctypes.byref(d), None, None, None, None, 10, None, None, None,
+                             None, None)
+    assert st == -1
+    st = lib.cm_loss_backward(fake, ctypes.byref(d), None, None, None, None, 0, None, None, None,
+                              None, None, None, None)
+    assert st == -1
+    assert lib.cm_destroy(None) == 0
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    monkeypatch.setattr(binding, "_lib", None)
+    monkeypatch.setattr(binding, "LIB_PATH", "/nonexistent/libcmloss.so")
+    with pytest.raises(RuntimeError, match="missing"):
+        binding.load()
