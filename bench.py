@@ -41,24 +41,26 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(phase: str, n: int, HW: int, R: int) -> float:
+def algorithmic_bytes(phase: str, n: int, HW: int, R: int, tiled: bool) -> float:
     """Bytes a phase must move at minimum for one window.
 
     events: 13 B each (x, y, t FP32 + p int8); rho: 4 B per pixel; splat images:
     C and S FP64 per pixel, polarity and reference (32 R B per pixel); d rho 4 B
-    per pixel."""
+    per pixel.  The tiled path's records and bin tables are not counted: they
+    are the implementation's traffic, not the method's."""
     ev = 13.0 * n
     rho = 4.0 * HW
     img = 32.0 * R * HW
-    return {
-        "zero": img,
-        "splat": ev + rho + img,
-        "reduce": img,
-        "finalize": 0.0,
-        "grad_zero": 4.0 * HW,
-        "adjoint": ev + rho + img + 4.0 * HW,
-        "grad_finalize": 0.0,
-    }[phase]
+    if tiled:
+        table = {"zero": 0.0, "count": ev + rho, "scan": 0.0, "scatter": ev + rho,
+                 "splat": img, "reduce": 0.0, "finalize": 0.0,
+                 "grad_count": ev + rho, "grad_scan": 0.0, "adjoint": ev + rho + img,
+                 "grad_tile": 8.0 * HW, "grad_finalize": 0.0}
+    else:
+        table = {"zero": img, "splat": ev + rho + img, "reduce": img, "finalize": 0.0,
+                 "grad_zero": 4.0 * HW, "adjoint": ev + rho + img + 4.0 * HW,
+                 "grad_finalize": 0.0}
+    return table.get(phase, 0.0)
 
 
 def measured_traffic(workload: str, kernel: str):
@@ -98,6 +100,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--path", default="auto", choices=["auto", "direct", "tiled"],
+                    help="kernel path of the library handle")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); windows are "
@@ -112,13 +116,15 @@ def main():
     cm.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    cm.set_path(0, {"auto": cm.CM_PATH_AUTO, "direct": cm.CM_PATH_DIRECT,
+                    "tiled": cm.CM_PATH_TILED}[args.path])
     win = eventgen.make_window(args.workload)
     desc = cm.WindowDesc.from_window(win)
     f32 = lambda a: torch.as_tensor(a, dtype=torch.float32).contiguous().to(dev)
     x, y, t = f32(win.x), f32(win.y), f32(win.t)
     p = torch.as_tensor(win.p, dtype=torch.int8).contiguous().to(dev)
     rho, ego = f32(win.rho), f32(win.theta)
-    state = torch.empty(cm.state_bytes(desc), dtype=torch.uint8, device=dev)
+    state = torch.empty(cm.state_bytes(desc, win.n), dtype=torch.uint8, device=dev)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     g_loss = torch.ones(1, dtype=torch.float32, device=dev)
     g_rho = torch.empty_like(rho)
@@ -149,12 +155,13 @@ def main():
         step()
     phases = cm.profile_read(0)
     cm.profile_enable(0, False)
-    per_launch = {k: (ms / max(c, 1), c) for k, (ms, c) in phases.items()}
+    per_launch = {k: (ms / max(c, 1), c) for k, (ms, c) in phases.items() if c > 0}
+    path_used = "tiled" if "count" in per_launch else "direct"
     dom = max(per_launch, key=lambda k: per_launch[k][0])
     dom_ms = per_launch[dom][0]
     HW = win.width * win.height
     R = len(win.refs)
-    alg = algorithmic_bytes(dom, win.n, HW, R)
+    alg = algorithmic_bytes(dom, win.n, HW, R, path_used == "tiled")
     achieved = alg / (dom_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, dom)
 
@@ -171,7 +178,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload], "path": "plain (one window per call)",
+        "config": {"workload": WORKLOADS[args.workload],
+                   "path": f"plain (one window per call), {path_used} kernels",
                    "sensor": f"{win.width}x{win.height}", "n_events": win.n, "refs": R,
                    "valid_fraction": n_valid / max(win.n, 1), "mode": "atomic",
                    "inputs": "FP32 events/rho/ego, FP64 warp and splat images"},

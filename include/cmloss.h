@@ -87,17 +87,29 @@ cm_status cm_destroy(cm_handle h);
 /* Human-readable name of a status code (static string). */
 const char* cm_status_string(cm_status s);
 
-/* Bytes of the per-window `state` buffer: the splatted images C and S per
- * reference and polarity (32 * R * width * height bytes, FP64) plus
- * per-reference sums and the reduction scratch.  0 if `d` is invalid. */
-size_t cm_state_bytes(const cm_window_desc* d);
+/* Bytes of the per-window `state` buffer for a window of n_events events: the
+ * splatted images C and S per reference and polarity (32 * R * width * height
+ * bytes, FP64), per-reference sums, reduction scratch and, where the tiled
+ * path applies, its workspace (binned records, at most 32 * R bytes per event,
+ * plus per-tile buffers).  The forward and backward of one window must be
+ * called with the same n_events.  0 if `d` is invalid or n_events < 0. */
+size_t cm_state_bytes(const cm_window_desc* d, int64_t n_events);
+
+/* Kernel path used by a handle.  AUTO picks per window: the direct path
+ * (floating-point atomics straight into the images) for small windows, the
+ * tiled path (warped positions binned by 32x32 tile and accumulated in LDS,
+ * each pixel written once) for large ones where the sensor allows it.  The
+ * two compute the same quantities; TILED fails with CM_ERR_UNSUPPORTED where
+ * it does not apply (more than 16384 reference-tile bins). */
+enum { CM_PATH_AUTO = 0, CM_PATH_DIRECT = 1, CM_PATH_TILED = 2 };
+cm_status cm_set_path(cm_handle h, int path);
 
 /* Forward (paper Sec. 3.1 Eq. 1 with Sec. 3.2 Eq. 2; Sec. 3.3 per-event
  * forward).
  *   ev_x, ev_y, ev_t, ev_p : n_events events (device; may be NULL if n_events == 0)
  *   inv_depth, ego         : as above (device)
  *   loss                   : float32 [1] (device), receives L
- *   state                  : cm_state_bytes(d) bytes (device), written; the
+ *   state                  : cm_state_bytes(d, n_events) bytes (device), written; the
  *                            backward reads it, so keep it and the inputs
  *                            unchanged until the backward has run.
  * n_events == 0 gives L = 0. */
@@ -138,13 +150,19 @@ cm_status cm_state_diagnostics(const cm_window_desc* d, const void* state, doubl
  * from one host thread at a time. */
 enum {
     CM_PHASE_ZERO = 0,          /* clear the splat images (forward) */
-    CM_PHASE_SPLAT = 1,         /* warp + splat (forward) */
-    CM_PHASE_REDUCE = 2,        /* per-reference sums (forward) */
+    CM_PHASE_SPLAT = 1,         /* warp + splat, or the tiled path's per-tile splat (forward) */
+    CM_PHASE_REDUCE = 2,        /* per-reference sums, or the tiled path's halo merge (forward) */
     CM_PHASE_FINALIZE = 3,      /* loss (forward) */
     CM_PHASE_GRAD_ZERO = 4,     /* clear d inv_depth (backward) */
     CM_PHASE_ADJOINT = 5,       /* recompute warp + adjoint sweep (backward) */
     CM_PHASE_GRAD_FINALIZE = 6, /* d ego (backward) */
-    CM_N_PHASES = 7
+    CM_PHASE_COUNT = 7,         /* tiled path: bin the warped positions (forward) */
+    CM_PHASE_SCAN = 8,          /* tiled path: bin offsets (forward) */
+    CM_PHASE_SCATTER = 9,       /* tiled path: write the binned records (forward) */
+    CM_PHASE_GRAD_COUNT = 10,   /* tiled path: bin the flow-sampling positions (backward) */
+    CM_PHASE_GRAD_SCAN = 11,    /* tiled path: bin offsets (backward) */
+    CM_PHASE_GRAD_TILE = 12,    /* tiled path: dL/du per tile -> d inv_depth, d ego (backward) */
+    CM_N_PHASES = 13
 };
 cm_status cm_profile_enable(cm_handle h, int enable);
 cm_status cm_profile_read(cm_handle h, double* ms, int64_t* count);

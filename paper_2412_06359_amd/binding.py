@@ -92,8 +92,10 @@ def load() -> ctypes.CDLL:
         lib.cm_destroy.restype = ctypes.c_int
         lib.cm_status_string.argtypes = [ctypes.c_int]
         lib.cm_status_string.restype = ctypes.c_char_p
-        lib.cm_state_bytes.argtypes = [D]
+        lib.cm_state_bytes.argtypes = [D, i64]
         lib.cm_state_bytes.restype = ctypes.c_size_t
+        lib.cm_set_path.argtypes = [P, ctypes.c_int]
+        lib.cm_set_path.restype = ctypes.c_int
         lib.cm_loss_forward.argtypes = [P, D, P, P, P, P, i64, P, P, P, P, P]
         lib.cm_loss_forward.restype = ctypes.c_int
         lib.cm_loss_backward.argtypes = [P, D, P, P, P, P, i64, P, P, P, P, P, P, P]
@@ -127,11 +129,19 @@ def handle(device: int) -> ctypes.c_void_p:
     return h
 
 
-def state_bytes(desc: WindowDesc) -> int:
-    n = load().cm_state_bytes(ctypes.byref(desc))
+CM_PATH_AUTO, CM_PATH_DIRECT, CM_PATH_TILED = 0, 1, 2
+
+
+def state_bytes(desc: WindowDesc, n_events: int) -> int:
+    n = load().cm_state_bytes(ctypes.byref(desc), int(n_events))
     if n == 0:
         raise CMError(-1, "cm_state_bytes (invalid descriptor)")
     return int(n)
+
+
+def set_path(device: int, path: int):
+    """Kernel path of this device's handle: CM_PATH_AUTO, _DIRECT or _TILED."""
+    _check(load().cm_set_path(handle(device), int(path)), "cm_set_path")
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -168,7 +178,7 @@ def forward(desc: WindowDesc, x, y, t, p, rho, ego, state: Optional[torch.Tensor
     n = _check_events(x, y, t, p)
     _check_params(desc, rho, ego)
     dev = rho.device
-    nbytes = state_bytes(desc)
+    nbytes = state_bytes(desc, n)
     if state is None:
         state = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     elif state.numel() * state.element_size() < nbytes or not state.is_contiguous():
@@ -189,7 +199,7 @@ def backward(desc: WindowDesc, x, y, t, p, rho, ego, state, grad_loss,
     n = _check_events(x, y, t, p)
     _check_params(desc, rho, ego)
     dev = rho.device
-    if state.numel() * state.element_size() < state_bytes(desc):
+    if state.numel() * state.element_size() < state_bytes(desc, n):
         raise ValueError("state buffer too small")
     gl = grad_loss.reshape(1).to(device=dev, dtype=torch.float32).contiguous()
     if grad_rho is None:
@@ -214,7 +224,8 @@ def diagnostics(desc: WindowDesc, state: torch.Tensor) -> dict:
     return dict(loss=vals[0], n_valid=int(vals[1]), num=vals[2:2 + R], nact=vals[2 + R:])
 
 
-PHASES = ("zero", "splat", "reduce", "finalize", "grad_zero", "adjoint", "grad_finalize")
+PHASES = ("zero", "splat", "reduce", "finalize", "grad_zero", "adjoint", "grad_finalize",
+          "count", "scan", "scatter", "grad_count", "grad_scan", "grad_tile")
 
 
 def profile_enable(device: int, enable: bool = True):

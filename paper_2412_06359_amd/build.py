@@ -14,8 +14,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcmloss.so")
+PROBE_LIB = os.path.join(PKG, "libcmprobe.so")
 
-SOURCES = ["cm_api.hip", "cm_kernels.hip"]
+SOURCES = ["cm_api.hip", "cm_kernels.hip", "cm_tiles.hip"]
+PROBE_SOURCES = ["cm_probe.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
@@ -27,19 +29,25 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def _hipcc(sources, out, verbose):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include")] + \
-        [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+        [os.path.join(CSRC, s) for s in sources] + ["-o", tmp]
     t0 = time.time()
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libcmloss.so")
-    os.replace(tmp, LIB)
+        raise RuntimeError(f"hipcc failed building {os.path.basename(out)}")
+    os.replace(tmp, out)
     if verbose:
-        print(f"built {LIB} in {time.time() - t0:.1f}s")
+        print(f"built {out} in {time.time() - t0:.1f}s")
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libcmloss.so (the loss) and libcmprobe.so (roofline microbenchmarks)."""
+    _hipcc(SOURCES, LIB, verbose)
+    _hipcc(PROBE_SOURCES, PROBE_LIB, verbose)
     return LIB
 
 

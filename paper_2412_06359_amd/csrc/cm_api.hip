@@ -9,6 +9,7 @@
 
 struct cm_handle_s {
     int device;
+    int path;               // CM_PATH_*
     cm::Profiler prof;
 };
 
@@ -39,18 +40,36 @@ bool desc_valid(const cm_window_desc* d)
     return true;
 }
 
+WinParams params_of(const cm_window_desc* d);
+
+// Records a window needs at least before the tiled path pays for its extra
+// launches (below it the direct atomic path is faster).
+constexpr int64_t kTiledMinRecords = 1 << 17;
+
 struct Layout {
-    size_t img_bytes, hdr_off, scratch_off, total;
+    size_t img_bytes, hdr_off, scratch_off, ws_off, total;
+    bool tiled;             // the workspace of the tiled path is present
 };
 
-Layout layout_of(const cm_window_desc* d)
+// state = images | header | reduction scratch | tiled-path workspace
+Layout layout_of(const cm_window_desc* d, int64_t n)
 {
     Layout L;
     L.img_bytes = (size_t)32 * d->n_refs * d->width * d->height;
     L.hdr_off = align_up(L.img_bytes, kAlign);
     L.scratch_off = L.hdr_off + align_up(sizeof(StateHeader), kAlign);
-    L.total = L.scratch_off + cm::kScratchDoubles * sizeof(double);
+    L.ws_off = L.scratch_off + align_up(cm::kScratchDoubles * sizeof(double), kAlign);
+    const WinParams P = params_of(d);
+    L.tiled = n > 0 && cm::tiled_supported(P, n);
+    L.total = L.ws_off + (L.tiled ? cm::tile_workspace_layout(P, n).total : 0);
     return L;
+}
+
+bool choose_tiled(const cm_handle_s* h, const Layout& L, const WinParams& P, int64_t n)
+{
+    if (!L.tiled || h->path == CM_PATH_DIRECT) return false;
+    if (h->path == CM_PATH_TILED) return true;
+    return n * (int64_t)P.R >= kTiledMinRecords;
 }
 
 WinParams params_of(const cm_window_desc* d)
@@ -77,9 +96,9 @@ WinParams params_of(const cm_window_desc* d)
     return P;
 }
 
-StatePtrs state_ptrs(const cm_window_desc* d, void* state)
+StatePtrs state_ptrs(const cm_window_desc* d, int64_t n, void* state)
 {
-    const Layout L = layout_of(d);
+    const Layout L = layout_of(d, n);
     char* base = static_cast<char*>(state);
     StatePtrs s;
     s.img = reinterpret_cast<double*>(base);
@@ -130,6 +149,7 @@ cm_status cm_create(cm_handle* h, int device)
     cm_handle_s* hs = new (std::nothrow) cm_handle_s();
     if (!hs) return CM_ERR_OOM;
     hs->device = device;
+    hs->path = CM_PATH_AUTO;
     *h = hs;
     return CM_OK;
 }
@@ -153,10 +173,17 @@ const char* cm_status_string(cm_status s)
     return "CM_ERR_UNKNOWN";
 }
 
-size_t cm_state_bytes(const cm_window_desc* d)
+size_t cm_state_bytes(const cm_window_desc* d, int64_t n_events)
 {
-    if (!desc_valid(d)) return 0;
-    return layout_of(d).total;
+    if (!desc_valid(d) || n_events < 0) return 0;
+    return layout_of(d, n_events).total;
+}
+
+cm_status cm_set_path(cm_handle h, int path)
+{
+    if (!h || path < CM_PATH_AUTO || path > CM_PATH_TILED) return CM_ERR_INVALID_ARG;
+    h->path = path;
+    return CM_OK;
 }
 
 cm_status cm_loss_forward(cm_handle h, const cm_window_desc* d, const float* ev_x,
@@ -168,13 +195,20 @@ cm_status cm_loss_forward(cm_handle h, const cm_window_desc* d, const float* ev_
         !ego || !loss || !state)
         return CM_ERR_INVALID_ARG;
     if (d->mode != CM_MODE_ATOMIC) return CM_ERR_UNSUPPORTED;
+    const Layout L = layout_of(d, n_events);
+    const WinParams P = params_of(d);
+    if (h->path == CM_PATH_TILED && !L.tiled && n_events > 0) return CM_ERR_UNSUPPORTED;
     DeviceGuard g(h->device);
     if (!g.ok()) return CM_ERR_HIP;
-    const WinParams P = params_of(d);
     const cm::EventPtrs ev{ev_x, ev_y, ev_t, ev_p, n_events};
-    const hipError_t e = cm::launch_forward(P, ev, inv_depth, ego, loss, state_ptrs(d, state),
-                                            static_cast<hipStream_t>(stream),
-                                            h->prof.enabled ? &h->prof : nullptr);
+    const StatePtrs sp = state_ptrs(d, n_events, state);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    cm::Profiler* prof = h->prof.enabled ? &h->prof : nullptr;
+    const hipError_t e =
+        choose_tiled(h, L, P, n_events)
+            ? cm::launch_forward_tiled(P, ev, inv_depth, ego, loss, sp,
+                                       static_cast<char*>(state) + L.ws_off, s, prof)
+            : cm::launch_forward(P, ev, inv_depth, ego, loss, sp, s, prof);
     return e == hipSuccess ? CM_OK : CM_ERR_HIP;
 }
 
@@ -188,14 +222,21 @@ cm_status cm_loss_backward(cm_handle h, const cm_window_desc* d, const float* ev
         !ego || !state || !grad_loss || !grad_inv_depth || !grad_ego)
         return CM_ERR_INVALID_ARG;
     if (d->mode != CM_MODE_ATOMIC) return CM_ERR_UNSUPPORTED;
+    const Layout L = layout_of(d, n_events);
+    const WinParams P = params_of(d);
+    if (h->path == CM_PATH_TILED && !L.tiled && n_events > 0) return CM_ERR_UNSUPPORTED;
     DeviceGuard g(h->device);
     if (!g.ok()) return CM_ERR_HIP;
-    const WinParams P = params_of(d);
     const cm::EventPtrs ev{ev_x, ev_y, ev_t, ev_p, n_events};
-    const hipError_t e = cm::launch_backward(P, ev, inv_depth, ego, state_ptrs(d, state),
-                                             grad_loss, grad_inv_depth, grad_ego,
-                                             static_cast<hipStream_t>(stream),
-                                             h->prof.enabled ? &h->prof : nullptr);
+    const StatePtrs sp = state_ptrs(d, n_events, state);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    cm::Profiler* prof = h->prof.enabled ? &h->prof : nullptr;
+    const hipError_t e =
+        choose_tiled(h, L, P, n_events)
+            ? cm::launch_backward_tiled(P, ev, inv_depth, ego, sp, grad_loss, grad_inv_depth,
+                                        grad_ego, static_cast<char*>(state) + L.ws_off, s, prof)
+            : cm::launch_backward(P, ev, inv_depth, ego, sp, grad_loss, grad_inv_depth, grad_ego,
+                                  s, prof);
     return e == hipSuccess ? CM_OK : CM_ERR_HIP;
 }
 
@@ -203,7 +244,7 @@ cm_status cm_state_diagnostics(const cm_window_desc* d, const void* state, doubl
                                void* stream)
 {
     if (!desc_valid(d) || !state || !out) return CM_ERR_INVALID_ARG;
-    const Layout L = layout_of(d);
+    const Layout L = layout_of(d, 0);
     StateHeader hdr;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (hipMemcpyAsync(&hdr, static_cast<const char*>(state) + L.hdr_off, sizeof hdr,

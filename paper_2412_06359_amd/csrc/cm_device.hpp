@@ -9,7 +9,7 @@
 // coordinates give for 100 px flows) flips whether a tiny bilinear weight is
 // zero, and a weight of 1e-5 counts in Eq. 1's ratio S/(C+eps) as much as a
 // weight of one; FP64 keeps those decisions on the same side as the FP64
-// reference.  Image data and atomics stay FP32.
+// reference.  The splat images are FP64 as well (see cm_kernels.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -124,24 +124,61 @@ __device__ __forceinline__ int tap_pix(const WinParams& P, const Taps& t, int q)
     return (t.y0 + (q >> 1)) * P.W + t.x0 + (q & 1);
 }
 
+// Where the warp reads the flow: inverse depth and the motion coefficients.
+// The flow at a tap, u = A + rho B, is recomputed in FP64 from rho (4 bytes a
+// pixel, small enough to stay in L2) rather than read from a materialised FP64
+// flow field (16 bytes a pixel), which measured slower.
+struct FlowSrc {
+    const float* __restrict__ rho;
+    Motion m;
+};
+
+__device__ __forceinline__ FlowSrc flow_src(const WinParams& P, const float* __restrict__ rho,
+                                            const float* __restrict__ ego)
+{
+    FlowSrc f;
+    f.rho = rho;
+    f.m = load_motion(P, ego);
+    return f;
+}
+
+__device__ __forceinline__ double2 flow_at(const WinParams& P, const Motion& m, int i, int j,
+                                           double r)
+{
+    double Ax, Ay, Bx, By;
+    flow_parts(P, m, i, j, Ax, Ay, Bx, By);
+    return make_double2(Ax + r * Bx, Ay + r * By);
+}
+
+// The flow at the four taps of a position on the image (zero off the sensor).
+__device__ __forceinline__ void tap_flows(const WinParams& P, const FlowSrc& f, const Taps& t,
+                                          double2 (&uq)[4])
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (tap_in(t, q)) {
+            const int i = t.x0 + (q & 1), j = t.y0 + (q >> 1);
+            uq[q] = flow_at(P, f.m, i, j, (double)f.rho[j * P.W + i]);
+        } else {
+            uq[q] = make_double2(0.0, 0.0);
+        }
+    }
+}
+
 // BS(u)(X, Y): the flow sampled bilinearly at a position on the image.
-__device__ __forceinline__ void sample_flow(const WinParams& P, const Motion& m,
-                                            const float* __restrict__ rho, double X, double Y,
-                                            double& ux, double& uy)
+__device__ __forceinline__ void sample_flow(const WinParams& P, const FlowSrc& f, double X,
+                                            double Y, double& ux, double& uy)
 {
     const Taps t = make_taps(P, X, Y);
+    double2 uq[4];
+    tap_flows(P, f, t, uq);
     ux = 0.0;
     uy = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if (!tap_in(t, q)) continue;
-        const int i = t.x0 + (q & 1), j = t.y0 + (q >> 1);
-        double Ax, Ay, Bx, By;
-        flow_parts(P, m, i, j, Ax, Ay, Bx, By);
-        const double r = (double)rho[j * P.W + i];
         const double w = tap_w(t, q);
-        ux += w * (Ax + r * Bx);
-        uy += w * (Ay + r * By);
+        ux += w * uq[q].x;
+        uy += w * uq[q].y;
     }
 }
 
@@ -177,44 +214,41 @@ __device__ __forceinline__ int refs_before(const WinParams& P, double t)
 // re-sampling the flow at each visited position.  Positions at reference r go
 // to (px[r], py[r]).  Returns false if the event is masked: non-finite input,
 // t outside [0,1], start off the image, or any visited position off the image.
+// Both sweeps run in one loop of R visits so that the lanes of a wave, whose
+// events split differently between the sweeps, step together.
 template <int RM>
-__device__ __forceinline__ bool warp_event(const WinParams& P, const Motion& m,
-                                           const float* __restrict__ rho, double x0, double y0,
-                                           double tk, double (&px)[RM], double (&py)[RM],
-                                           int& mbefore)
+__device__ __forceinline__ bool warp_event(const WinParams& P, const FlowSrc& u,
+                                           double x0, double y0, double tk, double (&px)[RM],
+                                           double (&py)[RM], int& mbefore)
 {
     mbefore = 0;
     if (!(isfinite(x0) && isfinite(y0) && tk >= 0.0 && tk <= 1.0 && inside(P, x0, y0)))
         return false;
     const int mb = refs_before(P, tk);
     mbefore = mb;
-    int r = mb;
-    if (r < P.R && P.refs[r] == tk) {
-        put(px, r, x0);
-        put(py, r, y0);
-        ++r;
+    int rs = mb;
+    if (rs < P.R && P.refs[rs] == tk) {
+        put(px, rs, x0);
+        put(py, rs, y0);
+        ++rs;
     }
-    // forward sweep
+    const int nf = P.R - rs;            // forward visits rs .. R-1, then backward mb-1 .. 0
+    const int nv = nf + mb;
     double X = x0, Y = y0, tau = tk;
-    for (; r < P.R; ++r) {
+    for (int j = 0; j < nv; ++j) {
+        int r;
+        if (j < nf) {
+            r = rs + j;
+        } else {
+            r = mb - 1 - (j - nf);
+            if (j == nf) {
+                X = x0;
+                Y = y0;
+                tau = tk;
+            }
+        }
         double ux, uy;
-        sample_flow(P, m, rho, X, Y, ux, uy);
-        const double ref = P.refs[r];
-        const double dt = ref - tau;
-        X = X + dt * ux;
-        Y = Y + dt * uy;
-        tau = ref;
-        if (!inside(P, X, Y)) return false;
-        put(px, r, X);
-        put(py, r, Y);
-    }
-    // backward sweep
-    X = x0;
-    Y = y0;
-    tau = tk;
-    for (r = mb - 1; r >= 0; --r) {
-        double ux, uy;
-        sample_flow(P, m, rho, X, Y, ux, uy);
+        sample_flow(P, u, X, Y, ux, uy);
         const double ref = P.refs[r];
         const double dt = ref - tau;
         X = X + dt * ux;
@@ -225,6 +259,102 @@ __device__ __forceinline__ bool warp_event(const WinParams& P, const Motion& m,
         put(py, r, Y);
     }
     return true;
+}
+
+// One step of the reverse pass over an event's visits, in the order: the
+// forward sweep backwards (R-1 down to rs), then the backward sweep backwards
+// (0 up to mb-1).  For visit index j it gives the reference r, the position the
+// step started from (the event for the first step of a sweep), the step's dt,
+// and whether the adjoint restarts (a new sweep).
+struct ReverseStep {
+    int r;
+    bool first;      // the step started at the event
+    bool restart;    // a new sweep begins: the adjoint restarts from zero
+    double X, Y, dt;
+};
+
+template <int RM>
+__device__ __forceinline__ ReverseStep reverse_step(const WinParams& P, int j, int rs, int mb,
+                                                    double x0, double y0, double tk,
+                                                    const double (&px)[RM],
+                                                    const double (&py)[RM])
+{
+    ReverseStep s;
+    const int nf = P.R - rs;
+    int rp;
+    if (j < nf) {
+        s.r = P.R - 1 - j;
+        s.first = (s.r == rs);
+        s.restart = (j == 0);
+        rp = s.first ? s.r : s.r - 1;
+    } else {
+        s.r = j - nf;
+        s.first = (s.r == mb - 1);
+        s.restart = (j == nf);
+        rp = s.first ? s.r : s.r + 1;
+    }
+    s.X = s.first ? x0 : sel(px, rp);
+    s.Y = s.first ? y0 : sel(py, rp);
+    s.dt = P.refs[s.r] - (s.first ? tk : P.refs[rp]);
+    return s;
+}
+
+// Direct sensitivity of the loss to the position of an event on reference r:
+// sum over taps of (dL/dC + tbar dL/dS) grad w, with
+//   dL/dS = coef S/(C+eps)^2,  dL/dC = -coef S^2/(C+eps)^3,  coef = (2/R)/(N_r+eps).
+__device__ __forceinline__ void direct_term(const WinParams& P, const double2* __restrict__ plane,
+                                            double coef, double tb, double X, double Y,
+                                            double& Lx, double& Ly)
+{
+    const Taps tp = make_taps(P, X, Y);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (!tap_in(tp, q)) continue;
+        const double2 cs = plane[tap_pix(P, tp, q)];
+        const double S = cs.y;
+        const double inv = 1.0 / (cs.x + P.eps);
+        const double sc = S * inv;
+        const double g = coef * sc * inv * (tb - sc);
+        double dX, dY;
+        tap_dw(tp, q, dX, dY);
+        Lx += g * dX;
+        Ly += g * dY;
+    }
+}
+
+// d theta contribution of dL/du = (gx, gy) at pixel (i, j) with inverse depth
+// r: the transpose of d u / d theta (first-order Eq. 2) applied to g.
+__device__ __forceinline__ void dtheta_at_pixel(const WinParams& P, int i, int j, double r,
+                                                double gx, double gy, double (&dth)[6])
+{
+    const double xb = (double)i - P.cx, yb = (double)j - P.cy;
+    dth[0] += r * P.fx * gx;
+    dth[1] += r * P.fy * gy;
+    dth[2] -= r * (xb * gx + yb * gy);
+    dth[3] -= (xb * yb * P.inv_fy) * gx + (P.fy + yb * yb * P.inv_fy) * gy;
+    dth[4] += (P.fx + xb * xb * P.inv_fx) * gx + (xb * yb * P.inv_fx) * gy;
+    dth[5] += (P.fy_over_fx * xb) * gy - (P.fx_over_fy * yb) * gx;
+}
+
+// J(P)^T L for the bilinear flow sample at (X, Y): sum over taps of
+// (L . u_tap) grad w_tap.
+__device__ __forceinline__ void jacobian_t(const WinParams& P, const FlowSrc& u,
+                                           double X, double Y, double Lx, double Ly, double& jx,
+                                           double& jy)
+{
+    const Taps tp = make_taps(P, X, Y);
+    double2 uq[4];
+    tap_flows(P, u, tp, uq);
+    jx = 0.0;
+    jy = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double lu = Lx * uq[q].x + Ly * uq[q].y;
+        double dX, dY;
+        tap_dw(tp, q, dX, dY);
+        jx += lu * dX;
+        jy += lu * dY;
+    }
 }
 
 // Block-wide sum of doubles (blockDim.x a multiple of 64, <= 1024).
@@ -242,6 +372,48 @@ __device__ __forceinline__ double block_sum(double v, double* lds /* >= 16 */)
         for (int w = 0; w < nw; ++w) s += lds[w];
     }
     return s;   // valid in thread 0
+}
+
+}  // namespace cm
+
+namespace cm {
+
+// ---------------------------------------------------------------------------
+// Tiled (owner-computes) splat geometry.  The image is cut into TW x TH tiles;
+// a warped position belongs to the tile of its tap (x0, y0), so its taps fall
+// in that tile or in the tile's right column / bottom row halo.
+// ---------------------------------------------------------------------------
+constexpr int TW = 32, TH = 32;
+constexpr int TLW = TW + 1, TLH = TH + 1;    // LDS tile with halo
+constexpr int NHALO = TH + 1 + TW;           // right column (rows 0..TH) + bottom row (cols 0..TW-1)
+constexpr int NBORDER = TW + TH - 1;         // own column 0 (rows 0..TH-1) + row 0 (cols 1..TW-1)
+constexpr int kMaxBins = 16384;              // LDS histogram limit (64 KB)
+constexpr int kBinThreads = 256;             // threads of the count / scatter kernels
+constexpr int kMaxEventsPerThread = 16;
+
+struct TileGeom {
+    int ntx, nty, ntiles;   // tiles per row / column / image
+    int nbins;              // bins of this pass (R * ntiles forward, ntiles backward)
+    int nblocks;            // count / scatter blocks
+    int ept;                // events per thread in the count / scatter kernels
+};
+
+// Forward record: a warped position on one reference time.
+struct SplatRec {
+    double X, Y;
+    float ts;               // event time, sign bit = polarity (set: negative)
+    uint32_t k;             // event index
+};
+
+// Backward record: a warp step's sampling position and dt * adjoint.
+struct GradRec {
+    double X, Y;
+    double gx, gy;
+};
+
+__device__ __forceinline__ int tile_index(const TileGeom& G, const Taps& t)
+{
+    return (t.y0 / TH) * G.ntx + t.x0 / TW;
 }
 
 }  // namespace cm

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void splat_kernel(WinParams P, const float* __
     __shared__ unsigned int cnt_lds;
     if (threadIdx.x == 0) cnt_lds = 0;
     __syncthreads();
-    const Motion m = load_motion(P, ego);
+    const FlowSrc u = flow_src(P, rho, ego);
     unsigned int cnt = 0;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
          k += (int64_t)gridDim.x * blockDim.x) {
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void splat_kernel(WinParams P, const float* __
         const int pol = ep[k] > 0 ? 0 : 1;
         double px[RM], py[RM];
         int mb;
-        if (!warp_event<RM>(P, m, rho, x0, y0, tk, px, py, mb)) continue;
+        if (!warp_event<RM>(P, u, x0, y0, tk, px, py, mb)) continue;
         ++cnt;
 #pragma unroll
         for (int r = 0; r < RM; ++r) {
@@ -145,79 +145,50 @@ __global__ __launch_bounds__(256) void finalize_forward_kernel(WinParams P,
 }
 
 // Adjoint of one warp step P_j = P_{j-1} + dt BS(u)(P_{j-1}) at P_{j-1} = (X, Y):
-// scatters dL/du at the taps into d rho (through dU/drho = B) and d theta,
+// scatters dL/du at the taps into d rho (through du/drho = B) and d theta,
 // and advances the adjoint (Lx, Ly) <- L + dt J^T L.
-__device__ __forceinline__ void adjoint_step(const WinParams& P, const Motion& m,
-                                             const float* __restrict__ rho, double X, double Y,
+__device__ __forceinline__ void adjoint_step(const WinParams& P, const FlowSrc& u, double X,
+                                             double Y,
                                              double dt, double& Lx, double& Ly, double gl,
                                              float* __restrict__ drho, double (&dth)[6])
 {
     const Taps tp = make_taps(P, X, Y);
+    double2 uq[4];
+    tap_flows(P, u, tp, uq);
     double jx = 0.0, jy = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if (!tap_in(tp, q)) continue;
-        const int i = tp.x0 + (q & 1), j = tp.y0 + (q >> 1);
-        const int pix = j * P.W + i;
-        double Ax, Ay, Bx, By;
-        flow_parts(P, m, i, j, Ax, Ay, Bx, By);
-        const double r = (double)rho[pix];
-        const double ux = Ax + r * Bx, uy = Ay + r * By;
         double dX, dY;
         tap_dw(tp, q, dX, dY);
-        const double lu = Lx * ux + Ly * uy;
+        const double lu = Lx * uq[q].x + Ly * uq[q].y;
         jx += lu * dX;
         jy += lu * dY;
+        if (!tap_in(tp, q)) continue;
         const double w = tap_w(tp, q);
         if (w != 0.0) {
+            const int i = tp.x0 + (q & 1), j = tp.y0 + (q >> 1);
+            const int pix = j * P.W + i;
+            double Ax, Ay, Bx, By;
+            flow_parts(P, u.m, i, j, Ax, Ay, Bx, By);
             const double gx = dt * w * Lx, gy = dt * w * Ly;
             unsafeAtomicAdd(drho + pix, (float)(gl * (gx * Bx + gy * By)));
-            const double xb = (double)i - P.cx, yb = (double)j - P.cy;
-            dth[0] += r * P.fx * gx;
-            dth[1] += r * P.fy * gy;
-            dth[2] -= r * (xb * gx + yb * gy);
-            dth[3] -= (xb * yb * P.inv_fy) * gx + (P.fy + yb * yb * P.inv_fy) * gy;
-            dth[4] += (P.fx + xb * xb * P.inv_fx) * gx + (xb * yb * P.inv_fx) * gy;
-            dth[5] += (P.fy_over_fx * xb) * gy - (P.fx_over_fy * yb) * gx;
+            dtheta_at_pixel(P, i, j, (double)u.rho[pix], gx, gy, dth);
         }
     }
     Lx += dt * jx;
     Ly += dt * jy;
 }
 
-// Direct sensitivity of the loss to the position of an event on reference r:
-// sum over taps of (dL/dC + tbar dL/dS) grad w, with
-//   dL/dS = coef S/(C+eps)^2,  dL/dC = -coef S^2/(C+eps)^3,  coef = (2/R)/(N_r+eps).
-__device__ __forceinline__ void direct_term(const WinParams& P, const double2* __restrict__ plane,
-                                            double coef, double tb, double X, double Y,
-                                            double& Lx, double& Ly)
-{
-    const Taps tp = make_taps(P, X, Y);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        if (!tap_in(tp, q)) continue;
-        const double2 cs = plane[tap_pix(P, tp, q)];
-        const double S = cs.y;
-        const double inv = 1.0 / (cs.x + P.eps);
-        const double sc = S * inv;
-        const double g = coef * sc * inv * (tb - sc);
-        double dX, dY;
-        tap_dw(tp, q, dX, dY);
-        Lx += g * dX;
-        Ly += g * dY;
-    }
-}
-
 template <int RM>
 __global__ __launch_bounds__(256) void backward_kernel(
     WinParams P, const float* __restrict__ ex, const float* __restrict__ ey,
     const float* __restrict__ et, const int8_t* __restrict__ ep, int64_t n,
-    const float* __restrict__ rho, const float* __restrict__ ego, const double* __restrict__ img,
-    const StateHeader* __restrict__ hdr, const float* __restrict__ grad_loss,
-    float* __restrict__ drho, double* __restrict__ part)
+    const float* __restrict__ rho, const float* __restrict__ ego,
+    const double* __restrict__ img, const StateHeader* __restrict__ hdr,
+    const float* __restrict__ grad_loss, float* __restrict__ drho, double* __restrict__ part)
 {
     __shared__ double lds[16];
-    const Motion m = load_motion(P, ego);
+    const FlowSrc u = flow_src(P, rho, ego);
     const double gl = (double)grad_loss[0];
     double coef[RM];
 #pragma unroll
@@ -230,35 +201,20 @@ __global__ __launch_bounds__(256) void backward_kernel(
         const int pol = ep[k] > 0 ? 0 : 1;
         double px[RM], py[RM];
         int mb;
-        if (!warp_event<RM>(P, m, rho, x0, y0, tk, px, py, mb)) continue;
+        if (!warp_event<RM>(P, u, x0, y0, tk, px, py, mb)) continue;
         const double2* planes = reinterpret_cast<const double2*>(img) + (size_t)pol * P.HW;
-
-        // Reverse of the forward sweep: references rs..R-1 were visited upward.
-        int rs = mb;
-        if (rs < P.R && P.refs[rs] == tk) ++rs;
+        const int rs = (mb < P.R && P.refs[mb] == tk) ? mb + 1 : mb;
+        const int nv = (P.R - rs) + mb;
         double Lx = 0.0, Ly = 0.0;
-        for (int r = P.R - 1; r >= rs; --r) {
-            direct_term(P, planes + (size_t)r * 2 * P.HW, sel(coef, r),
-                        1.0 - fabs(P.refs[r] - tk), sel(px, r), sel(py, r), Lx, Ly);
-            const bool first = (r == rs);
-            const int rp = first ? r : r - 1;           // previous reference (if any)
-            const double X = first ? x0 : sel(px, rp);
-            const double Y = first ? y0 : sel(py, rp);
-            const double tprev = first ? tk : P.refs[rp];
-            adjoint_step(P, m, rho, X, Y, P.refs[r] - tprev, Lx, Ly, gl, drho, dth);
-        }
-        // Reverse of the backward sweep: references mb-1..0 were visited downward.
-        Lx = 0.0;
-        Ly = 0.0;
-        for (int r = 0; r < mb; ++r) {
-            direct_term(P, planes + (size_t)r * 2 * P.HW, sel(coef, r),
-                        1.0 - fabs(P.refs[r] - tk), sel(px, r), sel(py, r), Lx, Ly);
-            const bool first = (r == mb - 1);
-            const int rp = first ? r : r + 1;           // previous reference (if any)
-            const double X = first ? x0 : sel(px, rp);
-            const double Y = first ? y0 : sel(py, rp);
-            const double tprev = first ? tk : P.refs[rp];
-            adjoint_step(P, m, rho, X, Y, P.refs[r] - tprev, Lx, Ly, gl, drho, dth);
+        for (int j = 0; j < nv; ++j) {
+            const ReverseStep s = reverse_step<RM>(P, j, rs, mb, x0, y0, tk, px, py);
+            if (s.restart) {
+                Lx = 0.0;
+                Ly = 0.0;
+            }
+            direct_term(P, planes + (size_t)s.r * 2 * P.HW, sel(coef, s.r),
+                        1.0 - fabs(P.refs[s.r] - tk), sel(px, s.r), sel(py, s.r), Lx, Ly);
+            adjoint_step(P, u, s.X, s.Y, s.dt, Lx, Ly, gl, drho, dth);
         }
     }
 #pragma unroll

@@ -93,7 +93,25 @@ struct PhaseScope {
     hipStream_t s_;
 };
 
-enum Phase { kPhZero = 0, kPhSplat, kPhReduce, kPhFinalize, kPhGradZero, kPhAdjoint, kPhGradFinalize };
+enum Phase {
+    kPhZero = 0, kPhSplat, kPhReduce, kPhFinalize, kPhGradZero, kPhAdjoint, kPhGradFinalize,
+    kPhCount, kPhScan, kPhScatter, kPhGradCount, kPhGradScan, kPhGradTile, kNumPhases
+};
+
+// Byte offsets of the tiled path's buffers inside the workspace region.
+struct TileWorkspace {
+    size_t hist, csum, totals, start, part, halo, records, total;
+};
+
+// Kernels shared by the direct and tiled paths.
+__global__ __launch_bounds__(256) void finalize_forward_kernel(WinParams P,
+                                                               const double* __restrict__ part,
+                                                               int RB, StateHeader* hdr,
+                                                               float* __restrict__ loss);
+__global__ __launch_bounds__(256) void finalize_backward_kernel(const double* __restrict__ part,
+                                                                int nblk,
+                                                                const float* __restrict__ grad_loss,
+                                                                float* __restrict__ grad_ego);
 
 int reduce_blocks(const WinParams& P);
 int backward_blocks(int64_t n);
@@ -105,5 +123,17 @@ hipError_t launch_forward(const WinParams& P, const EventPtrs& ev, const float* 
 hipError_t launch_backward(const WinParams& P, const EventPtrs& ev, const float* rho,
                            const float* ego, const StatePtrs& st, const float* grad_loss,
                            float* grad_rho, float* grad_ego, hipStream_t s, Profiler* prof);
+
+// Tiled (owner-computes) path, usable when tiled_supported(); `ws` is a device
+// region of tile_workspace_layout(P, n).total bytes.
+bool tiled_supported(const WinParams& P, int64_t n);
+TileWorkspace tile_workspace_layout(const WinParams& P, int64_t n);
+hipError_t launch_forward_tiled(const WinParams& P, const EventPtrs& ev, const float* rho,
+                                const float* ego, float* loss, const StatePtrs& st, char* ws,
+                                hipStream_t s, Profiler* prof);
+hipError_t launch_backward_tiled(const WinParams& P, const EventPtrs& ev, const float* rho,
+                                 const float* ego, const StatePtrs& st, const float* grad_loss,
+                                 float* grad_rho, float* grad_ego, char* ws, hipStream_t s,
+                                 Profiler* prof);
 
 }  // namespace cm

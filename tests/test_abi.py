@@ -45,9 +45,13 @@ def _desc(**kw):
 
 def test_state_bytes_formula(lib):
     d = _desc()
-    n = cm.state_bytes(d)
+    n = cm.state_bytes(d, 0)
     assert n >= 32 * 3 * 64 * 48
     assert n - 32 * 3 * 64 * 48 < 1 << 20
+    # the tiled path's workspace grows with the event count (records of <= 32 R bytes)
+    big = cm.state_bytes(d, 1_000_000)
+    assert big > n + 24 * 3 * 1_000_000
+    assert big < n + 32 * 3 * 1_000_000 + (64 << 20)
 
 
 @pytest.mark.parametrize("bad", [
@@ -57,7 +61,7 @@ def test_state_bytes_formula(lib):
 ])
 def test_invalid_descriptors_rejected(lib, bad):
     d = _desc(**bad)
-    assert lib.cm_state_bytes(ctypes.byref(d)) == 0
+    assert lib.cm_state_bytes(ctypes.byref(d), 0) == 0
     # a null handle or invalid descriptor returns CM_ERR_INVALID_ARG before any HIP call
     st = lib.cm_loss_forward(None, ctypes.byref(d), None, None, None, None, 0, None, None, None,
                              None, None)
@@ -67,9 +71,10 @@ def test_invalid_descriptors_rejected(lib, bad):
 def test_too_many_refs_rejected(lib):
     d = _desc()
     d.n_refs = 17
-    assert lib.cm_state_bytes(ctypes.byref(d)) == 0
+    assert lib.cm_state_bytes(ctypes.byref(d), 0) == 0
     d.n_refs = 0
-    assert lib.cm_state_bytes(ctypes.byref(d)) == 0
+    assert lib.cm_state_bytes(ctypes.byref(d), 0) == 0
+    assert lib.cm_state_bytes(ctypes.byref(_desc()), -1) == 0
 
 
 def test_null_arguments_rejected(lib):
@@ -84,6 +89,8 @@ def test_null_arguments_rejected(lib):
                               None, None, None, None)
     assert st == -1
     assert lib.cm_destroy(None) == 0
+    assert lib.cm_set_path(None, 0) == -1
+    assert lib.cm_set_path(fake, 3) == -1
 
 
 def test_binding_fails_loudly_without_library(monkeypatch):

@@ -16,12 +16,16 @@ from tests.helpers import assert_grads_close, assert_loss_close, to_device
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def cm():
+@pytest.fixture(scope="module", params=["direct", "tiled"])
+def cm(request):
+    """The binding, with the handle's kernel path forced to each of the two."""
     import paper_2412_06359_amd as cm
     cm.load()                       # raises if the HIP library is missing
     assert torch.cuda.is_available()
-    return cm
+    cm.set_path(0, cm.CM_PATH_DIRECT if request.param == "direct" else cm.CM_PATH_TILED)
+    print(f"[gpu] path={request.param}", flush=True)
+    yield cm
+    cm.set_path(0, cm.CM_PATH_AUTO)
 
 
 def run_gpu(cm, win, grad=True, grad_out=1.0):
