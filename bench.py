@@ -1,13 +1,16 @@
 #!/usr/bin/env python3
 """Throughput of the contrast-maximization loss forward + backward on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c5]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1|c5]
 
-One step is one pass of the whole path over one window: forward (clear, warp +
-splat, reduce, loss) and backward (clear, recompute + adjoint, d ego), through
-the C ABI with buffers allocated once; inputs are resident in HBM before the
-timed region.  Prints one JSON line.  Inputs are seeded synthetic windows
-(edge maps under rigid camera motion, see eventgen).
+One step is one pass of the whole path (forward: warp, splat, reduce, loss;
+backward: recomputed warp, adjoint, d inverse depth, d ego-motion) over the
+workload, through the C ABI with buffers allocated once; inputs are resident in
+HBM before the timed region.  The default workload is the batched one (64
+windows of uneven size): `value` is the batched path (one launch sequence for
+all windows, replayed as a hipGraph) and `plain_events_per_s` the same windows
+one call each on the same GPU.  Prints one JSON line.  Inputs are seeded
+synthetic windows (edge maps under rigid camera motion, see eventgen).
 """
 
 from __future__ import annotations
@@ -28,6 +31,8 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "c1": "c1: 64x64 f=50, 2k uniform events, refs {1}, fwd+bwd",
     "c2": "c2: 640x480 f=300, 100k edge-map events (50 segments), refs {0,0.5,1}, fwd+bwd",
+    "c3": "c3: 64 windows 346x260 f=200, log-uniform 5k..200k edge-map events, refs {0,1}, "
+          "fwd+bwd",
     "c5": "c5: 1280x720 f=600, 2M edge-map events (400 segments), 8 refs in [0,1], fwd+bwd",
 }
 
@@ -76,20 +81,78 @@ def measured_traffic(workload: str, kernel: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(win, seconds: float) -> dict:
+def cpu_baseline(wins, seconds: float, threads: int) -> dict:
+    """The FP64 oracle (forward + backward) over a bounded sample of the
+    workload's windows, one window per thread (ctypes releases the GIL)."""
     import oracle
-    reps = 0
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(w):
+        oracle.forward(w)
+        oracle.backward(w)
+        return w.n
+
+    done_events = 0
+    done_windows = 0
     t0 = time.perf_counter()
-    while True:
-        oracle.forward(win)
-        oracle.backward(win)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return {"value": reps * win.n / el, "unit": "events/s", "cores": 1, "kind": "oracle",
-            "sample": f"{win.name} window ({win.n} events, R={len(win.refs)}), FP64 oracle "
-                      f"forward+backward, {reps} repetitions in {el:.1f} s, single thread"}
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        i = 0
+        while time.perf_counter() - t0 < seconds:
+            chunk = [wins[(i + j) % len(wins)] for j in range(threads)]
+            i += threads
+            done_events += sum(pool.map(one, chunk))
+            done_windows += len(chunk)
+    el = time.perf_counter() - t0
+    return {"value": done_events / el, "unit": "events/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done_windows} windows of the workload ({done_events} events), FP64 "
+                      f"oracle forward+backward, {threads} threads (one window each), {el:.1f} s"}
+
+
+def to_device(wins, dev):
+    import numpy as np
+    import torch
+    f = lambda arrs: torch.from_numpy(np.ascontiguousarray(np.concatenate(
+        [np.asarray(a, np.float32).ravel() for a in arrs]))).to(dev)
+    return dict(x=f([w.x for w in wins]), y=f([w.y for w in wins]), t=f([w.t for w in wins]),
+                p=torch.from_numpy(np.concatenate([np.asarray(w.p, np.int8) for w in wins])).to(dev),
+                rho=f([w.rho for w in wins]), ego=f([w.theta for w in wins]))
+
+
+def timed(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def plain_step_fn(cm, wins, dev):
+    """One window per call through the C ABI (the library picks its kernel path
+    per window), buffers allocated once."""
+    import torch
+    items = []
+    for w in wins:
+        d = to_device([w], dev)
+        desc = cm.WindowDesc.from_window(w)
+        st = torch.empty(cm.state_bytes(desc, w.n), dtype=torch.uint8, device=dev)
+        items.append((desc, d, st, torch.empty(1, device=dev), torch.empty_like(d["rho"]),
+                      torch.empty(6, device=dev)))
+    g = torch.ones(1, device=dev)
+
+    def step():
+        for desc, d, st, loss, g_rho, g_ego in items:
+            cm.forward(desc, d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"], state=st,
+                       loss=loss)
+            cm.backward(desc, d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"], st, g,
+                        grad_rho=g_rho, grad_ego=g_ego)
+    return step
 
 
 def main():
@@ -97,11 +160,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the single-window c2 line")
     ap.add_argument("--path", default="auto", choices=["auto", "direct", "tiled"],
-                    help="kernel path of the library handle")
+                    help="kernel path of the library handle (plain calls)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); windows are "
@@ -116,58 +180,84 @@ def main():
     cm.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
     cm.set_path(0, {"auto": cm.CM_PATH_AUTO, "direct": cm.CM_PATH_DIRECT,
                     "tiled": cm.CM_PATH_TILED}[args.path])
-    win = eventgen.make_window(args.workload)
-    desc = cm.WindowDesc.from_window(win)
-    f32 = lambda a: torch.as_tensor(a, dtype=torch.float32).contiguous().to(dev)
-    x, y, t = f32(win.x), f32(win.y), f32(win.t)
-    p = torch.as_tensor(win.p, dtype=torch.int8).contiguous().to(dev)
-    rho, ego = f32(win.rho), f32(win.theta)
-    state = torch.empty(cm.state_bytes(desc, win.n), dtype=torch.uint8, device=dev)
-    loss = torch.empty(1, dtype=torch.float32, device=dev)
-    g_loss = torch.ones(1, dtype=torch.float32, device=dev)
-    g_rho = torch.empty_like(rho)
-    g_ego = torch.empty(6, dtype=torch.float32, device=dev)
+    batched = args.workload == "c3"
+    wins = eventgen.make_batch("c3", 64) if batched else [eventgen.make_window(args.workload)]
+    n_events = sum(w.n for w in wins)
+    out_extra = {}
 
-    def step():
-        cm.forward(desc, x, y, t, p, rho, ego, state=state, loss=loss)
-        cm.backward(desc, x, y, t, p, rho, ego, state, g_loss, grad_rho=g_rho, grad_ego=g_ego)
+    plain = plain_step_fn(cm, wins, dev)
+    ms_plain = timed(plain, args.steps, args.warmup, stream)
+    if batched:
+        d = to_device(wins, dev)
+        batch = cm.Batch([cm.WindowDesc.from_window(w) for w in wins], [w.n for w in wins],
+                         graph=True)
+        state = batch.new_state()
+        loss = torch.empty(batch.n, device=dev)
+        g_rho = torch.empty_like(d["rho"])
+        g_ego = torch.empty_like(d["ego"])
+        gl = torch.ones(batch.n, device=dev)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream(dev)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_per_step = e0.elapsed_time(e1) / args.steps
-    n_valid = cm.diagnostics(desc, state)["n_valid"]
+        def step():
+            batch.forward(d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"], state=state,
+                          loss=loss)
+            batch.backward(d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"], state, gl,
+                           grad_rho=g_rho, grad_ego=g_ego)
+        ms_per_step = timed(step, args.steps, args.warmup, stream)
+        n_valid = sum(v for _, v in batch.diagnostics(state))
+        # per-kernel timing of the same launch sequence without the graph
+        batch.set_graph(False)
+        cm.profile_enable(0, True)
+        cm.profile_read(0)
+        for _ in range(args.steps):
+            step()
+        phases = cm.profile_read(0)
+        cm.profile_enable(0, False)
+        path_used = "tiled"
+        out_extra["plain_events_per_s"] = n_events / (ms_plain * 1e-3)
+        out_extra["plain_ms_per_step"] = ms_plain
+        out_extra["batched_over_plain"] = ms_plain / ms_per_step
+    else:
+        ms_per_step = ms_plain
+        cm.profile_enable(0, True)
+        cm.profile_read(0)
+        for _ in range(args.steps):
+            plain()
+        phases = cm.profile_read(0)
+        cm.profile_enable(0, False)
+        path_used = "tiled" if phases["count"][1] > 0 else "direct"
+        n_valid = None
 
-    # second timed region with per-kernel HIP events on the launch stream
-    cm.profile_enable(0, True)
-    cm.profile_read(0)
-    for _ in range(args.steps):
-        step()
-    phases = cm.profile_read(0)
-    cm.profile_enable(0, False)
     per_launch = {k: (ms / max(c, 1), c) for k, (ms, c) in phases.items() if c > 0}
-    path_used = "tiled" if "count" in per_launch else "direct"
-    dom = max(per_launch, key=lambda k: per_launch[k][0])
+    dom = max(per_launch, key=lambda k: per_launch[k][0] * per_launch[k][1])
     dom_ms = per_launch[dom][0]
-    HW = win.width * win.height
-    R = len(win.refs)
-    alg = algorithmic_bytes(dom, win.n, HW, R, path_used == "tiled")
+    launches_per_step = per_launch[dom][1] / args.steps
+    alg = sum(algorithmic_bytes(dom, w.n, w.width * w.height, len(w.refs), path_used == "tiled")
+              for w in wins) / launches_per_step
     achieved = alg / (dom_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, dom)
 
+    if not args.no_extras and args.workload != "c2":
+        w2 = eventgen.make_window("c2")
+        dd = to_device([w2], dev)
+        desc2 = cm.WindowDesc.from_window(w2)
+        rho2 = dd["rho"].clone().requires_grad_(True)
+        ego2 = dd["ego"].clone().requires_grad_(True)
+
+        def step2():
+            L = cm.cm_loss(dd["x"], dd["y"], dd["t"], dd["p"], rho2, ego2, desc2)
+            L.backward()
+        ms2 = timed(step2, args.steps, args.warmup, stream)
+        out_extra["c2_single_window_autograd"] = {
+            "workload": WORKLOADS["c2"], "ms_per_step": ms2,
+            "events_per_s": w2.n / (ms2 * 1e-3)}
+
+    R = len(wins[0].refs)
     out = {
         "metric": METRIC,
-        "value": win.n / (ms_per_step * 1e-3),
+        "value": n_events / (ms_per_step * 1e-3),
         "unit": "events/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -179,17 +269,22 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload],
-                   "path": f"plain (one window per call), {path_used} kernels",
-                   "sensor": f"{win.width}x{win.height}", "n_events": win.n, "refs": R,
-                   "valid_fraction": n_valid / max(win.n, 1), "mode": "atomic",
+                   "path": ("batched: 64 windows per launch sequence, hipGraph replay, tiled "
+                            "kernels" if batched else f"plain (one window per call), "
+                                                      f"{path_used} kernels"),
+                   "windows": len(wins), "n_events": n_events, "refs": R,
+                   "valid_fraction": (n_valid / n_events) if n_valid is not None else None,
+                   "mode": "atomic",
                    "inputs": "FP32 events/rho/ego, FP64 warp and splat images"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg, "avg_launch_ms": dom_ms},
         "phases_ms_per_launch": {k: v[0] for k, v in per_launch.items()},
     }
+    out.update(out_extra)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(win, args.cpu_seconds)
+        threads = min(os.cpu_count() or 1, 16) if batched else 1
+        out["cpu_baseline"] = cpu_baseline(wins, args.cpu_seconds, threads)
     print(json.dumps(out), flush=True)
 
 

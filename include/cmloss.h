@@ -142,6 +142,41 @@ cm_status cm_loss_backward(cm_handle h, const cm_window_desc* d,
 cm_status cm_state_diagnostics(const cm_window_desc* d, const void* state, double* out,
                                void* stream);
 
+/* Batches (the tiled path over many windows in one launch sequence).
+ *
+ * A plan fixes a batch's shape: n_windows descriptors (host memory, each with
+ * CM_MODE_ATOMIC) and their event counts.  Events of all windows are packed in
+ * flat device arrays, window w at [event_offsets[w], event_offsets[w+1]), in
+ * window order; inverse depth and d inverse depth likewise at
+ * [pixel_offsets[w], pixel_offsets[w+1]) (height * width floats each); ego and
+ * d ego are [n_windows * 6]; loss and grad_loss are [n_windows].  Each window's
+ * loss and gradient equal those of a single-window call on the same data.
+ * cm_batch_create allocates the plan's metadata on the device (call it at set-
+ * up time, not in a hot loop); the state buffer (cm_batch_state_bytes) is the
+ * caller's.  With graphs enabled, the first call with a given set of buffers
+ * captures the launch sequence into a hipGraph and later calls with the same
+ * buffers replay it; a plan is used by one host thread at a time.  Windows that
+ * exceed the tiled path's limits (more than 16384 reference-tile bins, or 2^31
+ * records in the batch) make cm_batch_create fail with CM_ERR_UNSUPPORTED. */
+typedef struct cm_batch_s* cm_batch;
+cm_status cm_batch_create(cm_handle h, int32_t n_windows, const cm_window_desc* descs,
+                          const int64_t* n_events, cm_batch* out);
+cm_status cm_batch_destroy(cm_batch b);
+size_t cm_batch_state_bytes(cm_batch b);
+/* Host arrays of n_windows + 1 entries each (either may be NULL). */
+cm_status cm_batch_offsets(cm_batch b, int64_t* event_offsets, int64_t* pixel_offsets);
+cm_status cm_batch_set_graph(cm_batch b, int enable);
+cm_status cm_loss_forward_batched(cm_batch b, const float* ev_x, const float* ev_y,
+                                  const float* ev_t, const int8_t* ev_p, const float* inv_depth,
+                                  const float* ego, float* loss, void* state, void* stream);
+cm_status cm_loss_backward_batched(cm_batch b, const float* ev_x, const float* ev_y,
+                                   const float* ev_t, const int8_t* ev_p, const float* inv_depth,
+                                   const float* ego, void* state, const float* grad_loss,
+                                   float* grad_inv_depth, float* grad_ego, void* stream);
+/* Per-window (loss, valid events) of the last batched forward, host array of
+ * 2 * n_windows doubles; synchronises `stream`. */
+cm_status cm_batch_diagnostics(cm_batch b, const void* state, double* out, void* stream);
+
 /* Phase timing (diagnostics, not part of the method).  While enabled on a
  * handle, each call records a pair of HIP events on its stream around every
  * kernel it launches.  cm_profile_read waits for the recorded events, writes

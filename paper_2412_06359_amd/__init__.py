@@ -5,11 +5,12 @@ include/cmloss.h (libcmloss.so); this package is the thin Python binding.
 """
 
 from .binding import (CM_MODE_ATOMIC, CM_MODE_DETERMINISTIC, CM_PATH_AUTO, CM_PATH_DIRECT,
-                      CM_PATH_TILED, PHASES, CMError, CMLoss, WindowDesc, backward, cm_loss,
+                      CM_PATH_TILED, PHASES, Batch, BatchCMLoss, CMError, CMLoss, WindowDesc,
+                      backward, cm_loss,
                       diagnostics, forward, handle, load, profile_enable, profile_read, set_path,
                       state_bytes)
 
 __all__ = ["CM_MODE_ATOMIC", "CM_MODE_DETERMINISTIC", "CMError", "CMLoss", "WindowDesc",
            "backward", "cm_loss", "diagnostics", "forward", "handle", "load", "profile_enable",
            "profile_read", "state_bytes", "PHASES", "CM_PATH_AUTO", "CM_PATH_DIRECT",
-           "CM_PATH_TILED", "set_path"]
+           "CM_PATH_TILED", "set_path", "Batch", "BatchCMLoss"]

@@ -102,6 +102,22 @@ def load() -> ctypes.CDLL:
         lib.cm_loss_backward.restype = ctypes.c_int
         lib.cm_state_diagnostics.argtypes = [D, P, P, P]
         lib.cm_state_diagnostics.restype = ctypes.c_int
+        lib.cm_batch_create.argtypes = [P, ctypes.c_int32, P, P, ctypes.POINTER(P)]
+        lib.cm_batch_create.restype = ctypes.c_int
+        lib.cm_batch_destroy.argtypes = [P]
+        lib.cm_batch_destroy.restype = ctypes.c_int
+        lib.cm_batch_state_bytes.argtypes = [P]
+        lib.cm_batch_state_bytes.restype = ctypes.c_size_t
+        lib.cm_batch_offsets.argtypes = [P, P, P]
+        lib.cm_batch_offsets.restype = ctypes.c_int
+        lib.cm_batch_set_graph.argtypes = [P, ctypes.c_int]
+        lib.cm_batch_set_graph.restype = ctypes.c_int
+        lib.cm_loss_forward_batched.argtypes = [P, P, P, P, P, P, P, P, P, P]
+        lib.cm_loss_forward_batched.restype = ctypes.c_int
+        lib.cm_loss_backward_batched.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P]
+        lib.cm_loss_backward_batched.restype = ctypes.c_int
+        lib.cm_batch_diagnostics.argtypes = [P, P, P, P]
+        lib.cm_batch_diagnostics.restype = ctypes.c_int
         lib.cm_profile_enable.argtypes = [P, ctypes.c_int]
         lib.cm_profile_enable.restype = ctypes.c_int
         lib.cm_profile_read.argtypes = [P, P, P]
@@ -222,6 +238,111 @@ def diagnostics(desc: WindowDesc, state: torch.Tensor) -> dict:
     _check(st, "cm_state_diagnostics")
     vals = list(out)
     return dict(loss=vals[0], n_valid=int(vals[1]), num=vals[2:2 + R], nact=vals[2 + R:])
+
+
+class Batch:
+    """A plan for many windows in one launch sequence (cm_batch).
+
+    Events of all windows are packed in flat arrays (window w at
+    event_offsets[w]:event_offsets[w+1]), inverse depth and its gradient at
+    pixel_offsets; ego / grad ego are [n, 6], loss / grad_loss [n]."""
+
+    def __init__(self, descs: Sequence[WindowDesc], n_events: Sequence[int], device: int = 0,
+                 graph: bool = False):
+        lib = load()
+        n = len(descs)
+        self.device = device
+        self.descs = list(descs)
+        arr = (WindowDesc * n)(*descs)
+        cnt = (ctypes.c_int64 * n)(*[int(v) for v in n_events])
+        self._b = ctypes.c_void_p()
+        _check(lib.cm_batch_create(handle(device), n, arr, cnt, ctypes.byref(self._b)),
+               "cm_batch_create")
+        self.n = n
+        self.state_bytes = int(lib.cm_batch_state_bytes(self._b))
+        ev = (ctypes.c_int64 * (n + 1))()
+        px = (ctypes.c_int64 * (n + 1))()
+        _check(lib.cm_batch_offsets(self._b, ev, px), "cm_batch_offsets")
+        self.event_offsets = list(ev)
+        self.pixel_offsets = list(px)
+        self.set_graph(graph)
+
+    def set_graph(self, enable: bool):
+        _check(load().cm_batch_set_graph(self._b, int(enable)), "cm_batch_set_graph")
+
+    def close(self):
+        if self._b:
+            load().cm_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_state(self) -> torch.Tensor:
+        return torch.empty(self.state_bytes, dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def _check_flat(self, x, y, t, p, rho, ego):
+        n = _check_events(x, y, t, p)
+        if n != self.event_offsets[-1]:
+            raise ValueError(f"batch has {self.event_offsets[-1]} events, got {n}")
+        if rho.dtype != torch.float32 or rho.numel() != self.pixel_offsets[-1] or \
+                not rho.is_contiguous() or not rho.is_cuda:
+            raise ValueError(f"inv_depth: need {self.pixel_offsets[-1]} contiguous float32 values")
+        if ego.dtype != torch.float32 or ego.numel() != 6 * self.n or not ego.is_contiguous():
+            raise ValueError(f"ego: need {6 * self.n} contiguous float32 values")
+
+    def forward(self, x, y, t, p, rho, ego, state=None, loss=None):
+        self._check_flat(x, y, t, p, rho, ego)
+        dev = rho.device
+        state = self.new_state() if state is None else state
+        if state.numel() * state.element_size() < self.state_bytes:
+            raise ValueError("state buffer too small")
+        loss = torch.empty(self.n, dtype=torch.float32, device=dev) if loss is None else loss
+        st = load().cm_loss_forward_batched(self._b, _ptr(x), _ptr(y), _ptr(t), _ptr(p),
+                                            _ptr(rho), _ptr(ego), _ptr(loss), _ptr(state),
+                                            _stream(dev))
+        _check(st, "cm_loss_forward_batched")
+        return loss, state
+
+    def backward(self, x, y, t, p, rho, ego, state, grad_loss, grad_rho=None, grad_ego=None):
+        self._check_flat(x, y, t, p, rho, ego)
+        dev = rho.device
+        gl = grad_loss.reshape(self.n).to(device=dev, dtype=torch.float32).contiguous()
+        grad_rho = torch.empty_like(rho) if grad_rho is None else grad_rho
+        grad_ego = torch.empty_like(ego) if grad_ego is None else grad_ego
+        st = load().cm_loss_backward_batched(self._b, _ptr(x), _ptr(y), _ptr(t), _ptr(p),
+                                             _ptr(rho), _ptr(ego), _ptr(state), _ptr(gl),
+                                             _ptr(grad_rho), _ptr(grad_ego), _stream(dev))
+        _check(st, "cm_loss_backward_batched")
+        return grad_rho, grad_ego
+
+    def diagnostics(self, state) -> list:
+        out = (ctypes.c_double * (2 * self.n))()
+        st = load().cm_batch_diagnostics(self._b, _ptr(state), out, _stream(state.device))
+        _check(st, "cm_batch_diagnostics")
+        return [(out[2 * w], int(out[2 * w + 1])) for w in range(self.n)]
+
+
+class BatchCMLoss(torch.autograd.Function):
+    """Per-window CM losses of a batch; differentiable in inv_depth and ego."""
+
+    @staticmethod
+    def forward(ctx, x, y, t, p, rho, ego, batch):
+        rho_c = rho.detach().contiguous()
+        ego_c = ego.detach().contiguous()
+        loss, state = batch.forward(x, y, t, p, rho_c, ego_c)
+        ctx.batch = batch
+        ctx.save_for_backward(x, y, t, p, rho_c, ego_c, state)
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        x, y, t, p, rho, ego, state = ctx.saved_tensors
+        g_rho, g_ego = ctx.batch.backward(x, y, t, p, rho, ego, state, grad_out.contiguous())
+        return None, None, None, None, g_rho.reshape(rho.shape), g_ego.reshape(ego.shape), None
 
 
 PHASES = ("zero", "splat", "reduce", "finalize", "grad_zero", "adjoint", "grad_finalize",

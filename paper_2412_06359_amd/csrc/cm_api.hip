@@ -1,8 +1,9 @@
 // cm_api.hip -- the C ABI declared in include/cmloss.h: argument validation,
-// state layout, device selection and kernel launches.
+// state layout, path selection, batch plans and hipGraph replay.
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/cmloss.h"
 #include "cm_kernels.hpp"
@@ -15,11 +16,17 @@ struct cm_handle_s {
 
 namespace {
 
+using cm::BatchPlanHost;
 using cm::StateHeader;
 using cm::StatePtrs;
+using cm::WinMeta;
 using cm::WinParams;
 
 constexpr size_t kAlign = 256;
+
+// Records a window needs at least before the tiled path pays for its extra
+// launches (below it the direct atomic path is faster).
+constexpr int64_t kTiledMinRecords = 1 << 17;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -38,38 +45,6 @@ bool desc_valid(const cm_window_desc* d)
     if (d->mode != CM_MODE_ATOMIC && d->mode != CM_MODE_DETERMINISTIC) return false;
     if (!(std::isfinite(d->eps) && d->eps > 0.f)) return false;
     return true;
-}
-
-WinParams params_of(const cm_window_desc* d);
-
-// Records a window needs at least before the tiled path pays for its extra
-// launches (below it the direct atomic path is faster).
-constexpr int64_t kTiledMinRecords = 1 << 17;
-
-struct Layout {
-    size_t img_bytes, hdr_off, scratch_off, ws_off, total;
-    bool tiled;             // the workspace of the tiled path is present
-};
-
-// state = images | header | reduction scratch | tiled-path workspace
-Layout layout_of(const cm_window_desc* d, int64_t n)
-{
-    Layout L;
-    L.img_bytes = (size_t)32 * d->n_refs * d->width * d->height;
-    L.hdr_off = align_up(L.img_bytes, kAlign);
-    L.scratch_off = L.hdr_off + align_up(sizeof(StateHeader), kAlign);
-    L.ws_off = L.scratch_off + align_up(cm::kScratchDoubles * sizeof(double), kAlign);
-    const WinParams P = params_of(d);
-    L.tiled = n > 0 && cm::tiled_supported(P, n);
-    L.total = L.ws_off + (L.tiled ? cm::tile_workspace_layout(P, n).total : 0);
-    return L;
-}
-
-bool choose_tiled(const cm_handle_s* h, const Layout& L, const WinParams& P, int64_t n)
-{
-    if (!L.tiled || h->path == CM_PATH_DIRECT) return false;
-    if (h->path == CM_PATH_TILED) return true;
-    return n * (int64_t)P.R >= kTiledMinRecords;
 }
 
 WinParams params_of(const cm_window_desc* d)
@@ -96,9 +71,36 @@ WinParams params_of(const cm_window_desc* d)
     return P;
 }
 
-StatePtrs state_ptrs(const cm_window_desc* d, int64_t n, void* state)
+// Single-window state = images | header | reduction scratch | metadata |
+// tiled-path workspace (present where the tiled path applies).
+struct Layout {
+    size_t img_bytes, hdr_off, scratch_off, meta_off, ws_off, total;
+    bool tiled;
+};
+
+Layout layout_of(const cm_window_desc* d, int64_t n)
 {
-    const Layout L = layout_of(d, n);
+    Layout L;
+    L.img_bytes = (size_t)32 * d->n_refs * d->width * d->height;
+    L.hdr_off = align_up(L.img_bytes, kAlign);
+    L.scratch_off = L.hdr_off + align_up(sizeof(StateHeader), kAlign);
+    L.meta_off = L.scratch_off + align_up(cm::kScratchDoubles * sizeof(double), kAlign);
+    L.ws_off = L.meta_off + align_up(sizeof(WinMeta), kAlign);
+    const WinParams P = params_of(d);
+    L.tiled = n > 0 && cm::tiled_supported(P, n);
+    L.total = L.ws_off + (L.tiled ? cm::plan_batch(&P, &n, 1).ws.total : 0);
+    return L;
+}
+
+bool choose_tiled(const cm_handle_s* h, const Layout& L, const WinParams& P, int64_t n)
+{
+    if (!L.tiled || h->path == CM_PATH_DIRECT) return false;
+    if (h->path == CM_PATH_TILED) return true;
+    return n * (int64_t)P.R >= kTiledMinRecords;
+}
+
+StatePtrs state_ptrs(const Layout& L, void* state)
+{
     char* base = static_cast<char*>(state);
     StatePtrs s;
     s.img = reinterpret_cast<double*>(base);
@@ -134,6 +136,71 @@ private:
     int prev_;
     bool ok_;
 };
+
+cm_status status_of(hipError_t e) { return e == hipSuccess ? CM_OK : CM_ERR_HIP; }
+
+}  // namespace
+
+// A batch plan: per-window metadata in device memory, the state layout, and
+// the hipGraphs of the forward and backward launch sequences.
+struct cm_batch_s {
+    cm_handle h = nullptr;
+    BatchPlanHost B;
+    std::vector<int64_t> ev_offsets, pix_offsets;
+    WinMeta* d_meta = nullptr;
+    size_t img_off = 0, hdr_off = 0, ws_off = 0, total = 0;
+    bool use_graph = false;
+    hipStream_t capture = nullptr;
+    struct Graph {
+        hipGraphExec_t exec = nullptr;
+        std::vector<const void*> key;
+    } fwd, bwd;
+
+    ~cm_batch_s()
+    {
+        if (fwd.exec) (void)hipGraphExecDestroy(fwd.exec);
+        if (bwd.exec) (void)hipGraphExecDestroy(bwd.exec);
+        if (capture) (void)hipStreamDestroy(capture);
+        if (d_meta) (void)hipFree(d_meta);
+    }
+};
+
+namespace {
+
+// Runs `enqueue(stream, profiler)` directly, or replays a hipGraph captured
+// from it on a private stream (recaptured when the buffers change).
+template <typename F>
+cm_status run_maybe_graph(cm_batch_s* b, cm_batch_s::Graph& g, std::vector<const void*> key,
+                          hipStream_t s, F&& enqueue)
+{
+    if (!b->use_graph) {
+        cm::Profiler* prof = b->h->prof.enabled ? &b->h->prof : nullptr;
+        return status_of(enqueue(s, prof));
+    }
+    if (!g.exec || g.key != key) {
+        if (g.exec) {
+            (void)hipGraphExecDestroy(g.exec);
+            g.exec = nullptr;
+        }
+        hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return CM_ERR_HIP;
+        const hipError_t el = enqueue(b->capture, nullptr);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(b->capture, &graph);
+        if (el != hipSuccess || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return CM_ERR_HIP;
+        }
+        e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            g.exec = nullptr;
+            return CM_ERR_HIP;
+        }
+        g.key = std::move(key);
+    }
+    return status_of(hipGraphLaunch(g.exec, s));
+}
 
 }  // namespace
 
@@ -201,15 +268,19 @@ cm_status cm_loss_forward(cm_handle h, const cm_window_desc* d, const float* ev_
     DeviceGuard g(h->device);
     if (!g.ok()) return CM_ERR_HIP;
     const cm::EventPtrs ev{ev_x, ev_y, ev_t, ev_p, n_events};
-    const StatePtrs sp = state_ptrs(d, n_events, state);
+    const StatePtrs sp = state_ptrs(L, state);
     hipStream_t s = static_cast<hipStream_t>(stream);
     cm::Profiler* prof = h->prof.enabled ? &h->prof : nullptr;
-    const hipError_t e =
-        choose_tiled(h, L, P, n_events)
-            ? cm::launch_forward_tiled(P, ev, inv_depth, ego, loss, sp,
-                                       static_cast<char*>(state) + L.ws_off, s, prof)
-            : cm::launch_forward(P, ev, inv_depth, ego, loss, sp, s, prof);
-    return e == hipSuccess ? CM_OK : CM_ERR_HIP;
+    if (!choose_tiled(h, L, P, n_events))
+        return status_of(cm::launch_forward(P, ev, inv_depth, ego, loss, sp, s, prof));
+    char* base = static_cast<char*>(state);
+    const BatchPlanHost B = cm::plan_batch(&P, &n_events, 1);
+    WinMeta* meta = reinterpret_cast<WinMeta*>(base + L.meta_off);
+    hipError_t e = cm::launch_store_meta(B.meta[0], meta, s);
+    if (e != hipSuccess) return CM_ERR_HIP;
+    return status_of(cm::launch_forward_batch(B, meta, ev, inv_depth, ego, loss,
+                                              reinterpret_cast<double2*>(sp.img), sp.hdr,
+                                              base + L.ws_off, s, prof));
 }
 
 cm_status cm_loss_backward(cm_handle h, const cm_window_desc* d, const float* ev_x,
@@ -228,16 +299,21 @@ cm_status cm_loss_backward(cm_handle h, const cm_window_desc* d, const float* ev
     DeviceGuard g(h->device);
     if (!g.ok()) return CM_ERR_HIP;
     const cm::EventPtrs ev{ev_x, ev_y, ev_t, ev_p, n_events};
-    const StatePtrs sp = state_ptrs(d, n_events, state);
+    const StatePtrs sp = state_ptrs(L, state);
     hipStream_t s = static_cast<hipStream_t>(stream);
     cm::Profiler* prof = h->prof.enabled ? &h->prof : nullptr;
-    const hipError_t e =
-        choose_tiled(h, L, P, n_events)
-            ? cm::launch_backward_tiled(P, ev, inv_depth, ego, sp, grad_loss, grad_inv_depth,
-                                        grad_ego, static_cast<char*>(state) + L.ws_off, s, prof)
-            : cm::launch_backward(P, ev, inv_depth, ego, sp, grad_loss, grad_inv_depth, grad_ego,
-                                  s, prof);
-    return e == hipSuccess ? CM_OK : CM_ERR_HIP;
+    if (!choose_tiled(h, L, P, n_events))
+        return status_of(cm::launch_backward(P, ev, inv_depth, ego, sp, grad_loss, grad_inv_depth,
+                                             grad_ego, s, prof));
+    char* base = static_cast<char*>(state);
+    const BatchPlanHost B = cm::plan_batch(&P, &n_events, 1);
+    WinMeta* meta = reinterpret_cast<WinMeta*>(base + L.meta_off);
+    hipError_t e = cm::launch_store_meta(B.meta[0], meta, s);
+    if (e != hipSuccess) return CM_ERR_HIP;
+    return status_of(cm::launch_backward_batch(B, meta, ev, inv_depth, ego,
+                                               reinterpret_cast<const double2*>(sp.img), sp.hdr,
+                                               grad_loss, grad_inv_depth, grad_ego,
+                                               base + L.ws_off, s, prof));
 }
 
 cm_status cm_state_diagnostics(const cm_window_desc* d, const void* state, double* out,
@@ -273,6 +349,148 @@ cm_status cm_profile_read(cm_handle h, double* ms, int64_t* count)
     DeviceGuard g(h->device);
     if (!g.ok()) return CM_ERR_HIP;
     return h->prof.read(ms, count, CM_N_PHASES) == hipSuccess ? CM_OK : CM_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+
+cm_status cm_batch_create(cm_handle h, int32_t n_windows, const cm_window_desc* descs,
+                          const int64_t* n_events, cm_batch* out)
+{
+    if (!out) return CM_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!h || n_windows < 1 || !descs || !n_events) return CM_ERR_INVALID_ARG;
+    std::vector<WinParams> params(n_windows);
+    int64_t total_records = 0;
+    for (int w = 0; w < n_windows; ++w) {
+        if (!desc_valid(&descs[w]) || n_events[w] < 0) return CM_ERR_INVALID_ARG;
+        if (descs[w].mode != CM_MODE_ATOMIC) return CM_ERR_UNSUPPORTED;
+        params[w] = params_of(&descs[w]);
+        if (!cm::tiled_supported(params[w], n_events[w])) return CM_ERR_UNSUPPORTED;
+        total_records += n_events[w] * (int64_t)params[w].R;
+    }
+    if (total_records >= ((int64_t)1 << 31)) return CM_ERR_UNSUPPORTED;
+    DeviceGuard g(h->device);
+    if (!g.ok()) return CM_ERR_HIP;
+    cm_batch_s* b = new (std::nothrow) cm_batch_s();
+    if (!b) return CM_ERR_OOM;
+    b->h = h;
+    b->B = cm::plan_batch(params.data(), n_events, n_windows);
+    b->ev_offsets.resize(n_windows + 1);
+    b->pix_offsets.resize(n_windows + 1);
+    for (int w = 0; w < n_windows; ++w) {
+        b->ev_offsets[w] = b->B.meta[w].ev_off;
+        b->pix_offsets[w] = b->B.meta[w].pix_off;
+    }
+    b->ev_offsets[n_windows] = b->B.n_events;
+    b->pix_offsets[n_windows] = b->B.n_pixels;
+    b->img_off = 0;
+    b->hdr_off = align_up((size_t)b->B.img_elems * 16, kAlign);
+    b->ws_off = b->hdr_off + align_up((size_t)n_windows * sizeof(StateHeader), kAlign);
+    b->total = b->ws_off + b->B.ws.total;
+    if (hipMalloc(&b->d_meta, sizeof(WinMeta) * n_windows) != hipSuccess ||
+        hipMemcpy(b->d_meta, b->B.meta.data(), sizeof(WinMeta) * n_windows,
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        return CM_ERR_HIP;
+    }
+    *out = b;
+    return CM_OK;
+}
+
+cm_status cm_batch_destroy(cm_batch b)
+{
+    if (!b) return CM_OK;
+    DeviceGuard g(b->h->device);
+    delete b;
+    return CM_OK;
+}
+
+size_t cm_batch_state_bytes(cm_batch b) { return b ? b->total : 0; }
+
+cm_status cm_batch_offsets(cm_batch b, int64_t* event_offsets, int64_t* pixel_offsets)
+{
+    if (!b) return CM_ERR_INVALID_ARG;
+    const size_t n = b->ev_offsets.size();
+    if (event_offsets) std::memcpy(event_offsets, b->ev_offsets.data(), n * sizeof(int64_t));
+    if (pixel_offsets) std::memcpy(pixel_offsets, b->pix_offsets.data(), n * sizeof(int64_t));
+    return CM_OK;
+}
+
+cm_status cm_batch_set_graph(cm_batch b, int enable)
+{
+    if (!b) return CM_ERR_INVALID_ARG;
+    b->use_graph = enable != 0;
+    return CM_OK;
+}
+
+cm_status cm_loss_forward_batched(cm_batch b, const float* ev_x, const float* ev_y,
+                                  const float* ev_t, const int8_t* ev_p, const float* inv_depth,
+                                  const float* ego, float* loss, void* state, void* stream)
+{
+    if (!b || !events_valid(ev_x, ev_y, ev_t, ev_p, b->B.n_events) || !inv_depth || !ego ||
+        !loss || !state)
+        return CM_ERR_INVALID_ARG;
+    DeviceGuard g(b->h->device);
+    if (!g.ok()) return CM_ERR_HIP;
+    char* base = static_cast<char*>(state);
+    const cm::EventPtrs ev{ev_x, ev_y, ev_t, ev_p, b->B.n_events};
+    double2* img = reinterpret_cast<double2*>(base + b->img_off);
+    StateHeader* hdrs = reinterpret_cast<StateHeader*>(base + b->hdr_off);
+    char* ws = base + b->ws_off;
+    std::vector<const void*> key{ev_x, ev_y, ev_t, ev_p, inv_depth, ego, loss, state};
+    return run_maybe_graph(b, b->fwd, std::move(key), static_cast<hipStream_t>(stream),
+                           [&](hipStream_t s, cm::Profiler* prof) {
+                               return cm::launch_forward_batch(b->B, b->d_meta, ev, inv_depth, ego,
+                                                               loss, img, hdrs, ws, s, prof);
+                           });
+}
+
+cm_status cm_loss_backward_batched(cm_batch b, const float* ev_x, const float* ev_y,
+                                   const float* ev_t, const int8_t* ev_p, const float* inv_depth,
+                                   const float* ego, void* state, const float* grad_loss,
+                                   float* grad_inv_depth, float* grad_ego, void* stream)
+{
+    if (!b || !events_valid(ev_x, ev_y, ev_t, ev_p, b->B.n_events) || !inv_depth || !ego ||
+        !state || !grad_loss || !grad_inv_depth || !grad_ego)
+        return CM_ERR_INVALID_ARG;
+    DeviceGuard g(b->h->device);
+    if (!g.ok()) return CM_ERR_HIP;
+    char* base = static_cast<char*>(state);
+    const cm::EventPtrs ev{ev_x, ev_y, ev_t, ev_p, b->B.n_events};
+    const double2* img = reinterpret_cast<const double2*>(base + b->img_off);
+    const StateHeader* hdrs = reinterpret_cast<const StateHeader*>(base + b->hdr_off);
+    char* ws = base + b->ws_off;
+    std::vector<const void*> key{ev_x, ev_y, ev_t, ev_p, inv_depth, ego, state, grad_loss,
+                                 grad_inv_depth, grad_ego};
+    return run_maybe_graph(b, b->bwd, std::move(key), static_cast<hipStream_t>(stream),
+                           [&](hipStream_t s, cm::Profiler* prof) {
+                               return cm::launch_backward_batch(b->B, b->d_meta, ev, inv_depth,
+                                                                ego, img, hdrs, grad_loss,
+                                                                grad_inv_depth, grad_ego, ws, s,
+                                                                prof);
+                           });
+}
+
+cm_status cm_batch_diagnostics(cm_batch b, const void* state, double* out, void* stream)
+{
+    if (!b || !state || !out) return CM_ERR_INVALID_ARG;
+    const int nw = b->B.nw;
+    std::vector<StateHeader> hdr(nw);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceGuard g(b->h->device);
+    if (!g.ok()) return CM_ERR_HIP;
+    if (hipMemcpyAsync(hdr.data(), static_cast<const char*>(state) + b->hdr_off,
+                       sizeof(StateHeader) * nw, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return CM_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return CM_ERR_HIP;
+    for (int w = 0; w < nw; ++w) {
+        out[2 * w] = hdr[w].loss;
+        out[2 * w + 1] = (double)hdr[w].n_valid;
+    }
+    return CM_OK;
 }
 
 }  // extern "C"

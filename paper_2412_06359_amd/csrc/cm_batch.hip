@@ -1,0 +1,965 @@
+// cm_batch.hip -- the tiled (owner-computes) path for one or many windows.
+//
+// Scattered global floating-point atomics run at about 22 G/s on MI355X
+// whatever the array size (one request per distinct cache line), while LDS
+// FP64 atomics run at about 1.4 T/s.  So instead of splatting every tap with a
+// global atomic, each warped position becomes a record binned by the 32x32
+// tile of its tap (x0, y0) (a counting sort: count, scan, scatter), and one
+// workgroup per tile accumulates its records in LDS and writes every pixel it
+// owns once with plain, coalesced stores.  A record's taps can reach one
+// column right of and one row below its tile; that halo goes to a small
+// buffer and a merge pass adds it, in a fixed order, into column 0 / row 0 of
+// the neighbouring tiles.
+//
+// Forward:  count -> chunk sums -> chunk scan -> scan -> offsets -> scatter
+//           -> tile -> merge -> finalize.  The per-reference sums of Eq. 1
+//           are reduced in the tile (interior) and merge (border) kernels.
+// Backward: the same sort over flow-sampling positions; the sweep re-runs
+//           each event's warp, gathers the adjoint seeds, runs the reverse
+//           sweep and emits one record per sampling position with
+//           dt * adjoint; the tile kernels turn the accumulated dL/du into
+//           d rho and d theta per pixel.
+//
+// Every kernel covers all windows of a batch in one launch: per-window
+// metadata (WinMeta) lives in device memory and each block or thread finds its
+// window by binary search over prefix offsets.  A single window is a batch of
+// one.
+#include "cm_kernels.hpp"
+
+namespace cm {
+
+// ---------------------------------------------------------------------------
+// Window lookup
+// ---------------------------------------------------------------------------
+
+// Largest w with key >= field(meta[w]) (fields are nondecreasing in w).
+template <typename F>
+__device__ __forceinline__ int find_window(const WinMeta* __restrict__ meta, int nw, int64_t key,
+                                           F field)
+{
+    int lo = 0, hi = nw - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (field(meta[mid]) <= key) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int window_of_block(const WinMeta* meta, int nw, int64_t b)
+{
+    return find_window(meta, nw, b, [](const WinMeta& m) { return m.blk_off; });
+}
+
+// ---------------------------------------------------------------------------
+// Counting sort of records into bins
+// ---------------------------------------------------------------------------
+
+// Visit the forward records of one event: fn(bin, r) for every reference.
+template <int RM, typename F>
+__device__ __forceinline__ void for_each_splat(const WinParams& P, const TileGeom& G,
+                                               const double (&px)[RM], const double (&py)[RM],
+                                               F&& fn)
+{
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        if (r < P.R) {
+            const Taps t = make_taps(P, px[r], py[r]);
+            fn(r * G.ntiles + tile_index(G, t), r);
+        }
+    }
+}
+
+template <int RM>
+__global__ __launch_bounds__(kBinThreads) void fwd_count_kernel(
+    const WinMeta* __restrict__ meta, int nw, const float* __restrict__ ex,
+    const float* __restrict__ ey, const float* __restrict__ et, const float* __restrict__ rho,
+    const float* __restrict__ ego, uint32_t* __restrict__ hist, StateHeader* __restrict__ hdrs)
+{
+    extern __shared__ uint32_t lh[];
+    __shared__ uint32_t cnt_lds;
+    const int w = window_of_block(meta, nw, blockIdx.x);
+    const WinParams& P = meta[w].P;
+    const TileGeom G = meta[w].G;
+    const int64_t lb = blockIdx.x - meta[w].blk_off;
+    const int64_t ev0 = meta[w].ev_off, n = meta[w].n;
+    for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) lh[i] = 0;
+    if (threadIdx.x == 0) cnt_lds = 0;
+    __syncthreads();
+    const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
+    const int64_t base = lb * kBinThreads * G.ept;
+    uint32_t cnt = 0;
+    for (int e = 0; e < G.ept; ++e) {
+        const int64_t k = base + (int64_t)e * kBinThreads + threadIdx.x;
+        if (k >= n) break;
+        double px[RM], py[RM];
+        int mb;
+        if (!warp_event<RM>(P, u, ex[ev0 + k], ey[ev0 + k], et[ev0 + k], px, py, mb)) continue;
+        ++cnt;
+        for_each_splat<RM>(P, G, px, py, [&](int bin, int) { atomicAdd(&lh[bin], 1u); });
+    }
+    if (cnt) atomicAdd(&cnt_lds, cnt);
+    __syncthreads();
+    uint32_t* row = hist + meta[w].hist_off + lb * G.nbins;
+    for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) row[i] = lh[i];
+    if (threadIdx.x == 0 && cnt_lds) atomicAdd(&hdrs[w].n_valid, (unsigned long long)cnt_lds);
+}
+
+// Column scan of each window's block x bin histogram in two levels: blocks
+// are grouped in chunks of kScanChunk rows; chunk sums, then a per-bin scan
+// over chunks, then the per-block offsets inside each chunk.  `bwd` selects
+// the backward bin space (one bin per tile).
+struct BinSpace {
+    __device__ __forceinline__ static int nbins(const WinMeta& m, bool bwd)
+    {
+        return bwd ? m.G.ntiles : m.G.nbins;
+    }
+    __device__ __forceinline__ static int64_t bin_off(const WinMeta& m, bool bwd)
+    {
+        return bwd ? m.tile_off : m.bin_off;
+    }
+    __device__ __forceinline__ static int64_t cell_off(const WinMeta& m, bool bwd)
+    {
+        return bwd ? m.cell_off_b : m.cell_off_f;
+    }
+};
+
+__global__ __launch_bounds__(256) void chunk_sum_kernel(const WinMeta* __restrict__ meta, int nw,
+                                                        int64_t ncells, int bwd,
+                                                        const uint32_t* __restrict__ hist,
+                                                        uint32_t* __restrict__ csum)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= ncells) return;
+    const int w = find_window(meta, nw, id,
+                              [bwd](const WinMeta& m) { return BinSpace::cell_off(m, bwd); });
+    const WinMeta& M = meta[w];
+    const int nbins = BinSpace::nbins(M, bwd);
+    const int64_t local = id - BinSpace::cell_off(M, bwd);
+    const int c = (int)(local / nbins), bin = (int)(local - (int64_t)c * nbins);
+    const int b0 = c * kScanChunk, b1 = min(b0 + kScanChunk, M.G.nblocks);
+    const uint32_t* h = hist + M.hist_off;
+    uint32_t s = 0;
+    for (int b = b0; b < b1; ++b) s += h[(size_t)b * nbins + bin];
+    csum[M.csum_off + (size_t)c * nbins + bin] = s;
+}
+
+// In place: csum[c][bin] <- sum over chunks before c; totals[global bin] = column total.
+__global__ __launch_bounds__(256) void chunk_scan_kernel(const WinMeta* __restrict__ meta, int nw,
+                                                         int64_t nbins_total, int bwd,
+                                                         uint32_t* __restrict__ csum,
+                                                         uint32_t* __restrict__ totals)
+{
+    const int64_t gbin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gbin >= nbins_total) return;
+    const int w = find_window(meta, nw, gbin,
+                              [bwd](const WinMeta& m) { return BinSpace::bin_off(m, bwd); });
+    const WinMeta& M = meta[w];
+    const int nbins = BinSpace::nbins(M, bwd);
+    const int bin = (int)(gbin - BinSpace::bin_off(M, bwd));
+    uint32_t* cs = csum + M.csum_off;
+    uint32_t run = 0;
+    for (int c = 0; c < M.nchunks; ++c) {
+        const uint32_t v = cs[(size_t)c * nbins + bin];
+        cs[(size_t)c * nbins + bin] = run;
+        run += v;
+    }
+    totals[gbin] = run;
+}
+
+// start[bin] = exclusive prefix sum of totals over all windows' bins;
+// start[nbins] = total.  One block.
+__global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__ totals,
+                                                    int64_t nbins, uint32_t* __restrict__ start)
+{
+    __shared__ uint32_t sums[1024];
+    const int64_t per = (nbins + 1023) / 1024;
+    const int64_t lo = std::min<int64_t>((int64_t)threadIdx.x * per, nbins);
+    const int64_t hi = std::min<int64_t>(lo + per, nbins);
+    uint32_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += totals[i];
+    sums[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = threadIdx.x >= (unsigned)off ? sums[threadIdx.x - off] : 0u;
+        __syncthreads();
+        sums[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = threadIdx.x ? sums[threadIdx.x - 1] : 0u;
+    for (int64_t i = lo; i < hi; ++i) {
+        start[i] = run;
+        run += totals[i];
+    }
+    if (threadIdx.x == 1023) start[nbins] = sums[1023];
+}
+
+// In place: hist[b][bin] <- start[global bin] + sum_{b' < b} hist[b'][bin].
+__global__ __launch_bounds__(256) void offsets_kernel(const WinMeta* __restrict__ meta, int nw,
+                                                      int64_t ncells, int bwd,
+                                                      uint32_t* __restrict__ hist,
+                                                      const uint32_t* __restrict__ csum,
+                                                      const uint32_t* __restrict__ start)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= ncells) return;
+    const int w = find_window(meta, nw, id,
+                              [bwd](const WinMeta& m) { return BinSpace::cell_off(m, bwd); });
+    const WinMeta& M = meta[w];
+    const int nbins = BinSpace::nbins(M, bwd);
+    const int64_t local = id - BinSpace::cell_off(M, bwd);
+    const int c = (int)(local / nbins), bin = (int)(local - (int64_t)c * nbins);
+    const int b0 = c * kScanChunk, b1 = min(b0 + kScanChunk, M.G.nblocks);
+    uint32_t* h = hist + M.hist_off;
+    uint32_t run = start[BinSpace::bin_off(M, bwd) + bin] + csum[M.csum_off + (size_t)c * nbins + bin];
+    for (int b = b0; b < b1; ++b) {
+        const uint32_t v = h[(size_t)b * nbins + bin];
+        h[(size_t)b * nbins + bin] = run;
+        run += v;
+    }
+}
+
+template <int RM>
+__global__ __launch_bounds__(kBinThreads) void fwd_scatter_kernel(
+    const WinMeta* __restrict__ meta, int nw, const float* __restrict__ ex,
+    const float* __restrict__ ey, const float* __restrict__ et, const int8_t* __restrict__ ep,
+    const float* __restrict__ rho, const float* __restrict__ ego,
+    const uint32_t* __restrict__ offs, SplatRec* __restrict__ rec)
+{
+    extern __shared__ uint32_t lh[];
+    const int w = window_of_block(meta, nw, blockIdx.x);
+    const WinParams& P = meta[w].P;
+    const TileGeom G = meta[w].G;
+    const int64_t lb = blockIdx.x - meta[w].blk_off;
+    const int64_t ev0 = meta[w].ev_off, n = meta[w].n;
+    const uint32_t* row = offs + meta[w].hist_off + lb * G.nbins;
+    for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) lh[i] = row[i];
+    __syncthreads();
+    const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
+    const int64_t base = lb * kBinThreads * G.ept;
+    for (int e = 0; e < G.ept; ++e) {
+        const int64_t k = base + (int64_t)e * kBinThreads + threadIdx.x;
+        if (k >= n) break;
+        double px[RM], py[RM];
+        int mb;
+        const float tk = et[ev0 + k];
+        if (!warp_event<RM>(P, u, ex[ev0 + k], ey[ev0 + k], tk, px, py, mb)) continue;
+        const float ts = ep[ev0 + k] > 0 ? tk : -tk;   // t >= 0 here; sign bit = negative polarity
+        for_each_splat<RM>(P, G, px, py, [&](int bin, int r) {
+            const uint32_t slot = atomicAdd(&lh[bin], 1u);
+            SplatRec q;
+            q.X = sel(px, r);
+            q.Y = sel(py, r);
+            q.ts = ts;
+            q.k = (uint32_t)k;
+            rec[slot] = q;
+        });
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward tile kernels
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void reduce_pixel(double2 a, double2 b, double eps, double& sum,
+                                             double& cnt)
+{
+    if (a.x + b.x > 0.0) cnt += 1.0;
+    if (a.x != 0.0 || a.y != 0.0) {
+        const double T = a.y / (a.x + eps);
+        sum += T * T;
+    }
+    if (b.x != 0.0 || b.y != 0.0) {
+        const double T = b.y / (b.x + eps);
+        sum += T * T;
+    }
+}
+
+__device__ __forceinline__ void split_bin(const TileGeom& G, int bin, int& r, int& tx, int& ty)
+{
+    r = bin / G.ntiles;
+    const int tile = bin - r * G.ntiles;
+    ty = tile / G.ntx;
+    tx = tile - ty * G.ntx;
+}
+
+__device__ __forceinline__ int window_of_bin(const WinMeta* meta, int nw, int64_t gbin)
+{
+    return find_window(meta, nw, gbin, [](const WinMeta& m) { return m.bin_off; });
+}
+
+__device__ __forceinline__ int window_of_tile(const WinMeta* meta, int nw, int64_t gtile)
+{
+    return find_window(meta, nw, gtile, [](const WinMeta& m) { return m.tile_off; });
+}
+
+__global__ __launch_bounds__(256) void fwd_tile_kernel(const WinMeta* __restrict__ meta, int nw,
+                                                       const SplatRec* __restrict__ rec,
+                                                       const uint32_t* __restrict__ start,
+                                                       double2* __restrict__ img_base,
+                                                       double2* __restrict__ halo,
+                                                       double* __restrict__ part)
+{
+    __shared__ double2 lds[2 * TLW * TLH];
+    __shared__ double red[16];
+    const int64_t gbin = blockIdx.x;
+    const int w = window_of_bin(meta, nw, gbin);
+    const WinParams& P = meta[w].P;
+    const TileGeom G = meta[w].G;
+    int r, tx, ty;
+    split_bin(G, (int)(gbin - meta[w].bin_off), r, tx, ty);
+    const int xo = tx * TW, yo = ty * TH;
+    for (int i = threadIdx.x; i < 2 * TLW * TLH; i += blockDim.x) lds[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+    const double ref = P.refs[r];
+    const uint32_t s0 = start[gbin], s1 = start[gbin + 1];
+    for (uint32_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+        const SplatRec q = rec[i];
+        const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
+        const double tb = 1.0 - fabs(ref - (double)fabsf(q.ts));
+        const Taps tp = make_taps(P, q.X, q.Y);
+        const int lx = tp.x0 - xo, ly = tp.y0 - yo;
+        double2* L = lds + pol * TLW * TLH;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (!tap_in(tp, c)) continue;
+            const double wt = tap_w(tp, c);
+            if (wt == 0.0) continue;
+            double2* cell = L + (ly + (c >> 1)) * TLW + lx + (c & 1);
+            atomicAdd(&cell->x, wt);
+            atomicAdd(&cell->y, wt * tb);
+        }
+    }
+    __syncthreads();
+    double sum = 0.0, cnt = 0.0;
+    double2* img = img_base + meta[w].img_off;
+    double2* plane0 = img + (size_t)(r * 2 + 0) * P.HW;
+    double2* plane1 = img + (size_t)(r * 2 + 1) * P.HW;
+    for (int i = threadIdx.x; i < TW * TH; i += blockDim.x) {
+        const int lx = i % TW, ly = i / TW;
+        const int X = xo + lx, Y = yo + ly;
+        if (X >= P.W || Y >= P.H) continue;
+        const double2 a = lds[ly * TLW + lx], b = lds[TLW * TLH + ly * TLW + lx];
+        const int pix = Y * P.W + X;
+        plane0[pix] = a;
+        plane1[pix] = b;
+        if (lx > 0 && ly > 0) reduce_pixel(a, b, P.eps, sum, cnt);
+    }
+    double2* hb = halo + gbin * NHALO * 2;
+    for (int j = threadIdx.x; j < NHALO; j += blockDim.x) {
+        const int idx = (j <= TH) ? j * TLW + TW : TH * TLW + (j - (TH + 1));
+        hb[j * 2 + 0] = lds[idx];
+        hb[j * 2 + 1] = lds[TLW * TLH + idx];
+    }
+    sum = block_sum(sum, red);
+    cnt = block_sum(cnt, red);
+    if (threadIdx.x == 0) {
+        part[(gbin * 2 + 0) * 2 + 0] = sum;
+        part[(gbin * 2 + 0) * 2 + 1] = cnt;
+    }
+}
+
+// Column 0 and row 0 of each tile: add the halos of the left, top and
+// top-left tiles (in that order), store, and reduce those pixels.
+__global__ __launch_bounds__(64) void fwd_merge_kernel(const WinMeta* __restrict__ meta, int nw,
+                                                       double2* __restrict__ img_base,
+                                                       const double2* __restrict__ halo,
+                                                       double* __restrict__ part)
+{
+    __shared__ double red[16];
+    const int64_t gbin = blockIdx.x;
+    const int w = window_of_bin(meta, nw, gbin);
+    const WinParams& P = meta[w].P;
+    const TileGeom G = meta[w].G;
+    int r, tx, ty;
+    split_bin(G, (int)(gbin - meta[w].bin_off), r, tx, ty);
+    const int xo = tx * TW, yo = ty * TH;
+    double2* img = img_base + meta[w].img_off;
+    double sum = 0.0, cnt = 0.0;
+    for (int j = threadIdx.x; j < NBORDER; j += blockDim.x) {
+        const int lx = j < TH ? 0 : j - TH + 1;
+        const int ly = j < TH ? j : 0;
+        const int X = xo + lx, Y = yo + ly;
+        if (X >= P.W || Y >= P.H) continue;
+        const int pix = Y * P.W + X;
+        double2 v[2];
+#pragma unroll
+        for (int pol = 0; pol < 2; ++pol) {
+            double2 a = img[(size_t)(r * 2 + pol) * P.HW + pix];
+            if (lx == 0 && tx > 0) {
+                const double2 h = halo[((gbin - 1) * NHALO + ly) * 2 + pol];
+                a.x += h.x;
+                a.y += h.y;
+            }
+            if (ly == 0 && ty > 0) {
+                const double2 h = halo[((gbin - G.ntx) * NHALO + TH + 1 + lx) * 2 + pol];
+                a.x += h.x;
+                a.y += h.y;
+            }
+            if (lx == 0 && ly == 0 && tx > 0 && ty > 0) {
+                const double2 h = halo[((gbin - G.ntx - 1) * NHALO + TH) * 2 + pol];
+                a.x += h.x;
+                a.y += h.y;
+            }
+            img[(size_t)(r * 2 + pol) * P.HW + pix] = a;
+            v[pol] = a;
+        }
+        reduce_pixel(v[0], v[1], P.eps, sum, cnt);
+    }
+    sum = block_sum(sum, red);
+    cnt = block_sum(cnt, red);
+    if (threadIdx.x == 0) {
+        part[(gbin * 2 + 1) * 2 + 0] = sum;
+        part[(gbin * 2 + 1) * 2 + 1] = cnt;
+    }
+}
+
+// One block per window: fixed-order sums of the tile and merge partials per
+// reference, then Eq. 1.
+__global__ __launch_bounds__(256) void fwd_finalize_kernel(const WinMeta* __restrict__ meta,
+                                                           const double* __restrict__ part,
+                                                           StateHeader* __restrict__ hdrs,
+                                                           float* __restrict__ loss)
+{
+    __shared__ double red[16];
+    const int w = blockIdx.x;
+    const WinParams& P = meta[w].P;
+    const TileGeom G = meta[w].G;
+    const double* pw = part + meta[w].bin_off * 4;
+    StateHeader* hdr = hdrs + w;
+    double L = 0.0;
+    for (int r = 0; r < P.R; ++r) {
+        double s = 0.0, c = 0.0;
+        for (int j = threadIdx.x; j < 2 * G.ntiles; j += blockDim.x) {
+            s += pw[((size_t)r * 2 * G.ntiles + j) * 2 + 0];
+            c += pw[((size_t)r * 2 * G.ntiles + j) * 2 + 1];
+        }
+        s = block_sum(s, red);
+        c = block_sum(c, red);
+        if (threadIdx.x == 0) {
+            hdr->num[r] = s;
+            hdr->nact[r] = c;
+            L += s / (c + P.eps);
+        }
+    }
+    if (threadIdx.x == 0) {
+        L = L / (double)P.R;
+        hdr->loss = L;
+        loss[w] = (float)L;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backward: one record per flow-sampling position.  The forward sweep into
+// reference r samples the flow at the previous position (the event for the
+// first step), the backward sweep likewise; both first steps sample at the
+// event, so their contributions share one record.
+// ---------------------------------------------------------------------------
+
+// fn(X, Y) for every sampling position that is a reference position, then
+// fn(x0, y0) once for the event if it takes any step.
+template <int RM, typename F>
+__device__ __forceinline__ void for_each_sample(const WinParams& P, int rs, int mb,
+                                                const double (&px)[RM], const double (&py)[RM],
+                                                double x0, double y0, F&& fn)
+{
+    for (int r = rs + 1; r < P.R; ++r) fn(sel(px, r - 1), sel(py, r - 1));
+    for (int r = mb - 2; r >= 0; --r) fn(sel(px, r + 1), sel(py, r + 1));
+    if (rs < P.R || mb > 0) fn(x0, y0);
+}
+
+__device__ __forceinline__ int first_forward_ref(const WinParams& P, int mb, double tk)
+{
+    return (mb < P.R && P.refs[mb] == tk) ? mb + 1 : mb;
+}
+
+template <int RM>
+__global__ __launch_bounds__(kBinThreads) void bwd_count_kernel(
+    const WinMeta* __restrict__ meta, int nw, const float* __restrict__ ex,
+    const float* __restrict__ ey, const float* __restrict__ et, const float* __restrict__ rho,
+    const float* __restrict__ ego, uint32_t* __restrict__ hist)
+{
+    extern __shared__ uint32_t lh[];
+    const int w = window_of_block(meta, nw, blockIdx.x);
+    const WinParams& P = meta[w].P;
+    const TileGeom G = meta[w].G;
+    const int64_t lb = blockIdx.x - meta[w].blk_off;
+    const int64_t ev0 = meta[w].ev_off, n = meta[w].n;
+    for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x) lh[i] = 0;
+    __syncthreads();
+    const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
+    const int64_t base = lb * kBinThreads * G.ept;
+    for (int e = 0; e < G.ept; ++e) {
+        const int64_t k = base + (int64_t)e * kBinThreads + threadIdx.x;
+        if (k >= n) break;
+        double px[RM], py[RM];
+        int mb;
+        const double x0 = ex[ev0 + k], y0 = ey[ev0 + k], tk = et[ev0 + k];
+        if (!warp_event<RM>(P, u, x0, y0, tk, px, py, mb)) continue;
+        const int rs = first_forward_ref(P, mb, tk);
+        for_each_sample<RM>(P, rs, mb, px, py, x0, y0, [&](double X, double Y) {
+            atomicAdd(&lh[tile_index(G, make_taps(P, X, Y))], 1u);
+        });
+    }
+    __syncthreads();
+    uint32_t* row = hist + meta[w].hist_off + lb * G.ntiles;
+    for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x) row[i] = lh[i];
+}
+
+template <int RM>
+__global__ __launch_bounds__(kBinThreads) void bwd_sweep_kernel(
+    const WinMeta* __restrict__ meta, int nw, const float* __restrict__ ex,
+    const float* __restrict__ ey, const float* __restrict__ et, const int8_t* __restrict__ ep,
+    const float* __restrict__ rho, const float* __restrict__ ego,
+    const double2* __restrict__ img_base, const StateHeader* __restrict__ hdrs,
+    const uint32_t* __restrict__ offs, GradRec* __restrict__ rec)
+{
+    extern __shared__ uint32_t lh[];
+    const int w = window_of_block(meta, nw, blockIdx.x);
+    const WinParams& P = meta[w].P;
+    const TileGeom G = meta[w].G;
+    const int64_t lb = blockIdx.x - meta[w].blk_off;
+    const int64_t ev0 = meta[w].ev_off, n = meta[w].n;
+    const uint32_t* row = offs + meta[w].hist_off + lb * G.ntiles;
+    for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x) lh[i] = row[i];
+    __syncthreads();
+    const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
+    const StateHeader* hdr = hdrs + w;
+    double coef[RM];
+#pragma unroll
+    for (int r = 0; r < RM; ++r) coef[r] = r < P.R ? P.two_over_R / (hdr->nact[r] + P.eps) : 0.0;
+    const double2* img = img_base + meta[w].img_off;
+    const int64_t base = lb * kBinThreads * G.ept;
+
+    auto emit = [&](double X, double Y, double gx, double gy) {
+        const uint32_t slot = atomicAdd(&lh[tile_index(G, make_taps(P, X, Y))], 1u);
+        GradRec q;
+        q.X = X;
+        q.Y = Y;
+        q.gx = gx;
+        q.gy = gy;
+        rec[slot] = q;
+    };
+
+    for (int e = 0; e < G.ept; ++e) {
+        const int64_t k = base + (int64_t)e * kBinThreads + threadIdx.x;
+        if (k >= n) break;
+        double px[RM], py[RM];
+        int mb;
+        const double x0 = ex[ev0 + k], y0 = ey[ev0 + k], tk = et[ev0 + k];
+        if (!warp_event<RM>(P, u, x0, y0, tk, px, py, mb)) continue;
+        const int pol = ep[ev0 + k] > 0 ? 0 : 1;
+        const double2* planes = img + (size_t)pol * P.HW;
+        const int rs = first_forward_ref(P, mb, tk);
+        const int nv = (P.R - rs) + mb;
+        double g0x = 0.0, g0y = 0.0;     // contributions sampled at the event position
+        double Lx = 0.0, Ly = 0.0;
+        for (int j = 0; j < nv; ++j) {
+            const ReverseStep s = reverse_step<RM>(P, j, rs, mb, x0, y0, tk, px, py);
+            if (s.restart) {
+                Lx = 0.0;
+                Ly = 0.0;
+            }
+            direct_term(P, planes + (size_t)s.r * 2 * P.HW, sel(coef, s.r),
+                        1.0 - fabs(P.refs[s.r] - tk), sel(px, s.r), sel(py, s.r), Lx, Ly);
+            if (s.first) {
+                g0x += s.dt * Lx;
+                g0y += s.dt * Ly;
+            } else {
+                emit(s.X, s.Y, s.dt * Lx, s.dt * Ly);
+                double jx, jy;
+                jacobian_t(P, u, s.X, s.Y, Lx, Ly, jx, jy);
+                Lx += s.dt * jx;
+                Ly += s.dt * jy;
+            }
+        }
+        if (nv > 0) emit(x0, y0, g0x, g0y);
+    }
+}
+
+// Accumulate dL/du = sum over records of w_tap * (dt * adjoint) in LDS; own
+// pixels off the border get d rho and their d theta share here, the border
+// and the halo go to buffers for the merge.
+__global__ __launch_bounds__(256) void bwd_tile_kernel(
+    const WinMeta* __restrict__ meta, int nw, const GradRec* __restrict__ rec,
+    const uint32_t* __restrict__ start, const float* __restrict__ rho,
+    const float* __restrict__ ego, const float* __restrict__ grad_loss,
+    float* __restrict__ drho, double2* __restrict__ halo, double2* __restrict__ border,
+    double* __restrict__ part)
+{
+    __shared__ double2 lds[TLW * TLH];
+    __shared__ double red[16];
+    const int64_t gtile = blockIdx.x;
+    const int w = window_of_tile(meta, nw, gtile);
+    const WinParams& P = meta[w].P;
+    const TileGeom G = meta[w].G;
+    const int tile = (int)(gtile - meta[w].tile_off);
+    const int ty = tile / G.ntx, tx = tile - ty * G.ntx;
+    const int xo = tx * TW, yo = ty * TH;
+    for (int i = threadIdx.x; i < TLW * TLH; i += blockDim.x) lds[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+    const uint32_t s0 = start[gtile], s1 = start[gtile + 1];
+    for (uint32_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+        const GradRec q = rec[i];
+        const Taps tp = make_taps(P, q.X, q.Y);
+        const int lx = tp.x0 - xo, ly = tp.y0 - yo;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (!tap_in(tp, c)) continue;
+            const double wt = tap_w(tp, c);
+            if (wt == 0.0) continue;
+            double2* cell = lds + (ly + (c >> 1)) * TLW + lx + (c & 1);
+            atomicAdd(&cell->x, wt * q.gx);
+            atomicAdd(&cell->y, wt * q.gy);
+        }
+    }
+    __syncthreads();
+    const Motion m = load_motion(P, ego + 6 * w);
+    const float* rho_w = rho + meta[w].pix_off;
+    float* drho_w = drho + meta[w].pix_off;
+    const double gl = (double)grad_loss[w];
+    double dth[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < TW * TH; i += blockDim.x) {
+        const int lx = i % TW, ly = i / TW;
+        const int X = xo + lx, Y = yo + ly;
+        if (X >= P.W || Y >= P.H) continue;
+        const double2 g = lds[ly * TLW + lx];
+        if (lx == 0 || ly == 0) {
+            border[gtile * NBORDER + (lx == 0 ? ly : TH + lx - 1)] = g;
+            continue;
+        }
+        const int pix = Y * P.W + X;
+        double Ax, Ay, Bx, By;
+        flow_parts(P, m, X, Y, Ax, Ay, Bx, By);
+        drho_w[pix] = (float)(gl * (g.x * Bx + g.y * By));
+        if (g.x != 0.0 || g.y != 0.0) dtheta_at_pixel(P, X, Y, (double)rho_w[pix], g.x, g.y, dth);
+    }
+    double2* hb = halo + gtile * NHALO;
+    for (int j = threadIdx.x; j < NHALO; j += blockDim.x) {
+        const int idx = (j <= TH) ? j * TLW + TW : TH * TLW + (j - (TH + 1));
+        hb[j] = lds[idx];
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const double v = block_sum(dth[c], red);
+        if (threadIdx.x == 0) part[gtile * 12 + c] = v;
+    }
+}
+
+__global__ __launch_bounds__(64) void bwd_merge_kernel(
+    const WinMeta* __restrict__ meta, int nw, const float* __restrict__ rho,
+    const float* __restrict__ ego, const float* __restrict__ grad_loss,
+    float* __restrict__ drho, const double2* __restrict__ halo,
+    const double2* __restrict__ border, double* __restrict__ part)
+{
+    __shared__ double red[16];
+    const int64_t gtile = blockIdx.x;
+    const int w = window_of_tile(meta, nw, gtile);
+    const WinParams& P = meta[w].P;
+    const TileGeom G = meta[w].G;
+    const int tile = (int)(gtile - meta[w].tile_off);
+    const int ty = tile / G.ntx, tx = tile - ty * G.ntx;
+    const int xo = tx * TW, yo = ty * TH;
+    const Motion m = load_motion(P, ego + 6 * w);
+    const float* rho_w = rho + meta[w].pix_off;
+    float* drho_w = drho + meta[w].pix_off;
+    const double gl = (double)grad_loss[w];
+    double dth[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int j = threadIdx.x; j < NBORDER; j += blockDim.x) {
+        const int lx = j < TH ? 0 : j - TH + 1;
+        const int ly = j < TH ? j : 0;
+        const int X = xo + lx, Y = yo + ly;
+        if (X >= P.W || Y >= P.H) continue;
+        double2 g = border[gtile * NBORDER + j];
+        if (lx == 0 && tx > 0) {
+            const double2 h = halo[(gtile - 1) * NHALO + ly];
+            g.x += h.x;
+            g.y += h.y;
+        }
+        if (ly == 0 && ty > 0) {
+            const double2 h = halo[(gtile - G.ntx) * NHALO + TH + 1 + lx];
+            g.x += h.x;
+            g.y += h.y;
+        }
+        if (lx == 0 && ly == 0 && tx > 0 && ty > 0) {
+            const double2 h = halo[(gtile - G.ntx - 1) * NHALO + TH];
+            g.x += h.x;
+            g.y += h.y;
+        }
+        const int pix = Y * P.W + X;
+        double Ax, Ay, Bx, By;
+        flow_parts(P, m, X, Y, Ax, Ay, Bx, By);
+        drho_w[pix] = (float)(gl * (g.x * Bx + g.y * By));
+        if (g.x != 0.0 || g.y != 0.0) dtheta_at_pixel(P, X, Y, (double)rho_w[pix], g.x, g.y, dth);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const double v = block_sum(dth[c], red);
+        if (threadIdx.x == 0) part[gtile * 12 + 6 + c] = v;
+    }
+}
+
+// One block per window: fixed-order sum of its tiles' d theta partials.
+__global__ __launch_bounds__(256) void bwd_finalize_kernel(const WinMeta* __restrict__ meta,
+                                                           const double* __restrict__ part,
+                                                           const float* __restrict__ grad_loss,
+                                                           float* __restrict__ grad_ego)
+{
+    __shared__ double red[16];
+    const int w = blockIdx.x;
+    const int ntiles = meta[w].G.ntiles;
+    const double* pw = part + meta[w].tile_off * 12;
+    const double gl = (double)grad_loss[w];
+    for (int c = 0; c < 6; ++c) {
+        double s = 0.0;
+        for (int j = threadIdx.x; j < 2 * ntiles; j += blockDim.x) s += pw[(size_t)j * 6 + c];
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) grad_ego[w * 6 + c] = (float)(gl * s);
+    }
+}
+
+// Clears the per-window sums (n_valid is accumulated with atomics).
+__global__ __launch_bounds__(256) void clear_headers_kernel(StateHeader* __restrict__ hdrs, int nw)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nw) {
+        StateHeader z;
+        z.loss = 0.0;
+        z.n_valid = 0;
+        for (int r = 0; r < kMaxRefs; ++r) {
+            z.num[r] = 0.0;
+            z.nact[r] = 0.0;
+        }
+        hdrs[i] = z;
+    }
+}
+
+// Writes one window's metadata (single-window calls pass it by value).
+__global__ void store_meta_kernel(WinMeta m, WinMeta* __restrict__ out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = m;
+}
+
+// ---------------------------------------------------------------------------
+// Host side: geometry, layout, launches
+// ---------------------------------------------------------------------------
+
+TileGeom tile_geom(const WinParams& P, int64_t n)
+{
+    TileGeom G;
+    G.ntx = (P.W + TW - 1) / TW;
+    G.nty = (P.H + TH - 1) / TH;
+    G.ntiles = G.ntx * G.nty;
+    G.nbins = P.R * G.ntiles;
+    // enough blocks to fill the chip, few enough to keep the histogram matrix small
+    const int64_t ept = n / ((int64_t)kBinThreads * 1024);
+    G.ept = (int)std::max<int64_t>(1, std::min<int64_t>(ept, kMaxEventsPerThread));
+    const int64_t per_block = (int64_t)kBinThreads * G.ept;
+    G.nblocks = (int)std::max<int64_t>(1, (n + per_block - 1) / per_block);
+    return G;
+}
+
+bool tiled_supported(const WinParams& P, int64_t n)
+{
+    const TileGeom G = tile_geom(P, n);
+    return G.nbins <= kMaxBins && n * (int64_t)P.R < ((int64_t)1 << 31);
+}
+
+BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int nw)
+{
+    BatchPlanHost B;
+    B.nw = nw;
+    B.meta.resize(nw);
+    int64_t ev = 0, pix = 0, img = 0, hist = 0, csum = 0, bin = 0, tile = 0, blk = 0;
+    int64_t cf = 0, cb = 0, recs = 0;
+    B.max_R = 1;
+    B.max_lds_bins = 1;
+    for (int w = 0; w < nw; ++w) {
+        WinMeta& M = B.meta[w];
+        std::memset(&M, 0, sizeof M);
+        M.P = params[w];
+        M.G = tile_geom(M.P, n_events[w]);
+        M.nchunks = (M.G.nblocks + kScanChunk - 1) / kScanChunk;
+        M.ev_off = ev;
+        M.n = n_events[w];
+        M.pix_off = pix;
+        M.img_off = img;
+        M.hist_off = hist;
+        M.csum_off = csum;
+        M.bin_off = bin;
+        M.tile_off = tile;
+        M.blk_off = blk;
+        M.cell_off_f = cf;
+        M.cell_off_b = cb;
+        ev += M.n;
+        pix += M.P.HW;
+        img += (int64_t)2 * M.P.R * M.P.HW;
+        hist += (int64_t)M.G.nblocks * M.G.nbins;
+        csum += (int64_t)M.nchunks * M.G.nbins;
+        bin += M.G.nbins;
+        tile += M.G.ntiles;
+        blk += M.G.nblocks;
+        cf += (int64_t)M.nchunks * M.G.nbins;
+        cb += (int64_t)M.nchunks * M.G.ntiles;
+        recs += M.n * M.P.R;
+        B.max_R = std::max(B.max_R, M.P.R);
+        B.max_lds_bins = std::max(B.max_lds_bins, M.G.nbins);
+    }
+    B.n_events = ev;
+    B.n_pixels = pix;
+    B.img_elems = img;
+    B.nbins = bin;
+    B.ntiles = tile;
+    B.nblocks = blk;
+    B.cells_f = cf;
+    B.cells_b = cb;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    B.ws.hist = take((size_t)hist * sizeof(uint32_t));
+    B.ws.csum = take((size_t)csum * sizeof(uint32_t));
+    B.ws.totals = take((size_t)(bin + 1) * sizeof(uint32_t));
+    B.ws.start = take((size_t)(bin + 1) * sizeof(uint32_t));
+    B.ws.part = take((size_t)std::max(bin * 4, tile * 12) * sizeof(double));
+    B.ws.halo = take((size_t)std::max<int64_t>(bin * NHALO * 2, tile * (NHALO + NBORDER)) *
+                     sizeof(double2));
+    B.ws.records = take((size_t)recs * std::max(sizeof(SplatRec), sizeof(GradRec)));
+    B.ws.total = off;
+    return B;
+}
+
+template <int RM>
+static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
+                                   const EventPtrs& ev, const float* rho, const float* ego,
+                                   float* loss, double2* img, StateHeader* hdrs, char* ws,
+                                   hipStream_t s, Profiler* prof)
+{
+    const int nw = B.nw;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(ws + B.ws.hist);
+    uint32_t* csum = reinterpret_cast<uint32_t*>(ws + B.ws.csum);
+    uint32_t* totals = reinterpret_cast<uint32_t*>(ws + B.ws.totals);
+    uint32_t* start = reinterpret_cast<uint32_t*>(ws + B.ws.start);
+    double* part = reinterpret_cast<double*>(ws + B.ws.part);
+    double2* halo = reinterpret_cast<double2*>(ws + B.ws.halo);
+    SplatRec* rec = reinterpret_cast<SplatRec*>(ws + B.ws.records);
+    const size_t lds = (size_t)B.max_lds_bins * sizeof(uint32_t);
+    {
+        PhaseScope ph(prof, kPhZero, s);
+        clear_headers_kernel<<<(nw + 255) / 256, 256, 0, s>>>(hdrs, nw);
+    }
+    {
+        PhaseScope ph(prof, kPhCount, s);
+        fwd_count_kernel<RM><<<B.nblocks, kBinThreads, lds, s>>>(meta, nw, ev.x, ev.y, ev.t, rho,
+                                                                 ego, hist, hdrs);
+    }
+    {
+        PhaseScope ph(prof, kPhScan, s);
+        const int gc = (int)((B.cells_f + 255) / 256);
+        chunk_sum_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_f, 0, hist, csum);
+        chunk_scan_kernel<<<(int)((B.nbins + 255) / 256), 256, 0, s>>>(meta, nw, B.nbins, 0, csum,
+                                                                        totals);
+        scan_kernel<<<1, 1024, 0, s>>>(totals, B.nbins, start);
+        offsets_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_f, 0, hist, csum, start);
+    }
+    {
+        PhaseScope ph(prof, kPhScatter, s);
+        fwd_scatter_kernel<RM><<<B.nblocks, kBinThreads, lds, s>>>(meta, nw, ev.x, ev.y, ev.t,
+                                                                   ev.p, rho, ego, hist, rec);
+    }
+    {
+        PhaseScope ph(prof, kPhSplat, s);
+        fwd_tile_kernel<<<(int)B.nbins, 256, 0, s>>>(meta, nw, rec, start, img, halo, part);
+    }
+    {
+        PhaseScope ph(prof, kPhReduce, s);
+        fwd_merge_kernel<<<(int)B.nbins, 64, 0, s>>>(meta, nw, img, halo, part);
+    }
+    {
+        PhaseScope ph(prof, kPhFinalize, s);
+        fwd_finalize_kernel<<<nw, 256, 0, s>>>(meta, part, hdrs, loss);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_batch(const BatchPlanHost& B, const WinMeta* meta, const EventPtrs& ev,
+                                const float* rho, const float* ego, float* loss, double2* img,
+                                StateHeader* hdrs, char* ws, hipStream_t s, Profiler* prof)
+{
+    if (B.max_R <= 2) return batch_forward_rm<2>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof);
+    if (B.max_R <= 4) return batch_forward_rm<4>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof);
+    if (B.max_R <= 8) return batch_forward_rm<8>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof);
+    return batch_forward_rm<16>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof);
+}
+
+template <int RM>
+static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
+                                    const EventPtrs& ev, const float* rho, const float* ego,
+                                    const double2* img, const StateHeader* hdrs,
+                                    const float* grad_loss, float* grad_rho, float* grad_ego,
+                                    char* ws, hipStream_t s, Profiler* prof)
+{
+    const int nw = B.nw;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(ws + B.ws.hist);
+    uint32_t* csum = reinterpret_cast<uint32_t*>(ws + B.ws.csum);
+    uint32_t* totals = reinterpret_cast<uint32_t*>(ws + B.ws.totals);
+    uint32_t* start = reinterpret_cast<uint32_t*>(ws + B.ws.start);
+    double* part = reinterpret_cast<double*>(ws + B.ws.part);
+    double2* halo = reinterpret_cast<double2*>(ws + B.ws.halo);
+    double2* border = halo + B.ntiles * NHALO;
+    GradRec* rec = reinterpret_cast<GradRec*>(ws + B.ws.records);
+    const size_t lds = (size_t)B.max_lds_bins * sizeof(uint32_t);
+    {
+        PhaseScope ph(prof, kPhGradCount, s);
+        bwd_count_kernel<RM><<<B.nblocks, kBinThreads, lds, s>>>(meta, nw, ev.x, ev.y, ev.t, rho,
+                                                                 ego, hist);
+    }
+    {
+        PhaseScope ph(prof, kPhGradScan, s);
+        const int gc = (int)((B.cells_b + 255) / 256);
+        chunk_sum_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_b, 1, hist, csum);
+        chunk_scan_kernel<<<(int)((B.ntiles + 255) / 256), 256, 0, s>>>(meta, nw, B.ntiles, 1,
+                                                                          csum, totals);
+        scan_kernel<<<1, 1024, 0, s>>>(totals, B.ntiles, start);
+        offsets_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_b, 1, hist, csum, start);
+    }
+    {
+        PhaseScope ph(prof, kPhAdjoint, s);
+        bwd_sweep_kernel<RM><<<B.nblocks, kBinThreads, lds, s>>>(meta, nw, ev.x, ev.y, ev.t, ev.p,
+                                                                 rho, ego, img, hdrs, hist, rec);
+    }
+    {
+        PhaseScope ph(prof, kPhGradTile, s);
+        bwd_tile_kernel<<<(int)B.ntiles, 256, 0, s>>>(meta, nw, rec, start, rho, ego, grad_loss,
+                                                      grad_rho, halo, border, part);
+        bwd_merge_kernel<<<(int)B.ntiles, 64, 0, s>>>(meta, nw, rho, ego, grad_loss, grad_rho,
+                                                      halo, border, part);
+    }
+    {
+        PhaseScope ph(prof, kPhGradFinalize, s);
+        bwd_finalize_kernel<<<nw, 256, 0, s>>>(meta, part, grad_loss, grad_ego);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_backward_batch(const BatchPlanHost& B, const WinMeta* meta,
+                                 const EventPtrs& ev, const float* rho, const float* ego,
+                                 const double2* img, const StateHeader* hdrs,
+                                 const float* grad_loss, float* grad_rho, float* grad_ego,
+                                 char* ws, hipStream_t s, Profiler* prof)
+{
+    if (B.max_R <= 2) return batch_backward_rm<2>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof);
+    if (B.max_R <= 4) return batch_backward_rm<4>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof);
+    if (B.max_R <= 8) return batch_backward_rm<8>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof);
+    return batch_backward_rm<16>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof);
+}
+
+hipError_t launch_store_meta(const WinMeta& m, WinMeta* out, hipStream_t s)
+{
+    store_meta_kernel<<<1, 64, 0, s>>>(m, out);
+    return hipGetLastError();
+}
+
+}  // namespace cm

@@ -391,6 +391,7 @@ constexpr int kMaxBins = 16384;              // LDS histogram limit (64 KB)
 constexpr int kBinThreads = 256;             // threads of the count / scatter kernels
 constexpr int kMaxEventsPerThread = 16;
 
+
 struct TileGeom {
     int ntx, nty, ntiles;   // tiles per row / column / image
     int nbins;              // bins of this pass (R * ntiles forward, ntiles backward)

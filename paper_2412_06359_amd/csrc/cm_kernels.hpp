@@ -2,6 +2,7 @@
 #pragma once
 
 #include <algorithm>
+#include <cstring>
 #include <vector>
 #include <stdint.h>
 
@@ -98,9 +99,40 @@ enum Phase {
     kPhCount, kPhScan, kPhScatter, kPhGradCount, kPhGradScan, kPhGradTile, kNumPhases
 };
 
+// Per-window metadata of the tiled path (device memory).  All offsets are
+// into flat arrays shared by the windows of a batch.
+struct WinMeta {
+    WinParams P;
+    TileGeom G;             // forward bins R * ntiles; backward bins = tiles
+    int nchunks;            // column-scan chunks of this window's count blocks
+    int pad_;
+    int64_t ev_off, n;      // events [ev_off, ev_off + n) of the flat event arrays
+    int64_t pix_off;        // first pixel of rho / d rho
+    int64_t img_off;        // first image element (double2) in the state
+    int64_t hist_off;       // first histogram cell
+    int64_t csum_off;       // first chunk-sum cell
+    int64_t bin_off;        // first forward bin
+    int64_t tile_off;       // first tile (backward bin)
+    int64_t blk_off;        // first count / scatter / sweep block
+    int64_t cell_off_f;     // first forward chunk cell
+    int64_t cell_off_b;     // first backward chunk cell
+};
+
+constexpr int kScanChunk = 16;  // histogram rows per chunk of the column scan
+
 // Byte offsets of the tiled path's buffers inside the workspace region.
 struct TileWorkspace {
     size_t hist, csum, totals, start, part, halo, records, total;
+};
+
+// Host-side plan of a tiled batch: per-window metadata, totals, workspace layout.
+struct BatchPlanHost {
+    int nw = 0;
+    std::vector<WinMeta> meta;
+    int64_t n_events = 0, n_pixels = 0, img_elems = 0;
+    int64_t nbins = 0, ntiles = 0, nblocks = 0, cells_f = 0, cells_b = 0;
+    int max_R = 1, max_lds_bins = 1;
+    TileWorkspace ws;
 };
 
 // Kernels shared by the direct and tiled paths.
@@ -124,16 +156,20 @@ hipError_t launch_backward(const WinParams& P, const EventPtrs& ev, const float*
                            const float* ego, const StatePtrs& st, const float* grad_loss,
                            float* grad_rho, float* grad_ego, hipStream_t s, Profiler* prof);
 
-// Tiled (owner-computes) path, usable when tiled_supported(); `ws` is a device
-// region of tile_workspace_layout(P, n).total bytes.
+// Tiled (owner-computes) path over one or many windows.  `meta` is the device
+// copy of plan.meta; `ws` a device region of plan.ws.total bytes; images of
+// window w start at img + meta[w].img_off; hdrs[w] its sums.
 bool tiled_supported(const WinParams& P, int64_t n);
-TileWorkspace tile_workspace_layout(const WinParams& P, int64_t n);
-hipError_t launch_forward_tiled(const WinParams& P, const EventPtrs& ev, const float* rho,
-                                const float* ego, float* loss, const StatePtrs& st, char* ws,
-                                hipStream_t s, Profiler* prof);
-hipError_t launch_backward_tiled(const WinParams& P, const EventPtrs& ev, const float* rho,
-                                 const float* ego, const StatePtrs& st, const float* grad_loss,
-                                 float* grad_rho, float* grad_ego, char* ws, hipStream_t s,
-                                 Profiler* prof);
+TileGeom tile_geom(const WinParams& P, int64_t n);
+BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int nw);
+hipError_t launch_store_meta(const WinMeta& m, WinMeta* out, hipStream_t s);
+hipError_t launch_forward_batch(const BatchPlanHost& B, const WinMeta* meta, const EventPtrs& ev,
+                                const float* rho, const float* ego, float* loss, double2* img,
+                                StateHeader* hdrs, char* ws, hipStream_t s, Profiler* prof);
+hipError_t launch_backward_batch(const BatchPlanHost& B, const WinMeta* meta,
+                                 const EventPtrs& ev, const float* rho, const float* ego,
+                                 const double2* img, const StateHeader* hdrs,
+                                 const float* grad_loss, float* grad_rho, float* grad_ego,
+                                 char* ws, hipStream_t s, Profiler* prof);
 
 }  // namespace cm

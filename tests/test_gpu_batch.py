@@ -1,0 +1,155 @@
+"""GPU: batched windows (one launch sequence over a flat event buffer) against
+the oracle per window, against single-window calls, and under hipGraph replay."""
+
+import numpy as np
+import pytest
+import torch
+
+import eventgen
+import oracle
+from tests.helpers import assert_grads_close, assert_loss_close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cm():
+    import paper_2412_06359_amd as cm
+    cm.load()
+    assert torch.cuda.is_available()
+    return cm
+
+
+def mixed_windows():
+    """Uneven sizes, two sensors, 1-8 references, an empty and a one-event window."""
+    wins = []
+    for i, (sensor, n, refs) in enumerate([
+            ("346x260", 5000, [0.0, 1.0]), ("640x480", 30000, [0.0, 0.5, 1.0]),
+            ("346x260", 1, [0.0, 1.0]), ("346x260", 0, [0.0, 1.0]),
+            ("346x260", 120000, [0.0, 1.0]), ("640x480", 777, list(eventgen.refs_even(8))),
+            ("346x260", 20000, [1.0]), ("346x260", 60000, [0.0, 1.0])]):
+        w = eventgen.edge_window(600 + i, sensor, max(n, 1), refs=refs, n_segments=30,
+                                 name=f"b{i}")
+        if n == 0:
+            e = np.zeros(0, np.float32)
+            w = w.replace(x=e, y=e, t=e, p=np.zeros(0, np.int8))
+        wins.append(w)
+    return wins
+
+
+def pack(wins, dev="cuda:0"):
+    f = lambda arrs: torch.from_numpy(np.ascontiguousarray(np.concatenate(
+        [np.asarray(a, np.float32).ravel() for a in arrs]))).to(dev)
+    return dict(x=f([w.x for w in wins]), y=f([w.y for w in wins]), t=f([w.t for w in wins]),
+                p=torch.from_numpy(np.concatenate([np.asarray(w.p, np.int8) for w in wins])).to(dev),
+                rho=f([w.rho for w in wins]), ego=f([w.theta for w in wins]))
+
+
+def make_batch(cm, wins, graph=False):
+    descs = [cm.WindowDesc.from_window(w) for w in wins]
+    return cm.Batch(descs, [w.n for w in wins], graph=graph)
+
+
+def run_batch(cm, batch, d, grad_out=None):
+    n = batch.n
+    loss, state = batch.forward(d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"])
+    gl = torch.ones(n, device="cuda:0") if grad_out is None else grad_out
+    g_rho, g_ego = batch.backward(d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"], state, gl)
+    torch.cuda.synchronize()
+    return (loss.double().cpu().numpy(), g_rho.double().cpu().numpy(),
+            g_ego.double().cpu().numpy().reshape(n, 6), batch.diagnostics(state))
+
+
+def test_batch_matches_oracle_per_window(cm):
+    wins = mixed_windows()
+    batch = make_batch(cm, wins)
+    print(f"[gpu] batch of {batch.n} windows, {batch.event_offsets[-1]} events", flush=True)
+    loss, g_rho, g_ego, diag = run_batch(cm, batch, pack(wins))
+    for w, win in enumerate(wins):
+        o = oracle.forward(win, valid=True)
+        assert_loss_close(loss[w], o["loss"], what=win.name)
+        assert diag[w][1] == int(o["valid"].sum())
+        ob = oracle.backward(win)
+        a, b = batch.pixel_offsets[w], batch.pixel_offsets[w + 1]
+        assert_grads_close(g_rho[a:b], g_ego[w], ob["drho"].ravel(), ob["dtheta"], what=win.name)
+
+
+def test_batch_equals_single_window_calls(cm):
+    wins = mixed_windows()
+    batch = make_batch(cm, wins)
+    loss, g_rho, g_ego, _ = run_batch(cm, batch, pack(wins))
+    cm.set_path(0, cm.CM_PATH_TILED)
+    try:
+        for w, win in enumerate(wins):
+            d = pack([win])
+            desc = cm.WindowDesc.from_window(win)
+            rho = d["rho"].clone().requires_grad_(True)
+            ego = d["ego"].clone().requires_grad_(True)
+            L = cm.cm_loss(d["x"], d["y"], d["t"], d["p"], rho, ego, desc)
+            L.backward()
+            assert abs(float(L.item()) - loss[w]) <= 1e-6 * abs(loss[w]) + 1e-12
+            a, b = batch.pixel_offsets[w], batch.pixel_offsets[w + 1]
+            ref = rho.grad.double().cpu().numpy()
+            assert np.linalg.norm(g_rho[a:b] - ref) <= 1e-5 * np.linalg.norm(ref) + 1e-30
+            np.testing.assert_allclose(g_ego[w], ego.grad.double().cpu().numpy(), rtol=1e-5,
+                                       atol=1e-6 * np.abs(g_ego[w]).max() + 1e-30)
+    finally:
+        cm.set_path(0, cm.CM_PATH_AUTO)
+
+
+def test_batch_graph_replays_match_eager(cm):
+    wins = mixed_windows()
+    d = pack(wins)
+    eager = make_batch(cm, wins, graph=False)
+    ref = run_batch(cm, eager, d)
+    graphed = make_batch(cm, wins, graph=True)
+    state = graphed.new_state()
+    loss = torch.empty(graphed.n, device="cuda:0")
+    g_rho = torch.empty_like(d["rho"])
+    g_ego = torch.empty_like(d["ego"])
+    gl = torch.ones(graphed.n, device="cuda:0")
+    for rep in range(4):
+        graphed.forward(d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"], state=state, loss=loss)
+        graphed.backward(d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"], state, gl,
+                         grad_rho=g_rho, grad_ego=g_ego)
+        torch.cuda.synchronize()
+        # eager work of the program between replays
+        junk = torch.randn(1 << 20, device="cuda:0").sum().item()
+        assert np.isfinite(junk)
+        l = loss.double().cpu().numpy()
+        np.testing.assert_allclose(l, ref[0], rtol=1e-6, atol=1e-12)
+        gr = g_rho.double().cpu().numpy()
+        assert np.linalg.norm(gr - ref[1]) <= 1e-5 * np.linalg.norm(ref[1])
+        np.testing.assert_allclose(g_ego.double().cpu().numpy().reshape(-1, 6), ref[2],
+                                   rtol=1e-5, atol=1e-6 * np.abs(ref[2]).max())
+
+
+def test_batch_autograd_and_grad_scaling(cm):
+    wins = mixed_windows()[:3]
+    batch = make_batch(cm, wins)
+    d = pack(wins)
+    rho = d["rho"].clone().requires_grad_(True)
+    ego = d["ego"].clone().requires_grad_(True)
+    losses = cm.BatchCMLoss.apply(d["x"], d["y"], d["t"], d["p"], rho, ego, batch)
+    weights = torch.tensor([1.0, -2.0, 0.5], device="cuda:0")
+    (losses * weights).sum().backward()
+    for w, win in enumerate(wins):
+        ob = oracle.backward(win, grad_loss=float(weights[w]))
+        a, b = batch.pixel_offsets[w], batch.pixel_offsets[w + 1]
+        assert_grads_close(rho.grad.double().cpu().numpy()[a:b],
+                           ego.grad.double().cpu().numpy()[6 * w:6 * w + 6],
+                           ob["drho"].ravel(), ob["dtheta"], what=win.name)
+
+
+def test_c3_batch_full_size(cm):
+    wins = eventgen.make_batch("c3", 64)
+    batch = make_batch(cm, wins, graph=True)
+    print(f"[gpu] c3 batch {batch.event_offsets[-1]} events", flush=True)
+    loss, g_rho, g_ego, diag = run_batch(cm, batch, pack(wins))
+    for w in (0, 7, 31, 63):
+        o = oracle.forward(wins[w])
+        assert_loss_close(loss[w], o["loss"], what=f"c3[{w}]")
+        ob = oracle.backward(wins[w])
+        a, b = batch.pixel_offsets[w], batch.pixel_offsets[w + 1]
+        assert_grads_close(g_rho[a:b], g_ego[w], ob["drho"].ravel(), ob["dtheta"],
+                           what=f"c3[{w}]")
