@@ -61,9 +61,14 @@ typedef enum {
     CM_ERR_BUDGET = -5
 } cm_status;
 
-/* Splat modes.  ATOMIC: floating-point atomics, results vary in the last bits
- * from run to run.  DETERMINISTIC: a sort of the splat contributions by pixel
- * followed by a fixed-order reduction; bit-identical from run to run. */
+/* Splat modes.  ATOMIC: floating-point atomic accumulation, results vary in
+ * the last bits from run to run.  DETERMINISTIC: the warped positions are
+ * sorted stably (event order) into 32x32-tile bins and each tile accumulates
+ * them in a fixed order (records in event order, 64 at a time, per tap slot,
+ * equal pixels in lane order), and every reduction uses a fixed tree: results
+ * are bit-identical from run to run and between a window alone and in a batch.
+ * It always takes the tiled path (CM_ERR_UNSUPPORTED where that path does not
+ * apply) and is slower. */
 enum { CM_MODE_ATOMIC = 0, CM_MODE_DETERMINISTIC = 1 };
 
 #define CM_MAX_REFS 16
@@ -144,8 +149,8 @@ cm_status cm_state_diagnostics(const cm_window_desc* d, const void* state, doubl
 
 /* Batches (the tiled path over many windows in one launch sequence).
  *
- * A plan fixes a batch's shape: n_windows descriptors (host memory, each with
- * CM_MODE_ATOMIC) and their event counts.  Events of all windows are packed in
+ * A plan fixes a batch's shape: n_windows descriptors (host memory, all with
+ * the same mode) and their event counts.  Events of all windows are packed in
  * flat device arrays, window w at [event_offsets[w], event_offsets[w+1]), in
  * window order; inverse depth and d inverse depth likewise at
  * [pixel_offsets[w], pixel_offsets[w+1]) (height * width floats each); ego and

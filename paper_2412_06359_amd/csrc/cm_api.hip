@@ -88,13 +88,19 @@ Layout layout_of(const cm_window_desc* d, int64_t n)
     L.ws_off = L.meta_off + align_up(sizeof(WinMeta), kAlign);
     const WinParams P = params_of(d);
     L.tiled = n > 0 && cm::tiled_supported(P, n);
-    L.total = L.ws_off + (L.tiled ? cm::plan_batch(&P, &n, 1).ws.total : 0);
+    L.total = L.ws_off +
+              (L.tiled ? cm::plan_batch(&P, &n, 1, d->mode == CM_MODE_DETERMINISTIC).ws.total : 0);
     return L;
 }
 
-bool choose_tiled(const cm_handle_s* h, const Layout& L, const WinParams& P, int64_t n)
+// The deterministic mode always takes the tiled path (its record order and
+// accumulation order are fixed); windows it cannot take are rejected.
+bool choose_tiled(const cm_handle_s* h, const cm_window_desc* d, const Layout& L,
+                  const WinParams& P, int64_t n)
 {
-    if (!L.tiled || h->path == CM_PATH_DIRECT) return false;
+    if (!L.tiled) return false;
+    if (d->mode == CM_MODE_DETERMINISTIC) return true;
+    if (h->path == CM_PATH_DIRECT) return false;
     if (h->path == CM_PATH_TILED) return true;
     return n * (int64_t)P.R >= kTiledMinRecords;
 }
@@ -261,20 +267,21 @@ cm_status cm_loss_forward(cm_handle h, const cm_window_desc* d, const float* ev_
     if (!h || !desc_valid(d) || !events_valid(ev_x, ev_y, ev_t, ev_p, n_events) || !inv_depth ||
         !ego || !loss || !state)
         return CM_ERR_INVALID_ARG;
-    if (d->mode != CM_MODE_ATOMIC) return CM_ERR_UNSUPPORTED;
     const Layout L = layout_of(d, n_events);
     const WinParams P = params_of(d);
-    if (h->path == CM_PATH_TILED && !L.tiled && n_events > 0) return CM_ERR_UNSUPPORTED;
+    if ((h->path == CM_PATH_TILED || d->mode == CM_MODE_DETERMINISTIC) && !L.tiled && n_events > 0)
+        return CM_ERR_UNSUPPORTED;
     DeviceGuard g(h->device);
     if (!g.ok()) return CM_ERR_HIP;
     const cm::EventPtrs ev{ev_x, ev_y, ev_t, ev_p, n_events};
     const StatePtrs sp = state_ptrs(L, state);
     hipStream_t s = static_cast<hipStream_t>(stream);
     cm::Profiler* prof = h->prof.enabled ? &h->prof : nullptr;
-    if (!choose_tiled(h, L, P, n_events))
+    if (!choose_tiled(h, d, L, P, n_events))
         return status_of(cm::launch_forward(P, ev, inv_depth, ego, loss, sp, s, prof));
     char* base = static_cast<char*>(state);
-    const BatchPlanHost B = cm::plan_batch(&P, &n_events, 1);
+    const BatchPlanHost B =
+        cm::plan_batch(&P, &n_events, 1, d->mode == CM_MODE_DETERMINISTIC);
     WinMeta* meta = reinterpret_cast<WinMeta*>(base + L.meta_off);
     hipError_t e = cm::launch_store_meta(B.meta[0], meta, s);
     if (e != hipSuccess) return CM_ERR_HIP;
@@ -292,21 +299,22 @@ cm_status cm_loss_backward(cm_handle h, const cm_window_desc* d, const float* ev
     if (!h || !desc_valid(d) || !events_valid(ev_x, ev_y, ev_t, ev_p, n_events) || !inv_depth ||
         !ego || !state || !grad_loss || !grad_inv_depth || !grad_ego)
         return CM_ERR_INVALID_ARG;
-    if (d->mode != CM_MODE_ATOMIC) return CM_ERR_UNSUPPORTED;
     const Layout L = layout_of(d, n_events);
     const WinParams P = params_of(d);
-    if (h->path == CM_PATH_TILED && !L.tiled && n_events > 0) return CM_ERR_UNSUPPORTED;
+    if ((h->path == CM_PATH_TILED || d->mode == CM_MODE_DETERMINISTIC) && !L.tiled && n_events > 0)
+        return CM_ERR_UNSUPPORTED;
     DeviceGuard g(h->device);
     if (!g.ok()) return CM_ERR_HIP;
     const cm::EventPtrs ev{ev_x, ev_y, ev_t, ev_p, n_events};
     const StatePtrs sp = state_ptrs(L, state);
     hipStream_t s = static_cast<hipStream_t>(stream);
     cm::Profiler* prof = h->prof.enabled ? &h->prof : nullptr;
-    if (!choose_tiled(h, L, P, n_events))
+    if (!choose_tiled(h, d, L, P, n_events))
         return status_of(cm::launch_backward(P, ev, inv_depth, ego, sp, grad_loss, grad_inv_depth,
                                              grad_ego, s, prof));
     char* base = static_cast<char*>(state);
-    const BatchPlanHost B = cm::plan_batch(&P, &n_events, 1);
+    const BatchPlanHost B =
+        cm::plan_batch(&P, &n_events, 1, d->mode == CM_MODE_DETERMINISTIC);
     WinMeta* meta = reinterpret_cast<WinMeta*>(base + L.meta_off);
     hipError_t e = cm::launch_store_meta(B.meta[0], meta, s);
     if (e != hipSuccess) return CM_ERR_HIP;
@@ -365,7 +373,7 @@ cm_status cm_batch_create(cm_handle h, int32_t n_windows, const cm_window_desc* 
     int64_t total_records = 0;
     for (int w = 0; w < n_windows; ++w) {
         if (!desc_valid(&descs[w]) || n_events[w] < 0) return CM_ERR_INVALID_ARG;
-        if (descs[w].mode != CM_MODE_ATOMIC) return CM_ERR_UNSUPPORTED;
+        if (descs[w].mode != descs[0].mode) return CM_ERR_INVALID_ARG;
         params[w] = params_of(&descs[w]);
         if (!cm::tiled_supported(params[w], n_events[w])) return CM_ERR_UNSUPPORTED;
         total_records += n_events[w] * (int64_t)params[w].R;
@@ -376,7 +384,8 @@ cm_status cm_batch_create(cm_handle h, int32_t n_windows, const cm_window_desc* 
     cm_batch_s* b = new (std::nothrow) cm_batch_s();
     if (!b) return CM_ERR_OOM;
     b->h = h;
-    b->B = cm::plan_batch(params.data(), n_events, n_windows);
+    b->B = cm::plan_batch(params.data(), n_events, n_windows,
+                          descs[0].mode == CM_MODE_DETERMINISTIC);
     b->ev_offsets.resize(n_windows + 1);
     b->pix_offsets.resize(n_windows + 1);
     for (int w = 0; w < n_windows; ++w) {

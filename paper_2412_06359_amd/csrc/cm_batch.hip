@@ -52,6 +52,58 @@ __device__ __forceinline__ int window_of_block(const WinMeta* meta, int nw, int6
 }
 
 // ---------------------------------------------------------------------------
+// Deterministic mode helpers (one wavefront per block)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t lanes_below()
+{
+    return (1ull << __lane_id()) - 1ull;
+}
+
+// Slot of this lane's record in bin `bin`: counter[bin] plus the number of
+// active lanes with the same bin and a lower lane id; the counter then advances
+// by the group's size.  Lanes are served in lane order, so, with one wavefront
+// per block, a block's records land in each bin in (event, step) order.
+__device__ __forceinline__ uint32_t stable_slot(uint32_t* counter, int bin)
+{
+    uint64_t todo = __ballot(1);
+    uint32_t slot = 0;
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int b = __shfl(bin, leader);
+        const uint64_t same = __ballot(bin == b);
+        const uint32_t base = counter[b];
+        if (bin == b) slot = base + (uint32_t)__popcll(same & lanes_below());
+        if ((int)__lane_id() == leader) counter[b] = base + (uint32_t)__popcll(same);
+        todo &= ~same;
+    }
+    return slot;
+}
+
+// Adds (vx, vy) of every lane with `act` into cell[key], lanes with equal keys
+// in lane order, each add applied to the running value: the canonical order
+// of the deterministic mode.  Called by all lanes of the wavefront.
+__device__ __forceinline__ void ordered_add(double2* cells, bool act, int key, double vx, double vy)
+{
+    uint64_t todo = __ballot(act);
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int k = __shfl(key, leader);
+        const uint64_t same = __ballot(act && key == k);
+        double2 v = cells[k];
+        uint64_t m = same;
+        while (m) {
+            const int l = __ffsll((unsigned long long)m) - 1;
+            v.x += __shfl(vx, l);
+            v.y += __shfl(vy, l);
+            m &= m - 1;
+        }
+        if ((int)__lane_id() == leader) cells[k] = v;
+        todo &= ~same;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Counting sort of records into bins
 // ---------------------------------------------------------------------------
 
@@ -70,8 +122,8 @@ __device__ __forceinline__ void for_each_splat(const WinParams& P, const TileGeo
     }
 }
 
-template <int RM>
-__global__ __launch_bounds__(kBinThreads) void fwd_count_kernel(
+template <int RM, int NT>
+__global__ __launch_bounds__(NT) void fwd_count_kernel(
     const WinMeta* __restrict__ meta, int nw, const float* __restrict__ ex,
     const float* __restrict__ ey, const float* __restrict__ et, const float* __restrict__ rho,
     const float* __restrict__ ego, uint32_t* __restrict__ hist, StateHeader* __restrict__ hdrs)
@@ -87,10 +139,10 @@ __global__ __launch_bounds__(kBinThreads) void fwd_count_kernel(
     if (threadIdx.x == 0) cnt_lds = 0;
     __syncthreads();
     const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
-    const int64_t base = lb * kBinThreads * G.ept;
+    const int64_t base = lb * NT * G.ept;
     uint32_t cnt = 0;
     for (int e = 0; e < G.ept; ++e) {
-        const int64_t k = base + (int64_t)e * kBinThreads + threadIdx.x;
+        const int64_t k = base + (int64_t)e * NT + threadIdx.x;
         if (k >= n) break;
         double px[RM], py[RM];
         int mb;
@@ -219,8 +271,8 @@ __global__ __launch_bounds__(256) void offsets_kernel(const WinMeta* __restrict_
     }
 }
 
-template <int RM>
-__global__ __launch_bounds__(kBinThreads) void fwd_scatter_kernel(
+template <int RM, int NT, bool DET>
+__global__ __launch_bounds__(NT) void fwd_scatter_kernel(
     const WinMeta* __restrict__ meta, int nw, const float* __restrict__ ex,
     const float* __restrict__ ey, const float* __restrict__ et, const int8_t* __restrict__ ep,
     const float* __restrict__ rho, const float* __restrict__ ego,
@@ -236,9 +288,9 @@ __global__ __launch_bounds__(kBinThreads) void fwd_scatter_kernel(
     for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) lh[i] = row[i];
     __syncthreads();
     const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
-    const int64_t base = lb * kBinThreads * G.ept;
+    const int64_t base = lb * NT * G.ept;
     for (int e = 0; e < G.ept; ++e) {
-        const int64_t k = base + (int64_t)e * kBinThreads + threadIdx.x;
+        const int64_t k = base + (int64_t)e * NT + threadIdx.x;
         if (k >= n) break;
         double px[RM], py[RM];
         int mb;
@@ -246,7 +298,7 @@ __global__ __launch_bounds__(kBinThreads) void fwd_scatter_kernel(
         if (!warp_event<RM>(P, u, ex[ev0 + k], ey[ev0 + k], tk, px, py, mb)) continue;
         const float ts = ep[ev0 + k] > 0 ? tk : -tk;   // t >= 0 here; sign bit = negative polarity
         for_each_splat<RM>(P, G, px, py, [&](int bin, int r) {
-            const uint32_t slot = atomicAdd(&lh[bin], 1u);
+            const uint32_t slot = DET ? stable_slot(lh, bin) : atomicAdd(&lh[bin], 1u);
             SplatRec q;
             q.X = sel(px, r);
             q.Y = sel(py, r);
@@ -293,6 +345,7 @@ __device__ __forceinline__ int window_of_tile(const WinMeta* meta, int nw, int64
     return find_window(meta, nw, gtile, [](const WinMeta& m) { return m.tile_off; });
 }
 
+template <bool DET>
 __global__ __launch_bounds__(256) void fwd_tile_kernel(const WinMeta* __restrict__ meta, int nw,
                                                        const SplatRec* __restrict__ rec,
                                                        const uint32_t* __restrict__ start,
@@ -313,21 +366,44 @@ __global__ __launch_bounds__(256) void fwd_tile_kernel(const WinMeta* __restrict
     __syncthreads();
     const double ref = P.refs[r];
     const uint32_t s0 = start[gbin], s1 = start[gbin + 1];
-    for (uint32_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
-        const SplatRec q = rec[i];
-        const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
-        const double tb = 1.0 - fabs(ref - (double)fabsf(q.ts));
-        const Taps tp = make_taps(P, q.X, q.Y);
-        const int lx = tp.x0 - xo, ly = tp.y0 - yo;
-        double2* L = lds + pol * TLW * TLH;
+    if (!DET) {
+        for (uint32_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+            const SplatRec q = rec[i];
+            const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
+            const double tb = 1.0 - fabs(ref - (double)fabsf(q.ts));
+            const Taps tp = make_taps(P, q.X, q.Y);
+            const int lx = tp.x0 - xo, ly = tp.y0 - yo;
+            double2* L = lds + pol * TLW * TLH;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (!tap_in(tp, c)) continue;
-            const double wt = tap_w(tp, c);
-            if (wt == 0.0) continue;
-            double2* cell = L + (ly + (c >> 1)) * TLW + lx + (c & 1);
-            atomicAdd(&cell->x, wt);
-            atomicAdd(&cell->y, wt * tb);
+            for (int c = 0; c < 4; ++c) {
+                if (!tap_in(tp, c)) continue;
+                const double wt = tap_w(tp, c);
+                if (wt == 0.0) continue;
+                double2* cell = L + (ly + (c >> 1)) * TLW + lx + (c & 1);
+                atomicAdd(&cell->x, wt);
+                atomicAdd(&cell->y, wt * tb);
+            }
+        }
+    } else if (threadIdx.x < 64) {
+        // one wavefront walks the records in order, 64 at a time; per tap slot,
+        // equal cells are updated in lane order
+        for (uint32_t b0 = s0; b0 < s1; b0 += 64) {
+            const uint32_t i = b0 + threadIdx.x;
+            const bool live = i < s1;
+            SplatRec q;
+            if (live) q = rec[i];
+            else q.X = q.Y = (double)xo, q.ts = 0.f;
+            const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
+            const double tb = 1.0 - fabs(ref - (double)fabsf(q.ts));
+            const Taps tp = make_taps(P, q.X, q.Y);
+            const int lx = tp.x0 - xo, ly = tp.y0 - yo;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double wt = tap_w(tp, c);
+                const bool act = live && tap_in(tp, c) && wt != 0.0;
+                const int key = pol * TLW * TLH + (ly + (c >> 1)) * TLW + lx + (c & 1);
+                ordered_add(lds, act, key, wt, wt * tb);
+            }
         }
     }
     __syncthreads();
@@ -473,8 +549,8 @@ __device__ __forceinline__ int first_forward_ref(const WinParams& P, int mb, dou
     return (mb < P.R && P.refs[mb] == tk) ? mb + 1 : mb;
 }
 
-template <int RM>
-__global__ __launch_bounds__(kBinThreads) void bwd_count_kernel(
+template <int RM, int NT>
+__global__ __launch_bounds__(NT) void bwd_count_kernel(
     const WinMeta* __restrict__ meta, int nw, const float* __restrict__ ex,
     const float* __restrict__ ey, const float* __restrict__ et, const float* __restrict__ rho,
     const float* __restrict__ ego, uint32_t* __restrict__ hist)
@@ -488,9 +564,9 @@ __global__ __launch_bounds__(kBinThreads) void bwd_count_kernel(
     for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x) lh[i] = 0;
     __syncthreads();
     const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
-    const int64_t base = lb * kBinThreads * G.ept;
+    const int64_t base = lb * NT * G.ept;
     for (int e = 0; e < G.ept; ++e) {
-        const int64_t k = base + (int64_t)e * kBinThreads + threadIdx.x;
+        const int64_t k = base + (int64_t)e * NT + threadIdx.x;
         if (k >= n) break;
         double px[RM], py[RM];
         int mb;
@@ -506,8 +582,8 @@ __global__ __launch_bounds__(kBinThreads) void bwd_count_kernel(
     for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x) row[i] = lh[i];
 }
 
-template <int RM>
-__global__ __launch_bounds__(kBinThreads) void bwd_sweep_kernel(
+template <int RM, int NT, bool DET>
+__global__ __launch_bounds__(NT) void bwd_sweep_kernel(
     const WinMeta* __restrict__ meta, int nw, const float* __restrict__ ex,
     const float* __restrict__ ey, const float* __restrict__ et, const int8_t* __restrict__ ep,
     const float* __restrict__ rho, const float* __restrict__ ego,
@@ -529,10 +605,11 @@ __global__ __launch_bounds__(kBinThreads) void bwd_sweep_kernel(
 #pragma unroll
     for (int r = 0; r < RM; ++r) coef[r] = r < P.R ? P.two_over_R / (hdr->nact[r] + P.eps) : 0.0;
     const double2* img = img_base + meta[w].img_off;
-    const int64_t base = lb * kBinThreads * G.ept;
+    const int64_t base = lb * NT * G.ept;
 
     auto emit = [&](double X, double Y, double gx, double gy) {
-        const uint32_t slot = atomicAdd(&lh[tile_index(G, make_taps(P, X, Y))], 1u);
+        const int bin = tile_index(G, make_taps(P, X, Y));
+        const uint32_t slot = DET ? stable_slot(lh, bin) : atomicAdd(&lh[bin], 1u);
         GradRec q;
         q.X = X;
         q.Y = Y;
@@ -542,7 +619,7 @@ __global__ __launch_bounds__(kBinThreads) void bwd_sweep_kernel(
     };
 
     for (int e = 0; e < G.ept; ++e) {
-        const int64_t k = base + (int64_t)e * kBinThreads + threadIdx.x;
+        const int64_t k = base + (int64_t)e * NT + threadIdx.x;
         if (k >= n) break;
         double px[RM], py[RM];
         int mb;
@@ -580,6 +657,7 @@ __global__ __launch_bounds__(kBinThreads) void bwd_sweep_kernel(
 // Accumulate dL/du = sum over records of w_tap * (dt * adjoint) in LDS; own
 // pixels off the border get d rho and their d theta share here, the border
 // and the halo go to buffers for the merge.
+template <bool DET>
 __global__ __launch_bounds__(256) void bwd_tile_kernel(
     const WinMeta* __restrict__ meta, int nw, const GradRec* __restrict__ rec,
     const uint32_t* __restrict__ start, const float* __restrict__ rho,
@@ -599,18 +677,37 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(
     for (int i = threadIdx.x; i < TLW * TLH; i += blockDim.x) lds[i] = make_double2(0.0, 0.0);
     __syncthreads();
     const uint32_t s0 = start[gtile], s1 = start[gtile + 1];
-    for (uint32_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
-        const GradRec q = rec[i];
-        const Taps tp = make_taps(P, q.X, q.Y);
-        const int lx = tp.x0 - xo, ly = tp.y0 - yo;
+    if (!DET) {
+        for (uint32_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+            const GradRec q = rec[i];
+            const Taps tp = make_taps(P, q.X, q.Y);
+            const int lx = tp.x0 - xo, ly = tp.y0 - yo;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (!tap_in(tp, c)) continue;
-            const double wt = tap_w(tp, c);
-            if (wt == 0.0) continue;
-            double2* cell = lds + (ly + (c >> 1)) * TLW + lx + (c & 1);
-            atomicAdd(&cell->x, wt * q.gx);
-            atomicAdd(&cell->y, wt * q.gy);
+            for (int c = 0; c < 4; ++c) {
+                if (!tap_in(tp, c)) continue;
+                const double wt = tap_w(tp, c);
+                if (wt == 0.0) continue;
+                double2* cell = lds + (ly + (c >> 1)) * TLW + lx + (c & 1);
+                atomicAdd(&cell->x, wt * q.gx);
+                atomicAdd(&cell->y, wt * q.gy);
+            }
+        }
+    } else if (threadIdx.x < 64) {
+        for (uint32_t b0 = s0; b0 < s1; b0 += 64) {
+            const uint32_t i = b0 + threadIdx.x;
+            const bool live = i < s1;
+            GradRec q;
+            if (live) q = rec[i];
+            else q.X = q.Y = (double)xo, q.gx = q.gy = 0.0;
+            const Taps tp = make_taps(P, q.X, q.Y);
+            const int lx = tp.x0 - xo, ly = tp.y0 - yo;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double wt = tap_w(tp, c);
+                const bool act = live && tap_in(tp, c) && wt != 0.0;
+                const int key = (ly + (c >> 1)) * TLW + lx + (c & 1);
+                ordered_add(lds, act, key, wt * q.gx, wt * q.gy);
+            }
         }
     }
     __syncthreads();
@@ -744,7 +841,11 @@ __global__ void store_meta_kernel(WinMeta m, WinMeta* __restrict__ out)
 // Host side: geometry, layout, launches
 // ---------------------------------------------------------------------------
 
-TileGeom tile_geom(const WinParams& P, int64_t n)
+// Threads of the count / scatter / sweep blocks: one wavefront in the
+// deterministic mode (its record order is the lanes' order), else four.
+static int bin_threads(bool det) { return det ? 64 : kBinThreads; }
+
+TileGeom tile_geom(const WinParams& P, int64_t n, bool det)
 {
     TileGeom G;
     G.ntx = (P.W + TW - 1) / TW;
@@ -752,23 +853,25 @@ TileGeom tile_geom(const WinParams& P, int64_t n)
     G.ntiles = G.ntx * G.nty;
     G.nbins = P.R * G.ntiles;
     // enough blocks to fill the chip, few enough to keep the histogram matrix small
-    const int64_t ept = n / ((int64_t)kBinThreads * 1024);
+    const int nt = bin_threads(det);
+    const int64_t ept = n / ((int64_t)nt * 1024);
     G.ept = (int)std::max<int64_t>(1, std::min<int64_t>(ept, kMaxEventsPerThread));
-    const int64_t per_block = (int64_t)kBinThreads * G.ept;
+    const int64_t per_block = (int64_t)nt * G.ept;
     G.nblocks = (int)std::max<int64_t>(1, (n + per_block - 1) / per_block);
     return G;
 }
 
 bool tiled_supported(const WinParams& P, int64_t n)
 {
-    const TileGeom G = tile_geom(P, n);
+    const TileGeom G = tile_geom(P, n, false);
     return G.nbins <= kMaxBins && n * (int64_t)P.R < ((int64_t)1 << 31);
 }
 
-BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int nw)
+BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int nw, bool det)
 {
     BatchPlanHost B;
     B.nw = nw;
+    B.det = det;
     B.meta.resize(nw);
     int64_t ev = 0, pix = 0, img = 0, hist = 0, csum = 0, bin = 0, tile = 0, blk = 0;
     int64_t cf = 0, cb = 0, recs = 0;
@@ -778,7 +881,7 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
         WinMeta& M = B.meta[w];
         std::memset(&M, 0, sizeof M);
         M.P = params[w];
-        M.G = tile_geom(M.P, n_events[w]);
+        M.G = tile_geom(M.P, n_events[w], det);
         M.nchunks = (M.G.nblocks + kScanChunk - 1) / kScanChunk;
         M.ev_off = ev;
         M.n = n_events[w];
@@ -831,7 +934,7 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     return B;
 }
 
-template <int RM>
+template <int RM, bool DET>
 static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
                                    const EventPtrs& ev, const float* rho, const float* ego,
                                    float* loss, double2* img, StateHeader* hdrs, char* ws,
@@ -852,8 +955,9 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     }
     {
         PhaseScope ph(prof, kPhCount, s);
-        fwd_count_kernel<RM><<<B.nblocks, kBinThreads, lds, s>>>(meta, nw, ev.x, ev.y, ev.t, rho,
-                                                                 ego, hist, hdrs);
+        constexpr int NT = DET ? 64 : kBinThreads;
+        fwd_count_kernel<RM, NT><<<B.nblocks, NT, lds, s>>>(meta, nw, ev.x, ev.y, ev.t, rho, ego,
+                                                            hist, hdrs);
     }
     {
         PhaseScope ph(prof, kPhScan, s);
@@ -866,12 +970,13 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     }
     {
         PhaseScope ph(prof, kPhScatter, s);
-        fwd_scatter_kernel<RM><<<B.nblocks, kBinThreads, lds, s>>>(meta, nw, ev.x, ev.y, ev.t,
+        constexpr int NT = DET ? 64 : kBinThreads;
+        fwd_scatter_kernel<RM, NT, DET><<<B.nblocks, NT, lds, s>>>(meta, nw, ev.x, ev.y, ev.t,
                                                                    ev.p, rho, ego, hist, rec);
     }
     {
         PhaseScope ph(prof, kPhSplat, s);
-        fwd_tile_kernel<<<(int)B.nbins, 256, 0, s>>>(meta, nw, rec, start, img, halo, part);
+        fwd_tile_kernel<DET><<<(int)B.nbins, 256, 0, s>>>(meta, nw, rec, start, img, halo, part);
     }
     {
         PhaseScope ph(prof, kPhReduce, s);
@@ -888,13 +993,16 @@ hipError_t launch_forward_batch(const BatchPlanHost& B, const WinMeta* meta, con
                                 const float* rho, const float* ego, float* loss, double2* img,
                                 StateHeader* hdrs, char* ws, hipStream_t s, Profiler* prof)
 {
-    if (B.max_R <= 2) return batch_forward_rm<2>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof);
-    if (B.max_R <= 4) return batch_forward_rm<4>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof);
-    if (B.max_R <= 8) return batch_forward_rm<8>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof);
-    return batch_forward_rm<16>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof);
+#define CM_FWD(RM) (B.det ? batch_forward_rm<RM, true>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof) \
+                     : batch_forward_rm<RM, false>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof))
+    if (B.max_R <= 2) return CM_FWD(2);
+    if (B.max_R <= 4) return CM_FWD(4);
+    if (B.max_R <= 8) return CM_FWD(8);
+    return CM_FWD(16);
+#undef CM_FWD
 }
 
-template <int RM>
+template <int RM, bool DET>
 static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
                                     const EventPtrs& ev, const float* rho, const float* ego,
                                     const double2* img, const StateHeader* hdrs,
@@ -913,8 +1021,9 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
     const size_t lds = (size_t)B.max_lds_bins * sizeof(uint32_t);
     {
         PhaseScope ph(prof, kPhGradCount, s);
-        bwd_count_kernel<RM><<<B.nblocks, kBinThreads, lds, s>>>(meta, nw, ev.x, ev.y, ev.t, rho,
-                                                                 ego, hist);
+        constexpr int NT = DET ? 64 : kBinThreads;
+        bwd_count_kernel<RM, NT><<<B.nblocks, NT, lds, s>>>(meta, nw, ev.x, ev.y, ev.t, rho, ego,
+                                                            hist);
     }
     {
         PhaseScope ph(prof, kPhGradScan, s);
@@ -927,12 +1036,13 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
     }
     {
         PhaseScope ph(prof, kPhAdjoint, s);
-        bwd_sweep_kernel<RM><<<B.nblocks, kBinThreads, lds, s>>>(meta, nw, ev.x, ev.y, ev.t, ev.p,
+        constexpr int NT = DET ? 64 : kBinThreads;
+        bwd_sweep_kernel<RM, NT, DET><<<B.nblocks, NT, lds, s>>>(meta, nw, ev.x, ev.y, ev.t, ev.p,
                                                                  rho, ego, img, hdrs, hist, rec);
     }
     {
         PhaseScope ph(prof, kPhGradTile, s);
-        bwd_tile_kernel<<<(int)B.ntiles, 256, 0, s>>>(meta, nw, rec, start, rho, ego, grad_loss,
+        bwd_tile_kernel<DET><<<(int)B.ntiles, 256, 0, s>>>(meta, nw, rec, start, rho, ego, grad_loss,
                                                       grad_rho, halo, border, part);
         bwd_merge_kernel<<<(int)B.ntiles, 64, 0, s>>>(meta, nw, rho, ego, grad_loss, grad_rho,
                                                       halo, border, part);
@@ -950,10 +1060,13 @@ hipError_t launch_backward_batch(const BatchPlanHost& B, const WinMeta* meta,
                                  const float* grad_loss, float* grad_rho, float* grad_ego,
                                  char* ws, hipStream_t s, Profiler* prof)
 {
-    if (B.max_R <= 2) return batch_backward_rm<2>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof);
-    if (B.max_R <= 4) return batch_backward_rm<4>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof);
-    if (B.max_R <= 8) return batch_backward_rm<8>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof);
-    return batch_backward_rm<16>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof);
+#define CM_BWD(RM) (B.det ? batch_backward_rm<RM, true>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof) \
+                     : batch_backward_rm<RM, false>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof))
+    if (B.max_R <= 2) return CM_BWD(2);
+    if (B.max_R <= 4) return CM_BWD(4);
+    if (B.max_R <= 8) return CM_BWD(8);
+    return CM_BWD(16);
+#undef CM_BWD
 }
 
 hipError_t launch_store_meta(const WinMeta& m, WinMeta* out, hipStream_t s)

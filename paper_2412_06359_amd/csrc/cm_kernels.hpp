@@ -128,6 +128,7 @@ struct TileWorkspace {
 // Host-side plan of a tiled batch: per-window metadata, totals, workspace layout.
 struct BatchPlanHost {
     int nw = 0;
+    bool det = false;       // deterministic mode
     std::vector<WinMeta> meta;
     int64_t n_events = 0, n_pixels = 0, img_elems = 0;
     int64_t nbins = 0, ntiles = 0, nblocks = 0, cells_f = 0, cells_b = 0;
@@ -160,8 +161,8 @@ hipError_t launch_backward(const WinParams& P, const EventPtrs& ev, const float*
 // copy of plan.meta; `ws` a device region of plan.ws.total bytes; images of
 // window w start at img + meta[w].img_off; hdrs[w] its sums.
 bool tiled_supported(const WinParams& P, int64_t n);
-TileGeom tile_geom(const WinParams& P, int64_t n);
-BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int nw);
+TileGeom tile_geom(const WinParams& P, int64_t n, bool det);
+BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int nw, bool det);
 hipError_t launch_store_meta(const WinMeta& m, WinMeta* out, hipStream_t s);
 hipError_t launch_forward_batch(const BatchPlanHost& B, const WinMeta* meta, const EventPtrs& ev,
                                 const float* rho, const float* ego, float* loss, double2* img,
