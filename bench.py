@@ -155,6 +155,48 @@ def plain_step_fn(cm, wins, dev):
     return step
 
 
+def serve_stream(cm, seconds: float, rate: float, budget_gib: float) -> dict:
+    """Workload c4: Poisson arrivals of windows (sensors 50/50 346x260 / 640x480,
+    event counts log-uniform in [1k, 500k], refs {0,1}) into the continuous-
+    batching server; each request is a forward + backward.  Windows are thinned
+    from a pool of 2 base windows per sensor (500k events each).  Latency is
+    arrival -> loss on the host and gradients ready on the device, and includes
+    the host-to-device copy of the window."""
+    import eventgen
+    from paper_2412_06359_amd.serve import Server
+    pool = eventgen.stream_pool(2, 500_000)
+    trace = eventgen.poisson_stream(rate_hz=rate, duration_s=seconds)
+    reqs = [eventgen.thin(pool[s][i % 2], n, offset=i) for i, (_, s, n) in enumerate(trace)]
+    srv = Server(budget_bytes=int(budget_gib * (1 << 30)), max_batch=64, n_streams=2)
+    # warm-up: one request per sensor (allocator, code objects)
+    for s in pool:
+        srv.submit(eventgen.thin(pool[s][0], 10000)).result(timeout=60)
+    srv.drain()
+    srv.latencies.clear()
+    srv.events_done = srv.windows_done = srv.batches = 0
+    srv.t_first = srv.t_last = None
+    futs = []
+    t0 = time.perf_counter()
+    for (ta, _, _), w in zip(trace, reqs):
+        dt = t0 + ta - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        futs.append(srv.submit(w))
+    for f in futs:
+        f.result(timeout=300)
+    srv.drain()
+    st = srv.stats()
+    srv.close()
+    offered = sum(w.n for w in reqs) / seconds
+    return {"workload": f"c4: Poisson {rate:.0f} windows/s for {seconds:.0f} s, 346x260/640x480 "
+                        f"50/50, log-uniform 1k..500k events, refs {{0,1}}, fwd+bwd",
+            "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+            "events_per_s": st["events_per_s"], "offered_events_per_s": offered,
+            "windows": st["windows"], "batches": st["batches"],
+            "budget_GiB": budget_gib, "max_admitted_GiB": st["max_used_bytes"] / (1 << 30),
+            "latency_includes": "H2D copy of the window, batching wait, fwd+bwd, loss D2H"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +206,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the single-window c2 line")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="length of the served Poisson stream (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=500.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     ap.add_argument("--path", default="auto", choices=["auto", "direct", "tiled"],
                     help="kernel path of the library handle (plain calls)")
     args = ap.parse_args()
@@ -282,6 +328,10 @@ def main():
         "phases_ms_per_launch": {k: v[0] for k, v in per_launch.items()},
     }
     out.update(out_extra)
+    if args.serve_seconds > 0:
+        cm.set_path(0, cm.CM_PATH_AUTO)
+        out["serving"] = serve_stream(cm, args.serve_seconds, args.serve_rate,
+                                      args.serve_budget_gib)
     if not args.no_cpu_baseline:
         threads = min(os.cpu_count() or 1, 16) if batched else 1
         out["cpu_baseline"] = cpu_baseline(wins, args.cpu_seconds, threads)

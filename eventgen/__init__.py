@@ -312,3 +312,21 @@ def poisson_stream(rate_hz: float = 500.0, duration_s: float = 20.0, seed: int =
 def stream_window(sensor: str, n_events: int, seed: int) -> Window:
     """One window of the c4 stream (edge map, refs {0, 1})."""
     return edge_window(seed, sensor, n_events, refs=[0.0, 1.0], n_segments=50, name="c4")
+
+
+def stream_pool(n_per_sensor: int = 2, n_events: int = 500_000, seed: int = 4100):
+    """Base windows the c4 stream draws from: n_per_sensor edge-map windows of
+    n_events events per sensor (346x260 and 640x480), refs {0, 1}."""
+    pool = {}
+    for s, sensor in enumerate(("346x260", "640x480")):
+        pool[sensor] = [stream_window(sensor, n_events, seed + 10 * s + i)
+                        for i in range(n_per_sensor)]
+    return pool
+
+
+def thin(win: Window, n: int, offset: int = 0) -> Window:
+    """A window of about n events taken as every k-th event of `win` (time order
+    kept, the time span unchanged): a cheap way to vary the event count."""
+    k = max(1, win.n // max(n, 1))
+    sl = slice(offset % k, None, k)
+    return win.replace(x=win.x[sl][:n], y=win.y[sl][:n], t=win.t[sl][:n], p=win.p[sl][:n])

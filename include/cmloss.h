@@ -156,11 +156,13 @@ cm_status cm_state_diagnostics(const cm_window_desc* d, const void* state, doubl
  * [pixel_offsets[w], pixel_offsets[w+1]) (height * width floats each); ego and
  * d ego are [n_windows * 6]; loss and grad_loss are [n_windows].  Each window's
  * loss and gradient equal those of a single-window call on the same data.
- * cm_batch_create allocates the plan's metadata on the device (call it at set-
- * up time, not in a hot loop); the state buffer (cm_batch_state_bytes) is the
- * caller's.  With graphs enabled, the first call with a given set of buffers
- * captures the launch sequence into a hipGraph and later calls with the same
- * buffers replay it; a plan is used by one host thread at a time.  Windows that
+ * A plan holds host memory only: each call copies the per-window metadata into
+ * the caller's state buffer (cm_batch_state_bytes) on the call's stream, so
+ * plans are cheap to create and destroy per batch (a serving loop does).  With
+ * graphs enabled (cm_batch_set_graph allocates a device copy of the metadata
+ * and a capture stream), the first call with a given set of buffers captures
+ * the launch sequence into a hipGraph and later calls with the same buffers
+ * replay it.  A plan is used by one host thread at a time.  Windows that
  * exceed the tiled path's limits (more than 16384 reference-tile bins, or 2^31
  * records in the batch) make cm_batch_create fail with CM_ERR_UNSUPPORTED. */
 typedef struct cm_batch_s* cm_batch;

@@ -147,14 +147,18 @@ cm_status status_of(hipError_t e) { return e == hipSuccess ? CM_OK : CM_ERR_HIP;
 
 }  // namespace
 
-// A batch plan: per-window metadata in device memory, the state layout, and
-// the hipGraphs of the forward and backward launch sequences.
+// A batch plan: per-window metadata, the state layout, and (with graphs) the
+// hipGraphs of the forward and backward launch sequences.  Without graphs the
+// plan owns no device memory: each call copies the metadata into the caller's
+// state buffer on the call's stream, so creating and destroying plans never
+// synchronises the device.  With graphs the metadata gets a device copy of its
+// own (captured graphs cannot copy from pageable host memory).
 struct cm_batch_s {
     cm_handle h = nullptr;
     BatchPlanHost B;
     std::vector<int64_t> ev_offsets, pix_offsets;
     WinMeta* d_meta = nullptr;
-    size_t img_off = 0, hdr_off = 0, ws_off = 0, total = 0;
+    size_t img_off = 0, hdr_off = 0, meta_off = 0, ws_off = 0, total = 0;
     bool use_graph = false;
     hipStream_t capture = nullptr;
     struct Graph {
@@ -177,11 +181,15 @@ namespace {
 // from it on a private stream (recaptured when the buffers change).
 template <typename F>
 cm_status run_maybe_graph(cm_batch_s* b, cm_batch_s::Graph& g, std::vector<const void*> key,
-                          hipStream_t s, F&& enqueue)
+                          hipStream_t s, void* state, F&& enqueue)
 {
     if (!b->use_graph) {
+        WinMeta* meta = reinterpret_cast<WinMeta*>(static_cast<char*>(state) + b->meta_off);
+        if (hipMemcpyAsync(meta, b->B.meta.data(), sizeof(WinMeta) * b->B.nw,
+                           hipMemcpyHostToDevice, s) != hipSuccess)
+            return CM_ERR_HIP;
         cm::Profiler* prof = b->h->prof.enabled ? &b->h->prof : nullptr;
-        return status_of(enqueue(s, prof));
+        return status_of(enqueue(s, prof, meta));
     }
     if (!g.exec || g.key != key) {
         if (g.exec) {
@@ -190,7 +198,7 @@ cm_status run_maybe_graph(cm_batch_s* b, cm_batch_s::Graph& g, std::vector<const
         }
         hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return CM_ERR_HIP;
-        const hipError_t el = enqueue(b->capture, nullptr);
+        const hipError_t el = enqueue(b->capture, nullptr, b->d_meta);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(b->capture, &graph);
         if (el != hipSuccess || e != hipSuccess) {
@@ -396,15 +404,9 @@ cm_status cm_batch_create(cm_handle h, int32_t n_windows, const cm_window_desc* 
     b->pix_offsets[n_windows] = b->B.n_pixels;
     b->img_off = 0;
     b->hdr_off = align_up((size_t)b->B.img_elems * 16, kAlign);
-    b->ws_off = b->hdr_off + align_up((size_t)n_windows * sizeof(StateHeader), kAlign);
+    b->meta_off = b->hdr_off + align_up((size_t)n_windows * sizeof(StateHeader), kAlign);
+    b->ws_off = b->meta_off + align_up((size_t)n_windows * sizeof(WinMeta), kAlign);
     b->total = b->ws_off + b->B.ws.total;
-    if (hipMalloc(&b->d_meta, sizeof(WinMeta) * n_windows) != hipSuccess ||
-        hipMemcpy(b->d_meta, b->B.meta.data(), sizeof(WinMeta) * n_windows,
-                  hipMemcpyHostToDevice) != hipSuccess ||
-        hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess) {
-        delete b;
-        return CM_ERR_HIP;
-    }
     *out = b;
     return CM_OK;
 }
@@ -431,6 +433,15 @@ cm_status cm_batch_offsets(cm_batch b, int64_t* event_offsets, int64_t* pixel_of
 cm_status cm_batch_set_graph(cm_batch b, int enable)
 {
     if (!b) return CM_ERR_INVALID_ARG;
+    if (enable && !b->d_meta) {
+        DeviceGuard g(b->h->device);
+        if (!g.ok()) return CM_ERR_HIP;
+        const size_t bytes = sizeof(WinMeta) * b->B.nw;
+        if (hipMalloc(&b->d_meta, bytes) != hipSuccess) return CM_ERR_OOM;
+        if (hipMemcpy(b->d_meta, b->B.meta.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
+            hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess)
+            return CM_ERR_HIP;
+    }
     b->use_graph = enable != 0;
     return CM_OK;
 }
@@ -450,9 +461,9 @@ cm_status cm_loss_forward_batched(cm_batch b, const float* ev_x, const float* ev
     StateHeader* hdrs = reinterpret_cast<StateHeader*>(base + b->hdr_off);
     char* ws = base + b->ws_off;
     std::vector<const void*> key{ev_x, ev_y, ev_t, ev_p, inv_depth, ego, loss, state};
-    return run_maybe_graph(b, b->fwd, std::move(key), static_cast<hipStream_t>(stream),
-                           [&](hipStream_t s, cm::Profiler* prof) {
-                               return cm::launch_forward_batch(b->B, b->d_meta, ev, inv_depth, ego,
+    return run_maybe_graph(b, b->fwd, std::move(key), static_cast<hipStream_t>(stream), state,
+                           [&](hipStream_t s, cm::Profiler* prof, const WinMeta* meta) {
+                               return cm::launch_forward_batch(b->B, meta, ev, inv_depth, ego,
                                                                loss, img, hdrs, ws, s, prof);
                            });
 }
@@ -474,10 +485,10 @@ cm_status cm_loss_backward_batched(cm_batch b, const float* ev_x, const float* e
     char* ws = base + b->ws_off;
     std::vector<const void*> key{ev_x, ev_y, ev_t, ev_p, inv_depth, ego, state, grad_loss,
                                  grad_inv_depth, grad_ego};
-    return run_maybe_graph(b, b->bwd, std::move(key), static_cast<hipStream_t>(stream),
-                           [&](hipStream_t s, cm::Profiler* prof) {
-                               return cm::launch_backward_batch(b->B, b->d_meta, ev, inv_depth,
-                                                                ego, img, hdrs, grad_loss,
+    return run_maybe_graph(b, b->bwd, std::move(key), static_cast<hipStream_t>(stream), state,
+                           [&](hipStream_t s, cm::Profiler* prof, const WinMeta* meta) {
+                               return cm::launch_backward_batch(b->B, meta, ev, inv_depth, ego,
+                                                                img, hdrs, grad_loss,
                                                                 grad_inv_depth, grad_ego, ws, s,
                                                                 prof);
                            });
