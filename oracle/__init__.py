@@ -151,3 +151,77 @@ def backward(win, rho=None, theta=None, grad_loss: float = 1.0, flow_grad=False)
     if flow_grad:
         res["dflow"] = dflow
     return res
+
+
+# ---------------------------------------------------------------------------
+# Canonical-order mirror of the deterministic mode (cm_mirror.c)
+# ---------------------------------------------------------------------------
+
+_MIRROR_SRC = os.path.join(_HERE, "cm_mirror.c")
+_MIRROR_PATH = os.path.join(_HERE, "libcm_mirror.so")
+_mirror = None
+
+
+def build_mirror() -> str:
+    tmp = _MIRROR_PATH + ".tmp"
+    subprocess.run(["gcc"] + GCC_FLAGS + [_MIRROR_SRC, "-o", tmp, "-lm"], check=True)
+    os.replace(tmp, _MIRROR_PATH)
+    return _MIRROR_PATH
+
+
+def _load_mirror():
+    global _mirror
+    if _mirror is None:
+        if not os.path.exists(_MIRROR_PATH):
+            build_mirror()
+        lib = ctypes.CDLL(_MIRROR_PATH)
+        P = ctypes.c_void_p
+        lib.cmm_forward.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_float,
+                                    ctypes.c_int64, P, P, P, P, P, P, P, P]
+        lib.cmm_forward.restype = ctypes.c_int
+        lib.cmm_backward.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P,
+                                     ctypes.c_float, ctypes.c_int64, P, P, P, P, P, P,
+                                     ctypes.c_float, P, P]
+        lib.cmm_backward.restype = ctypes.c_int
+        _mirror = lib
+    return _mirror
+
+
+def _mirror_args(win):
+    f = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    return (f([win.fx, win.fy, win.cx, win.cy]), f(win.refs), f(win.x), f(win.y), f(win.t),
+            np.ascontiguousarray(np.asarray(win.p, dtype=np.int8)), f(win.rho), f(win.theta))
+
+
+def mirror_forward(win) -> dict:
+    """Deterministic-mode forward in its canonical order: dict(loss (float32),
+    loss64, n_valid, num [R], nact [R])."""
+    lib = _load_mirror()
+    K, refs, x, y, t, p, rho, th = _mirror_args(win)
+    R = refs.shape[0]
+    loss = np.zeros(1, np.float32)
+    hdr = np.zeros(2 + 2 * R, np.float64)
+    st = lib.cmm_forward(win.width, win.height, _ptr(K), R, _ptr(refs), float(np.float32(win.eps)),
+                         x.shape[0], _ptr(x), _ptr(y), _ptr(t), _ptr(p), _ptr(rho), _ptr(th),
+                         _ptr(loss), _ptr(hdr))
+    if st != 0:
+        raise ValueError(f"cmm_forward failed ({st})")
+    return dict(loss=loss[0], loss64=hdr[0], n_valid=int(hdr[1]), num=hdr[2:2 + R],
+                nact=hdr[2 + R:])
+
+
+def mirror_backward(win, grad_loss: float = 1.0) -> dict:
+    """Deterministic-mode backward in its canonical order: dict(drho float32
+    [H, W], dtheta float32 [6])."""
+    lib = _load_mirror()
+    K, refs, x, y, t, p, rho, th = _mirror_args(win)
+    R = refs.shape[0]
+    drho = np.zeros((win.height, win.width), np.float32)
+    dth = np.zeros(6, np.float32)
+    st = lib.cmm_backward(win.width, win.height, _ptr(K), R, _ptr(refs),
+                          float(np.float32(win.eps)), x.shape[0], _ptr(x), _ptr(y), _ptr(t),
+                          _ptr(p), _ptr(rho), _ptr(th), float(np.float32(grad_loss)), _ptr(drho),
+                          _ptr(dth))
+    if st != 0:
+        raise ValueError(f"cmm_backward failed ({st})")
+    return dict(drho=drho, dtheta=dth)

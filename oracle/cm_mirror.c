@@ -1,0 +1,659 @@
+/*
+ * cm_mirror.c -- CPU replica of the deterministic mode's canonical operation
+ * order, for bit-exact comparison with the GPU.
+ *
+ * TEST INFRASTRUCTURE.  This is not the oracle: the FP64 oracle (cm_oracle.c)
+ * states what the loss is; this file states in which order the deterministic
+ * mode adds things up, and follows that order operation by operation so that
+ * its results are bit-identical to a correct deterministic implementation.  It
+ * shares no code with the GPU library.
+ *
+ * The canonical order (the contract of the deterministic mode):
+ *  - Per-window constants: fx, fy, cx, cy, refs, eps widened from FP32;
+ *    inv_fx = 1/fx, inv_fy = 1/fy, fx/fy, fy/fx, 2/R in FP64.
+ *  - Motion coefficients k0 = fx w_y, k1 = (fx/fy) w_z, k2 = w_x inv_fy,
+ *    k3 = w_y inv_fx, k4 = -(fy w_x), k5 = (fy/fx) w_z, tvx = fx v_x,
+ *    tvy = fy v_y; the flow at pixel (i, j) with xb = i - cx, yb = j - cy:
+ *    s = k3 xb - k2 yb, Ax = (k0 - k1 yb) + xb s, Ay = (k4 + k5 xb) + yb s,
+ *    Bx = tvx - xb vz, By = tvy - yb vz, u = (Ax + rho Bx, Ay + rho By).
+ *    Every operation is a separate IEEE FP64 operation (no fused multiply-add).
+ *  - Bilinear sample: ux = ((((0 + w0 u0) + w1 u1) + w2 u2) + w3 u3) with
+ *    u = 0 for taps off the sensor; w_q = wa * wb.
+ *  - Warp: one loop over the visits (forward references from t_k upward, then
+ *    backward references downward), P += (ref - tau) * u.
+ *  - Events are grouped in blocks of 64 * ept consecutive events, ept =
+ *    clamp(n / 65536, 1, 16); records of a bin are ordered by (block,
+ *    iteration e, program point, lane); in the forward that is event order.
+ *  - Tile accumulation: records of a (reference, 32x32 tile) bin, 64 at a
+ *    time; for tap slot q = 0..3, then lane 0..63, the record's (w, w tbar) is
+ *    added to its cell.  Halos (right column rows 0..32, bottom row) are added
+ *    to the neighbours' column 0 / row 0 in the order left, top, top-left.
+ *  - Reductions: per thread in index order, then a 64-lane shuffle-down tree
+ *    (offsets 32..1), then the per-wavefront results in order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MM_MAX_REFS 16
+#define TW 32
+#define TH 32
+#define TLW 33
+#define TLH 33
+#define NHALO (TH + 1 + TW)
+#define NBORDER (TW + TH - 1)
+
+enum { MM_OK = 0, MM_BAD = -1, MM_NOMEM = -2 };
+
+typedef struct {
+    int W, H, R, HW;
+    double cx, cy, fx, fy, inv_fx, inv_fy, fx_over_fy, fy_over_fx, xmax, ymax, eps, two_over_R;
+    double refs[MM_MAX_REFS];
+    /* motion */
+    double k0, k1, k2, k3, k4, k5, tvx, tvy, vz;
+    const float* rho;
+    /* tiles */
+    int ntx, nty, ntiles, ept, nblocks;
+} mm_win;
+
+typedef struct { double x, y; } d2;
+
+static int mm_setup(mm_win* w, int W, int H, const float* K, int R, const float* refs, float eps,
+                    const float* rho, const float* theta, int64_t n)
+{
+    if (W <= 0 || H <= 0 || R < 1 || R > MM_MAX_REFS) return MM_BAD;
+    memset(w, 0, sizeof *w);
+    w->W = W; w->H = H; w->R = R; w->HW = W * H;
+    w->fx = K[0]; w->fy = K[1]; w->cx = K[2]; w->cy = K[3];
+    w->inv_fx = 1.0 / w->fx; w->inv_fy = 1.0 / w->fy;
+    w->fx_over_fy = w->fx / w->fy; w->fy_over_fx = w->fy / w->fx;
+    w->xmax = (double)(W - 1); w->ymax = (double)(H - 1);
+    w->eps = eps;
+    w->two_over_R = 2.0 / (double)R;
+    for (int r = 0; r < R; ++r) w->refs[r] = refs[r];
+    const double vx = theta[0], vy = theta[1], vz = theta[2];
+    const double wx = theta[3], wy = theta[4], wz = theta[5];
+    w->k0 = w->fx * wy;
+    w->k1 = w->fx_over_fy * wz;
+    w->k2 = wx * w->inv_fy;
+    w->k3 = wy * w->inv_fx;
+    w->k4 = -w->fy * wx;
+    w->k5 = w->fy_over_fx * wz;
+    w->tvx = w->fx * vx;
+    w->tvy = w->fy * vy;
+    w->vz = vz;
+    w->rho = rho;
+    w->ntx = (W + TW - 1) / TW;
+    w->nty = (H + TH - 1) / TH;
+    w->ntiles = w->ntx * w->nty;
+    int64_t ept = n / (64 * 1024);
+    if (ept < 1) ept = 1;
+    if (ept > 16) ept = 16;
+    w->ept = (int)ept;
+    const int64_t per = 64 * ept;
+    w->nblocks = (int)((n + per - 1) / per);
+    if (w->nblocks < 1) w->nblocks = 1;
+    return MM_OK;
+}
+
+static void mm_parts(const mm_win* w, int i, int j, double* Ax, double* Ay, double* Bx, double* By)
+{
+    const double xb = (double)i - w->cx;
+    const double yb = (double)j - w->cy;
+    const double s = w->k3 * xb - w->k2 * yb;
+    *Ax = (w->k0 - w->k1 * yb) + xb * s;
+    *Ay = (w->k4 + w->k5 * xb) + yb * s;
+    *Bx = w->tvx - xb * w->vz;
+    *By = w->tvy - yb * w->vz;
+}
+
+static d2 mm_flow(const mm_win* w, int i, int j)
+{
+    double Ax, Ay, Bx, By;
+    mm_parts(w, i, j, &Ax, &Ay, &Bx, &By);
+    const double r = (double)w->rho[j * w->W + i];
+    d2 u = {Ax + r * Bx, Ay + r * By};
+    return u;
+}
+
+typedef struct { int x0, y0; double a, b; int inx, iny; } mm_taps;
+
+static mm_taps mm_make_taps(const mm_win* w, double X, double Y)
+{
+    mm_taps t;
+    const double fx0 = floor(X), fy0 = floor(Y);
+    t.x0 = (int)fx0; t.y0 = (int)fy0;
+    t.a = X - fx0; t.b = Y - fy0;
+    t.inx = t.x0 + 1 < w->W;
+    t.iny = t.y0 + 1 < w->H;
+    return t;
+}
+
+static int mm_tap_in(const mm_taps* t, int q) { return ((q & 1) ? t->inx : 1) && ((q & 2) ? t->iny : 1); }
+
+static double mm_tap_w(const mm_taps* t, int q)
+{
+    const double wa = (q & 1) ? t->a : 1.0 - t->a;
+    const double wb = (q & 2) ? t->b : 1.0 - t->b;
+    return wa * wb;
+}
+
+static void mm_tap_dw(const mm_taps* t, int q, double* dX, double* dY)
+{
+    const double wa = (q & 1) ? t->a : 1.0 - t->a;
+    const double wb = (q & 2) ? t->b : 1.0 - t->b;
+    *dX = (q & 1) ? wb : -wb;
+    *dY = (q & 2) ? wa : -wa;
+}
+
+static void mm_tap_flows(const mm_win* w, const mm_taps* t, d2 uq[4])
+{
+    for (int q = 0; q < 4; ++q) {
+        if (mm_tap_in(t, q)) uq[q] = mm_flow(w, t->x0 + (q & 1), t->y0 + (q >> 1));
+        else { uq[q].x = 0.0; uq[q].y = 0.0; }
+    }
+}
+
+static int mm_inside(const mm_win* w, double X, double Y)
+{
+    return X >= 0.0 && X <= w->xmax && Y >= 0.0 && Y <= w->ymax;
+}
+
+static int mm_refs_before(const mm_win* w, double t)
+{
+    int m = 0;
+    for (int r = 0; r < w->R; ++r) m += w->refs[r] < t;
+    return m;
+}
+
+/* The warp; px/py indexed by reference.  Returns validity, *mb = refs before t. */
+static int mm_warp(const mm_win* w, double x0, double y0, double tk, double* px, double* py, int* mbo)
+{
+    *mbo = 0;
+    if (!(isfinite(x0) && isfinite(y0) && tk >= 0.0 && tk <= 1.0 && mm_inside(w, x0, y0))) return 0;
+    const int mb = mm_refs_before(w, tk);
+    *mbo = mb;
+    int rs = mb;
+    if (rs < w->R && w->refs[rs] == tk) { px[rs] = x0; py[rs] = y0; ++rs; }
+    const int nf = w->R - rs, nv = nf + mb;
+    double X = x0, Y = y0, tau = tk;
+    for (int j = 0; j < nv; ++j) {
+        int r;
+        if (j < nf) r = rs + j;
+        else {
+            r = mb - 1 - (j - nf);
+            if (j == nf) { X = x0; Y = y0; tau = tk; }
+        }
+        const mm_taps t = mm_make_taps(w, X, Y);
+        d2 uq[4];
+        mm_tap_flows(w, &t, uq);
+        double ux = 0.0, uy = 0.0;
+        for (int q = 0; q < 4; ++q) {
+            const double wq = mm_tap_w(&t, q);
+            ux += wq * uq[q].x;
+            uy += wq * uq[q].y;
+        }
+        const double ref = w->refs[r];
+        const double dt = ref - tau;
+        X = X + dt * ux;
+        Y = Y + dt * uy;
+        tau = ref;
+        if (!mm_inside(w, X, Y)) return 0;
+        px[r] = X; py[r] = Y;
+    }
+    return 1;
+}
+
+static int mm_tile_of(const mm_win* w, double X, double Y)
+{
+    const mm_taps t = mm_make_taps(w, X, Y);
+    return (t.y0 / TH) * w->ntx + t.x0 / TW;
+}
+
+/* ------------------------------------------------------------------------
+ * Reductions in the GPU's order
+ * ---------------------------------------------------------------------- */
+
+/* Lane 0 of a 64-lane shuffle-down tree. */
+static double mm_wave_sum(double* v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        for (int l = 0; l < o; ++l) v[l] = v[l] + v[l + o];
+    return v[0];
+}
+
+/* Block of nthreads (multiple of 64): per-wavefront trees, then the wave
+ * results in order. */
+static double mm_block_sum(double* v, int nthreads)
+{
+    double s = 0.0;
+    for (int wv = 0; wv < nthreads / 64; ++wv) {
+        const double ws = mm_wave_sum(v + 64 * wv);
+        s += ws;
+    }
+    return s;
+}
+
+static void mm_reduce_pixel(d2 a, d2 b, double eps, double* sum, double* cnt)
+{
+    if (a.x + b.x > 0.0) *cnt += 1.0;
+    if (a.x != 0.0 || a.y != 0.0) { const double T = a.y / (a.x + eps); *sum += T * T; }
+    if (b.x != 0.0 || b.y != 0.0) { const double T = b.y / (b.x + eps); *sum += T * T; }
+}
+
+/* ------------------------------------------------------------------------
+ * Forward
+ * ---------------------------------------------------------------------- */
+
+typedef struct { double X, Y; float t; int neg; } mm_srec;
+
+typedef struct {
+    mm_win w;
+    d2* img;           /* [R][2][HW] */
+    double num[MM_MAX_REFS], nact[MM_MAX_REFS];
+    double loss;
+    uint64_t n_valid;
+} mm_state;
+
+static int mm_forward_impl(mm_state* S, int64_t n, const float* ex, const float* ey,
+                           const float* et, const int8_t* ep)
+{
+    mm_win* w = &S->w;
+    const int R = w->R, nbins = R * w->ntiles;
+    /* records in canonical order: events in order, then references */
+    int64_t* cnt = (int64_t*)calloc((size_t)nbins + 1, sizeof(int64_t));
+    double px[MM_MAX_REFS], py[MM_MAX_REFS];
+    int mb;
+    S->n_valid = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        if (!mm_warp(w, ex[k], ey[k], et[k], px, py, &mb)) continue;
+        ++S->n_valid;
+        for (int r = 0; r < R; ++r) cnt[r * w->ntiles + mm_tile_of(w, px[r], py[r]) + 1]++;
+    }
+    for (int b = 0; b < nbins; ++b) cnt[b + 1] += cnt[b];
+    mm_srec* rec = (mm_srec*)malloc(sizeof(mm_srec) * (size_t)(cnt[nbins] + 1));
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)nbins);
+    if (!rec || !fill) { free(cnt); free(rec); free(fill); return MM_NOMEM; }
+    memcpy(fill, cnt, sizeof(int64_t) * (size_t)nbins);
+    for (int64_t k = 0; k < n; ++k) {
+        if (!mm_warp(w, ex[k], ey[k], et[k], px, py, &mb)) continue;
+        for (int r = 0; r < R; ++r) {
+            const int b = r * w->ntiles + mm_tile_of(w, px[r], py[r]);
+            mm_srec* q = &rec[fill[b]++];
+            q->X = px[r]; q->Y = py[r]; q->t = et[k]; q->neg = !(ep[k] > 0);
+        }
+    }
+    free(fill);
+
+    S->img = (d2*)calloc((size_t)R * 2 * w->HW, sizeof(d2));
+    d2* halo = (d2*)calloc((size_t)nbins * NHALO * 2, sizeof(d2));
+    double* part = (double*)calloc((size_t)nbins * 4, sizeof(double));
+    d2* lds = (d2*)malloc(sizeof(d2) * 2 * TLW * TLH);
+    double* red = (double*)malloc(sizeof(double) * 256);
+    double* red2 = (double*)malloc(sizeof(double) * 256);
+    if (!S->img || !halo || !part || !lds || !red || !red2) return MM_NOMEM;
+
+    for (int b = 0; b < nbins; ++b) {
+        const int r = b / w->ntiles, tile = b - r * w->ntiles;
+        const int ty = tile / w->ntx, tx = tile - ty * w->ntx;
+        const int xo = tx * TW, yo = ty * TH;
+        const double ref = w->refs[r];
+        memset(lds, 0, sizeof(d2) * 2 * TLW * TLH);
+        for (int64_t c0 = cnt[b]; c0 < cnt[b + 1]; c0 += 64) {
+            const int64_t c1 = c0 + 64 < cnt[b + 1] ? c0 + 64 : cnt[b + 1];
+            for (int q = 0; q < 4; ++q)
+                for (int64_t i = c0; i < c1; ++i) {
+                    const mm_srec* s = &rec[i];
+                    const mm_taps tp = mm_make_taps(w, s->X, s->Y);
+                    const double wt = mm_tap_w(&tp, q);
+                    if (!(mm_tap_in(&tp, q) && wt != 0.0)) continue;
+                    const double tb = 1.0 - fabs(ref - (double)s->t);
+                    const int key = (s->neg ? TLW * TLH : 0) + (tp.y0 - yo + (q >> 1)) * TLW +
+                                    tp.x0 - xo + (q & 1);
+                    lds[key].x = lds[key].x + wt;
+                    lds[key].y = lds[key].y + wt * tb;
+                }
+        }
+        /* own pixels + interior reduce (256 threads, pixel i to thread i % 256) */
+        for (int th = 0; th < 256; ++th) { red[th] = 0.0; red2[th] = 0.0; }
+        for (int i = 0; i < TW * TH; ++i) {
+            const int lx = i % TW, ly = i / TW, X = xo + lx, Y = yo + ly;
+            if (X >= w->W || Y >= w->H) continue;
+            const d2 a = lds[ly * TLW + lx], c = lds[TLW * TLH + ly * TLW + lx];
+            S->img[(size_t)(r * 2 + 0) * w->HW + Y * w->W + X] = a;
+            S->img[(size_t)(r * 2 + 1) * w->HW + Y * w->W + X] = c;
+            if (lx > 0 && ly > 0) mm_reduce_pixel(a, c, w->eps, &red[i % 256], &red2[i % 256]);
+        }
+        d2* hb = halo + (size_t)b * NHALO * 2;
+        for (int j = 0; j < NHALO; ++j) {
+            const int idx = (j <= TH) ? j * TLW + TW : TH * TLW + (j - (TH + 1));
+            hb[j * 2 + 0] = lds[idx];
+            hb[j * 2 + 1] = lds[TLW * TLH + idx];
+        }
+        part[(b * 2 + 0) * 2 + 0] = mm_block_sum(red, 256);
+        part[(b * 2 + 0) * 2 + 1] = mm_block_sum(red2, 256);
+    }
+    /* merge (64 threads, border pixel j to thread j) */
+    for (int b = 0; b < nbins; ++b) {
+        const int r = b / w->ntiles, tile = b - r * w->ntiles;
+        const int ty = tile / w->ntx, tx = tile - ty * w->ntx;
+        const int xo = tx * TW, yo = ty * TH;
+        for (int th = 0; th < 64; ++th) { red[th] = 0.0; red2[th] = 0.0; }
+        for (int j = 0; j < NBORDER; ++j) {
+            const int lx = j < TH ? 0 : j - TH + 1, ly = j < TH ? j : 0;
+            const int X = xo + lx, Y = yo + ly;
+            if (X >= w->W || Y >= w->H) continue;
+            const int pix = Y * w->W + X;
+            d2 v[2];
+            for (int pol = 0; pol < 2; ++pol) {
+                d2 a = S->img[(size_t)(r * 2 + pol) * w->HW + pix];
+                if (lx == 0 && tx > 0) {
+                    const d2 h = halo[((size_t)(b - 1) * NHALO + ly) * 2 + pol];
+                    a.x += h.x; a.y += h.y;
+                }
+                if (ly == 0 && ty > 0) {
+                    const d2 h = halo[((size_t)(b - w->ntx) * NHALO + TH + 1 + lx) * 2 + pol];
+                    a.x += h.x; a.y += h.y;
+                }
+                if (lx == 0 && ly == 0 && tx > 0 && ty > 0) {
+                    const d2 h = halo[((size_t)(b - w->ntx - 1) * NHALO + TH) * 2 + pol];
+                    a.x += h.x; a.y += h.y;
+                }
+                S->img[(size_t)(r * 2 + pol) * w->HW + pix] = a;
+                v[pol] = a;
+            }
+            mm_reduce_pixel(v[0], v[1], w->eps, &red[j % 64], &red2[j % 64]);
+        }
+        part[(b * 2 + 1) * 2 + 0] = mm_block_sum(red, 64);
+        part[(b * 2 + 1) * 2 + 1] = mm_block_sum(red2, 64);
+    }
+    /* finalize (256 threads) */
+    double L = 0.0;
+    for (int r = 0; r < R; ++r) {
+        for (int th = 0; th < 256; ++th) { red[th] = 0.0; red2[th] = 0.0; }
+        for (int j = 0; j < 2 * w->ntiles; ++j) {
+            red[j % 256] += part[((size_t)r * 2 * w->ntiles + j) * 2 + 0];
+            red2[j % 256] += part[((size_t)r * 2 * w->ntiles + j) * 2 + 1];
+        }
+        const double s = mm_block_sum(red, 256), c = mm_block_sum(red2, 256);
+        S->num[r] = s;
+        S->nact[r] = c;
+        L += s / (c + w->eps);
+    }
+    S->loss = L / (double)R;
+    free(cnt); free(rec); free(halo); free(part); free(lds); free(red); free(red2);
+    return MM_OK;
+}
+
+int cmm_forward(int W, int H, const float* K, int R, const float* refs, float eps, int64_t n,
+                const float* x, const float* y, const float* t, const int8_t* p,
+                const float* rho, const float* theta, float* loss_out, double* hdr_out)
+{
+    mm_state S;
+    memset(&S, 0, sizeof S);
+    if (mm_setup(&S.w, W, H, K, R, refs, eps, rho, theta, n)) return MM_BAD;
+    const int st = mm_forward_impl(&S, n, x, y, t, p);
+    if (st == MM_OK) {
+        *loss_out = (float)S.loss;
+        if (hdr_out) {
+            hdr_out[0] = S.loss;
+            hdr_out[1] = (double)S.n_valid;
+            for (int r = 0; r < R; ++r) { hdr_out[2 + r] = S.num[r]; hdr_out[2 + R + r] = S.nact[r]; }
+        }
+    }
+    free(S.img);
+    return st;
+}
+
+/* ------------------------------------------------------------------------
+ * Backward
+ * ---------------------------------------------------------------------- */
+
+typedef struct { double X, Y, gx, gy; } mm_grec;
+
+/* The direct sensitivity (seed) of one reference position, added into L. */
+static void mm_direct(const mm_win* w, const d2* plane, double coef, double tb, double X, double Y,
+                      double* Lx, double* Ly)
+{
+    const mm_taps tp = mm_make_taps(w, X, Y);
+    for (int q = 0; q < 4; ++q) {
+        if (!mm_tap_in(&tp, q)) continue;
+        const d2 cs = plane[(tp.y0 + (q >> 1)) * w->W + tp.x0 + (q & 1)];
+        const double S = cs.y;
+        const double inv = 1.0 / (cs.x + w->eps);
+        const double sc = S * inv;
+        const double g = coef * sc * inv * (tb - sc);
+        double dX, dY;
+        mm_tap_dw(&tp, q, &dX, &dY);
+        *Lx += g * dX;
+        *Ly += g * dY;
+    }
+}
+
+static void mm_jacobian_t(const mm_win* w, double X, double Y, double Lx, double Ly, double* jx,
+                          double* jy)
+{
+    const mm_taps tp = mm_make_taps(w, X, Y);
+    d2 uq[4];
+    mm_tap_flows(w, &tp, uq);
+    *jx = 0.0;
+    *jy = 0.0;
+    for (int q = 0; q < 4; ++q) {
+        const double lu = Lx * uq[q].x + Ly * uq[q].y;
+        double dX, dY;
+        mm_tap_dw(&tp, q, &dX, &dY);
+        *jx += lu * dX;
+        *jy += lu * dY;
+    }
+}
+
+static void mm_dtheta(const mm_win* w, int i, int j, double r, double gx, double gy, double* dth)
+{
+    const double xb = (double)i - w->cx, yb = (double)j - w->cy;
+    dth[0] += r * w->fx * gx;
+    dth[1] += r * w->fy * gy;
+    dth[2] -= r * (xb * gx + yb * gy);
+    dth[3] -= (xb * yb * w->inv_fy) * gx + (w->fy + yb * yb * w->inv_fy) * gy;
+    dth[4] += (w->fx + xb * xb * w->inv_fx) * gx + (xb * yb * w->inv_fx) * gy;
+    dth[5] += (w->fy_over_fx * xb) * gy - (w->fx_over_fy * yb) * gx;
+}
+
+/* One wavefront-iteration of the sweep: the per-lane reverse passes run in
+ * lockstep; records are emitted at each program point in lane order. */
+typedef struct {
+    int live, nv, rs, mb, pol;
+    double x0, y0, tk, px[MM_MAX_REFS], py[MM_MAX_REFS];
+    double Lx, Ly, g0x, g0y;
+} mm_lane;
+
+static void mm_emit(const mm_win* w, mm_grec* rec, int64_t* fill, double X, double Y, double gx,
+                    double gy)
+{
+    mm_grec* q = &rec[fill[mm_tile_of(w, X, Y)]++];
+    q->X = X; q->Y = Y; q->gx = gx; q->gy = gy;
+}
+
+int cmm_backward(int W, int H, const float* K, int R, const float* refs, float eps, int64_t n,
+                 const float* x, const float* y, const float* t, const int8_t* p,
+                 const float* rho, const float* theta, float grad_loss, float* drho_out,
+                 float* dtheta_out)
+{
+    mm_state S;
+    memset(&S, 0, sizeof S);
+    if (mm_setup(&S.w, W, H, K, R, refs, eps, rho, theta, n)) return MM_BAD;
+    int st = mm_forward_impl(&S, n, x, y, t, p);
+    if (st) { free(S.img); return st; }
+    const mm_win* w = &S.w;
+    const int nt = w->ntiles;
+    double coef[MM_MAX_REFS];
+    for (int r = 0; r < R; ++r) coef[r] = w->two_over_R / (S.nact[r] + w->eps);
+
+    /* count: sampling positions per tile, per event in order */
+    int64_t* cnt = (int64_t*)calloc((size_t)nt + 1, sizeof(int64_t));
+    double px[MM_MAX_REFS], py[MM_MAX_REFS];
+    int mb;
+    for (int64_t k = 0; k < n; ++k) {
+        if (!mm_warp(w, x[k], y[k], t[k], px, py, &mb)) continue;
+        const int rs = (mb < R && w->refs[mb] == (double)t[k]) ? mb + 1 : mb;
+        for (int r = rs + 1; r < R; ++r) cnt[mm_tile_of(w, px[r - 1], py[r - 1]) + 1]++;
+        for (int r = mb - 2; r >= 0; --r) cnt[mm_tile_of(w, px[r + 1], py[r + 1]) + 1]++;
+        if (rs < R || mb > 0) cnt[mm_tile_of(w, x[k], y[k]) + 1]++;
+    }
+    for (int b = 0; b < nt; ++b) cnt[b + 1] += cnt[b];
+    mm_grec* rec = (mm_grec*)malloc(sizeof(mm_grec) * (size_t)(cnt[nt] + 1));
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)nt);
+    memcpy(fill, cnt, sizeof(int64_t) * (size_t)nt);
+
+    /* sweep: blocks of 64 * ept events; per iteration, 64 lanes in lockstep */
+    mm_lane lanes[64];
+    for (int blk = 0; blk < w->nblocks; ++blk) {
+        for (int e = 0; e < w->ept; ++e) {
+            int maxnv = 0;
+            for (int l = 0; l < 64; ++l) {
+                mm_lane* L = &lanes[l];
+                const int64_t k = (int64_t)blk * 64 * w->ept + (int64_t)e * 64 + l;
+                L->live = 0;
+                if (k >= n) continue;
+                if (!mm_warp(w, x[k], y[k], t[k], L->px, L->py, &L->mb)) continue;
+                L->live = 1;
+                L->x0 = x[k]; L->y0 = y[k]; L->tk = t[k];
+                L->pol = p[k] > 0 ? 0 : 1;
+                L->rs = (L->mb < R && w->refs[L->mb] == L->tk) ? L->mb + 1 : L->mb;
+                L->nv = (R - L->rs) + L->mb;
+                L->Lx = L->Ly = L->g0x = L->g0y = 0.0;
+                if (L->nv > maxnv) maxnv = L->nv;
+            }
+            for (int j = 0; j < maxnv; ++j) {
+                /* every lane's step j; emits of this program point in lane order */
+                for (int l = 0; l < 64; ++l) {
+                    mm_lane* L = &lanes[l];
+                    if (!L->live || j >= L->nv) continue;
+                    const int nf = R - L->rs;
+                    int r, rp, first, restart;
+                    if (j < nf) {
+                        r = R - 1 - j; first = (r == L->rs); restart = (j == 0);
+                        rp = first ? r : r - 1;
+                    } else {
+                        r = j - nf; first = (r == L->mb - 1); restart = (j == nf);
+                        rp = first ? r : r + 1;
+                    }
+                    const double X = first ? L->x0 : L->px[rp];
+                    const double Y = first ? L->y0 : L->py[rp];
+                    const double dt = w->refs[r] - (first ? L->tk : w->refs[rp]);
+                    if (restart) { L->Lx = 0.0; L->Ly = 0.0; }
+                    mm_direct(w, S.img + (size_t)(r * 2 + L->pol) * w->HW, coef[r],
+                              1.0 - fabs(w->refs[r] - L->tk), L->px[r], L->py[r], &L->Lx, &L->Ly);
+                    if (first) {
+                        L->g0x += dt * L->Lx;
+                        L->g0y += dt * L->Ly;
+                    } else {
+                        mm_emit(w, rec, fill, X, Y, dt * L->Lx, dt * L->Ly);
+                        double jx, jy;
+                        mm_jacobian_t(w, X, Y, L->Lx, L->Ly, &jx, &jy);
+                        L->Lx += dt * jx;
+                        L->Ly += dt * jy;
+                    }
+                }
+            }
+            for (int l = 0; l < 64; ++l) {
+                mm_lane* L = &lanes[l];
+                if (L->live && L->nv > 0) mm_emit(w, rec, fill, L->x0, L->y0, L->g0x, L->g0y);
+            }
+        }
+    }
+    free(fill);
+
+    /* tiles: dL/du in LDS order, then d rho and d theta shares */
+    const double gl = (double)grad_loss;
+    d2* halo = (d2*)calloc((size_t)nt * NHALO, sizeof(d2));
+    d2* border = (d2*)calloc((size_t)nt * NBORDER, sizeof(d2));
+    double* part = (double*)calloc((size_t)nt * 12, sizeof(double));
+    d2* lds = (d2*)malloc(sizeof(d2) * TLW * TLH);
+    double* red = (double*)malloc(sizeof(double) * 256 * 6);
+    for (int tile = 0; tile < nt; ++tile) {
+        const int ty = tile / w->ntx, tx = tile - ty * w->ntx;
+        const int xo = tx * TW, yo = ty * TH;
+        memset(lds, 0, sizeof(d2) * TLW * TLH);
+        for (int64_t c0 = cnt[tile]; c0 < cnt[tile + 1]; c0 += 64) {
+            const int64_t c1 = c0 + 64 < cnt[tile + 1] ? c0 + 64 : cnt[tile + 1];
+            for (int q = 0; q < 4; ++q)
+                for (int64_t i = c0; i < c1; ++i) {
+                    const mm_grec* s = &rec[i];
+                    const mm_taps tp = mm_make_taps(w, s->X, s->Y);
+                    const double wt = mm_tap_w(&tp, q);
+                    if (!(mm_tap_in(&tp, q) && wt != 0.0)) continue;
+                    const int key = (tp.y0 - yo + (q >> 1)) * TLW + tp.x0 - xo + (q & 1);
+                    lds[key].x = lds[key].x + wt * s->gx;
+                    lds[key].y = lds[key].y + wt * s->gy;
+                }
+        }
+        memset(red, 0, sizeof(double) * 256 * 6);
+        for (int i = 0; i < TW * TH; ++i) {
+            const int lx = i % TW, ly = i / TW, X = xo + lx, Y = yo + ly;
+            if (X >= w->W || Y >= w->H) continue;
+            const d2 g = lds[ly * TLW + lx];
+            if (lx == 0 || ly == 0) {
+                border[(size_t)tile * NBORDER + (lx == 0 ? ly : TH + lx - 1)] = g;
+                continue;
+            }
+            double Ax, Ay, Bx, By;
+            mm_parts(w, X, Y, &Ax, &Ay, &Bx, &By);
+            const int pix = Y * w->W + X;
+            drho_out[pix] = (float)(gl * (g.x * Bx + g.y * By));
+            if (g.x != 0.0 || g.y != 0.0) {
+                double d[6];
+                for (int c = 0; c < 6; ++c) d[c] = red[c * 256 + i % 256];
+                mm_dtheta(w, X, Y, (double)rho[pix], g.x, g.y, d);
+                for (int c = 0; c < 6; ++c) red[c * 256 + i % 256] = d[c];
+            }
+        }
+        for (int j = 0; j < NHALO; ++j) {
+            const int idx = (j <= TH) ? j * TLW + TW : TH * TLW + (j - (TH + 1));
+            halo[(size_t)tile * NHALO + j] = lds[idx];
+        }
+        for (int c = 0; c < 6; ++c) part[(size_t)tile * 12 + c] = mm_block_sum(red + c * 256, 256);
+    }
+    for (int tile = 0; tile < nt; ++tile) {
+        const int ty = tile / w->ntx, tx = tile - ty * w->ntx;
+        const int xo = tx * TW, yo = ty * TH;
+        memset(red, 0, sizeof(double) * 64 * 6);
+        for (int j = 0; j < NBORDER; ++j) {
+            const int lx = j < TH ? 0 : j - TH + 1, ly = j < TH ? j : 0;
+            const int X = xo + lx, Y = yo + ly;
+            if (X >= w->W || Y >= w->H) continue;
+            d2 g = border[(size_t)tile * NBORDER + j];
+            if (lx == 0 && tx > 0) {
+                const d2 h = halo[(size_t)(tile - 1) * NHALO + ly];
+                g.x += h.x; g.y += h.y;
+            }
+            if (ly == 0 && ty > 0) {
+                const d2 h = halo[(size_t)(tile - w->ntx) * NHALO + TH + 1 + lx];
+                g.x += h.x; g.y += h.y;
+            }
+            if (lx == 0 && ly == 0 && tx > 0 && ty > 0) {
+                const d2 h = halo[(size_t)(tile - w->ntx - 1) * NHALO + TH];
+                g.x += h.x; g.y += h.y;
+            }
+            double Ax, Ay, Bx, By;
+            mm_parts(w, X, Y, &Ax, &Ay, &Bx, &By);
+            const int pix = Y * w->W + X;
+            drho_out[pix] = (float)(gl * (g.x * Bx + g.y * By));
+            if (g.x != 0.0 || g.y != 0.0) {
+                double d[6];
+                for (int c = 0; c < 6; ++c) d[c] = red[c * 64 + j % 64];
+                mm_dtheta(w, X, Y, (double)rho[pix], g.x, g.y, d);
+                for (int c = 0; c < 6; ++c) red[c * 64 + j % 64] = d[c];
+            }
+        }
+        for (int c = 0; c < 6; ++c) part[(size_t)tile * 12 + 6 + c] = mm_block_sum(red + c * 64, 64);
+    }
+    /* finalize (256 threads) */
+    for (int c = 0; c < 6; ++c) {
+        memset(red, 0, sizeof(double) * 256);
+        for (int j = 0; j < 2 * nt; ++j) red[j % 256] += part[(size_t)j * 6 + c];
+        dtheta_out[c] = (float)(gl * mm_block_sum(red, 256));
+    }
+    free(cnt); free(rec); free(halo); free(border); free(part); free(lds); free(red); free(S.img);
+    return MM_OK;
+}

@@ -85,3 +85,51 @@ def test_deterministic_ragged_and_edge_cases(cm):
         assert_loss_close(float(a[0][0]), o["loss"], what=win.name)
         ob = oracle.backward(win)
         assert_grads_close(a[1], a[2], ob["drho"], ob["dtheta"], what=win.name)
+
+
+def _mirror_cases():
+    wins = [eventgen.make_window("c1"), eventgen.make_window("c2"), eventgen.make_window("c3", 5)]
+    for n in (1, 65, 1000):
+        wins.append(eventgen.edge_window(950 + n, "346x260", n, refs=[0.0, 0.3, 1.0],
+                                         n_segments=5, name=f"m{n}"))
+    w = eventgen.make_window("c1")
+    t = w.t.copy()
+    x = w.x.copy()
+    t[::9] = 1.0
+    x[::13] = np.nan
+    wins.append(w.replace(t=t, x=x, name="c1-malformed"))
+    return wins
+
+
+@pytest.mark.parametrize("idx", range(7))
+def test_deterministic_bitwise_equals_canonical_mirror(cm, idx):
+    win = _mirror_cases()[idx]
+    d = to_device(win)
+    desc = cm.WindowDesc.from_window(win, mode=cm.CM_MODE_DETERMINISTIC)
+    print(f"[gpu] mirror {win.name} n={win.n}", flush=True)
+    loss, state = cm.forward(desc, d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"])
+    g_rho, g_ego = cm.backward(desc, d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"], state,
+                               torch.full((1,), 0.75, device="cuda:0"))
+    diag = cm.diagnostics(desc, state)
+    m = oracle.mirror_forward(win)
+    mb = oracle.mirror_backward(win, grad_loss=0.75)
+    assert float(loss.item()) == float(m["loss"])
+    assert diag["loss"] == m["loss64"]
+    assert diag["n_valid"] == m["n_valid"]
+    assert diag["num"] == list(m["num"]) and diag["nact"] == list(m["nact"])
+    assert np.array_equal(g_rho.cpu().numpy().reshape(win.height, win.width), mb["drho"])
+    assert np.array_equal(g_ego.cpu().numpy(), mb["dtheta"])
+
+
+def test_deterministic_c5_bitwise_equals_canonical_mirror(cm):
+    win = eventgen.make_window("c5")
+    d = to_device(win)
+    desc = cm.WindowDesc.from_window(win, mode=cm.CM_MODE_DETERMINISTIC)
+    loss, state = cm.forward(desc, d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"])
+    g_rho, g_ego = cm.backward(desc, d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"], state,
+                               torch.ones(1, device="cuda:0"))
+    m = oracle.mirror_forward(win)
+    mb = oracle.mirror_backward(win)
+    assert float(loss.item()) == float(m["loss"])
+    assert np.array_equal(g_rho.cpu().numpy().reshape(win.height, win.width), mb["drho"])
+    assert np.array_equal(g_ego.cpu().numpy(), mb["dtheta"])

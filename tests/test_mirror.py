@@ -1,0 +1,40 @@
+"""The canonical-order mirror of the deterministic mode computes the same loss
+and gradient as the FP64 oracle (within the parity tolerance): it only fixes
+the order of the additions, not what is added."""
+
+import numpy as np
+import pytest
+
+import eventgen
+import oracle
+from tests.helpers import assert_grads_close, assert_loss_close
+
+
+@pytest.mark.parametrize("case", ["c1", "edge3", "edge8", "ragged"])
+def test_mirror_agrees_with_oracle(case):
+    if case == "c1":
+        win = eventgen.make_window("c1")
+    elif case == "edge3":
+        win = eventgen.edge_window(31, "346x260", 6000, refs=[0.0, 0.5, 1.0], n_segments=20)
+    elif case == "edge8":
+        win = eventgen.edge_window(32, "346x260", 3000, refs=list(eventgen.refs_even(8)),
+                                   n_segments=10, motion_sigma=0.3)
+    else:
+        win = eventgen.edge_window(33, "346x260", 130, refs=[0.2, 0.7], n_segments=3)
+    m = oracle.mirror_forward(win)
+    o = oracle.forward(win, valid=True)
+    assert m["n_valid"] == int(o["valid"].sum())
+    np.testing.assert_array_equal(m["nact"], o["nact"])
+    assert_loss_close(float(m["loss64"]), o["loss"], rtol=1e-12, what=case)
+    mb = oracle.mirror_backward(win, grad_loss=1.5)
+    ob = oracle.backward(win, grad_loss=1.5)
+    assert_grads_close(mb["drho"], mb["dtheta"], ob["drho"], ob["dtheta"], rtol=1e-5, what=case)
+
+
+def test_mirror_empty_window():
+    win = eventgen.make_window("c1")
+    e = np.zeros(0, np.float32)
+    win = win.replace(x=e, y=e, t=e, p=np.zeros(0, np.int8))
+    assert oracle.mirror_forward(win)["loss"] == 0.0
+    mb = oracle.mirror_backward(win)
+    assert not mb["drho"].any() and not mb["dtheta"].any()
