@@ -24,6 +24,9 @@
  *  - Events are grouped in blocks of 64 * ept consecutive events, ept =
  *    clamp(n / 65536, 1, 16); records of a bin are ordered by (block,
  *    iteration e, program point, lane); in the forward that is event order.
+ *    The backward's program points are the visits j = R-1 .. 0 (visits: the
+ *    forward sweep's references at or after t_k upward, then the backward
+ *    sweep's downward), then the event's own record.
  *  - Tile accumulation: records of a (reference, 32x32 tile) bin, 64 at a
  *    time; for tap slot q = 0..3, then lane 0..63, the record's (w, w tbar) is
  *    added to its cell.  Halos (right column rows 0..32, bottom row) are added
@@ -505,11 +508,13 @@ int cmm_backward(int W, int H, const float* K, int R, const float* refs, float e
     int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)nt);
     memcpy(fill, cnt, sizeof(int64_t) * (size_t)nt);
 
-    /* sweep: blocks of 64 * ept events; per iteration, 64 lanes in lockstep */
+    /* sweep: blocks of 64 * ept events; per iteration, 64 lanes in lockstep
+     * over the visits j = R-1 .. 0 (the backward sweep backwards, then the
+     * forward sweep backwards); the records of one visit number are emitted
+     * in lane order, then the event records in lane order. */
     mm_lane lanes[64];
     for (int blk = 0; blk < w->nblocks; ++blk) {
         for (int e = 0; e < w->ept; ++e) {
-            int maxnv = 0;
             for (int l = 0; l < 64; ++l) {
                 mm_lane* L = &lanes[l];
                 const int64_t k = (int64_t)blk * 64 * w->ept + (int64_t)e * 64 + l;
@@ -519,28 +524,24 @@ int cmm_backward(int W, int H, const float* K, int R, const float* refs, float e
                 L->live = 1;
                 L->x0 = x[k]; L->y0 = y[k]; L->tk = t[k];
                 L->pol = p[k] > 0 ? 0 : 1;
-                L->rs = (L->mb < R && w->refs[L->mb] == L->tk) ? L->mb + 1 : L->mb;
-                L->nv = (R - L->rs) + L->mb;
+                L->rs = (L->mb < R && w->refs[L->mb] == L->tk) ? 1 : 0;   /* eq */
+                L->nv = R - L->mb;                                       /* nf */
                 L->Lx = L->Ly = L->g0x = L->g0y = 0.0;
-                if (L->nv > maxnv) maxnv = L->nv;
             }
-            for (int j = 0; j < maxnv; ++j) {
-                /* every lane's step j; emits of this program point in lane order */
+            for (int j = R - 1; j >= 0; --j) {
                 for (int l = 0; l < 64; ++l) {
                     mm_lane* L = &lanes[l];
-                    if (!L->live || j >= L->nv) continue;
-                    const int nf = R - L->rs;
-                    int r, rp, first, restart;
-                    if (j < nf) {
-                        r = R - 1 - j; first = (r == L->rs); restart = (j == 0);
-                        rp = first ? r : r - 1;
-                    } else {
-                        r = j - nf; first = (r == L->mb - 1); restart = (j == nf);
-                        rp = first ? r : r + 1;
-                    }
+                    if (!L->live) continue;
+                    const int nf = L->nv, eq = L->rs, jf = eq ? 1 : 0;
+                    if (eq && j == 0) continue;                     /* no step */
+                    const int first = (j == jf && j < nf) || (j == nf);
+                    const int restart = (j == R - 1) || (j == nf - 1);
+                    const int r = j < nf ? L->mb + j : L->mb - 1 - (j - nf);
+                    int rp = r;
+                    if (j > 0) rp = (j - 1) < nf ? L->mb + (j - 1) : L->mb - 1 - (j - 1 - nf);
                     const double X = first ? L->x0 : L->px[rp];
                     const double Y = first ? L->y0 : L->py[rp];
-                    const double dt = w->refs[r] - (first ? L->tk : w->refs[rp]);
+                    const double dt = w->refs[r] - ((first || j == 0) ? L->tk : w->refs[rp]);
                     if (restart) { L->Lx = 0.0; L->Ly = 0.0; }
                     mm_direct(w, S.img + (size_t)(r * 2 + L->pol) * w->HW, coef[r],
                               1.0 - fabs(w->refs[r] - L->tk), L->px[r], L->py[r], &L->Lx, &L->Ly);
@@ -558,7 +559,8 @@ int cmm_backward(int W, int H, const float* K, int R, const float* refs, float e
             }
             for (int l = 0; l < 64; ++l) {
                 mm_lane* L = &lanes[l];
-                if (L->live && L->nv > 0) mm_emit(w, rec, fill, L->x0, L->y0, L->g0x, L->g0y);
+                if (L->live && R - (L->rs ? 1 : 0) > 0)
+                    mm_emit(w, rec, fill, L->x0, L->y0, L->g0x, L->g0y);
             }
         }
     }

@@ -107,18 +107,15 @@ __device__ __forceinline__ void ordered_add(double2* cells, bool act, int key, d
 // Counting sort of records into bins
 // ---------------------------------------------------------------------------
 
-// Visit the forward records of one event: fn(bin, r) for every reference.
-template <int RM, typename F>
-__device__ __forceinline__ void for_each_splat(const WinParams& P, const TileGeom& G,
-                                               const double (&px)[RM], const double (&py)[RM],
-                                               F&& fn)
+// Fills the block's table of reference times (and, with hdr, the adjoint
+// seed coefficients) for window P.
+__device__ __forceinline__ void load_ref_table(const WinParams& P, const StateHeader* hdr,
+                                               RefTable& rt)
 {
-#pragma unroll
-    for (int r = 0; r < RM; ++r) {
-        if (r < P.R) {
-            const Taps t = make_taps(P, px[r], py[r]);
-            fn(r * G.ntiles + tile_index(G, t), r);
-        }
+    if (threadIdx.x < kMaxRefs) {
+        const int r = threadIdx.x;
+        rt.t[r] = P.refs[r];
+        rt.coef[r] = (hdr && r < P.R) ? P.two_over_R / (hdr->nact[r] + P.eps) : 0.0;
     }
 }
 
@@ -135,8 +132,10 @@ __global__ __launch_bounds__(NT) void fwd_count_kernel(
     const TileGeom G = meta[w].G;
     const int64_t lb = blockIdx.x - meta[w].blk_off;
     const int64_t ev0 = meta[w].ev_off, n = meta[w].n;
+    __shared__ RefTable rt;
     for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) lh[i] = 0;
     if (threadIdx.x == 0) cnt_lds = 0;
+    load_ref_table(P, nullptr, rt);
     __syncthreads();
     const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
     const int64_t base = lb * NT * G.ept;
@@ -144,11 +143,16 @@ __global__ __launch_bounds__(NT) void fwd_count_kernel(
     for (int e = 0; e < G.ept; ++e) {
         const int64_t k = base + (int64_t)e * NT + threadIdx.x;
         if (k >= n) break;
-        double px[RM], py[RM];
-        int mb;
-        if (!warp_event<RM>(P, u, ex[ev0 + k], ey[ev0 + k], et[ev0 + k], px, py, mb)) continue;
+        double vx[RM], vy[RM];
+        int vr[RM];
+        Visits v;
+        if (!warp_visits<RM>(P, u, rt, ex[ev0 + k], ey[ev0 + k], et[ev0 + k], vx, vy, vr, v))
+            continue;
         ++cnt;
-        for_each_splat<RM>(P, G, px, py, [&](int bin, int) { atomicAdd(&lh[bin], 1u); });
+#pragma unroll
+        for (int j = 0; j < RM; ++j)
+            if (j < P.R)
+                atomicAdd(&lh[vr[j] * G.ntiles + tile_index(G, make_taps(P, vx[j], vy[j]))], 1u);
     }
     if (cnt) atomicAdd(&cnt_lds, cnt);
     __syncthreads();
@@ -285,27 +289,34 @@ __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
     const int64_t lb = blockIdx.x - meta[w].blk_off;
     const int64_t ev0 = meta[w].ev_off, n = meta[w].n;
     const uint32_t* row = offs + meta[w].hist_off + lb * G.nbins;
+    __shared__ RefTable rt;
     for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) lh[i] = row[i];
+    load_ref_table(P, nullptr, rt);
     __syncthreads();
     const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
     const int64_t base = lb * NT * G.ept;
     for (int e = 0; e < G.ept; ++e) {
         const int64_t k = base + (int64_t)e * NT + threadIdx.x;
         if (k >= n) break;
-        double px[RM], py[RM];
-        int mb;
+        double vx[RM], vy[RM];
+        int vr[RM];
+        Visits v;
         const float tk = et[ev0 + k];
-        if (!warp_event<RM>(P, u, ex[ev0 + k], ey[ev0 + k], tk, px, py, mb)) continue;
+        if (!warp_visits<RM>(P, u, rt, ex[ev0 + k], ey[ev0 + k], tk, vx, vy, vr, v)) continue;
         const float ts = ep[ev0 + k] > 0 ? tk : -tk;   // t >= 0 here; sign bit = negative polarity
-        for_each_splat<RM>(P, G, px, py, [&](int bin, int r) {
-            const uint32_t slot = DET ? stable_slot(lh, bin) : atomicAdd(&lh[bin], 1u);
-            SplatRec q;
-            q.X = sel(px, r);
-            q.Y = sel(py, r);
-            q.ts = ts;
-            q.k = (uint32_t)k;
-            rec[slot] = q;
-        });
+#pragma unroll
+        for (int j = 0; j < RM; ++j) {
+            if (j < P.R) {
+                const int bin = vr[j] * G.ntiles + tile_index(G, make_taps(P, vx[j], vy[j]));
+                const uint32_t slot = DET ? stable_slot(lh, bin) : atomicAdd(&lh[bin], 1u);
+                SplatRec q;
+                q.X = vx[j];
+                q.Y = vy[j];
+                q.ts = ts;
+                q.k = (uint32_t)k;
+                rec[slot] = q;
+            }
+        }
     }
 }
 
@@ -532,21 +543,19 @@ __global__ __launch_bounds__(256) void fwd_finalize_kernel(const WinMeta* __rest
 // event, so their contributions share one record.
 // ---------------------------------------------------------------------------
 
-// fn(X, Y) for every sampling position that is a reference position, then
-// fn(x0, y0) once for the event if it takes any step.
+// The flow-sampling positions of an event's warp steps: the previous visit's
+// position for every real step that does not start at the event, then the
+// event once if it takes any step (both sweeps' first steps share its record).
 template <int RM, typename F>
-__device__ __forceinline__ void for_each_sample(const WinParams& P, int rs, int mb,
-                                                const double (&px)[RM], const double (&py)[RM],
+__device__ __forceinline__ void for_each_sample(const WinParams& P, const Visits& v,
+                                                const double (&vx)[RM], const double (&vy)[RM],
                                                 double x0, double y0, F&& fn)
 {
-    for (int r = rs + 1; r < P.R; ++r) fn(sel(px, r - 1), sel(py, r - 1));
-    for (int r = mb - 2; r >= 0; --r) fn(sel(px, r + 1), sel(py, r + 1));
-    if (rs < P.R || mb > 0) fn(x0, y0);
-}
-
-__device__ __forceinline__ int first_forward_ref(const WinParams& P, int mb, double tk)
-{
-    return (mb < P.R && P.refs[mb] == tk) ? mb + 1 : mb;
+    const int jf = v.eq ? 1 : 0;
+#pragma unroll
+    for (int j = 1; j < RM; ++j)
+        if (j < P.R && j != jf && j != v.nf) fn(vx[j - 1], vy[j - 1]);
+    if (P.R - jf > 0) fn(x0, y0);
 }
 
 template <int RM, int NT>
@@ -561,19 +570,21 @@ __global__ __launch_bounds__(NT) void bwd_count_kernel(
     const TileGeom G = meta[w].G;
     const int64_t lb = blockIdx.x - meta[w].blk_off;
     const int64_t ev0 = meta[w].ev_off, n = meta[w].n;
+    __shared__ RefTable rt;
     for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x) lh[i] = 0;
+    load_ref_table(P, nullptr, rt);
     __syncthreads();
     const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
     const int64_t base = lb * NT * G.ept;
     for (int e = 0; e < G.ept; ++e) {
         const int64_t k = base + (int64_t)e * NT + threadIdx.x;
         if (k >= n) break;
-        double px[RM], py[RM];
-        int mb;
+        double vx[RM], vy[RM];
+        int vr[RM];
+        Visits v;
         const double x0 = ex[ev0 + k], y0 = ey[ev0 + k], tk = et[ev0 + k];
-        if (!warp_event<RM>(P, u, x0, y0, tk, px, py, mb)) continue;
-        const int rs = first_forward_ref(P, mb, tk);
-        for_each_sample<RM>(P, rs, mb, px, py, x0, y0, [&](double X, double Y) {
+        if (!warp_visits<RM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
+        for_each_sample<RM>(P, v, vx, vy, x0, y0, [&](double X, double Y) {
             atomicAdd(&lh[tile_index(G, make_taps(P, X, Y))], 1u);
         });
     }
@@ -599,11 +610,10 @@ __global__ __launch_bounds__(NT) void bwd_sweep_kernel(
     const uint32_t* row = offs + meta[w].hist_off + lb * G.ntiles;
     for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x) lh[i] = row[i];
     __syncthreads();
+    __shared__ RefTable rt;
+    load_ref_table(P, hdrs + w, rt);
+    __syncthreads();
     const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
-    const StateHeader* hdr = hdrs + w;
-    double coef[RM];
-#pragma unroll
-    for (int r = 0; r < RM; ++r) coef[r] = r < P.R ? P.two_over_R / (hdr->nact[r] + P.eps) : 0.0;
     const double2* img = img_base + meta[w].img_off;
     const int64_t base = lb * NT * G.ept;
 
@@ -621,36 +631,42 @@ __global__ __launch_bounds__(NT) void bwd_sweep_kernel(
     for (int e = 0; e < G.ept; ++e) {
         const int64_t k = base + (int64_t)e * NT + threadIdx.x;
         if (k >= n) break;
-        double px[RM], py[RM];
-        int mb;
+        double vx[RM], vy[RM];
+        int vr[RM];
+        Visits v;
         const double x0 = ex[ev0 + k], y0 = ey[ev0 + k], tk = et[ev0 + k];
-        if (!warp_event<RM>(P, u, x0, y0, tk, px, py, mb)) continue;
+        if (!warp_visits<RM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
         const int pol = ep[ev0 + k] > 0 ? 0 : 1;
         const double2* planes = img + (size_t)pol * P.HW;
-        const int rs = first_forward_ref(P, mb, tk);
-        const int nv = (P.R - rs) + mb;
         double g0x = 0.0, g0y = 0.0;     // contributions sampled at the event position
         double Lx = 0.0, Ly = 0.0;
-        for (int j = 0; j < nv; ++j) {
-            const ReverseStep s = reverse_step<RM>(P, j, rs, mb, x0, y0, tk, px, py);
-            if (s.restart) {
-                Lx = 0.0;
-                Ly = 0.0;
-            }
-            direct_term(P, planes + (size_t)s.r * 2 * P.HW, sel(coef, s.r),
-                        1.0 - fabs(P.refs[s.r] - tk), sel(px, s.r), sel(py, s.r), Lx, Ly);
-            if (s.first) {
-                g0x += s.dt * Lx;
-                g0y += s.dt * Ly;
-            } else {
-                emit(s.X, s.Y, s.dt * Lx, s.dt * Ly);
-                double jx, jy;
-                jacobian_t(P, u, s.X, s.Y, Lx, Ly, jx, jy);
-                Lx += s.dt * jx;
-                Ly += s.dt * jy;
+#pragma unroll
+        for (int j = RM - 1; j >= 0; --j) {
+            if (j < P.R) {
+                const VisitStep s = visit_step<RM>(P, rt, v, vr, j, tk);
+                if (s.step) {
+                    if (s.restart) {
+                        Lx = 0.0;
+                        Ly = 0.0;
+                    }
+                    const int r = vr[j];
+                    direct_term(P, planes + (size_t)r * 2 * P.HW, rt.coef[r],
+                                1.0 - fabs(rt.t[r] - tk), vx[j], vy[j], Lx, Ly);
+                    if (s.first) {
+                        g0x += s.dt * Lx;
+                        g0y += s.dt * Ly;
+                    } else {
+                        const double X = vx[j > 0 ? j - 1 : 0], Y = vy[j > 0 ? j - 1 : 0];
+                        emit(X, Y, s.dt * Lx, s.dt * Ly);
+                        double jx, jy;
+                        jacobian_t(P, u, X, Y, Lx, Ly, jx, jy);
+                        Lx += s.dt * jx;
+                        Ly += s.dt * jy;
+                    }
+                }
             }
         }
-        if (nv > 0) emit(x0, y0, g0x, g0y);
+        if (P.R - (v.eq ? 1 : 0) > 0) emit(x0, y0, g0x, g0y);
     }
 }
 

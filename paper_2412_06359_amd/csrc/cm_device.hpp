@@ -151,17 +151,37 @@ __device__ __forceinline__ double2 flow_at(const WinParams& P, const Motion& m, 
 }
 
 // The flow at the four taps of a position on the image (zero off the sensor).
+// The taps share two columns and two rows, so the terms that depend on one
+// coordinate only are formed once per column or row; every value is the same
+// FP64 operation as flow_parts on that tap.
 __device__ __forceinline__ void tap_flows(const WinParams& P, const FlowSrc& f, const Taps& t,
                                           double2 (&uq)[4])
 {
+    const Motion& m = f.m;
+    const double xb[2] = {(double)t.x0 - P.cx, (double)(t.x0 + 1) - P.cx};
+    const double yb[2] = {(double)t.y0 - P.cy, (double)(t.y0 + 1) - P.cy};
+    double k3x[2], k2y[2], cy[2], dx[2], Bx[2], By[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        k3x[i] = m.k3 * xb[i];
+        k2y[i] = m.k2 * yb[i];
+        cy[i] = m.k0 - m.k1 * yb[i];
+        dx[i] = m.k4 + m.k5 * xb[i];
+        Bx[i] = m.tvx - xb[i] * m.vz;
+        By[i] = m.tvy - yb[i] * m.vz;
+    }
+    const float* row0 = f.rho + (size_t)t.y0 * P.W + t.x0;
+    const float rq[4] = {row0[0], t.inx ? row0[1] : 0.f, t.iny ? row0[P.W] : 0.f,
+                         (t.inx && t.iny) ? row0[P.W + 1] : 0.f};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if (tap_in(t, q)) {
-            const int i = t.x0 + (q & 1), j = t.y0 + (q >> 1);
-            uq[q] = flow_at(P, f.m, i, j, (double)f.rho[j * P.W + i]);
-        } else {
-            uq[q] = make_double2(0.0, 0.0);
-        }
+        const int a = q & 1, b = q >> 1;
+        const double s = k3x[a] - k2y[b];
+        const double Ax = cy[b] + xb[a] * s;
+        const double Ay = dx[a] + yb[b] * s;
+        const double r = (double)rq[q];
+        uq[q] = tap_in(t, q) ? make_double2(Ax + r * Bx[a], Ay + r * By[b])
+                             : make_double2(0.0, 0.0);
     }
 }
 
@@ -182,24 +202,6 @@ __device__ __forceinline__ void sample_flow(const WinParams& P, const FlowSrc& f
     }
 }
 
-// Select / insert into small register arrays with a per-lane index (a chain of
-// conditional moves, so the arrays stay in VGPRs).
-template <int N>
-__device__ __forceinline__ double sel(const double (&a)[N], int i)
-{
-    double r = a[0];
-#pragma unroll
-    for (int q = 1; q < N; ++q) r = (i == q) ? a[q] : r;
-    return r;
-}
-
-template <int N>
-__device__ __forceinline__ void put(double (&a)[N], int i, double v)
-{
-#pragma unroll
-    for (int q = 0; q < N; ++q) a[q] = (i == q) ? v : a[q];
-}
-
 // Number of reference times strictly before t.
 __device__ __forceinline__ int refs_before(const WinParams& P, double t)
 {
@@ -209,93 +211,100 @@ __device__ __forceinline__ int refs_before(const WinParams& P, double t)
     return m;
 }
 
-// Sec. 3.1 / 3.3: push one event through the reference times, forward for
-// those after t_k (increasing), backward for those before (decreasing),
-// re-sampling the flow at each visited position.  Positions at reference r go
-// to (px[r], py[r]).  Returns false if the event is masked: non-finite input,
-// t outside [0,1], start off the image, or any visited position off the image.
-// Both sweeps run in one loop of R visits so that the lanes of a wave, whose
-// events split differently between the sweeps, step together.
+// Per-block table of the reference times and adjoint seed coefficients
+// (2/R)/(N_r + eps), read with a per-lane index.
+struct RefTable {
+    double t[kMaxRefs];
+    double coef[kMaxRefs];
+};
+
+// An event's visits of the reference times.  Visit j (0 <= j < R) is
+// reference vr[j]: first the forward sweep over the references at or after
+// t_k in increasing order (j < nf), then the backward sweep over those before
+// t_k in decreasing order.  A reference equal to t_k is the first forward
+// visit and keeps the event's position.
+struct Visits {
+    int nf;      // forward visits
+    int mb;      // references before t_k (backward visits)
+    bool eq;     // the first forward visit is a reference equal to t_k
+};
+
+// Sec. 3.1 / 3.3: push one event through the reference times, re-sampling the
+// flow at each visited position; (vx[j], vy[j]) is the position at visit j.
+// Returns false if the event is masked: non-finite input, t outside [0,1],
+// start off the image, or any visited position off the image.  The loop is
+// unrolled over visits so that every array index is static, and all lanes of a
+// wave step through the same visit numbers together.
 template <int RM>
-__device__ __forceinline__ bool warp_event(const WinParams& P, const FlowSrc& u,
-                                           double x0, double y0, double tk, double (&px)[RM],
-                                           double (&py)[RM], int& mbefore)
+__device__ __forceinline__ bool warp_visits(const WinParams& P, const FlowSrc& u,
+                                            const RefTable& rt, double x0, double y0, double tk,
+                                            double (&vx)[RM], double (&vy)[RM], int (&vr)[RM],
+                                            Visits& v)
 {
-    mbefore = 0;
+    v.nf = 0;
+    v.mb = 0;
+    v.eq = false;
     if (!(isfinite(x0) && isfinite(y0) && tk >= 0.0 && tk <= 1.0 && inside(P, x0, y0)))
         return false;
     const int mb = refs_before(P, tk);
-    mbefore = mb;
-    int rs = mb;
-    if (rs < P.R && P.refs[rs] == tk) {
-        put(px, rs, x0);
-        put(py, rs, y0);
-        ++rs;
-    }
-    const int nf = P.R - rs;            // forward visits rs .. R-1, then backward mb-1 .. 0
-    const int nv = nf + mb;
+    v.mb = mb;
+    v.nf = P.R - mb;
+    v.eq = v.nf > 0 && rt.t[mb] == tk;
     double X = x0, Y = y0, tau = tk;
-    for (int j = 0; j < nv; ++j) {
-        int r;
-        if (j < nf) {
-            r = rs + j;
-        } else {
-            r = mb - 1 - (j - nf);
-            if (j == nf) {
-                X = x0;
-                Y = y0;
-                tau = tk;
+#pragma unroll
+    for (int j = 0; j < RM; ++j) {
+        if (j < P.R) {
+            int r;
+            if (j < v.nf) {
+                r = mb + j;
+            } else {
+                r = mb - 1 - (j - v.nf);
+                if (j == v.nf) {
+                    X = x0;
+                    Y = y0;
+                    tau = tk;
+                }
             }
+            const double ref = rt.t[r];
+            const double dt = ref - tau;
+            if (dt != 0.0) {
+                double ux, uy;
+                sample_flow(P, u, X, Y, ux, uy);
+                X = X + dt * ux;
+                Y = Y + dt * uy;
+            }
+            tau = ref;
+            if (!inside(P, X, Y)) return false;
+            vx[j] = X;
+            vy[j] = Y;
+            vr[j] = r;
         }
-        double ux, uy;
-        sample_flow(P, u, X, Y, ux, uy);
-        const double ref = P.refs[r];
-        const double dt = ref - tau;
-        X = X + dt * ux;
-        Y = Y + dt * uy;
-        tau = ref;
-        if (!inside(P, X, Y)) return false;
-        put(px, r, X);
-        put(py, r, Y);
     }
     return true;
 }
 
-// One step of the reverse pass over an event's visits, in the order: the
-// forward sweep backwards (R-1 down to rs), then the backward sweep backwards
-// (0 up to mb-1).  For visit index j it gives the reference r, the position the
-// step started from (the event for the first step of a sweep), the step's dt,
-// and whether the adjoint restarts (a new sweep).
-struct ReverseStep {
-    int r;
-    bool first;      // the step started at the event
-    bool restart;    // a new sweep begins: the adjoint restarts from zero
-    double X, Y, dt;
+// The warp step that ends at visit j: whether it is a real step (not the
+// reference equal to t_k), whether it starts at the event (the first step of
+// its sweep), and its dt.  The reverse pass walks j = R-1 .. 0 (the backward
+// sweep backwards, then the forward sweep backwards), restarting the adjoint
+// at j = R-1 and at j = nf-1.
+struct VisitStep {
+    bool step, first, restart;
+    double dt;
 };
 
 template <int RM>
-__device__ __forceinline__ ReverseStep reverse_step(const WinParams& P, int j, int rs, int mb,
-                                                    double x0, double y0, double tk,
-                                                    const double (&px)[RM],
-                                                    const double (&py)[RM])
+__device__ __forceinline__ VisitStep visit_step(const WinParams& P, const RefTable& rt,
+                                                const Visits& v, const int (&vr)[RM], int j,
+                                                double tk)
 {
-    ReverseStep s;
-    const int nf = P.R - rs;
-    int rp;
-    if (j < nf) {
-        s.r = P.R - 1 - j;
-        s.first = (s.r == rs);
-        s.restart = (j == 0);
-        rp = s.first ? s.r : s.r - 1;
-    } else {
-        s.r = j - nf;
-        s.first = (s.r == mb - 1);
-        s.restart = (j == nf);
-        rp = s.first ? s.r : s.r + 1;
-    }
-    s.X = s.first ? x0 : sel(px, rp);
-    s.Y = s.first ? y0 : sel(py, rp);
-    s.dt = P.refs[s.r] - (s.first ? tk : P.refs[rp]);
+    VisitStep s;
+    const int jf = v.eq ? 1 : 0;             // first real forward step
+    s.step = !(v.eq && j == 0);
+    s.first = (j == jf && j < v.nf) || (j == v.nf);
+    s.restart = (j == P.R - 1) || (j == v.nf - 1);
+    const double tprev = (s.first || j == 0) ? tk : rt.t[vr[j > 0 ? j - 1 : 0]];
+    s.dt = rt.t[vr[j]] - tprev;
     return s;
 }
 

@@ -53,7 +53,9 @@ __global__ __launch_bounds__(256) void splat_kernel(WinParams P, const float* __
                                                     unsigned long long* __restrict__ n_valid)
 {
     __shared__ unsigned int cnt_lds;
+    __shared__ RefTable rt;
     if (threadIdx.x == 0) cnt_lds = 0;
+    if (threadIdx.x < kMaxRefs) rt.t[threadIdx.x] = P.refs[threadIdx.x];
     __syncthreads();
     const FlowSrc u = flow_src(P, rho, ego);
     unsigned int cnt = 0;
@@ -61,15 +63,17 @@ __global__ __launch_bounds__(256) void splat_kernel(WinParams P, const float* __
          k += (int64_t)gridDim.x * blockDim.x) {
         const double x0 = ex[k], y0 = ey[k], tk = et[k];
         const int pol = ep[k] > 0 ? 0 : 1;
-        double px[RM], py[RM];
-        int mb;
-        if (!warp_event<RM>(P, u, x0, y0, tk, px, py, mb)) continue;
+        double vx[RM], vy[RM];
+        int vr[RM];
+        Visits v;
+        if (!warp_visits<RM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
         ++cnt;
 #pragma unroll
-        for (int r = 0; r < RM; ++r) {
-            if (r < P.R) {
-                const Taps tp = make_taps(P, px[r], py[r]);
-                const double tb = 1.0 - fabs(P.refs[r] - tk);
+        for (int j = 0; j < RM; ++j) {
+            if (j < P.R) {
+                const int r = vr[j];
+                const Taps tp = make_taps(P, vx[j], vy[j]);
+                const double tb = 1.0 - fabs(rt.t[r] - tk);
                 double* plane = img + (size_t)(r * 2 + pol) * P.HW * 2;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -188,33 +192,44 @@ __global__ __launch_bounds__(256) void backward_kernel(
     const float* __restrict__ grad_loss, float* __restrict__ drho, double* __restrict__ part)
 {
     __shared__ double lds[16];
+    __shared__ RefTable rt;
+    if (threadIdx.x < kMaxRefs) {
+        rt.t[threadIdx.x] = P.refs[threadIdx.x];
+        rt.coef[threadIdx.x] =
+            (int)threadIdx.x < P.R ? P.two_over_R / (hdr->nact[threadIdx.x] + P.eps) : 0.0;
+    }
+    __syncthreads();
     const FlowSrc u = flow_src(P, rho, ego);
     const double gl = (double)grad_loss[0];
-    double coef[RM];
-#pragma unroll
-    for (int r = 0; r < RM; ++r) coef[r] = r < P.R ? P.two_over_R / (hdr->nact[r] + P.eps) : 0.0;
     double dth[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
          k += (int64_t)gridDim.x * blockDim.x) {
         const double x0 = ex[k], y0 = ey[k], tk = et[k];
         const int pol = ep[k] > 0 ? 0 : 1;
-        double px[RM], py[RM];
-        int mb;
-        if (!warp_event<RM>(P, u, x0, y0, tk, px, py, mb)) continue;
+        double vx[RM], vy[RM];
+        int vr[RM];
+        Visits v;
+        if (!warp_visits<RM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
         const double2* planes = reinterpret_cast<const double2*>(img) + (size_t)pol * P.HW;
-        const int rs = (mb < P.R && P.refs[mb] == tk) ? mb + 1 : mb;
-        const int nv = (P.R - rs) + mb;
         double Lx = 0.0, Ly = 0.0;
-        for (int j = 0; j < nv; ++j) {
-            const ReverseStep s = reverse_step<RM>(P, j, rs, mb, x0, y0, tk, px, py);
-            if (s.restart) {
-                Lx = 0.0;
-                Ly = 0.0;
+#pragma unroll
+        for (int j = RM - 1; j >= 0; --j) {
+            if (j < P.R) {
+                const VisitStep s = visit_step<RM>(P, rt, v, vr, j, tk);
+                if (s.step) {
+                    if (s.restart) {
+                        Lx = 0.0;
+                        Ly = 0.0;
+                    }
+                    const int r = vr[j];
+                    direct_term(P, planes + (size_t)r * 2 * P.HW, rt.coef[r],
+                                1.0 - fabs(rt.t[r] - tk), vx[j], vy[j], Lx, Ly);
+                    const double X = s.first ? x0 : vx[j > 0 ? j - 1 : 0];
+                    const double Y = s.first ? y0 : vy[j > 0 ? j - 1 : 0];
+                    adjoint_step(P, u, X, Y, s.dt, Lx, Ly, gl, drho, dth);
+                }
             }
-            direct_term(P, planes + (size_t)s.r * 2 * P.HW, sel(coef, s.r),
-                        1.0 - fabs(P.refs[s.r] - tk), sel(px, s.r), sel(py, s.r), Lx, Ly);
-            adjoint_step(P, u, s.X, s.Y, s.dt, Lx, Ly, gl, drho, dth);
         }
     }
 #pragma unroll
