@@ -16,7 +16,6 @@ synthetic windows (edge maps under rigid camera motion, see eventgen).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -38,12 +37,8 @@ WORKLOADS = {
 
 
 def kernel_source_sha() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2412_06359_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + f.read())
-    return h.hexdigest()[:16]
+    from paper_2412_06359_amd.build import source_sha
+    return source_sha()
 
 
 def algorithmic_bytes(phase: str, n: int, HW: int, R: int, tiled: bool) -> float:
@@ -68,17 +63,19 @@ def algorithmic_bytes(phase: str, n: int, HW: int, R: int, tiled: bool) -> float
     return table.get(phase, 0.0)
 
 
-def measured_traffic(workload: str, kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+def measured_traffic(workload: str, phase: str):
+    """HBM bytes per launch of a phase's kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), if it
     was taken on the current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.json")
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     if rec.get("source_sha") != kernel_source_sha():
         return None
-    return rec.get("bytes_per_launch")
+    ph = rec.get("phases", {}).get(phase)
+    return ph["bytes_per_launch"] if ph else None
 
 
 def cpu_baseline(wins, seconds: float, threads: int) -> dict:

@@ -29,6 +29,17 @@ HIPCC_FLAGS = [
 ]
 
 
+
+def source_sha() -> str:
+    """Short hash of the kernel sources (csrc/); counter summaries record it so
+    that figures taken on older kernels are not reported against newer ones."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
 def _hipcc(sources, out, verbose):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = out + ".tmp"
