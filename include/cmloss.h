@@ -65,8 +65,10 @@ typedef enum {
  * the last bits from run to run.  DETERMINISTIC: the warped positions are
  * sorted stably (event order) into 32x32-tile bins and each tile accumulates
  * them in a fixed order (records in event order, 64 at a time, per tap slot,
- * equal pixels in lane order), and every reduction uses a fixed tree: results
- * are bit-identical from run to run and between a window alone and in a batch.
+ * equal pixels in lane order), the backward walks the valid events in the
+ * order of their reference-0 bins and bins its records the same way, and
+ * every reduction uses a fixed tree: results are bit-identical from run to run
+ * and between a window alone and in a batch.
  * It always takes the tiled path (CM_ERR_UNSUPPORTED where that path does not
  * apply) and is slower. */
 enum { CM_MODE_ATOMIC = 0, CM_MODE_DETERMINISTIC = 1 };
@@ -96,8 +98,9 @@ const char* cm_status_string(cm_status s);
  * splatted images C and S per reference and polarity (32 * R * width * height
  * bytes, FP64), per-reference sums, reduction scratch and, where the tiled
  * path applies, its workspace (binned records, at most 32 * R bytes per event,
- * plus per-tile buffers).  The forward and backward of one window must be
- * called with the same n_events.  0 if `d` is invalid or n_events < 0. */
+ * a 16-byte source record per event, per-tile buffers).  The forward and
+ * backward of one window must be called with the same n_events.  0 if `d` is
+ * invalid or n_events < 0. */
 size_t cm_state_bytes(const cm_window_desc* d, int64_t n_events);
 
 /* Kernel path used by a handle.  AUTO picks per window: the direct path
@@ -105,7 +108,10 @@ size_t cm_state_bytes(const cm_window_desc* d, int64_t n_events);
  * tiled path (warped positions binned by 32x32 tile and accumulated in LDS,
  * each pixel written once) for large ones where the sensor allows it.  The
  * two compute the same quantities; TILED fails with CM_ERR_UNSUPPORTED where
- * it does not apply (more than 16384 reference-tile bins). */
+ * it does not apply (more than 16384 reference-tile bins).  The forward and
+ * the backward on one state must take the same path: the tiled backward walks
+ * per-event source records that only the tiled forward writes, and on a state
+ * the direct forward filled it returns NaN in grad_ego. */
 enum { CM_PATH_AUTO = 0, CM_PATH_DIRECT = 1, CM_PATH_TILED = 2 };
 cm_status cm_set_path(cm_handle h, int path);
 

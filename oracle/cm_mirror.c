@@ -24,9 +24,12 @@
  *  - Events are grouped in blocks of 64 * ept consecutive events, ept =
  *    clamp(n / 65536, 1, 16); records of a bin are ordered by (block,
  *    iteration e, program point, lane); in the forward that is event order.
- *    The backward's program points are the visits j = R-1 .. 0 (visits: the
- *    forward sweep's references at or after t_k upward, then the backward
- *    sweep's downward), then the event's own record.
+ *    The backward's blocks run over the valid events in source order (grouped
+ *    by the tile of their reference-0 position, event order within a tile),
+ *    interleaved: iteration e of block b takes positions (e nblocks + b) 64 ..;
+ *    its program points are the visits j = R-1 .. 0 (visits: the forward
+ *    sweep's references at or after t_k upward, then the backward sweep's
+ *    downward), then the event's own record.
  *  - Tile accumulation: records of a (reference, 32x32 tile) bin, 64 at a
  *    time; for tap slot q = 0..3, then lane 0..63, the record's (w, w tbar) is
  *    added to its cell.  Halos (right column rows 0..32, bottom row) are added
@@ -508,18 +511,38 @@ int cmm_backward(int W, int H, const float* K, int R, const float* refs, float e
     int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)nt);
     memcpy(fill, cnt, sizeof(int64_t) * (size_t)nt);
 
-    /* sweep: blocks of 64 * ept events; per iteration, 64 lanes in lockstep
-     * over the visits j = R-1 .. 0 (the backward sweep backwards, then the
-     * forward sweep backwards); the records of one visit number are emitted
-     * in lane order, then the event records in lane order. */
+    /* source order: the valid events grouped by the tile of their position
+     * at reference 0, in event order within a tile (the forward's reference-0
+     * record order) */
+    int64_t* tcnt = (int64_t*)calloc((size_t)nt + 1, sizeof(int64_t));
+    int64_t nvalid = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        if (!mm_warp(w, x[k], y[k], t[k], px, py, &mb)) continue;
+        tcnt[mm_tile_of(w, px[0], py[0]) + 1]++;
+        ++nvalid;
+    }
+    for (int b = 0; b < nt; ++b) tcnt[b + 1] += tcnt[b];
+    int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nvalid + 1));
+    for (int64_t k = 0; k < n; ++k) {
+        if (!mm_warp(w, x[k], y[k], t[k], px, py, &mb)) continue;
+        order[tcnt[mm_tile_of(w, px[0], py[0])]++] = k;
+    }
+    free(tcnt);
+
+    /* sweep: in iteration e, block b takes the source positions
+     * [(e * nblocks + b) * 64, +64), its 64 lanes in lockstep over the visits
+     * j = R-1 .. 0 (the backward sweep backwards,
+     * then the forward sweep backwards); the records of one visit number are
+     * emitted in lane order, then the event records in lane order. */
     mm_lane lanes[64];
     for (int blk = 0; blk < w->nblocks; ++blk) {
         for (int e = 0; e < w->ept; ++e) {
             for (int l = 0; l < 64; ++l) {
                 mm_lane* L = &lanes[l];
-                const int64_t k = (int64_t)blk * 64 * w->ept + (int64_t)e * 64 + l;
+                const int64_t i = ((int64_t)e * w->nblocks + blk) * 64 + l;
                 L->live = 0;
-                if (k >= n) continue;
+                if (i >= nvalid) continue;
+                const int64_t k = order[i];
                 if (!mm_warp(w, x[k], y[k], t[k], L->px, L->py, &L->mb)) continue;
                 L->live = 1;
                 L->x0 = x[k]; L->y0 = y[k]; L->tk = t[k];
@@ -565,6 +588,7 @@ int cmm_backward(int W, int H, const float* K, int R, const float* refs, float e
         }
     }
     free(fill);
+    free(order);
 
     /* tiles: dL/du in LDS order, then d rho and d theta shares */
     const double gl = (double)grad_loss;

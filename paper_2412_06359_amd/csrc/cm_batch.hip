@@ -51,6 +51,20 @@ __device__ __forceinline__ int window_of_block(const WinMeta* meta, int nw, int6
     return find_window(meta, nw, b, [](const WinMeta& m) { return m.blk_off; });
 }
 
+// Workgroups go to the XCDs round-robin (workgroup b runs on XCD b % 8), and
+// each XCD has its own L2.  The event-block kernels renumber their workgroups
+// so that every XCD takes one contiguous range of event blocks: the blocks of
+// a window then gather its inverse depth and splat images through one L2
+// instead of all eight fetching the same lines.  A bijection of [0, n).
+constexpr uint32_t kXcds = 8;
+
+__device__ __forceinline__ int64_t xcd_block()
+{
+    const uint32_t b = blockIdx.x, n = gridDim.x;
+    const uint32_t q = n / kXcds, r = n % kXcds, x = b % kXcds, i = b / kXcds;
+    return (int64_t)x * q + min(x, r) + i;
+}
+
 // ---------------------------------------------------------------------------
 // Deterministic mode helpers (one wavefront per block)
 // ---------------------------------------------------------------------------
@@ -127,10 +141,11 @@ __global__ __launch_bounds__(NT) void fwd_count_kernel(
 {
     extern __shared__ uint32_t lh[];
     __shared__ uint32_t cnt_lds;
-    const int w = window_of_block(meta, nw, blockIdx.x);
+    const int64_t blk = xcd_block();
+    const int w = window_of_block(meta, nw, blk);
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
-    const int64_t lb = blockIdx.x - meta[w].blk_off;
+    const int64_t lb = blk - meta[w].blk_off;
     const int64_t ev0 = meta[w].ev_off, n = meta[w].n;
     __shared__ RefTable rt;
     for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) lh[i] = 0;
@@ -280,19 +295,25 @@ __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
     const WinMeta* __restrict__ meta, int nw, const float* __restrict__ ex,
     const float* __restrict__ ey, const float* __restrict__ et, const int8_t* __restrict__ ep,
     const float* __restrict__ rho, const float* __restrict__ ego,
-    const uint32_t* __restrict__ offs, SplatRec* __restrict__ rec)
+    const uint32_t* __restrict__ offs, const uint32_t* __restrict__ start,
+    SplatRec* __restrict__ rec, SrcRec* __restrict__ src)
 {
     extern __shared__ uint32_t lh[];
-    const int w = window_of_block(meta, nw, blockIdx.x);
+    const int64_t blk = xcd_block();
+    const int w = window_of_block(meta, nw, blk);
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
-    const int64_t lb = blockIdx.x - meta[w].blk_off;
+    const int64_t lb = blk - meta[w].blk_off;
     const int64_t ev0 = meta[w].ev_off, n = meta[w].n;
     const uint32_t* row = offs + meta[w].hist_off + lb * G.nbins;
     __shared__ RefTable rt;
     for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) lh[i] = row[i];
     load_ref_table(P, nullptr, rt);
     __syncthreads();
+    // the window's reference-0 records come first among its records: their
+    // slots minus this offset number its valid events
+    const uint32_t r0 = start[meta[w].bin_off];
+    SrcRec* wsrc = src + ev0;
     const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
     const int64_t base = lb * NT * G.ept;
     for (int e = 0; e < G.ept; ++e) {
@@ -301,9 +322,9 @@ __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
         double vx[RM], vy[RM];
         int vr[RM];
         Visits v;
-        const float tk = et[ev0 + k];
-        if (!warp_visits<RM>(P, u, rt, ex[ev0 + k], ey[ev0 + k], tk, vx, vy, vr, v)) continue;
-        const float ts = ep[ev0 + k] > 0 ? tk : -tk;   // t >= 0 here; sign bit = negative polarity
+        const float xk = ex[ev0 + k], yk = ey[ev0 + k], tk = et[ev0 + k];
+        if (!warp_visits<RM>(P, u, rt, xk, yk, tk, vx, vy, vr, v)) continue;
+        const float ts = ep[ev0 + k] > 0 ? fabsf(tk) : -fabsf(tk);   // sign bit = polarity
 #pragma unroll
         for (int j = 0; j < RM; ++j) {
             if (j < P.R) {
@@ -315,6 +336,14 @@ __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
                 q.ts = ts;
                 q.k = (uint32_t)k;
                 rec[slot] = q;
+                if (vr[j] == 0) {
+                    SrcRec o;
+                    o.x0 = xk;
+                    o.y0 = yk;
+                    o.ts = ts;
+                    o.k = (uint32_t)k;
+                    wsrc[slot - r0] = o;
+                }
             }
         }
     }
@@ -532,6 +561,7 @@ __global__ __launch_bounds__(256) void fwd_finalize_kernel(const WinMeta* __rest
     if (threadIdx.x == 0) {
         L = L / (double)P.R;
         hdr->loss = L;
+        hdr->flags = kHdrSourceRecords;
         loss[w] = (float)L;
     }
 }
@@ -558,31 +588,40 @@ __device__ __forceinline__ void for_each_sample(const WinParams& P, const Visits
     if (P.R - jf > 0) fn(x0, y0);
 }
 
+// The backward's event blocks run over the source records (valid events in
+// reference-0 tile order) instead of the raw events, with the same block
+// geometry, interleaved: in iteration e, block b of a window takes source
+// positions [(e * nblocks + b) * NT, +NT).  The blocks in flight then work on
+// one compact stretch of the source order, that is on neighbouring tiles, and
+// their image and inverse-depth gathers share the L2.
 template <int RM, int NT>
 __global__ __launch_bounds__(NT) void bwd_count_kernel(
-    const WinMeta* __restrict__ meta, int nw, const float* __restrict__ ex,
-    const float* __restrict__ ey, const float* __restrict__ et, const float* __restrict__ rho,
-    const float* __restrict__ ego, uint32_t* __restrict__ hist)
+    const WinMeta* __restrict__ meta, int nw, const SrcRec* __restrict__ src,
+    const float* __restrict__ rho, const float* __restrict__ ego,
+    const StateHeader* __restrict__ hdrs, uint32_t* __restrict__ hist)
 {
     extern __shared__ uint32_t lh[];
-    const int w = window_of_block(meta, nw, blockIdx.x);
+    const int64_t blk = xcd_block();
+    const int w = window_of_block(meta, nw, blk);
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
-    const int64_t lb = blockIdx.x - meta[w].blk_off;
-    const int64_t ev0 = meta[w].ev_off, n = meta[w].n;
+    const int64_t lb = blk - meta[w].blk_off;
+    const int64_t nv =
+        (hdrs[w].flags & kHdrSourceRecords) ? (int64_t)hdrs[w].n_valid : 0;
+    const SrcRec* wsrc = src + meta[w].ev_off;
     __shared__ RefTable rt;
     for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x) lh[i] = 0;
     load_ref_table(P, nullptr, rt);
     __syncthreads();
     const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
-    const int64_t base = lb * NT * G.ept;
     for (int e = 0; e < G.ept; ++e) {
-        const int64_t k = base + (int64_t)e * NT + threadIdx.x;
-        if (k >= n) break;
+        const int64_t i = ((int64_t)e * G.nblocks + lb) * NT + threadIdx.x;
+        if (i >= nv) break;
         double vx[RM], vy[RM];
         int vr[RM];
         Visits v;
-        const double x0 = ex[ev0 + k], y0 = ey[ev0 + k], tk = et[ev0 + k];
+        const SrcRec q = load_nt(wsrc + i);
+        const double x0 = q.x0, y0 = q.y0, tk = fabsf(q.ts);
         if (!warp_visits<RM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
         for_each_sample<RM>(P, v, vx, vy, x0, y0, [&](double X, double Y) {
             atomicAdd(&lh[tile_index(G, make_taps(P, X, Y))], 1u);
@@ -595,18 +634,20 @@ __global__ __launch_bounds__(NT) void bwd_count_kernel(
 
 template <int RM, int NT, bool DET>
 __global__ __launch_bounds__(NT) void bwd_sweep_kernel(
-    const WinMeta* __restrict__ meta, int nw, const float* __restrict__ ex,
-    const float* __restrict__ ey, const float* __restrict__ et, const int8_t* __restrict__ ep,
+    const WinMeta* __restrict__ meta, int nw, const SrcRec* __restrict__ src,
     const float* __restrict__ rho, const float* __restrict__ ego,
     const double2* __restrict__ img_base, const StateHeader* __restrict__ hdrs,
     const uint32_t* __restrict__ offs, GradRec* __restrict__ rec)
 {
     extern __shared__ uint32_t lh[];
-    const int w = window_of_block(meta, nw, blockIdx.x);
+    const int64_t blk = xcd_block();
+    const int w = window_of_block(meta, nw, blk);
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
-    const int64_t lb = blockIdx.x - meta[w].blk_off;
-    const int64_t ev0 = meta[w].ev_off, n = meta[w].n;
+    const int64_t lb = blk - meta[w].blk_off;
+    const int64_t nv =
+        (hdrs[w].flags & kHdrSourceRecords) ? (int64_t)hdrs[w].n_valid : 0;
+    const SrcRec* wsrc = src + meta[w].ev_off;
     const uint32_t* row = offs + meta[w].hist_off + lb * G.ntiles;
     for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x) lh[i] = row[i];
     __syncthreads();
@@ -615,7 +656,6 @@ __global__ __launch_bounds__(NT) void bwd_sweep_kernel(
     __syncthreads();
     const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
     const double2* img = img_base + meta[w].img_off;
-    const int64_t base = lb * NT * G.ept;
 
     auto emit = [&](double X, double Y, double gx, double gy) {
         const int bin = tile_index(G, make_taps(P, X, Y));
@@ -625,18 +665,19 @@ __global__ __launch_bounds__(NT) void bwd_sweep_kernel(
         q.Y = Y;
         q.gx = gx;
         q.gy = gy;
-        rec[slot] = q;
+        store_nt(rec + slot, q);
     };
 
     for (int e = 0; e < G.ept; ++e) {
-        const int64_t k = base + (int64_t)e * NT + threadIdx.x;
-        if (k >= n) break;
+        const int64_t i = ((int64_t)e * G.nblocks + lb) * NT + threadIdx.x;
+        if (i >= nv) break;
         double vx[RM], vy[RM];
         int vr[RM];
         Visits v;
-        const double x0 = ex[ev0 + k], y0 = ey[ev0 + k], tk = et[ev0 + k];
+        const SrcRec q = load_nt(wsrc + i);
+        const double x0 = q.x0, y0 = q.y0, tk = fabsf(q.ts);
         if (!warp_visits<RM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
-        const int pol = ep[ev0 + k] > 0 ? 0 : 1;
+        const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
         const double2* planes = img + (size_t)pol * P.HW;
         double g0x = 0.0, g0y = 0.0;     // contributions sampled at the event position
         double Lx = 0.0, Ly = 0.0;
@@ -815,6 +856,7 @@ __global__ __launch_bounds__(64) void bwd_merge_kernel(
 // One block per window: fixed-order sum of its tiles' d theta partials.
 __global__ __launch_bounds__(256) void bwd_finalize_kernel(const WinMeta* __restrict__ meta,
                                                            const double* __restrict__ part,
+                                                           const StateHeader* __restrict__ hdrs,
                                                            const float* __restrict__ grad_loss,
                                                            float* __restrict__ grad_ego)
 {
@@ -822,7 +864,7 @@ __global__ __launch_bounds__(256) void bwd_finalize_kernel(const WinMeta* __rest
     const int w = blockIdx.x;
     const int ntiles = meta[w].G.ntiles;
     const double* pw = part + meta[w].tile_off * 12;
-    const double gl = (double)grad_loss[w];
+    const double gl = (hdrs[w].flags & kHdrSourceRecords) ? (double)grad_loss[w] : (double)NAN;
     for (int c = 0; c < 6; ++c) {
         double s = 0.0;
         for (int j = threadIdx.x; j < 2 * ntiles; j += blockDim.x) s += pw[(size_t)j * 6 + c];
@@ -839,6 +881,7 @@ __global__ __launch_bounds__(256) void clear_headers_kernel(StateHeader* __restr
         StateHeader z;
         z.loss = 0.0;
         z.n_valid = 0;
+        z.flags = 0;
         for (int r = 0; r < kMaxRefs; ++r) {
             z.num[r] = 0.0;
             z.nact[r] = 0.0;
@@ -946,6 +989,7 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     B.ws.halo = take((size_t)std::max<int64_t>(bin * NHALO * 2, tile * (NHALO + NBORDER)) *
                      sizeof(double2));
     B.ws.records = take((size_t)recs * std::max(sizeof(SplatRec), sizeof(GradRec)));
+    B.ws.src = take((size_t)ev * sizeof(SrcRec));
     B.ws.total = off;
     return B;
 }
@@ -964,6 +1008,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     double* part = reinterpret_cast<double*>(ws + B.ws.part);
     double2* halo = reinterpret_cast<double2*>(ws + B.ws.halo);
     SplatRec* rec = reinterpret_cast<SplatRec*>(ws + B.ws.records);
+    SrcRec* src = reinterpret_cast<SrcRec*>(ws + B.ws.src);
     const size_t lds = (size_t)B.max_lds_bins * sizeof(uint32_t);
     {
         PhaseScope ph(prof, kPhZero, s);
@@ -987,8 +1032,8 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     {
         PhaseScope ph(prof, kPhScatter, s);
         constexpr int NT = DET ? 64 : kBinThreads;
-        fwd_scatter_kernel<RM, NT, DET><<<B.nblocks, NT, lds, s>>>(meta, nw, ev.x, ev.y, ev.t,
-                                                                   ev.p, rho, ego, hist, rec);
+        fwd_scatter_kernel<RM, NT, DET><<<B.nblocks, NT, lds, s>>>(
+            meta, nw, ev.x, ev.y, ev.t, ev.p, rho, ego, hist, start, rec, src);
     }
     {
         PhaseScope ph(prof, kPhSplat, s);
@@ -1034,12 +1079,12 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
     double2* halo = reinterpret_cast<double2*>(ws + B.ws.halo);
     double2* border = halo + B.ntiles * NHALO;
     GradRec* rec = reinterpret_cast<GradRec*>(ws + B.ws.records);
+    const SrcRec* src = reinterpret_cast<const SrcRec*>(ws + B.ws.src);
     const size_t lds = (size_t)B.max_lds_bins * sizeof(uint32_t);
     {
         PhaseScope ph(prof, kPhGradCount, s);
         constexpr int NT = DET ? 64 : kBinThreads;
-        bwd_count_kernel<RM, NT><<<B.nblocks, NT, lds, s>>>(meta, nw, ev.x, ev.y, ev.t, rho, ego,
-                                                            hist);
+        bwd_count_kernel<RM, NT><<<B.nblocks, NT, lds, s>>>(meta, nw, src, rho, ego, hdrs, hist);
     }
     {
         PhaseScope ph(prof, kPhGradScan, s);
@@ -1053,8 +1098,8 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
     {
         PhaseScope ph(prof, kPhAdjoint, s);
         constexpr int NT = DET ? 64 : kBinThreads;
-        bwd_sweep_kernel<RM, NT, DET><<<B.nblocks, NT, lds, s>>>(meta, nw, ev.x, ev.y, ev.t, ev.p,
-                                                                 rho, ego, img, hdrs, hist, rec);
+        bwd_sweep_kernel<RM, NT, DET><<<B.nblocks, NT, lds, s>>>(meta, nw, src, rho, ego, img,
+                                                                 hdrs, hist, rec);
     }
     {
         PhaseScope ph(prof, kPhGradTile, s);
@@ -1065,7 +1110,7 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
     }
     {
         PhaseScope ph(prof, kPhGradFinalize, s);
-        bwd_finalize_kernel<<<nw, 256, 0, s>>>(meta, part, grad_loss, grad_ego);
+        bwd_finalize_kernel<<<nw, 256, 0, s>>>(meta, part, hdrs, grad_loss, grad_ego);
     }
     return hipGetLastError();
 }

@@ -250,7 +250,11 @@ __device__ __forceinline__ bool warp_visits(const WinParams& P, const FlowSrc& u
     v.mb = mb;
     v.nf = P.R - mb;
     v.eq = v.nf > 0 && rt.t[mb] == tk;
+    // Both sweeps start at the event: its flow is sampled once and reused.
+    double u0x, u0y;
+    sample_flow(P, u, x0, y0, u0x, u0y);
     double X = x0, Y = y0, tau = tk;
+    bool at_event = true;
 #pragma unroll
     for (int j = 0; j < RM; ++j) {
         if (j < P.R) {
@@ -263,15 +267,17 @@ __device__ __forceinline__ bool warp_visits(const WinParams& P, const FlowSrc& u
                     X = x0;
                     Y = y0;
                     tau = tk;
+                    at_event = true;
                 }
             }
             const double ref = rt.t[r];
             const double dt = ref - tau;
             if (dt != 0.0) {
-                double ux, uy;
-                sample_flow(P, u, X, Y, ux, uy);
+                double ux = u0x, uy = u0y;
+                if (!at_event) sample_flow(P, u, X, Y, ux, uy);
                 X = X + dt * ux;
                 Y = Y + dt * uy;
+                at_event = false;
             }
             tau = ref;
             if (!inside(P, X, Y)) return false;
@@ -415,11 +421,85 @@ struct SplatRec {
     uint32_t k;             // event index
 };
 
+// A valid event as the backward reads it: coordinates, time with the
+// polarity in the sign bit (set: negative), index.  The forward writes one per
+// valid event in the order of its reference-0 splat records (grouped by the
+// tile its reference-0 position falls in), so that neighbouring lanes of the
+// backward warp, sample and gather near each other.
+struct SrcRec {
+    float x0, y0, ts;
+    uint32_t k;
+};
+
 // Backward record: a warp step's sampling position and dt * adjoint.
 struct GradRec {
     double X, Y;
     double gx, gy;
 };
+
+// Record I/O with the non-temporal hint: each record is written once and read
+// once, so the stream of records should not push the inverse-depth and image
+// lines that the gathers reuse out of the caches.
+typedef double nt_d2 __attribute__((ext_vector_type(2), aligned(8)));
+typedef uint32_t nt_u2 __attribute__((ext_vector_type(2), aligned(8)));
+typedef uint32_t nt_u4 __attribute__((ext_vector_type(4), aligned(16)));
+
+__device__ __forceinline__ void store_nt(SplatRec* p, const SplatRec& q)
+{
+    const nt_d2 a = {q.X, q.Y};
+    const nt_u2 b = {__float_as_uint(q.ts), q.k};
+    __builtin_nontemporal_store(a, reinterpret_cast<nt_d2*>(p));
+    __builtin_nontemporal_store(b, reinterpret_cast<nt_u2*>(reinterpret_cast<char*>(p) + 16));
+}
+
+__device__ __forceinline__ SplatRec load_nt(const SplatRec* p)
+{
+    const nt_d2 a = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+    const nt_u2 b = __builtin_nontemporal_load(
+        reinterpret_cast<const nt_u2*>(reinterpret_cast<const char*>(p) + 16));
+    SplatRec q;
+    q.X = a.x;
+    q.Y = a.y;
+    q.ts = __uint_as_float(b.x);
+    q.k = b.y;
+    return q;
+}
+
+__device__ __forceinline__ void store_nt(GradRec* p, const GradRec& q)
+{
+    const nt_d2 a = {q.X, q.Y}, b = {q.gx, q.gy};
+    __builtin_nontemporal_store(a, reinterpret_cast<nt_d2*>(p));
+    __builtin_nontemporal_store(b, reinterpret_cast<nt_d2*>(p) + 1);
+}
+
+__device__ __forceinline__ GradRec load_nt(const GradRec* p)
+{
+    const nt_d2 a = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+    const nt_d2 b = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p) + 1);
+    GradRec q;
+    q.X = a.x;
+    q.Y = a.y;
+    q.gx = b.x;
+    q.gy = b.y;
+    return q;
+}
+
+__device__ __forceinline__ void store_nt(SrcRec* p, const SrcRec& q)
+{
+    const nt_u4 a = {__float_as_uint(q.x0), __float_as_uint(q.y0), __float_as_uint(q.ts), q.k};
+    __builtin_nontemporal_store(a, reinterpret_cast<nt_u4*>(p));
+}
+
+__device__ __forceinline__ SrcRec load_nt(const SrcRec* p)
+{
+    const nt_u4 a = __builtin_nontemporal_load(reinterpret_cast<const nt_u4*>(p));
+    SrcRec q;
+    q.x0 = __uint_as_float(a.x);
+    q.y0 = __uint_as_float(a.y);
+    q.ts = __uint_as_float(a.z);
+    q.k = a.w;
+    return q;
+}
 
 __device__ __forceinline__ int tile_index(const TileGeom& G, const Taps& t)
 {

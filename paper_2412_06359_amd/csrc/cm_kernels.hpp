@@ -14,9 +14,15 @@ namespace cm {
 struct StateHeader {
     double loss;
     unsigned long long n_valid;
+    unsigned long long flags;   // kHdrSourceRecords: written by the tiled forward
     double num[kMaxRefs];
     double nact[kMaxRefs];
 };
+
+// The tiled forward leaves per-event source records for the tiled backward;
+// a state filled by the direct forward has none, and a tiled backward on it
+// returns NaN gradients instead of reading them.
+constexpr unsigned long long kHdrSourceRecords = 1ull;
 
 constexpr int kReduceBlocks = 256;     // reduce blocks per reference (max)
 constexpr int kBackwardBlocks = 4096;  // backward grid (max), grid-stride beyond
@@ -122,7 +128,7 @@ constexpr int kScanChunk = 16;  // histogram rows per chunk of the column scan
 
 // Byte offsets of the tiled path's buffers inside the workspace region.
 struct TileWorkspace {
-    size_t hist, csum, totals, start, part, halo, records, total;
+    size_t hist, csum, totals, start, part, halo, records, src, total;
 };
 
 // Host-side plan of a tiled batch: per-window metadata, totals, workspace layout.
