@@ -48,10 +48,11 @@ def _load():
     lib.cmo_flow_field.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P]
     lib.cmo_flow_field.restype = ctypes.c_int
     lib.cmo_forward.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double,
-                                ctypes.c_int64, P, P, P, P, P, P, P, P, P, P]
+                                ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P, P, P, P, P]
     lib.cmo_forward.restype = ctypes.c_int
     lib.cmo_backward.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double,
-                                 ctypes.c_int64, P, P, P, P, P, P, ctypes.c_double, P, P, P]
+                                 ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P, ctypes.c_double,
+                                 P, P, P]
     lib.cmo_backward.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -69,7 +70,9 @@ def _f64(a):
 def _window_args(win, rho=None, theta=None):
     """The window's arrays as the oracle takes them.  FP32 fields (the form the
     GPU library reads) widen exactly; FP64 arrays pass through unchanged so
-    that finite-difference tests can perturb below FP32 resolution."""
+    that finite-difference tests can perturb below FP32 resolution.  rho is
+    [H, W] with theta [6] (one flow), or [F, H, W] with theta [F, 6] (one flow
+    per segment between consecutive knots {0, 1} U refs)."""
     rho = _f64(win.rho if rho is None else rho)
     theta = _f64(win.theta if theta is None else theta)
     K = _f64([_as_f(win.fx), _as_f(win.fy), _as_f(win.cx), _as_f(win.cy)])
@@ -101,6 +104,11 @@ def flow_field(width, height, K, rho, theta) -> np.ndarray:
     return u
 
 
+def n_flows(rho) -> int:
+    """Number of flow sets an inverse-depth array holds ([H, W] -> 1)."""
+    return 1 if np.ndim(rho) == 2 else int(np.shape(rho)[0])
+
+
 def forward(win, rho=None, theta=None, images=False, valid=False, positions=False) -> dict:
     """Loss and per-reference terms of Eq. 1 for one window.
 
@@ -108,13 +116,14 @@ def forward(win, rho=None, theta=None, images=False, valid=False, positions=Fals
     images [R, 2 pol, 2 (C,S), H, W], valid [n] bool, positions [n, R, 2]."""
     lib = _load()
     K, refs, x, y, t, p, rho, theta = _window_args(win, rho, theta)
+    F = n_flows(rho)
     R = refs.shape[0]
     n = x.shape[0]
     out = np.zeros(1 + 2 * R, dtype=np.float64)
     img = np.zeros((R, 2, 2, win.height, win.width), dtype=np.float64) if images else None
     val = np.zeros(n, dtype=np.uint8) if valid else None
     pos = np.zeros((n, R, 2), dtype=np.float64) if positions else None
-    st = lib.cmo_forward(win.width, win.height, _ptr(K), R, _ptr(refs), _eps(win),
+    st = lib.cmo_forward(win.width, win.height, _ptr(K), R, _ptr(refs), _eps(win), F,
                          n, _ptr(x), _ptr(y), _ptr(t), _ptr(p), _ptr(rho), _ptr(theta), _ptr(out),
                          _ptr(img), _ptr(val), _ptr(pos))
     if st != 0:
@@ -134,15 +143,19 @@ def loss(win, rho=None, theta=None) -> float:
 
 
 def backward(win, rho=None, theta=None, grad_loss: float = 1.0, flow_grad=False) -> dict:
-    """Gradient of the loss: dict(drho [H, W], dtheta [6]) (+ dflow [H, W, 2])."""
+    """Gradient of the loss: dict(drho, dtheta) (+ dflow) shaped like the flow
+    sets: [H, W], [6], [H, W, 2] for one flow; [F, H, W], [F, 6], [F, H, W, 2]
+    for F."""
     lib = _load()
     K, refs, x, y, t, p, rho, theta = _window_args(win, rho, theta)
     R = refs.shape[0]
     n = x.shape[0]
-    drho = np.zeros((win.height, win.width), dtype=np.float64)
-    dth = np.zeros(6, dtype=np.float64)
-    dflow = np.zeros((win.height, win.width, 2), dtype=np.float64) if flow_grad else None
-    st = lib.cmo_backward(win.width, win.height, _ptr(K), R, _ptr(refs), _eps(win),
+    F = n_flows(rho)
+    lead = () if rho.ndim == 2 else (F,)
+    drho = np.zeros(lead + (win.height, win.width), dtype=np.float64)
+    dth = np.zeros(lead + (6,), dtype=np.float64)
+    dflow = np.zeros(lead + (win.height, win.width, 2), dtype=np.float64) if flow_grad else None
+    st = lib.cmo_backward(win.width, win.height, _ptr(K), R, _ptr(refs), _eps(win), F,
                           n, _ptr(x), _ptr(y), _ptr(t), _ptr(p), _ptr(rho), _ptr(theta),
                           ctypes.c_double(grad_loss), _ptr(drho), _ptr(dth), _ptr(dflow))
     if st != 0:

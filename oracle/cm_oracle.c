@@ -25,6 +25,13 @@
  *   5. The gradient: dL/du at every pixel (the quantity the paper's backward
  *      kernel produces), then chained through Eq. 2 to rho and theta.
  *
+ * Flow sets (Sec. 3.1: flows of consecutive slices are concatenated,
+ * Delta x_k = sum_i (Delta t_i u_i)(e_k)): the window holds either one flow,
+ * or one flow per segment between consecutive knots {0, 1} U refs, each from
+ * its own inverse depth and ego-motion.  A warp step moves between two
+ * consecutive visited times, which always lie in one segment, and samples
+ * that segment's flow.
+ *
  * Readings of points the paper leaves open (each also listed in the design
  * notes): timestamp contribution tbar = 1 - |t_ref - t_k|; eps in both the
  * per-pixel ratio and the active-pixel normaliser; pixel centres at integer
@@ -53,10 +60,14 @@ typedef struct {
     int R;
     double refs[CMO_MAX_REFS];
     double eps;
+    int F;                          /* flow sets: 1, or one per segment */
+    int nk;                         /* knots: sorted unique {0, 1} U refs */
+    double knots[CMO_MAX_REFS + 2];
+    int kidx[CMO_MAX_REFS];         /* knot index of each reference */
 } cmo_cam;
 
 static int cmo_setup(cmo_cam* c, int W, int H, const double* K, int R, const double* refs,
-                     double eps)
+                     double eps, int F)
 {
     if (W <= 0 || H <= 0 || !K || !refs || R < 1 || R > CMO_MAX_REFS) return CMO_BAD_ARG;
     c->W = W; c->H = H;
@@ -69,8 +80,21 @@ static int cmo_setup(cmo_cam* c, int W, int H, const double* K, int R, const dou
         if (r > 0 && !(c->refs[r] > c->refs[r - 1])) return CMO_BAD_ARG;
     }
     c->eps = eps;
+    /* knots: 0, the references, 1 (each once) */
+    c->nk = 0;
+    if (c->refs[0] > 0.0) c->knots[c->nk++] = 0.0;
+    for (int r = 0; r < R; ++r) { c->kidx[r] = c->nk; c->knots[c->nk++] = c->refs[r]; }
+    if (c->refs[R - 1] < 1.0) c->knots[c->nk++] = 1.0;
+    if (F != 1 && F != c->nk - 1) return CMO_BAD_ARG;
+    c->F = F;
     return CMO_OK;
 }
+
+/* Flow set of the step that ends at reference r: a forward step (from a
+ * smaller time) crosses the segment that ends at r's knot, a backward step
+ * the segment that starts there. */
+static int cmo_set_fwd(const cmo_cam* c, int r) { return c->F == 1 ? 0 : c->kidx[r] - 1; }
+static int cmo_set_bwd(const cmo_cam* c, int r) { return c->F == 1 ? 0 : c->kidx[r]; }
 
 /* ---------------------------------------------------------------------------
  * Step 1: flow from inverse depth and ego-motion (Eq. 2, first order).
@@ -164,9 +188,9 @@ static void cmo_sample(const cmo_cam* c, const double* u, double X, double Y, do
  * Sec. 3.3 pushing each event forward or backward through time).
  *
  * From (x_k, t_k) the event is moved through the reference times after t_k in
- * increasing order, P <- P + (r - tau) BS(u)(P), tau <- r; then, from the
- * original position again, through the reference times before t_k in
- * decreasing order.  A reference equal to t_k gets the unwarped position.
+ * increasing order, P <- P + (r - tau) BS(u_s)(P), tau <- r, with u_s the flow
+ * of the segment the step crosses; then, from the original position again,
+ * through the reference times before t_k in decreasing order.  A reference equal to t_k gets the unwarped position.
  * The event is valid iff its inputs are finite, t_k lies in [0,1], it starts
  * on the image and every visited position lies on the image.  pos[2r..2r+1]
  * receives the position at reference r.  Returns validity.
@@ -174,6 +198,7 @@ static void cmo_sample(const cmo_cam* c, const double* u, double X, double Y, do
 static int cmo_warp_event(const cmo_cam* c, const double* u, double xk, double yk, double tk,
                           double* pos)
 {
+    const size_t HW2 = 2 * (size_t)c->H * c->W;
     const int R = c->R;
     for (int r = 0; r < 2 * R; ++r) pos[r] = NAN;
     if (!isfinite(xk) || !isfinite(yk) || !isfinite(tk)) return 0;
@@ -188,7 +213,7 @@ static int cmo_warp_event(const cmo_cam* c, const double* u, double xk, double y
     for (int r = m; r < R; ++r) {
         if (c->refs[r] == tk) { pos[2 * r] = xk; pos[2 * r + 1] = yk; continue; }
         double s[2];
-        cmo_sample(c, u, X, Y, s);
+        cmo_sample(c, u + HW2 * cmo_set_fwd(c, r), X, Y, s);
         const double dt = c->refs[r] - tau;
         X = X + dt * s[0];
         Y = Y + dt * s[1];
@@ -200,7 +225,7 @@ static int cmo_warp_event(const cmo_cam* c, const double* u, double xk, double y
     X = xk; Y = yk; tau = tk;
     for (int r = m - 1; r >= 0; --r) {
         double s[2];
-        cmo_sample(c, u, X, Y, s);
+        cmo_sample(c, u + HW2 * cmo_set_bwd(c, r), X, Y, s);
         const double dt = c->refs[r] - tau;
         X = X + dt * s[0];
         Y = Y + dt * s[1];
@@ -224,7 +249,7 @@ static size_t cmo_img_index(const cmo_cam* c, int r, int pol, int ch, int xi, in
 
 typedef struct {
     cmo_cam cam;
-    double* u;      /* [H*W*2] flow */
+    double* u;      /* [F][H*W*2] flow */
     double* img;    /* [R*2*2*H*W] */
     double* nact;   /* [R] */
     double* num;    /* [R] */
@@ -244,13 +269,14 @@ static int cmo_forward_impl(cmo_fwd* f, int64_t n, const double* x, const double
     const cmo_cam* c = &f->cam;
     const int R = c->R;
     const size_t HW = (size_t)c->H * c->W;
-    f->u = (double*)malloc(sizeof(double) * 2 * HW);
+    f->u = (double*)malloc(sizeof(double) * 2 * HW * (size_t)c->F);
     f->img = (double*)calloc((size_t)R * 4 * HW, sizeof(double));
     f->nact = (double*)calloc((size_t)R, sizeof(double));
     f->num = (double*)calloc((size_t)R, sizeof(double));
     if (!f->u || !f->img || !f->nact || !f->num) return CMO_NO_MEM;
 
-    cmo_fill_flow(c, rho, theta, f->u);
+    for (int fs = 0; fs < c->F; ++fs)
+        cmo_fill_flow(c, rho + HW * fs, theta + 6 * fs, f->u + 2 * HW * fs);
 
     double pos[2 * CMO_MAX_REFS];
     for (int64_t k = 0; k < n; ++k) {
@@ -302,7 +328,7 @@ int cmo_flow_field(int W, int H, const double* K, const double* rho, const doubl
 {
     cmo_cam c;
     const double one = 1.0;
-    int st = cmo_setup(&c, W, H, K, 1, &one, 1e-9);
+    int st = cmo_setup(&c, W, H, K, 1, &one, 1e-9, 1);
     if (st) return st;
     if (!rho || !theta || !u_out) return CMO_BAD_ARG;
     cmo_fill_flow(&c, rho, theta, u_out);
@@ -311,18 +337,20 @@ int cmo_flow_field(int W, int H, const double* K, const double* rho, const doubl
 
 /* ---------------------------------------------------------------------------
  * Public: forward.
+ *   rho [F][H*W], theta [F][6] with F flow sets (1, or one per segment).
  *   out[0] = loss, out[1..R] = num_r, out[R+1..2R] = N_r.
  *   img (optional): [R][2 pol][2 (C,S)][H][W] FP64.
  *   valid (optional): [n] 0/1.   pos (optional): [n][R][2], NaN if unvisited.
  * ------------------------------------------------------------------------- */
-int cmo_forward(int W, int H, const double* K, int R, const double* refs, double eps, int64_t n,
+int cmo_forward(int W, int H, const double* K, int R, const double* refs, double eps, int F,
+                int64_t n,
                 const double* x, const double* y, const double* t, const int8_t* p,
                 const double* rho, const double* theta, double* out, double* img,
                 uint8_t* valid, double* pos)
 {
     cmo_fwd f;
     memset(&f, 0, sizeof f);
-    int st = cmo_setup(&f.cam, W, H, K, R, refs, eps);
+    int st = cmo_setup(&f.cam, W, H, K, R, refs, eps, F);
     if (st) return st;
     if (n < 0 || !rho || !theta || !out || (n > 0 && (!x || !y || !t || !p)))
         return CMO_BAD_ARG;
@@ -375,12 +403,14 @@ static void cmo_direct(const cmo_cam* c, const double* img, const double* nact, 
 }
 
 /* Reverse pass over one sweep: path[0] is the event, path[1..len] the visited
- * reference positions with reference indices ridx[1..len] and times tau. */
+ * reference positions with reference indices ridx[1..len] and times tau; the
+ * step into path[j] used flow set fset[j] (u and dflow are [F][H*W*2]). */
 static void cmo_reverse_sweep(const cmo_cam* c, const double* u, const double* img,
                               const double* nact, int pol, double tk, int len,
                               const double* px, const double* py, const double* tau,
-                              const int* ridx, double* dflow)
+                              const int* ridx, const int* fset, double* dflow_all)
 {
+    const size_t HW2 = 2 * (size_t)c->H * c->W;
     double Lx = 0.0, Ly = 0.0;
     for (int j = len; j >= 1; --j) {
         double lam[2];
@@ -389,6 +419,8 @@ static void cmo_reverse_sweep(const cmo_cam* c, const double* u, const double* i
         Lx += lam[0];
         Ly += lam[1];
         const double dt = tau[j] - tau[j - 1];
+        const double* us = u + HW2 * fset[j];
+        double* dflow = dflow_all + HW2 * fset[j];
         cmo_taps tp;
         cmo_bilinear(c, px[j - 1], py[j - 1], &tp);
         double jx = 0.0, jy = 0.0;   /* J(P_{j-1})^T Lam */
@@ -397,7 +429,7 @@ static void cmo_reverse_sweep(const cmo_cam* c, const double* u, const double* i
             const size_t pix = (size_t)tp.yi[q] * c->W + tp.xi[q];
             dflow[2 * pix] += dt * tp.w[q] * Lx;
             dflow[2 * pix + 1] += dt * tp.w[q] * Ly;
-            const double lu = Lx * u[2 * pix] + Ly * u[2 * pix + 1];
+            const double lu = Lx * us[2 * pix] + Ly * us[2 * pix + 1];
             jx += lu * tp.dwx[q];
             jy += lu * tp.dwy[q];
         }
@@ -429,18 +461,19 @@ static void cmo_chain(const cmo_cam* c, const double* rho, const double* theta,
 }
 
 /* ---------------------------------------------------------------------------
- * Public: backward.  Recomputes the forward, then
- *   drho [H*W] = grad_loss * dL/drho,  dtheta [6] = grad_loss * dL/dtheta,
- *   dflow (optional) [H*W*2] = grad_loss * dL/du.
+ * Public: backward.  Recomputes the forward, then, per flow set,
+ *   drho [F][H*W] = grad_loss * dL/drho,  dtheta [F][6] = grad_loss * dL/dtheta,
+ *   dflow (optional) [F][H*W*2] = grad_loss * dL/du.
  * ------------------------------------------------------------------------- */
-int cmo_backward(int W, int H, const double* K, int R, const double* refs, double eps, int64_t n,
+int cmo_backward(int W, int H, const double* K, int R, const double* refs, double eps, int F,
+                 int64_t n,
                  const double* x, const double* y, const double* t, const int8_t* p,
                  const double* rho, const double* theta, double grad_loss, double* drho,
                  double* dtheta, double* dflow_out)
 {
     cmo_fwd f;
     memset(&f, 0, sizeof f);
-    int st = cmo_setup(&f.cam, W, H, K, R, refs, eps);
+    int st = cmo_setup(&f.cam, W, H, K, R, refs, eps, F);
     if (st) return st;
     if (n < 0 || !rho || !theta || !drho || !dtheta || (n > 0 && (!x || !y || !t || !p)))
         return CMO_BAD_ARG;
@@ -448,12 +481,12 @@ int cmo_backward(int W, int H, const double* K, int R, const double* refs, doubl
     if (st) { cmo_fwd_free(&f); return st; }
     const cmo_cam* c = &f.cam;
     const size_t HW = (size_t)H * W;
-    double* dflow = (double*)calloc(2 * HW, sizeof(double));
+    double* dflow = (double*)calloc(2 * HW * (size_t)F, sizeof(double));
     if (!dflow) { cmo_fwd_free(&f); return CMO_NO_MEM; }
 
     double pos[2 * CMO_MAX_REFS];
     double px[CMO_MAX_REFS + 1], py[CMO_MAX_REFS + 1], tau[CMO_MAX_REFS + 1];
-    int ridx[CMO_MAX_REFS + 1];
+    int ridx[CMO_MAX_REFS + 1], fset[CMO_MAX_REFS + 1];
     for (int64_t k = 0; k < n; ++k) {
         const double tk = t[k];
         if (!cmo_warp_event(c, f.u, x[k], y[k], tk, pos)) continue;
@@ -467,19 +500,23 @@ int cmo_backward(int W, int H, const double* K, int R, const double* refs, doubl
             if (c->refs[r] == tk) continue;
             ++len;
             px[len] = pos[2 * r]; py[len] = pos[2 * r + 1]; tau[len] = c->refs[r]; ridx[len] = r;
+            fset[len] = cmo_set_fwd(c, r);
         }
-        cmo_reverse_sweep(c, f.u, f.img, f.nact, pol, tk, len, px, py, tau, ridx, dflow);
+        cmo_reverse_sweep(c, f.u, f.img, f.nact, pol, tk, len, px, py, tau, ridx, fset, dflow);
         /* backward sweep path: refs before t_k in decreasing order */
         len = 0;
         for (int r = m - 1; r >= 0; --r) {
             ++len;
             px[len] = pos[2 * r]; py[len] = pos[2 * r + 1]; tau[len] = c->refs[r]; ridx[len] = r;
+            fset[len] = cmo_set_bwd(c, r);
         }
-        cmo_reverse_sweep(c, f.u, f.img, f.nact, pol, tk, len, px, py, tau, ridx, dflow);
+        cmo_reverse_sweep(c, f.u, f.img, f.nact, pol, tk, len, px, py, tau, ridx, fset, dflow);
     }
-    for (size_t i = 0; i < 2 * HW; ++i) dflow[i] *= grad_loss;
-    cmo_chain(c, rho, theta, dflow, drho, dtheta);
-    if (dflow_out) memcpy(dflow_out, dflow, sizeof(double) * 2 * HW);
+    for (size_t i = 0; i < 2 * HW * (size_t)F; ++i) dflow[i] *= grad_loss;
+    for (int fs = 0; fs < F; ++fs)
+        cmo_chain(c, rho + HW * fs, theta + 6 * fs, dflow + 2 * HW * fs, drho + HW * fs,
+                  dtheta + 6 * fs);
+    if (dflow_out) memcpy(dflow_out, dflow, sizeof(double) * 2 * HW * (size_t)F);
     free(dflow);
     cmo_fwd_free(&f);
     return CMO_OK;
