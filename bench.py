@@ -33,6 +33,8 @@ WORKLOADS = {
     "c3": "c3: 64 windows 346x260 f=200, log-uniform 5k..200k edge-map events, refs {0,1}, "
           "fwd+bwd",
     "c5": "c5: 1280x720 f=600, 2M edge-map events (400 segments), 8 refs in [0,1], fwd+bwd",
+    "c6": "c6: 64 windows 346x260 f=200, 10 slices of log-uniform 1k..10k edge-map events, "
+          "refs at the 11 slice edges, one depth + ego-motion per slice (10 flow sets), fwd+bwd",
 }
 
 
@@ -41,24 +43,24 @@ def kernel_source_sha() -> str:
     return source_sha()
 
 
-def algorithmic_bytes(phase: str, n: int, HW: int, R: int, tiled: bool) -> float:
+def algorithmic_bytes(phase: str, n: int, HW: int, R: int, tiled: bool, F: int = 1) -> float:
     """Bytes a phase must move at minimum for one window.
 
-    events: 13 B each (x, y, t FP32 + p int8); rho: 4 B per pixel; splat images:
-    C and S FP64 per pixel, polarity and reference (32 R B per pixel); d rho 4 B
-    per pixel.  The tiled path's records and bin tables are not counted: they
+    events: 13 B each (x, y, t FP32 + p int8); rho: 4 B per pixel and flow set;
+    splat images: C and S FP64 per pixel, polarity and reference (32 R B per
+    pixel); d rho 4 B per pixel and flow set.  The tiled path's records and bin tables are not counted: they
     are the implementation's traffic, not the method's."""
     ev = 13.0 * n
-    rho = 4.0 * HW
+    rho = 4.0 * HW * F
     img = 32.0 * R * HW
     if tiled:
         table = {"zero": 0.0, "count": ev + rho, "scan": 0.0, "scatter": ev + rho,
                  "splat": img, "reduce": 0.0, "finalize": 0.0,
                  "grad_count": ev + rho, "grad_scan": 0.0, "adjoint": ev + rho + img,
-                 "grad_tile": 8.0 * HW, "grad_finalize": 0.0}
+                 "grad_tile": 8.0 * HW * F, "grad_finalize": 0.0}
     else:
         table = {"zero": img, "splat": ev + rho + img, "reduce": img, "finalize": 0.0,
-                 "grad_zero": 4.0 * HW, "adjoint": ev + rho + img + 4.0 * HW,
+                 "grad_zero": 4.0 * HW * F, "adjoint": ev + rho + img + 4.0 * HW * F,
                  "grad_finalize": 0.0}
     return table.get(phase, 0.0)
 
@@ -202,7 +204,8 @@ def main():
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the single-window c2 line")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the c6 (flow sets) and single-window c2 lines")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the served Poisson stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=500.0)
@@ -226,8 +229,9 @@ def main():
     stream = torch.cuda.current_stream(dev)
     cm.set_path(0, {"auto": cm.CM_PATH_AUTO, "direct": cm.CM_PATH_DIRECT,
                     "tiled": cm.CM_PATH_TILED}[args.path])
-    batched = args.workload == "c3"
-    wins = eventgen.make_batch("c3", 64) if batched else [eventgen.make_window(args.workload)]
+    batched = args.workload in ("c3", "c6")
+    wins = eventgen.make_batch(args.workload, 64) if batched else \
+        [eventgen.make_window(args.workload)]
     n_events = sum(w.n for w in wins)
     out_extra = {}
 
@@ -277,10 +281,32 @@ def main():
     dom = max(per_launch, key=lambda k: per_launch[k][0] * per_launch[k][1])
     dom_ms = per_launch[dom][0]
     launches_per_step = per_launch[dom][1] / args.steps
-    alg = sum(algorithmic_bytes(dom, w.n, w.width * w.height, len(w.refs), path_used == "tiled")
+    alg = sum(algorithmic_bytes(dom, w.n, w.width * w.height, len(w.refs), path_used == "tiled",
+                                w.rho.shape[0] if w.rho.ndim == 3 else 1)
               for w in wins) / launches_per_step
     achieved = alg / (dom_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, dom)
+
+    if not args.no_extras and args.workload == "c3":
+        # the paper's training setting: 10 slices per window, one flow per slice
+        w6 = eventgen.make_batch("c6", 64)
+        d6 = to_device(w6, dev)
+        b6 = cm.Batch([cm.WindowDesc.from_window(w) for w in w6], [w.n for w in w6], graph=True)
+        st6 = b6.new_state()
+        l6 = torch.empty(b6.n, device=dev)
+        gr6, ge6 = torch.empty_like(d6["rho"]), torch.empty_like(d6["ego"])
+        gl6 = torch.ones(b6.n, device=dev)
+
+        def step6():
+            b6.forward(d6["x"], d6["y"], d6["t"], d6["p"], d6["rho"], d6["ego"], state=st6,
+                       loss=l6)
+            b6.backward(d6["x"], d6["y"], d6["t"], d6["p"], d6["rho"], d6["ego"], st6, gl6,
+                        grad_rho=gr6, grad_ego=ge6)
+        ms6 = timed(step6, args.steps, args.warmup, stream)
+        n6 = sum(w.n for w in w6)
+        out_extra["c6_batched"] = {"workload": WORKLOADS["c6"], "n_events": n6,
+                                   "ms_per_step": ms6, "events_per_s": n6 / (ms6 * 1e-3)}
+        b6.close()
 
     if not args.no_extras and args.workload != "c2":
         w2 = eventgen.make_window("c2")

@@ -20,6 +20,9 @@ supplement's training details):
   c3  64 windows at 346x260, f=200, log-uniform 5k..200k events, refs {0, 1}
   c4  Poisson stream, 346x260 (f=200) or 640x480 (f=300), 1k..500k events, refs {0, 1}
   c5  1280x720, f=600, 2M events (400 segments), 8 refs evenly spaced in [0, 1]
+  c6  64 windows at 346x260, f=200, 10 bins of 1k..10k events each (log-uniform),
+      refs at the 11 bin edges, one inverse depth and ego-motion per bin (the
+      paper's training setting: flows of consecutive slices concatenated)
 
 Seeds: numpy PCG64 with seed = 1000 * config_number + window_index.
 """
@@ -257,12 +260,55 @@ def edge_window(seed: int, sensor: str, n_events: int, refs, n_segments: int = 5
                   x, y, t, p, rho, theta)
 
 
+def knots_of(refs) -> np.ndarray:
+    """Sorted knots {0, 1} U refs (refs sorted and in [0, 1])."""
+    k = [float(r) for r in refs]
+    if k[0] > 0.0:
+        k = [0.0] + k
+    if k[-1] < 1.0:
+        k = k + [1.0]
+    return np.asarray(k)
+
+
+def with_flow_sets(win: Window, seed: int, jitter: float = 0.15) -> Window:
+    """The window with one inverse depth and ego-motion per segment between
+    consecutive knots {0, 1} U refs.  Each set is the window's own, perturbed:
+    rho times a smooth positive field (1 + jitter * bump), theta plus
+    N(0, jitter^2 |theta|_rms^2) per axis."""
+    F = len(knots_of(win.refs)) - 1
+    rng = _rng(seed)
+    W, H = win.width, win.height
+    rhos, thetas = [], []
+    base_rho = np.asarray(win.rho, np.float64)
+    base_th = np.asarray(win.theta, np.float64)
+    scale = float(np.sqrt(np.mean(base_th ** 2))) or 1.0
+    for _ in range(F):
+        mus = np.stack([rng.uniform(0, W - 1, 2), rng.uniform(0, H - 1, 2)], 1)
+        bump = _GaussianBumps(mus, W / 5.0, base=0.0, amp=1.0).grid(W, H)
+        rhos.append(base_rho * (1.0 + jitter * (bump - 0.5)))
+        thetas.append(base_th + rng.normal(0.0, jitter * scale, 6))
+    return win.replace(rho=np.stack(rhos).astype(np.float32),
+                       theta=np.stack(thetas).astype(np.float32))
+
+
+def bins_window(index: int, n_bins: int = 10, sensor: str = "346x260",
+                per_bin=(1e3, 1e4)) -> Window:
+    """Workload c6: an edge-map window of n_bins slices with log-uniform 1k..10k
+    events per slice, references at the n_bins + 1 slice edges and one flow
+    set per slice."""
+    seed = 1000 * 6 + index
+    counts = log_uniform_counts(_rng(seed + 500), n_bins, *per_bin)
+    refs = np.linspace(0.0, 1.0, n_bins + 1)
+    win = edge_window(seed, sensor, int(counts.sum()), refs=refs, n_segments=50, name="c6")
+    return with_flow_sets(win, seed + 700)
+
+
 def log_uniform_counts(rng, n, lo, hi) -> np.ndarray:
     return np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), n))).astype(np.int64)
 
 
 def make_window(config: str, index: int = 0, n_events: Optional[int] = None) -> Window:
-    """The `index`-th window of workload `config` (c1, c2, c3, c5)."""
+    """The `index`-th window of workload `config` (c1, c2, c3, c5, c6)."""
     if config == "c1":
         return uniform_window(1000 * 1 + index, n_events=n_events or 2000)
     if config == "c2":
@@ -276,11 +322,16 @@ def make_window(config: str, index: int = 0, n_events: Optional[int] = None) -> 
     if config == "c5":
         return edge_window(1000 * 5 + index, "1280x720", n_events or 2_000_000,
                            refs=refs_even(8), n_segments=400, name="c5")
+    if config == "c6":
+        return bins_window(index)
     raise ValueError(f"unknown config {config!r}")
 
 
 def make_batch(config: str = "c3", n_windows: int = 64, scale: float = 1.0) -> List[Window]:
-    """Workload c3: n_windows windows with log-uniform event counts (optionally scaled)."""
+    """Workload c3 (or c6): n_windows windows with log-uniform event counts
+    (optionally scaled)."""
+    if config == "c6":
+        return [bins_window(i) for i in range(n_windows)]
     counts = log_uniform_counts(_rng(1000 * 3 + 999), 64, 5e3, 2e5)
     out = []
     for i in range(n_windows):

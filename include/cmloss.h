@@ -20,11 +20,17 @@
  *  - Events are structure-of-arrays in device memory: x, y, t float32, p int8
  *    (p > 0 positive polarity, anything else negative).  t is the timestamp
  *    normalised to the window, expected in [0, 1].
- *  - inv_depth: float32 [height * width] device array, rho = 1/depth (any
+ *  - inv_depth: float32 [F][height * width] device array, rho = 1/depth (any
  *    common scale, Eq. 2 fixes depth only up to scale).
- *  - ego: float32 [6] device array (v_x, v_y, v_z, w_x, w_y, w_z): translation
- *    and rotation (exponential coordinates) of the camera over the window;
- *    flow is in pixels per window.
+ *  - ego: float32 [F][6] device array (v_x, v_y, v_z, w_x, w_y, w_z):
+ *    translation and rotation (exponential coordinates) of the camera over the
+ *    window; flow is in pixels per window.
+ *  - Flow sets (Sec. 3.1 concatenates the flows of consecutive slices of the
+ *    event stream): F = 1 warps the whole window with one flow.  Otherwise F
+ *    is the number of segments between consecutive knots {0, 1} U refs and
+ *    segment f (in time order) has its own inverse depth and ego-motion; a warp
+ *    step samples the flow of the segment it crosses.  Gradients have the same
+ *    [F] layout.
  *  - Loss: L = (1/R) sum_r [sum_x sum_p (S_p/(C_p+eps))^2] / (N_r + eps), with
  *    C_p / S_p the bilinear splat of the surviving events' weights / weights
  *    times (1 - |r - t_k|), and N_r the number of pixels with C_+ + C_- > 0.
@@ -83,6 +89,8 @@ typedef struct {
     float refs[CM_MAX_REFS];        /* reference times, strictly increasing, in [0, 1] */
     int32_t mode;                   /* CM_MODE_* */
     float eps;                      /* regulariser of Eq. 1's ratios, finite and > 0 (1e-9 by default) */
+    int32_t n_flows;                /* F: 0 or 1 (one flow), or the number of segments between
+                                       consecutive knots {0, 1} U refs */
 } cm_window_desc;
 
 /* Create a handle bound to HIP device `device`.  *h receives the handle. */
@@ -136,9 +144,9 @@ cm_status cm_loss_forward(cm_handle h, const cm_window_desc* d,
  *   state          : the buffer the forward wrote for the same inputs; its
  *                    scratch tail is overwritten, the images are only read.
  *   grad_loss      : float32 [1] (device), dOut/dL from the caller
- *   grad_inv_depth : float32 [height * width] (device), overwritten with
+ *   grad_inv_depth : float32 [F][height * width] (device), overwritten with
  *                    grad_loss * dL/d(inv_depth)
- *   grad_ego       : float32 [6] (device), overwritten with grad_loss * dL/d(ego) */
+ *   grad_ego       : float32 [F][6] (device), overwritten with grad_loss * dL/d(ego) */
 cm_status cm_loss_backward(cm_handle h, const cm_window_desc* d,
                            const float* ev_x, const float* ev_y, const float* ev_t,
                            const int8_t* ev_p, int64_t n_events,
@@ -159,8 +167,10 @@ cm_status cm_state_diagnostics(const cm_window_desc* d, const void* state, doubl
  * the same mode) and their event counts.  Events of all windows are packed in
  * flat device arrays, window w at [event_offsets[w], event_offsets[w+1]), in
  * window order; inverse depth and d inverse depth likewise at
- * [pixel_offsets[w], pixel_offsets[w+1]) (height * width floats each); ego and
- * d ego are [n_windows * 6]; loss and grad_loss are [n_windows].  Each window's
+ * [pixel_offsets[w], pixel_offsets[w+1]) (F * height * width floats each);
+ * ego and d ego hold 6 floats per flow set, window w's sets starting at set
+ * set_offsets[w] (cm_batch_flow_offsets; w * 6 floats when every window has
+ * one flow); loss and grad_loss are [n_windows].  Each window's
  * loss and gradient equal those of a single-window call on the same data.
  * A plan holds host memory only: each call copies the per-window metadata into
  * the caller's state buffer (cm_batch_state_bytes) on the call's stream, so
@@ -178,6 +188,9 @@ cm_status cm_batch_destroy(cm_batch b);
 size_t cm_batch_state_bytes(cm_batch b);
 /* Host arrays of n_windows + 1 entries each (either may be NULL). */
 cm_status cm_batch_offsets(cm_batch b, int64_t* event_offsets, int64_t* pixel_offsets);
+/* First flow set of each window (host array of n_windows + 1 entries): ego and
+ * d ego of window w are floats [6 * set_offsets[w], 6 * set_offsets[w+1]). */
+cm_status cm_batch_flow_offsets(cm_batch b, int64_t* set_offsets);
 cm_status cm_batch_set_graph(cm_batch b, int enable);
 cm_status cm_loss_forward_batched(cm_batch b, const float* ev_x, const float* ev_y,
                                   const float* ev_t, const int8_t* ev_p, const float* inv_depth,

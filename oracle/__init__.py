@@ -190,11 +190,11 @@ def _load_mirror():
         lib = ctypes.CDLL(_MIRROR_PATH)
         P = ctypes.c_void_p
         lib.cmm_forward.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_float,
-                                    ctypes.c_int64, P, P, P, P, P, P, P, P]
+                                    ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P, P, P]
         lib.cmm_forward.restype = ctypes.c_int
         lib.cmm_backward.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P,
-                                     ctypes.c_float, ctypes.c_int64, P, P, P, P, P, P,
-                                     ctypes.c_float, P, P]
+                                     ctypes.c_float, ctypes.c_int, ctypes.c_int64, P, P, P, P, P,
+                                     P, ctypes.c_float, P, P]
         lib.cmm_backward.restype = ctypes.c_int
         _mirror = lib
     return _mirror
@@ -215,7 +215,7 @@ def mirror_forward(win) -> dict:
     loss = np.zeros(1, np.float32)
     hdr = np.zeros(2 + 2 * R, np.float64)
     st = lib.cmm_forward(win.width, win.height, _ptr(K), R, _ptr(refs), float(np.float32(win.eps)),
-                         x.shape[0], _ptr(x), _ptr(y), _ptr(t), _ptr(p), _ptr(rho), _ptr(th),
+                         n_flows(rho), x.shape[0], _ptr(x), _ptr(y), _ptr(t), _ptr(p), _ptr(rho), _ptr(th),
                          _ptr(loss), _ptr(hdr))
     if st != 0:
         raise ValueError(f"cmm_forward failed ({st})")
@@ -225,14 +225,16 @@ def mirror_forward(win) -> dict:
 
 def mirror_backward(win, grad_loss: float = 1.0) -> dict:
     """Deterministic-mode backward in its canonical order: dict(drho float32
-    [H, W], dtheta float32 [6])."""
+    [H, W] or [F, H, W], dtheta float32 [6] or [F, 6])."""
     lib = _load_mirror()
     K, refs, x, y, t, p, rho, th = _mirror_args(win)
     R = refs.shape[0]
-    drho = np.zeros((win.height, win.width), np.float32)
-    dth = np.zeros(6, np.float32)
+    F = n_flows(rho)
+    lead = () if rho.ndim == 2 else (F,)
+    drho = np.zeros(lead + (win.height, win.width), np.float32)
+    dth = np.zeros(lead + (6,), np.float32)
     st = lib.cmm_backward(win.width, win.height, _ptr(K), R, _ptr(refs),
-                          float(np.float32(win.eps)), x.shape[0], _ptr(x), _ptr(y), _ptr(t),
+                          float(np.float32(win.eps)), F, x.shape[0], _ptr(x), _ptr(y), _ptr(t),
                           _ptr(p), _ptr(rho), _ptr(th), float(np.float32(grad_loss)), _ptr(drho),
                           _ptr(dth))
     if st != 0:

@@ -52,12 +52,19 @@
 
 enum { MM_OK = 0, MM_BAD = -1, MM_NOMEM = -2 };
 
+#define MM_MAX_FLOWS (MM_MAX_REFS + 1)
+
 typedef struct {
     int W, H, R, HW;
     double cx, cy, fx, fy, inv_fx, inv_fy, fx_over_fy, fy_over_fx, xmax, ymax, eps, two_over_R;
     double refs[MM_MAX_REFS];
-    /* motion */
-    double k0, k1, k2, k3, k4, k5, tvx, tvy, vz;
+    /* flow sets: motion per set, inverse depth of set f at rho + f HW; the step
+     * into reference r uses set sf[r] forward in time, sb[r] backward */
+    int F;
+    double k0[MM_MAX_FLOWS], k1[MM_MAX_FLOWS], k2[MM_MAX_FLOWS], k3[MM_MAX_FLOWS];
+    double k4[MM_MAX_FLOWS], k5[MM_MAX_FLOWS], tvx[MM_MAX_FLOWS], tvy[MM_MAX_FLOWS];
+    double vz[MM_MAX_FLOWS];
+    int sf[MM_MAX_REFS], sb[MM_MAX_REFS];
     const float* rho;
     /* tiles */
     int ntx, nty, ntiles, ept, nblocks;
@@ -66,7 +73,7 @@ typedef struct {
 typedef struct { double x, y; } d2;
 
 static int mm_setup(mm_win* w, int W, int H, const float* K, int R, const float* refs, float eps,
-                    const float* rho, const float* theta, int64_t n)
+                    int F, const float* rho, const float* theta, int64_t n)
 {
     if (W <= 0 || H <= 0 || R < 1 || R > MM_MAX_REFS) return MM_BAD;
     memset(w, 0, sizeof *w);
@@ -78,17 +85,29 @@ static int mm_setup(mm_win* w, int W, int H, const float* K, int R, const float*
     w->eps = eps;
     w->two_over_R = 2.0 / (double)R;
     for (int r = 0; r < R; ++r) w->refs[r] = refs[r];
-    const double vx = theta[0], vy = theta[1], vz = theta[2];
-    const double wx = theta[3], wy = theta[4], wz = theta[5];
-    w->k0 = w->fx * wy;
-    w->k1 = w->fx_over_fy * wz;
-    w->k2 = wx * w->inv_fy;
-    w->k3 = wy * w->inv_fx;
-    w->k4 = -w->fy * wx;
-    w->k5 = w->fy_over_fx * wz;
-    w->tvx = w->fx * vx;
-    w->tvy = w->fy * vy;
-    w->vz = vz;
+    /* knots {0, 1} U refs; segment f between knots f and f+1 */
+    const int k0 = refs[0] > 0.f ? 1 : 0;
+    const int nseg = R - 1 + k0 + (refs[R - 1] < 1.f ? 1 : 0);
+    if (F != 1 && F != nseg) return MM_BAD;
+    w->F = F;
+    for (int r = 0; r < R; ++r) {
+        w->sf[r] = F > 1 ? (k0 + r - 1 > 0 ? k0 + r - 1 : 0) : 0;
+        w->sb[r] = F > 1 ? (k0 + r < F - 1 ? k0 + r : F - 1) : 0;
+    }
+    for (int f = 0; f < F; ++f) {
+        const float* th = theta + 6 * f;
+        const double vx = th[0], vy = th[1], vz = th[2];
+        const double wx = th[3], wy = th[4], wz = th[5];
+        w->k0[f] = w->fx * wy;
+        w->k1[f] = w->fx_over_fy * wz;
+        w->k2[f] = wx * w->inv_fy;
+        w->k3[f] = wy * w->inv_fx;
+        w->k4[f] = -w->fy * wx;
+        w->k5[f] = w->fy_over_fx * wz;
+        w->tvx[f] = w->fx * vx;
+        w->tvy[f] = w->fy * vy;
+        w->vz[f] = vz;
+    }
     w->rho = rho;
     w->ntx = (W + TW - 1) / TW;
     w->nty = (H + TH - 1) / TH;
@@ -103,22 +122,23 @@ static int mm_setup(mm_win* w, int W, int H, const float* K, int R, const float*
     return MM_OK;
 }
 
-static void mm_parts(const mm_win* w, int i, int j, double* Ax, double* Ay, double* Bx, double* By)
+static void mm_parts(const mm_win* w, int f, int i, int j, double* Ax, double* Ay, double* Bx,
+                     double* By)
 {
     const double xb = (double)i - w->cx;
     const double yb = (double)j - w->cy;
-    const double s = w->k3 * xb - w->k2 * yb;
-    *Ax = (w->k0 - w->k1 * yb) + xb * s;
-    *Ay = (w->k4 + w->k5 * xb) + yb * s;
-    *Bx = w->tvx - xb * w->vz;
-    *By = w->tvy - yb * w->vz;
+    const double s = w->k3[f] * xb - w->k2[f] * yb;
+    *Ax = (w->k0[f] - w->k1[f] * yb) + xb * s;
+    *Ay = (w->k4[f] + w->k5[f] * xb) + yb * s;
+    *Bx = w->tvx[f] - xb * w->vz[f];
+    *By = w->tvy[f] - yb * w->vz[f];
 }
 
-static d2 mm_flow(const mm_win* w, int i, int j)
+static d2 mm_flow(const mm_win* w, int f, int i, int j)
 {
     double Ax, Ay, Bx, By;
-    mm_parts(w, i, j, &Ax, &Ay, &Bx, &By);
-    const double r = (double)w->rho[j * w->W + i];
+    mm_parts(w, f, i, j, &Ax, &Ay, &Bx, &By);
+    const double r = (double)w->rho[(size_t)f * w->HW + j * w->W + i];
     d2 u = {Ax + r * Bx, Ay + r * By};
     return u;
 }
@@ -153,10 +173,10 @@ static void mm_tap_dw(const mm_taps* t, int q, double* dX, double* dY)
     *dY = (q & 2) ? wa : -wa;
 }
 
-static void mm_tap_flows(const mm_win* w, const mm_taps* t, d2 uq[4])
+static void mm_tap_flows(const mm_win* w, int f, const mm_taps* t, d2 uq[4])
 {
     for (int q = 0; q < 4; ++q) {
-        if (mm_tap_in(t, q)) uq[q] = mm_flow(w, t->x0 + (q & 1), t->y0 + (q >> 1));
+        if (mm_tap_in(t, q)) uq[q] = mm_flow(w, f, t->x0 + (q & 1), t->y0 + (q >> 1));
         else { uq[q].x = 0.0; uq[q].y = 0.0; }
     }
 }
@@ -185,15 +205,16 @@ static int mm_warp(const mm_win* w, double x0, double y0, double tk, double* px,
     const int nf = w->R - rs, nv = nf + mb;
     double X = x0, Y = y0, tau = tk;
     for (int j = 0; j < nv; ++j) {
-        int r;
-        if (j < nf) r = rs + j;
+        int r, f;
+        if (j < nf) { r = rs + j; f = w->sf[r]; }
         else {
             r = mb - 1 - (j - nf);
+            f = w->sb[r];
             if (j == nf) { X = x0; Y = y0; tau = tk; }
         }
         const mm_taps t = mm_make_taps(w, X, Y);
         d2 uq[4];
-        mm_tap_flows(w, &t, uq);
+        mm_tap_flows(w, f, &t, uq);
         double ux = 0.0, uy = 0.0;
         for (int q = 0; q < 4; ++q) {
             const double wq = mm_tap_w(&t, q);
@@ -392,13 +413,13 @@ static int mm_forward_impl(mm_state* S, int64_t n, const float* ex, const float*
     return MM_OK;
 }
 
-int cmm_forward(int W, int H, const float* K, int R, const float* refs, float eps, int64_t n,
-                const float* x, const float* y, const float* t, const int8_t* p,
+int cmm_forward(int W, int H, const float* K, int R, const float* refs, float eps, int F,
+                int64_t n, const float* x, const float* y, const float* t, const int8_t* p,
                 const float* rho, const float* theta, float* loss_out, double* hdr_out)
 {
     mm_state S;
     memset(&S, 0, sizeof S);
-    if (mm_setup(&S.w, W, H, K, R, refs, eps, rho, theta, n)) return MM_BAD;
+    if (mm_setup(&S.w, W, H, K, R, refs, eps, F, rho, theta, n)) return MM_BAD;
     const int st = mm_forward_impl(&S, n, x, y, t, p);
     if (st == MM_OK) {
         *loss_out = (float)S.loss;
@@ -437,12 +458,12 @@ static void mm_direct(const mm_win* w, const d2* plane, double coef, double tb, 
     }
 }
 
-static void mm_jacobian_t(const mm_win* w, double X, double Y, double Lx, double Ly, double* jx,
-                          double* jy)
+static void mm_jacobian_t(const mm_win* w, int f, double X, double Y, double Lx, double Ly,
+                          double* jx, double* jy)
 {
     const mm_taps tp = mm_make_taps(w, X, Y);
     d2 uq[4];
-    mm_tap_flows(w, &tp, uq);
+    mm_tap_flows(w, f, &tp, uq);
     *jx = 0.0;
     *jy = 0.0;
     for (int q = 0; q < 4; ++q) {
@@ -473,43 +494,56 @@ typedef struct {
     double Lx, Ly, g0x, g0y;
 } mm_lane;
 
-static void mm_emit(const mm_win* w, mm_grec* rec, int64_t* fill, double X, double Y, double gx,
-                    double gy)
+static void mm_emit(const mm_win* w, mm_grec* rec, int64_t* fill, int f, double X, double Y,
+                    double gx, double gy)
 {
-    mm_grec* q = &rec[fill[mm_tile_of(w, X, Y)]++];
+    mm_grec* q = &rec[fill[f * w->ntiles + mm_tile_of(w, X, Y)]++];
     q->X = X; q->Y = Y; q->gx = gx; q->gy = gy;
 }
 
-int cmm_backward(int W, int H, const float* K, int R, const float* refs, float eps, int64_t n,
-                 const float* x, const float* y, const float* t, const int8_t* p,
+int cmm_backward(int W, int H, const float* K, int R, const float* refs, float eps, int F,
+                 int64_t n, const float* x, const float* y, const float* t, const int8_t* p,
                  const float* rho, const float* theta, float grad_loss, float* drho_out,
                  float* dtheta_out)
 {
     mm_state S;
     memset(&S, 0, sizeof S);
-    if (mm_setup(&S.w, W, H, K, R, refs, eps, rho, theta, n)) return MM_BAD;
+    if (mm_setup(&S.w, W, H, K, R, refs, eps, F, rho, theta, n)) return MM_BAD;
     int st = mm_forward_impl(&S, n, x, y, t, p);
     if (st) { free(S.img); return st; }
     const mm_win* w = &S.w;
-    const int nt = w->ntiles;
+    const int nt = w->ntiles, nbb = F * nt;
+    const int split = F > 1;     /* one record per first step (else one per event) */
     double coef[MM_MAX_REFS];
     for (int r = 0; r < R; ++r) coef[r] = w->two_over_R / (S.nact[r] + w->eps);
 
-    /* count: sampling positions per tile, per event in order */
-    int64_t* cnt = (int64_t*)calloc((size_t)nt + 1, sizeof(int64_t));
+    /* count: sampling positions per (flow set, tile) bin */
+    int64_t* cnt = (int64_t*)calloc((size_t)nbb + 1, sizeof(int64_t));
     double px[MM_MAX_REFS], py[MM_MAX_REFS];
     int mb;
     for (int64_t k = 0; k < n; ++k) {
         if (!mm_warp(w, x[k], y[k], t[k], px, py, &mb)) continue;
         const int rs = (mb < R && w->refs[mb] == (double)t[k]) ? mb + 1 : mb;
-        for (int r = rs + 1; r < R; ++r) cnt[mm_tile_of(w, px[r - 1], py[r - 1]) + 1]++;
-        for (int r = mb - 2; r >= 0; --r) cnt[mm_tile_of(w, px[r + 1], py[r + 1]) + 1]++;
-        if (rs < R || mb > 0) cnt[mm_tile_of(w, x[k], y[k]) + 1]++;
+        if (split) {
+            for (int r = rs; r < R; ++r) {
+                const double X = r == rs ? x[k] : px[r - 1], Y = r == rs ? y[k] : py[r - 1];
+                cnt[w->sf[r] * nt + mm_tile_of(w, X, Y) + 1]++;
+            }
+            for (int r = mb - 1; r >= 0; --r) {
+                const double X = r == mb - 1 ? x[k] : px[r + 1];
+                const double Y = r == mb - 1 ? y[k] : py[r + 1];
+                cnt[w->sb[r] * nt + mm_tile_of(w, X, Y) + 1]++;
+            }
+        } else {
+            for (int r = rs + 1; r < R; ++r) cnt[mm_tile_of(w, px[r - 1], py[r - 1]) + 1]++;
+            for (int r = mb - 2; r >= 0; --r) cnt[mm_tile_of(w, px[r + 1], py[r + 1]) + 1]++;
+            if (rs < R || mb > 0) cnt[mm_tile_of(w, x[k], y[k]) + 1]++;
+        }
     }
-    for (int b = 0; b < nt; ++b) cnt[b + 1] += cnt[b];
-    mm_grec* rec = (mm_grec*)malloc(sizeof(mm_grec) * (size_t)(cnt[nt] + 1));
-    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)nt);
-    memcpy(fill, cnt, sizeof(int64_t) * (size_t)nt);
+    for (int b = 0; b < nbb; ++b) cnt[b + 1] += cnt[b];
+    mm_grec* rec = (mm_grec*)malloc(sizeof(mm_grec) * (size_t)(cnt[nbb] + 1));
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)nbb);
+    memcpy(fill, cnt, sizeof(int64_t) * (size_t)nbb);
 
     /* source order: the valid events grouped by the tile of their position
      * at reference 0, in event order within a tile (the forward's reference-0
@@ -531,9 +565,9 @@ int cmm_backward(int W, int H, const float* K, int R, const float* refs, float e
 
     /* sweep: in iteration e, block b takes the source positions
      * [(e * nblocks + b) * 64, +64), its 64 lanes in lockstep over the visits
-     * j = R-1 .. 0 (the backward sweep backwards,
-     * then the forward sweep backwards); the records of one visit number are
-     * emitted in lane order, then the event records in lane order. */
+     * j = R-1 .. 0 (the backward sweep backwards, then the forward sweep
+     * backwards); the records of one visit number are emitted in lane order,
+     * then (one flow set) the event records in lane order. */
     mm_lane lanes[64];
     for (int blk = 0; blk < w->nblocks; ++blk) {
         for (int e = 0; e < w->ept; ++e) {
@@ -560,6 +594,7 @@ int cmm_backward(int W, int H, const float* K, int R, const float* refs, float e
                     const int first = (j == jf && j < nf) || (j == nf);
                     const int restart = (j == R - 1) || (j == nf - 1);
                     const int r = j < nf ? L->mb + j : L->mb - 1 - (j - nf);
+                    const int f = j < nf ? w->sf[r] : w->sb[r];
                     int rp = r;
                     if (j > 0) rp = (j - 1) < nf ? L->mb + (j - 1) : L->mb - 1 - (j - 1 - nf);
                     const double X = first ? L->x0 : L->px[rp];
@@ -569,12 +604,16 @@ int cmm_backward(int W, int H, const float* K, int R, const float* refs, float e
                     mm_direct(w, S.img + (size_t)(r * 2 + L->pol) * w->HW, coef[r],
                               1.0 - fabs(w->refs[r] - L->tk), L->px[r], L->py[r], &L->Lx, &L->Ly);
                     if (first) {
-                        L->g0x += dt * L->Lx;
-                        L->g0y += dt * L->Ly;
+                        if (split) {
+                            mm_emit(w, rec, fill, f, L->x0, L->y0, dt * L->Lx, dt * L->Ly);
+                        } else {
+                            L->g0x += dt * L->Lx;
+                            L->g0y += dt * L->Ly;
+                        }
                     } else {
-                        mm_emit(w, rec, fill, X, Y, dt * L->Lx, dt * L->Ly);
+                        mm_emit(w, rec, fill, f, X, Y, dt * L->Lx, dt * L->Ly);
                         double jx, jy;
-                        mm_jacobian_t(w, X, Y, L->Lx, L->Ly, &jx, &jy);
+                        mm_jacobian_t(w, f, X, Y, L->Lx, L->Ly, &jx, &jy);
                         L->Lx += dt * jx;
                         L->Ly += dt * jy;
                     }
@@ -582,27 +621,31 @@ int cmm_backward(int W, int H, const float* K, int R, const float* refs, float e
             }
             for (int l = 0; l < 64; ++l) {
                 mm_lane* L = &lanes[l];
-                if (L->live && R - (L->rs ? 1 : 0) > 0)
-                    mm_emit(w, rec, fill, L->x0, L->y0, L->g0x, L->g0y);
+                if (!split && L->live && R - (L->rs ? 1 : 0) > 0)
+                    mm_emit(w, rec, fill, 0, L->x0, L->y0, L->g0x, L->g0y);
             }
         }
     }
     free(fill);
     free(order);
 
-    /* tiles: dL/du in LDS order, then d rho and d theta shares */
+    /* tiles, per (flow set, tile) bin: dL/du in LDS order, then d rho and
+     * d theta shares of that set */
     const double gl = (double)grad_loss;
-    d2* halo = (d2*)calloc((size_t)nt * NHALO, sizeof(d2));
-    d2* border = (d2*)calloc((size_t)nt * NBORDER, sizeof(d2));
-    double* part = (double*)calloc((size_t)nt * 12, sizeof(double));
+    d2* halo = (d2*)calloc((size_t)nbb * NHALO, sizeof(d2));
+    d2* border = (d2*)calloc((size_t)nbb * NBORDER, sizeof(d2));
+    double* part = (double*)calloc((size_t)nbb * 12, sizeof(double));
     d2* lds = (d2*)malloc(sizeof(d2) * TLW * TLH);
     double* red = (double*)malloc(sizeof(double) * 256 * 6);
-    for (int tile = 0; tile < nt; ++tile) {
+    for (int b = 0; b < nbb; ++b) {
+        const int f = b / nt, tile = b - f * nt;
         const int ty = tile / w->ntx, tx = tile - ty * w->ntx;
         const int xo = tx * TW, yo = ty * TH;
+        const float* rho_f = rho + (size_t)f * w->HW;
+        float* drho_f = drho_out + (size_t)f * w->HW;
         memset(lds, 0, sizeof(d2) * TLW * TLH);
-        for (int64_t c0 = cnt[tile]; c0 < cnt[tile + 1]; c0 += 64) {
-            const int64_t c1 = c0 + 64 < cnt[tile + 1] ? c0 + 64 : cnt[tile + 1];
+        for (int64_t c0 = cnt[b]; c0 < cnt[b + 1]; c0 += 64) {
+            const int64_t c1 = c0 + 64 < cnt[b + 1] ? c0 + 64 : cnt[b + 1];
             for (int q = 0; q < 4; ++q)
                 for (int64_t i = c0; i < c1; ++i) {
                     const mm_grec* s = &rec[i];
@@ -620,66 +663,71 @@ int cmm_backward(int W, int H, const float* K, int R, const float* refs, float e
             if (X >= w->W || Y >= w->H) continue;
             const d2 g = lds[ly * TLW + lx];
             if (lx == 0 || ly == 0) {
-                border[(size_t)tile * NBORDER + (lx == 0 ? ly : TH + lx - 1)] = g;
+                border[(size_t)b * NBORDER + (lx == 0 ? ly : TH + lx - 1)] = g;
                 continue;
             }
             double Ax, Ay, Bx, By;
-            mm_parts(w, X, Y, &Ax, &Ay, &Bx, &By);
+            mm_parts(w, f, X, Y, &Ax, &Ay, &Bx, &By);
             const int pix = Y * w->W + X;
-            drho_out[pix] = (float)(gl * (g.x * Bx + g.y * By));
+            drho_f[pix] = (float)(gl * (g.x * Bx + g.y * By));
             if (g.x != 0.0 || g.y != 0.0) {
                 double d[6];
                 for (int c = 0; c < 6; ++c) d[c] = red[c * 256 + i % 256];
-                mm_dtheta(w, X, Y, (double)rho[pix], g.x, g.y, d);
+                mm_dtheta(w, X, Y, (double)rho_f[pix], g.x, g.y, d);
                 for (int c = 0; c < 6; ++c) red[c * 256 + i % 256] = d[c];
             }
         }
         for (int j = 0; j < NHALO; ++j) {
             const int idx = (j <= TH) ? j * TLW + TW : TH * TLW + (j - (TH + 1));
-            halo[(size_t)tile * NHALO + j] = lds[idx];
+            halo[(size_t)b * NHALO + j] = lds[idx];
         }
-        for (int c = 0; c < 6; ++c) part[(size_t)tile * 12 + c] = mm_block_sum(red + c * 256, 256);
+        for (int c = 0; c < 6; ++c) part[(size_t)b * 12 + c] = mm_block_sum(red + c * 256, 256);
     }
-    for (int tile = 0; tile < nt; ++tile) {
+    for (int b = 0; b < nbb; ++b) {
+        const int f = b / nt, tile = b - f * nt;
         const int ty = tile / w->ntx, tx = tile - ty * w->ntx;
         const int xo = tx * TW, yo = ty * TH;
+        const float* rho_f = rho + (size_t)f * w->HW;
+        float* drho_f = drho_out + (size_t)f * w->HW;
         memset(red, 0, sizeof(double) * 64 * 6);
         for (int j = 0; j < NBORDER; ++j) {
             const int lx = j < TH ? 0 : j - TH + 1, ly = j < TH ? j : 0;
             const int X = xo + lx, Y = yo + ly;
             if (X >= w->W || Y >= w->H) continue;
-            d2 g = border[(size_t)tile * NBORDER + j];
+            d2 g = border[(size_t)b * NBORDER + j];
             if (lx == 0 && tx > 0) {
-                const d2 h = halo[(size_t)(tile - 1) * NHALO + ly];
+                const d2 h = halo[(size_t)(b - 1) * NHALO + ly];
                 g.x += h.x; g.y += h.y;
             }
             if (ly == 0 && ty > 0) {
-                const d2 h = halo[(size_t)(tile - w->ntx) * NHALO + TH + 1 + lx];
+                const d2 h = halo[(size_t)(b - w->ntx) * NHALO + TH + 1 + lx];
                 g.x += h.x; g.y += h.y;
             }
             if (lx == 0 && ly == 0 && tx > 0 && ty > 0) {
-                const d2 h = halo[(size_t)(tile - w->ntx - 1) * NHALO + TH];
+                const d2 h = halo[(size_t)(b - w->ntx - 1) * NHALO + TH];
                 g.x += h.x; g.y += h.y;
             }
             double Ax, Ay, Bx, By;
-            mm_parts(w, X, Y, &Ax, &Ay, &Bx, &By);
+            mm_parts(w, f, X, Y, &Ax, &Ay, &Bx, &By);
             const int pix = Y * w->W + X;
-            drho_out[pix] = (float)(gl * (g.x * Bx + g.y * By));
+            drho_f[pix] = (float)(gl * (g.x * Bx + g.y * By));
             if (g.x != 0.0 || g.y != 0.0) {
                 double d[6];
                 for (int c = 0; c < 6; ++c) d[c] = red[c * 64 + j % 64];
-                mm_dtheta(w, X, Y, (double)rho[pix], g.x, g.y, d);
+                mm_dtheta(w, X, Y, (double)rho_f[pix], g.x, g.y, d);
                 for (int c = 0; c < 6; ++c) red[c * 64 + j % 64] = d[c];
             }
         }
-        for (int c = 0; c < 6; ++c) part[(size_t)tile * 12 + 6 + c] = mm_block_sum(red + c * 64, 64);
+        for (int c = 0; c < 6; ++c) part[(size_t)b * 12 + 6 + c] = mm_block_sum(red + c * 64, 64);
     }
-    /* finalize (256 threads) */
-    for (int c = 0; c < 6; ++c) {
-        memset(red, 0, sizeof(double) * 256);
-        for (int j = 0; j < 2 * nt; ++j) red[j % 256] += part[(size_t)j * 6 + c];
-        dtheta_out[c] = (float)(gl * mm_block_sum(red, 256));
-    }
+    /* finalize per flow set (256 threads) */
+    for (int f = 0; f < F; ++f)
+        for (int c = 0; c < 6; ++c) {
+            memset(red, 0, sizeof(double) * 256);
+            const double* pf = part + (size_t)f * nt * 12;
+            for (int j = 0; j < 2 * nt; ++j) red[j % 256] += pf[(size_t)j * 6 + c];
+            dtheta_out[f * 6 + c] = (float)(gl * mm_block_sum(red, 256));
+        }
     free(cnt); free(rec); free(halo); free(border); free(part); free(lds); free(red); free(S.img);
     return MM_OK;
 }

@@ -32,17 +32,18 @@ class CMError(RuntimeError):
 
 
 class WindowDesc(ctypes.Structure):
-    """cm_window_desc: sensor, intrinsics, reference times, mode, eps."""
+    """cm_window_desc: sensor, intrinsics, reference times, mode, eps, flow sets."""
 
     _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
                 ("fx", ctypes.c_float), ("fy", ctypes.c_float),
                 ("cx", ctypes.c_float), ("cy", ctypes.c_float),
                 ("n_refs", ctypes.c_int32), ("refs", ctypes.c_float * CM_MAX_REFS),
-                ("mode", ctypes.c_int32), ("eps", ctypes.c_float)]
+                ("mode", ctypes.c_int32), ("eps", ctypes.c_float), ("n_flows", ctypes.c_int32)]
 
     @classmethod
     def make(cls, width: int, height: int, fx: float, fy: float, cx: float, cy: float,
-             refs: Sequence[float], mode: int = CM_MODE_ATOMIC, eps: float = 1e-9) -> "WindowDesc":
+             refs: Sequence[float], mode: int = CM_MODE_ATOMIC, eps: float = 1e-9,
+             n_flows: int = 1) -> "WindowDesc":
         refs = [float(r) for r in refs]
         if not 1 <= len(refs) <= CM_MAX_REFS:
             raise ValueError(f"need 1..{CM_MAX_REFS} reference times, got {len(refs)}")
@@ -54,17 +55,26 @@ class WindowDesc(ctypes.Structure):
             d.refs[i] = r
         d.mode = int(mode)
         d.eps = eps
+        d.n_flows = int(n_flows)
         return d
 
     @classmethod
     def from_window(cls, win, mode: int = CM_MODE_ATOMIC) -> "WindowDesc":
-        """From an object with width, height, fx, fy, cx, cy, refs, eps."""
+        """From an object with width, height, fx, fy, cx, cy, refs, eps, rho
+        ([H, W] for one flow, [F, H, W] for F flow sets)."""
+        rho = getattr(win, "rho", None)
+        F = 1 if rho is None or len(getattr(rho, "shape", ())) != 3 else int(rho.shape[0])
         return cls.make(win.width, win.height, win.fx, win.fy, win.cx, win.cy, list(win.refs),
-                        mode, getattr(win, "eps", 1e-9))
+                        mode, getattr(win, "eps", 1e-9), F)
 
     @property
     def R(self) -> int:
         return int(self.n_refs)
+
+    @property
+    def F(self) -> int:
+        """Flow sets (inverse-depth images and ego-motion vectors)."""
+        return max(1, int(self.n_flows))
 
 
 _lib = None
@@ -110,6 +120,8 @@ def load() -> ctypes.CDLL:
         lib.cm_batch_state_bytes.restype = ctypes.c_size_t
         lib.cm_batch_offsets.argtypes = [P, P, P]
         lib.cm_batch_offsets.restype = ctypes.c_int
+        lib.cm_batch_flow_offsets.argtypes = [P, P]
+        lib.cm_batch_flow_offsets.restype = ctypes.c_int
         lib.cm_batch_set_graph.argtypes = [P, ctypes.c_int]
         lib.cm_batch_set_graph.restype = ctypes.c_int
         lib.cm_loss_forward_batched.argtypes = [P, P, P, P, P, P, P, P, P, P]
@@ -180,12 +192,14 @@ def _check_events(x, y, t, p):
 
 
 def _check_params(desc, rho, ego):
-    if rho.dtype != torch.float32 or rho.numel() != desc.width * desc.height or \
+    F = desc.F
+    if rho.dtype != torch.float32 or rho.numel() != F * desc.width * desc.height or \
             not rho.is_contiguous() or not rho.is_cuda:
         raise ValueError(f"inv_depth: need contiguous float32 GPU tensor of "
-                         f"{desc.height}x{desc.width} elements")
-    if ego.dtype != torch.float32 or ego.numel() != 6 or not ego.is_contiguous() or not ego.is_cuda:
-        raise ValueError("ego: need contiguous float32 GPU tensor of 6 elements")
+                         f"{F}x{desc.height}x{desc.width} elements")
+    if ego.dtype != torch.float32 or ego.numel() != 6 * F or not ego.is_contiguous() or \
+            not ego.is_cuda:
+        raise ValueError(f"ego: need contiguous float32 GPU tensor of {6 * F} elements")
 
 
 def forward(desc: WindowDesc, x, y, t, p, rho, ego, state: Optional[torch.Tensor] = None,
@@ -221,7 +235,7 @@ def backward(desc: WindowDesc, x, y, t, p, rho, ego, state, grad_loss,
     if grad_rho is None:
         grad_rho = torch.empty_like(rho)
     if grad_ego is None:
-        grad_ego = torch.empty(6, dtype=torch.float32, device=dev)
+        grad_ego = torch.empty_like(ego)
     lib = load()
     st = lib.cm_loss_backward(handle(dev.index), ctypes.byref(desc), _ptr(x), _ptr(y), _ptr(t),
                               _ptr(p), n, _ptr(rho), _ptr(ego), _ptr(state), _ptr(gl),
@@ -245,7 +259,8 @@ class Batch:
 
     Events of all windows are packed in flat arrays (window w at
     event_offsets[w]:event_offsets[w+1]), inverse depth and its gradient at
-    pixel_offsets; ego / grad ego are [n, 6], loss / grad_loss [n]."""
+    pixel_offsets (F images per window); ego / grad ego hold 6 floats per flow
+    set, window w's at 6 * set_offsets[w]; loss / grad_loss are [n]."""
 
     def __init__(self, descs: Sequence[WindowDesc], n_events: Sequence[int], device: int = 0,
                  graph: bool = False):
@@ -263,8 +278,11 @@ class Batch:
         ev = (ctypes.c_int64 * (n + 1))()
         px = (ctypes.c_int64 * (n + 1))()
         _check(lib.cm_batch_offsets(self._b, ev, px), "cm_batch_offsets")
+        so = (ctypes.c_int64 * (n + 1))()
+        _check(lib.cm_batch_flow_offsets(self._b, so), "cm_batch_flow_offsets")
         self.event_offsets = list(ev)
         self.pixel_offsets = list(px)
+        self.set_offsets = list(so)
         self.set_graph(graph)
 
     def set_graph(self, enable: bool):
@@ -291,8 +309,9 @@ class Batch:
         if rho.dtype != torch.float32 or rho.numel() != self.pixel_offsets[-1] or \
                 not rho.is_contiguous() or not rho.is_cuda:
             raise ValueError(f"inv_depth: need {self.pixel_offsets[-1]} contiguous float32 values")
-        if ego.dtype != torch.float32 or ego.numel() != 6 * self.n or not ego.is_contiguous():
-            raise ValueError(f"ego: need {6 * self.n} contiguous float32 values")
+        ne = 6 * self.set_offsets[-1]
+        if ego.dtype != torch.float32 or ego.numel() != ne or not ego.is_contiguous():
+            raise ValueError(f"ego: need {ne} contiguous float32 values")
 
     def forward(self, x, y, t, p, rho, ego, state=None, loss=None):
         self._check_flat(x, y, t, p, rho, ego)

@@ -30,6 +30,15 @@ constexpr int64_t kTiledMinRecords = 1 << 17;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Segments between consecutive knots {0, 1} U refs (refs validated first).
+int n_segments(const cm_window_desc* d)
+{
+    int nk = d->n_refs;
+    if (d->refs[0] > 0.f) ++nk;
+    if (d->refs[d->n_refs - 1] < 1.f) ++nk;
+    return nk - 1;
+}
+
 bool desc_valid(const cm_window_desc* d)
 {
     if (!d) return false;
@@ -44,8 +53,12 @@ bool desc_valid(const cm_window_desc* d)
     }
     if (d->mode != CM_MODE_ATOMIC && d->mode != CM_MODE_DETERMINISTIC) return false;
     if (!(std::isfinite(d->eps) && d->eps > 0.f)) return false;
+    if (d->n_flows != 0 && d->n_flows != 1 && d->n_flows != n_segments(d)) return false;
     return true;
 }
+
+// Flow sets of a window: 1 (n_flows 0 or 1) or one per segment.
+int flows_of(const cm_window_desc* d) { return d->n_flows > 1 ? d->n_flows : 1; }
 
 WinParams params_of(const cm_window_desc* d)
 {
@@ -68,6 +81,16 @@ WinParams params_of(const cm_window_desc* d)
     P.eps = d->eps;
     P.two_over_R = 2.0 / (double)d->n_refs;
     for (int r = 0; r < d->n_refs; ++r) P.refs[r] = d->refs[r];
+    // Flow set of the step into reference r: forward steps cross the segment
+    // that ends at r's knot, backward steps the one that starts there.
+    P.F = flows_of(d);
+    const int k0 = d->refs[0] > 0.f ? 1 : 0;      // knot index of reference 0
+    for (int r = 0; r < d->n_refs; ++r) {
+        // (a forward step into the first knot or a backward step into the
+        // last cannot happen; the clamp only keeps those entries in range)
+        P.sf[r] = (int8_t)(P.F > 1 ? std::max(0, k0 + r - 1) : 0);
+        P.sb[r] = (int8_t)(P.F > 1 ? std::min(P.F - 1, k0 + r) : 0);
+    }
     return P;
 }
 
@@ -84,7 +107,7 @@ Layout layout_of(const cm_window_desc* d, int64_t n)
     L.img_bytes = (size_t)32 * d->n_refs * d->width * d->height;
     L.hdr_off = align_up(L.img_bytes, kAlign);
     L.scratch_off = L.hdr_off + align_up(sizeof(StateHeader), kAlign);
-    L.meta_off = L.scratch_off + align_up(cm::kScratchDoubles * sizeof(double), kAlign);
+    L.meta_off = L.scratch_off + align_up(cm::scratch_doubles(flows_of(d)) * sizeof(double), kAlign);
     L.ws_off = L.meta_off + align_up(sizeof(WinMeta), kAlign);
     const WinParams P = params_of(d);
     L.tiled = n > 0 && cm::tiled_supported(P, n);
@@ -156,7 +179,7 @@ cm_status status_of(hipError_t e) { return e == hipSuccess ? CM_OK : CM_ERR_HIP;
 struct cm_batch_s {
     cm_handle h = nullptr;
     BatchPlanHost B;
-    std::vector<int64_t> ev_offsets, pix_offsets;
+    std::vector<int64_t> ev_offsets, pix_offsets, set_offsets;
     WinMeta* d_meta = nullptr;
     size_t img_off = 0, hdr_off = 0, meta_off = 0, ws_off = 0, total = 0;
     bool use_graph = false;
@@ -396,12 +419,15 @@ cm_status cm_batch_create(cm_handle h, int32_t n_windows, const cm_window_desc* 
                           descs[0].mode == CM_MODE_DETERMINISTIC);
     b->ev_offsets.resize(n_windows + 1);
     b->pix_offsets.resize(n_windows + 1);
+    b->set_offsets.resize(n_windows + 1);
     for (int w = 0; w < n_windows; ++w) {
         b->ev_offsets[w] = b->B.meta[w].ev_off;
         b->pix_offsets[w] = b->B.meta[w].pix_off;
+        b->set_offsets[w] = b->B.meta[w].ego_off;
     }
     b->ev_offsets[n_windows] = b->B.n_events;
     b->pix_offsets[n_windows] = b->B.n_pixels;
+    b->set_offsets[n_windows] = b->B.n_sets;
     b->img_off = 0;
     b->hdr_off = align_up((size_t)b->B.img_elems * 16, kAlign);
     b->meta_off = b->hdr_off + align_up((size_t)n_windows * sizeof(StateHeader), kAlign);
@@ -427,6 +453,13 @@ cm_status cm_batch_offsets(cm_batch b, int64_t* event_offsets, int64_t* pixel_of
     const size_t n = b->ev_offsets.size();
     if (event_offsets) std::memcpy(event_offsets, b->ev_offsets.data(), n * sizeof(int64_t));
     if (pixel_offsets) std::memcpy(pixel_offsets, b->pix_offsets.data(), n * sizeof(int64_t));
+    return CM_OK;
+}
+
+cm_status cm_batch_flow_offsets(cm_batch b, int64_t* set_offsets)
+{
+    if (!b || !set_offsets) return CM_ERR_INVALID_ARG;
+    std::memcpy(set_offsets, b->set_offsets.data(), b->set_offsets.size() * sizeof(int64_t));
     return CM_OK;
 }
 

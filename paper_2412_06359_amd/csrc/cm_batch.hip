@@ -130,19 +130,21 @@ __device__ __forceinline__ void load_ref_table(const WinParams& P, const StateHe
         const int r = threadIdx.x;
         rt.t[r] = P.refs[r];
         rt.coef[r] = (hdr && r < P.R) ? P.two_over_R / (hdr->nact[r] + P.eps) : 0.0;
+        rt.sf[r] = P.sf[r];
+        rt.sb[r] = P.sb[r];
     }
 }
 
-template <int RM, int NT>
+template <int RM, int NT, bool MF>
 __global__ __launch_bounds__(NT) void fwd_count_kernel(
-    const WinMeta* __restrict__ meta, int nw, const float* __restrict__ ex,
+    const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const float* __restrict__ ex,
     const float* __restrict__ ey, const float* __restrict__ et, const float* __restrict__ rho,
     const float* __restrict__ ego, uint32_t* __restrict__ hist, StateHeader* __restrict__ hdrs)
 {
     extern __shared__ uint32_t lh[];
     __shared__ uint32_t cnt_lds;
     const int64_t blk = xcd_block();
-    const int w = window_of_block(meta, nw, blk);
+    const int w = win_of[blk];
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
     const int64_t lb = blk - meta[w].blk_off;
@@ -151,8 +153,9 @@ __global__ __launch_bounds__(NT) void fwd_count_kernel(
     for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) lh[i] = 0;
     if (threadIdx.x == 0) cnt_lds = 0;
     load_ref_table(P, nullptr, rt);
+    __shared__ Motion mt[kMaxFlows];
+    const Flows<MF> u = make_flows<MF>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off, mt);
     __syncthreads();
-    const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
     const int64_t base = lb * NT * G.ept;
     uint32_t cnt = 0;
     for (int e = 0; e < G.ept; ++e) {
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(NT) void fwd_count_kernel(
         double vx[RM], vy[RM];
         int vr[RM];
         Visits v;
-        if (!warp_visits<RM>(P, u, rt, ex[ev0 + k], ey[ev0 + k], et[ev0 + k], vx, vy, vr, v))
+        if (!warp_visits<RM, MF>(P, u, rt, ex[ev0 + k], ey[ev0 + k], et[ev0 + k], vx, vy, vr, v))
             continue;
         ++cnt;
 #pragma unroll
@@ -179,15 +182,15 @@ __global__ __launch_bounds__(NT) void fwd_count_kernel(
 // Column scan of each window's block x bin histogram in two levels: blocks
 // are grouped in chunks of kScanChunk rows; chunk sums, then a per-bin scan
 // over chunks, then the per-block offsets inside each chunk.  `bwd` selects
-// the backward bin space (one bin per tile).
+// the backward bin space (one bin per flow set and tile).
 struct BinSpace {
     __device__ __forceinline__ static int nbins(const WinMeta& m, bool bwd)
     {
-        return bwd ? m.G.ntiles : m.G.nbins;
+        return bwd ? m.G.nbins_b : m.G.nbins;
     }
     __device__ __forceinline__ static int64_t bin_off(const WinMeta& m, bool bwd)
     {
-        return bwd ? m.tile_off : m.bin_off;
+        return bwd ? m.bbin_off : m.bin_off;
     }
     __device__ __forceinline__ static int64_t cell_off(const WinMeta& m, bool bwd)
     {
@@ -290,9 +293,9 @@ __global__ __launch_bounds__(256) void offsets_kernel(const WinMeta* __restrict_
     }
 }
 
-template <int RM, int NT, bool DET>
+template <int RM, int NT, bool DET, bool MF>
 __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
-    const WinMeta* __restrict__ meta, int nw, const float* __restrict__ ex,
+    const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const float* __restrict__ ex,
     const float* __restrict__ ey, const float* __restrict__ et, const int8_t* __restrict__ ep,
     const float* __restrict__ rho, const float* __restrict__ ego,
     const uint32_t* __restrict__ offs, const uint32_t* __restrict__ start,
@@ -300,7 +303,7 @@ __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
 {
     extern __shared__ uint32_t lh[];
     const int64_t blk = xcd_block();
-    const int w = window_of_block(meta, nw, blk);
+    const int w = win_of[blk];
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
     const int64_t lb = blk - meta[w].blk_off;
@@ -309,12 +312,13 @@ __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
     __shared__ RefTable rt;
     for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) lh[i] = row[i];
     load_ref_table(P, nullptr, rt);
+    __shared__ Motion mt[kMaxFlows];
+    const Flows<MF> u = make_flows<MF>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off, mt);
     __syncthreads();
     // the window's reference-0 records come first among its records: their
     // slots minus this offset number its valid events
     const uint32_t r0 = start[meta[w].bin_off];
     SrcRec* wsrc = src + ev0;
-    const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
     const int64_t base = lb * NT * G.ept;
     for (int e = 0; e < G.ept; ++e) {
         const int64_t k = base + (int64_t)e * NT + threadIdx.x;
@@ -323,7 +327,7 @@ __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
         int vr[RM];
         Visits v;
         const float xk = ex[ev0 + k], yk = ey[ev0 + k], tk = et[ev0 + k];
-        if (!warp_visits<RM>(P, u, rt, xk, yk, tk, vx, vy, vr, v)) continue;
+        if (!warp_visits<RM, MF>(P, u, rt, xk, yk, tk, vx, vy, vr, v)) continue;
         const float ts = ep[ev0 + k] > 0 ? fabsf(tk) : -fabsf(tk);   // sign bit = polarity
 #pragma unroll
         for (int j = 0; j < RM; ++j) {
@@ -380,13 +384,30 @@ __device__ __forceinline__ int window_of_bin(const WinMeta* meta, int nw, int64_
     return find_window(meta, nw, gbin, [](const WinMeta& m) { return m.bin_off; });
 }
 
-__device__ __forceinline__ int window_of_tile(const WinMeta* meta, int nw, int64_t gtile)
+__device__ __forceinline__ int window_of_bbin(const WinMeta* meta, int nw, int64_t gbb)
 {
-    return find_window(meta, nw, gtile, [](const WinMeta& m) { return m.tile_off; });
+    return find_window(meta, nw, gbb, [](const WinMeta& m) { return m.bbin_off; });
+}
+
+// The window of every event block, forward bin and backward bin of the
+// batch, one binary search per entry per call instead of one chain of
+// dependent loads at the start of every workgroup.
+// tab = [blocks | forward bins | backward bins].
+__global__ __launch_bounds__(256) void window_table_kernel(const WinMeta* __restrict__ meta,
+                                                           int nw, int64_t nblk, int64_t nbin,
+                                                           int64_t nbb, int* __restrict__ tab)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nblk)
+        tab[i] = window_of_block(meta, nw, i);
+    else if (i < nblk + nbin)
+        tab[i] = window_of_bin(meta, nw, i - nblk);
+    else if (i < nblk + nbin + nbb)
+        tab[i] = window_of_bbin(meta, nw, i - nblk - nbin);
 }
 
 template <bool DET>
-__global__ __launch_bounds__(256) void fwd_tile_kernel(const WinMeta* __restrict__ meta, int nw,
+__global__ __launch_bounds__(256) void fwd_tile_kernel(const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of,
                                                        const SplatRec* __restrict__ rec,
                                                        const uint32_t* __restrict__ start,
                                                        double2* __restrict__ img_base,
@@ -396,7 +417,7 @@ __global__ __launch_bounds__(256) void fwd_tile_kernel(const WinMeta* __restrict
     __shared__ double2 lds[2 * TLW * TLH];
     __shared__ double red[16];
     const int64_t gbin = blockIdx.x;
-    const int w = window_of_bin(meta, nw, gbin);
+    const int w = win_of[gbin];
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
     int r, tx, ty;
@@ -477,14 +498,14 @@ __global__ __launch_bounds__(256) void fwd_tile_kernel(const WinMeta* __restrict
 
 // Column 0 and row 0 of each tile: add the halos of the left, top and
 // top-left tiles (in that order), store, and reduce those pixels.
-__global__ __launch_bounds__(64) void fwd_merge_kernel(const WinMeta* __restrict__ meta, int nw,
+__global__ __launch_bounds__(64) void fwd_merge_kernel(const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of,
                                                        double2* __restrict__ img_base,
                                                        const double2* __restrict__ halo,
                                                        double* __restrict__ part)
 {
     __shared__ double red[16];
     const int64_t gbin = blockIdx.x;
-    const int w = window_of_bin(meta, nw, gbin);
+    const int w = win_of[gbin];
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
     int r, tx, ty;
@@ -573,19 +594,36 @@ __global__ __launch_bounds__(256) void fwd_finalize_kernel(const WinMeta* __rest
 // event, so their contributions share one record.
 // ---------------------------------------------------------------------------
 
-// The flow-sampling positions of an event's warp steps: the previous visit's
-// position for every real step that does not start at the event, then the
-// event once if it takes any step (both sweeps' first steps share its record).
-template <int RM, typename F>
-__device__ __forceinline__ void for_each_sample(const WinParams& P, const Visits& v,
-                                                const double (&vx)[RM], const double (&vy)[RM],
+// The flow-sampling positions of an event's warp steps, with the flow set of
+// each step: the previous visit's position for every real step that does not
+// start at the event, and the event for the steps that do.  A window with one
+// flow set has both sweeps' first steps share one event record; with several,
+// each step has its own record (its set may differ).  Which of the two is
+// decided per window, so a one-flow window gives the same records in any
+// batch.
+template <int RM, bool MF, typename F>
+__device__ __forceinline__ void for_each_sample(const WinParams& P, const RefTable& rt,
+                                                const Visits& v, const double (&vx)[RM],
+                                                const double (&vy)[RM], const int (&vr)[RM],
                                                 double x0, double y0, F&& fn)
 {
     const int jf = v.eq ? 1 : 0;
+    if (MF && P.F > 1) {
 #pragma unroll
-    for (int j = 1; j < RM; ++j)
-        if (j < P.R && j != jf && j != v.nf) fn(vx[j - 1], vy[j - 1]);
-    if (P.R - jf > 0) fn(x0, y0);
+        for (int j = 0; j < RM; ++j) {
+            if (j < P.R && !(v.eq && j == 0)) {
+                const bool first = (j == jf && j < v.nf) || (j == v.nf);
+                const int set = j < v.nf ? rt.sf[vr[j]] : rt.sb[vr[j]];
+                const int jp = j > 0 ? j - 1 : 0;
+                fn(first ? x0 : vx[jp], first ? y0 : vy[jp], set);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 1; j < RM; ++j)
+            if (j < P.R && j != jf && j != v.nf) fn(vx[j - 1], vy[j - 1], 0);
+        if (P.R - jf > 0) fn(x0, y0, 0);
+    }
 }
 
 // The backward's event blocks run over the source records (valid events in
@@ -594,15 +632,15 @@ __device__ __forceinline__ void for_each_sample(const WinParams& P, const Visits
 // positions [(e * nblocks + b) * NT, +NT).  The blocks in flight then work on
 // one compact stretch of the source order, that is on neighbouring tiles, and
 // their image and inverse-depth gathers share the L2.
-template <int RM, int NT>
+template <int RM, int NT, bool MF>
 __global__ __launch_bounds__(NT) void bwd_count_kernel(
-    const WinMeta* __restrict__ meta, int nw, const SrcRec* __restrict__ src,
+    const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const SrcRec* __restrict__ src,
     const float* __restrict__ rho, const float* __restrict__ ego,
     const StateHeader* __restrict__ hdrs, uint32_t* __restrict__ hist)
 {
     extern __shared__ uint32_t lh[];
     const int64_t blk = xcd_block();
-    const int w = window_of_block(meta, nw, blk);
+    const int w = win_of[blk];
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
     const int64_t lb = blk - meta[w].blk_off;
@@ -610,10 +648,11 @@ __global__ __launch_bounds__(NT) void bwd_count_kernel(
         (hdrs[w].flags & kHdrSourceRecords) ? (int64_t)hdrs[w].n_valid : 0;
     const SrcRec* wsrc = src + meta[w].ev_off;
     __shared__ RefTable rt;
-    for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x) lh[i] = 0;
+    for (int i = threadIdx.x; i < G.nbins_b; i += blockDim.x) lh[i] = 0;
     load_ref_table(P, nullptr, rt);
+    __shared__ Motion mt[kMaxFlows];
+    const Flows<MF> u = make_flows<MF>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off, mt);
     __syncthreads();
-    const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
     for (int e = 0; e < G.ept; ++e) {
         const int64_t i = ((int64_t)e * G.nblocks + lb) * NT + threadIdx.x;
         if (i >= nv) break;
@@ -622,43 +661,45 @@ __global__ __launch_bounds__(NT) void bwd_count_kernel(
         Visits v;
         const SrcRec q = load_nt(wsrc + i);
         const double x0 = q.x0, y0 = q.y0, tk = fabsf(q.ts);
-        if (!warp_visits<RM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
-        for_each_sample<RM>(P, v, vx, vy, x0, y0, [&](double X, double Y) {
-            atomicAdd(&lh[tile_index(G, make_taps(P, X, Y))], 1u);
+        if (!warp_visits<RM, MF>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
+        for_each_sample<RM, MF>(P, rt, v, vx, vy, vr, x0, y0, [&](double X, double Y, int set) {
+            atomicAdd(&lh[set * G.ntiles + tile_index(G, make_taps(P, X, Y))], 1u);
         });
     }
     __syncthreads();
-    uint32_t* row = hist + meta[w].hist_off + lb * G.ntiles;
-    for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x) row[i] = lh[i];
+    uint32_t* row = hist + meta[w].hist_off + lb * G.nbins_b;
+    for (int i = threadIdx.x; i < G.nbins_b; i += blockDim.x) row[i] = lh[i];
 }
 
-template <int RM, int NT, bool DET>
+template <int RM, int NT, bool DET, bool MF>
 __global__ __launch_bounds__(NT) void bwd_sweep_kernel(
-    const WinMeta* __restrict__ meta, int nw, const SrcRec* __restrict__ src,
+    const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const SrcRec* __restrict__ src,
     const float* __restrict__ rho, const float* __restrict__ ego,
     const double2* __restrict__ img_base, const StateHeader* __restrict__ hdrs,
     const uint32_t* __restrict__ offs, GradRec* __restrict__ rec)
 {
     extern __shared__ uint32_t lh[];
     const int64_t blk = xcd_block();
-    const int w = window_of_block(meta, nw, blk);
+    const int w = win_of[blk];
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
     const int64_t lb = blk - meta[w].blk_off;
     const int64_t nv =
         (hdrs[w].flags & kHdrSourceRecords) ? (int64_t)hdrs[w].n_valid : 0;
     const SrcRec* wsrc = src + meta[w].ev_off;
-    const uint32_t* row = offs + meta[w].hist_off + lb * G.ntiles;
-    for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x) lh[i] = row[i];
+    const uint32_t* row = offs + meta[w].hist_off + lb * G.nbins_b;
+    for (int i = threadIdx.x; i < G.nbins_b; i += blockDim.x) lh[i] = row[i];
     __syncthreads();
     __shared__ RefTable rt;
     load_ref_table(P, hdrs + w, rt);
+    __shared__ Motion mt[kMaxFlows];
+    const Flows<MF> u = make_flows<MF>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off, mt);
     __syncthreads();
-    const FlowSrc u = flow_src(P, rho + meta[w].pix_off, ego + 6 * w);
     const double2* img = img_base + meta[w].img_off;
+    const bool split = MF && P.F > 1;    // one record per first step (see for_each_sample)
 
-    auto emit = [&](double X, double Y, double gx, double gy) {
-        const int bin = tile_index(G, make_taps(P, X, Y));
+    auto emit = [&](double X, double Y, double gx, double gy, int set) {
+        const int bin = set * G.ntiles + tile_index(G, make_taps(P, X, Y));
         const uint32_t slot = DET ? stable_slot(lh, bin) : atomicAdd(&lh[bin], 1u);
         GradRec q;
         q.X = X;
@@ -676,7 +717,7 @@ __global__ __launch_bounds__(NT) void bwd_sweep_kernel(
         Visits v;
         const SrcRec q = load_nt(wsrc + i);
         const double x0 = q.x0, y0 = q.y0, tk = fabsf(q.ts);
-        if (!warp_visits<RM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
+        if (!warp_visits<RM, MF>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
         const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
         const double2* planes = img + (size_t)pol * P.HW;
         double g0x = 0.0, g0y = 0.0;     // contributions sampled at the event position
@@ -694,20 +735,24 @@ __global__ __launch_bounds__(NT) void bwd_sweep_kernel(
                     direct_term(P, planes + (size_t)r * 2 * P.HW, rt.coef[r],
                                 1.0 - fabs(rt.t[r] - tk), vx[j], vy[j], Lx, Ly);
                     if (s.first) {
-                        g0x += s.dt * Lx;
-                        g0y += s.dt * Ly;
+                        if (split) {
+                            emit(x0, y0, s.dt * Lx, s.dt * Ly, s.set);
+                        } else {
+                            g0x += s.dt * Lx;
+                            g0y += s.dt * Ly;
+                        }
                     } else {
                         const double X = vx[j > 0 ? j - 1 : 0], Y = vy[j > 0 ? j - 1 : 0];
-                        emit(X, Y, s.dt * Lx, s.dt * Ly);
+                        emit(X, Y, s.dt * Lx, s.dt * Ly, s.set);
                         double jx, jy;
-                        jacobian_t(P, u, X, Y, Lx, Ly, jx, jy);
+                        jacobian_t(P, u.at(s.set), X, Y, Lx, Ly, jx, jy);
                         Lx += s.dt * jx;
                         Ly += s.dt * jy;
                     }
                 }
             }
         }
-        if (P.R - (v.eq ? 1 : 0) > 0) emit(x0, y0, g0x, g0y);
+        if (!split && P.R - (v.eq ? 1 : 0) > 0) emit(x0, y0, g0x, g0y, 0);
     }
 }
 
@@ -716,7 +761,7 @@ __global__ __launch_bounds__(NT) void bwd_sweep_kernel(
 // and the halo go to buffers for the merge.
 template <bool DET>
 __global__ __launch_bounds__(256) void bwd_tile_kernel(
-    const WinMeta* __restrict__ meta, int nw, const GradRec* __restrict__ rec,
+    const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const GradRec* __restrict__ rec,
     const uint32_t* __restrict__ start, const float* __restrict__ rho,
     const float* __restrict__ ego, const float* __restrict__ grad_loss,
     float* __restrict__ drho, double2* __restrict__ halo, double2* __restrict__ border,
@@ -724,11 +769,12 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(
 {
     __shared__ double2 lds[TLW * TLH];
     __shared__ double red[16];
-    const int64_t gtile = blockIdx.x;
-    const int w = window_of_tile(meta, nw, gtile);
+    const int64_t gtile = blockIdx.x;       // backward bin: (flow set, tile) of a window
+    const int w = win_of[gtile];
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
-    const int tile = (int)(gtile - meta[w].tile_off);
+    const int lbin = (int)(gtile - meta[w].bbin_off);
+    const int set = lbin / G.ntiles, tile = lbin - set * G.ntiles;
     const int ty = tile / G.ntx, tx = tile - ty * G.ntx;
     const int xo = tx * TW, yo = ty * TH;
     for (int i = threadIdx.x; i < TLW * TLH; i += blockDim.x) lds[i] = make_double2(0.0, 0.0);
@@ -768,9 +814,9 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(
         }
     }
     __syncthreads();
-    const Motion m = load_motion(P, ego + 6 * w);
-    const float* rho_w = rho + meta[w].pix_off;
-    float* drho_w = drho + meta[w].pix_off;
+    const Motion m = load_motion(P, ego + 6 * (meta[w].ego_off + set));
+    const float* rho_w = rho + meta[w].pix_off + (size_t)set * P.HW;
+    float* drho_w = drho + meta[w].pix_off + (size_t)set * P.HW;
     const double gl = (double)grad_loss[w];
     double dth[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int i = threadIdx.x; i < TW * TH; i += blockDim.x) {
@@ -801,22 +847,23 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(
 }
 
 __global__ __launch_bounds__(64) void bwd_merge_kernel(
-    const WinMeta* __restrict__ meta, int nw, const float* __restrict__ rho,
+    const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const float* __restrict__ rho,
     const float* __restrict__ ego, const float* __restrict__ grad_loss,
     float* __restrict__ drho, const double2* __restrict__ halo,
     const double2* __restrict__ border, double* __restrict__ part)
 {
     __shared__ double red[16];
-    const int64_t gtile = blockIdx.x;
-    const int w = window_of_tile(meta, nw, gtile);
+    const int64_t gtile = blockIdx.x;       // backward bin: (flow set, tile) of a window
+    const int w = win_of[gtile];
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
-    const int tile = (int)(gtile - meta[w].tile_off);
+    const int lbin = (int)(gtile - meta[w].bbin_off);
+    const int set = lbin / G.ntiles, tile = lbin - set * G.ntiles;
     const int ty = tile / G.ntx, tx = tile - ty * G.ntx;
     const int xo = tx * TW, yo = ty * TH;
-    const Motion m = load_motion(P, ego + 6 * w);
-    const float* rho_w = rho + meta[w].pix_off;
-    float* drho_w = drho + meta[w].pix_off;
+    const Motion m = load_motion(P, ego + 6 * (meta[w].ego_off + set));
+    const float* rho_w = rho + meta[w].pix_off + (size_t)set * P.HW;
+    float* drho_w = drho + meta[w].pix_off + (size_t)set * P.HW;
     const double gl = (double)grad_loss[w];
     double dth[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int j = threadIdx.x; j < NBORDER; j += blockDim.x) {
@@ -853,7 +900,8 @@ __global__ __launch_bounds__(64) void bwd_merge_kernel(
     }
 }
 
-// One block per window: fixed-order sum of its tiles' d theta partials.
+// One block per window: fixed-order sum of its tiles' d theta partials, per
+// flow set.
 __global__ __launch_bounds__(256) void bwd_finalize_kernel(const WinMeta* __restrict__ meta,
                                                            const double* __restrict__ part,
                                                            const StateHeader* __restrict__ hdrs,
@@ -863,13 +911,15 @@ __global__ __launch_bounds__(256) void bwd_finalize_kernel(const WinMeta* __rest
     __shared__ double red[16];
     const int w = blockIdx.x;
     const int ntiles = meta[w].G.ntiles;
-    const double* pw = part + meta[w].tile_off * 12;
     const double gl = (hdrs[w].flags & kHdrSourceRecords) ? (double)grad_loss[w] : (double)NAN;
-    for (int c = 0; c < 6; ++c) {
-        double s = 0.0;
-        for (int j = threadIdx.x; j < 2 * ntiles; j += blockDim.x) s += pw[(size_t)j * 6 + c];
-        s = block_sum(s, red);
-        if (threadIdx.x == 0) grad_ego[w * 6 + c] = (float)(gl * s);
+    for (int f = 0; f < meta[w].P.F; ++f) {
+        const double* pw = part + (meta[w].bbin_off + (int64_t)f * ntiles) * 12;
+        for (int c = 0; c < 6; ++c) {
+            double s = 0.0;
+            for (int j = threadIdx.x; j < 2 * ntiles; j += blockDim.x) s += pw[(size_t)j * 6 + c];
+            s = block_sum(s, red);
+            if (threadIdx.x == 0) grad_ego[(meta[w].ego_off + f) * 6 + c] = (float)(gl * s);
+        }
     }
 }
 
@@ -911,6 +961,7 @@ TileGeom tile_geom(const WinParams& P, int64_t n, bool det)
     G.nty = (P.H + TH - 1) / TH;
     G.ntiles = G.ntx * G.nty;
     G.nbins = P.R * G.ntiles;
+    G.nbins_b = P.F * G.ntiles;
     // enough blocks to fill the chip, few enough to keep the histogram matrix small
     const int nt = bin_threads(det);
     const int64_t ept = n / ((int64_t)nt * 1024);
@@ -923,7 +974,7 @@ TileGeom tile_geom(const WinParams& P, int64_t n, bool det)
 bool tiled_supported(const WinParams& P, int64_t n)
 {
     const TileGeom G = tile_geom(P, n, false);
-    return G.nbins <= kMaxBins && n * (int64_t)P.R < ((int64_t)1 << 31);
+    return G.nbins <= kMaxBins && G.nbins_b <= kMaxBins && n * (int64_t)P.R < ((int64_t)1 << 31);
 }
 
 BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int nw, bool det)
@@ -932,9 +983,10 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     B.nw = nw;
     B.det = det;
     B.meta.resize(nw);
-    int64_t ev = 0, pix = 0, img = 0, hist = 0, csum = 0, bin = 0, tile = 0, blk = 0;
+    int64_t ev = 0, pix = 0, sets = 0, img = 0, hist = 0, csum = 0, bin = 0, bbin = 0, blk = 0;
     int64_t cf = 0, cb = 0, recs = 0;
     B.max_R = 1;
+    B.max_F = 1;
     B.max_lds_bins = 1;
     for (int w = 0; w < nw; ++w) {
         WinMeta& M = B.meta[w];
@@ -945,33 +997,38 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
         M.ev_off = ev;
         M.n = n_events[w];
         M.pix_off = pix;
+        M.ego_off = sets;
         M.img_off = img;
         M.hist_off = hist;
         M.csum_off = csum;
         M.bin_off = bin;
-        M.tile_off = tile;
+        M.bbin_off = bbin;
         M.blk_off = blk;
         M.cell_off_f = cf;
         M.cell_off_b = cb;
+        const int64_t row = std::max(M.G.nbins, M.G.nbins_b);   // forward and backward rows
         ev += M.n;
-        pix += M.P.HW;
+        pix += (int64_t)M.P.F * M.P.HW;
+        sets += M.P.F;
         img += (int64_t)2 * M.P.R * M.P.HW;
-        hist += (int64_t)M.G.nblocks * M.G.nbins;
-        csum += (int64_t)M.nchunks * M.G.nbins;
+        hist += (int64_t)M.G.nblocks * row;
+        csum += (int64_t)M.nchunks * row;
         bin += M.G.nbins;
-        tile += M.G.ntiles;
+        bbin += M.G.nbins_b;
         blk += M.G.nblocks;
         cf += (int64_t)M.nchunks * M.G.nbins;
-        cb += (int64_t)M.nchunks * M.G.ntiles;
+        cb += (int64_t)M.nchunks * M.G.nbins_b;
         recs += M.n * M.P.R;
         B.max_R = std::max(B.max_R, M.P.R);
-        B.max_lds_bins = std::max(B.max_lds_bins, M.G.nbins);
+        B.max_F = std::max(B.max_F, M.P.F);
+        B.max_lds_bins = std::max(B.max_lds_bins, (int)row);
     }
     B.n_events = ev;
     B.n_pixels = pix;
+    B.n_sets = sets;
     B.img_elems = img;
     B.nbins = bin;
-    B.ntiles = tile;
+    B.nbins_b = bbin;
     B.nblocks = blk;
     B.cells_f = cf;
     B.cells_b = cb;
@@ -981,20 +1038,30 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
         off += (bytes + 255) / 256 * 256;
         return o;
     };
+    const int64_t bins = std::max(bin, bbin);
     B.ws.hist = take((size_t)hist * sizeof(uint32_t));
     B.ws.csum = take((size_t)csum * sizeof(uint32_t));
-    B.ws.totals = take((size_t)(bin + 1) * sizeof(uint32_t));
-    B.ws.start = take((size_t)(bin + 1) * sizeof(uint32_t));
-    B.ws.part = take((size_t)std::max(bin * 4, tile * 12) * sizeof(double));
-    B.ws.halo = take((size_t)std::max<int64_t>(bin * NHALO * 2, tile * (NHALO + NBORDER)) *
+    B.ws.totals = take((size_t)(bins + 1) * sizeof(uint32_t));
+    B.ws.start = take((size_t)(bins + 1) * sizeof(uint32_t));
+    B.ws.part = take((size_t)std::max(bin * 4, bbin * 12) * sizeof(double));
+    B.ws.halo = take((size_t)std::max<int64_t>(bin * NHALO * 2, bbin * (NHALO + NBORDER)) *
                      sizeof(double2));
     B.ws.records = take((size_t)recs * std::max(sizeof(SplatRec), sizeof(GradRec)));
     B.ws.src = take((size_t)ev * sizeof(SrcRec));
+    B.ws.win = take((size_t)(blk + bin + bbin) * sizeof(int));
     B.ws.total = off;
     return B;
 }
 
-template <int RM, bool DET>
+static void launch_window_table(const BatchPlanHost& B, const WinMeta* meta, int* tab,
+                                hipStream_t s)
+{
+    const int64_t n = B.nblocks + B.nbins + B.nbins_b;
+    window_table_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(meta, B.nw, B.nblocks, B.nbins,
+                                                                B.nbins_b, tab);
+}
+
+template <int RM, bool DET, bool MF>
 static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
                                    const EventPtrs& ev, const float* rho, const float* ego,
                                    float* loss, double2* img, StateHeader* hdrs, char* ws,
@@ -1009,15 +1076,19 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     double2* halo = reinterpret_cast<double2*>(ws + B.ws.halo);
     SplatRec* rec = reinterpret_cast<SplatRec*>(ws + B.ws.records);
     SrcRec* src = reinterpret_cast<SrcRec*>(ws + B.ws.src);
+    int* wtab = reinterpret_cast<int*>(ws + B.ws.win);
+    const int* win_blk = wtab;
+    const int* win_bin = wtab + B.nblocks;
     const size_t lds = (size_t)B.max_lds_bins * sizeof(uint32_t);
     {
         PhaseScope ph(prof, kPhZero, s);
         clear_headers_kernel<<<(nw + 255) / 256, 256, 0, s>>>(hdrs, nw);
+        launch_window_table(B, meta, wtab, s);
     }
     {
         PhaseScope ph(prof, kPhCount, s);
         constexpr int NT = DET ? 64 : kBinThreads;
-        fwd_count_kernel<RM, NT><<<B.nblocks, NT, lds, s>>>(meta, nw, ev.x, ev.y, ev.t, rho, ego,
+        fwd_count_kernel<RM, NT, MF><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, ev.x, ev.y, ev.t, rho, ego,
                                                             hist, hdrs);
     }
     {
@@ -1032,16 +1103,16 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     {
         PhaseScope ph(prof, kPhScatter, s);
         constexpr int NT = DET ? 64 : kBinThreads;
-        fwd_scatter_kernel<RM, NT, DET><<<B.nblocks, NT, lds, s>>>(
-            meta, nw, ev.x, ev.y, ev.t, ev.p, rho, ego, hist, start, rec, src);
+        fwd_scatter_kernel<RM, NT, DET, MF><<<B.nblocks, NT, lds, s>>>(
+            meta, nw, win_blk, ev.x, ev.y, ev.t, ev.p, rho, ego, hist, start, rec, src);
     }
     {
         PhaseScope ph(prof, kPhSplat, s);
-        fwd_tile_kernel<DET><<<(int)B.nbins, 256, 0, s>>>(meta, nw, rec, start, img, halo, part);
+        fwd_tile_kernel<DET><<<(int)B.nbins, 256, 0, s>>>(meta, nw, win_bin, rec, start, img, halo, part);
     }
     {
         PhaseScope ph(prof, kPhReduce, s);
-        fwd_merge_kernel<<<(int)B.nbins, 64, 0, s>>>(meta, nw, img, halo, part);
+        fwd_merge_kernel<<<(int)B.nbins, 64, 0, s>>>(meta, nw, win_bin, img, halo, part);
     }
     {
         PhaseScope ph(prof, kPhFinalize, s);
@@ -1054,16 +1125,18 @@ hipError_t launch_forward_batch(const BatchPlanHost& B, const WinMeta* meta, con
                                 const float* rho, const float* ego, float* loss, double2* img,
                                 StateHeader* hdrs, char* ws, hipStream_t s, Profiler* prof)
 {
-#define CM_FWD(RM) (B.det ? batch_forward_rm<RM, true>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof) \
-                     : batch_forward_rm<RM, false>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof))
+#define CM_FWD_D(RM, MF) (B.det ? batch_forward_rm<RM, true, MF>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof) \
+                            : batch_forward_rm<RM, false, MF>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof))
+#define CM_FWD(RM) (B.max_F > 1 ? CM_FWD_D(RM, true) : CM_FWD_D(RM, false))
     if (B.max_R <= 2) return CM_FWD(2);
     if (B.max_R <= 4) return CM_FWD(4);
     if (B.max_R <= 8) return CM_FWD(8);
     return CM_FWD(16);
 #undef CM_FWD
+#undef CM_FWD_D
 }
 
-template <int RM, bool DET>
+template <int RM, bool DET, bool MF>
 static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
                                     const EventPtrs& ev, const float* rho, const float* ego,
                                     const double2* img, const StateHeader* hdrs,
@@ -1077,35 +1150,39 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
     uint32_t* start = reinterpret_cast<uint32_t*>(ws + B.ws.start);
     double* part = reinterpret_cast<double*>(ws + B.ws.part);
     double2* halo = reinterpret_cast<double2*>(ws + B.ws.halo);
-    double2* border = halo + B.ntiles * NHALO;
+    double2* border = halo + B.nbins_b * NHALO;
     GradRec* rec = reinterpret_cast<GradRec*>(ws + B.ws.records);
     const SrcRec* src = reinterpret_cast<const SrcRec*>(ws + B.ws.src);
+    int* wtab = reinterpret_cast<int*>(ws + B.ws.win);
+    const int* win_blk = wtab;
+    const int* win_tile = wtab + B.nblocks + B.nbins;
     const size_t lds = (size_t)B.max_lds_bins * sizeof(uint32_t);
     {
         PhaseScope ph(prof, kPhGradCount, s);
+        launch_window_table(B, meta, wtab, s);
         constexpr int NT = DET ? 64 : kBinThreads;
-        bwd_count_kernel<RM, NT><<<B.nblocks, NT, lds, s>>>(meta, nw, src, rho, ego, hdrs, hist);
+        bwd_count_kernel<RM, NT, MF><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, src, rho, ego, hdrs, hist);
     }
     {
         PhaseScope ph(prof, kPhGradScan, s);
         const int gc = (int)((B.cells_b + 255) / 256);
         chunk_sum_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_b, 1, hist, csum);
-        chunk_scan_kernel<<<(int)((B.ntiles + 255) / 256), 256, 0, s>>>(meta, nw, B.ntiles, 1,
+        chunk_scan_kernel<<<(int)((B.nbins_b + 255) / 256), 256, 0, s>>>(meta, nw, B.nbins_b, 1,
                                                                           csum, totals);
-        scan_kernel<<<1, 1024, 0, s>>>(totals, B.ntiles, start);
+        scan_kernel<<<1, 1024, 0, s>>>(totals, B.nbins_b, start);
         offsets_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_b, 1, hist, csum, start);
     }
     {
         PhaseScope ph(prof, kPhAdjoint, s);
         constexpr int NT = DET ? 64 : kBinThreads;
-        bwd_sweep_kernel<RM, NT, DET><<<B.nblocks, NT, lds, s>>>(meta, nw, src, rho, ego, img,
+        bwd_sweep_kernel<RM, NT, DET, MF><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, src, rho, ego, img,
                                                                  hdrs, hist, rec);
     }
     {
         PhaseScope ph(prof, kPhGradTile, s);
-        bwd_tile_kernel<DET><<<(int)B.ntiles, 256, 0, s>>>(meta, nw, rec, start, rho, ego, grad_loss,
+        bwd_tile_kernel<DET><<<(int)B.nbins_b, 256, 0, s>>>(meta, nw, win_tile, rec, start, rho, ego, grad_loss,
                                                       grad_rho, halo, border, part);
-        bwd_merge_kernel<<<(int)B.ntiles, 64, 0, s>>>(meta, nw, rho, ego, grad_loss, grad_rho,
+        bwd_merge_kernel<<<(int)B.nbins_b, 64, 0, s>>>(meta, nw, win_tile, rho, ego, grad_loss, grad_rho,
                                                       halo, border, part);
     }
     {
@@ -1121,13 +1198,15 @@ hipError_t launch_backward_batch(const BatchPlanHost& B, const WinMeta* meta,
                                  const float* grad_loss, float* grad_rho, float* grad_ego,
                                  char* ws, hipStream_t s, Profiler* prof)
 {
-#define CM_BWD(RM) (B.det ? batch_backward_rm<RM, true>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof) \
-                     : batch_backward_rm<RM, false>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof))
+#define CM_BWD_D(RM, MF) (B.det ? batch_backward_rm<RM, true, MF>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof) \
+                            : batch_backward_rm<RM, false, MF>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof))
+#define CM_BWD(RM) (B.max_F > 1 ? CM_BWD_D(RM, true) : CM_BWD_D(RM, false))
     if (B.max_R <= 2) return CM_BWD(2);
     if (B.max_R <= 4) return CM_BWD(4);
     if (B.max_R <= 8) return CM_BWD(8);
     return CM_BWD(16);
 #undef CM_BWD
+#undef CM_BWD_D
 }
 
 hipError_t launch_store_meta(const WinMeta& m, WinMeta* out, hipStream_t s)

@@ -19,15 +19,26 @@ namespace cm {
 
 constexpr int kMaxRefs = 16;
 
+constexpr int kMaxFlows = kMaxRefs + 1;   // segments between knots {0, 1} U refs
+
 // Per-window constants, built on the host from the descriptor.
+//
+// Flow sets (Sec. 3.1 concatenates the flows of consecutive slices): a window
+// warps with one flow (F = 1) or with one flow per segment between
+// consecutive knots {0, 1} U refs, each from its own inverse depth
+// (rho + f HW) and ego-motion (ego + 6 f).  A step that ends at reference r
+// crosses the segment ending at r's knot when it runs forward in time
+// (set sf[r]) and the segment starting there when it runs backward (sb[r]).
 struct WinParams {
     int W, H, R, HW;
+    int F;                      // flow sets
     double cx, cy, fx, fy;
     double inv_fx, inv_fy, fx_over_fy, fy_over_fx;
     double xmax, ymax;          // W - 1, H - 1
     double eps;
     double two_over_R;
     double refs[kMaxRefs];
+    int8_t sf[kMaxRefs], sb[kMaxRefs];
 };
 
 // Ego-motion folded into the coefficients of the motion field.  With
@@ -142,6 +153,63 @@ __device__ __forceinline__ FlowSrc flow_src(const WinParams& P, const float* __r
     return f;
 }
 
+// The flows of a window, by set.  Flows<false>: one flow in registers.
+// Flows<true>: F flows, inverse depth f at rho + f HW, motion coefficients in
+// a per-block LDS table.
+template <bool MF>
+struct Flows;
+
+template <>
+struct Flows<false> {
+    FlowSrc f;
+    __device__ __forceinline__ const FlowSrc& at(int) const { return f; }
+};
+
+template <>
+struct Flows<true> {
+    const float* __restrict__ rho;
+    int HW;
+    const Motion* m;
+    __device__ __forceinline__ FlowSrc at(int s) const
+    {
+        FlowSrc f;
+        f.rho = rho + (size_t)s * HW;
+        f.m = m[s];
+        return f;
+    }
+};
+
+// Builds a block's flows.  `mt` is the block's LDS motion table (kMaxFlows
+// entries, used with MF); all threads call this, followed by a barrier
+// before the first use.
+template <bool MF>
+__device__ __forceinline__ Flows<MF> make_flows(const WinParams& P, const float* __restrict__ rho,
+                                                const float* __restrict__ ego, Motion* mt);
+
+template <>
+__device__ __forceinline__ Flows<false> make_flows<false>(const WinParams& P,
+                                                          const float* __restrict__ rho,
+                                                          const float* __restrict__ ego,
+                                                          Motion*)
+{
+    Flows<false> fl;
+    fl.f = flow_src(P, rho, ego);
+    return fl;
+}
+
+template <>
+__device__ __forceinline__ Flows<true> make_flows<true>(const WinParams& P,
+                                                        const float* __restrict__ rho,
+                                                        const float* __restrict__ ego, Motion* mt)
+{
+    if ((int)threadIdx.x < P.F) mt[threadIdx.x] = load_motion(P, ego + 6 * threadIdx.x);
+    Flows<true> fl;
+    fl.rho = rho;
+    fl.HW = P.HW;
+    fl.m = mt;
+    return fl;
+}
+
 __device__ __forceinline__ double2 flow_at(const WinParams& P, const Motion& m, int i, int j,
                                            double r)
 {
@@ -216,6 +284,7 @@ __device__ __forceinline__ int refs_before(const WinParams& P, double t)
 struct RefTable {
     double t[kMaxRefs];
     double coef[kMaxRefs];
+    int sf[kMaxRefs], sb[kMaxRefs];   // flow set of the forward / backward step into r
 };
 
 // An event's visits of the reference times.  Visit j (0 <= j < R) is
@@ -235,8 +304,8 @@ struct Visits {
 // start off the image, or any visited position off the image.  The loop is
 // unrolled over visits so that every array index is static, and all lanes of a
 // wave step through the same visit numbers together.
-template <int RM>
-__device__ __forceinline__ bool warp_visits(const WinParams& P, const FlowSrc& u,
+template <int RM, bool MF>
+__device__ __forceinline__ bool warp_visits(const WinParams& P, const Flows<MF>& fl,
                                             const RefTable& rt, double x0, double y0, double tk,
                                             double (&vx)[RM], double (&vy)[RM], int (&vr)[RM],
                                             Visits& v)
@@ -250,19 +319,22 @@ __device__ __forceinline__ bool warp_visits(const WinParams& P, const FlowSrc& u
     v.mb = mb;
     v.nf = P.R - mb;
     v.eq = v.nf > 0 && rt.t[mb] == tk;
-    // Both sweeps start at the event: its flow is sampled once and reused.
-    double u0x, u0y;
-    sample_flow(P, u, x0, y0, u0x, u0y);
+    // Both sweeps start at the event; when their first steps use the same flow
+    // (always with one flow set) the sample there is taken once.
+    double u0x = 0.0, u0y = 0.0;
+    int u0set = -1;
     double X = x0, Y = y0, tau = tk;
     bool at_event = true;
 #pragma unroll
     for (int j = 0; j < RM; ++j) {
         if (j < P.R) {
-            int r;
+            int r, set;
             if (j < v.nf) {
                 r = mb + j;
+                set = MF ? rt.sf[r] : 0;
             } else {
                 r = mb - 1 - (j - v.nf);
+                set = MF ? rt.sb[r] : 0;
                 if (j == v.nf) {
                     X = x0;
                     Y = y0;
@@ -274,7 +346,14 @@ __device__ __forceinline__ bool warp_visits(const WinParams& P, const FlowSrc& u
             const double dt = ref - tau;
             if (dt != 0.0) {
                 double ux = u0x, uy = u0y;
-                if (!at_event) sample_flow(P, u, X, Y, ux, uy);
+                if (!(at_event && u0set == set)) {
+                    sample_flow(P, fl.at(set), X, Y, ux, uy);
+                    if (at_event) {
+                        u0x = ux;
+                        u0y = uy;
+                        u0set = set;
+                    }
+                }
                 X = X + dt * ux;
                 Y = Y + dt * uy;
                 at_event = false;
@@ -296,6 +375,7 @@ __device__ __forceinline__ bool warp_visits(const WinParams& P, const FlowSrc& u
 // at j = R-1 and at j = nf-1.
 struct VisitStep {
     bool step, first, restart;
+    int set;        // flow set of the step
     double dt;
 };
 
@@ -311,6 +391,7 @@ __device__ __forceinline__ VisitStep visit_step(const WinParams& P, const RefTab
     s.restart = (j == P.R - 1) || (j == v.nf - 1);
     const double tprev = (s.first || j == 0) ? tk : rt.t[vr[j > 0 ? j - 1 : 0]];
     s.dt = rt.t[vr[j]] - tprev;
+    s.set = (j < v.nf) ? rt.sf[vr[j]] : rt.sb[vr[j]];
     return s;
 }
 
@@ -409,7 +490,8 @@ constexpr int kMaxEventsPerThread = 16;
 
 struct TileGeom {
     int ntx, nty, ntiles;   // tiles per row / column / image
-    int nbins;              // bins of this pass (R * ntiles forward, ntiles backward)
+    int nbins;              // forward bins: R * ntiles (reference, tile)
+    int nbins_b;            // backward bins: F * ntiles (flow set, tile)
     int nblocks;            // count / scatter blocks
     int ept;                // events per thread in the count / scatter kernels
 };

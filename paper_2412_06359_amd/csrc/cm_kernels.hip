@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(float* __restrict__ p, s
     }
 }
 
-template <int RM>
+template <int RM, bool MF>
 __global__ __launch_bounds__(256) void splat_kernel(WinParams P, const float* __restrict__ ex,
                                                     const float* __restrict__ ey,
                                                     const float* __restrict__ et,
@@ -54,10 +54,15 @@ __global__ __launch_bounds__(256) void splat_kernel(WinParams P, const float* __
 {
     __shared__ unsigned int cnt_lds;
     __shared__ RefTable rt;
+    __shared__ Motion mt[kMaxFlows];
     if (threadIdx.x == 0) cnt_lds = 0;
-    if (threadIdx.x < kMaxRefs) rt.t[threadIdx.x] = P.refs[threadIdx.x];
+    if (threadIdx.x < kMaxRefs) {
+        rt.t[threadIdx.x] = P.refs[threadIdx.x];
+        rt.sf[threadIdx.x] = P.sf[threadIdx.x];
+        rt.sb[threadIdx.x] = P.sb[threadIdx.x];
+    }
+    const Flows<MF> u = make_flows<MF>(P, rho, ego, mt);
     __syncthreads();
-    const FlowSrc u = flow_src(P, rho, ego);
     unsigned int cnt = 0;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
          k += (int64_t)gridDim.x * blockDim.x) {
@@ -66,7 +71,7 @@ __global__ __launch_bounds__(256) void splat_kernel(WinParams P, const float* __
         double vx[RM], vy[RM];
         int vr[RM];
         Visits v;
-        if (!warp_visits<RM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
+        if (!warp_visits<RM, MF>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
         ++cnt;
 #pragma unroll
         for (int j = 0; j < RM; ++j) {
@@ -183,7 +188,7 @@ __device__ __forceinline__ void adjoint_step(const WinParams& P, const FlowSrc& 
     Ly += dt * jy;
 }
 
-template <int RM>
+template <int RM, bool MF>
 __global__ __launch_bounds__(256) void backward_kernel(
     WinParams P, const float* __restrict__ ex, const float* __restrict__ ey,
     const float* __restrict__ et, const int8_t* __restrict__ ep, int64_t n,
@@ -193,14 +198,21 @@ __global__ __launch_bounds__(256) void backward_kernel(
 {
     __shared__ double lds[16];
     __shared__ RefTable rt;
+    __shared__ Motion mt[kMaxFlows];
     if (threadIdx.x < kMaxRefs) {
         rt.t[threadIdx.x] = P.refs[threadIdx.x];
         rt.coef[threadIdx.x] =
             (int)threadIdx.x < P.R ? P.two_over_R / (hdr->nact[threadIdx.x] + P.eps) : 0.0;
+        rt.sf[threadIdx.x] = P.sf[threadIdx.x];
+        rt.sb[threadIdx.x] = P.sb[threadIdx.x];
     }
+    const Flows<MF> u = make_flows<MF>(P, rho, ego, mt);
     __syncthreads();
-    const FlowSrc u = flow_src(P, rho, ego);
     const double gl = (double)grad_loss[0];
+    // d theta partials: in registers with one flow set, per set in LDS with several
+    __shared__ double dth_sets[MF ? kMaxFlows * 6 : 1];
+    if (MF)
+        for (int i = threadIdx.x; i < kMaxFlows * 6; i += blockDim.x) dth_sets[i] = 0.0;
     double dth[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
@@ -210,7 +222,7 @@ __global__ __launch_bounds__(256) void backward_kernel(
         double vx[RM], vy[RM];
         int vr[RM];
         Visits v;
-        if (!warp_visits<RM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
+        if (!warp_visits<RM, MF>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
         const double2* planes = reinterpret_cast<const double2*>(img) + (size_t)pol * P.HW;
         double Lx = 0.0, Ly = 0.0;
 #pragma unroll
@@ -227,31 +239,48 @@ __global__ __launch_bounds__(256) void backward_kernel(
                                 1.0 - fabs(rt.t[r] - tk), vx[j], vy[j], Lx, Ly);
                     const double X = s.first ? x0 : vx[j > 0 ? j - 1 : 0];
                     const double Y = s.first ? y0 : vy[j > 0 ? j - 1 : 0];
-                    adjoint_step(P, u, X, Y, s.dt, Lx, Ly, gl, drho, dth);
+                    if (MF) {
+                        double d6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                        adjoint_step(P, u.at(s.set), X, Y, s.dt, Lx, Ly, gl,
+                                     drho + (size_t)s.set * P.HW, d6);
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) atomicAdd(&dth_sets[s.set * 6 + c], d6[c]);
+                    } else {
+                        adjoint_step(P, u.at(0), X, Y, s.dt, Lx, Ly, gl, drho, dth);
+                    }
                 }
             }
         }
     }
+    // part[block][set][6]
+    if (MF) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < P.F * 6; i += blockDim.x)
+            part[(size_t)blockIdx.x * P.F * 6 + i] = dth_sets[i];
+    } else {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        const double s = block_sum(dth[c], lds);
-        if (threadIdx.x == 0) part[(size_t)blockIdx.x * 6 + c] = s;
+        for (int c = 0; c < 6; ++c) {
+            const double v = block_sum(dth[c], lds);
+            if (threadIdx.x == 0) part[(size_t)blockIdx.x * 6 + c] = v;
+        }
     }
 }
 
 __global__ __launch_bounds__(256) void finalize_backward_kernel(const double* __restrict__ part,
-                                                                int nblk,
+                                                                int nblk, int F,
                                                                 const float* __restrict__ grad_loss,
                                                                 float* __restrict__ grad_ego)
 {
     __shared__ double lds[16];
     const double gl = (double)grad_loss[0];
-    for (int c = 0; c < 6; ++c) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[(size_t)b * 6 + c];
-        s = block_sum(s, lds);
-        if (threadIdx.x == 0) grad_ego[c] = (float)(gl * s);
-    }
+    for (int f = 0; f < F; ++f)
+        for (int c = 0; c < 6; ++c) {
+            double s = 0.0;
+            for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+                s += part[((size_t)b * F + f) * 6 + c];
+            s = block_sum(s, lds);
+            if (threadIdx.x == 0) grad_ego[f * 6 + c] = (float)(gl * s);
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -275,7 +304,12 @@ static void launch_splat_rm(const WinParams& P, const EventPtrs& ev, const float
                             const float* ego, double* img, unsigned long long* nv, hipStream_t s)
 {
     const int grid = std::max(1, std::min(ceil_div(ev.n, 256), 1 << 20));
-    splat_kernel<RM><<<grid, 256, 0, s>>>(P, ev.x, ev.y, ev.t, ev.p, ev.n, rho, ego, img, nv);
+    if (P.F > 1)
+        splat_kernel<RM, true><<<grid, 256, 0, s>>>(P, ev.x, ev.y, ev.t, ev.p, ev.n, rho, ego, img,
+                                                    nv);
+    else
+        splat_kernel<RM, false><<<grid, 256, 0, s>>>(P, ev.x, ev.y, ev.t, ev.p, ev.n, rho, ego,
+                                                     img, nv);
 }
 
 template <int RM>
@@ -283,8 +317,12 @@ static void launch_backward_rm(const WinParams& P, const EventPtrs& ev, const fl
                                const float* ego, const double* img, const StateHeader* hdr,
                                const float* gl, float* drho, double* part, int grid, hipStream_t s)
 {
-    backward_kernel<RM><<<grid, 256, 0, s>>>(P, ev.x, ev.y, ev.t, ev.p, ev.n, rho, ego, img, hdr,
-                                             gl, drho, part);
+    if (P.F > 1)
+        backward_kernel<RM, true><<<grid, 256, 0, s>>>(P, ev.x, ev.y, ev.t, ev.p, ev.n, rho, ego,
+                                                       img, hdr, gl, drho, part);
+    else
+        backward_kernel<RM, false><<<grid, 256, 0, s>>>(P, ev.x, ev.y, ev.t, ev.p, ev.n, rho, ego,
+                                                        img, hdr, gl, drho, part);
 }
 
 int reduce_blocks(const WinParams& P) { return std::max(1, std::min(ceil_div(P.HW, 1024), kReduceBlocks)); }
@@ -332,7 +370,7 @@ hipError_t launch_backward(const WinParams& P, const EventPtrs& ev, const float*
     hipError_t e;
     {
         PhaseScope ph(prof, kPhGradZero, s);
-        e = launch_fill_zero(grad_rho, (size_t)P.HW, s);
+        e = launch_fill_zero(grad_rho, (size_t)P.HW * P.F, s);
     }
     if (e != hipSuccess) return e;
     const int grid = backward_blocks(ev.n);
@@ -347,8 +385,8 @@ hipError_t launch_backward(const WinParams& P, const EventPtrs& ev, const float*
     }
     {
         PhaseScope ph(prof, kPhGradFinalize, s);
-        finalize_backward_kernel<<<1, 256, 0, s>>>(st.scratch, ev.n > 0 ? grid : 0, grad_loss,
-                                                   grad_ego);
+        finalize_backward_kernel<<<1, 256, 0, s>>>(st.scratch, ev.n > 0 ? grid : 0, P.F,
+                                                   grad_loss, grad_ego);
         e = hipGetLastError();
     }
     return e;

@@ -26,8 +26,12 @@ constexpr unsigned long long kHdrSourceRecords = 1ull;
 
 constexpr int kReduceBlocks = 256;     // reduce blocks per reference (max)
 constexpr int kBackwardBlocks = 4096;  // backward grid (max), grid-stride beyond
-constexpr size_t kScratchDoubles =
-    std::max<size_t>((size_t)kReduceBlocks * kMaxRefs * 2, (size_t)kBackwardBlocks * 6);
+// Reduction scratch of the direct path: forward partials per reference and
+// block, backward d theta partials per block and flow set.
+inline size_t scratch_doubles(int F)
+{
+    return std::max<size_t>((size_t)kReduceBlocks * kMaxRefs * 2, (size_t)kBackwardBlocks * 6 * F);
+}
 
 struct EventPtrs {
     const float* x;
@@ -40,7 +44,7 @@ struct EventPtrs {
 struct StatePtrs {
     double* img;           // [R][2][H*W][2] FP64
     StateHeader* hdr;
-    double* scratch;       // kScratchDoubles
+    double* scratch;       // scratch_doubles(F)
     size_t zero_floats;    // floats to clear before a forward (images + header)
 };
 
@@ -109,16 +113,17 @@ enum Phase {
 // into flat arrays shared by the windows of a batch.
 struct WinMeta {
     WinParams P;
-    TileGeom G;             // forward bins R * ntiles; backward bins = tiles
+    TileGeom G;             // forward bins R * ntiles; backward bins F * ntiles
     int nchunks;            // column-scan chunks of this window's count blocks
     int pad_;
     int64_t ev_off, n;      // events [ev_off, ev_off + n) of the flat event arrays
-    int64_t pix_off;        // first pixel of rho / d rho
+    int64_t pix_off;        // first pixel of rho / d rho (F images of H W each)
+    int64_t ego_off;        // first flow set of ego / d ego (6 floats each)
     int64_t img_off;        // first image element (double2) in the state
     int64_t hist_off;       // first histogram cell
     int64_t csum_off;       // first chunk-sum cell
     int64_t bin_off;        // first forward bin
-    int64_t tile_off;       // first tile (backward bin)
+    int64_t bbin_off;       // first backward bin (flow set, tile)
     int64_t blk_off;        // first count / scatter / sweep block
     int64_t cell_off_f;     // first forward chunk cell
     int64_t cell_off_b;     // first backward chunk cell
@@ -128,7 +133,7 @@ constexpr int kScanChunk = 16;  // histogram rows per chunk of the column scan
 
 // Byte offsets of the tiled path's buffers inside the workspace region.
 struct TileWorkspace {
-    size_t hist, csum, totals, start, part, halo, records, src, total;
+    size_t hist, csum, totals, start, part, halo, records, src, win, total;
 };
 
 // Host-side plan of a tiled batch: per-window metadata, totals, workspace layout.
@@ -136,9 +141,9 @@ struct BatchPlanHost {
     int nw = 0;
     bool det = false;       // deterministic mode
     std::vector<WinMeta> meta;
-    int64_t n_events = 0, n_pixels = 0, img_elems = 0;
-    int64_t nbins = 0, ntiles = 0, nblocks = 0, cells_f = 0, cells_b = 0;
-    int max_R = 1, max_lds_bins = 1;
+    int64_t n_events = 0, n_pixels = 0, n_sets = 0, img_elems = 0;
+    int64_t nbins = 0, nbins_b = 0, nblocks = 0, cells_f = 0, cells_b = 0;
+    int max_R = 1, max_F = 1, max_lds_bins = 1;
     TileWorkspace ws;
 };
 
@@ -148,7 +153,7 @@ __global__ __launch_bounds__(256) void finalize_forward_kernel(WinParams P,
                                                                int RB, StateHeader* hdr,
                                                                float* __restrict__ loss);
 __global__ __launch_bounds__(256) void finalize_backward_kernel(const double* __restrict__ part,
-                                                                int nblk,
+                                                                int nblk, int F,
                                                                 const float* __restrict__ grad_loss,
                                                                 float* __restrict__ grad_ego);
 

@@ -13,8 +13,9 @@ gradients (on the device).
 
 Footprint of a window (bytes): its share of the batch state (splat images
 32 R H W, header, tiled workspace: the single-window state size), the events
-(13 N), inverse depth and its gradient (8 H W) and the small per-window
-vectors; the admitted batches' footprints never sum above the budget.  A
+(13 N), inverse depth and its gradient (8 F H W for F flow sets) and the small
+per-window vectors; the admitted batches' footprints never sum above the
+budget.  A
 window larger than the whole budget is refused with CM_ERR_BUDGET.
 """
 
@@ -49,7 +50,7 @@ class Request:
 
 def window_footprint(desc: WindowDesc, n_events: int) -> int:
     hw = desc.width * desc.height
-    return binding.state_bytes(desc, n_events) + 13 * n_events + 8 * hw + 64
+    return binding.state_bytes(desc, n_events) + 13 * n_events + 8 * hw * desc.F + 48 * desc.F + 16
 
 
 class _InFlight:
@@ -160,12 +161,13 @@ class Server:
             t = time.perf_counter()
             loss = fl.loss_host.numpy()
             g_rho, g_ego = fl.keep["g_rho"], fl.keep["g_ego"]
-            offs = fl.batch.pixel_offsets
+            offs, sets = fl.batch.pixel_offsets, fl.batch.set_offsets
             for w, r in enumerate(fl.reqs):
+                lead = (r.desc.F,) if r.desc.F > 1 else ()
                 res = {"loss": float(loss[w]),
-                       "grad_inv_depth": g_rho[offs[w]:offs[w + 1]].view(r.desc.height,
-                                                                          r.desc.width),
-                       "grad_ego": g_ego[6 * w:6 * w + 6],
+                       "grad_inv_depth": g_rho[offs[w]:offs[w + 1]].view(
+                           *lead, r.desc.height, r.desc.width),
+                       "grad_ego": g_ego[6 * sets[w]:6 * sets[w + 1]].view(*lead, 6),
                        "latency_s": t - r.t_arrival}
                 self.latencies.append(t - r.t_arrival)
                 self.events_done += r.n

@@ -12,7 +12,7 @@ def to_device(win, device="cuda:0"):
     f = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float32))).to(device)
     return dict(x=f(win.x), y=f(win.y), t=f(win.t),
                 p=torch.from_numpy(np.ascontiguousarray(np.asarray(win.p, dtype=np.int8))).to(device),
-                rho=f(win.rho).reshape(win.height, win.width), ego=f(win.theta))
+                rho=f(win.rho).reshape(np.shape(win.rho)), ego=f(win.theta))
 
 
 def assert_loss_close(got, want, rtol=LOSS_RTOL, what=""):

@@ -98,3 +98,25 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(binding, "LIB_PATH", "/nonexistent/libcmloss.so")
     with pytest.raises(RuntimeError, match="missing"):
         binding.load()
+
+
+@pytest.mark.parametrize("refs,F,ok", [
+    ([0.0, 0.5, 1.0], 0, True), ([0.0, 0.5, 1.0], 1, True), ([0.0, 0.5, 1.0], 2, True),
+    ([0.0, 0.5, 1.0], 3, False), ([0.0, 0.5, 1.0], -1, False),
+    ([0.2, 0.6], 3, True), ([0.2, 0.6], 2, False), ([1.0], 1, True), ([1.0], 2, False),
+    ([0.5], 2, True), ([0.0, 1.0], 1, True), ([0.0, 1.0], 2, False),
+])
+def test_flow_set_count_validated(lib, refs, F, ok):
+    """n_flows must be 1 (or 0) or the number of segments between consecutive
+    knots {0, 1} U refs."""
+    d = _desc(refs=refs)
+    d.n_flows = F
+    assert (lib.cm_state_bytes(ctypes.byref(d), 100) > 0) == ok
+
+
+def test_flow_sets_enlarge_only_the_scratch(lib):
+    d1 = _desc(refs=[0.0, 0.25, 0.5, 0.75, 1.0])
+    d4 = _desc(refs=[0.0, 0.25, 0.5, 0.75, 1.0])
+    d4.n_flows = 4
+    b1, b4 = cm.state_bytes(d1, 0), cm.state_bytes(d4, 0)
+    assert b4 >= b1 and b4 - b1 < 2 << 20

@@ -38,3 +38,30 @@ def test_mirror_empty_window():
     assert oracle.mirror_forward(win)["loss"] == 0.0
     mb = oracle.mirror_backward(win)
     assert not mb["drho"].any() and not mb["dtheta"].any()
+
+
+@pytest.mark.parametrize("refs", [[0.0, 0.25, 0.5, 0.75, 1.0], [0.15, 0.5, 0.85]])
+def test_mirror_agrees_with_oracle_flow_sets(refs):
+    """One flow per segment: the mirror routes steps and gradients to the same
+    sets as the oracle."""
+    win = eventgen.edge_window(34, "346x260", 4000, refs=refs, n_segments=12, motion_sigma=0.3)
+    win = eventgen.with_flow_sets(win, 35)
+    F = win.rho.shape[0]
+    assert F == len(eventgen.knots_of(refs)) - 1
+    m = oracle.mirror_forward(win)
+    o = oracle.forward(win, valid=True)
+    assert m["n_valid"] == int(o["valid"].sum())
+    np.testing.assert_array_equal(m["nact"], o["nact"])
+    assert_loss_close(float(m["loss64"]), o["loss"], rtol=1e-12, what="sets")
+    mb = oracle.mirror_backward(win, grad_loss=0.7)
+    ob = oracle.backward(win, grad_loss=0.7)
+    assert mb["drho"].shape == (F, win.height, win.width) and mb["dtheta"].shape == (F, 6)
+    for f in range(F):
+        assert_grads_close(mb["drho"][f], mb["dtheta"][f], ob["drho"][f], ob["dtheta"][f],
+                           rtol=1e-5, what=f"set {f}")
+
+
+def test_c6_window_shape():
+    win = eventgen.make_window("c6", 3)
+    assert win.rho.shape == (10, win.height, win.width) and win.theta.shape == (10, 6)
+    assert len(win.refs) == 11 and 10_000 <= win.n <= 100_000
