@@ -65,6 +65,43 @@ __device__ __forceinline__ int64_t xcd_block()
     return (int64_t)x * q + min(x, r) + i;
 }
 
+// One lane's next event, loaded an iteration ahead so that its latency
+// overlaps the current event's warp and gathers.
+struct EventPrefetch {
+    struct Ev {
+        float x, y, t;
+        int8_t p;
+    };
+    const float* __restrict__ ex;
+    const float* __restrict__ ey;
+    const float* __restrict__ et;
+    const int8_t* __restrict__ ep;
+    int64_t n;
+    Ev nxt;
+    __device__ __forceinline__ EventPrefetch(const float* x, const float* y, const float* t,
+                                             const int8_t* p, int64_t k, int64_t n_)
+        : ex(x), ey(y), et(t), ep(p), n(n_)
+    {
+        load(k);
+    }
+    __device__ __forceinline__ void load(int64_t k)
+    {
+        if (k < n) {
+            nxt.x = ex[k];
+            nxt.y = ey[k];
+            nxt.t = et[k];
+            nxt.p = ep ? ep[k] : (int8_t)0;
+        }
+    }
+    // The event loaded last; starts loading event k (k >= n: nothing).
+    __device__ __forceinline__ Ev take(int64_t k)
+    {
+        const Ev cur = nxt;
+        load(k);
+        return cur;
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Deterministic mode helpers (one wavefront per block)
 // ---------------------------------------------------------------------------
@@ -158,14 +195,16 @@ __global__ __launch_bounds__(NT) void fwd_count_kernel(
     __syncthreads();
     const int64_t base = lb * NT * G.ept;
     uint32_t cnt = 0;
+    // the next iteration's event is loaded before this one is warped
+    EventPrefetch nx(ex + ev0, ey + ev0, et + ev0, nullptr, base + threadIdx.x, n);
     for (int e = 0; e < G.ept; ++e) {
         const int64_t k = base + (int64_t)e * NT + threadIdx.x;
         if (k >= n) break;
+        const EventPrefetch::Ev cur = nx.take(e + 1 < G.ept ? k + NT : n);
         double vx[RM], vy[RM];
         int vr[RM];
         Visits v;
-        if (!warp_visits<RM, MF>(P, u, rt, ex[ev0 + k], ey[ev0 + k], et[ev0 + k], vx, vy, vr, v))
-            continue;
+        if (!warp_visits<RM, MF>(P, u, rt, cur.x, cur.y, cur.t, vx, vy, vr, v)) continue;
         ++cnt;
 #pragma unroll
         for (int j = 0; j < RM; ++j)
@@ -320,15 +359,17 @@ __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
     const uint32_t r0 = start[meta[w].bin_off];
     SrcRec* wsrc = src + ev0;
     const int64_t base = lb * NT * G.ept;
+    EventPrefetch nx(ex + ev0, ey + ev0, et + ev0, ep + ev0, base + threadIdx.x, n);
     for (int e = 0; e < G.ept; ++e) {
         const int64_t k = base + (int64_t)e * NT + threadIdx.x;
         if (k >= n) break;
+        const EventPrefetch::Ev cur = nx.take(e + 1 < G.ept ? k + NT : n);
         double vx[RM], vy[RM];
         int vr[RM];
         Visits v;
-        const float xk = ex[ev0 + k], yk = ey[ev0 + k], tk = et[ev0 + k];
+        const float xk = cur.x, yk = cur.y, tk = cur.t;
         if (!warp_visits<RM, MF>(P, u, rt, xk, yk, tk, vx, vy, vr, v)) continue;
-        const float ts = ep[ev0 + k] > 0 ? fabsf(tk) : -fabsf(tk);   // sign bit = polarity
+        const float ts = cur.p > 0 ? fabsf(tk) : -fabsf(tk);   // sign bit = polarity
 #pragma unroll
         for (int j = 0; j < RM; ++j) {
             if (j < P.R) {
@@ -653,13 +694,17 @@ __global__ __launch_bounds__(NT) void bwd_count_kernel(
     __shared__ Motion mt[kMaxFlows];
     const Flows<MF> u = make_flows<MF>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off, mt);
     __syncthreads();
-    for (int e = 0; e < G.ept; ++e) {
-        const int64_t i = ((int64_t)e * G.nblocks + lb) * NT + threadIdx.x;
+    const int64_t stride = (int64_t)G.nblocks * NT;
+    SrcRec qn;
+    int64_t i = (int64_t)lb * NT + threadIdx.x;
+    if (i < nv) qn = load_nt(wsrc + i);
+    for (int e = 0; e < G.ept; ++e, i += stride) {
         if (i >= nv) break;
+        const SrcRec q = qn;
+        if (e + 1 < G.ept && i + stride < nv) qn = load_nt(wsrc + i + stride);
         double vx[RM], vy[RM];
         int vr[RM];
         Visits v;
-        const SrcRec q = load_nt(wsrc + i);
         const double x0 = q.x0, y0 = q.y0, tk = fabsf(q.ts);
         if (!warp_visits<RM, MF>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
         for_each_sample<RM, MF>(P, rt, v, vx, vy, vr, x0, y0, [&](double X, double Y, int set) {
@@ -709,13 +754,17 @@ __global__ __launch_bounds__(NT) void bwd_sweep_kernel(
         store_nt(rec + slot, q);
     };
 
-    for (int e = 0; e < G.ept; ++e) {
-        const int64_t i = ((int64_t)e * G.nblocks + lb) * NT + threadIdx.x;
+    const int64_t stride = (int64_t)G.nblocks * NT;
+    SrcRec qn;
+    int64_t i = (int64_t)lb * NT + threadIdx.x;
+    if (i < nv) qn = load_nt(wsrc + i);
+    for (int e = 0; e < G.ept; ++e, i += stride) {
         if (i >= nv) break;
+        const SrcRec q = qn;
+        if (e + 1 < G.ept && i + stride < nv) qn = load_nt(wsrc + i + stride);
         double vx[RM], vy[RM];
         int vr[RM];
         Visits v;
-        const SrcRec q = load_nt(wsrc + i);
         const double x0 = q.x0, y0 = q.y0, tk = fabsf(q.ts);
         if (!warp_visits<RM, MF>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
         const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
@@ -954,7 +1003,12 @@ __global__ void store_meta_kernel(WinMeta m, WinMeta* __restrict__ out)
 // deterministic mode (its record order is the lanes' order), else four.
 static int bin_threads(bool det) { return det ? 64 : kBinThreads; }
 
-TileGeom tile_geom(const WinParams& P, int64_t n, bool det)
+// Blocks a batch's event kernels aim for: a few waves of the 256 CUs, so that
+// every block warps several events per lane and the next event's loads overlap
+// the current one's gathers.
+constexpr int64_t kTargetEventBlocks = 4096;
+
+TileGeom tile_geom(const WinParams& P, int64_t n, bool det, int min_ept)
 {
     TileGeom G;
     G.ntx = (P.W + TW - 1) / TW;
@@ -964,7 +1018,7 @@ TileGeom tile_geom(const WinParams& P, int64_t n, bool det)
     G.nbins_b = P.F * G.ntiles;
     // enough blocks to fill the chip, few enough to keep the histogram matrix small
     const int nt = bin_threads(det);
-    const int64_t ept = n / ((int64_t)nt * 1024);
+    const int64_t ept = std::max<int64_t>(n / ((int64_t)nt * 1024), min_ept);
     G.ept = (int)std::max<int64_t>(1, std::min<int64_t>(ept, kMaxEventsPerThread));
     const int64_t per_block = (int64_t)nt * G.ept;
     G.nblocks = (int)std::max<int64_t>(1, (n + per_block - 1) / per_block);
@@ -973,7 +1027,7 @@ TileGeom tile_geom(const WinParams& P, int64_t n, bool det)
 
 bool tiled_supported(const WinParams& P, int64_t n)
 {
-    const TileGeom G = tile_geom(P, n, false);
+    const TileGeom G = tile_geom(P, n, false, 1);
     return G.nbins <= kMaxBins && G.nbins_b <= kMaxBins && n * (int64_t)P.R < ((int64_t)1 << 31);
 }
 
@@ -988,11 +1042,22 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     B.max_R = 1;
     B.max_F = 1;
     B.max_lds_bins = 1;
+    // Events per lane from the batch's size (the atomic mode only: the
+    // deterministic mode's block partition, and with it its operation order,
+    // depends on the window alone).
+    int64_t total = 0;
+    for (int w = 0; w < nw; ++w) total += n_events[w];
+    const int nt = bin_threads(det);
+    const int min_ept = det ? 1
+                            : (int)std::min<int64_t>(
+                                  kMaxEventsPerThread,
+                                  std::max<int64_t>(1, (total + nt * kTargetEventBlocks - 1) /
+                                                           (nt * kTargetEventBlocks)));
     for (int w = 0; w < nw; ++w) {
         WinMeta& M = B.meta[w];
         std::memset(&M, 0, sizeof M);
         M.P = params[w];
-        M.G = tile_geom(M.P, n_events[w], det);
+        M.G = tile_geom(M.P, n_events[w], det, min_ept);
         M.nchunks = (M.G.nblocks + kScanChunk - 1) / kScanChunk;
         M.ev_off = ev;
         M.n = n_events[w];

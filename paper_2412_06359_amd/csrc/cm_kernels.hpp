@@ -172,7 +172,7 @@ hipError_t launch_backward(const WinParams& P, const EventPtrs& ev, const float*
 // copy of plan.meta; `ws` a device region of plan.ws.total bytes; images of
 // window w start at img + meta[w].img_off; hdrs[w] its sums.
 bool tiled_supported(const WinParams& P, int64_t n);
-TileGeom tile_geom(const WinParams& P, int64_t n, bool det);
+TileGeom tile_geom(const WinParams& P, int64_t n, bool det, int min_ept);
 BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int nw, bool det);
 hipError_t launch_store_meta(const WinMeta& m, WinMeta* out, hipStream_t s);
 hipError_t launch_forward_batch(const BatchPlanHost& B, const WinMeta* meta, const EventPtrs& ev,
