@@ -464,10 +464,25 @@ __global__ __launch_bounds__(256) void fwd_tile_kernel(const WinMeta* __restrict
     int r, tx, ty;
     split_bin(G, (int)(gbin - meta[w].bin_off), r, tx, ty);
     const int xo = tx * TW, yo = ty * TH;
+    const uint32_t s0 = start[gbin], s1 = start[gbin + 1];
+    if (s0 == s1) {
+        // No warped position falls in this tile at this reference.  Nothing
+        // reads its pixels except column 0 and row 0, which the merge writes
+        // from the neighbours' halos; a backward gather at a tap of this tile
+        // comes from a position binned in a left or upper neighbour, whose
+        // taps reach only that column and row.  So only the zero halo and
+        // zero sums are written (56% of the c3 bins are empty).
+        double2* hb = halo + gbin * NHALO * 2;
+        for (int j = threadIdx.x; j < NHALO * 2; j += blockDim.x) hb[j] = make_double2(0.0, 0.0);
+        if (threadIdx.x == 0) {
+            part[(gbin * 2 + 0) * 2 + 0] = 0.0;
+            part[(gbin * 2 + 0) * 2 + 1] = 0.0;
+        }
+        return;
+    }
     for (int i = threadIdx.x; i < 2 * TLW * TLH; i += blockDim.x) lds[i] = make_double2(0.0, 0.0);
     __syncthreads();
     const double ref = P.refs[r];
-    const uint32_t s0 = start[gbin], s1 = start[gbin + 1];
     if (!DET) {
         for (uint32_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
             const SplatRec q = rec[i];
@@ -540,6 +555,7 @@ __global__ __launch_bounds__(256) void fwd_tile_kernel(const WinMeta* __restrict
 // Column 0 and row 0 of each tile: add the halos of the left, top and
 // top-left tiles (in that order), store, and reduce those pixels.
 __global__ __launch_bounds__(64) void fwd_merge_kernel(const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of,
+                                                       const uint32_t* __restrict__ start,
                                                        double2* __restrict__ img_base,
                                                        const double2* __restrict__ halo,
                                                        double* __restrict__ part)
@@ -553,6 +569,7 @@ __global__ __launch_bounds__(64) void fwd_merge_kernel(const WinMeta* __restrict
     split_bin(G, (int)(gbin - meta[w].bin_off), r, tx, ty);
     const int xo = tx * TW, yo = ty * TH;
     double2* img = img_base + meta[w].img_off;
+    const bool own = start[gbin] != start[gbin + 1];   // the tile kernel wrote this tile
     double sum = 0.0, cnt = 0.0;
     for (int j = threadIdx.x; j < NBORDER; j += blockDim.x) {
         const int lx = j < TH ? 0 : j - TH + 1;
@@ -563,7 +580,7 @@ __global__ __launch_bounds__(64) void fwd_merge_kernel(const WinMeta* __restrict
         double2 v[2];
 #pragma unroll
         for (int pol = 0; pol < 2; ++pol) {
-            double2 a = img[(size_t)(r * 2 + pol) * P.HW + pix];
+            double2 a = own ? img[(size_t)(r * 2 + pol) * P.HW + pix] : make_double2(0.0, 0.0);
             if (lx == 0 && tx > 0) {
                 const double2 h = halo[((gbin - 1) * NHALO + ly) * 2 + pol];
                 a.x += h.x;
@@ -826,9 +843,28 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(
     const int set = lbin / G.ntiles, tile = lbin - set * G.ntiles;
     const int ty = tile / G.ntx, tx = tile - ty * G.ntx;
     const int xo = tx * TW, yo = ty * TH;
+    const uint32_t s0 = start[gtile], s1 = start[gtile + 1];
+    if (s0 == s1) {
+        // no records: dL/du is zero on the tile; write its d rho, zero border
+        // values and halo for the merge, and zero d theta shares
+        float* drho_w = drho + meta[w].pix_off + (size_t)set * P.HW;
+        const float z = (float)((double)grad_loss[w] * 0.0);
+        for (int i = threadIdx.x; i < TW * TH; i += blockDim.x) {
+            const int lx = i % TW, ly = i / TW;
+            const int X = xo + lx, Y = yo + ly;
+            if (X >= P.W || Y >= P.H) continue;
+            if (lx == 0 || ly == 0)
+                border[gtile * NBORDER + (lx == 0 ? ly : TH + lx - 1)] = make_double2(0.0, 0.0);
+            else
+                drho_w[Y * P.W + X] = z;
+        }
+        for (int j = threadIdx.x; j < NHALO; j += blockDim.x)
+            halo[gtile * NHALO + j] = make_double2(0.0, 0.0);
+        if (threadIdx.x < 6) part[gtile * 12 + threadIdx.x] = 0.0;
+        return;
+    }
     for (int i = threadIdx.x; i < TLW * TLH; i += blockDim.x) lds[i] = make_double2(0.0, 0.0);
     __syncthreads();
-    const uint32_t s0 = start[gtile], s1 = start[gtile + 1];
     if (!DET) {
         for (uint32_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
             const GradRec q = rec[i];
@@ -1177,7 +1213,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     }
     {
         PhaseScope ph(prof, kPhReduce, s);
-        fwd_merge_kernel<<<(int)B.nbins, 64, 0, s>>>(meta, nw, win_bin, img, halo, part);
+        fwd_merge_kernel<<<(int)B.nbins, 64, 0, s>>>(meta, nw, win_bin, start, img, halo, part);
     }
     {
         PhaseScope ph(prof, kPhFinalize, s);
