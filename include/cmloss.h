@@ -202,6 +202,13 @@ cm_status cm_loss_backward_batched(cm_batch b, const float* ev_x, const float* e
 /* Per-window (loss, valid events) of the last batched forward, host array of
  * 2 * n_windows doubles; synchronises `stream`. */
 cm_status cm_batch_diagnostics(cm_batch b, const void* state, double* out, void* stream);
+/* Per window, the bytes of splat image held by its occupied (reference,
+ * 32x32 tile) bins after the last batched forward on `state`: 32 bytes per
+ * pixel of every tile that some warped position falls in (the other tiles
+ * hold only zeros and are not written).  Host array of n_windows doubles;
+ * call between the forward and the backward; synchronises `stream`.  A
+ * measurement aid for the splat's minimal image traffic. */
+cm_status cm_batch_occupied_image_bytes(cm_batch b, const void* state, double* out, void* stream);
 
 /* Phase timing (diagnostics, not part of the method).  While enabled on a
  * handle, each call records a pair of HIP events on its stream around every

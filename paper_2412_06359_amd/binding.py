@@ -130,6 +130,8 @@ def load() -> ctypes.CDLL:
         lib.cm_loss_backward_batched.restype = ctypes.c_int
         lib.cm_batch_diagnostics.argtypes = [P, P, P, P]
         lib.cm_batch_diagnostics.restype = ctypes.c_int
+        lib.cm_batch_occupied_image_bytes.argtypes = [P, P, P, P]
+        lib.cm_batch_occupied_image_bytes.restype = ctypes.c_int
         lib.cm_profile_enable.argtypes = [P, ctypes.c_int]
         lib.cm_profile_enable.restype = ctypes.c_int
         lib.cm_profile_read.argtypes = [P, P, P]
@@ -337,6 +339,15 @@ class Batch:
                                              _ptr(grad_rho), _ptr(grad_ego), _stream(dev))
         _check(st, "cm_loss_backward_batched")
         return grad_rho, grad_ego
+
+    def occupied_image_bytes(self, state) -> list:
+        """Per window, splat-image bytes of its occupied tiles after the last
+        forward (call before the backward; synchronises)."""
+        out = (ctypes.c_double * self.n)()
+        st = load().cm_batch_occupied_image_bytes(self._b, _ptr(state), out,
+                                                  _stream(state.device))
+        _check(st, "cm_batch_occupied_image_bytes")
+        return list(out)
 
     def diagnostics(self, state) -> list:
         out = (ctypes.c_double * (2 * self.n))()

@@ -546,4 +546,33 @@ cm_status cm_batch_diagnostics(cm_batch b, const void* state, double* out, void*
     return CM_OK;
 }
 
+cm_status cm_batch_occupied_image_bytes(cm_batch b, const void* state, double* out, void* stream)
+{
+    if (!b || !state || !out) return CM_ERR_INVALID_ARG;
+    const BatchPlanHost& B = b->B;
+    std::vector<uint32_t> start((size_t)B.nbins + 1);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceGuard g(b->h->device);
+    if (!g.ok()) return CM_ERR_HIP;
+    if (hipMemcpyAsync(start.data(), static_cast<const char*>(state) + b->ws_off + B.ws.start,
+                       sizeof(uint32_t) * start.size(), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return CM_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return CM_ERR_HIP;
+    for (int w = 0; w < B.nw; ++w) {
+        const WinMeta& M = B.meta[w];
+        double bytes = 0.0;
+        for (int bin = 0; bin < M.G.nbins; ++bin) {
+            const int64_t gb = M.bin_off + bin;
+            if (start[gb + 1] == start[gb]) continue;
+            const int tile = bin % M.G.ntiles;
+            const int tx = tile % M.G.ntx, ty = tile / M.G.ntx;
+            const int pw = std::min(cm::TW, M.P.W - tx * cm::TW);
+            const int ph = std::min(cm::TH, M.P.H - ty * cm::TH);
+            bytes += 2.0 * 16.0 * pw * ph;      // C and S, FP64, both polarities
+        }
+        out[w] = bytes;
+    }
+    return CM_OK;
+}
+
 }  // extern "C"

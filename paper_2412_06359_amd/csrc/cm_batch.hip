@@ -176,7 +176,8 @@ template <int RM, int NT, bool MF>
 __global__ __launch_bounds__(NT) void fwd_count_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const float* __restrict__ ex,
     const float* __restrict__ ey, const float* __restrict__ et, const float* __restrict__ rho,
-    const float* __restrict__ ego, uint32_t* __restrict__ hist, StateHeader* __restrict__ hdrs)
+    const float* __restrict__ ego, uint32_t* __restrict__ hist, uint32_t* __restrict__ csum,
+    StateHeader* __restrict__ hdrs)
 {
     extern __shared__ uint32_t lh[];
     __shared__ uint32_t cnt_lds;
@@ -214,13 +215,19 @@ __global__ __launch_bounds__(NT) void fwd_count_kernel(
     if (cnt) atomicAdd(&cnt_lds, cnt);
     __syncthreads();
     uint32_t* row = hist + meta[w].hist_off + lb * G.nbins;
-    for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) row[i] = lh[i];
+    uint32_t* cs = csum + meta[w].csum_off + (size_t)(lb / kScanChunk) * G.nbins;
+    for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) {
+        const uint32_t c = lh[i];
+        row[i] = c;
+        if (c) atomicAdd(cs + i, c);       // the chunk's column sums (integer: order-free)
+    }
     if (threadIdx.x == 0 && cnt_lds) atomicAdd(&hdrs[w].n_valid, (unsigned long long)cnt_lds);
 }
 
 // Column scan of each window's block x bin histogram in two levels: blocks
-// are grouped in chunks of kScanChunk rows; chunk sums, then a per-bin scan
-// over chunks, then the per-block offsets inside each chunk.  `bwd` selects
+// are grouped in chunks of kScanChunk rows; the count kernels add their rows
+// into the chunk sums, then a per-bin scan over chunks, then the per-block
+// offsets inside each chunk.  `bwd` selects
 // the backward bin space (one bin per flow set and tile).
 struct BinSpace {
     __device__ __forceinline__ static int nbins(const WinMeta& m, bool bwd)
@@ -237,24 +244,12 @@ struct BinSpace {
     }
 };
 
-__global__ __launch_bounds__(256) void chunk_sum_kernel(const WinMeta* __restrict__ meta, int nw,
-                                                        int64_t ncells, int bwd,
-                                                        const uint32_t* __restrict__ hist,
-                                                        uint32_t* __restrict__ csum)
+// Zeroes n counters (a kernel, not a memset, so that graph replays clear them).
+__global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n)
 {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= ncells) return;
-    const int w = find_window(meta, nw, id,
-                              [bwd](const WinMeta& m) { return BinSpace::cell_off(m, bwd); });
-    const WinMeta& M = meta[w];
-    const int nbins = BinSpace::nbins(M, bwd);
-    const int64_t local = id - BinSpace::cell_off(M, bwd);
-    const int c = (int)(local / nbins), bin = (int)(local - (int64_t)c * nbins);
-    const int b0 = c * kScanChunk, b1 = min(b0 + kScanChunk, M.G.nblocks);
-    const uint32_t* h = hist + M.hist_off;
-    uint32_t s = 0;
-    for (int b = b0; b < b1; ++b) s += h[(size_t)b * nbins + bin];
-    csum[M.csum_off + (size_t)c * nbins + bin] = s;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
 }
 
 // In place: csum[c][bin] <- sum over chunks before c; totals[global bin] = column total.
@@ -694,7 +689,7 @@ template <int RM, int NT, bool MF>
 __global__ __launch_bounds__(NT) void bwd_count_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const SrcRec* __restrict__ src,
     const float* __restrict__ rho, const float* __restrict__ ego,
-    const StateHeader* __restrict__ hdrs, uint32_t* __restrict__ hist)
+    const StateHeader* __restrict__ hdrs, uint32_t* __restrict__ hist, uint32_t* __restrict__ csum)
 {
     extern __shared__ uint32_t lh[];
     const int64_t blk = xcd_block();
@@ -730,7 +725,12 @@ __global__ __launch_bounds__(NT) void bwd_count_kernel(
     }
     __syncthreads();
     uint32_t* row = hist + meta[w].hist_off + lb * G.nbins_b;
-    for (int i = threadIdx.x; i < G.nbins_b; i += blockDim.x) row[i] = lh[i];
+    uint32_t* cs = csum + meta[w].csum_off + (size_t)(lb / kScanChunk) * G.nbins_b;
+    for (int i = threadIdx.x; i < G.nbins_b; i += blockDim.x) {
+        const uint32_t c = lh[i];
+        row[i] = c;
+        if (c) atomicAdd(cs + i, c);
+    }
 }
 
 template <int RM, int NT, bool DET, bool MF>
@@ -1133,6 +1133,7 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     B.nblocks = blk;
     B.cells_f = cf;
     B.cells_b = cb;
+    B.csum_cells = csum;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -1185,17 +1186,18 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
         PhaseScope ph(prof, kPhZero, s);
         clear_headers_kernel<<<(nw + 255) / 256, 256, 0, s>>>(hdrs, nw);
         launch_window_table(B, meta, wtab, s);
+        fill_u32_kernel<<<(int)std::min<int64_t>((B.csum_cells + 255) / 256, 4096), 256, 0, s>>>(
+            csum, B.csum_cells);
     }
     {
         PhaseScope ph(prof, kPhCount, s);
         constexpr int NT = DET ? 64 : kBinThreads;
         fwd_count_kernel<RM, NT, MF><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, ev.x, ev.y, ev.t, rho, ego,
-                                                            hist, hdrs);
+                                                            hist, csum, hdrs);
     }
     {
         PhaseScope ph(prof, kPhScan, s);
         const int gc = (int)((B.cells_f + 255) / 256);
-        chunk_sum_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_f, 0, hist, csum);
         chunk_scan_kernel<<<(int)((B.nbins + 255) / 256), 256, 0, s>>>(meta, nw, B.nbins, 0, csum,
                                                                         totals);
         scan_kernel<<<1, 1024, 0, s>>>(totals, B.nbins, start);
@@ -1261,13 +1263,15 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
     {
         PhaseScope ph(prof, kPhGradCount, s);
         launch_window_table(B, meta, wtab, s);
+        fill_u32_kernel<<<(int)std::min<int64_t>((B.csum_cells + 255) / 256, 4096), 256, 0, s>>>(
+            csum, B.csum_cells);
         constexpr int NT = DET ? 64 : kBinThreads;
-        bwd_count_kernel<RM, NT, MF><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, src, rho, ego, hdrs, hist);
+        bwd_count_kernel<RM, NT, MF><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, src, rho, ego,
+                                                                hdrs, hist, csum);
     }
     {
         PhaseScope ph(prof, kPhGradScan, s);
         const int gc = (int)((B.cells_b + 255) / 256);
-        chunk_sum_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_b, 1, hist, csum);
         chunk_scan_kernel<<<(int)((B.nbins_b + 255) / 256), 256, 0, s>>>(meta, nw, B.nbins_b, 1,
                                                                           csum, totals);
         scan_kernel<<<1, 1024, 0, s>>>(totals, B.nbins_b, start);

@@ -142,7 +142,7 @@ struct BatchPlanHost {
     bool det = false;       // deterministic mode
     std::vector<WinMeta> meta;
     int64_t n_events = 0, n_pixels = 0, n_sets = 0, img_elems = 0;
-    int64_t nbins = 0, nbins_b = 0, nblocks = 0, cells_f = 0, cells_b = 0;
+    int64_t nbins = 0, nbins_b = 0, nblocks = 0, cells_f = 0, cells_b = 0, csum_cells = 0;
     int max_R = 1, max_F = 1, max_lds_bins = 1;
     TileWorkspace ws;
 };
