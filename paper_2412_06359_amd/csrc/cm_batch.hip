@@ -442,12 +442,19 @@ __global__ __launch_bounds__(256) void window_table_kernel(const WinMeta* __rest
         tab[i] = window_of_bbin(meta, nw, i - nblk - nbin);
 }
 
+// Threads of the forward tile kernel: the deterministic mode keeps 256 (its
+// reduction order is defined on them); the atomic mode uses more, so that the
+// four blocks whose LDS tiles fit a CU keep more wavefronts in flight.
+constexpr int kTileThreadsDet = 256;
+constexpr int kTileThreads = 512;
+
 template <bool DET>
-__global__ __launch_bounds__(256) void fwd_tile_kernel(const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of,
+__global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile_kernel(const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of,
                                                        const SplatRec* __restrict__ rec,
                                                        const uint32_t* __restrict__ start,
                                                        double2* __restrict__ img_base,
                                                        double2* __restrict__ halo,
+                                                       double2* __restrict__ border,
                                                        double* __restrict__ part)
 {
     __shared__ double2 lds[2 * TLW * TLH];
@@ -523,15 +530,24 @@ __global__ __launch_bounds__(256) void fwd_tile_kernel(const WinMeta* __restrict
     double2* img = img_base + meta[w].img_off;
     double2* plane0 = img + (size_t)(r * 2 + 0) * P.HW;
     double2* plane1 = img + (size_t)(r * 2 + 1) * P.HW;
+    // interior pixels to the image; column 0 and row 0 to the border buffer,
+    // which the merge completes with the neighbours' halos and stores
+    double2* fb = border + gbin * NBORDER * 2;
     for (int i = threadIdx.x; i < TW * TH; i += blockDim.x) {
         const int lx = i % TW, ly = i / TW;
         const int X = xo + lx, Y = yo + ly;
         if (X >= P.W || Y >= P.H) continue;
         const double2 a = lds[ly * TLW + lx], b = lds[TLW * TLH + ly * TLW + lx];
+        if (lx == 0 || ly == 0) {
+            const int j = lx == 0 ? ly : TH + lx - 1;
+            fb[j * 2 + 0] = a;
+            fb[j * 2 + 1] = b;
+            continue;
+        }
         const int pix = Y * P.W + X;
         plane0[pix] = a;
         plane1[pix] = b;
-        if (lx > 0 && ly > 0) reduce_pixel(a, b, P.eps, sum, cnt);
+        reduce_pixel(a, b, P.eps, sum, cnt);
     }
     double2* hb = halo + gbin * NHALO * 2;
     for (int j = threadIdx.x; j < NHALO; j += blockDim.x) {
@@ -547,12 +563,14 @@ __global__ __launch_bounds__(256) void fwd_tile_kernel(const WinMeta* __restrict
     }
 }
 
-// Column 0 and row 0 of each tile: add the halos of the left, top and
-// top-left tiles (in that order), store, and reduce those pixels.
+// Column 0 and row 0 of each tile: the tile's own values (border buffer) plus
+// the halos of the left, top and top-left tiles (in that order); store and
+// reduce those pixels.
 __global__ __launch_bounds__(64) void fwd_merge_kernel(const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of,
                                                        const uint32_t* __restrict__ start,
                                                        double2* __restrict__ img_base,
                                                        const double2* __restrict__ halo,
+                                                       const double2* __restrict__ border,
                                                        double* __restrict__ part)
 {
     __shared__ double red[16];
@@ -575,7 +593,7 @@ __global__ __launch_bounds__(64) void fwd_merge_kernel(const WinMeta* __restrict
         double2 v[2];
 #pragma unroll
         for (int pol = 0; pol < 2; ++pol) {
-            double2 a = own ? img[(size_t)(r * 2 + pol) * P.HW + pix] : make_double2(0.0, 0.0);
+            double2 a = own ? border[(gbin * NBORDER + j) * 2 + pol] : make_double2(0.0, 0.0);
             if (lx == 0 && tx > 0) {
                 const double2 h = halo[((gbin - 1) * NHALO + ly) * 2 + pol];
                 a.x += h.x;
@@ -1146,7 +1164,8 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     B.ws.totals = take((size_t)(bins + 1) * sizeof(uint32_t));
     B.ws.start = take((size_t)(bins + 1) * sizeof(uint32_t));
     B.ws.part = take((size_t)std::max(bin * 4, bbin * 12) * sizeof(double));
-    B.ws.halo = take((size_t)std::max<int64_t>(bin * NHALO * 2, bbin * (NHALO + NBORDER)) *
+    B.ws.halo = take((size_t)std::max<int64_t>(bin * (NHALO + NBORDER) * 2,
+                                               bbin * (NHALO + NBORDER)) *
                      sizeof(double2));
     B.ws.records = take((size_t)recs * std::max(sizeof(SplatRec), sizeof(GradRec)));
     B.ws.src = take((size_t)ev * sizeof(SrcRec));
@@ -1176,6 +1195,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     uint32_t* start = reinterpret_cast<uint32_t*>(ws + B.ws.start);
     double* part = reinterpret_cast<double*>(ws + B.ws.part);
     double2* halo = reinterpret_cast<double2*>(ws + B.ws.halo);
+    double2* fborder = halo + B.nbins * NHALO * 2;
     SplatRec* rec = reinterpret_cast<SplatRec*>(ws + B.ws.records);
     SrcRec* src = reinterpret_cast<SrcRec*>(ws + B.ws.src);
     int* wtab = reinterpret_cast<int*>(ws + B.ws.win);
@@ -1211,11 +1231,13 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     }
     {
         PhaseScope ph(prof, kPhSplat, s);
-        fwd_tile_kernel<DET><<<(int)B.nbins, 256, 0, s>>>(meta, nw, win_bin, rec, start, img, halo, part);
+        fwd_tile_kernel<DET><<<(int)B.nbins, DET ? kTileThreadsDet : kTileThreads, 0, s>>>(
+            meta, nw, win_bin, rec, start, img, halo, fborder, part);
     }
     {
         PhaseScope ph(prof, kPhReduce, s);
-        fwd_merge_kernel<<<(int)B.nbins, 64, 0, s>>>(meta, nw, win_bin, start, img, halo, part);
+        fwd_merge_kernel<<<(int)B.nbins, 64, 0, s>>>(meta, nw, win_bin, start, img, halo, fborder,
+                                                     part);
     }
     {
         PhaseScope ph(prof, kPhFinalize, s);
