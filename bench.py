@@ -194,15 +194,21 @@ def serve_stream(cm, seconds: float, rate: float, budget_gib: float) -> dict:
     srv.latencies.clear()
     srv.events_done = srv.windows_done = srv.batches = 0
     srv.t_first = srv.t_last = None
-    futs = []
+    # the client consumes each result as it arrives (holding every window's
+    # gradients until the end would grow device memory by ~8 GB over the
+    # stream and time the allocator instead of the server)
+    import collections
+    pending = collections.deque()
     t0 = time.perf_counter()
     for (ta, _, _), w in zip(trace, reqs):
         dt = t0 + ta - time.perf_counter()
         if dt > 0:
             time.sleep(dt)
-        futs.append(srv.submit(w))
-    for f in futs:
-        f.result(timeout=300)
+        pending.append(srv.submit(w))
+        while pending and pending[0].done():
+            pending.popleft().result()
+    while pending:
+        pending.popleft().result(timeout=300)
     srv.drain()
     st = srv.stats()
     srv.close()

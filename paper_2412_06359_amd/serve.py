@@ -53,6 +53,50 @@ def window_footprint(desc: WindowDesc, n_events: int) -> int:
     return binding.state_bytes(desc, n_events) + 13 * n_events + 8 * hw * desc.F + 48 * desc.F + 16
 
 
+class _Staging:
+    """A stream slot's pinned host buffer, reused from batch to batch and grown
+    when a batch needs more (allocating pinned memory per batch costs
+    milliseconds, which showed up in the tail latency).  A slot's buffer is
+    refilled only after its previous batch has retired, so its copies are
+    complete."""
+
+    def __init__(self):
+        self.buf = None
+        self.loss = None
+        self.dev = None
+
+    def device_buffer(self, nbytes, device):
+        """The slot's device workspace (inputs and state of its batch: the
+        caller gets only the gradients, which are allocated per batch)."""
+        if self.dev is None or self.dev.numel() < nbytes:
+            cap = max(nbytes, 2 * (self.dev.numel() if self.dev is not None else 0))
+            self.dev = torch.empty(cap, dtype=torch.uint8, device=device)
+        return self.dev
+
+    def arrays(self, spec):
+        """spec: [(name, numpy dtype, count)] -> {name: numpy view} in one
+        pinned buffer (16-byte aligned pieces) and {name: torch view}."""
+        offs, total = [], 0
+        for _, dt, cnt in spec:
+            offs.append(total)
+            total += (np.dtype(dt).itemsize * cnt + 15) // 16 * 16
+        if self.buf is None or self.buf.numel() < total:
+            cap = max(total, 2 * (self.buf.numel() if self.buf is not None else 0))
+            self.buf = torch.empty(cap, dtype=torch.uint8, pin_memory=True)
+        raw = self.buf.numpy()
+        np_views, t_views = {}, {}
+        for (name, dt, cnt), o in zip(spec, offs):
+            nb = np.dtype(dt).itemsize * cnt
+            np_views[name] = raw[o:o + nb].view(dt)
+            t_views[name] = self.buf[o:o + nb].view(torch.int8 if dt == np.int8 else torch.float32)
+        return np_views, t_views
+
+    def loss_buffer(self, n):
+        if self.loss is None or self.loss.numel() < n:
+            self.loss = torch.empty(max(n, 64), dtype=torch.float32, pin_memory=True)
+        return self.loss[:n]
+
+
 class _InFlight:
     def __init__(self, reqs, batch, stream, event, keep, loss_host, footprint):
         self.reqs = reqs
@@ -78,6 +122,7 @@ class Server:
         self._lock = threading.Lock()
         self._wake = threading.Event()
         self._streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
+        self._staging = [_Staging() for _ in range(n_streams)]
         self._busy = [None] * n_streams
         self._used = 0
         self._running = True
@@ -201,37 +246,55 @@ class Server:
             return False
         if self.t_first is None:
             self.t_first = min(r.t_arrival for r in reqs)
-        self._busy[slot] = self._launch(reqs, self._streams[slot], fp)
+        try:
+            self._busy[slot] = self._launch(reqs, self._streams[slot], self._staging[slot], fp)
+        except Exception as exc:       # these requests fail; the server keeps serving
+            with self._lock:
+                self._used -= fp
+            for r in reqs:
+                r.future.set_exception(exc)
+            return True
         self.batches += 1
         return True
 
-    def _launch(self, reqs, stream, fp) -> _InFlight:
+    def _launch(self, reqs, stream, staging, fp) -> _InFlight:
         wins = [r.window for r in reqs]
         batch = binding.Batch([r.desc for r in reqs], [r.n for r in reqs], device=self.device)
         dev = torch.device("cuda", self.device)
-
-        def pinned(arrs, dtype):
-            a = np.concatenate([np.asarray(v, dtype=dtype).ravel() for v in arrs])
-            return torch.from_numpy(a).pin_memory()
-
-        host = {"x": pinned([w.x for w in wins], np.float32),
-                "y": pinned([w.y for w in wins], np.float32),
-                "t": pinned([w.t for w in wins], np.float32),
-                "p": pinned([w.p for w in wins], np.int8),
-                "rho": pinned([w.rho for w in wins], np.float32),
-                "ego": pinned([w.theta for w in wins], np.float32)}
+        n = batch.event_offsets[-1]
+        spec = [("x", np.float32, n), ("y", np.float32, n), ("t", np.float32, n),
+                ("p", np.int8, n), ("rho", np.float32, batch.pixel_offsets[-1]),
+                ("ego", np.float32, 6 * batch.set_offsets[-1])]
+        host, tv = staging.arrays(spec)
+        for name, field in (("x", "x"), ("y", "y"), ("t", "t"), ("p", "p"), ("rho", "rho"),
+                            ("ego", "theta")):
+            dt = host[name].dtype
+            np.concatenate([np.asarray(getattr(w, field), dtype=dt).ravel() for w in wins],
+                           out=host[name])
         with torch.cuda.stream(stream):
-            d = {k: v.to(dev, non_blocking=True) for k, v in host.items()}
-            state = batch.new_state()
-            loss = torch.empty(batch.n, dtype=torch.float32, device=dev)
-            gl = torch.ones(batch.n, dtype=torch.float32, device=dev)
+            # one device workspace per slot: inputs, state, loss, grad_loss
+            sizes = [v.numel() * v.element_size() for v in tv.values()] + \
+                [batch.state_bytes, 4 * batch.n, 4 * batch.n]
+            offs, total = [], 0
+            for nb in sizes:
+                offs.append(total)
+                total += (nb + 255) // 256 * 256
+            dbuf = staging.device_buffer(total, dev)
+            d = {}
+            for (k, v), o, nb in zip(tv.items(), offs, sizes):
+                d[k] = dbuf[o:o + nb].view(v.dtype)
+                d[k].copy_(v, non_blocking=True)
+            state = dbuf[offs[6]:offs[6] + batch.state_bytes]
+            loss = dbuf[offs[7]:offs[7] + 4 * batch.n].view(torch.float32)
+            gl = dbuf[offs[8]:offs[8] + 4 * batch.n].view(torch.float32)
+            gl.fill_(1.0)
             batch.forward(d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"], state=state,
                           loss=loss)
             g_rho, g_ego = batch.backward(d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"],
                                           state, gl)
-            loss_host = torch.empty(batch.n, dtype=torch.float32).pin_memory()
+            loss_host = staging.loss_buffer(batch.n)
             loss_host.copy_(loss, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(stream)
-        keep = dict(host=host, d=d, state=state, loss=loss, gl=gl, g_rho=g_rho, g_ego=g_ego)
+        keep = dict(d=d, state=state, loss=loss, gl=gl, g_rho=g_rho, g_ego=g_ego)
         return _InFlight(reqs, batch, stream, ev, keep, loss_host, fp)
