@@ -43,8 +43,10 @@ class Window:
     """One CM window: sensor, intrinsics, reference times, events, rho, theta.
 
     x, y, t are float32 arrays of length n, p is int8 (+1 / -1).  rho is the
-    per-pixel inverse depth, float32 [H, W] (row-major, row y, column x).
-    theta is float32 [6] = (v_x, v_y, v_z, w_x, w_y, w_z).
+    per-pixel inverse depth, float32 [H, W] (row-major, row y, column x), or
+    [F, H, W] for F flow sets.  theta is float32 [6] = (v_x, v_y, v_z, w_x,
+    w_y, w_z), or [F, 6].  flow_model: 0 for the first-order motion field of
+    Eq. 2, 1 for exact reprojection.
     """
 
     name: str
@@ -62,6 +64,7 @@ class Window:
     rho: np.ndarray
     theta: np.ndarray
     eps: float = EPS_DEFAULT
+    flow_model: int = 0
 
     @property
     def n(self) -> int:

@@ -45,14 +45,15 @@ def _load():
         build()
     lib = ctypes.CDLL(_LIB_PATH)
     P = ctypes.c_void_p
-    lib.cmo_flow_field.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P]
+    lib.cmo_flow_field.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P]
     lib.cmo_flow_field.restype = ctypes.c_int
     lib.cmo_forward.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double,
-                                ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P, P, P, P, P]
+                                ctypes.c_int, ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P, P,
+                                P, P, P]
     lib.cmo_forward.restype = ctypes.c_int
     lib.cmo_backward.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double,
-                                 ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P, ctypes.c_double,
-                                 P, P, P]
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P,
+                                 ctypes.c_double, P, P, P]
     lib.cmo_backward.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -91,14 +92,15 @@ def _eps(win):
     return ctypes.c_double(_as_f(win.eps))
 
 
-def flow_field(width, height, K, rho, theta) -> np.ndarray:
-    """Eq. 2 (first order): flow [H, W, 2] in px per window."""
+def flow_field(width, height, K, rho, theta, model: int = 0) -> np.ndarray:
+    """Eq. 2: flow [H, W, 2] in px per window (model 0: first order, 1: exact
+    reprojection)."""
     lib = _load()
     K = _f64(K)
     rho = _f64(rho)
     theta = _f64(theta)
     u = np.empty((height, width, 2), dtype=np.float64)
-    st = lib.cmo_flow_field(width, height, _ptr(K), _ptr(rho), _ptr(theta), _ptr(u))
+    st = lib.cmo_flow_field(width, height, _ptr(K), _ptr(rho), _ptr(theta), int(model), _ptr(u))
     if st != 0:
         raise ValueError(f"cmo_flow_field failed ({st})")
     return u
@@ -124,7 +126,7 @@ def forward(win, rho=None, theta=None, images=False, valid=False, positions=Fals
     val = np.zeros(n, dtype=np.uint8) if valid else None
     pos = np.zeros((n, R, 2), dtype=np.float64) if positions else None
     st = lib.cmo_forward(win.width, win.height, _ptr(K), R, _ptr(refs), _eps(win), F,
-                         n, _ptr(x), _ptr(y), _ptr(t), _ptr(p), _ptr(rho), _ptr(theta), _ptr(out),
+                         int(getattr(win, "flow_model", 0)), n, _ptr(x), _ptr(y), _ptr(t), _ptr(p), _ptr(rho), _ptr(theta), _ptr(out),
                          _ptr(img), _ptr(val), _ptr(pos))
     if st != 0:
         raise ValueError(f"cmo_forward failed ({st})")
@@ -156,7 +158,7 @@ def backward(win, rho=None, theta=None, grad_loss: float = 1.0, flow_grad=False)
     dth = np.zeros(lead + (6,), dtype=np.float64)
     dflow = np.zeros(lead + (win.height, win.width, 2), dtype=np.float64) if flow_grad else None
     st = lib.cmo_backward(win.width, win.height, _ptr(K), R, _ptr(refs), _eps(win), F,
-                          n, _ptr(x), _ptr(y), _ptr(t), _ptr(p), _ptr(rho), _ptr(theta),
+                          int(getattr(win, "flow_model", 0)), n, _ptr(x), _ptr(y), _ptr(t), _ptr(p), _ptr(rho), _ptr(theta),
                           ctypes.c_double(grad_loss), _ptr(drho), _ptr(dth), _ptr(dflow))
     if st != 0:
         raise ValueError(f"cmo_backward failed ({st})")

@@ -60,6 +60,7 @@ typedef struct {
     int R;
     double refs[CMO_MAX_REFS];
     double eps;
+    int model;                      /* flow model: 0 first order, 1 exact reprojection */
     int F;                          /* flow sets: 1, or one per segment */
     int nk;                         /* knots: sorted unique {0, 1} U refs */
     double knots[CMO_MAX_REFS + 2];
@@ -67,8 +68,10 @@ typedef struct {
 } cmo_cam;
 
 static int cmo_setup(cmo_cam* c, int W, int H, const double* K, int R, const double* refs,
-                     double eps, int F)
+                     double eps, int F, int model)
 {
+    if (model != 0 && model != 1) return CMO_BAD_ARG;
+    c->model = model;
     if (W <= 0 || H <= 0 || !K || !refs || R < 1 || R > CMO_MAX_REFS) return CMO_BAD_ARG;
     c->W = W; c->H = H;
     c->fx = K[0]; c->fy = K[1]; c->cx = K[2]; c->cy = K[3];
@@ -95,6 +98,85 @@ static int cmo_setup(cmo_cam* c, int W, int H, const double* K, int R, const dou
  * the segment that starts there. */
 static int cmo_set_fwd(const cmo_cam* c, int r) { return c->F == 1 ? 0 : c->kidx[r] - 1; }
 static int cmo_set_bwd(const cmo_cam* c, int r) { return c->F == 1 ? 0 : c->kidx[r]; }
+
+/* ---------------------------------------------------------------------------
+ * Rotation by exponential coordinates (Rodrigues' formula, Sec. 3.2) and the
+ * right Jacobian of the exponential map: R(w + d) = R(w) Exp(Jr(w) d) to
+ * first order in d.  With theta = |w| and K = [w]x,
+ *   R  = I + a K + b K^2,          a = sin(theta)/theta, b = (1 - cos theta)/theta^2
+ *   Jr = I - b K + c K^2,          c = (theta - sin theta)/theta^3
+ * (series in theta below 1e-4, where the closed forms lose digits).
+ * ------------------------------------------------------------------------- */
+static void cmo_skew(const double w[3], double K[9])
+{
+    K[0] = 0.0;   K[1] = -w[2]; K[2] = w[1];
+    K[3] = w[2];  K[4] = 0.0;   K[5] = -w[0];
+    K[6] = -w[1]; K[7] = w[0];  K[8] = 0.0;
+}
+
+static void cmo_matmul3(const double A[9], const double B[9], double C[9])
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k) acc += A[3 * i + k] * B[3 * k + j];
+            C[3 * i + j] = acc;
+        }
+}
+
+static void cmo_rodrigues(const double w[3], double R[9], double Jr[9])
+{
+    const double t2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    const double t = sqrt(t2);
+    double a, b, c;
+    if (t < 1e-4) {
+        a = 1.0 - t2 / 6.0;
+        b = 0.5 - t2 / 24.0;
+        c = 1.0 / 6.0 - t2 / 120.0;
+    } else {
+        a = sin(t) / t;
+        b = (1.0 - cos(t)) / t2;
+        c = (t - sin(t)) / (t2 * t);
+    }
+    double K[9], K2[9];
+    cmo_skew(w, K);
+    cmo_matmul3(K, K, K2);
+    for (int i = 0; i < 9; ++i) {
+        const double I = (i % 4 == 0) ? 1.0 : 0.0;
+        R[i] = I + a * K[i] + b * K2[i];
+        Jr[i] = I - b * K[i] + c * K2[i];
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Step 1b: flow from exact reprojection (Eq. 2 without the first-order
+ * expansion).  A pixel's ray x0 = (xbar/fx, ybar/fy, 1) at inverse depth rho
+ * is the point x0/rho; the pose maps it to R x0/rho + v, which projects like
+ *   p = R x0 + rho v,   u = (fx p_x/p_z + cx - i, fy p_y/p_z + cy - j)
+ * (depth cancels in the projection).  A point that lands on or behind the
+ * camera plane (p_z <= 0) has no image: its flow is taken as zero, with zero
+ * derivatives.
+ * ------------------------------------------------------------------------- */
+static int cmo_exact_point(const cmo_cam* c, int i, int j, double rho, const double th[6],
+                           double p[3], double x0[3], double R[9], double Jr[9])
+{
+    cmo_rodrigues(th + 3, R, Jr);
+    x0[0] = ((double)i - c->cx) / c->fx;
+    x0[1] = ((double)j - c->cy) / c->fy;
+    x0[2] = 1.0;
+    for (int k = 0; k < 3; ++k)
+        p[k] = R[3 * k + 0] * x0[0] + R[3 * k + 1] * x0[1] + R[3 * k + 2] * x0[2] + rho * th[k];
+    return p[2] > 0.0;
+}
+
+static void cmo_flow_exact(const cmo_cam* c, int i, int j, double rho, const double th[6],
+                           double u[2])
+{
+    double p[3], x0[3], R[9], Jr[9];
+    if (!cmo_exact_point(c, i, j, rho, th, p, x0, R, Jr)) { u[0] = 0.0; u[1] = 0.0; return; }
+    u[0] = c->fx * p[0] / p[2] + c->cx - (double)i;
+    u[1] = c->fy * p[1] / p[2] + c->cy - (double)j;
+}
 
 /* ---------------------------------------------------------------------------
  * Step 1: flow from inverse depth and ego-motion (Eq. 2, first order).
@@ -127,9 +209,11 @@ static void cmo_fill_flow(const cmo_cam* c, const double* rho, const double* the
     double th[6];
     for (int k = 0; k < 6; ++k) th[k] = theta[k];
     for (int j = 0; j < c->H; ++j)
-        for (int i = 0; i < c->W; ++i)
-            cmo_flow_at(c, i, j, rho[(size_t)j * c->W + i], th,
-                        &u[2 * ((size_t)j * c->W + i)]);
+        for (int i = 0; i < c->W; ++i) {
+            double* uij = &u[2 * ((size_t)j * c->W + i)];
+            if (c->model == 1) cmo_flow_exact(c, i, j, rho[(size_t)j * c->W + i], th, uij);
+            else cmo_flow_at(c, i, j, rho[(size_t)j * c->W + i], th, uij);
+        }
 }
 
 /* ---------------------------------------------------------------------------
@@ -324,11 +408,11 @@ static int cmo_forward_impl(cmo_fwd* f, int64_t n, const double* x, const double
  * Public: flow field only (for tests of Eq. 2).
  * ------------------------------------------------------------------------- */
 int cmo_flow_field(int W, int H, const double* K, const double* rho, const double* theta,
-                   double* u_out)
+                   int model, double* u_out)
 {
     cmo_cam c;
     const double one = 1.0;
-    int st = cmo_setup(&c, W, H, K, 1, &one, 1e-9, 1);
+    int st = cmo_setup(&c, W, H, K, 1, &one, 1e-9, 1, model);
     if (st) return st;
     if (!rho || !theta || !u_out) return CMO_BAD_ARG;
     cmo_fill_flow(&c, rho, theta, u_out);
@@ -343,14 +427,14 @@ int cmo_flow_field(int W, int H, const double* K, const double* rho, const doubl
  *   valid (optional): [n] 0/1.   pos (optional): [n][R][2], NaN if unvisited.
  * ------------------------------------------------------------------------- */
 int cmo_forward(int W, int H, const double* K, int R, const double* refs, double eps, int F,
-                int64_t n,
+                int model, int64_t n,
                 const double* x, const double* y, const double* t, const int8_t* p,
                 const double* rho, const double* theta, double* out, double* img,
                 uint8_t* valid, double* pos)
 {
     cmo_fwd f;
     memset(&f, 0, sizeof f);
-    int st = cmo_setup(&f.cam, W, H, K, R, refs, eps, F);
+    int st = cmo_setup(&f.cam, W, H, K, R, refs, eps, F, model);
     if (st) return st;
     if (n < 0 || !rho || !theta || !out || (n > 0 && (!x || !y || !t || !p)))
         return CMO_BAD_ARG;
@@ -438,7 +522,31 @@ static void cmo_reverse_sweep(const cmo_cam* c, const double* u, const double* i
     }
 }
 
-/* Chain dL/du through Eq. 2 (first order) to rho and theta. */
+/* Exact model: with J = du/dp = [[fx/pz, 0, -fx px/pz^2], [0, fy/pz, -fy py/pz^2]]
+ * and q = J^T g,
+ *   d rho  += q . v,     d v += rho q,     d w += (d(R x0)/dw)^T q,
+ *   d(R x0)/dw = -R [x0]x Jr(w)   (so (.)^T q = -Jr^T [x0]x^T R^T q = Jr^T (x0 x (R^T q))). */
+static void cmo_chain_exact_pixel(const cmo_cam* c, int i, int j, double rho,
+                                  const double th[6], double gx, double gy, double* drho,
+                                  double dth[6])
+{
+    double p[3], x0[3], R[9], Jr[9];
+    *drho = 0.0;
+    if (!cmo_exact_point(c, i, j, rho, th, p, x0, R, Jr)) return;
+    const double iz = 1.0 / p[2];
+    const double q[3] = {gx * c->fx * iz, gy * c->fy * iz,
+                         -(gx * c->fx * p[0] + gy * c->fy * p[1]) * iz * iz};
+    *drho = q[0] * th[0] + q[1] * th[1] + q[2] * th[2];
+    for (int k = 0; k < 3; ++k) dth[k] += rho * q[k];
+    double s[3];                                   /* R^T q */
+    for (int k = 0; k < 3; ++k) s[k] = R[0 * 3 + k] * q[0] + R[1 * 3 + k] * q[1] + R[2 * 3 + k] * q[2];
+    const double cr[3] = {x0[1] * s[2] - x0[2] * s[1], x0[2] * s[0] - x0[0] * s[2],
+                          x0[0] * s[1] - x0[1] * s[0]};   /* x0 x (R^T q) */
+    for (int k = 0; k < 3; ++k)
+        dth[3 + k] += Jr[0 * 3 + k] * cr[0] + Jr[1 * 3 + k] * cr[1] + Jr[2 * 3 + k] * cr[2];
+}
+
+/* Chain dL/du through Eq. 2 (first order, or exact) to rho and theta. */
 static void cmo_chain(const cmo_cam* c, const double* rho, const double* theta,
                       const double* dflow, double* drho, double* dth)
 {
@@ -448,6 +556,10 @@ static void cmo_chain(const cmo_cam* c, const double* rho, const double* theta,
         for (int i = 0; i < c->W; ++i) {
             const size_t pix = (size_t)j * c->W + i;
             const double gx = dflow[2 * pix], gy = dflow[2 * pix + 1];
+            if (c->model == 1) {
+                cmo_chain_exact_pixel(c, i, j, rho[pix], theta, gx, gy, &drho[pix], dth);
+                continue;
+            }
             const double xb = (double)i - c->cx, yb = (double)j - c->cy;
             const double rh = rho[pix];
             /* u_x = fx a1 - xb a3, u_y = fy a2 - yb a3 */
@@ -466,14 +578,14 @@ static void cmo_chain(const cmo_cam* c, const double* rho, const double* theta,
  *   dflow (optional) [F][H*W*2] = grad_loss * dL/du.
  * ------------------------------------------------------------------------- */
 int cmo_backward(int W, int H, const double* K, int R, const double* refs, double eps, int F,
-                 int64_t n,
+                 int model, int64_t n,
                  const double* x, const double* y, const double* t, const int8_t* p,
                  const double* rho, const double* theta, double grad_loss, double* drho,
                  double* dtheta, double* dflow_out)
 {
     cmo_fwd f;
     memset(&f, 0, sizeof f);
-    int st = cmo_setup(&f.cam, W, H, K, R, refs, eps, F);
+    int st = cmo_setup(&f.cam, W, H, K, R, refs, eps, F, model);
     if (st) return st;
     if (n < 0 || !rho || !theta || !drho || !dtheta || (n > 0 && (!x || !y || !t || !p)))
         return CMO_BAD_ARG;
