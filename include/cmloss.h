@@ -9,8 +9,9 @@
  * every event to all reference times, bilinear splatting into per-polarity
  * images of warped events, active-pixel normalisation, masking of events that
  * leave the image); the flow comes from inverse depth and ego-motion through
- * Eq. 2 of Sec. 3.2 (taken in its first-order, motion-field form); the
- * gradient is the analytic backward of Sec. 3.3.
+ * Eq. 2 of Sec. 3.2 (by default in its first-order, motion-field form; the
+ * exact reprojection is a per-window option); the gradient is the analytic
+ * backward of Sec. 3.3.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -91,7 +92,17 @@ typedef struct {
     float eps;                      /* regulariser of Eq. 1's ratios, finite and > 0 (1e-9 by default) */
     int32_t n_flows;                /* F: 0 or 1 (one flow), or the number of segments between
                                        consecutive knots {0, 1} U refs */
+    int32_t flow_model;             /* CM_FLOW_* */
 } cm_window_desc;
+
+/* How Eq. 2 turns inverse depth and ego-motion into a flow (pixels per
+ * window).  FIRST_ORDER: the motion field, linear in (v, w) and in rho
+ * (u = A(x) w + rho B(x) v).  EXACT: the pixel is back-projected with depth
+ * 1/rho, moved by the rigid motion (rotation exp([w]x) by Rodrigues' formula,
+ * then translation v) and projected again; u = projection - pixel, and a point
+ * that lands on or behind the camera plane (z <= 0) has zero flow and no
+ * gradient.  The two agree to first order in (v, w). */
+enum { CM_FLOW_FIRST_ORDER = 0, CM_FLOW_EXACT = 1 };
 
 /* Create a handle bound to HIP device `device`.  *h receives the handle. */
 cm_status cm_create(cm_handle* h, int device);
@@ -164,7 +175,7 @@ cm_status cm_state_diagnostics(const cm_window_desc* d, const void* state, doubl
 /* Batches (the tiled path over many windows in one launch sequence).
  *
  * A plan fixes a batch's shape: n_windows descriptors (host memory, all with
- * the same mode) and their event counts.  Events of all windows are packed in
+ * the same mode and flow model) and their event counts.  Events of all windows are packed in
  * flat device arrays, window w at [event_offsets[w], event_offsets[w+1]), in
  * window order; inverse depth and d inverse depth likewise at
  * [pixel_offsets[w], pixel_offsets[w+1]) (F * height * width floats each);

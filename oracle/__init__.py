@@ -126,7 +126,7 @@ def forward(win, rho=None, theta=None, images=False, valid=False, positions=Fals
     val = np.zeros(n, dtype=np.uint8) if valid else None
     pos = np.zeros((n, R, 2), dtype=np.float64) if positions else None
     st = lib.cmo_forward(win.width, win.height, _ptr(K), R, _ptr(refs), _eps(win), F,
-                         int(getattr(win, "flow_model", 0)), n, _ptr(x), _ptr(y), _ptr(t), _ptr(p), _ptr(rho), _ptr(theta), _ptr(out),
+                         _flow_model(win), n, _ptr(x), _ptr(y), _ptr(t), _ptr(p), _ptr(rho), _ptr(theta), _ptr(out),
                          _ptr(img), _ptr(val), _ptr(pos))
     if st != 0:
         raise ValueError(f"cmo_forward failed ({st})")
@@ -158,7 +158,7 @@ def backward(win, rho=None, theta=None, grad_loss: float = 1.0, flow_grad=False)
     dth = np.zeros(lead + (6,), dtype=np.float64)
     dflow = np.zeros(lead + (win.height, win.width, 2), dtype=np.float64) if flow_grad else None
     st = lib.cmo_backward(win.width, win.height, _ptr(K), R, _ptr(refs), _eps(win), F,
-                          int(getattr(win, "flow_model", 0)), n, _ptr(x), _ptr(y), _ptr(t), _ptr(p), _ptr(rho), _ptr(theta),
+                          _flow_model(win), n, _ptr(x), _ptr(y), _ptr(t), _ptr(p), _ptr(rho), _ptr(theta),
                           ctypes.c_double(grad_loss), _ptr(drho), _ptr(dth), _ptr(dflow))
     if st != 0:
         raise ValueError(f"cmo_backward failed ({st})")
@@ -184,6 +184,14 @@ def build_mirror() -> str:
     return _MIRROR_PATH
 
 
+def _flow_model(win) -> int:
+    """0: first-order flow (motion field), 1: exact reprojection."""
+    m = int(getattr(win, "flow_model", 0))
+    if m not in (0, 1):
+        raise ValueError(f"flow_model must be 0 or 1, got {m}")
+    return m
+
+
 def _load_mirror():
     global _mirror
     if _mirror is None:
@@ -192,11 +200,12 @@ def _load_mirror():
         lib = ctypes.CDLL(_MIRROR_PATH)
         P = ctypes.c_void_p
         lib.cmm_forward.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_float,
-                                    ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P, P, P]
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P,
+                                    P, P]
         lib.cmm_forward.restype = ctypes.c_int
         lib.cmm_backward.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P,
-                                     ctypes.c_float, ctypes.c_int, ctypes.c_int64, P, P, P, P, P,
-                                     P, ctypes.c_float, P, P]
+                                     ctypes.c_float, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                     P, P, P, P, P, P, ctypes.c_float, P, P]
         lib.cmm_backward.restype = ctypes.c_int
         _mirror = lib
     return _mirror
@@ -217,7 +226,7 @@ def mirror_forward(win) -> dict:
     loss = np.zeros(1, np.float32)
     hdr = np.zeros(2 + 2 * R, np.float64)
     st = lib.cmm_forward(win.width, win.height, _ptr(K), R, _ptr(refs), float(np.float32(win.eps)),
-                         n_flows(rho), x.shape[0], _ptr(x), _ptr(y), _ptr(t), _ptr(p), _ptr(rho), _ptr(th),
+                         n_flows(rho), _flow_model(win), x.shape[0], _ptr(x), _ptr(y), _ptr(t), _ptr(p), _ptr(rho), _ptr(th),
                          _ptr(loss), _ptr(hdr))
     if st != 0:
         raise ValueError(f"cmm_forward failed ({st})")
@@ -236,7 +245,7 @@ def mirror_backward(win, grad_loss: float = 1.0) -> dict:
     drho = np.zeros(lead + (win.height, win.width), np.float32)
     dth = np.zeros(lead + (6,), np.float32)
     st = lib.cmm_backward(win.width, win.height, _ptr(K), R, _ptr(refs),
-                          float(np.float32(win.eps)), F, x.shape[0], _ptr(x), _ptr(y), _ptr(t),
+                          float(np.float32(win.eps)), F, _flow_model(win), x.shape[0], _ptr(x), _ptr(y), _ptr(t),
                           _ptr(p), _ptr(rho), _ptr(th), float(np.float32(grad_loss)), _ptr(drho),
                           _ptr(dth))
     if st != 0:

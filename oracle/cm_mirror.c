@@ -17,6 +17,20 @@
  *    s = k3 xb - k2 yb, Ax = (k0 - k1 yb) + xb s, Ay = (k4 + k5 xb) + yb s,
  *    Bx = tvx - xb vz, By = tvy - yb vz, u = (Ax + rho Bx, Ay + rho By).
  *    Every operation is a separate IEEE FP64 operation (no fused multiply-add).
+ *  - Exact flow (Eq. 2 without the first-order expansion): with t^2 = s =
+ *    (wx^2 + wy^2) + wz^2 and series(s, o) = 1 - (s/d_1)(1 - (s/d_2)(...)),
+ *    d_k = (o + 2k - 1)(o + 2k), 18 terms, Horner from the innermost:
+ *    a = series(s, 1), b = 0.5 series(s, 2), c = series(s, 3) / 6;
+ *    K = [w]x, K2 = K K (entries (K_i0 K_0j + K_i1 K_1j) + K_i2 K_2j),
+ *    R = (I + a K) + b K2, Jr = (I - b K) + c K2.  At pixel (i, j):
+ *    xn = (i - cx) inv_fx, yn = (j - cy) inv_fy,
+ *    p_k = (R_k0 xn + (R_k1 yn + R_k2)) + rho v_k; if p_z > 0, iz = 1/p_z,
+ *    u = ((fx p_x) iz + (cx - i), (fy p_y) iz + (cy - j)), else u = 0.
+ *    The chain of dL/du = g at a pixel: ax = gx fx, ay = gy fy,
+ *    q = (ax iz, ay iz, -((ax p_x + ay p_y) iz) iz), d rho = (q_x v_x + q_y v_y)
+ *    + q_z v_z, d v_k += rho q_k, s_k = (R_0k q_x + R_1k q_y) + R_2k q_z,
+ *    c = (yn s_z - s_y, s_x - xn s_z, xn s_y - yn s_x),
+ *    d w_k += (Jr_0k c_0 + Jr_1k c_1) + Jr_2k c_2.
  *  - Bilinear sample: ux = ((((0 + w0 u0) + w1 u1) + w2 u2) + w3 u3) with
  *    u = 0 for taps off the sensor; w_q = wa * wb.
  *  - Warp: one loop over the visits (forward references from t_k upward, then
@@ -65,6 +79,9 @@ typedef struct {
     double k4[MM_MAX_FLOWS], k5[MM_MAX_FLOWS], tvx[MM_MAX_FLOWS], tvy[MM_MAX_FLOWS];
     double vz[MM_MAX_FLOWS];
     int sf[MM_MAX_REFS], sb[MM_MAX_REFS];
+    /* exact flow (model 1): rotation, translation, right Jacobian per set */
+    int model;
+    double Rm[MM_MAX_FLOWS][9], v[MM_MAX_FLOWS][3], Jr[MM_MAX_FLOWS][9];
     const float* rho;
     /* tiles */
     int ntx, nty, ntiles, ept, nblocks;
@@ -72,10 +89,35 @@ typedef struct {
 
 typedef struct { double x, y; } d2;
 
-static int mm_setup(mm_win* w, int W, int H, const float* K, int R, const float* refs, float eps,
-                    int F, const float* rho, const float* theta, int64_t n)
+static double mm_series(double s, int o)
 {
-    if (W <= 0 || H <= 0 || R < 1 || R > MM_MAX_REFS) return MM_BAD;
+    double h = 1.0;
+    for (int k = 18; k >= 1; --k) {
+        const double d = (double)(o + 2 * k - 1) * (double)(o + 2 * k);
+        h = 1.0 - (s / d) * h;
+    }
+    return h;
+}
+
+static void mm_rotation(const float* th, double* Rm, double* Jr)
+{
+    const double wx = th[3], wy = th[4], wz = th[5];
+    const double s = (wx * wx + wy * wy) + wz * wz;
+    const double a = mm_series(s, 1), b = 0.5 * mm_series(s, 2), c = mm_series(s, 3) / 6.0;
+    const double K[9] = {0.0, -wz, wy, wz, 0.0, -wx, -wy, wx, 0.0};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const double k2 = (K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j]) + K[3 * i + 2] * K[6 + j];
+            const double I = i == j ? 1.0 : 0.0;
+            Rm[3 * i + j] = (I + a * K[3 * i + j]) + b * k2;
+            Jr[3 * i + j] = (I - b * K[3 * i + j]) + c * k2;
+        }
+}
+
+static int mm_setup(mm_win* w, int W, int H, const float* K, int R, const float* refs, float eps,
+                    int F, int model, const float* rho, const float* theta, int64_t n)
+{
+    if (W <= 0 || H <= 0 || R < 1 || R > MM_MAX_REFS || (model != 0 && model != 1)) return MM_BAD;
     memset(w, 0, sizeof *w);
     w->W = W; w->H = H; w->R = R; w->HW = W * H;
     w->fx = K[0]; w->fy = K[1]; w->cx = K[2]; w->cy = K[3];
@@ -107,7 +149,10 @@ static int mm_setup(mm_win* w, int W, int H, const float* K, int R, const float*
         w->tvx[f] = w->fx * vx;
         w->tvy[f] = w->fy * vy;
         w->vz[f] = vz;
+        mm_rotation(th, w->Rm[f], w->Jr[f]);
+        w->v[f][0] = vx; w->v[f][1] = vy; w->v[f][2] = vz;
     }
+    w->model = model;
     w->rho = rho;
     w->ntx = (W + TW - 1) / TW;
     w->nty = (H + TH - 1) / TH;
@@ -134,8 +179,31 @@ static void mm_parts(const mm_win* w, int f, int i, int j, double* Ax, double* A
     *By = w->tvy[f] - yb * w->vz[f];
 }
 
+/* the exact model's camera-frame point of pixel (i, j) after the motion */
+static void mm_point(const mm_win* w, int f, int i, int j, double r, double* xn, double* yn,
+                     double p[3])
+{
+    const double* Rm = w->Rm[f];
+    *xn = ((double)i - w->cx) * w->inv_fx;
+    *yn = ((double)j - w->cy) * w->inv_fy;
+    for (int k = 0; k < 3; ++k)
+        p[k] = (Rm[3 * k] * *xn + (Rm[3 * k + 1] * *yn + Rm[3 * k + 2])) + r * w->v[f][k];
+}
+
 static d2 mm_flow(const mm_win* w, int f, int i, int j)
 {
+    if (w->model == 1) {
+        const double r = (double)w->rho[(size_t)f * w->HW + j * w->W + i];
+        double xn, yn, p[3];
+        mm_point(w, f, i, j, r, &xn, &yn, p);
+        d2 u = {0.0, 0.0};
+        if (p[2] > 0.0) {
+            const double iz = 1.0 / p[2];
+            u.x = (w->fx * p[0]) * iz + (w->cx - (double)i);
+            u.y = (w->fy * p[1]) * iz + (w->cy - (double)j);
+        }
+        return u;
+    }
     double Ax, Ay, Bx, By;
     mm_parts(w, f, i, j, &Ax, &Ay, &Bx, &By);
     const double r = (double)w->rho[(size_t)f * w->HW + j * w->W + i];
@@ -414,12 +482,12 @@ static int mm_forward_impl(mm_state* S, int64_t n, const float* ex, const float*
 }
 
 int cmm_forward(int W, int H, const float* K, int R, const float* refs, float eps, int F,
-                int64_t n, const float* x, const float* y, const float* t, const int8_t* p,
+                int model, int64_t n, const float* x, const float* y, const float* t, const int8_t* p,
                 const float* rho, const float* theta, float* loss_out, double* hdr_out)
 {
     mm_state S;
     memset(&S, 0, sizeof S);
-    if (mm_setup(&S.w, W, H, K, R, refs, eps, F, rho, theta, n)) return MM_BAD;
+    if (mm_setup(&S.w, W, H, K, R, refs, eps, F, model, rho, theta, n)) return MM_BAD;
     const int st = mm_forward_impl(&S, n, x, y, t, p);
     if (st == MM_OK) {
         *loss_out = (float)S.loss;
@@ -486,6 +554,35 @@ static void mm_dtheta(const mm_win* w, int i, int j, double r, double gx, double
     dth[5] += (w->fy_over_fx * xb) * gy - (w->fx_over_fy * yb) * gx;
 }
 
+/* d rho of dL/du = (gx, gy) at pixel (i, j) of set f; the pixel's d theta
+ * share is added into dth (both models) */
+static double mm_chain(const mm_win* w, int f, int i, int j, double r, double gx, double gy,
+                       double* dth)
+{
+    if (w->model == 1) {
+        double xn, yn, p[3];
+        mm_point(w, f, i, j, r, &xn, &yn, p);
+        if (!(p[2] > 0.0)) return 0.0;
+        const double* Rm = w->Rm[f];
+        const double* v = w->v[f];
+        const double* Jr = w->Jr[f];
+        const double iz = 1.0 / p[2];
+        const double ax = gx * w->fx, ay = gy * w->fy;
+        const double q[3] = {ax * iz, ay * iz, -((ax * p[0] + ay * p[1]) * iz) * iz};
+        const double drho = (q[0] * v[0] + q[1] * v[1]) + q[2] * v[2];
+        for (int k = 0; k < 3; ++k) dth[k] += r * q[k];
+        double sv[3];
+        for (int k = 0; k < 3; ++k) sv[k] = (Rm[k] * q[0] + Rm[3 + k] * q[1]) + Rm[6 + k] * q[2];
+        const double c[3] = {yn * sv[2] - sv[1], sv[0] - xn * sv[2], xn * sv[1] - yn * sv[0]};
+        for (int k = 0; k < 3; ++k) dth[3 + k] += (Jr[k] * c[0] + Jr[3 + k] * c[1]) + Jr[6 + k] * c[2];
+        return drho;
+    }
+    double Ax, Ay, Bx, By;
+    mm_parts(w, f, i, j, &Ax, &Ay, &Bx, &By);
+    if (gx != 0.0 || gy != 0.0) mm_dtheta(w, i, j, r, gx, gy, dth);
+    return gx * Bx + gy * By;
+}
+
 /* One wavefront-iteration of the sweep: the per-lane reverse passes run in
  * lockstep; records are emitted at each program point in lane order. */
 typedef struct {
@@ -502,13 +599,13 @@ static void mm_emit(const mm_win* w, mm_grec* rec, int64_t* fill, int f, double 
 }
 
 int cmm_backward(int W, int H, const float* K, int R, const float* refs, float eps, int F,
-                 int64_t n, const float* x, const float* y, const float* t, const int8_t* p,
+                 int model, int64_t n, const float* x, const float* y, const float* t, const int8_t* p,
                  const float* rho, const float* theta, float grad_loss, float* drho_out,
                  float* dtheta_out)
 {
     mm_state S;
     memset(&S, 0, sizeof S);
-    if (mm_setup(&S.w, W, H, K, R, refs, eps, F, rho, theta, n)) return MM_BAD;
+    if (mm_setup(&S.w, W, H, K, R, refs, eps, F, model, rho, theta, n)) return MM_BAD;
     int st = mm_forward_impl(&S, n, x, y, t, p);
     if (st) { free(S.img); return st; }
     const mm_win* w = &S.w;
@@ -666,16 +763,14 @@ int cmm_backward(int W, int H, const float* K, int R, const float* refs, float e
                 border[(size_t)b * NBORDER + (lx == 0 ? ly : TH + lx - 1)] = g;
                 continue;
             }
-            double Ax, Ay, Bx, By;
-            mm_parts(w, f, X, Y, &Ax, &Ay, &Bx, &By);
             const int pix = Y * w->W + X;
-            drho_f[pix] = (float)(gl * (g.x * Bx + g.y * By));
-            if (g.x != 0.0 || g.y != 0.0) {
-                double d[6];
-                for (int c = 0; c < 6; ++c) d[c] = red[c * 256 + i % 256];
-                mm_dtheta(w, X, Y, (double)rho_f[pix], g.x, g.y, d);
-                for (int c = 0; c < 6; ++c) red[c * 256 + i % 256] = d[c];
-            }
+            double d[6];
+            for (int c = 0; c < 6; ++c) d[c] = red[c * 256 + i % 256];
+            double dr = 0.0;
+            if (w->model == 0 || g.x != 0.0 || g.y != 0.0)
+                dr = mm_chain(w, f, X, Y, (double)rho_f[pix], g.x, g.y, d);
+            drho_f[pix] = (float)(gl * dr);
+            for (int c = 0; c < 6; ++c) red[c * 256 + i % 256] = d[c];
         }
         for (int j = 0; j < NHALO; ++j) {
             const int idx = (j <= TH) ? j * TLW + TW : TH * TLW + (j - (TH + 1));
@@ -707,16 +802,14 @@ int cmm_backward(int W, int H, const float* K, int R, const float* refs, float e
                 const d2 h = halo[(size_t)(b - w->ntx - 1) * NHALO + TH];
                 g.x += h.x; g.y += h.y;
             }
-            double Ax, Ay, Bx, By;
-            mm_parts(w, f, X, Y, &Ax, &Ay, &Bx, &By);
             const int pix = Y * w->W + X;
-            drho_f[pix] = (float)(gl * (g.x * Bx + g.y * By));
-            if (g.x != 0.0 || g.y != 0.0) {
-                double d[6];
-                for (int c = 0; c < 6; ++c) d[c] = red[c * 64 + j % 64];
-                mm_dtheta(w, X, Y, (double)rho_f[pix], g.x, g.y, d);
-                for (int c = 0; c < 6; ++c) red[c * 64 + j % 64] = d[c];
-            }
+            double d[6];
+            for (int c = 0; c < 6; ++c) d[c] = red[c * 64 + j % 64];
+            double dr = 0.0;
+            if (w->model == 0 || g.x != 0.0 || g.y != 0.0)
+                dr = mm_chain(w, f, X, Y, (double)rho_f[pix], g.x, g.y, d);
+            drho_f[pix] = (float)(gl * dr);
+            for (int c = 0; c < 6; ++c) red[c * 64 + j % 64] = d[c];
         }
         for (int c = 0; c < 6; ++c) part[(size_t)b * 12 + 6 + c] = mm_block_sum(red + c * 64, 64);
     }

@@ -4,7 +4,8 @@ The loss and its gradient run in HIP kernels for gfx950 behind the C ABI of
 include/cmloss.h (libcmloss.so); this package is the thin Python binding.
 """
 
-from .binding import (CM_MODE_ATOMIC, CM_MODE_DETERMINISTIC, CM_PATH_AUTO, CM_PATH_DIRECT,
+from .binding import (CM_FLOW_EXACT, CM_FLOW_FIRST_ORDER, CM_MODE_ATOMIC, CM_MODE_DETERMINISTIC,
+                      CM_PATH_AUTO, CM_PATH_DIRECT,
                       CM_PATH_TILED, PHASES, Batch, BatchCMLoss, CMError, CMLoss, WindowDesc,
                       backward, cm_loss,
                       diagnostics, forward, handle, load, profile_enable, profile_read, set_path,
@@ -13,4 +14,5 @@ from .binding import (CM_MODE_ATOMIC, CM_MODE_DETERMINISTIC, CM_PATH_AUTO, CM_PA
 __all__ = ["CM_MODE_ATOMIC", "CM_MODE_DETERMINISTIC", "CMError", "CMLoss", "WindowDesc",
            "backward", "cm_loss", "diagnostics", "forward", "handle", "load", "profile_enable",
            "profile_read", "state_bytes", "PHASES", "CM_PATH_AUTO", "CM_PATH_DIRECT",
-           "CM_PATH_TILED", "set_path", "Batch", "BatchCMLoss"]
+           "CM_PATH_TILED", "set_path", "Batch", "BatchCMLoss", "CM_FLOW_FIRST_ORDER",
+           "CM_FLOW_EXACT"]

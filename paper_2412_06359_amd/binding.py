@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_PKG, "libcmloss.so")
 CM_MAX_REFS = 16
 CM_MODE_ATOMIC = 0
 CM_MODE_DETERMINISTIC = 1
+CM_FLOW_FIRST_ORDER = 0
+CM_FLOW_EXACT = 1
 
 _STATUS = {0: "CM_OK", -1: "CM_ERR_INVALID_ARG", -2: "CM_ERR_OOM", -3: "CM_ERR_HIP",
            -4: "CM_ERR_UNSUPPORTED", -5: "CM_ERR_BUDGET"}
@@ -38,12 +40,13 @@ class WindowDesc(ctypes.Structure):
                 ("fx", ctypes.c_float), ("fy", ctypes.c_float),
                 ("cx", ctypes.c_float), ("cy", ctypes.c_float),
                 ("n_refs", ctypes.c_int32), ("refs", ctypes.c_float * CM_MAX_REFS),
-                ("mode", ctypes.c_int32), ("eps", ctypes.c_float), ("n_flows", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("eps", ctypes.c_float), ("n_flows", ctypes.c_int32),
+                ("flow_model", ctypes.c_int32)]
 
     @classmethod
     def make(cls, width: int, height: int, fx: float, fy: float, cx: float, cy: float,
              refs: Sequence[float], mode: int = CM_MODE_ATOMIC, eps: float = 1e-9,
-             n_flows: int = 1) -> "WindowDesc":
+             n_flows: int = 1, flow_model: int = CM_FLOW_FIRST_ORDER) -> "WindowDesc":
         refs = [float(r) for r in refs]
         if not 1 <= len(refs) <= CM_MAX_REFS:
             raise ValueError(f"need 1..{CM_MAX_REFS} reference times, got {len(refs)}")
@@ -56,16 +59,19 @@ class WindowDesc(ctypes.Structure):
         d.mode = int(mode)
         d.eps = eps
         d.n_flows = int(n_flows)
+        d.flow_model = int(flow_model)
         return d
 
     @classmethod
     def from_window(cls, win, mode: int = CM_MODE_ATOMIC) -> "WindowDesc":
         """From an object with width, height, fx, fy, cx, cy, refs, eps, rho
-        ([H, W] for one flow, [F, H, W] for F flow sets)."""
+        ([H, W] for one flow, [F, H, W] for F flow sets) and optionally
+        flow_model (0 first order, 1 exact)."""
         rho = getattr(win, "rho", None)
         F = 1 if rho is None or len(getattr(rho, "shape", ())) != 3 else int(rho.shape[0])
         return cls.make(win.width, win.height, win.fx, win.fy, win.cx, win.cy, list(win.refs),
-                        mode, getattr(win, "eps", 1e-9), F)
+                        mode, getattr(win, "eps", 1e-9), F,
+                        int(getattr(win, "flow_model", CM_FLOW_FIRST_ORDER)))
 
     @property
     def R(self) -> int:

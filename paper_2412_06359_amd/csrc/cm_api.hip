@@ -54,6 +54,7 @@ bool desc_valid(const cm_window_desc* d)
     if (d->mode != CM_MODE_ATOMIC && d->mode != CM_MODE_DETERMINISTIC) return false;
     if (!(std::isfinite(d->eps) && d->eps > 0.f)) return false;
     if (d->n_flows != 0 && d->n_flows != 1 && d->n_flows != n_segments(d)) return false;
+    if (d->flow_model != CM_FLOW_FIRST_ORDER && d->flow_model != CM_FLOW_EXACT) return false;
     return true;
 }
 
@@ -84,6 +85,7 @@ WinParams params_of(const cm_window_desc* d)
     // Flow set of the step into reference r: forward steps cross the segment
     // that ends at r's knot, backward steps the one that starts there.
     P.F = flows_of(d);
+    P.model = d->flow_model == CM_FLOW_EXACT ? 1 : 0;
     const int k0 = d->refs[0] > 0.f ? 1 : 0;      // knot index of reference 0
     for (int r = 0; r < d->n_refs; ++r) {
         // (a forward step into the first knot or a backward step into the
@@ -405,6 +407,7 @@ cm_status cm_batch_create(cm_handle h, int32_t n_windows, const cm_window_desc* 
     for (int w = 0; w < n_windows; ++w) {
         if (!desc_valid(&descs[w]) || n_events[w] < 0) return CM_ERR_INVALID_ARG;
         if (descs[w].mode != descs[0].mode) return CM_ERR_INVALID_ARG;
+        if (descs[w].flow_model != descs[0].flow_model) return CM_ERR_INVALID_ARG;
         params[w] = params_of(&descs[w]);
         if (!cm::tiled_supported(params[w], n_events[w])) return CM_ERR_UNSUPPORTED;
         total_records += n_events[w] * (int64_t)params[w].R;

@@ -172,7 +172,7 @@ __device__ __forceinline__ void load_ref_table(const WinParams& P, const StateHe
     }
 }
 
-template <int RM, int NT, bool MF>
+template <int RM, int NT, int FM>
 __global__ __launch_bounds__(NT) void fwd_count_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const float* __restrict__ ex,
     const float* __restrict__ ey, const float* __restrict__ et, const float* __restrict__ rho,
@@ -191,8 +191,8 @@ __global__ __launch_bounds__(NT) void fwd_count_kernel(
     for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) lh[i] = 0;
     if (threadIdx.x == 0) cnt_lds = 0;
     load_ref_table(P, nullptr, rt);
-    __shared__ Motion mt[kMaxFlows];
-    const Flows<MF> u = make_flows<MF>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off, mt);
+    __shared__ MotionTable mt;
+    const Flows<FM> u = make_flows<FM>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off, &mt);
     __syncthreads();
     const int64_t base = lb * NT * G.ept;
     uint32_t cnt = 0;
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(NT) void fwd_count_kernel(
         double vx[RM], vy[RM];
         int vr[RM];
         Visits v;
-        if (!warp_visits<RM, MF>(P, u, rt, cur.x, cur.y, cur.t, vx, vy, vr, v)) continue;
+        if (!warp_visits<RM, FM>(P, u, rt, cur.x, cur.y, cur.t, vx, vy, vr, v)) continue;
         ++cnt;
 #pragma unroll
         for (int j = 0; j < RM; ++j)
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256) void offsets_kernel(const WinMeta* __restrict_
     }
 }
 
-template <int RM, int NT, bool DET, bool MF>
+template <int RM, int NT, bool DET, int FM>
 __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const float* __restrict__ ex,
     const float* __restrict__ ey, const float* __restrict__ et, const int8_t* __restrict__ ep,
@@ -346,8 +346,8 @@ __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
     __shared__ RefTable rt;
     for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) lh[i] = row[i];
     load_ref_table(P, nullptr, rt);
-    __shared__ Motion mt[kMaxFlows];
-    const Flows<MF> u = make_flows<MF>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off, mt);
+    __shared__ MotionTable mt;
+    const Flows<FM> u = make_flows<FM>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off, &mt);
     __syncthreads();
     // the window's reference-0 records come first among its records: their
     // slots minus this offset number its valid events
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
         int vr[RM];
         Visits v;
         const float xk = cur.x, yk = cur.y, tk = cur.t;
-        if (!warp_visits<RM, MF>(P, u, rt, xk, yk, tk, vx, vy, vr, v)) continue;
+        if (!warp_visits<RM, FM>(P, u, rt, xk, yk, tk, vx, vy, vr, v)) continue;
         const float ts = cur.p > 0 ? fabsf(tk) : -fabsf(tk);   // sign bit = polarity
 #pragma unroll
         for (int j = 0; j < RM; ++j) {
@@ -672,14 +672,14 @@ __global__ __launch_bounds__(256) void fwd_finalize_kernel(const WinMeta* __rest
 // each step has its own record (its set may differ).  Which of the two is
 // decided per window, so a one-flow window gives the same records in any
 // batch.
-template <int RM, bool MF, typename F>
+template <int RM, int FM, typename F>
 __device__ __forceinline__ void for_each_sample(const WinParams& P, const RefTable& rt,
                                                 const Visits& v, const double (&vx)[RM],
                                                 const double (&vy)[RM], const int (&vr)[RM],
                                                 double x0, double y0, F&& fn)
 {
     const int jf = v.eq ? 1 : 0;
-    if (MF && P.F > 1) {
+    if (FM != 0 && P.F > 1) {
 #pragma unroll
         for (int j = 0; j < RM; ++j) {
             if (j < P.R && !(v.eq && j == 0)) {
@@ -703,7 +703,7 @@ __device__ __forceinline__ void for_each_sample(const WinParams& P, const RefTab
 // positions [(e * nblocks + b) * NT, +NT).  The blocks in flight then work on
 // one compact stretch of the source order, that is on neighbouring tiles, and
 // their image and inverse-depth gathers share the L2.
-template <int RM, int NT, bool MF>
+template <int RM, int NT, int FM>
 __global__ __launch_bounds__(NT) void bwd_count_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const SrcRec* __restrict__ src,
     const float* __restrict__ rho, const float* __restrict__ ego,
@@ -721,8 +721,8 @@ __global__ __launch_bounds__(NT) void bwd_count_kernel(
     __shared__ RefTable rt;
     for (int i = threadIdx.x; i < G.nbins_b; i += blockDim.x) lh[i] = 0;
     load_ref_table(P, nullptr, rt);
-    __shared__ Motion mt[kMaxFlows];
-    const Flows<MF> u = make_flows<MF>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off, mt);
+    __shared__ MotionTable mt;
+    const Flows<FM> u = make_flows<FM>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off, &mt);
     __syncthreads();
     const int64_t stride = (int64_t)G.nblocks * NT;
     SrcRec qn;
@@ -736,8 +736,8 @@ __global__ __launch_bounds__(NT) void bwd_count_kernel(
         int vr[RM];
         Visits v;
         const double x0 = q.x0, y0 = q.y0, tk = fabsf(q.ts);
-        if (!warp_visits<RM, MF>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
-        for_each_sample<RM, MF>(P, rt, v, vx, vy, vr, x0, y0, [&](double X, double Y, int set) {
+        if (!warp_visits<RM, FM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
+        for_each_sample<RM, FM>(P, rt, v, vx, vy, vr, x0, y0, [&](double X, double Y, int set) {
             atomicAdd(&lh[set * G.ntiles + tile_index(G, make_taps(P, X, Y))], 1u);
         });
     }
@@ -751,7 +751,7 @@ __global__ __launch_bounds__(NT) void bwd_count_kernel(
     }
 }
 
-template <int RM, int NT, bool DET, bool MF>
+template <int RM, int NT, bool DET, int FM>
 __global__ __launch_bounds__(NT) void bwd_sweep_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const SrcRec* __restrict__ src,
     const float* __restrict__ rho, const float* __restrict__ ego,
@@ -772,11 +772,11 @@ __global__ __launch_bounds__(NT) void bwd_sweep_kernel(
     __syncthreads();
     __shared__ RefTable rt;
     load_ref_table(P, hdrs + w, rt);
-    __shared__ Motion mt[kMaxFlows];
-    const Flows<MF> u = make_flows<MF>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off, mt);
+    __shared__ MotionTable mt;
+    const Flows<FM> u = make_flows<FM>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off, &mt);
     __syncthreads();
     const double2* img = img_base + meta[w].img_off;
-    const bool split = MF && P.F > 1;    // one record per first step (see for_each_sample)
+    const bool split = FM != 0 && P.F > 1;    // one record per first step (see for_each_sample)
 
     auto emit = [&](double X, double Y, double gx, double gy, int set) {
         const int bin = set * G.ntiles + tile_index(G, make_taps(P, X, Y));
@@ -801,7 +801,7 @@ __global__ __launch_bounds__(NT) void bwd_sweep_kernel(
         int vr[RM];
         Visits v;
         const double x0 = q.x0, y0 = q.y0, tk = fabsf(q.ts);
-        if (!warp_visits<RM, MF>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
+        if (!warp_visits<RM, FM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
         const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
         const double2* planes = img + (size_t)pol * P.HW;
         double g0x = 0.0, g0y = 0.0;     // contributions sampled at the event position
@@ -917,7 +917,11 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(
         }
     }
     __syncthreads();
-    const Motion m = load_motion(P, ego + 6 * (meta[w].ego_off + set));
+    const float* ego_s = ego + 6 * (meta[w].ego_off + set);
+    const Motion m = load_motion(P, ego_s);
+    __shared__ MotionXJ mx;
+    if (P.model == 1 && threadIdx.x == 0) mx = load_motion_xj(ego_s);
+    __syncthreads();
     const float* rho_w = rho + meta[w].pix_off + (size_t)set * P.HW;
     float* drho_w = drho + meta[w].pix_off + (size_t)set * P.HW;
     const double gl = (double)grad_loss[w];
@@ -932,6 +936,12 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(
             continue;
         }
         const int pix = Y * P.W + X;
+        if (P.model == 1) {
+            double d = 0.0;
+            if (g.x != 0.0 || g.y != 0.0) d = chain_exact(P, mx, X, Y, (double)rho_w[pix], g.x, g.y, dth);
+            drho_w[pix] = (float)(gl * d);
+            continue;
+        }
         double Ax, Ay, Bx, By;
         flow_parts(P, m, X, Y, Ax, Ay, Bx, By);
         drho_w[pix] = (float)(gl * (g.x * Bx + g.y * By));
@@ -964,7 +974,11 @@ __global__ __launch_bounds__(64) void bwd_merge_kernel(
     const int set = lbin / G.ntiles, tile = lbin - set * G.ntiles;
     const int ty = tile / G.ntx, tx = tile - ty * G.ntx;
     const int xo = tx * TW, yo = ty * TH;
-    const Motion m = load_motion(P, ego + 6 * (meta[w].ego_off + set));
+    const float* ego_s = ego + 6 * (meta[w].ego_off + set);
+    const Motion m = load_motion(P, ego_s);
+    __shared__ MotionXJ mx;
+    if (P.model == 1 && threadIdx.x == 0) mx = load_motion_xj(ego_s);
+    __syncthreads();
     const float* rho_w = rho + meta[w].pix_off + (size_t)set * P.HW;
     float* drho_w = drho + meta[w].pix_off + (size_t)set * P.HW;
     const double gl = (double)grad_loss[w];
@@ -991,6 +1005,12 @@ __global__ __launch_bounds__(64) void bwd_merge_kernel(
             g.y += h.y;
         }
         const int pix = Y * P.W + X;
+        if (P.model == 1) {
+            double d = 0.0;
+            if (g.x != 0.0 || g.y != 0.0) d = chain_exact(P, mx, X, Y, (double)rho_w[pix], g.x, g.y, dth);
+            drho_w[pix] = (float)(gl * d);
+            continue;
+        }
         double Ax, Ay, Bx, By;
         flow_parts(P, m, X, Y, Ax, Ay, Bx, By);
         drho_w[pix] = (float)(gl * (g.x * Bx + g.y * By));
@@ -1140,6 +1160,7 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
         recs += M.n * M.P.R;
         B.max_R = std::max(B.max_R, M.P.R);
         B.max_F = std::max(B.max_F, M.P.F);
+        B.model = M.P.model;      // uniform over a batch (checked when the batch is created)
         B.max_lds_bins = std::max(B.max_lds_bins, (int)row);
     }
     B.n_events = ev;
@@ -1182,7 +1203,7 @@ static void launch_window_table(const BatchPlanHost& B, const WinMeta* meta, int
                                                                 B.nbins_b, tab);
 }
 
-template <int RM, bool DET, bool MF>
+template <int RM, bool DET, int FM>
 static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
                                    const EventPtrs& ev, const float* rho, const float* ego,
                                    float* loss, double2* img, StateHeader* hdrs, char* ws,
@@ -1212,7 +1233,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     {
         PhaseScope ph(prof, kPhCount, s);
         constexpr int NT = DET ? 64 : kBinThreads;
-        fwd_count_kernel<RM, NT, MF><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, ev.x, ev.y, ev.t, rho, ego,
+        fwd_count_kernel<RM, NT, FM><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, ev.x, ev.y, ev.t, rho, ego,
                                                             hist, csum, hdrs);
     }
     {
@@ -1226,7 +1247,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     {
         PhaseScope ph(prof, kPhScatter, s);
         constexpr int NT = DET ? 64 : kBinThreads;
-        fwd_scatter_kernel<RM, NT, DET, MF><<<B.nblocks, NT, lds, s>>>(
+        fwd_scatter_kernel<RM, NT, DET, FM><<<B.nblocks, NT, lds, s>>>(
             meta, nw, win_blk, ev.x, ev.y, ev.t, ev.p, rho, ego, hist, start, rec, src);
     }
     {
@@ -1250,9 +1271,9 @@ hipError_t launch_forward_batch(const BatchPlanHost& B, const WinMeta* meta, con
                                 const float* rho, const float* ego, float* loss, double2* img,
                                 StateHeader* hdrs, char* ws, hipStream_t s, Profiler* prof)
 {
-#define CM_FWD_D(RM, MF) (B.det ? batch_forward_rm<RM, true, MF>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof) \
-                            : batch_forward_rm<RM, false, MF>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof))
-#define CM_FWD(RM) (B.max_F > 1 ? CM_FWD_D(RM, true) : CM_FWD_D(RM, false))
+#define CM_FWD_D(RM, FM) (B.det ? batch_forward_rm<RM, true, FM>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof) \
+                            : batch_forward_rm<RM, false, FM>(B, meta, ev, rho, ego, loss, img, hdrs, ws, s, prof))
+#define CM_FWD(RM) (B.model == 1 ? CM_FWD_D(RM, 2) : B.max_F > 1 ? CM_FWD_D(RM, 1) : CM_FWD_D(RM, 0))
     if (B.max_R <= 2) return CM_FWD(2);
     if (B.max_R <= 4) return CM_FWD(4);
     if (B.max_R <= 8) return CM_FWD(8);
@@ -1261,7 +1282,7 @@ hipError_t launch_forward_batch(const BatchPlanHost& B, const WinMeta* meta, con
 #undef CM_FWD_D
 }
 
-template <int RM, bool DET, bool MF>
+template <int RM, bool DET, int FM>
 static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
                                     const EventPtrs& ev, const float* rho, const float* ego,
                                     const double2* img, const StateHeader* hdrs,
@@ -1288,7 +1309,7 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
         fill_u32_kernel<<<(int)std::min<int64_t>((B.csum_cells + 255) / 256, 4096), 256, 0, s>>>(
             csum, B.csum_cells);
         constexpr int NT = DET ? 64 : kBinThreads;
-        bwd_count_kernel<RM, NT, MF><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, src, rho, ego,
+        bwd_count_kernel<RM, NT, FM><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, src, rho, ego,
                                                                 hdrs, hist, csum);
     }
     {
@@ -1302,7 +1323,7 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
     {
         PhaseScope ph(prof, kPhAdjoint, s);
         constexpr int NT = DET ? 64 : kBinThreads;
-        bwd_sweep_kernel<RM, NT, DET, MF><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, src, rho, ego, img,
+        bwd_sweep_kernel<RM, NT, DET, FM><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, src, rho, ego, img,
                                                                  hdrs, hist, rec);
     }
     {
@@ -1325,9 +1346,9 @@ hipError_t launch_backward_batch(const BatchPlanHost& B, const WinMeta* meta,
                                  const float* grad_loss, float* grad_rho, float* grad_ego,
                                  char* ws, hipStream_t s, Profiler* prof)
 {
-#define CM_BWD_D(RM, MF) (B.det ? batch_backward_rm<RM, true, MF>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof) \
-                            : batch_backward_rm<RM, false, MF>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof))
-#define CM_BWD(RM) (B.max_F > 1 ? CM_BWD_D(RM, true) : CM_BWD_D(RM, false))
+#define CM_BWD_D(RM, FM) (B.det ? batch_backward_rm<RM, true, FM>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof) \
+                            : batch_backward_rm<RM, false, FM>(B, meta, ev, rho, ego, img, hdrs, grad_loss, grad_rho, grad_ego, ws, s, prof))
+#define CM_BWD(RM) (B.model == 1 ? CM_BWD_D(RM, 2) : B.max_F > 1 ? CM_BWD_D(RM, 1) : CM_BWD_D(RM, 0))
     if (B.max_R <= 2) return CM_BWD(2);
     if (B.max_R <= 4) return CM_BWD(4);
     if (B.max_R <= 8) return CM_BWD(8);

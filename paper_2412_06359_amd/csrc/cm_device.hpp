@@ -32,6 +32,7 @@ constexpr int kMaxFlows = kMaxRefs + 1;   // segments between knots {0, 1} U ref
 struct WinParams {
     int W, H, R, HW;
     int F;                      // flow sets
+    int model;                  // flow model: 0 first-order motion field, 1 exact reprojection
     double cx, cy, fx, fy;
     double inv_fx, inv_fy, fx_over_fy, fy_over_fx;
     double xmax, ymax;          // W - 1, H - 1
@@ -153,20 +154,119 @@ __device__ __forceinline__ FlowSrc flow_src(const WinParams& P, const float* __r
     return f;
 }
 
-// The flows of a window, by set.  Flows<false>: one flow in registers.
-// Flows<true>: F flows, inverse depth f at rho + f HW, motion coefficients in
-// a per-block LDS table.
-template <bool MF>
+// ---------------------------------------------------------------------------
+// Exact reprojection (Eq. 2 without the first-order expansion).  The pixel's
+// ray xn = ((i - cx)/fx, (j - cy)/fy, 1) at inverse depth rho is the point
+// xn/rho; the pose maps it to R xn/rho + v, which projects like
+//   p = R xn + rho v,   u = (fx p_x/p_z + cx - i, fy p_y/p_z + cy - j);
+// a point on or behind the camera plane (p_z <= 0) gets zero flow.
+//
+// R = I + a K + b K^2 and the right Jacobian of the exponential map
+// Jr = I - b K + c K^2 (K = [w]x, t = |w|) use a = sin t/t, b = (1 - cos t)/t^2,
+// c = (t - sin t)/t^3, evaluated as their power series in t^2 (Horner, 18
+// terms: below 1e-16 relative for t <= pi), so that every operation is plain
+// FP64 arithmetic in a fixed order.
+// ---------------------------------------------------------------------------
+struct MotionX {
+    double R[9];     // row-major rotation
+    double v[3];     // translation
+};
+
+struct MotionXJ {
+    double R[9];
+    double v[3];
+    double Jr[9];    // right Jacobian, row-major
+};
+
+// sum_k (-s)^k / ((2k+o)! / o!) ... with o the first denominator offset:
+// series(s, o) = 1 - s/((o+1)(o+2)) (1 - s/((o+3)(o+4)) (1 - ...)).
+__device__ __forceinline__ double rot_series(double s, int o)
+{
+    double h = 1.0;
+#pragma unroll
+    for (int k = 18; k >= 1; --k) {
+        const double d = (double)(o + 2 * k - 1) * (double)(o + 2 * k);
+        h = 1.0 - (s / d) * h;
+    }
+    return h;
+}
+
+__device__ __forceinline__ void rotation_of(const float* __restrict__ ego, double (&R)[9],
+                                            double* Jr)
+{
+    const double wx = ego[3], wy = ego[4], wz = ego[5];
+    const double s = (wx * wx + wy * wy) + wz * wz;
+    const double a = rot_series(s, 1);           // sin t / t
+    const double b = 0.5 * rot_series(s, 2);     // (1 - cos t) / t^2
+    const double K[9] = {0.0, -wz, wy, wz, 0.0, -wx, -wy, wx, 0.0};
+    double K2[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            K2[3 * i + j] = (K[3 * i + 0] * K[0 * 3 + j] + K[3 * i + 1] * K[1 * 3 + j]) +
+                            K[3 * i + 2] * K[2 * 3 + j];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double I = (i % 4 == 0) ? 1.0 : 0.0;
+        R[i] = (I + a * K[i]) + b * K2[i];
+    }
+    if (Jr) {
+        const double c = rot_series(s, 3) / 6.0;   // (t - sin t) / t^3
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const double I = (i % 4 == 0) ? 1.0 : 0.0;
+            Jr[i] = (I - b * K[i]) + c * K2[i];
+        }
+    }
+}
+
+__device__ __forceinline__ MotionX load_motion_x(const float* __restrict__ ego)
+{
+    MotionX m;
+    rotation_of(ego, m.R, nullptr);
+    m.v[0] = ego[0];
+    m.v[1] = ego[1];
+    m.v[2] = ego[2];
+    return m;
+}
+
+__device__ __forceinline__ MotionXJ load_motion_xj(const float* __restrict__ ego)
+{
+    MotionXJ m;
+    rotation_of(ego, m.R, m.Jr);
+    m.v[0] = ego[0];
+    m.v[1] = ego[1];
+    m.v[2] = ego[2];
+    return m;
+}
+
+// Where the warp reads an exact flow: inverse depth and the set's pose.
+struct FlowSrcX {
+    const float* __restrict__ rho;
+    const MotionX* m;
+};
+
+// The flows of a window, by set.  FM (flow kind) 0: one first-order flow in
+// registers; 1: first-order flows, motion coefficients in a per-block LDS
+// table; 2: exact-reprojection flows, poses in the LDS table.  Set f reads
+// inverse depth at rho + f HW.
+union MotionTable {
+    Motion m[kMaxFlows];
+    MotionX x[kMaxFlows];
+};
+
+template <int FM>
 struct Flows;
 
 template <>
-struct Flows<false> {
+struct Flows<0> {
     FlowSrc f;
     __device__ __forceinline__ const FlowSrc& at(int) const { return f; }
 };
 
 template <>
-struct Flows<true> {
+struct Flows<1> {
     const float* __restrict__ rho;
     int HW;
     const Motion* m;
@@ -179,34 +279,59 @@ struct Flows<true> {
     }
 };
 
-// Builds a block's flows.  `mt` is the block's LDS motion table (kMaxFlows
-// entries, used with MF); all threads call this, followed by a barrier
-// before the first use.
-template <bool MF>
-__device__ __forceinline__ Flows<MF> make_flows(const WinParams& P, const float* __restrict__ rho,
-                                                const float* __restrict__ ego, Motion* mt);
+template <>
+struct Flows<2> {
+    const float* __restrict__ rho;
+    int HW;
+    const MotionX* m;
+    __device__ __forceinline__ FlowSrcX at(int s) const
+    {
+        FlowSrcX f;
+        f.rho = rho + (size_t)s * HW;
+        f.m = m + s;
+        return f;
+    }
+};
+
+// Builds a block's flows.  `mt` is the block's LDS table (used with FM 1, 2);
+// all threads call this, followed by a barrier before the first use.
+template <int FM>
+__device__ __forceinline__ Flows<FM> make_flows(const WinParams& P, const float* __restrict__ rho,
+                                                const float* __restrict__ ego, MotionTable* mt);
 
 template <>
-__device__ __forceinline__ Flows<false> make_flows<false>(const WinParams& P,
-                                                          const float* __restrict__ rho,
-                                                          const float* __restrict__ ego,
-                                                          Motion*)
+__device__ __forceinline__ Flows<0> make_flows<0>(const WinParams& P,
+                                                  const float* __restrict__ rho,
+                                                  const float* __restrict__ ego, MotionTable*)
 {
-    Flows<false> fl;
+    Flows<0> fl;
     fl.f = flow_src(P, rho, ego);
     return fl;
 }
 
 template <>
-__device__ __forceinline__ Flows<true> make_flows<true>(const WinParams& P,
-                                                        const float* __restrict__ rho,
-                                                        const float* __restrict__ ego, Motion* mt)
+__device__ __forceinline__ Flows<1> make_flows<1>(const WinParams& P,
+                                                  const float* __restrict__ rho,
+                                                  const float* __restrict__ ego, MotionTable* mt)
 {
-    if ((int)threadIdx.x < P.F) mt[threadIdx.x] = load_motion(P, ego + 6 * threadIdx.x);
-    Flows<true> fl;
+    if ((int)threadIdx.x < P.F) mt->m[threadIdx.x] = load_motion(P, ego + 6 * threadIdx.x);
+    Flows<1> fl;
     fl.rho = rho;
     fl.HW = P.HW;
-    fl.m = mt;
+    fl.m = mt->m;
+    return fl;
+}
+
+template <>
+__device__ __forceinline__ Flows<2> make_flows<2>(const WinParams& P,
+                                                  const float* __restrict__ rho,
+                                                  const float* __restrict__ ego, MotionTable* mt)
+{
+    if ((int)threadIdx.x < P.F) mt->x[threadIdx.x] = load_motion_x(ego + 6 * threadIdx.x);
+    Flows<2> fl;
+    fl.rho = rho;
+    fl.HW = P.HW;
+    fl.m = mt->x;
     return fl;
 }
 
@@ -253,8 +378,46 @@ __device__ __forceinline__ void tap_flows(const WinParams& P, const FlowSrc& f, 
     }
 }
 
+// The exact flow at the four taps; the row and column terms of R xn are formed
+// once per column or row:  p_k = (R[k][0] xn + (R[k][1] yn + R[k][2])) + rho v_k.
+__device__ __forceinline__ void tap_flows(const WinParams& P, const FlowSrcX& f, const Taps& t,
+                                          double2 (&uq)[4])
+{
+    const MotionX& m = *f.m;
+    double col[2][3], row[2][3];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const double xn = ((double)(t.x0 + a) - P.cx) * P.inv_fx;
+        const double yn = ((double)(t.y0 + a) - P.cy) * P.inv_fy;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            col[a][k] = m.R[3 * k + 0] * xn;
+            row[a][k] = m.R[3 * k + 1] * yn + m.R[3 * k + 2];
+        }
+    }
+    const float* row0 = f.rho + (size_t)t.y0 * P.W + t.x0;
+    const float rq[4] = {row0[0], t.inx ? row0[1] : 0.f, t.iny ? row0[P.W] : 0.f,
+                         (t.inx && t.iny) ? row0[P.W + 1] : 0.f};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int a = q & 1, b = q >> 1;
+        const double r = (double)rq[q];
+        const double px = (col[a][0] + row[b][0]) + r * m.v[0];
+        const double py = (col[a][1] + row[b][1]) + r * m.v[1];
+        const double pz = (col[a][2] + row[b][2]) + r * m.v[2];
+        double2 u = make_double2(0.0, 0.0);
+        if (tap_in(t, q) && pz > 0.0) {
+            const double iz = 1.0 / pz;
+            u.x = (P.fx * px) * iz + (P.cx - (double)(t.x0 + a));
+            u.y = (P.fy * py) * iz + (P.cy - (double)(t.y0 + b));
+        }
+        uq[q] = u;
+    }
+}
+
 // BS(u)(X, Y): the flow sampled bilinearly at a position on the image.
-__device__ __forceinline__ void sample_flow(const WinParams& P, const FlowSrc& f, double X,
+template <typename Src>
+__device__ __forceinline__ void sample_flow(const WinParams& P, const Src& f, double X,
                                             double Y, double& ux, double& uy)
 {
     const Taps t = make_taps(P, X, Y);
@@ -304,8 +467,8 @@ struct Visits {
 // start off the image, or any visited position off the image.  The loop is
 // unrolled over visits so that every array index is static, and all lanes of a
 // wave step through the same visit numbers together.
-template <int RM, bool MF>
-__device__ __forceinline__ bool warp_visits(const WinParams& P, const Flows<MF>& fl,
+template <int RM, int FM>
+__device__ __forceinline__ bool warp_visits(const WinParams& P, const Flows<FM>& fl,
                                             const RefTable& rt, double x0, double y0, double tk,
                                             double (&vx)[RM], double (&vy)[RM], int (&vr)[RM],
                                             Visits& v)
@@ -331,10 +494,10 @@ __device__ __forceinline__ bool warp_visits(const WinParams& P, const Flows<MF>&
             int r, set;
             if (j < v.nf) {
                 r = mb + j;
-                set = MF ? rt.sf[r] : 0;
+                set = FM ? rt.sf[r] : 0;
             } else {
                 r = mb - 1 - (j - v.nf);
-                set = MF ? rt.sb[r] : 0;
+                set = FM ? rt.sb[r] : 0;
                 if (j == v.nf) {
                     X = x0;
                     Y = y0;
@@ -432,9 +595,42 @@ __device__ __forceinline__ void dtheta_at_pixel(const WinParams& P, int i, int j
     dth[5] += (P.fy_over_fx * xb) * gy - (P.fx_over_fy * yb) * gx;
 }
 
+// Exact model: d rho and d theta of dL/du = (gx, gy) at pixel (i, j) with
+// inverse depth r.  With J = du/dp = [[fx/pz, 0, -fx px/pz^2], [0, fy/pz,
+// -fy py/pz^2]] and q = J^T g:  d rho = q . v,  d v += r q,
+// d w += Jr^T (xn x (R^T q))  (the adjoint of d(R xn)/dw = -R [xn]x Jr).
+// Returns d rho (zero for a point on or behind the camera plane).
+__device__ __forceinline__ double chain_exact(const WinParams& P, const MotionXJ& m, int i, int j,
+                                              double r, double gx, double gy, double (&dth)[6])
+{
+    const double xn = ((double)i - P.cx) * P.inv_fx;
+    const double yn = ((double)j - P.cy) * P.inv_fy;
+    double p[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        p[k] = (m.R[3 * k + 0] * xn + (m.R[3 * k + 1] * yn + m.R[3 * k + 2])) + r * m.v[k];
+    if (!(p[2] > 0.0)) return 0.0;
+    const double iz = 1.0 / p[2];
+    const double ax = gx * P.fx, ay = gy * P.fy;
+    const double q[3] = {ax * iz, ay * iz, -((ax * p[0] + ay * p[1]) * iz) * iz};
+    const double drho = (q[0] * m.v[0] + q[1] * m.v[1]) + q[2] * m.v[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dth[k] += r * q[k];
+    double sv[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        sv[k] = (m.R[0 * 3 + k] * q[0] + m.R[1 * 3 + k] * q[1]) + m.R[2 * 3 + k] * q[2];
+    const double cr[3] = {yn * sv[2] - sv[1], sv[0] - xn * sv[2], xn * sv[1] - yn * sv[0]};
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        dth[3 + k] += (m.Jr[0 * 3 + k] * cr[0] + m.Jr[1 * 3 + k] * cr[1]) + m.Jr[2 * 3 + k] * cr[2];
+    return drho;
+}
+
 // J(P)^T L for the bilinear flow sample at (X, Y): sum over taps of
 // (L . u_tap) grad w_tap.
-__device__ __forceinline__ void jacobian_t(const WinParams& P, const FlowSrc& u,
+template <typename Src>
+__device__ __forceinline__ void jacobian_t(const WinParams& P, const Src& u,
                                            double X, double Y, double Lx, double Ly, double& jx,
                                            double& jy)
 {

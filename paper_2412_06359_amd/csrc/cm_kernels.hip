@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(float* __restrict__ p, s
     }
 }
 
-template <int RM, bool MF>
+template <int RM, int FM>
 __global__ __launch_bounds__(256) void splat_kernel(WinParams P, const float* __restrict__ ex,
                                                     const float* __restrict__ ey,
                                                     const float* __restrict__ et,
@@ -54,14 +54,14 @@ __global__ __launch_bounds__(256) void splat_kernel(WinParams P, const float* __
 {
     __shared__ unsigned int cnt_lds;
     __shared__ RefTable rt;
-    __shared__ Motion mt[kMaxFlows];
+    __shared__ MotionTable mt;
     if (threadIdx.x == 0) cnt_lds = 0;
     if (threadIdx.x < kMaxRefs) {
         rt.t[threadIdx.x] = P.refs[threadIdx.x];
         rt.sf[threadIdx.x] = P.sf[threadIdx.x];
         rt.sb[threadIdx.x] = P.sb[threadIdx.x];
     }
-    const Flows<MF> u = make_flows<MF>(P, rho, ego, mt);
+    const Flows<FM> u = make_flows<FM>(P, rho, ego, &mt);
     __syncthreads();
     unsigned int cnt = 0;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void splat_kernel(WinParams P, const float* __
         double vx[RM], vy[RM];
         int vr[RM];
         Visits v;
-        if (!warp_visits<RM, MF>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
+        if (!warp_visits<RM, FM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
         ++cnt;
 #pragma unroll
         for (int j = 0; j < RM; ++j) {
@@ -188,7 +188,40 @@ __device__ __forceinline__ void adjoint_step(const WinParams& P, const FlowSrc& 
     Ly += dt * jy;
 }
 
-template <int RM, bool MF>
+// The same step for an exact-reprojection flow: the chain to rho and theta
+// per tap goes through the projection, translation and rotation of the set's
+// pose (chain_exact).
+__device__ __forceinline__ void adjoint_step(const WinParams& P, const FlowSrcX& u,
+                                             const MotionXJ& mj, double X, double Y, double dt,
+                                             double& Lx, double& Ly, double gl,
+                                             float* __restrict__ drho, double (&dth)[6])
+{
+    const Taps tp = make_taps(P, X, Y);
+    double2 uq[4];
+    tap_flows(P, u, tp, uq);
+    double jx = 0.0, jy = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        double dX, dY;
+        tap_dw(tp, q, dX, dY);
+        const double lu = Lx * uq[q].x + Ly * uq[q].y;
+        jx += lu * dX;
+        jy += lu * dY;
+        if (!tap_in(tp, q)) continue;
+        const double w = tap_w(tp, q);
+        if (w != 0.0) {
+            const int i = tp.x0 + (q & 1), j = tp.y0 + (q >> 1);
+            const int pix = j * P.W + i;
+            const double gx = dt * w * Lx, gy = dt * w * Ly;
+            const double d = chain_exact(P, mj, i, j, (double)u.rho[pix], gx, gy, dth);
+            unsafeAtomicAdd(drho + pix, (float)(gl * d));
+        }
+    }
+    Lx += dt * jx;
+    Ly += dt * jy;
+}
+
+template <int RM, int FM>
 __global__ __launch_bounds__(256) void backward_kernel(
     WinParams P, const float* __restrict__ ex, const float* __restrict__ ey,
     const float* __restrict__ et, const int8_t* __restrict__ ep, int64_t n,
@@ -198,7 +231,8 @@ __global__ __launch_bounds__(256) void backward_kernel(
 {
     __shared__ double lds[16];
     __shared__ RefTable rt;
-    __shared__ Motion mt[kMaxFlows];
+    __shared__ MotionTable mt;
+    __shared__ MotionXJ mxj[FM == 2 ? kMaxFlows : 1];   // poses with right Jacobians (exact)
     if (threadIdx.x < kMaxRefs) {
         rt.t[threadIdx.x] = P.refs[threadIdx.x];
         rt.coef[threadIdx.x] =
@@ -206,12 +240,13 @@ __global__ __launch_bounds__(256) void backward_kernel(
         rt.sf[threadIdx.x] = P.sf[threadIdx.x];
         rt.sb[threadIdx.x] = P.sb[threadIdx.x];
     }
-    const Flows<MF> u = make_flows<MF>(P, rho, ego, mt);
+    if (FM == 2 && (int)threadIdx.x < P.F) mxj[threadIdx.x] = load_motion_xj(ego + 6 * threadIdx.x);
+    const Flows<FM> u = make_flows<FM>(P, rho, ego, &mt);
     __syncthreads();
     const double gl = (double)grad_loss[0];
     // d theta partials: in registers with one flow set, per set in LDS with several
-    __shared__ double dth_sets[MF ? kMaxFlows * 6 : 1];
-    if (MF)
+    __shared__ double dth_sets[FM ? kMaxFlows * 6 : 1];
+    if (FM)
         for (int i = threadIdx.x; i < kMaxFlows * 6; i += blockDim.x) dth_sets[i] = 0.0;
     double dth[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 
@@ -222,7 +257,7 @@ __global__ __launch_bounds__(256) void backward_kernel(
         double vx[RM], vy[RM];
         int vr[RM];
         Visits v;
-        if (!warp_visits<RM, MF>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
+        if (!warp_visits<RM, FM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
         const double2* planes = reinterpret_cast<const double2*>(img) + (size_t)pol * P.HW;
         double Lx = 0.0, Ly = 0.0;
 #pragma unroll
@@ -239,21 +274,25 @@ __global__ __launch_bounds__(256) void backward_kernel(
                                 1.0 - fabs(rt.t[r] - tk), vx[j], vy[j], Lx, Ly);
                     const double X = s.first ? x0 : vx[j > 0 ? j - 1 : 0];
                     const double Y = s.first ? y0 : vy[j > 0 ? j - 1 : 0];
-                    if (MF) {
+                    if (FM) {
                         double d6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                        adjoint_step(P, u.at(s.set), X, Y, s.dt, Lx, Ly, gl,
-                                     drho + (size_t)s.set * P.HW, d6);
+                        if constexpr (FM == 2)
+                            adjoint_step(P, u.at(s.set), mxj[s.set], X, Y, s.dt, Lx, Ly, gl,
+                                         drho + (size_t)s.set * P.HW, d6);
+                        else
+                            adjoint_step(P, u.at(s.set), X, Y, s.dt, Lx, Ly, gl,
+                                         drho + (size_t)s.set * P.HW, d6);
 #pragma unroll
                         for (int c = 0; c < 6; ++c) atomicAdd(&dth_sets[s.set * 6 + c], d6[c]);
                     } else {
-                        adjoint_step(P, u.at(0), X, Y, s.dt, Lx, Ly, gl, drho, dth);
+                        if constexpr (FM == 0) adjoint_step(P, u.at(0), X, Y, s.dt, Lx, Ly, gl, drho, dth);
                     }
                 }
             }
         }
     }
     // part[block][set][6]
-    if (MF) {
+    if (FM) {
         __syncthreads();
         for (int i = threadIdx.x; i < P.F * 6; i += blockDim.x)
             part[(size_t)blockIdx.x * P.F * 6 + i] = dth_sets[i];
@@ -304,12 +343,12 @@ static void launch_splat_rm(const WinParams& P, const EventPtrs& ev, const float
                             const float* ego, double* img, unsigned long long* nv, hipStream_t s)
 {
     const int grid = std::max(1, std::min(ceil_div(ev.n, 256), 1 << 20));
-    if (P.F > 1)
-        splat_kernel<RM, true><<<grid, 256, 0, s>>>(P, ev.x, ev.y, ev.t, ev.p, ev.n, rho, ego, img,
-                                                    nv);
+    if (P.model == 1)
+        splat_kernel<RM, 2><<<grid, 256, 0, s>>>(P, ev.x, ev.y, ev.t, ev.p, ev.n, rho, ego, img, nv);
+    else if (P.F > 1)
+        splat_kernel<RM, 1><<<grid, 256, 0, s>>>(P, ev.x, ev.y, ev.t, ev.p, ev.n, rho, ego, img, nv);
     else
-        splat_kernel<RM, false><<<grid, 256, 0, s>>>(P, ev.x, ev.y, ev.t, ev.p, ev.n, rho, ego,
-                                                     img, nv);
+        splat_kernel<RM, 0><<<grid, 256, 0, s>>>(P, ev.x, ev.y, ev.t, ev.p, ev.n, rho, ego, img, nv);
 }
 
 template <int RM>
@@ -317,12 +356,15 @@ static void launch_backward_rm(const WinParams& P, const EventPtrs& ev, const fl
                                const float* ego, const double* img, const StateHeader* hdr,
                                const float* gl, float* drho, double* part, int grid, hipStream_t s)
 {
-    if (P.F > 1)
-        backward_kernel<RM, true><<<grid, 256, 0, s>>>(P, ev.x, ev.y, ev.t, ev.p, ev.n, rho, ego,
-                                                       img, hdr, gl, drho, part);
+    if (P.model == 1)
+        backward_kernel<RM, 2><<<grid, 256, 0, s>>>(P, ev.x, ev.y, ev.t, ev.p, ev.n, rho, ego,
+                                                    img, hdr, gl, drho, part);
+    else if (P.F > 1)
+        backward_kernel<RM, 1><<<grid, 256, 0, s>>>(P, ev.x, ev.y, ev.t, ev.p, ev.n, rho, ego,
+                                                    img, hdr, gl, drho, part);
     else
-        backward_kernel<RM, false><<<grid, 256, 0, s>>>(P, ev.x, ev.y, ev.t, ev.p, ev.n, rho, ego,
-                                                        img, hdr, gl, drho, part);
+        backward_kernel<RM, 0><<<grid, 256, 0, s>>>(P, ev.x, ev.y, ev.t, ev.p, ev.n, rho, ego,
+                                                    img, hdr, gl, drho, part);
 }
 
 int reduce_blocks(const WinParams& P) { return std::max(1, std::min(ceil_div(P.HW, 1024), kReduceBlocks)); }

@@ -144,6 +144,7 @@ struct BatchPlanHost {
     int64_t n_events = 0, n_pixels = 0, n_sets = 0, img_elems = 0;
     int64_t nbins = 0, nbins_b = 0, nblocks = 0, cells_f = 0, cells_b = 0, csum_cells = 0;
     int max_R = 1, max_F = 1, max_lds_bins = 1;
+    int model = 0;          // flow model of the batch's windows
     TileWorkspace ws;
 };
 

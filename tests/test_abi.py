@@ -57,7 +57,8 @@ def test_state_bytes_formula(lib):
 @pytest.mark.parametrize("bad", [
     dict(width=0), dict(height=-3), dict(fx=0.0), dict(fy=-1.0), dict(fx=float("nan")),
     dict(refs=[0.5, 0.5]), dict(refs=[0.7, 0.2]), dict(refs=[-0.1, 1.0]), dict(refs=[0.0, 1.5]),
-    dict(mode=7), dict(eps=0.0), dict(eps=float("inf")),
+    dict(mode=7), dict(eps=0.0), dict(eps=float("inf")), dict(flow_model=2),
+    dict(flow_model=-1),
 ])
 def test_invalid_descriptors_rejected(lib, bad):
     d = _desc(**bad)
@@ -120,3 +121,12 @@ def test_flow_sets_enlarge_only_the_scratch(lib):
     d4.n_flows = 4
     b1, b4 = cm.state_bytes(d1, 0), cm.state_bytes(d4, 0)
     assert b4 >= b1 and b4 - b1 < 2 << 20
+
+
+def test_descriptor_layout_matches_header():
+    """The ctypes mirror of cm_window_desc has the C layout: fields in header
+    order, 4-byte members, flow_model last."""
+    names = [f[0] for f in cm.WindowDesc._fields_]
+    assert names[-2:] == ["n_flows", "flow_model"]
+    assert ctypes.sizeof(cm.WindowDesc) == 4 * (2 + 4 + 1 + 16 + 1 + 1 + 1 + 1)
+    assert cm.WindowDesc.flow_model.offset == ctypes.sizeof(cm.WindowDesc) - 4

@@ -65,3 +65,29 @@ def test_c6_window_shape():
     win = eventgen.make_window("c6", 3)
     assert win.rho.shape == (10, win.height, win.width) and win.theta.shape == (10, 6)
     assert len(win.refs) == 11 and 10_000 <= win.n <= 100_000
+
+
+@pytest.mark.parametrize("sets", [False, True])
+def test_mirror_agrees_with_oracle_exact_flow(sets):
+    """Exact reprojection (Eq. 2 without the first-order expansion): the
+    mirror's rotation series, reprojection and chain agree with the oracle's
+    Rodrigues formula and adjoint."""
+    refs = [0.0, 0.3, 0.6, 1.0] if sets else [0.1, 0.5, 0.9]
+    win = eventgen.edge_window(36, "346x260", 3000, refs=refs, n_segments=12, motion_sigma=0.3)
+    if sets:
+        win = eventgen.with_flow_sets(win, 37)
+    win = win.replace(flow_model=1)
+    m = oracle.mirror_forward(win)
+    o = oracle.forward(win, valid=True)
+    assert m["n_valid"] == int(o["valid"].sum()) and m["n_valid"] > 1000
+    np.testing.assert_array_equal(m["nact"], o["nact"])
+    assert_loss_close(float(m["loss64"]), o["loss"], rtol=1e-12, what="exact")
+    # the first-order loss differs: the model switch is live
+    assert abs(oracle.loss(win.replace(flow_model=0)) - o["loss"]) > 1e-6 * abs(o["loss"])
+    mb = oracle.mirror_backward(win, grad_loss=1.3)
+    ob = oracle.backward(win, grad_loss=1.3)
+    F = win.rho.shape[0] if win.rho.ndim == 3 else 1
+    drm, dtm = mb["drho"].reshape(F, -1), mb["dtheta"].reshape(F, 6)
+    dro, dto = ob["drho"].reshape(F, -1), ob["dtheta"].reshape(F, 6)
+    for f in range(F):
+        assert_grads_close(drm[f], dtm[f], dro[f], dto[f], rtol=1e-5, what=f"exact set {f}")
