@@ -55,6 +55,9 @@ def _load():
                                  ctypes.c_int, ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P,
                                  ctypes.c_double, P, P, P]
     lib.cmo_backward.restype = ctypes.c_int
+    lib.cmo_geo.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int, P, P,
+                            ctypes.c_double, P, P, P, P]
+    lib.cmo_geo.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -166,6 +169,51 @@ def backward(win, rho=None, theta=None, grad_loss: float = 1.0, flow_grad=False)
     if flow_grad:
         res["dflow"] = dflow
     return res
+
+
+# ---------------------------------------------------------------------------
+# Geometry consistency (Eq. 3) and the full loss (Eq. 4)
+# ---------------------------------------------------------------------------
+
+LAMBDA_GEO = 0.05       # weight of L_geo in the paper's training set-up
+
+
+def geo(win, rho=None, theta=None, grad=False, grad_loss: float = 1.0) -> dict:
+    """L_geo (Eq. 3) of a window's consecutive flow sets: dict(loss,
+    pairs [F-1, 2] = per-pair (mean over V, |V|)) and, with grad, drho and
+    dtheta shaped like the flow sets (grad_loss * dL_geo/d(.)).  A window with
+    one flow set has L_geo = 0."""
+    lib = _load()
+    rho = _f64(win.rho if rho is None else rho)
+    theta = _f64(win.theta if theta is None else theta)
+    K = _f64([_as_f(win.fx), _as_f(win.fy), _as_f(win.cx), _as_f(win.cy)])
+    refs = _f64(win.refs)
+    F = n_flows(rho)
+    out = np.zeros(1, np.float64)
+    pairs = np.zeros((max(F - 1, 0), 2), np.float64)
+    drho = np.zeros(rho.shape, np.float64) if grad else None
+    dth = np.zeros(theta.shape, np.float64) if grad else None
+    st = lib.cmo_geo(win.width, win.height, _ptr(K), refs.shape[0], _ptr(refs), F, _ptr(rho),
+                     _ptr(theta), ctypes.c_double(grad_loss), _ptr(out),
+                     _ptr(pairs) if F > 1 else None, _ptr(drho), _ptr(dth))
+    if st != 0:
+        raise ValueError(f"cmo_geo failed ({st})")
+    res = dict(loss=float(out[0]), pairs=pairs)
+    if grad:
+        res["drho"], res["dtheta"] = drho, dth
+    return res
+
+
+def full_loss(win, lam: float = LAMBDA_GEO, rho=None, theta=None) -> float:
+    """Eq. 4: L = L_CM + lambda L_geo."""
+    return loss(win, rho, theta) + lam * geo(win, rho, theta)["loss"]
+
+
+def full_backward(win, lam: float = LAMBDA_GEO, grad_loss: float = 1.0) -> dict:
+    """Gradient of Eq. 4: the CM gradient plus lambda times the L_geo one."""
+    b = backward(win, grad_loss=grad_loss)
+    g = geo(win, grad=True, grad_loss=grad_loss)
+    return dict(drho=b["drho"] + lam * g["drho"], dtheta=b["dtheta"] + lam * g["dtheta"])
 
 
 # ---------------------------------------------------------------------------

@@ -633,3 +633,158 @@ int cmo_backward(int W, int H, const double* K, int R, const double* refs, doubl
     cmo_fwd_free(&f);
     return CMO_OK;
 }
+
+/* ===========================================================================
+ * Geometry consistency between consecutive flow sets (Sec. 3.2, Eq. 3) and
+ * the full loss (Eq. 4: L = L_CM + lambda L_geo, lambda = 0.05 in the paper's
+ * training set-up).
+ *
+ * The paper gives Eq. 3 and takes the rest from Bian et al.'s scale-consistency
+ * loss.  Readings:
+ *  - The depth of flow set f is D_f = 1/rho_f.  Consecutive sets f and f+1
+ *    form a pair.  The relative pose from set f's camera to set f+1's is the
+ *    motion over segment f at set f's velocity: rotation R = Exp(Delta_f w_f)
+ *    (Rodrigues) and translation t = Delta_f v_f, with Delta_f = k_{f+1} - k_f
+ *    the segment's length; a point maps as X -> R X + t, the convention of
+ *    Eq. 2's flow.
+ *  - Pixel x of set f back-projects to X = x0 / rho_f(x), x0 = ((i - cx)/fx,
+ *    (j - cy)/fy, 1).  The forward-projected depth D_{0->1}(x) is the z of
+ *    P = R X + t.  The interpolated depth D'_1(x) is the bilinear
+ *    interpolation of D_{f+1} at P's projection x' = (fx Px/Pz + cx,
+ *    fy Py/Pz + cy), over the taps that lie on the sensor.
+ *  - V (visible in both images): rho_f(x) > 0, Pz > 0, x' in the closed box
+ *    [0, W-1] x [0, H-1], and rho_{f+1} > 0 at every on-sensor tap of x'.
+ *  - L_geo of a window = mean over its F-1 pairs of the pair's mean over V of
+ *    |D_{0->1} - D'_1| / (D_{0->1} + D'_1).  An empty V gives that pair 0; a
+ *    window with one flow set has no pair and L_geo = 0.
+ *  - Derivative: |V| is held constant (it changes only where a pixel crosses
+ *    the validity boundary), d|d|/dd = sign(d) with sign(0) = 0, bilinear
+ *    weights differentiated with the floor-based formula.
+ * ======================================================================== */
+
+/* One pixel of a pair.  Returns 1 if x is in V; fills the scaled point
+ * p = rho_a P = R x0 + rho_a t, the taps of x', a = D_{0->1} = p_z / rho_a and
+ * b = D'_1.  x' is formed as the pixel plus its displacement,
+ * x' = i + fx (p_x/p_z - x0_x) (algebraically fx p_x/p_z + cx), so that zero
+ * motion maps every pixel exactly onto itself. */
+static int cmo_geo_pixel(const cmo_cam* c, int i, int j, double rho_a, const double* rho_b,
+                         const double R[9], const double t[3], double x0[3], double p[3],
+                         cmo_taps* tp, double* a, double* b)
+{
+    if (!(rho_a > 0.0)) return 0;
+    x0[0] = ((double)i - c->cx) / c->fx;
+    x0[1] = ((double)j - c->cy) / c->fy;
+    x0[2] = 1.0;
+    for (int k = 0; k < 3; ++k)
+        p[k] = R[3 * k + 0] * x0[0] + R[3 * k + 1] * x0[1] + R[3 * k + 2] * x0[2] + rho_a * t[k];
+    if (!(p[2] > 0.0)) return 0;
+    const double xs = (double)i + c->fx * (p[0] / p[2] - x0[0]);
+    const double ys = (double)j + c->fy * (p[1] / p[2] - x0[1]);
+    if (!cmo_inside(c, xs, ys)) return 0;
+    cmo_bilinear(c, xs, ys, tp);
+    *b = 0.0;
+    for (int q = 0; q < 4; ++q) {
+        if (!tp->in[q]) continue;
+        const double rb = rho_b[(size_t)tp->yi[q] * c->W + tp->xi[q]];
+        if (!(rb > 0.0)) return 0;
+        *b += tp->w[q] / rb;
+    }
+    *a = p[2] / rho_a;
+    return 1;
+}
+
+static void cmo_pair_pose(const cmo_cam* c, const double* theta, int f, double R[9],
+                          double Jr[9], double t[3], double* delta)
+{
+    *delta = c->knots[f + 1] - c->knots[f];
+    const double w[3] = {*delta * theta[6 * f + 3], *delta * theta[6 * f + 4],
+                         *delta * theta[6 * f + 5]};
+    cmo_rodrigues(w, R, Jr);
+    for (int k = 0; k < 3; ++k) t[k] = *delta * theta[6 * f + k];
+}
+
+/* Public: L_geo of one window (F >= 1 flow sets, rho [F][H*W], theta [F][6]).
+ * loss receives L_geo; pair_out (optional, [F-1][2]) the per-pair (mean over
+ * V, |V|); drho [F][H*W] and dtheta [F][6] (optional, both or neither)
+ * receive grad_loss * dL_geo/d(.). */
+int cmo_geo(int W, int H, const double* K, int R, const double* refs, int F,
+            const double* rho, const double* theta, double grad_loss, double* loss,
+            double* pair_out, double* drho, double* dtheta)
+{
+    cmo_cam cam;
+    int st = cmo_setup(&cam, W, H, K, R, refs, 1e-9, F, 0);
+    if (st) return st;
+    if (!rho || !theta || !loss || (!drho) != (!dtheta)) return CMO_BAD_ARG;
+    const cmo_cam* c = &cam;
+    const size_t HW = (size_t)H * W;
+    *loss = 0.0;
+    if (drho) {
+        memset(drho, 0, sizeof(double) * HW * (size_t)F);
+        memset(dtheta, 0, sizeof(double) * 6 * (size_t)F);
+    }
+    if (F < 2) return CMO_OK;
+    for (int f = 0; f + 1 < F; ++f) {
+        double Rm[9], Jr[9], t[3], delta;
+        cmo_pair_pose(c, theta, f, Rm, Jr, t, &delta);
+        const double* ra = rho + HW * f;
+        const double* rb = rho + HW * (f + 1);
+        double sum = 0.0, nv = 0.0;
+        for (int j = 0; j < H; ++j)
+            for (int i = 0; i < W; ++i) {
+                double x0[3], pp[3], a, b;
+                cmo_taps tp;
+                if (!cmo_geo_pixel(c, i, j, ra[(size_t)j * W + i], rb, Rm, t, x0, pp, &tp, &a, &b))
+                    continue;
+                sum += fabs(a - b) / (a + b);
+                nv += 1.0;
+            }
+        const double mean = nv > 0.0 ? sum / nv : 0.0;
+        *loss += mean / (double)(F - 1);
+        if (pair_out) { pair_out[2 * f] = mean; pair_out[2 * f + 1] = nv; }
+        if (!drho || nv == 0.0) continue;
+        /* backward of the pair */
+        const double cf = grad_loss / ((double)(F - 1) * nv);
+        double* dra = drho + HW * f;
+        double* drb = drho + HW * (f + 1);
+        double dpose[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < H; ++j)
+            for (int i = 0; i < W; ++i) {
+                const double rho_a = ra[(size_t)j * W + i];
+                double x0[3], pp[3], a, b;
+                cmo_taps tp;
+                if (!cmo_geo_pixel(c, i, j, rho_a, rb, Rm, t, x0, pp, &tp, &a, &b)) continue;
+                const double s = a > b ? 1.0 : (a < b ? -1.0 : 0.0);
+                const double den = (a + b) * (a + b);
+                const double ga = cf * s * 2.0 * b / den;      /* d/da of |a-b|/(a+b) */
+                const double gb = -cf * s * 2.0 * a / den;     /* d/db */
+                /* b = sum_q w_q / rho_b[q] */
+                double dbx = 0.0, dby = 0.0;
+                for (int q = 0; q < 4; ++q) {
+                    if (!tp.in[q]) continue;
+                    const size_t pq = (size_t)tp.yi[q] * W + tp.xi[q];
+                    drb[pq] += gb * tp.w[q] * (-1.0 / (rb[pq] * rb[pq]));
+                    dbx += tp.dwx[q] / rb[pq];
+                    dby += tp.dwy[q] / rb[pq];
+                }
+                /* x' = i + fx (p_x/p_z - x0_x), y' likewise, a = p_z / rho_a */
+                const double gxs = gb * dbx, gys = gb * dby;
+                const double gp[3] = {gxs * c->fx / pp[2], gys * c->fy / pp[2],
+                                      ga / rho_a - (gxs * c->fx * pp[0] + gys * c->fy * pp[1]) / (pp[2] * pp[2])};
+                /* p = R x0 + rho_a t */
+                dra[(size_t)j * W + i] += gp[0] * t[0] + gp[1] * t[1] + gp[2] * t[2]
+                                          - ga * pp[2] / (rho_a * rho_a);
+                for (int k = 0; k < 3; ++k) dpose[k] += rho_a * gp[k];
+                /* d(R x0)/dw = -R [x0]x Jr  =>  dw += Jr^T (x0 x (R^T gp)) */
+                double sv[3];
+                for (int k = 0; k < 3; ++k)
+                    sv[k] = Rm[0 * 3 + k] * gp[0] + Rm[1 * 3 + k] * gp[1] + Rm[2 * 3 + k] * gp[2];
+                const double cr[3] = {x0[1] * sv[2] - x0[2] * sv[1], x0[2] * sv[0] - x0[0] * sv[2],
+                                      x0[0] * sv[1] - x0[1] * sv[0]};
+                for (int k = 0; k < 3; ++k)
+                    dpose[3 + k] += Jr[0 * 3 + k] * cr[0] + Jr[1 * 3 + k] * cr[1] + Jr[2 * 3 + k] * cr[2];
+            }
+        /* pose = Delta_f theta_f */
+        for (int k = 0; k < 6; ++k) dtheta[6 * f + k] += delta * dpose[k];
+    }
+    return CMO_OK;
+}

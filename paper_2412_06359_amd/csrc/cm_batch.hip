@@ -843,7 +843,7 @@ __global__ __launch_bounds__(NT) void bwd_sweep_kernel(
 // Accumulate dL/du = sum over records of w_tap * (dt * adjoint) in LDS; own
 // pixels off the border get d rho and their d theta share here, the border
 // and the halo go to buffers for the merge.
-template <bool DET>
+template <bool DET, bool EXACT>
 __global__ __launch_bounds__(256) void bwd_tile_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const GradRec* __restrict__ rec,
     const uint32_t* __restrict__ start, const float* __restrict__ rho,
@@ -919,9 +919,11 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(
     __syncthreads();
     const float* ego_s = ego + 6 * (meta[w].ego_off + set);
     const Motion m = load_motion(P, ego_s);
-    __shared__ MotionXJ mx;
-    if (P.model == 1 && threadIdx.x == 0) mx = load_motion_xj(ego_s);
-    __syncthreads();
+    __shared__ MotionXJ mx[1];      // used by the exact model only
+    if (EXACT) {
+        if (threadIdx.x == 0) mx[0] = load_motion_xj(ego_s);
+        __syncthreads();
+    }
     const float* rho_w = rho + meta[w].pix_off + (size_t)set * P.HW;
     float* drho_w = drho + meta[w].pix_off + (size_t)set * P.HW;
     const double gl = (double)grad_loss[w];
@@ -936,9 +938,9 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(
             continue;
         }
         const int pix = Y * P.W + X;
-        if (P.model == 1) {
+        if constexpr (EXACT) {
             double d = 0.0;
-            if (g.x != 0.0 || g.y != 0.0) d = chain_exact(P, mx, X, Y, (double)rho_w[pix], g.x, g.y, dth);
+            if (g.x != 0.0 || g.y != 0.0) d = chain_exact(P, mx[0], X, Y, (double)rho_w[pix], g.x, g.y, dth);
             drho_w[pix] = (float)(gl * d);
             continue;
         }
@@ -959,6 +961,7 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(
     }
 }
 
+template <bool EXACT>
 __global__ __launch_bounds__(64) void bwd_merge_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const float* __restrict__ rho,
     const float* __restrict__ ego, const float* __restrict__ grad_loss,
@@ -976,9 +979,11 @@ __global__ __launch_bounds__(64) void bwd_merge_kernel(
     const int xo = tx * TW, yo = ty * TH;
     const float* ego_s = ego + 6 * (meta[w].ego_off + set);
     const Motion m = load_motion(P, ego_s);
-    __shared__ MotionXJ mx;
-    if (P.model == 1 && threadIdx.x == 0) mx = load_motion_xj(ego_s);
-    __syncthreads();
+    __shared__ MotionXJ mx[1];      // used by the exact model only
+    if (EXACT) {
+        if (threadIdx.x == 0) mx[0] = load_motion_xj(ego_s);
+        __syncthreads();
+    }
     const float* rho_w = rho + meta[w].pix_off + (size_t)set * P.HW;
     float* drho_w = drho + meta[w].pix_off + (size_t)set * P.HW;
     const double gl = (double)grad_loss[w];
@@ -1005,9 +1010,9 @@ __global__ __launch_bounds__(64) void bwd_merge_kernel(
             g.y += h.y;
         }
         const int pix = Y * P.W + X;
-        if (P.model == 1) {
+        if constexpr (EXACT) {
             double d = 0.0;
-            if (g.x != 0.0 || g.y != 0.0) d = chain_exact(P, mx, X, Y, (double)rho_w[pix], g.x, g.y, dth);
+            if (g.x != 0.0 || g.y != 0.0) d = chain_exact(P, mx[0], X, Y, (double)rho_w[pix], g.x, g.y, dth);
             drho_w[pix] = (float)(gl * d);
             continue;
         }
@@ -1328,10 +1333,11 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
     }
     {
         PhaseScope ph(prof, kPhGradTile, s);
-        bwd_tile_kernel<DET><<<(int)B.nbins_b, 256, 0, s>>>(meta, nw, win_tile, rec, start, rho, ego, grad_loss,
-                                                      grad_rho, halo, border, part);
-        bwd_merge_kernel<<<(int)B.nbins_b, 64, 0, s>>>(meta, nw, win_tile, rho, ego, grad_loss, grad_rho,
-                                                      halo, border, part);
+        constexpr bool EX = FM == 2;
+        bwd_tile_kernel<DET, EX><<<(int)B.nbins_b, 256, 0, s>>>(meta, nw, win_tile, rec, start, rho, ego,
+                                                                grad_loss, grad_rho, halo, border, part);
+        bwd_merge_kernel<EX><<<(int)B.nbins_b, 64, 0, s>>>(meta, nw, win_tile, rho, ego, grad_loss,
+                                                           grad_rho, halo, border, part);
     }
     {
         PhaseScope ph(prof, kPhGradFinalize, s);
