@@ -38,6 +38,12 @@ WORKLOADS = {
 }
 
 
+# L_geo forward + backward per (pixel, pair): rho_a and the rho_{f+1} image
+# read twice (8 + 8 bytes), d rho_a and d rho_{f+1} read-modify-written
+# (8 + 8 bytes); pose partials and pair sums are negligible.
+GEO_BYTES_PER_PIXEL_PAIR = 32
+
+
 def kernel_source_sha() -> str:
     from paper_2412_06359_amd.build import source_sha
     return source_sha()
@@ -333,6 +339,28 @@ def main():
         n6 = sum(w.n for w in w6)
         out_extra["c6_batched"] = {"workload": WORKLOADS["c6"], "n_events": n6,
                                    "ms_per_step": ms6, "events_per_s": n6 / (ms6 * 1e-3)}
+        # the full training loss of Eq. 4: L_CM + 0.05 L_geo over consecutive slices
+        gst6 = torch.empty(b6.geo_state_bytes(), dtype=torch.uint8, device=dev)
+
+        def step6_full():
+            step6()
+            b6.geo_forward(d6["rho"], d6["ego"], cm.LAMBDA_GEO, l6, state=gst6)
+            b6.geo_backward(d6["rho"], d6["ego"], gst6, gl6, gr6, ge6, cm.LAMBDA_GEO)
+
+        def step6_geo():
+            b6.geo_forward(d6["rho"], d6["ego"], cm.LAMBDA_GEO, l6, state=gst6)
+            b6.geo_backward(d6["rho"], d6["ego"], gst6, gl6, gr6, ge6, cm.LAMBDA_GEO)
+        ms6f = timed(step6_full, args.steps, args.warmup, stream)
+        ms6g = timed(step6_geo, args.steps, args.warmup, stream)
+        pairs = sum((w.rho.shape[0] - 1) * w.width * w.height for w in w6)
+        geo_bytes = GEO_BYTES_PER_PIXEL_PAIR * pairs
+        out_extra["c6_full_loss"] = {
+            "workload": WORKLOADS["c6"] + " + lambda L_geo (Eq. 4, lambda 0.05) over the 9 "
+                        "consecutive slice pairs",
+            "ms_per_step": ms6f, "events_per_s": n6 / (ms6f * 1e-3),
+            "geo_ms_per_step": ms6g, "pixel_pairs": pairs,
+            "geo_algorithmic_bytes": geo_bytes,
+            "geo_achieved_gbs": geo_bytes / (ms6g * 1e-3) / 1e9}
         b6.close()
 
     if not args.no_extras and args.workload != "c2":

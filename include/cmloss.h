@@ -221,6 +221,50 @@ cm_status cm_batch_diagnostics(cm_batch b, const void* state, double* out, void*
  * measurement aid for the splat's minimal image traffic. */
 cm_status cm_batch_occupied_image_bytes(cm_batch b, const void* state, double* out, void* stream);
 
+/* Geometry consistency and the full loss (paper Sec. 3.2 Eq. 3, Eq. 4).
+ *
+ * For a window with F >= 2 flow sets, consecutive sets f and f+1 form a pair.
+ * Set f's pixel x (depth D_f = 1/rho_f(x)) moves with segment f's motion --
+ * rotation Exp(Delta_f w_f), translation Delta_f v_f, Delta_f the segment's
+ * length in window time -- giving the forward-projected depth D_{0->1}(x)
+ * (the moved point's z) and, at the moved point's projection x', the bilinear
+ * interpolation D'_1(x) of D_{f+1}.  V: pixels with rho_f > 0 whose point
+ * stays in front of the camera, with x' inside the image and rho_{f+1} > 0 at
+ * x''s on-sensor taps.  L_geo = mean over the F-1 pairs of
+ * mean over V of |D_{0->1} - D'_1| / (D_{0->1} + D'_1) (an empty V counts
+ * 0); a window with one flow set has L_geo = 0.  The full loss is
+ * L = L_CM + lambda L_geo (the paper trains with lambda = 0.05).
+ *
+ * inv_depth and ego are laid out as for the CM loss.  `state` is a caller
+ * buffer of cm_geo_state_bytes (cm_batch_geo_state_bytes) bytes, separate from
+ * the CM state; the backward reads what the forward on the same state and
+ * inputs wrote.  Results are deterministic in both modes (fixed-order
+ * reductions; in the deterministic mode the scatter of d rho_{f+1} is summed
+ * in 64-bit fixed point, so d inv_depth is bit-identical from run to run).
+ *
+ * Forward: loss_geo (device, [1] or [n_windows]) receives L_geo; if loss_total
+ * is not NULL it receives loss_cm + lambda L_geo, loss_cm (device, may be NULL
+ * for 0) being the CM loss of the same windows.  lambda must be finite.
+ * Backward: ACCUMULATES grad_loss * lambda * dL_geo/d(inv_depth, ego) into
+ * grad_inv_depth and grad_ego, so that after cm_loss_backward (which writes
+ * them) they hold the gradient of L = L_CM + lambda L_geo; grad_loss (device,
+ * [1] or [n_windows]) is dE/dL of the caller's objective E.  |V| is held
+ * constant in the derivative and d|d|/dd = sign(d), sign(0) = 0. */
+size_t cm_geo_state_bytes(const cm_window_desc* d);
+cm_status cm_geo_forward(cm_handle h, const cm_window_desc* d, const float* inv_depth,
+                         const float* ego, float lambda, const float* loss_cm, float* loss_geo,
+                         float* loss_total, void* state, void* stream);
+cm_status cm_geo_backward(cm_handle h, const cm_window_desc* d, const float* inv_depth,
+                          const float* ego, float lambda, void* state, const float* grad_loss,
+                          float* grad_inv_depth, float* grad_ego, void* stream);
+size_t cm_batch_geo_state_bytes(cm_batch b);
+cm_status cm_geo_forward_batched(cm_batch b, const float* inv_depth, const float* ego,
+                                 float lambda, const float* loss_cm, float* loss_geo,
+                                 float* loss_total, void* state, void* stream);
+cm_status cm_geo_backward_batched(cm_batch b, const float* inv_depth, const float* ego,
+                                  float lambda, void* state, const float* grad_loss,
+                                  float* grad_inv_depth, float* grad_ego, void* stream);
+
 /* Phase timing (diagnostics, not part of the method).  While enabled on a
  * handle, each call records a pair of HIP events on its stream around every
  * kernel it launches.  cm_profile_read waits for the recorded events, writes

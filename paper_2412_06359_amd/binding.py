@@ -138,6 +138,19 @@ def load() -> ctypes.CDLL:
         lib.cm_batch_diagnostics.restype = ctypes.c_int
         lib.cm_batch_occupied_image_bytes.argtypes = [P, P, P, P]
         lib.cm_batch_occupied_image_bytes.restype = ctypes.c_int
+        f32 = ctypes.c_float
+        lib.cm_geo_state_bytes.argtypes = [D]
+        lib.cm_geo_state_bytes.restype = ctypes.c_size_t
+        lib.cm_geo_forward.argtypes = [P, D, P, P, f32, P, P, P, P, P]
+        lib.cm_geo_forward.restype = ctypes.c_int
+        lib.cm_geo_backward.argtypes = [P, D, P, P, f32, P, P, P, P, P]
+        lib.cm_geo_backward.restype = ctypes.c_int
+        lib.cm_batch_geo_state_bytes.argtypes = [P]
+        lib.cm_batch_geo_state_bytes.restype = ctypes.c_size_t
+        lib.cm_geo_forward_batched.argtypes = [P, P, P, f32, P, P, P, P, P]
+        lib.cm_geo_forward_batched.restype = ctypes.c_int
+        lib.cm_geo_backward_batched.argtypes = [P, P, P, f32, P, P, P, P, P]
+        lib.cm_geo_backward_batched.restype = ctypes.c_int
         lib.cm_profile_enable.argtypes = [P, ctypes.c_int]
         lib.cm_profile_enable.restype = ctypes.c_int
         lib.cm_profile_read.argtypes = [P, P, P]
@@ -252,6 +265,54 @@ def backward(desc: WindowDesc, x, y, t, p, rho, ego, state, grad_loss,
     return grad_rho, grad_ego
 
 
+LAMBDA_GEO = 0.05       # weight of L_geo in the full loss (the paper's training value)
+
+
+def geo_state_bytes(desc: WindowDesc) -> int:
+    n = load().cm_geo_state_bytes(ctypes.byref(desc))
+    if n == 0:
+        raise CMError(-1, "cm_geo_state_bytes (invalid descriptor)")
+    return int(n)
+
+
+def geo_forward(desc: WindowDesc, rho, ego, lam: float = LAMBDA_GEO, loss_cm=None, state=None):
+    """cm_geo_forward on torch's current stream.  Returns (loss_geo [1],
+    loss_total [1] = loss_cm + lam * loss_geo (None without loss_cm), state)."""
+    _check_params(desc, rho, ego)
+    dev = rho.device
+    nbytes = geo_state_bytes(desc)
+    if state is None:
+        state = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    elif state.numel() * state.element_size() < nbytes or not state.is_contiguous():
+        raise ValueError(f"geo state: need {nbytes} contiguous bytes")
+    loss_geo = torch.empty(1, dtype=torch.float32, device=dev)
+    total = None if loss_cm is None else torch.empty(1, dtype=torch.float32, device=dev)
+    st = load().cm_geo_forward(handle(dev.index), ctypes.byref(desc), _ptr(rho), _ptr(ego),
+                               float(lam), _ptr(loss_cm), _ptr(loss_geo), _ptr(total),
+                               _ptr(state), _stream(dev))
+    _check(st, "cm_geo_forward")
+    return loss_geo, total, state
+
+
+def geo_backward(desc: WindowDesc, rho, ego, state, grad_loss, grad_rho, grad_ego,
+                 lam: float = LAMBDA_GEO):
+    """cm_geo_backward: adds grad_loss * lam * dL_geo/d(rho, ego) into grad_rho
+    and grad_ego (in place)."""
+    _check_params(desc, rho, ego)
+    dev = rho.device
+    if state.numel() * state.element_size() < geo_state_bytes(desc):
+        raise ValueError("geo state buffer too small")
+    gl = grad_loss.reshape(1).to(device=dev, dtype=torch.float32).contiguous()
+    for name, g, ref in (("grad_rho", grad_rho, rho), ("grad_ego", grad_ego, ego)):
+        if g.dtype != torch.float32 or g.numel() != ref.numel() or not g.is_contiguous():
+            raise ValueError(f"{name}: need contiguous float32 of {ref.numel()} elements")
+    st = load().cm_geo_backward(handle(dev.index), ctypes.byref(desc), _ptr(rho), _ptr(ego),
+                                float(lam), _ptr(state), _ptr(gl), _ptr(grad_rho),
+                                _ptr(grad_ego), _stream(dev))
+    _check(st, "cm_geo_backward")
+    return grad_rho, grad_ego
+
+
 def diagnostics(desc: WindowDesc, state: torch.Tensor) -> dict:
     """Per-window sums of the last forward (synchronises the stream)."""
     R = desc.R
@@ -346,6 +407,42 @@ class Batch:
         _check(st, "cm_loss_backward_batched")
         return grad_rho, grad_ego
 
+    def geo_state_bytes(self) -> int:
+        return int(load().cm_batch_geo_state_bytes(self._b))
+
+    def geo_forward(self, rho, ego, lam: float = LAMBDA_GEO, loss_cm=None, state=None):
+        """cm_geo_forward_batched: (loss_geo [n], loss_total [n] or None, state)."""
+        dev = rho.device
+        ne = 6 * self.set_offsets[-1]
+        if rho.dtype != torch.float32 or rho.numel() != self.pixel_offsets[-1] or \
+                not rho.is_contiguous() or ego.dtype != torch.float32 or ego.numel() != ne or \
+                not ego.is_contiguous():
+            raise ValueError("inv_depth / ego do not match the batch")
+        nbytes = self.geo_state_bytes()
+        state = torch.empty(nbytes, dtype=torch.uint8, device=dev) if state is None else state
+        if state.numel() * state.element_size() < nbytes:
+            raise ValueError("geo state buffer too small")
+        loss_geo = torch.empty(self.n, dtype=torch.float32, device=dev)
+        total = None if loss_cm is None else torch.empty(self.n, dtype=torch.float32, device=dev)
+        st = load().cm_geo_forward_batched(self._b, _ptr(rho), _ptr(ego), float(lam),
+                                           _ptr(loss_cm), _ptr(loss_geo), _ptr(total),
+                                           _ptr(state), _stream(dev))
+        _check(st, "cm_geo_forward_batched")
+        return loss_geo, total, state
+
+    def geo_backward(self, rho, ego, state, grad_loss, grad_rho, grad_ego,
+                     lam: float = LAMBDA_GEO):
+        """cm_geo_backward_batched: adds the L_geo gradient into grad_rho / grad_ego."""
+        dev = rho.device
+        gl = grad_loss.reshape(self.n).to(device=dev, dtype=torch.float32).contiguous()
+        if grad_rho.numel() != rho.numel() or grad_ego.numel() != ego.numel():
+            raise ValueError("gradient buffers do not match the batch")
+        st = load().cm_geo_backward_batched(self._b, _ptr(rho), _ptr(ego), float(lam),
+                                            _ptr(state), _ptr(gl), _ptr(grad_rho),
+                                            _ptr(grad_ego), _stream(dev))
+        _check(st, "cm_geo_backward_batched")
+        return grad_rho, grad_ego
+
     def occupied_image_bytes(self, state) -> list:
         """Per window, splat-image bytes of its occupied tiles after the last
         forward (call before the backward; synchronises)."""
@@ -379,6 +476,30 @@ class BatchCMLoss(torch.autograd.Function):
         x, y, t, p, rho, ego, state = ctx.saved_tensors
         g_rho, g_ego = ctx.batch.backward(x, y, t, p, rho, ego, state, grad_out.contiguous())
         return None, None, None, None, g_rho.reshape(rho.shape), g_ego.reshape(ego.shape), None
+
+
+class BatchFullLoss(torch.autograd.Function):
+    """Per-window full losses L = L_CM + lam L_geo (Eq. 4) of a batch;
+    differentiable in inv_depth and ego."""
+
+    @staticmethod
+    def forward(ctx, x, y, t, p, rho, ego, batch, lam):
+        rho_c = rho.detach().contiguous()
+        ego_c = ego.detach().contiguous()
+        loss_cm, state = batch.forward(x, y, t, p, rho_c, ego_c)
+        _, total, gstate = batch.geo_forward(rho_c, ego_c, lam, loss_cm)
+        ctx.batch, ctx.lam = batch, lam
+        ctx.save_for_backward(x, y, t, p, rho_c, ego_c, state, gstate)
+        return total
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        x, y, t, p, rho, ego, state, gstate = ctx.saved_tensors
+        g = grad_out.contiguous()
+        g_rho, g_ego = ctx.batch.backward(x, y, t, p, rho, ego, state, g)
+        ctx.batch.geo_backward(rho, ego, gstate, g, g_rho, g_ego, ctx.lam)
+        return (None, None, None, None, g_rho.reshape(rho.shape), g_ego.reshape(ego.shape), None,
+                None)
 
 
 PHASES = ("zero", "splat", "reduce", "finalize", "grad_zero", "adjoint", "grad_finalize",
@@ -426,3 +547,31 @@ class CMLoss(torch.autograd.Function):
 def cm_loss(x, y, t, p, inv_depth, ego, desc: WindowDesc) -> torch.Tensor:
     """Differentiable CM loss (see CMLoss)."""
     return CMLoss.apply(x, y, t, p, inv_depth, ego, desc)
+
+
+class FullLoss(torch.autograd.Function):
+    """Full loss of one window, L = L_CM + lam L_geo (Eq. 4); differentiable
+    in inv_depth and ego (both terms' gradients come from the library)."""
+
+    @staticmethod
+    def forward(ctx, x, y, t, p, rho, ego, desc, lam):
+        rho_c = rho.detach().contiguous()
+        ego_c = ego.detach().contiguous()
+        loss_cm, state = forward(desc, x, y, t, p, rho_c, ego_c)
+        _, total, gstate = geo_forward(desc, rho_c, ego_c, lam, loss_cm)
+        ctx.desc, ctx.lam = desc, lam
+        ctx.save_for_backward(x, y, t, p, rho_c, ego_c, state, gstate)
+        return total.reshape(())
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        x, y, t, p, rho, ego, state, gstate = ctx.saved_tensors
+        g_rho, g_ego = backward(ctx.desc, x, y, t, p, rho, ego, state, grad_out)
+        geo_backward(ctx.desc, rho, ego, gstate, grad_out, g_rho, g_ego, ctx.lam)
+        return (None, None, None, None, g_rho.reshape(rho.shape), g_ego.reshape(ego.shape), None,
+                None)
+
+
+def full_loss(x, y, t, p, inv_depth, ego, desc: WindowDesc, lam: float = LAMBDA_GEO):
+    """Differentiable L = L_CM + lam L_geo of one window (see FullLoss)."""
+    return FullLoss.apply(x, y, t, p, inv_depth, ego, desc, lam)

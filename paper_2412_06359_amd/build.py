@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcmloss.so")
 PROBE_LIB = os.path.join(PKG, "libcmprobe.so")
 
-SOURCES = ["cm_api.hip", "cm_kernels.hip", "cm_batch.hip"]
+SOURCES = ["cm_api.hip", "cm_kernels.hip", "cm_batch.hip", "cm_geo.hip"]
 PROBE_SOURCES = ["cm_probe.hip"]
 
 HIPCC_FLAGS = [

@@ -578,4 +578,112 @@ cm_status cm_batch_occupied_image_bytes(cm_batch b, const void* state, double* o
     return CM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Geometry consistency (Eq. 3) and the full loss (Eq. 4)
+// ---------------------------------------------------------------------------
+
+static cm::GeoLayout geo_layout_one(const cm_window_desc* d)
+{
+    const int F = flows_of(d);
+    const int HW = d->width * d->height;
+    return cm::geo_layout(1, F, cm::geo_tiles(d->width, d->height), HW, (int64_t)F * HW,
+                          d->mode == CM_MODE_DETERMINISTIC);
+}
+
+static cm::GeoLayout geo_layout_batch(const cm_batch_s* b)
+{
+    int max_F = 1, max_HW = 1, max_tiles = 1;
+    for (const WinMeta& m : b->B.meta) {
+        max_F = std::max(max_F, m.P.F);
+        max_HW = std::max(max_HW, m.P.HW);
+        max_tiles = std::max(max_tiles, cm::geo_tiles(m.P.W, m.P.H));
+    }
+    return cm::geo_layout(b->B.nw, max_F, max_tiles, max_HW, b->B.n_pixels, b->B.det);
+}
+
+static WinMeta geo_meta_one(const cm_window_desc* d)
+{
+    WinMeta m;
+    std::memset(&m, 0, sizeof m);
+    m.P = params_of(d);
+    return m;
+}
+
+size_t cm_geo_state_bytes(const cm_window_desc* d)
+{
+    if (!desc_valid(d)) return 0;
+    return geo_layout_one(d).total;
+}
+
+cm_status cm_geo_forward(cm_handle h, const cm_window_desc* d, const float* inv_depth,
+                         const float* ego, float lambda, const float* loss_cm, float* loss_geo,
+                         float* loss_total, void* state, void* stream)
+{
+    if (!h || !desc_valid(d) || !inv_depth || !ego || !loss_geo || !state ||
+        !std::isfinite(lambda))
+        return CM_ERR_INVALID_ARG;
+    DeviceGuard g(h->device);
+    if (!g.ok()) return CM_ERR_HIP;
+    const cm::GeoLayout L = geo_layout_one(d);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    WinMeta* meta = reinterpret_cast<WinMeta*>(static_cast<char*>(state) + L.meta);
+    if (cm::launch_store_meta(geo_meta_one(d), meta, s) != hipSuccess) return CM_ERR_HIP;
+    return status_of(cm::launch_geo_forward(L, 1, state, inv_depth, ego, lambda, loss_cm,
+                                            loss_geo, loss_total, s));
+}
+
+cm_status cm_geo_backward(cm_handle h, const cm_window_desc* d, const float* inv_depth,
+                          const float* ego, float lambda, void* state, const float* grad_loss,
+                          float* grad_inv_depth, float* grad_ego, void* stream)
+{
+    if (!h || !desc_valid(d) || !inv_depth || !ego || !state || !grad_loss || !grad_inv_depth ||
+        !grad_ego || !std::isfinite(lambda))
+        return CM_ERR_INVALID_ARG;
+    DeviceGuard g(h->device);
+    if (!g.ok()) return CM_ERR_HIP;
+    const cm::GeoLayout L = geo_layout_one(d);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    WinMeta* meta = reinterpret_cast<WinMeta*>(static_cast<char*>(state) + L.meta);
+    if (cm::launch_store_meta(geo_meta_one(d), meta, s) != hipSuccess) return CM_ERR_HIP;
+    return status_of(cm::launch_geo_backward(L, 1, state, inv_depth, ego, lambda, grad_loss,
+                                             grad_inv_depth, grad_ego, s));
+}
+
+size_t cm_batch_geo_state_bytes(cm_batch b) { return b ? geo_layout_batch(b).total : 0; }
+
+cm_status cm_geo_forward_batched(cm_batch b, const float* inv_depth, const float* ego,
+                                 float lambda, const float* loss_cm, float* loss_geo,
+                                 float* loss_total, void* state, void* stream)
+{
+    if (!b || !inv_depth || !ego || !loss_geo || !state || !std::isfinite(lambda))
+        return CM_ERR_INVALID_ARG;
+    DeviceGuard g(b->h->device);
+    if (!g.ok()) return CM_ERR_HIP;
+    const cm::GeoLayout L = geo_layout_batch(b);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(static_cast<char*>(state) + L.meta, b->B.meta.data(),
+                       sizeof(WinMeta) * b->B.nw, hipMemcpyHostToDevice, s) != hipSuccess)
+        return CM_ERR_HIP;
+    return status_of(cm::launch_geo_forward(L, b->B.nw, state, inv_depth, ego, lambda, loss_cm,
+                                            loss_geo, loss_total, s));
+}
+
+cm_status cm_geo_backward_batched(cm_batch b, const float* inv_depth, const float* ego,
+                                  float lambda, void* state, const float* grad_loss,
+                                  float* grad_inv_depth, float* grad_ego, void* stream)
+{
+    if (!b || !inv_depth || !ego || !state || !grad_loss || !grad_inv_depth || !grad_ego ||
+        !std::isfinite(lambda))
+        return CM_ERR_INVALID_ARG;
+    DeviceGuard g(b->h->device);
+    if (!g.ok()) return CM_ERR_HIP;
+    const cm::GeoLayout L = geo_layout_batch(b);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(static_cast<char*>(state) + L.meta, b->B.meta.data(),
+                       sizeof(WinMeta) * b->B.nw, hipMemcpyHostToDevice, s) != hipSuccess)
+        return CM_ERR_HIP;
+    return status_of(cm::launch_geo_backward(L, b->B.nw, state, inv_depth, ego, lambda,
+                                             grad_loss, grad_inv_depth, grad_ego, s));
+}
+
 }  // extern "C"

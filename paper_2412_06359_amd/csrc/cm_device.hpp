@@ -191,10 +191,9 @@ __device__ __forceinline__ double rot_series(double s, int o)
     return h;
 }
 
-__device__ __forceinline__ void rotation_of(const float* __restrict__ ego, double (&R)[9],
-                                            double* Jr)
+__device__ __forceinline__ void rotation_exp(double wx, double wy, double wz, double (&R)[9],
+                                             double* Jr)
 {
-    const double wx = ego[3], wy = ego[4], wz = ego[5];
     const double s = (wx * wx + wy * wy) + wz * wz;
     const double a = rot_series(s, 1);           // sin t / t
     const double b = 0.5 * rot_series(s, 2);     // (1 - cos t) / t^2
@@ -219,6 +218,12 @@ __device__ __forceinline__ void rotation_of(const float* __restrict__ ego, doubl
             Jr[i] = (I - b * K[i]) + c * K2[i];
         }
     }
+}
+
+__device__ __forceinline__ void rotation_of(const float* __restrict__ ego, double (&R)[9],
+                                            double* Jr)
+{
+    rotation_exp(ego[3], ego[4], ego[5], R, Jr);
 }
 
 __device__ __forceinline__ MotionX load_motion_x(const float* __restrict__ ego)

@@ -185,4 +185,33 @@ hipError_t launch_backward_batch(const BatchPlanHost& B, const WinMeta* meta,
                                  const float* grad_loss, float* grad_rho, float* grad_ego,
                                  char* ws, hipStream_t s, Profiler* prof);
 
+
+// Geometry consistency (Eq. 3) between consecutive flow sets and the full loss
+// (Eq. 4).  Per (window, pair) results of a forward, read by the backward.
+struct GeoPairSum {
+    double mean;            // mean over V of |D_{0->1} - D'_1| / (D_{0->1} + D'_1)
+    double count;           // |V|
+    double scale;           // fixed-point scale of the deterministic scatter (2^e)
+};
+
+// Byte offsets of the geometry-consistency state: window metadata, block
+// partials, pair sums, pair poses, fixed-point accumulator (deterministic mode only, one
+// 64-bit cell per inverse-depth pixel).
+struct GeoLayout {
+    int nblk = 1;           // 32 x 32 tiles per (window, pair) in the grid
+    int napply = 1;         // pixel blocks per (window, pair) of the deterministic apply pass
+    int npm = 1;            // pair slots per window (max F - 1)
+    bool det = false;
+    int64_t n_acc = 0;
+    size_t meta = 0, part = 0, pairs = 0, poses = 0, acc = 0, total = 0;
+};
+GeoLayout geo_layout(int nw, int max_F, int max_tiles, int max_HW, int64_t n_pixels, bool det);
+inline int geo_tiles(int W, int H) { return ((W + 31) / 32) * ((H + 31) / 32); }
+hipError_t launch_geo_forward(const GeoLayout& L, int nw, void* state, const float* rho,
+                              const float* ego, float lambda, const float* loss_cm,
+                              float* loss_geo, float* loss_total, hipStream_t s);
+hipError_t launch_geo_backward(const GeoLayout& L, int nw, void* state, const float* rho,
+                               const float* ego, float lambda, const float* grad_loss,
+                               float* grad_rho, float* grad_ego, hipStream_t s);
+
 }  // namespace cm
