@@ -263,6 +263,35 @@ def edge_window(seed: int, sensor: str, n_events: int, refs, n_segments: int = 5
                   x, y, t, p, rho, theta)
 
 
+def motion_stream(seed: int, n_windows: int, sensor: str = "346x260", n_events: int = 20000,
+                  refs=(0.0, 0.5, 1.0), motion_sigma: float = 0.3, drift: float = 0.03,
+                  n_segments: int = 20) -> List[Window]:
+    """Windows of one stream for online fitting: a fixed edge map and depth
+    (drawn as in edge_window), camera motion theta_0 ~ N(0, motion_sigma^2)
+    per axis drifting by N(0, drift^2) per axis from one window to the next.
+    Each window observes the same edge map (same segments and event draws)
+    under its own motion; theta of window k is its ground truth."""
+    s = SENSORS[sensor]
+    W, H, f = s["width"], s["height"], s["f"]
+    cx, cy = (W - 1) / 2.0, (H - 1) / 2.0
+    rng = _rng(seed)
+    mus = np.stack([rng.uniform(0, W - 1, 4), rng.uniform(0, H - 1, 4)], 1)
+    rho_fn = _GaussianBumps(mus, W / 6.0, norm_range=(0.2, 2.0), grid=(W, H))
+    rho = rho_fn.grid(W, H)
+    theta = rng.normal(0.0, motion_sigma, 6)
+    out = []
+    for k in range(n_windows):
+        if k > 0:
+            theta = theta + rng.normal(0.0, drift, 6)
+        th = theta.astype(np.float32)
+        x, y, t, p = _simulate_edge_events(_rng(seed + 77), n_events, W, H, f, f, cx, cy, rho_fn,
+                                           th[:3].astype(np.float64), th[3:].astype(np.float64),
+                                           n_segments)
+        out.append(Window(f"stream{k}", W, H, f, f, cx, cy, np.asarray(refs, dtype=np.float32),
+                          x, y, t, p, rho, th))
+    return out
+
+
 def knots_of(refs) -> np.ndarray:
     """Sorted knots {0, 1} U refs (refs sorted and in [0, 1])."""
     k = [float(r) for r in refs]

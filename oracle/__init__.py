@@ -204,6 +204,14 @@ def geo(win, rho=None, theta=None, grad=False, grad_loss: float = 1.0) -> dict:
     return res
 
 
+def rsat(win, rho=None, theta=None) -> float:
+    """RSAT (ratio of squared average timestamps, the paper's deblurring
+    metric after Hagenaars et al.): the loss of Eq. 1 at the window's motion
+    over the loss with zero motion (no warp).  Below 1: the warp sharpens."""
+    th = _f64(win.theta if theta is None else theta)
+    return loss(win, rho, th) / loss(win, rho, np.zeros_like(th))
+
+
 def full_loss(win, lam: float = LAMBDA_GEO, rho=None, theta=None) -> float:
     """Eq. 4: L = L_CM + lambda L_geo."""
     return loss(win, rho, theta) + lam * geo(win, rho, theta)["loss"]

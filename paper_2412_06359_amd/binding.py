@@ -313,6 +313,16 @@ def geo_backward(desc: WindowDesc, rho, ego, state, grad_loss, grad_rho, grad_eg
     return grad_rho, grad_ego
 
 
+def rsat(desc: WindowDesc, x, y, t, p, rho, ego):
+    """RSAT, the paper's deblurring metric (ratio of squared average
+    timestamps, after Hagenaars et al.): the CM loss at `ego` over the CM loss
+    at zero motion, two library forwards.  Returns (rsat, loss, loss_zero),
+    0-d device tensors."""
+    loss, _ = forward(desc, x, y, t, p, rho, ego)
+    loss0, _ = forward(desc, x, y, t, p, rho, torch.zeros_like(ego))
+    return (loss / loss0).reshape(()), loss.reshape(()), loss0.reshape(())
+
+
 def diagnostics(desc: WindowDesc, state: torch.Tensor) -> dict:
     """Per-window sums of the last forward (synchronises the stream)."""
     R = desc.R
@@ -442,6 +452,12 @@ class Batch:
                                             _ptr(grad_ego), _stream(dev))
         _check(st, "cm_geo_backward_batched")
         return grad_rho, grad_ego
+
+    def rsat(self, x, y, t, p, rho, ego):
+        """Per-window RSAT: (rsat [n], loss [n], loss at zero motion [n])."""
+        loss, _ = self.forward(x, y, t, p, rho, ego)
+        loss0, _ = self.forward(x, y, t, p, rho, torch.zeros_like(ego))
+        return loss / loss0, loss, loss0
 
     def occupied_image_bytes(self, state) -> list:
         """Per window, splat-image bytes of its occupied tiles after the last

@@ -257,3 +257,13 @@ def test_full_loss_is_cm_plus_weighted_geo():
     L = oracle.full_loss(win)
     assert oracle.LAMBDA_GEO == 0.05
     assert abs(L - (oracle.loss(win) + 0.05 * oracle.geo(win)["loss"])) < 1e-15
+
+
+def test_rsat_is_one_without_motion_and_a_loss_ratio():
+    """RSAT = L(motion) / L(no motion): exactly 1 at zero motion.  Catches an
+    RSAT computed against the wrong reference loss."""
+    import eventgen
+    win = eventgen.edge_window(4, "64x64", 3000, refs=[0.0, 0.5, 1.0], n_segments=10)
+    assert oracle.rsat(win, theta=np.zeros(6)) == 1.0
+    r = oracle.rsat(win)
+    assert r == oracle.loss(win) / oracle.loss(win, theta=np.zeros(6)) and r != 1.0
