@@ -50,7 +50,7 @@ def kernel_source_sha() -> str:
 
 
 def algorithmic_bytes(phase: str, n: int, HW: int, R: int, tiled: bool, F: int = 1,
-                      img_bytes=None) -> float:
+                      img_bytes=None, active_bytes=None) -> float:
     """Bytes a phase must move at minimum for one window.
 
     events: 13 B each (x, y, t FP32 + p int8); rho: 4 B per pixel and flow set;
@@ -58,34 +58,40 @@ def algorithmic_bytes(phase: str, n: int, HW: int, R: int, tiled: bool, F: int =
     polarity and reference (32 R B per pixel) on the direct path, which writes
     every pixel; on the tiled path only the tiles that some warped position
     falls in (img_bytes, from cm_batch_occupied_image_bytes): the others hold
-    zeros that are neither written nor read.  The tiled path's records and bin
-    tables are not counted: they are the implementation's traffic, not the
-    method's."""
+    zeros that are neither written nor read.  The backward gathers C and S only
+    at the pixels the splat touched, 32 B at each of the sum over references of
+    N_r (active_bytes, from cm_batch_active_pixels).  The tiled path's records
+    and bin tables are not counted: they are the implementation's traffic, not
+    the method's."""
     ev = 13.0 * n
     rho = 4.0 * HW * F
     img = 32.0 * R * HW
+    act = img if active_bytes is None else active_bytes
     if tiled:
         occ = img if img_bytes is None else img_bytes
         table = {"zero": 0.0, "count": ev + rho, "scan": 0.0, "scatter": ev + rho,
                  "splat": occ, "reduce": 0.0, "finalize": 0.0,
-                 "grad_count": ev + rho, "grad_scan": 0.0, "adjoint": ev + rho + occ,
+                 "grad_count": ev + rho, "grad_scan": 0.0, "adjoint": ev + rho + act,
                  "grad_tile": 8.0 * HW * F, "grad_finalize": 0.0}
     else:
         table = {"zero": img, "splat": ev + rho + img, "reduce": img, "finalize": 0.0,
-                 "grad_zero": 4.0 * HW * F, "adjoint": ev + rho + img + 4.0 * HW * F,
+                 "grad_zero": 4.0 * HW * F, "adjoint": ev + rho + act + 4.0 * HW * F,
                  "grad_finalize": 0.0}
     return table.get(phase, 0.0)
 
 
-def occupied_image_bytes(cm, wins, dev):
-    """Per window, the splat-image bytes of its occupied tiles (one batched
-    forward of the windows, read back before any backward)."""
+def image_bytes(cm, wins, dev):
+    """Per window, the splat-image bytes of its occupied tiles and of its
+    active pixels (32 B times the sum over references of N_r), from one
+    batched forward of the windows, read back before any backward."""
     import torch
     d = to_device(wins, dev)
     b = cm.Batch([cm.WindowDesc.from_window(w) for w in wins], [w.n for w in wins])
     try:
         _, st = b.forward(d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"])
-        return b.occupied_image_bytes(st)
+        occ = b.occupied_image_bytes(st)
+        act = [32.0 * sum(nr) for nr in b.active_pixels(st)]
+        return occ, act
     finally:
         b.close()
         torch.cuda.synchronize()
@@ -313,10 +319,12 @@ def main():
     dom = max(per_launch, key=lambda k: per_launch[k][0] * per_launch[k][1])
     dom_ms = per_launch[dom][0]
     launches_per_step = per_launch[dom][1] / args.steps
-    occ = occupied_image_bytes(cm, wins, dev) if path_used == "tiled" else [None] * len(wins)
+    occ, act = image_bytes(cm, wins, dev)
+    if path_used != "tiled":
+        occ = [None] * len(wins)
     alg = sum(algorithmic_bytes(dom, w.n, w.width * w.height, len(w.refs), path_used == "tiled",
-                                w.rho.shape[0] if w.rho.ndim == 3 else 1, o)
-              for w, o in zip(wins, occ)) / launches_per_step
+                                w.rho.shape[0] if w.rho.ndim == 3 else 1, o, a)
+              for w, o, a in zip(wins, occ, act)) / launches_per_step
     achieved = alg / (dom_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, dom)
 
@@ -405,7 +413,9 @@ def main():
                      "algorithmic_bytes_per_launch": alg, "avg_launch_ms": dom_ms,
                      "image_occupancy": (sum(occ) / sum(32.0 * len(w.refs) * w.width * w.height
                                                         for w in wins)
-                                         if occ and occ[0] is not None else None)},
+                                         if occ and occ[0] is not None else None),
+                     "active_pixel_fraction": (sum(act) / sum(32.0 * len(w.refs) * w.width *
+                                                              w.height for w in wins))},
         "phases_ms_per_launch": {k: v[0] for k, v in per_launch.items()},
     }
     out.update(out_extra)

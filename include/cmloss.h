@@ -220,6 +220,12 @@ cm_status cm_batch_diagnostics(cm_batch b, const void* state, double* out, void*
  * call between the forward and the backward; synchronises `stream`.  A
  * measurement aid for the splat's minimal image traffic. */
 cm_status cm_batch_occupied_image_bytes(cm_batch b, const void* state, double* out, void* stream);
+/* Per window and reference, N_r (pixels with C_+ + C_- > 0) of the last
+ * batched forward on `state`: host array of n_windows * CM_MAX_REFS doubles,
+ * window w's at [w * CM_MAX_REFS, w * CM_MAX_REFS + R), zeros after;
+ * synchronises `stream`.  The splat images hold their non-zero values at
+ * these pixels only: the backward's gathers read 32 bytes at each. */
+cm_status cm_batch_active_pixels(cm_batch b, const void* state, double* out, void* stream);
 
 /* Geometry consistency and the full loss (paper Sec. 3.2 Eq. 3, Eq. 4).
  *
@@ -238,7 +244,9 @@ cm_status cm_batch_occupied_image_bytes(cm_batch b, const void* state, double* o
  * inv_depth and ego are laid out as for the CM loss.  `state` is a caller
  * buffer of cm_geo_state_bytes (cm_batch_geo_state_bytes) bytes, separate from
  * the CM state; the backward reads what the forward on the same state and
- * inputs wrote.  Results are deterministic in both modes (fixed-order
+ * inputs wrote.  The first batched call on a plan allocates a device copy of
+ * the plan's metadata (as cm_batch_set_graph does), freed with the plan.
+ * Results are deterministic in both modes (fixed-order
  * reductions; in the deterministic mode the scatter of d rho_{f+1} is summed
  * in 64-bit fixed point, so d inv_depth is bit-identical from run to run).
  *

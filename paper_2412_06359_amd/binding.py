@@ -138,6 +138,8 @@ def load() -> ctypes.CDLL:
         lib.cm_batch_diagnostics.restype = ctypes.c_int
         lib.cm_batch_occupied_image_bytes.argtypes = [P, P, P, P]
         lib.cm_batch_occupied_image_bytes.restype = ctypes.c_int
+        lib.cm_batch_active_pixels.argtypes = [P, P, P, P]
+        lib.cm_batch_active_pixels.restype = ctypes.c_int
         f32 = ctypes.c_float
         lib.cm_geo_state_bytes.argtypes = [D]
         lib.cm_geo_state_bytes.restype = ctypes.c_size_t
@@ -467,6 +469,14 @@ class Batch:
                                                   _stream(state.device))
         _check(st, "cm_batch_occupied_image_bytes")
         return list(out)
+
+    def active_pixels(self, state) -> list:
+        """Per window, [N_r for r < R] of the last forward (synchronises)."""
+        out = (ctypes.c_double * (CM_MAX_REFS * self.n))()
+        st = load().cm_batch_active_pixels(self._b, _ptr(state), out, _stream(state.device))
+        _check(st, "cm_batch_active_pixels")
+        return [[out[CM_MAX_REFS * w + r] for r in range(self.descs[w].R)]
+                for w in range(self.n)]
 
     def diagnostics(self, state) -> list:
         out = (ctypes.c_double * (2 * self.n))()

@@ -466,17 +466,36 @@ cm_status cm_batch_flow_offsets(cm_batch b, int64_t* set_offsets)
     return CM_OK;
 }
 
+// The plan's metadata in device memory (allocated and filled once per plan:
+// graphs and the geometry-consistency calls read it there).
+static cm_status ensure_device_meta(cm_batch_s* b)
+{
+    if (b->d_meta) return CM_OK;
+    DeviceGuard g(b->h->device);
+    if (!g.ok()) return CM_ERR_HIP;
+    const size_t bytes = sizeof(WinMeta) * b->B.nw;
+    WinMeta* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return CM_ERR_OOM;
+    if (hipMemcpy(p, b->B.meta.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(p);
+        return CM_ERR_HIP;
+    }
+    b->d_meta = p;
+    return CM_OK;
+}
+
 cm_status cm_batch_set_graph(cm_batch b, int enable)
 {
     if (!b) return CM_ERR_INVALID_ARG;
-    if (enable && !b->d_meta) {
-        DeviceGuard g(b->h->device);
-        if (!g.ok()) return CM_ERR_HIP;
-        const size_t bytes = sizeof(WinMeta) * b->B.nw;
-        if (hipMalloc(&b->d_meta, bytes) != hipSuccess) return CM_ERR_OOM;
-        if (hipMemcpy(b->d_meta, b->B.meta.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
-            hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess)
-            return CM_ERR_HIP;
+    if (enable) {
+        const cm_status st = ensure_device_meta(b);
+        if (st != CM_OK) return st;
+        if (!b->capture) {
+            DeviceGuard g(b->h->device);
+            if (!g.ok()) return CM_ERR_HIP;
+            if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess)
+                return CM_ERR_HIP;
+        }
     }
     b->use_graph = enable != 0;
     return CM_OK;
@@ -546,6 +565,24 @@ cm_status cm_batch_diagnostics(cm_batch b, const void* state, double* out, void*
         out[2 * w] = hdr[w].loss;
         out[2 * w + 1] = (double)hdr[w].n_valid;
     }
+    return CM_OK;
+}
+
+cm_status cm_batch_active_pixels(cm_batch b, const void* state, double* out, void* stream)
+{
+    if (!b || !state || !out) return CM_ERR_INVALID_ARG;
+    const int nw = b->B.nw;
+    std::vector<StateHeader> hdr(nw);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceGuard g(b->h->device);
+    if (!g.ok()) return CM_ERR_HIP;
+    if (hipMemcpyAsync(hdr.data(), static_cast<const char*>(state) + b->hdr_off,
+                       sizeof(StateHeader) * nw, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return CM_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return CM_ERR_HIP;
+    for (int w = 0; w < nw; ++w)
+        for (int r = 0; r < CM_MAX_REFS; ++r)
+            out[(size_t)w * CM_MAX_REFS + r] = r < b->B.meta[w].P.R ? hdr[w].nact[r] : 0.0;
     return CM_OK;
 }
 
@@ -628,7 +665,7 @@ cm_status cm_geo_forward(cm_handle h, const cm_window_desc* d, const float* inv_
     hipStream_t s = static_cast<hipStream_t>(stream);
     WinMeta* meta = reinterpret_cast<WinMeta*>(static_cast<char*>(state) + L.meta);
     if (cm::launch_store_meta(geo_meta_one(d), meta, s) != hipSuccess) return CM_ERR_HIP;
-    return status_of(cm::launch_geo_forward(L, 1, state, inv_depth, ego, lambda, loss_cm,
+    return status_of(cm::launch_geo_forward(L, meta, 1, state, inv_depth, ego, lambda, loss_cm,
                                             loss_geo, loss_total, s));
 }
 
@@ -645,7 +682,7 @@ cm_status cm_geo_backward(cm_handle h, const cm_window_desc* d, const float* inv
     hipStream_t s = static_cast<hipStream_t>(stream);
     WinMeta* meta = reinterpret_cast<WinMeta*>(static_cast<char*>(state) + L.meta);
     if (cm::launch_store_meta(geo_meta_one(d), meta, s) != hipSuccess) return CM_ERR_HIP;
-    return status_of(cm::launch_geo_backward(L, 1, state, inv_depth, ego, lambda, grad_loss,
+    return status_of(cm::launch_geo_backward(L, meta, 1, state, inv_depth, ego, lambda, grad_loss,
                                              grad_inv_depth, grad_ego, s));
 }
 
@@ -661,11 +698,10 @@ cm_status cm_geo_forward_batched(cm_batch b, const float* inv_depth, const float
     if (!g.ok()) return CM_ERR_HIP;
     const cm::GeoLayout L = geo_layout_batch(b);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (hipMemcpyAsync(static_cast<char*>(state) + L.meta, b->B.meta.data(),
-                       sizeof(WinMeta) * b->B.nw, hipMemcpyHostToDevice, s) != hipSuccess)
-        return CM_ERR_HIP;
-    return status_of(cm::launch_geo_forward(L, b->B.nw, state, inv_depth, ego, lambda, loss_cm,
-                                            loss_geo, loss_total, s));
+    const cm_status st = ensure_device_meta(b);
+    if (st != CM_OK) return st;
+    return status_of(cm::launch_geo_forward(L, b->d_meta, b->B.nw, state, inv_depth, ego, lambda,
+                                            loss_cm, loss_geo, loss_total, s));
 }
 
 cm_status cm_geo_backward_batched(cm_batch b, const float* inv_depth, const float* ego,
@@ -679,10 +715,9 @@ cm_status cm_geo_backward_batched(cm_batch b, const float* inv_depth, const floa
     if (!g.ok()) return CM_ERR_HIP;
     const cm::GeoLayout L = geo_layout_batch(b);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (hipMemcpyAsync(static_cast<char*>(state) + L.meta, b->B.meta.data(),
-                       sizeof(WinMeta) * b->B.nw, hipMemcpyHostToDevice, s) != hipSuccess)
-        return CM_ERR_HIP;
-    return status_of(cm::launch_geo_backward(L, b->B.nw, state, inv_depth, ego, lambda,
+    const cm_status st = ensure_device_meta(b);
+    if (st != CM_OK) return st;
+    return status_of(cm::launch_geo_backward(L, b->d_meta, b->B.nw, state, inv_depth, ego, lambda,
                                              grad_loss, grad_inv_depth, grad_ego, s));
 }
 

@@ -516,12 +516,12 @@ GeoLayout geo_layout(int nw, int max_F, int max_tiles, int max_HW, int64_t n_pix
     return L;
 }
 
-hipError_t launch_geo_forward(const GeoLayout& L, int nw, void* state, const float* rho,
-                              const float* ego, float lambda, const float* loss_cm,
-                              float* loss_geo, float* loss_total, hipStream_t s)
+hipError_t launch_geo_forward(const GeoLayout& L, const WinMeta* meta, int nw, void* state,
+                              const float* rho, const float* ego, float lambda,
+                              const float* loss_cm, float* loss_geo, float* loss_total,
+                              hipStream_t s)
 {
     char* st = static_cast<char*>(state);
-    const WinMeta* meta = reinterpret_cast<const WinMeta*>(st + L.meta);
     double* part = reinterpret_cast<double*>(st + L.part);
     GeoPairSum* pairs = reinterpret_cast<GeoPairSum*>(st + L.pairs);
     if (L.det)   // the backward's fixed-point accumulator starts at zero
@@ -536,12 +536,12 @@ hipError_t launch_geo_forward(const GeoLayout& L, int nw, void* state, const flo
     return hipGetLastError();
 }
 
-hipError_t launch_geo_backward(const GeoLayout& L, int nw, void* state, const float* rho,
-                               const float* ego, float lambda, const float* grad_loss,
-                               float* grad_rho, float* grad_ego, hipStream_t s)
+hipError_t launch_geo_backward(const GeoLayout& L, const WinMeta* meta, int nw, void* state,
+                               const float* rho, const float* ego, float lambda,
+                               const float* grad_loss, float* grad_rho, float* grad_ego,
+                               hipStream_t s)
 {
     char* st = static_cast<char*>(state);
-    const WinMeta* meta = reinterpret_cast<const WinMeta*>(st + L.meta);
     double* part = reinterpret_cast<double*>(st + L.part);
     const GeoPairSum* pairs = reinterpret_cast<const GeoPairSum*>(st + L.pairs);
     unsigned long long* acc = L.det ? reinterpret_cast<unsigned long long*>(st + L.acc) : nullptr;

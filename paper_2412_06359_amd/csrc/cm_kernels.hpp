@@ -207,11 +207,15 @@ struct GeoLayout {
 };
 GeoLayout geo_layout(int nw, int max_F, int max_tiles, int max_HW, int64_t n_pixels, bool det);
 inline int geo_tiles(int W, int H) { return ((W + 31) / 32) * ((H + 31) / 32); }
-hipError_t launch_geo_forward(const GeoLayout& L, int nw, void* state, const float* rho,
-                              const float* ego, float lambda, const float* loss_cm,
-                              float* loss_geo, float* loss_total, hipStream_t s);
-hipError_t launch_geo_backward(const GeoLayout& L, int nw, void* state, const float* rho,
-                               const float* ego, float lambda, const float* grad_loss,
-                               float* grad_rho, float* grad_ego, hipStream_t s);
+// `meta`: the windows' metadata in device memory (the state's copy, or a
+// batch plan's device array).
+hipError_t launch_geo_forward(const GeoLayout& L, const WinMeta* meta, int nw, void* state,
+                              const float* rho, const float* ego, float lambda,
+                              const float* loss_cm, float* loss_geo, float* loss_total,
+                              hipStream_t s);
+hipError_t launch_geo_backward(const GeoLayout& L, const WinMeta* meta, int nw, void* state,
+                               const float* rho, const float* ego, float lambda,
+                               const float* grad_loss, float* grad_rho, float* grad_ego,
+                               hipStream_t s);
 
 }  // namespace cm
