@@ -176,8 +176,8 @@ template <int RM, int NT, int FM>
 __global__ __launch_bounds__(NT) void fwd_count_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const float* __restrict__ ex,
     const float* __restrict__ ey, const float* __restrict__ et, const float* __restrict__ rho,
-    const float* __restrict__ ego, uint32_t* __restrict__ hist, uint32_t* __restrict__ csum,
-    StateHeader* __restrict__ hdrs)
+    const float* __restrict__ ego, const Motion* __restrict__ mtab, uint32_t* __restrict__ hist,
+    uint32_t* __restrict__ csum, StateHeader* __restrict__ hdrs)
 {
     extern __shared__ uint32_t lh[];
     __shared__ uint32_t cnt_lds;
@@ -192,7 +192,8 @@ __global__ __launch_bounds__(NT) void fwd_count_kernel(
     if (threadIdx.x == 0) cnt_lds = 0;
     load_ref_table(P, nullptr, rt);
     __shared__ MotionTable mt;
-    const Flows<FM> u = make_flows<FM>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off, &mt);
+    const Flows<FM> u = make_flows_tab<FM>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off,
+                                           mtab + meta[w].ego_off, &mt);
     __syncthreads();
     const int64_t base = lb * NT * G.ept;
     uint32_t cnt = 0;
@@ -331,7 +332,7 @@ template <int RM, int NT, bool DET, int FM>
 __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const float* __restrict__ ex,
     const float* __restrict__ ey, const float* __restrict__ et, const int8_t* __restrict__ ep,
-    const float* __restrict__ rho, const float* __restrict__ ego,
+    const float* __restrict__ rho, const float* __restrict__ ego, const Motion* __restrict__ mtab,
     const uint32_t* __restrict__ offs, const uint32_t* __restrict__ start,
     SplatRec* __restrict__ rec, SrcRec* __restrict__ src)
 {
@@ -347,7 +348,8 @@ __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
     for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) lh[i] = row[i];
     load_ref_table(P, nullptr, rt);
     __shared__ MotionTable mt;
-    const Flows<FM> u = make_flows<FM>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off, &mt);
+    const Flows<FM> u = make_flows_tab<FM>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off,
+                                           mtab + meta[w].ego_off, &mt);
     __syncthreads();
     // the window's reference-0 records come first among its records: their
     // slots minus this offset number its valid events
@@ -429,9 +431,13 @@ __device__ __forceinline__ int window_of_bbin(const WinMeta* meta, int nw, int64
 // batch, one binary search per entry per call instead of one chain of
 // dependent loads at the start of every workgroup.
 // tab = [blocks | forward bins | backward bins].
+// The window of every event block, bin and backward bin, and (one thread per
+// window) the first-order motion coefficients of every flow set.
 __global__ __launch_bounds__(256) void window_table_kernel(const WinMeta* __restrict__ meta,
                                                            int nw, int64_t nblk, int64_t nbin,
-                                                           int64_t nbb, int* __restrict__ tab)
+                                                           int64_t nbb, int* __restrict__ tab,
+                                                           const float* __restrict__ ego,
+                                                           Motion* __restrict__ mtab)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nblk)
@@ -440,6 +446,12 @@ __global__ __launch_bounds__(256) void window_table_kernel(const WinMeta* __rest
         tab[i] = window_of_bin(meta, nw, i - nblk);
     else if (i < nblk + nbin + nbb)
         tab[i] = window_of_bbin(meta, nw, i - nblk - nbin);
+    else if (i < nblk + nbin + nbb + nw) {
+        const int w = (int)(i - nblk - nbin - nbb);
+        const WinParams& P = meta[w].P;
+        for (int f = 0; f < P.F; ++f)
+            mtab[meta[w].ego_off + f] = load_motion(P, ego + 6 * (meta[w].ego_off + f));
+    }
 }
 
 // Threads of the forward tile kernel: the deterministic mode keeps 256 (its
@@ -706,7 +718,7 @@ __device__ __forceinline__ void for_each_sample(const WinParams& P, const RefTab
 template <int RM, int NT, int FM>
 __global__ __launch_bounds__(NT) void bwd_count_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const SrcRec* __restrict__ src,
-    const float* __restrict__ rho, const float* __restrict__ ego,
+    const float* __restrict__ rho, const float* __restrict__ ego, const Motion* __restrict__ mtab,
     const StateHeader* __restrict__ hdrs, uint32_t* __restrict__ hist, uint32_t* __restrict__ csum)
 {
     extern __shared__ uint32_t lh[];
@@ -722,7 +734,8 @@ __global__ __launch_bounds__(NT) void bwd_count_kernel(
     for (int i = threadIdx.x; i < G.nbins_b; i += blockDim.x) lh[i] = 0;
     load_ref_table(P, nullptr, rt);
     __shared__ MotionTable mt;
-    const Flows<FM> u = make_flows<FM>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off, &mt);
+    const Flows<FM> u = make_flows_tab<FM>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off,
+                                           mtab + meta[w].ego_off, &mt);
     __syncthreads();
     const int64_t stride = (int64_t)G.nblocks * NT;
     SrcRec qn;
@@ -754,7 +767,7 @@ __global__ __launch_bounds__(NT) void bwd_count_kernel(
 template <int RM, int NT, bool DET, int FM>
 __global__ __launch_bounds__(NT) void bwd_sweep_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const SrcRec* __restrict__ src,
-    const float* __restrict__ rho, const float* __restrict__ ego,
+    const float* __restrict__ rho, const float* __restrict__ ego, const Motion* __restrict__ mtab,
     const double2* __restrict__ img_base, const StateHeader* __restrict__ hdrs,
     const uint32_t* __restrict__ offs, GradRec* __restrict__ rec)
 {
@@ -773,7 +786,8 @@ __global__ __launch_bounds__(NT) void bwd_sweep_kernel(
     __shared__ RefTable rt;
     load_ref_table(P, hdrs + w, rt);
     __shared__ MotionTable mt;
-    const Flows<FM> u = make_flows<FM>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off, &mt);
+    const Flows<FM> u = make_flows_tab<FM>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off,
+                                           mtab + meta[w].ego_off, &mt);
     __syncthreads();
     const double2* img = img_base + meta[w].img_off;
     const bool split = FM != 0 && P.F > 1;    // one record per first step (see for_each_sample)
@@ -1196,16 +1210,17 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     B.ws.records = take((size_t)recs * std::max(sizeof(SplatRec), sizeof(GradRec)));
     B.ws.src = take((size_t)ev * sizeof(SrcRec));
     B.ws.win = take((size_t)(blk + bin + bbin) * sizeof(int));
+    B.ws.motion = take((size_t)B.n_sets * sizeof(Motion));
     B.ws.total = off;
     return B;
 }
 
 static void launch_window_table(const BatchPlanHost& B, const WinMeta* meta, int* tab,
-                                hipStream_t s)
+                                const float* ego, Motion* mtab, hipStream_t s)
 {
-    const int64_t n = B.nblocks + B.nbins + B.nbins_b;
+    const int64_t n = B.nblocks + B.nbins + B.nbins_b + B.nw;
     window_table_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(meta, B.nw, B.nblocks, B.nbins,
-                                                                B.nbins_b, tab);
+                                                                B.nbins_b, tab, ego, mtab);
 }
 
 template <int RM, bool DET, int FM>
@@ -1225,13 +1240,14 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     SplatRec* rec = reinterpret_cast<SplatRec*>(ws + B.ws.records);
     SrcRec* src = reinterpret_cast<SrcRec*>(ws + B.ws.src);
     int* wtab = reinterpret_cast<int*>(ws + B.ws.win);
+    Motion* mtab = reinterpret_cast<Motion*>(ws + B.ws.motion);
     const int* win_blk = wtab;
     const int* win_bin = wtab + B.nblocks;
     const size_t lds = (size_t)B.max_lds_bins * sizeof(uint32_t);
     {
         PhaseScope ph(prof, kPhZero, s);
         clear_headers_kernel<<<(nw + 255) / 256, 256, 0, s>>>(hdrs, nw);
-        launch_window_table(B, meta, wtab, s);
+        launch_window_table(B, meta, wtab, ego, mtab, s);
         fill_u32_kernel<<<(int)std::min<int64_t>((B.csum_cells + 255) / 256, 4096), 256, 0, s>>>(
             csum, B.csum_cells);
     }
@@ -1239,7 +1255,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
         PhaseScope ph(prof, kPhCount, s);
         constexpr int NT = DET ? 64 : kBinThreads;
         fwd_count_kernel<RM, NT, FM><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, ev.x, ev.y, ev.t, rho, ego,
-                                                            hist, csum, hdrs);
+                                                            mtab, hist, csum, hdrs);
     }
     {
         PhaseScope ph(prof, kPhScan, s);
@@ -1253,7 +1269,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
         PhaseScope ph(prof, kPhScatter, s);
         constexpr int NT = DET ? 64 : kBinThreads;
         fwd_scatter_kernel<RM, NT, DET, FM><<<B.nblocks, NT, lds, s>>>(
-            meta, nw, win_blk, ev.x, ev.y, ev.t, ev.p, rho, ego, hist, start, rec, src);
+            meta, nw, win_blk, ev.x, ev.y, ev.t, ev.p, rho, ego, mtab, hist, start, rec, src);
     }
     {
         PhaseScope ph(prof, kPhSplat, s);
@@ -1305,17 +1321,18 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
     GradRec* rec = reinterpret_cast<GradRec*>(ws + B.ws.records);
     const SrcRec* src = reinterpret_cast<const SrcRec*>(ws + B.ws.src);
     int* wtab = reinterpret_cast<int*>(ws + B.ws.win);
+    Motion* mtab = reinterpret_cast<Motion*>(ws + B.ws.motion);
     const int* win_blk = wtab;
     const int* win_tile = wtab + B.nblocks + B.nbins;
     const size_t lds = (size_t)B.max_lds_bins * sizeof(uint32_t);
     {
         PhaseScope ph(prof, kPhGradCount, s);
-        launch_window_table(B, meta, wtab, s);
+        launch_window_table(B, meta, wtab, ego, mtab, s);
         fill_u32_kernel<<<(int)std::min<int64_t>((B.csum_cells + 255) / 256, 4096), 256, 0, s>>>(
             csum, B.csum_cells);
         constexpr int NT = DET ? 64 : kBinThreads;
         bwd_count_kernel<RM, NT, FM><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, src, rho, ego,
-                                                                hdrs, hist, csum);
+                                                                mtab, hdrs, hist, csum);
     }
     {
         PhaseScope ph(prof, kPhGradScan, s);
@@ -1328,7 +1345,7 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
     {
         PhaseScope ph(prof, kPhAdjoint, s);
         constexpr int NT = DET ? 64 : kBinThreads;
-        bwd_sweep_kernel<RM, NT, DET, FM><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, src, rho, ego, img,
+        bwd_sweep_kernel<RM, NT, DET, FM><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, src, rho, ego, mtab, img,
                                                                  hdrs, hist, rec);
     }
     {

@@ -340,6 +340,27 @@ __device__ __forceinline__ Flows<2> make_flows<2>(const WinParams& P,
     return fl;
 }
 
+// As make_flows, with one flow's motion coefficients read from a per-set
+// table in device memory: the address is uniform over the block, so the
+// coefficients stay in scalar registers instead of occupying vector registers
+// for the whole kernel.
+template <int FM>
+__device__ __forceinline__ Flows<FM> make_flows_tab(const WinParams& P,
+                                                    const float* __restrict__ rho,
+                                                    const float* __restrict__ ego,
+                                                    const Motion* __restrict__ mtab,
+                                                    MotionTable* mt)
+{
+    if constexpr (FM == 0) {
+        Flows<0> fl;
+        fl.f.rho = rho;
+        fl.f.m = mtab[0];
+        return fl;
+    } else {
+        return make_flows<FM>(P, rho, ego, mt);
+    }
+}
+
 __device__ __forceinline__ double2 flow_at(const WinParams& P, const Motion& m, int i, int j,
                                            double r)
 {
