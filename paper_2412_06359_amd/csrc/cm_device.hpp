@@ -441,12 +441,20 @@ __device__ __forceinline__ void tap_flows(const WinParams& P, const FlowSrcX& f,
     }
 }
 
-// BS(u)(X, Y): the flow sampled bilinearly at a position on the image.
+// BS(u)(X, Y): the flow sampled bilinearly at a position on the image.  At a
+// pixel centre (both fractional parts zero) taps 1-3 carry zero weight and
+// only add signed zeros to the sum, so they are treated as off the sensor and
+// their inverse depth is not loaded: events lie on pixel centres, and the
+// warp's first sample of every event is taken there.
 template <typename Src>
 __device__ __forceinline__ void sample_flow(const WinParams& P, const Src& f, double X,
                                             double Y, double& ux, double& uy)
 {
-    const Taps t = make_taps(P, X, Y);
+    Taps t = make_taps(P, X, Y);
+    if (t.a == 0.0 && t.b == 0.0) {
+        t.inx = false;
+        t.iny = false;
+    }
     double2 uq[4];
     tap_flows(P, f, t, uq);
     ux = 0.0;
