@@ -738,6 +738,13 @@ __global__ __launch_bounds__(NT) void bwd_count_kernel(
                                            mtab + meta[w].ego_off, &mt);
     __syncthreads();
     const int64_t stride = (int64_t)G.nblocks * NT;
+    // One flow and references {0, 1} (or a single reference): every warp step
+    // starts at the event, so the sweep's records all sit at the events' own
+    // positions (one per valid event, none for an event on the single
+    // reference) and the bins need no warp.  Source records exist for valid
+    // events only.
+    const bool at_events = !(FM != 0 && P.F > 1) &&
+                           (P.R == 1 || (P.R == 2 && rt.t[0] == 0.0 && rt.t[1] == 1.0));
     SrcRec qn;
     int64_t i = (int64_t)lb * NT + threadIdx.x;
     if (i < nv) qn = load_nt(wsrc + i);
@@ -745,10 +752,15 @@ __global__ __launch_bounds__(NT) void bwd_count_kernel(
         if (i >= nv) break;
         const SrcRec q = qn;
         if (e + 1 < G.ept && i + stride < nv) qn = load_nt(wsrc + i + stride);
+        const double x0 = q.x0, y0 = q.y0, tk = fabsf(q.ts);
+        if (at_events) {
+            if (!(P.R == 1 && rt.t[0] == tk))
+                atomicAdd(&lh[tile_index(G, make_taps(P, x0, y0))], 1u);
+            continue;
+        }
         double vx[RM], vy[RM];
         int vr[RM];
         Visits v;
-        const double x0 = q.x0, y0 = q.y0, tk = fabsf(q.ts);
         if (!warp_visits<RM, FM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
         for_each_sample<RM, FM>(P, rt, v, vx, vy, vr, x0, y0, [&](double X, double Y, int set) {
             atomicAdd(&lh[set * G.ntiles + tile_index(G, make_taps(P, X, Y))], 1u);
