@@ -276,9 +276,15 @@ def main():
     plain = plain_step_fn(cm, wins, dev)
     ms_plain = timed(plain, args.steps, args.warmup, stream)
     if batched:
+        from paper_2412_06359_amd import autotune
         d = to_device(wins, dev)
-        batch = cm.Batch([cm.WindowDesc.from_window(w) for w in wins], [w.n for w in wins],
-                         graph=True)
+        descs = [cm.WindowDesc.from_window(w) for w in wins]
+        tune_log = []
+        tuning = autotune.tune(descs, [w.n for w in wins], d, steps=3, warmup=1,
+                               log=tune_log)
+        out_extra["tuning"] = {"chosen": tuning, "candidates": [dict(c, ms=ms)
+                                                                for c, ms in tune_log]}
+        batch = cm.Batch(descs, [w.n for w in wins], graph=True, tuning=tuning)
         state = batch.new_state()
         loss = torch.empty(batch.n, device=dev)
         g_rho = torch.empty_like(d["rho"])

@@ -134,6 +134,30 @@ size_t cm_state_bytes(const cm_window_desc* d, int64_t n_events);
 enum { CM_PATH_AUTO = 0, CM_PATH_DIRECT = 1, CM_PATH_TILED = 2 };
 cm_status cm_set_path(cm_handle h, int path);
 
+/* Launch tuning of a handle (the project's autotuner searches it; see
+ * paper_2412_06359_amd/autotune.py).  Zero fields keep the defaults.
+ *   event_blocks      : event blocks a batch's count / scatter / sweep
+ *                       kernels aim for (sets events per lane), 256..65536,
+ *                       default 4096
+ *   tile_threads      : threads of the forward tile kernel, 256 or 512,
+ *                       default 512
+ *   tiled_min_records : CM_PATH_AUTO takes the tiled path for single windows
+ *                       with at least this many event-reference records,
+ *                       >= 1, default 131072
+ * event_blocks and tile_threads apply to batch plans created after the call,
+ * in the atomic mode only (the deterministic mode's launch geometry defines
+ * its operation order and is fixed); single-window calls keep the default
+ * geometry, which cm_state_bytes sizes.  Results in the atomic mode agree
+ * across tunings within rounding.  CM_ERR_INVALID_ARG for values out of
+ * range, with the handle unchanged. */
+typedef struct {
+    int32_t event_blocks;
+    int32_t tile_threads;
+    int64_t tiled_min_records;
+} cm_tuning;
+cm_status cm_set_tuning(cm_handle h, const cm_tuning* t);
+cm_status cm_get_tuning(cm_handle h, cm_tuning* out);
+
 /* Forward (paper Sec. 3.1 Eq. 1 with Sec. 3.2 Eq. 2; Sec. 3.3 per-event
  * forward).
  *   ev_x, ev_y, ev_t, ev_p : n_events events (device; may be NULL if n_events == 0)

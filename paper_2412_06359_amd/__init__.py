@@ -6,7 +6,8 @@ include/cmloss.h (libcmloss.so); this package is the thin Python binding.
 
 from .binding import (CM_FLOW_EXACT, CM_FLOW_FIRST_ORDER, CM_MODE_ATOMIC, CM_MODE_DETERMINISTIC,
                       CM_PATH_AUTO, CM_PATH_DIRECT, LAMBDA_GEO, BatchFullLoss, FullLoss,
-                      full_loss, geo_backward, geo_forward, geo_state_bytes, rsat,
+                      full_loss, geo_backward, geo_forward, geo_state_bytes, rsat, Tuning,
+                      get_tuning, set_tuning,
                       CM_PATH_TILED, PHASES, Batch, BatchCMLoss, CMError, CMLoss, WindowDesc,
                       backward, cm_loss,
                       diagnostics, forward, handle, load, profile_enable, profile_read, set_path,
@@ -17,4 +18,4 @@ __all__ = ["CM_MODE_ATOMIC", "CM_MODE_DETERMINISTIC", "CMError", "CMLoss", "Wind
            "profile_read", "state_bytes", "PHASES", "CM_PATH_AUTO", "CM_PATH_DIRECT",
            "CM_PATH_TILED", "set_path", "Batch", "BatchCMLoss", "CM_FLOW_FIRST_ORDER",
            "CM_FLOW_EXACT", "LAMBDA_GEO", "BatchFullLoss", "FullLoss", "full_loss", "geo_backward",
-           "geo_forward", "geo_state_bytes", "rsat"]
+           "geo_forward", "geo_state_bytes", "rsat", "Tuning", "get_tuning", "set_tuning"]

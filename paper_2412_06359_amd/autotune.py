@@ -1,0 +1,127 @@
+"""Autotuner for batched launches.
+
+A batch's launch shape in the atomic mode has two tunables (cm_tuning): the
+number of event blocks the count / scatter / sweep kernels aim for (which sets
+events per lane) and the forward tile kernel's thread count.  `tune` times
+each candidate on a real batch -- forward + backward, replayed from a
+hipGraph, between HIP events on the current stream -- and returns the
+fastest.  Results are cached per shape class (mode, flow model, references,
+flow sets, sensor size, total events and window count, the last three
+rounded to powers of two) in a JSON file, so that a serving loop or a
+training run tunes once per class:
+
+    from paper_2412_06359_amd import autotune
+    tuning = autotune.tune(descs, counts, inputs, cache_path="tune.json")
+    batch = Batch(descs, counts, tuning=tuning)
+
+The deterministic mode's launch shape defines its operation order, so it is
+not tuned (`tune` returns the defaults).  The cache path defaults to the
+environment variable CM_AUTOTUNE_CACHE (no file when unset).
+"""
+
+import json
+import math
+import os
+from typing import Optional, Sequence
+
+import torch
+
+from . import binding as cm
+
+DEFAULT = dict(event_blocks=4096, tile_threads=512)
+CANDIDATES = [dict(event_blocks=e, tile_threads=t)
+              for e in (1024, 2048, 4096, 8192, 16384) for t in (256, 512)]
+
+
+def _pow2(v: float) -> int:
+    return 1 << max(0, int(math.ceil(math.log2(max(1.0, float(v))))))
+
+
+def shape_class(descs: Sequence[cm.WindowDesc], n_events: Sequence[int]) -> str:
+    """Cache key of a batch."""
+    d0 = descs[0]
+    R = max(d.R for d in descs)
+    F = max(d.F for d in descs)
+    px = max(int(d.width) * int(d.height) for d in descs)
+    return (f"mode{int(d0.mode)}-flow{int(d0.flow_model)}-R{R}-F{F}-px{_pow2(px)}"
+            f"-ev{_pow2(sum(int(n) for n in n_events))}-nw{_pow2(len(descs))}")
+
+
+def load_cache(path: Optional[str]) -> dict:
+    if not path or not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        data = json.load(fh)
+    return data if isinstance(data, dict) else {}
+
+
+def save_cache(path: str, data: dict):
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+    os.replace(tmp, path)
+
+
+def time_step(batch: "cm.Batch", inputs: dict, steps: int = 5, warmup: int = 2) -> float:
+    """ms per forward + backward of `batch` on `inputs` (dict x, y, t, p, rho,
+    ego device tensors), HIP events on the current stream."""
+    dev = inputs["rho"].device
+    state = batch.new_state()
+    loss = torch.empty(batch.n, device=dev)
+    g_rho = torch.empty_like(inputs["rho"])
+    g_ego = torch.empty_like(inputs["ego"])
+    gl = torch.ones(batch.n, device=dev)
+    a = (inputs["x"], inputs["y"], inputs["t"], inputs["p"], inputs["rho"], inputs["ego"])
+
+    def step():
+        batch.forward(*a, state=state, loss=loss)
+        batch.backward(*a, state, gl, grad_rho=g_rho, grad_ego=g_ego)
+
+    for _ in range(warmup):
+        step()
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def tune(descs: Sequence[cm.WindowDesc], n_events: Sequence[int], inputs: Optional[dict] = None,
+         candidates=None, steps: int = 5, warmup: int = 2, cache_path: Optional[str] = None,
+         device: int = 0, log: Optional[list] = None) -> dict:
+    """The fastest candidate tuning for this batch's shape class (cached).
+
+    inputs: the batch's packed device tensors (x, y, t, p, rho, ego); without
+    them only the cache is consulted (defaults on a miss).  log, if given,
+    receives (tuning, ms) for every candidate timed."""
+    if int(descs[0].mode) == cm.CM_MODE_DETERMINISTIC:
+        return dict(DEFAULT)
+    path = cache_path if cache_path is not None else os.environ.get("CM_AUTOTUNE_CACHE")
+    key = shape_class(descs, n_events)
+    cache = load_cache(path)
+    if key in cache:
+        hit = cache[key]
+        return dict(event_blocks=int(hit["event_blocks"]), tile_threads=int(hit["tile_threads"]))
+    if inputs is None:
+        return dict(DEFAULT)
+    best, best_ms = None, float("inf")
+    for cand in candidates or CANDIDATES:
+        b = cm.Batch(descs, n_events, device=device, graph=True, tuning=cand)
+        try:
+            ms = time_step(b, inputs, steps, warmup)
+        finally:
+            b.close()
+        if log is not None:
+            log.append((dict(cand), ms))
+        if ms < best_ms:
+            best, best_ms = dict(cand), ms
+    if path:
+        cache = load_cache(path)
+        cache[key] = dict(best, ms=best_ms)
+        save_cache(path, cache)
+    return best

@@ -83,8 +83,21 @@ class WindowDesc(ctypes.Structure):
         return max(1, int(self.n_flows))
 
 
+class Tuning(ctypes.Structure):
+    """cm_tuning: launch shape of batch plans (atomic mode) and the direct /
+    tiled crossover of single windows; zero fields keep the defaults."""
+
+    _fields_ = [("event_blocks", ctypes.c_int32), ("tile_threads", ctypes.c_int32),
+                ("tiled_min_records", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return dict(event_blocks=int(self.event_blocks), tile_threads=int(self.tile_threads),
+                    tiled_min_records=int(self.tiled_min_records))
+
+
 _lib = None
 _lib_lock = threading.Lock()
+_tuning_lock = threading.Lock()
 
 
 def load() -> ctypes.CDLL:
@@ -112,6 +125,10 @@ def load() -> ctypes.CDLL:
         lib.cm_state_bytes.restype = ctypes.c_size_t
         lib.cm_set_path.argtypes = [P, ctypes.c_int]
         lib.cm_set_path.restype = ctypes.c_int
+        lib.cm_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+        lib.cm_set_tuning.restype = ctypes.c_int
+        lib.cm_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+        lib.cm_get_tuning.restype = ctypes.c_int
         lib.cm_loss_forward.argtypes = [P, D, P, P, P, P, i64, P, P, P, P, P]
         lib.cm_loss_forward.restype = ctypes.c_int
         lib.cm_loss_backward.argtypes = [P, D, P, P, P, P, i64, P, P, P, P, P, P, P]
@@ -193,6 +210,21 @@ def state_bytes(desc: WindowDesc, n_events: int) -> int:
 def set_path(device: int, path: int):
     """Kernel path of this device's handle: CM_PATH_AUTO, _DIRECT or _TILED."""
     _check(load().cm_set_path(handle(device), int(path)), "cm_set_path")
+
+
+def get_tuning(device: int = 0) -> dict:
+    t = Tuning()
+    _check(load().cm_get_tuning(handle(device), ctypes.byref(t)), "cm_get_tuning")
+    return t.as_dict()
+
+
+def set_tuning(device: int = 0, event_blocks: int = 0, tile_threads: int = 0,
+               tiled_min_records: int = 0) -> dict:
+    """cm_set_tuning on this device's handle (0 keeps a field's default);
+    returns the tuning now in effect."""
+    t = Tuning(int(event_blocks), int(tile_threads), int(tiled_min_records))
+    _check(load().cm_set_tuning(handle(device), ctypes.byref(t)), "cm_set_tuning")
+    return get_tuning(device)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -344,7 +376,9 @@ class Batch:
     set, window w's at 6 * set_offsets[w]; loss / grad_loss are [n]."""
 
     def __init__(self, descs: Sequence[WindowDesc], n_events: Sequence[int], device: int = 0,
-                 graph: bool = False):
+                 graph: bool = False, tuning: Optional[dict] = None):
+        """tuning: dict(event_blocks=, tile_threads=) for this plan (atomic
+        mode), e.g. from autotune.tune; None takes the handle's current one."""
         lib = load()
         n = len(descs)
         self.device = device
@@ -352,8 +386,21 @@ class Batch:
         arr = (WindowDesc * n)(*descs)
         cnt = (ctypes.c_int64 * n)(*[int(v) for v in n_events])
         self._b = ctypes.c_void_p()
-        _check(lib.cm_batch_create(handle(device), n, arr, cnt, ctypes.byref(self._b)),
-               "cm_batch_create")
+        h = handle(device)
+        with _tuning_lock:
+            prev = Tuning()
+            _check(lib.cm_get_tuning(h, ctypes.byref(prev)), "cm_get_tuning")
+            if tuning is not None:
+                t = Tuning(int(tuning.get("event_blocks", 0)), int(tuning.get("tile_threads", 0)),
+                           int(prev.tiled_min_records))
+                _check(lib.cm_set_tuning(h, ctypes.byref(t)), "cm_set_tuning")
+            try:
+                st = lib.cm_batch_create(h, n, arr, cnt, ctypes.byref(self._b))
+                self.tuning = get_tuning(device)
+            finally:
+                if tuning is not None:
+                    lib.cm_set_tuning(h, ctypes.byref(prev))
+        _check(st, "cm_batch_create")
         self.n = n
         self.state_bytes = int(lib.cm_batch_state_bytes(self._b))
         ev = (ctypes.c_int64 * (n + 1))()

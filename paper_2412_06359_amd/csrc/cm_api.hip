@@ -10,7 +10,9 @@
 
 struct cm_handle_s {
     int device;
-    int path;               // CM_PATH_*
+    int path;                               // CM_PATH_*
+    cm::PlanTuning tune;                    // batch plans' launch shape (atomic mode)
+    int64_t tiled_min_records = 1 << 17;    // CM_PATH_AUTO crossover for single windows
     cm::Profiler prof;
 };
 
@@ -26,7 +28,7 @@ constexpr size_t kAlign = 256;
 
 // Records a window needs at least before the tiled path pays for its extra
 // launches (below it the direct atomic path is faster).
-constexpr int64_t kTiledMinRecords = 1 << 17;
+constexpr int64_t kTiledMinRecords = 1 << 17;   // default tiled_min_records
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -127,7 +129,7 @@ bool choose_tiled(const cm_handle_s* h, const cm_window_desc* d, const Layout& L
     if (d->mode == CM_MODE_DETERMINISTIC) return true;
     if (h->path == CM_PATH_DIRECT) return false;
     if (h->path == CM_PATH_TILED) return true;
-    return n * (int64_t)P.R >= kTiledMinRecords;
+    return n * (int64_t)P.R >= h->tiled_min_records;
 }
 
 StatePtrs state_ptrs(const Layout& L, void* state)
@@ -292,6 +294,28 @@ cm_status cm_set_path(cm_handle h, int path)
     return CM_OK;
 }
 
+cm_status cm_set_tuning(cm_handle h, const cm_tuning* t)
+{
+    if (!h || !t) return CM_ERR_INVALID_ARG;
+    const int eb = t->event_blocks ? t->event_blocks : 4096;
+    const int tt = t->tile_threads ? t->tile_threads : 512;
+    const int64_t tm = t->tiled_min_records ? t->tiled_min_records : kTiledMinRecords;
+    if (eb < 256 || eb > 65536 || (tt != 256 && tt != 512) || tm < 1) return CM_ERR_INVALID_ARG;
+    h->tune.event_blocks = eb;
+    h->tune.tile_threads = tt;
+    h->tiled_min_records = tm;
+    return CM_OK;
+}
+
+cm_status cm_get_tuning(cm_handle h, cm_tuning* out)
+{
+    if (!h || !out) return CM_ERR_INVALID_ARG;
+    out->event_blocks = h->tune.event_blocks;
+    out->tile_threads = h->tune.tile_threads;
+    out->tiled_min_records = h->tiled_min_records;
+    return CM_OK;
+}
+
 cm_status cm_loss_forward(cm_handle h, const cm_window_desc* d, const float* ev_x,
                           const float* ev_y, const float* ev_t, const int8_t* ev_p,
                           int64_t n_events, const float* inv_depth, const float* ego, float* loss,
@@ -419,7 +443,7 @@ cm_status cm_batch_create(cm_handle h, int32_t n_windows, const cm_window_desc* 
     if (!b) return CM_ERR_OOM;
     b->h = h;
     b->B = cm::plan_batch(params.data(), n_events, n_windows,
-                          descs[0].mode == CM_MODE_DETERMINISTIC);
+                          descs[0].mode == CM_MODE_DETERMINISTIC, h->tune);
     b->ev_offsets.resize(n_windows + 1);
     b->pix_offsets.resize(n_windows + 1);
     b->set_offsets.resize(n_windows + 1);

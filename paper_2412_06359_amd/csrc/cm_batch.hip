@@ -1108,10 +1108,9 @@ __global__ void store_meta_kernel(WinMeta m, WinMeta* __restrict__ out)
 // deterministic mode (its record order is the lanes' order), else four.
 static int bin_threads(bool det) { return det ? 64 : kBinThreads; }
 
-// Blocks a batch's event kernels aim for: a few waves of the 256 CUs, so that
-// every block warps several events per lane and the next event's loads overlap
-// the current one's gathers.
-constexpr int64_t kTargetEventBlocks = 4096;
+// Blocks a batch's event kernels aim for (PlanTuning::event_blocks, default
+// 4096): a few waves of the 256 CUs, so that every block warps several events
+// per lane and the next event's loads overlap the current one's gathers.
 
 TileGeom tile_geom(const WinParams& P, int64_t n, bool det, int min_ept)
 {
@@ -1136,11 +1135,14 @@ bool tiled_supported(const WinParams& P, int64_t n)
     return G.nbins <= kMaxBins && G.nbins_b <= kMaxBins && n * (int64_t)P.R < ((int64_t)1 << 31);
 }
 
-BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int nw, bool det)
+BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int nw, bool det,
+                         const PlanTuning& tune)
 {
     BatchPlanHost B;
     B.nw = nw;
     B.det = det;
+    B.tile_threads = det ? kTileThreadsDet : tune.tile_threads;
+    const int64_t target_blocks = tune.event_blocks;
     B.meta.resize(nw);
     int64_t ev = 0, pix = 0, sets = 0, img = 0, hist = 0, csum = 0, bin = 0, bbin = 0, blk = 0;
     int64_t cf = 0, cb = 0, recs = 0;
@@ -1156,8 +1158,8 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     const int min_ept = det ? 1
                             : (int)std::min<int64_t>(
                                   kMaxEventsPerThread,
-                                  std::max<int64_t>(1, (total + nt * kTargetEventBlocks - 1) /
-                                                           (nt * kTargetEventBlocks)));
+                                  std::max<int64_t>(1, (total + nt * target_blocks - 1) /
+                                                           (nt * target_blocks)));
     for (int w = 0; w < nw; ++w) {
         WinMeta& M = B.meta[w];
         std::memset(&M, 0, sizeof M);
@@ -1285,7 +1287,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     }
     {
         PhaseScope ph(prof, kPhSplat, s);
-        fwd_tile_kernel<DET><<<(int)B.nbins, DET ? kTileThreadsDet : kTileThreads, 0, s>>>(
+        fwd_tile_kernel<DET><<<(int)B.nbins, B.tile_threads, 0, s>>>(
             meta, nw, win_bin, rec, start, img, halo, fborder, part);
     }
     {
@@ -1339,6 +1341,8 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
     const size_t lds = (size_t)B.max_lds_bins * sizeof(uint32_t);
     {
         PhaseScope ph(prof, kPhGradCount, s);
+        // rebuilt rather than taken from the forward: a state the direct
+        // forward filled has no tables, and the backward must stay in bounds
         launch_window_table(B, meta, wtab, ego, mtab, s);
         fill_u32_kernel<<<(int)std::min<int64_t>((B.csum_cells + 255) / 256, 4096), 256, 0, s>>>(
             csum, B.csum_cells);

@@ -145,6 +145,7 @@ struct BatchPlanHost {
     int64_t nbins = 0, nbins_b = 0, nblocks = 0, cells_f = 0, cells_b = 0, csum_cells = 0;
     int max_R = 1, max_F = 1, max_lds_bins = 1;
     int model = 0;          // flow model of the batch's windows
+    int tile_threads = 512; // forward tile kernel threads (atomic mode)
     TileWorkspace ws;
 };
 
@@ -174,7 +175,13 @@ hipError_t launch_backward(const WinParams& P, const EventPtrs& ev, const float*
 // window w start at img + meta[w].img_off; hdrs[w] its sums.
 bool tiled_supported(const WinParams& P, int64_t n);
 TileGeom tile_geom(const WinParams& P, int64_t n, bool det, int min_ept);
-BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int nw, bool det);
+// Launch shape of a plan (the atomic mode's tunables; see cm_tuning).
+struct PlanTuning {
+    int event_blocks = 4096;
+    int tile_threads = 512;
+};
+BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int nw, bool det,
+                         const PlanTuning& tune = PlanTuning());
 hipError_t launch_store_meta(const WinMeta& m, WinMeta* out, hipStream_t s);
 hipError_t launch_forward_batch(const BatchPlanHost& B, const WinMeta* meta, const EventPtrs& ev,
                                 const float* rho, const float* ego, float* loss, double2* img,

@@ -1,0 +1,79 @@
+"""GPU: launch tuning (cm_set_tuning) and the autotuner.  Every tuning gives
+the same per-window losses and gradients within the parity tolerances."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.helpers import assert_grads_close, assert_loss_close
+from tests.test_gpu_batch import mixed_windows, pack
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cm():
+    import paper_2412_06359_amd as cm
+    cm.load()
+    assert torch.cuda.is_available()
+    yield cm
+    cm.set_tuning(0)                      # back to the defaults
+
+
+def test_set_tuning_validates(cm):
+    t0 = cm.get_tuning(0)
+    assert t0 == dict(event_blocks=4096, tile_threads=512, tiled_min_records=1 << 17)
+    for bad in (dict(event_blocks=100), dict(event_blocks=1 << 20), dict(tile_threads=384),
+                dict(tiled_min_records=-5)):
+        with pytest.raises(cm.CMError):
+            cm.set_tuning(0, **bad)
+        assert cm.get_tuning(0) == t0      # unchanged on error
+    assert cm.set_tuning(0, event_blocks=1024, tile_threads=256)["tile_threads"] == 256
+    cm.set_tuning(0)
+    assert cm.get_tuning(0) == t0
+
+
+def run_batch(cm, wins, tuning):
+    descs = [cm.WindowDesc.from_window(w) for w in wins]
+    batch = cm.Batch(descs, [w.n for w in wins], tuning=tuning)
+    print(f"[gpu] tuned batch {batch.tuning}", flush=True)
+    d = pack(wins)
+    loss, state = batch.forward(d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"])
+    g_rho, g_ego = batch.backward(d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"], state,
+                                  torch.ones(batch.n, device="cuda:0"))
+    torch.cuda.synchronize()
+    return batch, loss.cpu().numpy(), g_rho.cpu().numpy(), g_ego.cpu().numpy()
+
+
+@pytest.mark.parametrize("tuning", [dict(event_blocks=256, tile_threads=256),
+                                    dict(event_blocks=16384, tile_threads=512),
+                                    dict(event_blocks=1024, tile_threads=512)])
+def test_tuned_batches_match_oracle(cm, tuning):
+    wins = mixed_windows()
+    batch, loss, g_rho, g_ego = run_batch(cm, wins, tuning)
+    assert batch.tuning["event_blocks"] == tuning["event_blocks"]
+    assert cm.get_tuning(0)["event_blocks"] == 4096        # the handle's own is restored
+    for w, win in enumerate(wins):
+        o = oracle.forward(win)
+        assert_loss_close(float(loss[w]), o["loss"], what=f"{tuning} {win.name}")
+        ob = oracle.backward(win)
+        pr = g_rho[batch.pixel_offsets[w]:batch.pixel_offsets[w + 1]]
+        pe = g_ego[6 * batch.set_offsets[w]:6 * batch.set_offsets[w + 1]]
+        assert_grads_close(pr, pe, ob["drho"].ravel(), ob["dtheta"], what=f"{tuning} {win.name}")
+
+
+def test_autotuner_times_candidates_and_caches(cm, tmp_path):
+    from paper_2412_06359_amd import autotune
+    wins = mixed_windows()[:6]
+    descs = [cm.WindowDesc.from_window(w) for w in wins]
+    counts = [w.n for w in wins]
+    cands = [dict(event_blocks=1024, tile_threads=256), dict(event_blocks=4096, tile_threads=512)]
+    log = []
+    path = str(tmp_path / "tune.json")
+    best = autotune.tune(descs, counts, pack(wins), candidates=cands, steps=2, warmup=1,
+                         cache_path=path, log=log)
+    print(f"[gpu] autotune {log} -> {best}", flush=True)
+    assert best in cands and len(log) == 2 and all(ms > 0 for _, ms in log)
+    assert best == min(log, key=lambda r: r[1])[0]
+    assert autotune.tune(descs, counts, cache_path=path) == best      # cached
