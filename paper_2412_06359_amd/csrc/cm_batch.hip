@@ -278,29 +278,65 @@ __global__ __launch_bounds__(256) void chunk_scan_kernel(const WinMeta* __restri
 
 // start[bin] = exclusive prefix sum of totals over all windows' bins;
 // start[nbins] = total.  One block.
+// Exclusive scan of the bins' totals into start (start[nbins] = the sum), one
+// block: chunks of 8192 totals are loaded coalesced into LDS, each thread sums
+// 8 consecutive ones, the 1024 sums are scanned with in-wave shuffles and the
+// 16 wave totals by one wave, and the results go out coalesced.
 __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__ totals,
                                                     int64_t nbins, uint32_t* __restrict__ start)
 {
-    __shared__ uint32_t sums[1024];
-    const int64_t per = (nbins + 1023) / 1024;
-    const int64_t lo = std::min<int64_t>((int64_t)threadIdx.x * per, nbins);
-    const int64_t hi = std::min<int64_t>(lo + per, nbins);
-    uint32_t s = 0;
-    for (int64_t i = lo; i < hi; ++i) s += totals[i];
-    sums[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = threadIdx.x >= (unsigned)off ? sums[threadIdx.x - off] : 0u;
+    constexpr int T = 1024, K = 8, CH = T * K, NWV = T / 64;
+    __shared__ uint32_t buf[CH];
+    __shared__ uint32_t wsum[NWV];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < nbins; base += CH) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int64_t i = base + k * T + tid;
+            buf[k * T + tid] = i < nbins ? totals[i] : 0u;
+        }
         __syncthreads();
-        sums[threadIdx.x] += v;
+        uint32_t v[K], sum = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            v[k] = buf[tid * K + k];
+            sum += v[k];
+        }
+        uint32_t x = sum;                                  // inclusive scan within the wave
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wid] = x;
+        __syncthreads();
+        if (wid == 0) {
+            uint32_t t = lane < NWV ? wsum[lane] : 0u;
+#pragma unroll
+            for (int o = 1; o < NWV; o <<= 1) {
+                const uint32_t y = __shfl_up(t, o, 64);
+                if (lane >= o) t += y;
+            }
+            if (lane < NWV) wsum[lane] = t;
+        }
+        __syncthreads();
+        uint32_t run = carry + (wid ? wsum[wid - 1] : 0u) + (x - sum);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            buf[tid * K + k] = run;
+            run += v[k];
+        }
+        carry += wsum[NWV - 1];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int64_t i = base + k * T + tid;
+            if (i < nbins) start[i] = buf[k * T + tid];
+        }
         __syncthreads();
     }
-    uint32_t run = threadIdx.x ? sums[threadIdx.x - 1] : 0u;
-    for (int64_t i = lo; i < hi; ++i) {
-        start[i] = run;
-        run += totals[i];
-    }
-    if (threadIdx.x == 1023) start[nbins] = sums[1023];
+    if (tid == 0) start[nbins] = carry;
 }
 
 // In place: hist[b][bin] <- start[global bin] + sum_{b' < b} hist[b'][bin].
@@ -484,10 +520,9 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
         // reads its pixels except column 0 and row 0, which the merge writes
         // from the neighbours' halos; a backward gather at a tap of this tile
         // comes from a position binned in a left or upper neighbour, whose
-        // taps reach only that column and row.  So only the zero halo and
-        // zero sums are written (56% of the c3 bins are empty).
-        double2* hb = halo + gbin * NHALO * 2;
-        for (int j = threadIdx.x; j < NHALO * 2; j += blockDim.x) hb[j] = make_double2(0.0, 0.0);
+        // taps reach only that column and row.  Its halo is not written
+        // either: the merge reads halos of occupied bins only.  So only zero
+        // sums are written (56% of the c3 bins are empty).
         if (threadIdx.x == 0) {
             part[(gbin * 2 + 0) * 2 + 0] = 0.0;
             part[(gbin * 2 + 0) * 2 + 1] = 0.0;
@@ -578,15 +613,30 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
 // Column 0 and row 0 of each tile: the tile's own values (border buffer) plus
 // the halos of the left, top and top-left tiles (in that order); store and
 // reduce those pixels.
-__global__ __launch_bounds__(64) void fwd_merge_kernel(const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of,
+// One wavefront's sum (lanes in the shuffle-down tree of block_sum; the
+// result, valid in lane 0, is 0.0 + the tree's value as block_sum gives it
+// for a one-wavefront block).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return 0.0 + v;
+}
+
+// One wavefront per bin, kMergeBins bins per block (the bins are
+// independent: no barrier).
+constexpr int kMergeBins = 4;
+
+__global__ __launch_bounds__(64 * kMergeBins) void fwd_merge_kernel(const WinMeta* __restrict__ meta, int nw, int64_t nbins, const int* __restrict__ win_of,
                                                        const uint32_t* __restrict__ start,
                                                        double2* __restrict__ img_base,
                                                        const double2* __restrict__ halo,
                                                        const double2* __restrict__ border,
                                                        double* __restrict__ part)
 {
-    __shared__ double red[16];
-    const int64_t gbin = blockIdx.x;
+    const int64_t gbin = (int64_t)blockIdx.x * kMergeBins + (threadIdx.x >> 6);
+    if (gbin >= nbins) return;
+    const int lane = threadIdx.x & 63;
     const int w = win_of[gbin];
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
@@ -594,9 +644,23 @@ __global__ __launch_bounds__(64) void fwd_merge_kernel(const WinMeta* __restrict
     split_bin(G, (int)(gbin - meta[w].bin_off), r, tx, ty);
     const int xo = tx * TW, yo = ty * TH;
     double2* img = img_base + meta[w].img_off;
-    const bool own = start[gbin] != start[gbin + 1];   // the tile kernel wrote this tile
+    // occupied bins (the tile kernel wrote their border and halo); an empty
+    // bin whose left, upper and upper-left neighbours are empty too has a
+    // zero border that no gather reads: nothing to write
+    auto occupied = [&](int64_t b) { return start[b] != start[b + 1]; };
+    const bool own = occupied(gbin);
+    const bool left = tx > 0 && occupied(gbin - 1);
+    const bool up = ty > 0 && occupied(gbin - G.ntx);
+    const bool upleft = tx > 0 && ty > 0 && occupied(gbin - G.ntx - 1);
+    if (!(own || left || up || upleft)) {
+        if (lane == 0) {
+            part[(gbin * 2 + 1) * 2 + 0] = 0.0;
+            part[(gbin * 2 + 1) * 2 + 1] = 0.0;
+        }
+        return;
+    }
     double sum = 0.0, cnt = 0.0;
-    for (int j = threadIdx.x; j < NBORDER; j += blockDim.x) {
+    for (int j = lane; j < NBORDER; j += 64) {
         const int lx = j < TH ? 0 : j - TH + 1;
         const int ly = j < TH ? j : 0;
         const int X = xo + lx, Y = yo + ly;
@@ -606,17 +670,17 @@ __global__ __launch_bounds__(64) void fwd_merge_kernel(const WinMeta* __restrict
 #pragma unroll
         for (int pol = 0; pol < 2; ++pol) {
             double2 a = own ? border[(gbin * NBORDER + j) * 2 + pol] : make_double2(0.0, 0.0);
-            if (lx == 0 && tx > 0) {
+            if (lx == 0 && left) {
                 const double2 h = halo[((gbin - 1) * NHALO + ly) * 2 + pol];
                 a.x += h.x;
                 a.y += h.y;
             }
-            if (ly == 0 && ty > 0) {
+            if (ly == 0 && up) {
                 const double2 h = halo[((gbin - G.ntx) * NHALO + TH + 1 + lx) * 2 + pol];
                 a.x += h.x;
                 a.y += h.y;
             }
-            if (lx == 0 && ly == 0 && tx > 0 && ty > 0) {
+            if (lx == 0 && ly == 0 && upleft) {
                 const double2 h = halo[((gbin - G.ntx - 1) * NHALO + TH) * 2 + pol];
                 a.x += h.x;
                 a.y += h.y;
@@ -626,9 +690,9 @@ __global__ __launch_bounds__(64) void fwd_merge_kernel(const WinMeta* __restrict
         }
         reduce_pixel(v[0], v[1], P.eps, sum, cnt);
     }
-    sum = block_sum(sum, red);
-    cnt = block_sum(cnt, red);
-    if (threadIdx.x == 0) {
+    sum = wave_sum(sum);
+    cnt = wave_sum(cnt);
+    if (lane == 0) {
         part[(gbin * 2 + 1) * 2 + 0] = sum;
         part[(gbin * 2 + 1) * 2 + 1] = cnt;
     }
@@ -988,14 +1052,17 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(
 }
 
 template <bool EXACT>
-__global__ __launch_bounds__(64) void bwd_merge_kernel(
-    const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const float* __restrict__ rho,
-    const float* __restrict__ ego, const float* __restrict__ grad_loss,
+__global__ __launch_bounds__(64 * kMergeBins) void bwd_merge_kernel(
+    const WinMeta* __restrict__ meta, int nw, int64_t nbins, const int* __restrict__ win_of,
+    const float* __restrict__ rho, const float* __restrict__ ego, const float* __restrict__ grad_loss,
     float* __restrict__ drho, const double2* __restrict__ halo,
     const double2* __restrict__ border, double* __restrict__ part)
 {
-    __shared__ double red[16];
-    const int64_t gtile = blockIdx.x;       // backward bin: (flow set, tile) of a window
+    // one wavefront per backward bin (flow set, tile) of a window
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t graw = (int64_t)blockIdx.x * kMergeBins + wv;
+    const bool live = graw < nbins;
+    const int64_t gtile = live ? graw : nbins - 1;   // a dead wave reads a valid bin, writes nothing
     const int w = win_of[gtile];
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
@@ -1005,16 +1072,17 @@ __global__ __launch_bounds__(64) void bwd_merge_kernel(
     const int xo = tx * TW, yo = ty * TH;
     const float* ego_s = ego + 6 * (meta[w].ego_off + set);
     const Motion m = load_motion(P, ego_s);
-    __shared__ MotionXJ mx[1];      // used by the exact model only
+    __shared__ MotionXJ mx[kMergeBins];      // used by the exact model only
     if (EXACT) {
-        if (threadIdx.x == 0) mx[0] = load_motion_xj(ego_s);
+        if (lane == 0) mx[wv] = load_motion_xj(ego_s);
         __syncthreads();
     }
+    if (!live) return;
     const float* rho_w = rho + meta[w].pix_off + (size_t)set * P.HW;
     float* drho_w = drho + meta[w].pix_off + (size_t)set * P.HW;
     const double gl = (double)grad_loss[w];
     double dth[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int j = threadIdx.x; j < NBORDER; j += blockDim.x) {
+    for (int j = lane; j < NBORDER; j += 64) {
         const int lx = j < TH ? 0 : j - TH + 1;
         const int ly = j < TH ? j : 0;
         const int X = xo + lx, Y = yo + ly;
@@ -1038,7 +1106,7 @@ __global__ __launch_bounds__(64) void bwd_merge_kernel(
         const int pix = Y * P.W + X;
         if constexpr (EXACT) {
             double d = 0.0;
-            if (g.x != 0.0 || g.y != 0.0) d = chain_exact(P, mx[0], X, Y, (double)rho_w[pix], g.x, g.y, dth);
+            if (g.x != 0.0 || g.y != 0.0) d = chain_exact(P, mx[wv], X, Y, (double)rho_w[pix], g.x, g.y, dth);
             drho_w[pix] = (float)(gl * d);
             continue;
         }
@@ -1049,8 +1117,8 @@ __global__ __launch_bounds__(64) void bwd_merge_kernel(
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-        const double v = block_sum(dth[c], red);
-        if (threadIdx.x == 0) part[gtile * 12 + 6 + c] = v;
+        const double v = wave_sum(dth[c]);
+        if (lane == 0) part[gtile * 12 + 6 + c] = v;
     }
 }
 
@@ -1292,7 +1360,8 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     }
     {
         PhaseScope ph(prof, kPhReduce, s);
-        fwd_merge_kernel<<<(int)B.nbins, 64, 0, s>>>(meta, nw, win_bin, start, img, halo, fborder,
+        fwd_merge_kernel<<<(int)((B.nbins + kMergeBins - 1) / kMergeBins), 64 * kMergeBins, 0, s>>>(
+            meta, nw, B.nbins, win_bin, start, img, halo, fborder,
                                                      part);
     }
     {
@@ -1369,7 +1438,8 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
         constexpr bool EX = FM == 2;
         bwd_tile_kernel<DET, EX><<<(int)B.nbins_b, 256, 0, s>>>(meta, nw, win_tile, rec, start, rho, ego,
                                                                 grad_loss, grad_rho, halo, border, part);
-        bwd_merge_kernel<EX><<<(int)B.nbins_b, 64, 0, s>>>(meta, nw, win_tile, rho, ego, grad_loss,
+        bwd_merge_kernel<EX><<<(int)((B.nbins_b + kMergeBins - 1) / kMergeBins), 64 * kMergeBins, 0,
+                               s>>>(meta, nw, B.nbins_b, win_tile, rho, ego, grad_loss,
                                                            grad_rho, halo, border, part);
     }
     {
