@@ -953,21 +953,17 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(
     const int xo = tx * TW, yo = ty * TH;
     const uint32_t s0 = start[gtile], s1 = start[gtile + 1];
     if (s0 == s1) {
-        // no records: dL/du is zero on the tile; write its d rho, zero border
-        // values and halo for the merge, and zero d theta shares
+        // no records: dL/du is zero on the tile; write its interior d rho and
+        // zero d theta shares (the merge writes column 0 and row 0, and reads
+        // border values and halos of occupied bins only)
         float* drho_w = drho + meta[w].pix_off + (size_t)set * P.HW;
         const float z = (float)((double)grad_loss[w] * 0.0);
         for (int i = threadIdx.x; i < TW * TH; i += blockDim.x) {
             const int lx = i % TW, ly = i / TW;
             const int X = xo + lx, Y = yo + ly;
-            if (X >= P.W || Y >= P.H) continue;
-            if (lx == 0 || ly == 0)
-                border[gtile * NBORDER + (lx == 0 ? ly : TH + lx - 1)] = make_double2(0.0, 0.0);
-            else
-                drho_w[Y * P.W + X] = z;
+            if (X >= P.W || Y >= P.H || lx == 0 || ly == 0) continue;
+            drho_w[Y * P.W + X] = z;
         }
-        for (int j = threadIdx.x; j < NHALO; j += blockDim.x)
-            halo[gtile * NHALO + j] = make_double2(0.0, 0.0);
         if (threadIdx.x < 6) part[gtile * 12 + threadIdx.x] = 0.0;
         return;
     }
@@ -1055,7 +1051,7 @@ template <bool EXACT>
 __global__ __launch_bounds__(64 * kMergeBins) void bwd_merge_kernel(
     const WinMeta* __restrict__ meta, int nw, int64_t nbins, const int* __restrict__ win_of,
     const float* __restrict__ rho, const float* __restrict__ ego, const float* __restrict__ grad_loss,
-    float* __restrict__ drho, const double2* __restrict__ halo,
+    const uint32_t* __restrict__ start, float* __restrict__ drho, const double2* __restrict__ halo,
     const double2* __restrict__ border, double* __restrict__ part)
 {
     // one wavefront per backward bin (flow set, tile) of a window
@@ -1082,23 +1078,29 @@ __global__ __launch_bounds__(64 * kMergeBins) void bwd_merge_kernel(
     float* drho_w = drho + meta[w].pix_off + (size_t)set * P.HW;
     const double gl = (double)grad_loss[w];
     double dth[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // border values and halos exist for occupied bins only (zero otherwise)
+    auto occupied = [&](int64_t b) { return start[b] != start[b + 1]; };
+    const bool own = occupied(gtile);
+    const bool left = tx > 0 && occupied(gtile - 1);
+    const bool up = ty > 0 && occupied(gtile - G.ntx);
+    const bool upleft = tx > 0 && ty > 0 && occupied(gtile - G.ntx - 1);
     for (int j = lane; j < NBORDER; j += 64) {
         const int lx = j < TH ? 0 : j - TH + 1;
         const int ly = j < TH ? j : 0;
         const int X = xo + lx, Y = yo + ly;
         if (X >= P.W || Y >= P.H) continue;
-        double2 g = border[gtile * NBORDER + j];
-        if (lx == 0 && tx > 0) {
+        double2 g = own ? border[gtile * NBORDER + j] : make_double2(0.0, 0.0);
+        if (lx == 0 && left) {
             const double2 h = halo[(gtile - 1) * NHALO + ly];
             g.x += h.x;
             g.y += h.y;
         }
-        if (ly == 0 && ty > 0) {
+        if (ly == 0 && up) {
             const double2 h = halo[(gtile - G.ntx) * NHALO + TH + 1 + lx];
             g.x += h.x;
             g.y += h.y;
         }
-        if (lx == 0 && ly == 0 && tx > 0 && ty > 0) {
+        if (lx == 0 && ly == 0 && upleft) {
             const double2 h = halo[(gtile - G.ntx - 1) * NHALO + TH];
             g.x += h.x;
             g.y += h.y;
@@ -1439,7 +1441,7 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
         bwd_tile_kernel<DET, EX><<<(int)B.nbins_b, 256, 0, s>>>(meta, nw, win_tile, rec, start, rho, ego,
                                                                 grad_loss, grad_rho, halo, border, part);
         bwd_merge_kernel<EX><<<(int)((B.nbins_b + kMergeBins - 1) / kMergeBins), 64 * kMergeBins, 0,
-                               s>>>(meta, nw, B.nbins_b, win_tile, rho, ego, grad_loss,
+                               s>>>(meta, nw, B.nbins_b, win_tile, rho, ego, grad_loss, start,
                                                            grad_rho, halo, border, part);
     }
     {
