@@ -245,14 +245,6 @@ struct BinSpace {
     }
 };
 
-// Zeroes n counters (a kernel, not a memset, so that graph replays clear them).
-__global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0u;
-}
-
 // In place: csum[c][bin] <- sum over chunks before c; totals[global bin] = column total.
 __global__ __launch_bounds__(256) void chunk_scan_kernel(const WinMeta* __restrict__ meta, int nw,
                                                          int64_t nbins_total, int bwd,
@@ -467,27 +459,55 @@ __device__ __forceinline__ int window_of_bbin(const WinMeta* meta, int nw, int64
 // batch, one binary search per entry per call instead of one chain of
 // dependent loads at the start of every workgroup.
 // tab = [blocks | forward bins | backward bins].
-// The window of every event block, bin and backward bin, and (one thread per
-// window) the first-order motion coefficients of every flow set.
+// Per-call preparation, one launch: the window of every event block, bin and
+// backward bin; (one thread per window) the first-order motion coefficients
+// of every flow set; cleared per-window headers (hdrs, forward only); zeroed
+// chunk sums.
 __global__ __launch_bounds__(256) void window_table_kernel(const WinMeta* __restrict__ meta,
                                                            int nw, int64_t nblk, int64_t nbin,
                                                            int64_t nbb, int* __restrict__ tab,
                                                            const float* __restrict__ ego,
-                                                           Motion* __restrict__ mtab)
+                                                           Motion* __restrict__ mtab,
+                                                           StateHeader* __restrict__ hdrs,
+                                                           uint32_t* __restrict__ csum,
+                                                           int64_t ncsum)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nblk)
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nblk) {
         tab[i] = window_of_block(meta, nw, i);
-    else if (i < nblk + nbin)
-        tab[i] = window_of_bin(meta, nw, i - nblk);
-    else if (i < nblk + nbin + nbb)
-        tab[i] = window_of_bbin(meta, nw, i - nblk - nbin);
-    else if (i < nblk + nbin + nbb + nw) {
-        const int w = (int)(i - nblk - nbin - nbb);
+        return;
+    }
+    i -= nblk;
+    if (i < nbin) {
+        tab[nblk + i] = window_of_bin(meta, nw, i);
+        return;
+    }
+    i -= nbin;
+    if (i < nbb) {
+        tab[nblk + nbin + i] = window_of_bbin(meta, nw, i);
+        return;
+    }
+    i -= nbb;
+    if (i < nw) {
+        const int w = (int)i;
         const WinParams& P = meta[w].P;
         for (int f = 0; f < P.F; ++f)
             mtab[meta[w].ego_off + f] = load_motion(P, ego + 6 * (meta[w].ego_off + f));
+        if (hdrs) {
+            StateHeader z;
+            z.loss = 0.0;
+            z.n_valid = 0;
+            z.flags = 0;
+            for (int r = 0; r < kMaxRefs; ++r) {
+                z.num[r] = 0.0;
+                z.nact[r] = 0.0;
+            }
+            hdrs[w] = z;
+        }
+        return;
     }
+    i -= nw;
+    if (i < ncsum) csum[i] = 0u;
 }
 
 // Threads of the forward tile kernel: the deterministic mode keeps 256 (its
@@ -1147,23 +1167,6 @@ __global__ __launch_bounds__(256) void bwd_finalize_kernel(const WinMeta* __rest
     }
 }
 
-// Clears the per-window sums (n_valid is accumulated with atomics).
-__global__ __launch_bounds__(256) void clear_headers_kernel(StateHeader* __restrict__ hdrs, int nw)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nw) {
-        StateHeader z;
-        z.loss = 0.0;
-        z.n_valid = 0;
-        z.flags = 0;
-        for (int r = 0; r < kMaxRefs; ++r) {
-            z.num[r] = 0.0;
-            z.nact[r] = 0.0;
-        }
-        hdrs[i] = z;
-    }
-}
-
 // Writes one window's metadata (single-window calls pass it by value).
 __global__ void store_meta_kernel(WinMeta m, WinMeta* __restrict__ out)
 {
@@ -1300,11 +1303,12 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
 }
 
 static void launch_window_table(const BatchPlanHost& B, const WinMeta* meta, int* tab,
-                                const float* ego, Motion* mtab, hipStream_t s)
+                                const float* ego, Motion* mtab, StateHeader* hdrs,
+                                uint32_t* csum, hipStream_t s)
 {
-    const int64_t n = B.nblocks + B.nbins + B.nbins_b + B.nw;
-    window_table_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(meta, B.nw, B.nblocks, B.nbins,
-                                                                B.nbins_b, tab, ego, mtab);
+    const int64_t n = B.nblocks + B.nbins + B.nbins_b + B.nw + B.csum_cells;
+    window_table_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(
+        meta, B.nw, B.nblocks, B.nbins, B.nbins_b, tab, ego, mtab, hdrs, csum, B.csum_cells);
 }
 
 template <int RM, bool DET, int FM>
@@ -1330,10 +1334,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     const size_t lds = (size_t)B.max_lds_bins * sizeof(uint32_t);
     {
         PhaseScope ph(prof, kPhZero, s);
-        clear_headers_kernel<<<(nw + 255) / 256, 256, 0, s>>>(hdrs, nw);
-        launch_window_table(B, meta, wtab, ego, mtab, s);
-        fill_u32_kernel<<<(int)std::min<int64_t>((B.csum_cells + 255) / 256, 4096), 256, 0, s>>>(
-            csum, B.csum_cells);
+        launch_window_table(B, meta, wtab, ego, mtab, hdrs, csum, s);
     }
     {
         PhaseScope ph(prof, kPhCount, s);
@@ -1414,9 +1415,7 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
         PhaseScope ph(prof, kPhGradCount, s);
         // rebuilt rather than taken from the forward: a state the direct
         // forward filled has no tables, and the backward must stay in bounds
-        launch_window_table(B, meta, wtab, ego, mtab, s);
-        fill_u32_kernel<<<(int)std::min<int64_t>((B.csum_cells + 255) / 256, 4096), 256, 0, s>>>(
-            csum, B.csum_cells);
+        launch_window_table(B, meta, wtab, ego, mtab, nullptr, csum, s);
         constexpr int NT = DET ? 64 : kBinThreads;
         bwd_count_kernel<RM, NT, FM><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, src, rho, ego,
                                                                 mtab, hdrs, hist, csum);
