@@ -246,24 +246,30 @@ struct BinSpace {
 };
 
 // In place: csum[c][bin] <- sum over chunks before c; totals[global bin] = column total.
-__global__ __launch_bounds__(256) void chunk_scan_kernel(const WinMeta* __restrict__ meta, int nw,
+__global__ __launch_bounds__(256) void chunk_scan_kernel(const WinMeta* __restrict__ meta,
+                                                         const int* __restrict__ win_of,
                                                          int64_t nbins_total, int bwd,
                                                          uint32_t* __restrict__ csum,
                                                          uint32_t* __restrict__ totals)
 {
     const int64_t gbin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gbin >= nbins_total) return;
-    const int w = find_window(meta, nw, gbin,
-                              [bwd](const WinMeta& m) { return BinSpace::bin_off(m, bwd); });
+    const int w = win_of[gbin];
     const WinMeta& M = meta[w];
     const int nbins = BinSpace::nbins(M, bwd);
     const int bin = (int)(gbin - BinSpace::bin_off(M, bwd));
-    uint32_t* cs = csum + M.csum_off;
+    uint32_t* cs = csum + M.csum_off + bin;
     uint32_t run = 0;
-    for (int c = 0; c < M.nchunks; ++c) {
-        const uint32_t v = cs[(size_t)c * nbins + bin];
-        cs[(size_t)c * nbins + bin] = run;
-        run += v;
+    // eight chunk sums in flight at a time (no serial load-store chain)
+    for (int c0 = 0; c0 < M.nchunks; c0 += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = c0 + i < M.nchunks ? cs[(size_t)(c0 + i) * nbins] : 0u;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (c0 + i < M.nchunks) cs[(size_t)(c0 + i) * nbins] = run;
+            run += v[i];
+        }
     }
     totals[gbin] = run;
 }
@@ -346,13 +352,18 @@ __global__ __launch_bounds__(256) void offsets_kernel(const WinMeta* __restrict_
     const int nbins = BinSpace::nbins(M, bwd);
     const int64_t local = id - BinSpace::cell_off(M, bwd);
     const int c = (int)(local / nbins), bin = (int)(local - (int64_t)c * nbins);
-    const int b0 = c * kScanChunk, b1 = min(b0 + kScanChunk, M.G.nblocks);
-    uint32_t* h = hist + M.hist_off;
+    const int b0 = c * kScanChunk, nb = min(kScanChunk, M.G.nblocks - b0);
+    uint32_t* h = hist + M.hist_off + (size_t)b0 * nbins + bin;
+    // all of the chunk's counts are loaded before the first store (no serial
+    // load-store chain down the column)
+    uint32_t v[kScanChunk];
+#pragma unroll
+    for (int i = 0; i < kScanChunk; ++i) v[i] = i < nb ? h[(size_t)i * nbins] : 0u;
     uint32_t run = start[BinSpace::bin_off(M, bwd) + bin] + csum[M.csum_off + (size_t)c * nbins + bin];
-    for (int b = b0; b < b1; ++b) {
-        const uint32_t v = h[(size_t)b * nbins + bin];
-        h[(size_t)b * nbins + bin] = run;
-        run += v;
+#pragma unroll
+    for (int i = 0; i < kScanChunk; ++i) {
+        if (i < nb) h[(size_t)i * nbins] = run;
+        run += v[i];
     }
 }
 
@@ -1345,8 +1356,8 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     {
         PhaseScope ph(prof, kPhScan, s);
         const int gc = (int)((B.cells_f + 255) / 256);
-        chunk_scan_kernel<<<(int)((B.nbins + 255) / 256), 256, 0, s>>>(meta, nw, B.nbins, 0, csum,
-                                                                        totals);
+        chunk_scan_kernel<<<(int)((B.nbins + 255) / 256), 256, 0, s>>>(meta, win_bin, B.nbins, 0,
+                                                                        csum, totals);
         scan_kernel<<<1, 1024, 0, s>>>(totals, B.nbins, start);
         offsets_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_f, 0, hist, csum, start);
     }
@@ -1423,8 +1434,8 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
     {
         PhaseScope ph(prof, kPhGradScan, s);
         const int gc = (int)((B.cells_b + 255) / 256);
-        chunk_scan_kernel<<<(int)((B.nbins_b + 255) / 256), 256, 0, s>>>(meta, nw, B.nbins_b, 1,
-                                                                          csum, totals);
+        chunk_scan_kernel<<<(int)((B.nbins_b + 255) / 256), 256, 0, s>>>(meta, win_tile, B.nbins_b,
+                                                                          1, csum, totals);
         scan_kernel<<<1, 1024, 0, s>>>(totals, B.nbins_b, start);
         offsets_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_b, 1, hist, csum, start);
     }
