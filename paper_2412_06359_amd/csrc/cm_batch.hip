@@ -173,7 +173,7 @@ __device__ __forceinline__ void load_ref_table(const WinParams& P, const StateHe
 }
 
 template <int RM, int NT, int FM>
-__global__ __launch_bounds__(NT) void fwd_count_kernel(
+__global__ __launch_bounds__(NT, 3) void fwd_count_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const float* __restrict__ ex,
     const float* __restrict__ ey, const float* __restrict__ et, const float* __restrict__ rho,
     const float* __restrict__ ego, const Motion* __restrict__ mtab, uint32_t* __restrict__ hist,
@@ -203,15 +203,18 @@ __global__ __launch_bounds__(NT) void fwd_count_kernel(
         const int64_t k = base + (int64_t)e * NT + threadIdx.x;
         if (k >= n) break;
         const EventPrefetch::Ev cur = nx.take(e + 1 < G.ept ? k + NT : n);
-        double vx[RM], vy[RM];
-        int vr[RM];
+        // only the bins are kept (positions would hold 4 RM registers)
+        int bins[RM];
         Visits v;
-        if (!warp_visits<RM, FM>(P, u, rt, cur.x, cur.y, cur.t, vx, vy, vr, v)) continue;
+        if (!warp_visits_v<RM, FM>(P, u, rt, cur.x, cur.y, cur.t, v,
+                                   [&](int j, double X, double Y, int r) {
+                                       bins[j] = r * G.ntiles + tile_index(G, make_taps(P, X, Y));
+                                   }))
+            continue;
         ++cnt;
 #pragma unroll
         for (int j = 0; j < RM; ++j)
-            if (j < P.R)
-                atomicAdd(&lh[vr[j] * G.ntiles + tile_index(G, make_taps(P, vx[j], vy[j]))], 1u);
+            if (j < P.R) atomicAdd(&lh[bins[j]], 1u);
     }
     if (cnt) atomicAdd(&cnt_lds, cnt);
     __syncthreads();
@@ -781,26 +784,26 @@ __global__ __launch_bounds__(256) void fwd_finalize_kernel(const WinMeta* __rest
 // batch.
 template <int RM, int FM, typename F>
 __device__ __forceinline__ void for_each_sample(const WinParams& P, const RefTable& rt,
-                                                const Visits& v, const double (&vx)[RM],
-                                                const double (&vy)[RM], const int (&vr)[RM],
-                                                double x0, double y0, F&& fn)
+                                                const Visits& v, const int (&tl)[RM], int tev,
+                                                F&& fn)
 {
+    // tl[j]: tile of visit j's position; tev: tile of the event.  A visit's
+    // reference is mb + j in the forward sweep, mb - 1 - (j - nf) backward.
     const int jf = v.eq ? 1 : 0;
     if (FM != 0 && P.F > 1) {
 #pragma unroll
         for (int j = 0; j < RM; ++j) {
             if (j < P.R && !(v.eq && j == 0)) {
                 const bool first = (j == jf && j < v.nf) || (j == v.nf);
-                const int set = j < v.nf ? rt.sf[vr[j]] : rt.sb[vr[j]];
-                const int jp = j > 0 ? j - 1 : 0;
-                fn(first ? x0 : vx[jp], first ? y0 : vy[jp], set);
+                const int set = j < v.nf ? rt.sf[v.mb + j] : rt.sb[v.mb - 1 - (j - v.nf)];
+                fn(first ? tev : tl[j > 0 ? j - 1 : 0], set);
             }
         }
     } else {
 #pragma unroll
         for (int j = 1; j < RM; ++j)
-            if (j < P.R && j != jf && j != v.nf) fn(vx[j - 1], vy[j - 1], 0);
-        if (P.R - jf > 0) fn(x0, y0, 0);
+            if (j < P.R && j != jf && j != v.nf) fn(tl[j - 1], 0);
+        if (P.R - jf > 0) fn(tev, 0);
     }
 }
 
@@ -811,7 +814,7 @@ __device__ __forceinline__ void for_each_sample(const WinParams& P, const RefTab
 // one compact stretch of the source order, that is on neighbouring tiles, and
 // their image and inverse-depth gathers share the L2.
 template <int RM, int NT, int FM>
-__global__ __launch_bounds__(NT) void bwd_count_kernel(
+__global__ __launch_bounds__(NT, 3) void bwd_count_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const SrcRec* __restrict__ src,
     const float* __restrict__ rho, const float* __restrict__ ego, const Motion* __restrict__ mtab,
     const StateHeader* __restrict__ hdrs, uint32_t* __restrict__ hist, uint32_t* __restrict__ csum)
@@ -853,13 +856,15 @@ __global__ __launch_bounds__(NT) void bwd_count_kernel(
                 atomicAdd(&lh[tile_index(G, make_taps(P, x0, y0))], 1u);
             continue;
         }
-        double vx[RM], vy[RM];
-        int vr[RM];
+        int tl[RM];
         Visits v;
-        if (!warp_visits<RM, FM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
-        for_each_sample<RM, FM>(P, rt, v, vx, vy, vr, x0, y0, [&](double X, double Y, int set) {
-            atomicAdd(&lh[set * G.ntiles + tile_index(G, make_taps(P, X, Y))], 1u);
-        });
+        if (!warp_visits_v<RM, FM>(P, u, rt, x0, y0, tk, v,
+                                   [&](int j, double X, double Y, int) {
+                                       tl[j] = tile_index(G, make_taps(P, X, Y));
+                                   }))
+            continue;
+        for_each_sample<RM, FM>(P, rt, v, tl, tile_index(G, make_taps(P, x0, y0)),
+                                [&](int tile, int set) { atomicAdd(&lh[set * G.ntiles + tile], 1u); });
     }
     __syncthreads();
     uint32_t* row = hist + meta[w].hist_off + lb * G.nbins_b;

@@ -501,11 +501,13 @@ struct Visits {
 // start off the image, or any visited position off the image.  The loop is
 // unrolled over visits so that every array index is static, and all lanes of a
 // wave step through the same visit numbers together.
-template <int RM, int FM>
-__device__ __forceinline__ bool warp_visits(const WinParams& P, const Flows<FM>& fl,
-                                            const RefTable& rt, double x0, double y0, double tk,
-                                            double (&vx)[RM], double (&vy)[RM], int (&vr)[RM],
-                                            Visits& v)
+// The same warp handing each visit (j, X, Y, reference) to `visit` as it is
+// reached instead of storing the positions (the mask still applies to the
+// whole event: a false return discards what the visitor saw).
+template <int RM, int FM, typename Visit>
+__device__ __forceinline__ bool warp_visits_v(const WinParams& P, const Flows<FM>& fl,
+                                              const RefTable& rt, double x0, double y0,
+                                              double tk, Visits& v, Visit&& visit)
 {
     v.nf = 0;
     v.mb = 0;
@@ -557,12 +559,23 @@ __device__ __forceinline__ bool warp_visits(const WinParams& P, const Flows<FM>&
             }
             tau = ref;
             if (!inside(P, X, Y)) return false;
-            vx[j] = X;
-            vy[j] = Y;
-            vr[j] = r;
+            visit(j, X, Y, r);
         }
     }
     return true;
+}
+
+template <int RM, int FM>
+__device__ __forceinline__ bool warp_visits(const WinParams& P, const Flows<FM>& fl,
+                                            const RefTable& rt, double x0, double y0, double tk,
+                                            double (&vx)[RM], double (&vy)[RM], int (&vr)[RM],
+                                            Visits& v)
+{
+    return warp_visits_v<RM, FM>(P, fl, rt, x0, y0, tk, v, [&](int j, double X, double Y, int r) {
+        vx[j] = X;
+        vy[j] = Y;
+        vr[j] = r;
+    });
 }
 
 // The warp step that ends at visit j: whether it is a real step (not the
