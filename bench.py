@@ -50,27 +50,25 @@ def kernel_source_sha() -> str:
 
 
 def algorithmic_bytes(phase: str, n: int, HW: int, R: int, tiled: bool, F: int = 1,
-                      img_bytes=None, active_bytes=None) -> float:
+                      active_bytes=None) -> float:
     """Bytes a phase must move at minimum for one window.
 
     events: 13 B each (x, y, t FP32 + p int8); rho: 4 B per pixel and flow set;
     d rho 4 B per pixel and flow set; splat images: C and S FP64 per pixel,
     polarity and reference (32 R B per pixel) on the direct path, which writes
-    every pixel; on the tiled path only the tiles that some warped position
-    falls in (img_bytes, from cm_batch_occupied_image_bytes): the others hold
-    zeros that are neither written nor read.  The backward gathers C and S only
-    at the pixels the splat touched, 32 B at each of the sum over references of
-    N_r (active_bytes, from cm_batch_active_pixels).  The tiled path's records
-    and bin tables are not counted: they are the implementation's traffic, not
-    the method's."""
+    every pixel; the tiled path stores only the pixels some tap reached, 32 B
+    at each of the sum over references of N_r (active_bytes, from
+    cm_batch_active_pixels): the others hold zeros that are neither written
+    nor read.  The backward gathers C and S at those pixels only.  The tiled
+    path's records, bin tables and tile borders are not counted: they are the
+    implementation's traffic, not the method's."""
     ev = 13.0 * n
     rho = 4.0 * HW * F
     img = 32.0 * R * HW
     act = img if active_bytes is None else active_bytes
     if tiled:
-        occ = img if img_bytes is None else img_bytes
         table = {"zero": 0.0, "count": ev + rho, "scan": 0.0, "scatter": ev + rho,
-                 "splat": occ, "reduce": 0.0, "finalize": 0.0,
+                 "splat": act, "reduce": 0.0, "finalize": 0.0,
                  "grad_count": ev + rho, "grad_scan": 0.0, "adjoint": ev + rho + act,
                  "grad_tile": 8.0 * HW * F, "grad_finalize": 0.0}
     else:
@@ -329,8 +327,8 @@ def main():
     if path_used != "tiled":
         occ = [None] * len(wins)
     alg = sum(algorithmic_bytes(dom, w.n, w.width * w.height, len(w.refs), path_used == "tiled",
-                                w.rho.shape[0] if w.rho.ndim == 3 else 1, o, a)
-              for w, o, a in zip(wins, occ, act)) / launches_per_step
+                                w.rho.shape[0] if w.rho.ndim == 3 else 1, a)
+              for w, a in zip(wins, act)) / launches_per_step
     achieved = alg / (dom_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, dom)
 

@@ -240,9 +240,10 @@ cm_status cm_batch_diagnostics(cm_batch b, const void* state, double* out, void*
 /* Per window, the bytes of splat image held by its occupied (reference,
  * 32x32 tile) bins after the last batched forward on `state`: 32 bytes per
  * pixel of every tile that some warped position falls in (the other tiles
- * hold only zeros and are not written).  Host array of n_windows doubles;
- * call between the forward and the backward; synchronises `stream`.  A
- * measurement aid for the splat's minimal image traffic. */
+ * hold only zeros and are not written; inside an occupied tile only the
+ * pixels some tap reached are).  Host array of n_windows doubles; call
+ * between the forward and the backward; synchronises `stream`.  A
+ * measurement aid. */
 cm_status cm_batch_occupied_image_bytes(cm_batch b, const void* state, double* out, void* stream);
 /* Per window and reference, N_r (pixels with C_+ + C_- > 0) of the last
  * batched forward on `state`: host array of n_windows * CM_MAX_REFS doubles,

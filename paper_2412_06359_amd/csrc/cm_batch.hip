@@ -172,6 +172,11 @@ __device__ __forceinline__ void load_ref_table(const WinParams& P, const StateHe
     }
 }
 
+// The count and sweep kernels ask for 3 waves per SIMD: their 16-reference
+// instances would otherwise need 170-180 VGPRs and run 2 waves; the few
+// spilled registers cost less than the lost latency hiding (the scatter,
+// which holds every visit's position until its records are written, loses
+// more to spills and is left at 2).
 template <int RM, int NT, int FM>
 __global__ __launch_bounds__(NT, 3) void fwd_count_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const float* __restrict__ ex,
@@ -540,6 +545,9 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
                                                        double* __restrict__ part)
 {
     __shared__ double2 lds[2 * TLW * TLH];
+    // cells reached only by zero-weight taps (positions on a pixel row or
+    // column): they hold zeros, but the backward reads them (see below)
+    __shared__ uint32_t zbit[(2 * TLW * TLH + 31) / 32];
     __shared__ double red[16];
     const int64_t gbin = blockIdx.x;
     const int w = win_of[gbin];
@@ -564,6 +572,7 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
         return;
     }
     for (int i = threadIdx.x; i < 2 * TLW * TLH; i += blockDim.x) lds[i] = make_double2(0.0, 0.0);
+    for (int i = threadIdx.x; i < (2 * TLW * TLH + 31) / 32; i += blockDim.x) zbit[i] = 0u;
     __syncthreads();
     const double ref = P.refs[r];
     if (!DET) {
@@ -578,8 +587,13 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
             for (int c = 0; c < 4; ++c) {
                 if (!tap_in(tp, c)) continue;
                 const double wt = tap_w(tp, c);
-                if (wt == 0.0) continue;
-                double2* cell = L + (ly + (c >> 1)) * TLW + lx + (c & 1);
+                const int key = (ly + (c >> 1)) * TLW + lx + (c & 1);
+                if (wt == 0.0) {
+                    const int zk = pol * TLW * TLH + key;
+                    atomicOr(&zbit[zk >> 5], 1u << (zk & 31));
+                    continue;
+                }
+                double2* cell = L + key;
                 atomicAdd(&cell->x, wt);
                 atomicAdd(&cell->y, wt * tb);
             }
@@ -602,6 +616,7 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
                 const double wt = tap_w(tp, c);
                 const bool act = live && tap_in(tp, c) && wt != 0.0;
                 const int key = pol * TLW * TLH + (ly + (c >> 1)) * TLW + lx + (c & 1);
+                if (live && tap_in(tp, c) && wt == 0.0) atomicOr(&zbit[key >> 5], 1u << (key & 31));
                 ordered_add(lds, act, key, wt, wt * tb);
             }
         }
@@ -611,14 +626,23 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
     double2* img = img_base + meta[w].img_off;
     double2* plane0 = img + (size_t)(r * 2 + 0) * P.HW;
     double2* plane1 = img + (size_t)(r * 2 + 1) * P.HW;
-    // interior pixels to the image; column 0 and row 0 to the border buffer,
-    // which the merge completes with the neighbours' halos and stores
+    // Interior pixels to the image; column 0 and row 0 to the border buffer,
+    // which the merge completes with the neighbours' halos and stores.  The
+    // backward reads the image only at the taps of the positions splatted
+    // here, and an interior pixel's taps all come from this bin's records: so
+    // of the interior only the cells some tap reached are stored (a non-zero
+    // sum, or a zero-weight tap's bit), the others are neither written nor
+    // read.
     double2* fb = border + gbin * NBORDER * 2;
+    auto reached = [&](int k, const double2& c) {
+        return c.x != 0.0 || c.y != 0.0 || ((zbit[k >> 5] >> (k & 31)) & 1u);
+    };
     for (int i = threadIdx.x; i < TW * TH; i += blockDim.x) {
         const int lx = i % TW, ly = i / TW;
         const int X = xo + lx, Y = yo + ly;
         if (X >= P.W || Y >= P.H) continue;
-        const double2 a = lds[ly * TLW + lx], b = lds[TLW * TLH + ly * TLW + lx];
+        const int k = ly * TLW + lx;
+        const double2 a = lds[k], b = lds[TLW * TLH + k];
         if (lx == 0 || ly == 0) {
             const int j = lx == 0 ? ly : TH + lx - 1;
             fb[j * 2 + 0] = a;
@@ -626,8 +650,8 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
             continue;
         }
         const int pix = Y * P.W + X;
-        plane0[pix] = a;
-        plane1[pix] = b;
+        if (reached(k, a)) plane0[pix] = a;
+        if (reached(TLW * TLH + k, b)) plane1[pix] = b;
         reduce_pixel(a, b, P.eps, sum, cnt);
     }
     double2* hb = halo + gbin * NHALO * 2;
@@ -877,7 +901,7 @@ __global__ __launch_bounds__(NT, 3) void bwd_count_kernel(
 }
 
 template <int RM, int NT, bool DET, int FM>
-__global__ __launch_bounds__(NT) void bwd_sweep_kernel(
+__global__ __launch_bounds__(NT, 3) void bwd_sweep_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const SrcRec* __restrict__ src,
     const float* __restrict__ rho, const float* __restrict__ ego, const Motion* __restrict__ mtab,
     const double2* __restrict__ img_base, const StateHeader* __restrict__ hdrs,
