@@ -136,6 +136,20 @@ __device__ __forceinline__ int tap_pix(const WinParams& P, const Taps& t, int q)
     return (t.y0 + (q >> 1)) * P.W + t.x0 + (q & 1);
 }
 
+// Offsets of the four taps from tap 0 for gathers that load every tap
+// unconditionally: a tap off the sensor (not tap_in) reads its on-sensor
+// neighbour instead, and the caller discards that value.  The four loads then
+// carry no branch and issue back to back under one wait, where a load guarded
+// by its tap_in test would pay a full memory latency per tap.
+__device__ __forceinline__ void tap_offsets(const WinParams& P, const Taps& t, int (&off)[4])
+{
+    const int dx = t.inx ? 1 : 0, dy = t.iny ? P.W : 0;
+    off[0] = 0;
+    off[1] = dx;
+    off[2] = dy;
+    off[3] = dx + dy;
+}
+
 // Where the warp reads the flow: inverse depth and the motion coefficients.
 // The flow at a tap, u = A + rho B, is recomputed in FP64 from rho (4 bytes a
 // pixel, small enough to stay in L2) rather than read from a materialised FP64
@@ -390,8 +404,11 @@ __device__ __forceinline__ void tap_flows(const WinParams& P, const FlowSrc& f, 
         By[i] = m.tvy - yb[i] * m.vz;
     }
     const float* row0 = f.rho + (size_t)t.y0 * P.W + t.x0;
-    const float rq[4] = {row0[0], t.inx ? row0[1] : 0.f, t.iny ? row0[P.W] : 0.f,
-                         (t.inx && t.iny) ? row0[P.W + 1] : 0.f};
+    int off[4];
+    tap_offsets(P, t, off);
+    float rq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rq[q] = row0[off[q]];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int a = q & 1, b = q >> 1;
@@ -422,8 +439,11 @@ __device__ __forceinline__ void tap_flows(const WinParams& P, const FlowSrcX& f,
         }
     }
     const float* row0 = f.rho + (size_t)t.y0 * P.W + t.x0;
-    const float rq[4] = {row0[0], t.inx ? row0[1] : 0.f, t.iny ? row0[P.W] : 0.f,
-                         (t.inx && t.iny) ? row0[P.W + 1] : 0.f};
+    int off[4];
+    tap_offsets(P, t, off);
+    float rq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rq[q] = row0[off[q]];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int a = q & 1, b = q >> 1;
@@ -613,10 +633,16 @@ __device__ __forceinline__ void direct_term(const WinParams& P, const double2* _
                                             double& Lx, double& Ly)
 {
     const Taps tp = make_taps(P, X, Y);
+    int off[4];
+    tap_offsets(P, tp, off);
+    const double2* p0 = plane + tap_pix(P, tp, 0);
+    double2 csq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) csq[q] = p0[off[q]];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if (!tap_in(tp, q)) continue;
-        const double2 cs = plane[tap_pix(P, tp, q)];
+        const double2 cs = csq[q];
         const double S = cs.y;
         const double inv = 1.0 / (cs.x + P.eps);
         const double sc = S * inv;

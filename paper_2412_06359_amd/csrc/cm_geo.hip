@@ -123,8 +123,14 @@ __device__ __forceinline__ bool geo_pixel(const WinParams& P, const GeoPose& g, 
     if (!(xs >= 0.0 && xs <= P.xmax && ys >= 0.0 && ys <= P.ymax)) return false;
     o.tp = make_taps(P, xs, ys);
     const float* row0 = rb + (size_t)o.tp.y0 * P.W + o.tp.x0;
-    const float rq[4] = {row0[0], o.tp.inx ? row0[1] : 1.f, o.tp.iny ? row0[P.W] : 1.f,
-                         (o.tp.inx && o.tp.iny) ? row0[P.W + 1] : 1.f};
+    int off[4];
+    tap_offsets(P, o.tp, off);
+    float rq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rq[q] = row0[off[q]];
+#pragma unroll
+    for (int q = 1; q < 4; ++q)
+        if (!tap_in(o.tp, q)) rq[q] = 1.f;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
         if (!(rq[q] > 0.f)) return false;        // off-sensor taps read 1
