@@ -548,14 +548,9 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
     // cells reached only by zero-weight taps (positions on a pixel row or
     // column): they hold zeros, but the backward reads them (see below)
     __shared__ uint32_t zbit[(2 * TLW * TLH + 31) / 32];
-    __shared__ double red[16];
+    __shared__ double red[32];
     const int64_t gbin = blockIdx.x;
-    const int w = win_of[gbin];
-    const WinParams& P = meta[w].P;
-    const TileGeom G = meta[w].G;
-    int r, tx, ty;
-    split_bin(G, (int)(gbin - meta[w].bin_off), r, tx, ty);
-    const int xo = tx * TW, yo = ty * TH;
+    // emptiness first: it needs no window lookup, and most bins are empty
     const uint32_t s0 = start[gbin], s1 = start[gbin + 1];
     if (s0 == s1) {
         // No warped position falls in this tile at this reference.  Nothing
@@ -571,31 +566,49 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
         }
         return;
     }
+    const int w = win_of[gbin];
+    const WinParams& P = meta[w].P;
+    const TileGeom G = meta[w].G;
+    int r, tx, ty;
+    split_bin(G, (int)(gbin - meta[w].bin_off), r, tx, ty);
+    const int xo = tx * TW, yo = ty * TH;
     for (int i = threadIdx.x; i < 2 * TLW * TLH; i += blockDim.x) lds[i] = make_double2(0.0, 0.0);
     for (int i = threadIdx.x; i < (2 * TLW * TLH + 31) / 32; i += blockDim.x) zbit[i] = 0u;
     __syncthreads();
     const double ref = P.refs[r];
     if (!DET) {
-        for (uint32_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
-            const SplatRec q = rec[i];
-            const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
-            const double tb = 1.0 - fabs(ref - (double)fabsf(q.ts));
-            const Taps tp = make_taps(P, q.X, q.Y);
-            const int lx = tp.x0 - xo, ly = tp.y0 - yo;
-            double2* L = lds + pol * TLW * TLH;
+        // two records per thread and round, both loads issued before either
+        // is used (a heavy bin takes several rounds); the second load reads
+        // the first record again when there is no second one
+        const uint32_t nt = blockDim.x;
+        for (uint32_t i0 = s0 + threadIdx.x; i0 < s1; i0 += 2 * nt) {
+            const bool two = i0 + nt < s1;
+            SplatRec qq[2];
+            qq[0] = rec[i0];
+            qq[1] = rec[two ? i0 + nt : i0];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if (!tap_in(tp, c)) continue;
-                const double wt = tap_w(tp, c);
-                const int key = (ly + (c >> 1)) * TLW + lx + (c & 1);
-                if (wt == 0.0) {
-                    const int zk = pol * TLW * TLH + key;
-                    atomicOr(&zbit[zk >> 5], 1u << (zk & 31));
-                    continue;
+            for (int u = 0; u < 2; ++u) {
+                if (u == 1 && !two) break;
+                const SplatRec q = qq[u];
+                const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
+                const double tb = 1.0 - fabs(ref - (double)fabsf(q.ts));
+                const Taps tp = make_taps(P, q.X, q.Y);
+                const int lx = tp.x0 - xo, ly = tp.y0 - yo;
+                double2* L = lds + pol * TLW * TLH;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    if (!tap_in(tp, c)) continue;
+                    const double wt = tap_w(tp, c);
+                    const int key = (ly + (c >> 1)) * TLW + lx + (c & 1);
+                    if (wt == 0.0) {
+                        const int zk = pol * TLW * TLH + key;
+                        atomicOr(&zbit[zk >> 5], 1u << (zk & 31));
+                        continue;
+                    }
+                    double2* cell = L + key;
+                    atomicAdd(&cell->x, wt);
+                    atomicAdd(&cell->y, wt * tb);
                 }
-                double2* cell = L + key;
-                atomicAdd(&cell->x, wt);
-                atomicAdd(&cell->y, wt * tb);
             }
         }
     } else if (threadIdx.x < 64) {
@@ -660,11 +673,11 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
         hb[j * 2 + 0] = lds[idx];
         hb[j * 2 + 1] = lds[TLW * TLH + idx];
     }
-    sum = block_sum(sum, red);
-    cnt = block_sum(cnt, red);
+    double sc[2] = {sum, cnt};
+    block_sum_n(sc, red);
     if (threadIdx.x == 0) {
-        part[(gbin * 2 + 0) * 2 + 0] = sum;
-        part[(gbin * 2 + 0) * 2 + 1] = cnt;
+        part[(gbin * 2 + 0) * 2 + 0] = sc[0];
+        part[(gbin * 2 + 0) * 2 + 1] = sc[1];
     }
 }
 
@@ -1002,7 +1015,7 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(
     double* __restrict__ part)
 {
     __shared__ double2 lds[TLW * TLH];
-    __shared__ double red[16];
+    __shared__ double red[16 * 6];
     const int64_t gtile = blockIdx.x;       // backward bin: (flow set, tile) of a window
     const int w = win_of[gtile];
     const WinParams& P = meta[w].P;
@@ -1030,18 +1043,28 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(
     for (int i = threadIdx.x; i < TLW * TLH; i += blockDim.x) lds[i] = make_double2(0.0, 0.0);
     __syncthreads();
     if (!DET) {
-        for (uint32_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
-            const GradRec q = rec[i];
-            const Taps tp = make_taps(P, q.X, q.Y);
-            const int lx = tp.x0 - xo, ly = tp.y0 - yo;
+        // two records per thread and round, loaded together (see fwd_tile)
+        const uint32_t nt = blockDim.x;
+        for (uint32_t i0 = s0 + threadIdx.x; i0 < s1; i0 += 2 * nt) {
+            const bool two = i0 + nt < s1;
+            GradRec qq[2];
+            qq[0] = rec[i0];
+            qq[1] = rec[two ? i0 + nt : i0];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if (!tap_in(tp, c)) continue;
-                const double wt = tap_w(tp, c);
-                if (wt == 0.0) continue;
-                double2* cell = lds + (ly + (c >> 1)) * TLW + lx + (c & 1);
-                atomicAdd(&cell->x, wt * q.gx);
-                atomicAdd(&cell->y, wt * q.gy);
+            for (int u = 0; u < 2; ++u) {
+                if (u == 1 && !two) break;
+                const GradRec q = qq[u];
+                const Taps tp = make_taps(P, q.X, q.Y);
+                const int lx = tp.x0 - xo, ly = tp.y0 - yo;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    if (!tap_in(tp, c)) continue;
+                    const double wt = tap_w(tp, c);
+                    if (wt == 0.0) continue;
+                    double2* cell = lds + (ly + (c >> 1)) * TLW + lx + (c & 1);
+                    atomicAdd(&cell->x, wt * q.gx);
+                    atomicAdd(&cell->y, wt * q.gy);
+                }
             }
         }
     } else if (threadIdx.x < 64) {
@@ -1100,11 +1123,10 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(
         const int idx = (j <= TH) ? j * TLW + TW : TH * TLW + (j - (TH + 1));
         hb[j] = lds[idx];
     }
+    block_sum_n(dth, red);
+    if (threadIdx.x == 0)
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        const double v = block_sum(dth[c], red);
-        if (threadIdx.x == 0) part[gtile * 12 + c] = v;
-    }
+        for (int c = 0; c < 6; ++c) part[gtile * 12 + c] = dth[c];
 }
 
 template <bool EXACT>

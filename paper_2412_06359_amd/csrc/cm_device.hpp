@@ -739,6 +739,32 @@ __device__ __forceinline__ double block_sum(double v, double* lds /* >= 16 */)
     return s;   // valid in thread 0
 }
 
+// K block_sum reductions in one pass: each value is added up in block_sum's
+// order, with one pair of barriers for all of them.  Results in thread 0.
+template <int K>
+__device__ __forceinline__ void block_sum_n(double (&v)[K], double* lds /* >= 16 K */)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += __shfl_down(v[k], o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) lds[16 * k + wid] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x >> 6;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += lds[16 * k + w];
+            v[k] = s;
+        }
+    }
+}
+
 }  // namespace cm
 
 namespace cm {
