@@ -182,7 +182,7 @@ __global__ __launch_bounds__(NT, 3) void fwd_count_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const float* __restrict__ ex,
     const float* __restrict__ ey, const float* __restrict__ et, const float* __restrict__ rho,
     const float* __restrict__ ego, const Motion* __restrict__ mtab, uint32_t* __restrict__ hist,
-    uint32_t* __restrict__ csum, StateHeader* __restrict__ hdrs)
+    uint32_t* __restrict__ csum, StateHeader* __restrict__ hdrs, uint8_t* __restrict__ valid)
 {
     extern __shared__ uint32_t lh[];
     __shared__ uint32_t cnt_lds;
@@ -211,11 +211,14 @@ __global__ __launch_bounds__(NT, 3) void fwd_count_kernel(
         // only the bins are kept (positions would hold 4 RM registers)
         int bins[RM];
         Visits v;
-        if (!warp_visits_v<RM, FM>(P, u, rt, cur.x, cur.y, cur.t, v,
-                                   [&](int j, double X, double Y, int r) {
-                                       bins[j] = r * G.ntiles + tile_index(G, make_taps(P, X, Y));
-                                   }))
-            continue;
+        const bool ok = warp_visits_v<RM, FM>(P, u, rt, cur.x, cur.y, cur.t, v,
+                                              [&](int j, double X, double Y, int r) {
+                                                  bins[j] = r * G.ntiles +
+                                                            tile_index(G, make_taps(P, X, Y));
+                                              });
+        // the mask, for the scatter (which then warps valid events only)
+        valid[ev0 + k] = ok ? 1 : 0;
+        if (!ok) continue;
         ++cnt;
 #pragma unroll
         for (int j = 0; j < RM; ++j)
@@ -381,7 +384,7 @@ __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
     const float* __restrict__ ey, const float* __restrict__ et, const int8_t* __restrict__ ep,
     const float* __restrict__ rho, const float* __restrict__ ego, const Motion* __restrict__ mtab,
     const uint32_t* __restrict__ offs, const uint32_t* __restrict__ start,
-    SplatRec* __restrict__ rec, SrcRec* __restrict__ src)
+    const uint8_t* __restrict__ valid, SplatRec* __restrict__ rec, SrcRec* __restrict__ src)
 {
     extern __shared__ uint32_t lh[];
     const int64_t blk = xcd_block();
@@ -403,38 +406,41 @@ __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
     const uint32_t r0 = start[meta[w].bin_off];
     SrcRec* wsrc = src + ev0;
     const int64_t base = lb * NT * G.ept;
+    const uint8_t* wvalid = valid + ev0;
     EventPrefetch nx(ex + ev0, ey + ev0, et + ev0, ep + ev0, base + threadIdx.x, n);
+    uint8_t vn = base + threadIdx.x < n ? wvalid[base + threadIdx.x] : (uint8_t)0;
     for (int e = 0; e < G.ept; ++e) {
         const int64_t k = base + (int64_t)e * NT + threadIdx.x;
         if (k >= n) break;
         const EventPrefetch::Ev cur = nx.take(e + 1 < G.ept ? k + NT : n);
-        double vx[RM], vy[RM];
-        int vr[RM];
-        Visits v;
+        const uint8_t vk = vn;
+        if (e + 1 < G.ept && k + NT < n) vn = wvalid[k + NT];
+        // The count kernel's warp of this event masked it or not; the same
+        // warp here (same code, same inputs, no contraction: the same bits)
+        // reaches the same visits, so a valid event's records are written as
+        // its visits are reached, into the slots its counts reserved.
+        if (!vk) continue;
         const float xk = cur.x, yk = cur.y, tk = cur.t;
-        if (!warp_visits<RM, FM>(P, u, rt, xk, yk, tk, vx, vy, vr, v)) continue;
         const float ts = cur.p > 0 ? fabsf(tk) : -fabsf(tk);   // sign bit = polarity
-#pragma unroll
-        for (int j = 0; j < RM; ++j) {
-            if (j < P.R) {
-                const int bin = vr[j] * G.ntiles + tile_index(G, make_taps(P, vx[j], vy[j]));
-                const uint32_t slot = DET ? stable_slot(lh, bin) : atomicAdd(&lh[bin], 1u);
-                SplatRec q;
-                q.X = vx[j];
-                q.Y = vy[j];
-                q.ts = ts;
-                q.k = (uint32_t)k;
-                rec[slot] = q;
-                if (vr[j] == 0) {
-                    SrcRec o;
-                    o.x0 = xk;
-                    o.y0 = yk;
-                    o.ts = ts;
-                    o.k = (uint32_t)k;
-                    wsrc[slot - r0] = o;
-                }
+        Visits v;
+        warp_visits_v<RM, FM>(P, u, rt, xk, yk, tk, v, [&](int, double X, double Y, int r) {
+            const int bin = r * G.ntiles + tile_index(G, make_taps(P, X, Y));
+            const uint32_t slot = DET ? stable_slot(lh, bin) : atomicAdd(&lh[bin], 1u);
+            SplatRec q;
+            q.X = X;
+            q.Y = Y;
+            q.ts = ts;
+            q.k = (uint32_t)k;
+            rec[slot] = q;
+            if (r == 0) {
+                SrcRec o;
+                o.x0 = xk;
+                o.y0 = yk;
+                o.ts = ts;
+                o.k = (uint32_t)k;
+                wsrc[slot - r0] = o;
             }
-        }
+        });
     }
 }
 
@@ -1358,6 +1364,7 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
                      sizeof(double2));
     B.ws.records = take((size_t)recs * std::max(sizeof(SplatRec), sizeof(GradRec)));
     B.ws.src = take((size_t)ev * sizeof(SrcRec));
+    B.ws.valid = take((size_t)ev);
     B.ws.win = take((size_t)(blk + bin + bbin) * sizeof(int));
     B.ws.motion = take((size_t)B.n_sets * sizeof(Motion));
     B.ws.total = off;
@@ -1389,6 +1396,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     double2* fborder = halo + B.nbins * NHALO * 2;
     SplatRec* rec = reinterpret_cast<SplatRec*>(ws + B.ws.records);
     SrcRec* src = reinterpret_cast<SrcRec*>(ws + B.ws.src);
+    uint8_t* valid = reinterpret_cast<uint8_t*>(ws + B.ws.valid);
     int* wtab = reinterpret_cast<int*>(ws + B.ws.win);
     Motion* mtab = reinterpret_cast<Motion*>(ws + B.ws.motion);
     const int* win_blk = wtab;
@@ -1402,7 +1410,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
         PhaseScope ph(prof, kPhCount, s);
         constexpr int NT = DET ? 64 : kBinThreads;
         fwd_count_kernel<RM, NT, FM><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, ev.x, ev.y, ev.t, rho, ego,
-                                                            mtab, hist, csum, hdrs);
+                                                            mtab, hist, csum, hdrs, valid);
     }
     {
         PhaseScope ph(prof, kPhScan, s);
@@ -1416,7 +1424,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
         PhaseScope ph(prof, kPhScatter, s);
         constexpr int NT = DET ? 64 : kBinThreads;
         fwd_scatter_kernel<RM, NT, DET, FM><<<B.nblocks, NT, lds, s>>>(
-            meta, nw, win_blk, ev.x, ev.y, ev.t, ev.p, rho, ego, mtab, hist, start, rec, src);
+            meta, nw, win_blk, ev.x, ev.y, ev.t, ev.p, rho, ego, mtab, hist, start, valid, rec, src);
     }
     {
         PhaseScope ph(prof, kPhSplat, s);

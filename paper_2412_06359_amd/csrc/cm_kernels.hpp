@@ -133,7 +133,7 @@ constexpr int kScanChunk = 16;  // histogram rows per chunk of the column scan
 
 // Byte offsets of the tiled path's buffers inside the workspace region.
 struct TileWorkspace {
-    size_t hist, csum, totals, start, part, halo, records, src, win, motion, total;
+    size_t hist, csum, totals, start, part, halo, records, src, valid, win, motion, total;
 };
 
 // Host-side plan of a tiled batch: per-window metadata, totals, workspace layout.
