@@ -117,7 +117,7 @@ const char* cm_status_string(cm_status s);
  * splatted images C and S per reference and polarity (32 * R * width * height
  * bytes, FP64), per-reference sums, reduction scratch and, where the tiled
  * path applies, its workspace (binned records, at most 32 * R bytes per event,
- * a 16-byte source record per event, per-tile buffers).  The forward and
+ * a 16-byte source record and a 1-byte mask per event, per-tile buffers).  The forward and
  * backward of one window must be called with the same n_events.  0 if `d` is
  * invalid or n_events < 0. */
 size_t cm_state_bytes(const cm_window_desc* d, int64_t n_events);

@@ -186,6 +186,7 @@ __global__ __launch_bounds__(NT, 3) void fwd_count_kernel(
 {
     extern __shared__ uint32_t lh[];
     __shared__ uint32_t cnt_lds;
+    __shared__ int bins[RM][NT];
     const int64_t blk = xcd_block();
     const int w = win_of[blk];
     const WinParams& P = meta[w].P;
@@ -208,13 +209,14 @@ __global__ __launch_bounds__(NT, 3) void fwd_count_kernel(
         const int64_t k = base + (int64_t)e * NT + threadIdx.x;
         if (k >= n) break;
         const EventPrefetch::Ev cur = nx.take(e + 1 < G.ept ? k + NT : n);
-        // only the bins are kept (positions would hold 4 RM registers)
-        int bins[RM];
+        // only the bins are kept, in the thread's LDS column (registers
+        // would stay live through the whole warp)
         Visits v;
         const bool ok = warp_visits_v<RM, FM>(P, u, rt, cur.x, cur.y, cur.t, v,
                                               [&](int j, double X, double Y, int r) {
-                                                  bins[j] = r * G.ntiles +
-                                                            tile_index(G, make_taps(P, X, Y));
+                                                  bins[j][threadIdx.x] =
+                                                      r * G.ntiles +
+                                                      tile_index(G, make_taps(P, X, Y));
                                               });
         // the mask, for the scatter (which then warps valid events only)
         valid[ev0 + k] = ok ? 1 : 0;
@@ -222,7 +224,7 @@ __global__ __launch_bounds__(NT, 3) void fwd_count_kernel(
         ++cnt;
 #pragma unroll
         for (int j = 0; j < RM; ++j)
-            if (j < P.R) atomicAdd(&lh[bins[j]], 1u);
+            if (j < P.R) atomicAdd(&lh[bins[j][threadIdx.x]], 1u);
     }
     if (cnt) atomicAdd(&cnt_lds, cnt);
     __syncthreads();
@@ -863,6 +865,7 @@ __global__ __launch_bounds__(NT, 3) void bwd_count_kernel(
     const StateHeader* __restrict__ hdrs, uint32_t* __restrict__ hist, uint32_t* __restrict__ csum)
 {
     extern __shared__ uint32_t lh[];
+    __shared__ int tls[RM][NT];
     const int64_t blk = xcd_block();
     const int w = win_of[blk];
     const WinParams& P = meta[w].P;
@@ -899,13 +902,16 @@ __global__ __launch_bounds__(NT, 3) void bwd_count_kernel(
                 atomicAdd(&lh[tile_index(G, make_taps(P, x0, y0))], 1u);
             continue;
         }
-        int tl[RM];
+        // each visit's tile, in the thread's LDS column (see fwd_count)
         Visits v;
         if (!warp_visits_v<RM, FM>(P, u, rt, x0, y0, tk, v,
                                    [&](int j, double X, double Y, int) {
-                                       tl[j] = tile_index(G, make_taps(P, X, Y));
+                                       tls[j][threadIdx.x] = tile_index(G, make_taps(P, X, Y));
                                    }))
             continue;
+        int tl[RM];
+#pragma unroll
+        for (int j = 0; j < RM; ++j) tl[j] = j < P.R ? tls[j][threadIdx.x] : 0;
         for_each_sample<RM, FM>(P, rt, v, tl, tile_index(G, make_taps(P, x0, y0)),
                                 [&](int tile, int set) { atomicAdd(&lh[set * G.ntiles + tile], 1u); });
     }
