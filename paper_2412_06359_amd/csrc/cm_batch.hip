@@ -973,10 +973,13 @@ __global__ __launch_bounds__(NT, 3) void bwd_sweep_kernel(
         const SrcRec q = qn;
         if (e + 1 < G.ept && i + stride < nv) qn = load_nt(wsrc + i + stride);
         double vx[RM], vy[RM];
-        int vr[RM];
         Visits v;
         const double x0 = q.x0, y0 = q.y0, tk = fabsf(q.ts);
-        if (!warp_visits<RM, FM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
+        if (!warp_visits_v<RM, FM>(P, u, rt, x0, y0, tk, v, [&](int j, double X, double Y, int) {
+                vx[j] = X;
+                vy[j] = Y;
+            }))
+            continue;
         const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
         const double2* planes = img + (size_t)pol * P.HW;
         double g0x = 0.0, g0y = 0.0;     // contributions sampled at the event position
@@ -984,13 +987,13 @@ __global__ __launch_bounds__(NT, 3) void bwd_sweep_kernel(
 #pragma unroll
         for (int j = RM - 1; j >= 0; --j) {
             if (j < P.R) {
-                const VisitStep s = visit_step<RM>(P, rt, v, vr, j, tk);
+                const VisitStep s = visit_step(P, rt, v, j, tk);
                 if (s.step) {
                     if (s.restart) {
                         Lx = 0.0;
                         Ly = 0.0;
                     }
-                    const int r = vr[j];
+                    const int r = visit_ref(v, j);
                     direct_term(P, planes + (size_t)r * 2 * P.HW, rt.coef[r],
                                 1.0 - fabs(rt.t[r] - tk), vx[j], vy[j], Lx, Ly);
                     if (s.first) {

@@ -609,19 +609,25 @@ struct VisitStep {
     double dt;
 };
 
-template <int RM>
+// The reference of visit j: mb + j in the forward sweep, mb - 1 - (j - nf)
+// in the backward sweep (the same order warp_visits_v takes).
+__device__ __forceinline__ int visit_ref(const Visits& v, int j)
+{
+    return j < v.nf ? v.mb + j : v.mb - 1 - (j - v.nf);
+}
+
 __device__ __forceinline__ VisitStep visit_step(const WinParams& P, const RefTable& rt,
-                                                const Visits& v, const int (&vr)[RM], int j,
-                                                double tk)
+                                                const Visits& v, int j, double tk)
 {
     VisitStep s;
     const int jf = v.eq ? 1 : 0;             // first real forward step
+    const int r = visit_ref(v, j);
     s.step = !(v.eq && j == 0);
     s.first = (j == jf && j < v.nf) || (j == v.nf);
     s.restart = (j == P.R - 1) || (j == v.nf - 1);
-    const double tprev = (s.first || j == 0) ? tk : rt.t[vr[j > 0 ? j - 1 : 0]];
-    s.dt = rt.t[vr[j]] - tprev;
-    s.set = (j < v.nf) ? rt.sf[vr[j]] : rt.sb[vr[j]];
+    const double tprev = (s.first || j == 0) ? tk : rt.t[visit_ref(v, j > 0 ? j - 1 : 0)];
+    s.dt = rt.t[r] - tprev;
+    s.set = (j < v.nf) ? rt.sf[r] : rt.sb[r];
     return s;
 }
 

@@ -255,21 +255,24 @@ __global__ __launch_bounds__(256) void backward_kernel(
         const double x0 = ex[k], y0 = ey[k], tk = et[k];
         const int pol = ep[k] > 0 ? 0 : 1;
         double vx[RM], vy[RM];
-        int vr[RM];
         Visits v;
-        if (!warp_visits<RM, FM>(P, u, rt, x0, y0, tk, vx, vy, vr, v)) continue;
+        if (!warp_visits_v<RM, FM>(P, u, rt, x0, y0, tk, v, [&](int j, double X, double Y, int) {
+                vx[j] = X;
+                vy[j] = Y;
+            }))
+            continue;
         const double2* planes = reinterpret_cast<const double2*>(img) + (size_t)pol * P.HW;
         double Lx = 0.0, Ly = 0.0;
 #pragma unroll
         for (int j = RM - 1; j >= 0; --j) {
             if (j < P.R) {
-                const VisitStep s = visit_step<RM>(P, rt, v, vr, j, tk);
+                const VisitStep s = visit_step(P, rt, v, j, tk);
                 if (s.step) {
                     if (s.restart) {
                         Lx = 0.0;
                         Ly = 0.0;
                     }
-                    const int r = vr[j];
+                    const int r = visit_ref(v, j);
                     direct_term(P, planes + (size_t)r * 2 * P.HW, rt.coef[r],
                                 1.0 - fabs(rt.t[r] - tk), vx[j], vy[j], Lx, Ly);
                     const double X = s.first ? x0 : vx[j > 0 ? j - 1 : 0];
