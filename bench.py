@@ -78,6 +78,25 @@ def algorithmic_bytes(phase: str, n: int, HW: int, R: int, tiled: bool, F: int =
     return table.get(phase, 0.0)
 
 
+def launches_per_splat(per_launch: dict, steps: int) -> float:
+    return per_launch["splat"][1] / steps
+
+
+def splat_atomic_roofline(n_valid: int, R: int, splat_ms: float, launches_per_step: float) -> dict:
+    """The tiled splat against the atomic roofline: 8 LDS FP64 adds per valid
+    event and reference (4 taps x {C, S}; taps off the sensor or of zero
+    weight add nothing, so this is an upper bound of the issued count) per
+    launch, over the LDS FP64 atomic-add rate of random addresses in a
+    workgroup's array, measured in this run by the probe kernel."""
+    from paper_2412_06359_amd import probe
+    peak = probe.lds_atomic_rate(32768 // 8, 8) / 1e9
+    atomics = 8.0 * R * n_valid / launches_per_step
+    achieved = atomics / (splat_ms * 1e-3) / 1e9
+    return {"bound": "lds_atomic", "kernel": "splat", "atomics_per_launch": atomics,
+            "achieved": achieved, "peak": peak, "unit": "G atomics/s", "frac": achieved / peak,
+            "peak_source": "LDS FP64 atomic adds, random addresses, measured in this run"}
+
+
 def image_bytes(cm, wins, dev):
     """Per window, the splat-image bytes of its occupied tiles and of its
     active pixels (32 B times the sum over references of N_r), from one
@@ -422,6 +441,9 @@ def main():
                                                               w.height for w in wins))},
         "phases_ms_per_launch": {k: v[0] for k, v in per_launch.items()},
     }
+    if batched and "splat" in per_launch and n_valid:
+        out["atomic_roofline"] = splat_atomic_roofline(n_valid, R, per_launch["splat"][0],
+                                                       launches_per_splat(per_launch, args.steps))
     out.update(out_extra)
     if args.serve_seconds > 0:
         cm.set_path(0, cm.CM_PATH_AUTO)
