@@ -125,8 +125,8 @@ size_t cm_state_bytes(const cm_window_desc* d, int64_t n_events);
 /* Kernel path used by a handle.  AUTO picks per window: the direct path
  * (floating-point atomics straight into the images) for small windows, the
  * tiled path (warped positions binned by 32x32 tile and accumulated in LDS,
- * each pixel written once) for large ones where the sensor allows it.  The
- * two compute the same quantities; TILED fails with CM_ERR_UNSUPPORTED where
+ * each pixel written at most once) for large ones where the sensor allows
+ * it.  The two compute the same quantities; TILED fails with CM_ERR_UNSUPPORTED where
  * it does not apply (more than 16384 reference-tile bins).  The forward and
  * the backward on one state must take the same path: the tiled backward walks
  * per-event source records that only the tiled forward writes, and on a state
