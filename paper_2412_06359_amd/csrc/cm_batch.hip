@@ -497,7 +497,7 @@ __global__ __launch_bounds__(256) void window_table_kernel(const WinMeta* __rest
                                                            Motion* __restrict__ mtab,
                                                            StateHeader* __restrict__ hdrs,
                                                            uint32_t* __restrict__ csum,
-                                                           int64_t ncsum)
+                                                           int64_t ncsum, TileBin* __restrict__ tbin)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nblk) {
@@ -506,7 +506,20 @@ __global__ __launch_bounds__(256) void window_table_kernel(const WinMeta* __rest
     }
     i -= nblk;
     if (i < nbin) {
-        tab[nblk + i] = window_of_bin(meta, nw, i);
+        const int w = window_of_bin(meta, nw, i);
+        tab[nblk + i] = w;
+        const WinParams& P = meta[w].P;
+        int r, tx, ty;
+        split_bin(meta[w].G, (int)(i - meta[w].bin_off), r, tx, ty);
+        TileBin b;
+        b.ref = P.refs[r];
+        b.eps = P.eps;
+        b.plane = meta[w].img_off + (int64_t)r * 2 * P.HW;
+        b.W = P.W;
+        b.H = P.H;
+        b.xo = tx * TW;
+        b.yo = ty * TH;
+        tbin[i] = b;
         return;
     }
     i -= nbin;
@@ -544,7 +557,7 @@ constexpr int kTileThreadsDet = 256;
 constexpr int kTileThreads = 512;
 
 template <bool DET>
-__global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile_kernel(const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of,
+__global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile_kernel(const TileBin* __restrict__ tbin,
                                                        const SplatRec* __restrict__ rec,
                                                        const uint32_t* __restrict__ start,
                                                        double2* __restrict__ img_base,
@@ -558,8 +571,9 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
     __shared__ uint32_t zbit[(2 * TLW * TLH + 31) / 32];
     __shared__ double red[32];
     const int64_t gbin = blockIdx.x;
-    // emptiness first: it needs no window lookup, and most bins are empty
+    // the bin's bounds and its record, loaded together
     const uint32_t s0 = start[gbin], s1 = start[gbin + 1];
+    const TileBin bi = tbin[gbin];
     if (s0 == s1) {
         // No warped position falls in this tile at this reference.  Nothing
         // reads its pixels except column 0 and row 0, which the merge writes
@@ -574,16 +588,11 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
         }
         return;
     }
-    const int w = win_of[gbin];
-    const WinParams& P = meta[w].P;
-    const TileGeom G = meta[w].G;
-    int r, tx, ty;
-    split_bin(G, (int)(gbin - meta[w].bin_off), r, tx, ty);
-    const int xo = tx * TW, yo = ty * TH;
+    const int xo = bi.xo, yo = bi.yo;
     for (int i = threadIdx.x; i < 2 * TLW * TLH; i += blockDim.x) lds[i] = make_double2(0.0, 0.0);
     for (int i = threadIdx.x; i < (2 * TLW * TLH + 31) / 32; i += blockDim.x) zbit[i] = 0u;
     __syncthreads();
-    const double ref = P.refs[r];
+    const double ref = bi.ref;
     if (!DET) {
         // two records per thread and round, both loads issued before either
         // is used (a heavy bin takes several rounds); the second load reads
@@ -600,7 +609,7 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
                 const SplatRec q = qq[u];
                 const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
                 const double tb = 1.0 - fabs(ref - (double)fabsf(q.ts));
-                const Taps tp = make_taps(P, q.X, q.Y);
+                const Taps tp = make_taps_wh(bi.W, bi.H, q.X, q.Y);
                 const int lx = tp.x0 - xo, ly = tp.y0 - yo;
                 double2* L = lds + pol * TLW * TLH;
 #pragma unroll
@@ -630,7 +639,7 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
             else q.X = q.Y = (double)xo, q.ts = 0.f;
             const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
             const double tb = 1.0 - fabs(ref - (double)fabsf(q.ts));
-            const Taps tp = make_taps(P, q.X, q.Y);
+            const Taps tp = make_taps_wh(bi.W, bi.H, q.X, q.Y);
             const int lx = tp.x0 - xo, ly = tp.y0 - yo;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -644,9 +653,8 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
     }
     __syncthreads();
     double sum = 0.0, cnt = 0.0;
-    double2* img = img_base + meta[w].img_off;
-    double2* plane0 = img + (size_t)(r * 2 + 0) * P.HW;
-    double2* plane1 = img + (size_t)(r * 2 + 1) * P.HW;
+    double2* plane0 = img_base + bi.plane;
+    double2* plane1 = plane0 + (size_t)bi.W * bi.H;
     // Interior pixels to the image; column 0 and row 0 to the border buffer,
     // which the merge completes with the neighbours' halos and stores.  The
     // backward reads the image only at the taps of the positions splatted
@@ -661,7 +669,7 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
     for (int i = threadIdx.x; i < TW * TH; i += blockDim.x) {
         const int lx = i % TW, ly = i / TW;
         const int X = xo + lx, Y = yo + ly;
-        if (X >= P.W || Y >= P.H) continue;
+        if (X >= bi.W || Y >= bi.H) continue;
         const int k = ly * TLW + lx;
         const double2 a = lds[k], b = lds[TLW * TLH + k];
         if (lx == 0 || ly == 0) {
@@ -670,10 +678,10 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
             fb[j * 2 + 1] = b;
             continue;
         }
-        const int pix = Y * P.W + X;
+        const int pix = Y * bi.W + X;
         if (reached(k, a)) plane0[pix] = a;
         if (reached(TLW * TLH + k, b)) plane1[pix] = b;
-        reduce_pixel(a, b, P.eps, sum, cnt);
+        reduce_pixel(a, b, bi.eps, sum, cnt);
     }
     double2* hb = halo + gbin * NHALO * 2;
     for (int j = threadIdx.x; j < NHALO; j += blockDim.x) {
@@ -1376,17 +1384,19 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     B.ws.valid = take((size_t)ev);
     B.ws.win = take((size_t)(blk + bin + bbin) * sizeof(int));
     B.ws.motion = take((size_t)B.n_sets * sizeof(Motion));
+    B.ws.tbin = take((size_t)bin * sizeof(TileBin));
     B.ws.total = off;
     return B;
 }
 
 static void launch_window_table(const BatchPlanHost& B, const WinMeta* meta, int* tab,
                                 const float* ego, Motion* mtab, StateHeader* hdrs,
-                                uint32_t* csum, hipStream_t s)
+                                uint32_t* csum, TileBin* tbin, hipStream_t s)
 {
     const int64_t n = B.nblocks + B.nbins + B.nbins_b + B.nw + B.csum_cells;
     window_table_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(
-        meta, B.nw, B.nblocks, B.nbins, B.nbins_b, tab, ego, mtab, hdrs, csum, B.csum_cells);
+        meta, B.nw, B.nblocks, B.nbins, B.nbins_b, tab, ego, mtab, hdrs, csum, B.csum_cells,
+        tbin);
 }
 
 template <int RM, bool DET, int FM>
@@ -1408,12 +1418,13 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     uint8_t* valid = reinterpret_cast<uint8_t*>(ws + B.ws.valid);
     int* wtab = reinterpret_cast<int*>(ws + B.ws.win);
     Motion* mtab = reinterpret_cast<Motion*>(ws + B.ws.motion);
+    TileBin* tbin = reinterpret_cast<TileBin*>(ws + B.ws.tbin);
     const int* win_blk = wtab;
     const int* win_bin = wtab + B.nblocks;
     const size_t lds = (size_t)B.max_lds_bins * sizeof(uint32_t);
     {
         PhaseScope ph(prof, kPhZero, s);
-        launch_window_table(B, meta, wtab, ego, mtab, hdrs, csum, s);
+        launch_window_table(B, meta, wtab, ego, mtab, hdrs, csum, tbin, s);
     }
     {
         PhaseScope ph(prof, kPhCount, s);
@@ -1438,7 +1449,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     {
         PhaseScope ph(prof, kPhSplat, s);
         fwd_tile_kernel<DET><<<(int)B.nbins, B.tile_threads, 0, s>>>(
-            meta, nw, win_bin, rec, start, img, halo, fborder, part);
+            tbin, rec, start, img, halo, fborder, part);
     }
     {
         PhaseScope ph(prof, kPhReduce, s);
@@ -1494,7 +1505,8 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
         PhaseScope ph(prof, kPhGradCount, s);
         // rebuilt rather than taken from the forward: a state the direct
         // forward filled has no tables, and the backward must stay in bounds
-        launch_window_table(B, meta, wtab, ego, mtab, nullptr, csum, s);
+        launch_window_table(B, meta, wtab, ego, mtab, nullptr, csum,
+                            reinterpret_cast<TileBin*>(ws + B.ws.tbin), s);
         constexpr int NT = DET ? 64 : kBinThreads;
         bwd_count_kernel<RM, NT, FM><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, src, rho, ego,
                                                                 mtab, hdrs, hist, csum);

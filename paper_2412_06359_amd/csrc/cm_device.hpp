@@ -97,7 +97,7 @@ struct Taps {
     bool inx, iny;       // x0+1 < W, y0+1 < H
 };
 
-__device__ __forceinline__ Taps make_taps(const WinParams& P, double X, double Y)
+__device__ __forceinline__ Taps make_taps_wh(int W, int H, double X, double Y)
 {
     Taps t;
     const double fx0 = floor(X), fy0 = floor(Y);
@@ -105,9 +105,14 @@ __device__ __forceinline__ Taps make_taps(const WinParams& P, double X, double Y
     t.y0 = (int)fy0;
     t.a = X - fx0;
     t.b = Y - fy0;
-    t.inx = t.x0 + 1 < P.W;
-    t.iny = t.y0 + 1 < P.H;
+    t.inx = t.x0 + 1 < W;
+    t.iny = t.y0 + 1 < H;
     return t;
+}
+
+__device__ __forceinline__ Taps make_taps(const WinParams& P, double X, double Y)
+{
+    return make_taps_wh(P.W, P.H, X, Y);
 }
 
 __device__ __forceinline__ bool tap_in(const Taps& t, int q)

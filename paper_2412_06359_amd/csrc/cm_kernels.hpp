@@ -133,7 +133,17 @@ constexpr int kScanChunk = 16;  // histogram rows per chunk of the column scan
 
 // Byte offsets of the tiled path's buffers inside the workspace region.
 struct TileWorkspace {
-    size_t hist, csum, totals, start, part, halo, records, src, valid, win, motion, total;
+    size_t hist, csum, totals, start, part, halo, records, src, valid, win, motion, tbin, total;
+};
+
+// What the forward tile kernel needs of its bin, in one record written with
+// the window table: read together with the bin's bounds, it spares the kernel
+// the dependent lookups of the bin's window and the window's parameters.
+struct TileBin {
+    double ref, eps;        // the bin's reference time; the window's eps
+    int64_t plane;          // first element of the bin's (reference, positive) image plane
+    int W, H;               // sensor
+    int xo, yo;             // tile origin
 };
 
 // Host-side plan of a tiled batch: per-window metadata, totals, workspace layout.
