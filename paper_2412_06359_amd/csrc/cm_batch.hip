@@ -519,6 +519,8 @@ __global__ __launch_bounds__(256) void window_table_kernel(const WinMeta* __rest
         b.H = P.H;
         b.xo = tx * TW;
         b.yo = ty * TH;
+        b.ntx = meta[w].G.ntx;
+        b.pad = 0;
         tbin[i] = b;
         return;
     }
@@ -714,7 +716,7 @@ __device__ __forceinline__ double wave_sum(double v)
 // independent: no barrier).
 constexpr int kMergeBins = 4;
 
-__global__ __launch_bounds__(64 * kMergeBins) void fwd_merge_kernel(const WinMeta* __restrict__ meta, int nw, int64_t nbins, const int* __restrict__ win_of,
+__global__ __launch_bounds__(64 * kMergeBins) void fwd_merge_kernel(const TileBin* __restrict__ tbin, int64_t nbins,
                                                        const uint32_t* __restrict__ start,
                                                        double2* __restrict__ img_base,
                                                        const double2* __restrict__ halo,
@@ -724,21 +726,17 @@ __global__ __launch_bounds__(64 * kMergeBins) void fwd_merge_kernel(const WinMet
     const int64_t gbin = (int64_t)blockIdx.x * kMergeBins + (threadIdx.x >> 6);
     if (gbin >= nbins) return;
     const int lane = threadIdx.x & 63;
-    const int w = win_of[gbin];
-    const WinParams& P = meta[w].P;
-    const TileGeom G = meta[w].G;
-    int r, tx, ty;
-    split_bin(G, (int)(gbin - meta[w].bin_off), r, tx, ty);
-    const int xo = tx * TW, yo = ty * TH;
-    double2* img = img_base + meta[w].img_off;
+    const TileBin bi = tbin[gbin];     // the bin's geometry without a window lookup
+    const int xo = bi.xo, yo = bi.yo, tx = xo / TW, ty = yo / TH;
+    const int64_t HW = (int64_t)bi.W * bi.H;
     // occupied bins (the tile kernel wrote their border and halo); an empty
     // bin whose left, upper and upper-left neighbours are empty too has a
     // zero border that no gather reads: nothing to write
     auto occupied = [&](int64_t b) { return start[b] != start[b + 1]; };
     const bool own = occupied(gbin);
     const bool left = tx > 0 && occupied(gbin - 1);
-    const bool up = ty > 0 && occupied(gbin - G.ntx);
-    const bool upleft = tx > 0 && ty > 0 && occupied(gbin - G.ntx - 1);
+    const bool up = ty > 0 && occupied(gbin - bi.ntx);
+    const bool upleft = tx > 0 && ty > 0 && occupied(gbin - bi.ntx - 1);
     if (!(own || left || up || upleft)) {
         if (lane == 0) {
             part[(gbin * 2 + 1) * 2 + 0] = 0.0;
@@ -751,8 +749,8 @@ __global__ __launch_bounds__(64 * kMergeBins) void fwd_merge_kernel(const WinMet
         const int lx = j < TH ? 0 : j - TH + 1;
         const int ly = j < TH ? j : 0;
         const int X = xo + lx, Y = yo + ly;
-        if (X >= P.W || Y >= P.H) continue;
-        const int pix = Y * P.W + X;
+        if (X >= bi.W || Y >= bi.H) continue;
+        const int pix = Y * bi.W + X;
         double2 v[2];
 #pragma unroll
         for (int pol = 0; pol < 2; ++pol) {
@@ -763,19 +761,19 @@ __global__ __launch_bounds__(64 * kMergeBins) void fwd_merge_kernel(const WinMet
                 a.y += h.y;
             }
             if (ly == 0 && up) {
-                const double2 h = halo[((gbin - G.ntx) * NHALO + TH + 1 + lx) * 2 + pol];
+                const double2 h = halo[((gbin - bi.ntx) * NHALO + TH + 1 + lx) * 2 + pol];
                 a.x += h.x;
                 a.y += h.y;
             }
             if (lx == 0 && ly == 0 && upleft) {
-                const double2 h = halo[((gbin - G.ntx - 1) * NHALO + TH) * 2 + pol];
+                const double2 h = halo[((gbin - bi.ntx - 1) * NHALO + TH) * 2 + pol];
                 a.x += h.x;
                 a.y += h.y;
             }
-            img[(size_t)(r * 2 + pol) * P.HW + pix] = a;
+            img_base[bi.plane + pol * HW + pix] = a;
             v[pol] = a;
         }
-        reduce_pixel(v[0], v[1], P.eps, sum, cnt);
+        reduce_pixel(v[0], v[1], bi.eps, sum, cnt);
     }
     sum = wave_sum(sum);
     cnt = wave_sum(cnt);
@@ -1454,8 +1452,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     {
         PhaseScope ph(prof, kPhReduce, s);
         fwd_merge_kernel<<<(int)((B.nbins + kMergeBins - 1) / kMergeBins), 64 * kMergeBins, 0, s>>>(
-            meta, nw, B.nbins, win_bin, start, img, halo, fborder,
-                                                     part);
+            tbin, B.nbins, start, img, halo, fborder, part);
     }
     {
         PhaseScope ph(prof, kPhFinalize, s);

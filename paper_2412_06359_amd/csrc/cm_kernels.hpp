@@ -144,6 +144,7 @@ struct TileBin {
     int64_t plane;          // first element of the bin's (reference, positive) image plane
     int W, H;               // sensor
     int xo, yo;             // tile origin
+    int ntx, pad;           // tiles per row
 };
 
 // Host-side plan of a tiled batch: per-window metadata, totals, workspace layout.
