@@ -153,3 +153,36 @@ def test_c3_batch_full_size(cm):
         a, b = batch.pixel_offsets[w], batch.pixel_offsets[w + 1]
         assert_grads_close(g_rho[a:b], g_ego[w], ob["drho"].ravel(), ob["dtheta"],
                            what=f"c3[{w}]")
+
+
+@pytest.mark.parametrize("case", ["c1", "edges_R3"])
+def test_reused_state_zero_flow_reads_no_stale_pixels(cm, case):
+    """The tiled splat stores only the image pixels some tap reached.  With
+    zero motion every warped position stays on its pixel centre, where taps
+    1-3 have zero weight but a non-zero weight derivative, so the backward
+    reads those pixels: they must be stored too (a zero), not left holding a
+    previous window's values.  One state serves a moving window first, then
+    the same events without motion; the second run must give the oracle's
+    loss and gradients."""
+    if case == "c1":
+        moving = eventgen.make_window("c1")
+    else:
+        moving = eventgen.edge_window(951, "346x260", 20000, refs=[0.0, 0.5, 1.0],
+                                      n_segments=20, name="stale")
+    still = moving.replace(theta=np.zeros_like(moving.theta))
+    batch = make_batch(cm, [moving])
+    state = batch.new_state()
+    gl = torch.ones(1, device="cuda:0")
+    for win in (moving, still):
+        print(f"[gpu] stale-pixel check {case} theta={np.asarray(win.theta)[:3]}", flush=True)
+        d = pack([win])
+        loss, _ = batch.forward(d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"], state=state)
+        g_rho, g_ego = batch.backward(d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"], state,
+                                      gl)
+    torch.cuda.synchronize()
+    o = oracle.forward(still)
+    assert_loss_close(float(loss.item()), o["loss"], what=f"{case} zero flow, reused state")
+    ob = oracle.backward(still)
+    assert np.abs(ob["dtheta"]).max() > 0.0
+    assert_grads_close(g_rho.double().cpu().numpy(), g_ego.double().cpu().numpy(), ob["drho"],
+                       ob["dtheta"], what=f"{case} zero flow, reused state")
