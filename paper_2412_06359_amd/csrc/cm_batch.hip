@@ -5,15 +5,17 @@
 // FP64 atomics run at about 1.4 T/s.  So instead of splatting every tap with a
 // global atomic, each warped position becomes a record binned by the 32x32
 // tile of its tap (x0, y0) (a counting sort: count, scan, scatter), and one
-// workgroup per tile accumulates its records in LDS and writes every pixel it
-// owns once with plain, coalesced stores.  A record's taps can reach one
-// column right of and one row below its tile; that halo goes to a small
-// buffer and a merge pass adds it, in a fixed order, into column 0 / row 0 of
-// the neighbouring tiles.
+// workgroup per tile accumulates its records in LDS and writes the pixels it
+// owns that some tap reached, once, with plain stores.  A record's taps can
+// reach one column right of and one row below its tile; that halo goes to a
+// small buffer and a merge pass adds it, in a fixed order, into column 0 /
+// row 0 of the neighbouring tiles.
 //
 // Forward:  count -> chunk sums -> chunk scan -> scan -> offsets -> scatter
-//           -> tile -> merge -> finalize.  The per-reference sums of Eq. 1
-//           are reduced in the tile (interior) and merge (border) kernels.
+//           -> tile -> merge -> finalize.  The count also stores each event's
+//           mask, so the scatter warps valid events only.  The per-reference
+//           sums of Eq. 1 are reduced in the tile (interior) and merge
+//           (border) kernels.
 // Backward: the same sort over flow-sampling positions; the sweep re-runs
 //           each event's warp, gathers the adjoint seeds, runs the reverse
 //           sweep and emits one record per sampling position with
@@ -21,9 +23,11 @@
 //           d rho and d theta per pixel.
 //
 // Every kernel covers all windows of a batch in one launch: per-window
-// metadata (WinMeta) lives in device memory and each block or thread finds its
-// window by binary search over prefix offsets.  A single window is a batch of
-// one.
+// metadata (WinMeta) lives in device memory, and a table kernel run first in
+// each call finds the window of every event block, bin and tile (binary search
+// over prefix offsets), the motion coefficients of every flow set and, per
+// forward bin, the few values its tile and merge kernels need.  A single
+// window is a batch of one.
 #include "cm_kernels.hpp"
 
 namespace cm {
