@@ -148,7 +148,7 @@ def _rotate(points, phi):
 
 
 def _simulate_edge_events(rng, n_events, W, H, fx, fy, cx, cy, rho_fn, v, w, n_segments,
-                          max_rounds=400):
+                          max_rounds=400, subpixel=False):
     """Events of a random edge map observed by a camera in constant rigid motion.
 
     Each event: t ~ U[0,1]; a segment picked with probability proportional to
@@ -157,6 +157,10 @@ def _simulate_edge_events(rng, n_events, W, H, fx, fy, cx, cy, rho_fn, v, w, n_s
     to the nearest pixel and kept if it lands on the sensor in front of the
     camera.  Polarity is the segment's contrast sign.  Sampling repeats until
     n_events are kept; the result is sorted by time.
+
+    subpixel: keep the projected position real-valued (undistorted, rectified
+    events, as the supplement's training data are) instead of rounding it to
+    the pixel; see _subpixel_mix for the share placed on integers and borders.
     """
     A = np.stack([rng.uniform(0, W - 1, n_segments), rng.uniform(0, H - 1, n_segments)], 1)
     B = np.stack([rng.uniform(0, W - 1, n_segments), rng.uniform(0, H - 1, n_segments)], 1)
@@ -185,8 +189,11 @@ def _simulate_edge_events(rng, n_events, W, H, fx, fy, cx, cy, rho_fn, v, w, n_s
         Xt = _rotate(X0, tt * w[None, :]) + tt * v[None, :]
         front = Xt[:, 2] > 1e-3
         Z = np.where(front, Xt[:, 2], 1.0)
-        px = np.rint(fx * Xt[:, 0] / Z + cx)
-        py = np.rint(fy * Xt[:, 1] / Z + cy)
+        px = fx * Xt[:, 0] / Z + cx
+        py = fy * Xt[:, 1] / Z + cy
+        if not subpixel:
+            px = np.rint(px)
+            py = np.rint(py)
         ok = front & (px >= 0) & (px <= W - 1) & (py >= 0) & (py <= H - 1)
         accept = 0.7 * accept + 0.3 * max(float(ok.mean()), 1e-4)
         idx = np.nonzero(ok)[0][:need]
@@ -201,8 +208,43 @@ def _simulate_edge_events(rng, n_events, W, H, fx, fy, cx, cy, rho_fn, v, w, n_s
     y = np.concatenate(ys)
     t = np.concatenate(ts)
     p = np.concatenate(ps)
+    if subpixel:
+        x, y = _subpixel_mix(rng, x, y, W, H)
     order = np.argsort(t, kind="stable")
     return x[order], y[order], t[order], p[order]
+
+
+SUBPIXEL_ON_INTEGER = 0.10      # share of real-valued events moved onto a pixel centre
+SUBPIXEL_ON_BORDER = 0.02       # share moved onto the image border (one coordinate)
+SUBPIXEL_ON_ROW = 0.05          # share with one coordinate on an integer, the other real
+
+
+def _subpixel_mix(rng, x, y, W, H):
+    """Real-valued event coordinates (float32, inside [0, W-1] x [0, H-1]) with
+    the special positions of the bilinear kernel mixed in: a share exactly on
+    pixel centres, a share with one integer coordinate, and a share exactly on
+    the image border (x = 0, x = W-1, y = 0 or y = H-1), the rest as projected."""
+    x = np.asarray(x, np.float32).copy()
+    y = np.asarray(y, np.float32).copy()
+    n = x.shape[0]
+    u = rng.random(n)
+    on_int = u < SUBPIXEL_ON_INTEGER
+    x[on_int] = np.rint(x[on_int])
+    y[on_int] = np.rint(y[on_int])
+    on_row = (u >= SUBPIXEL_ON_INTEGER) & (u < SUBPIXEL_ON_INTEGER + SUBPIXEL_ON_ROW)
+    which = rng.random(n) < 0.5
+    x[on_row & which] = np.rint(x[on_row & which])
+    y[on_row & ~which] = np.rint(y[on_row & ~which])
+    lo = SUBPIXEL_ON_INTEGER + SUBPIXEL_ON_ROW
+    on_border = (u >= lo) & (u < lo + SUBPIXEL_ON_BORDER)
+    side = rng.integers(0, 4, n)
+    x[on_border & (side == 0)] = 0.0
+    x[on_border & (side == 1)] = np.float32(W - 1)
+    y[on_border & (side == 2)] = 0.0
+    y[on_border & (side == 3)] = np.float32(H - 1)
+    np.clip(x, 0.0, np.float32(W - 1), out=x)
+    np.clip(y, 0.0, np.float32(H - 1), out=y)
+    return x, y
 
 
 # ----------------------------------------------------------------------------
@@ -223,14 +265,20 @@ def refs_even(k: int) -> np.ndarray:
 
 
 def uniform_window(seed: int, sensor: str = "64x64", n_events: int = 2000,
-                   refs=(1.0,), motion_sigma: float = 0.3, name: str = "c1") -> Window:
+                   refs=(1.0,), motion_sigma: float = 0.3, name: str = "c1",
+                   subpixel: bool = False) -> Window:
     """Config c1: integer-uniform x, y; t ~ U[0,1] sorted; fair-coin polarity;
-    rho = 0.5 + sum of three Gaussian bumps (amplitude 0.5, sigma 8 px)."""
+    rho = 0.5 + sum of three Gaussian bumps (amplitude 0.5, sigma 8 px).
+    subpixel: x, y uniform over the closed image box instead (real-valued,
+    with the mix of integer and border positions of _subpixel_mix)."""
     s = SENSORS[sensor]
     W, H, f = s["width"], s["height"], s["f"]
     rng = _rng(seed)
     x = rng.integers(0, W, n_events).astype(np.float32)
     y = rng.integers(0, H, n_events).astype(np.float32)
+    if subpixel:
+        x, y = _subpixel_mix(rng, rng.uniform(0, W - 1, n_events),
+                             rng.uniform(0, H - 1, n_events), W, H)
     t = np.sort(rng.random(n_events).astype(np.float32))
     p = np.where(rng.random(n_events) < 0.5, 1, -1).astype(np.int8)
     mus = np.stack([rng.uniform(0, W - 1, 3), rng.uniform(0, H - 1, 3)], 1)
@@ -241,11 +289,12 @@ def uniform_window(seed: int, sensor: str = "64x64", n_events: int = 2000,
 
 
 def edge_window(seed: int, sensor: str, n_events: int, refs, n_segments: int = 50,
-                motion_sigma: float = 0.5, name: str = "edge") -> Window:
+                motion_sigma: float = 0.5, name: str = "edge", subpixel: bool = False) -> Window:
     """Configs c2-c5: events of a moving random edge map.
 
     rho = 0.2 + 1.8 * (min-max normalised sum of 4 Gaussians, sigma = W/6);
-    v, w ~ N(0, motion_sigma^2) per axis.
+    v, w ~ N(0, motion_sigma^2) per axis.  subpixel: real-valued event
+    coordinates (see _simulate_edge_events).
     """
     s = SENSORS[sensor]
     W, H, f = s["width"], s["height"], s["f"]
@@ -258,7 +307,7 @@ def edge_window(seed: int, sensor: str, n_events: int, refs, n_segments: int = 5
     v = theta[:3].astype(np.float64)
     w = theta[3:].astype(np.float64)
     x, y, t, p = _simulate_edge_events(rng, n_events, W, H, f, f, cx, cy, rho_fn, v, w,
-                                       n_segments)
+                                       n_segments, subpixel=subpixel)
     return Window(name, W, H, f, f, cx, cy, np.asarray(refs, dtype=np.float32),
                   x, y, t, p, rho, theta)
 
@@ -324,14 +373,15 @@ def with_flow_sets(win: Window, seed: int, jitter: float = 0.15) -> Window:
 
 
 def bins_window(index: int, n_bins: int = 10, sensor: str = "346x260",
-                per_bin=(1e3, 1e4)) -> Window:
+                per_bin=(1e3, 1e4), subpixel: bool = False) -> Window:
     """Workload c6: an edge-map window of n_bins slices with log-uniform 1k..10k
     events per slice, references at the n_bins + 1 slice edges and one flow
     set per slice."""
     seed = 1000 * 6 + index
     counts = log_uniform_counts(_rng(seed + 500), n_bins, *per_bin)
     refs = np.linspace(0.0, 1.0, n_bins + 1)
-    win = edge_window(seed, sensor, int(counts.sum()), refs=refs, n_segments=50, name="c6")
+    win = edge_window(seed, sensor, int(counts.sum()), refs=refs, n_segments=50, name="c6",
+                      subpixel=subpixel)
     return with_flow_sets(win, seed + 700)
 
 
@@ -339,36 +389,44 @@ def log_uniform_counts(rng, n, lo, hi) -> np.ndarray:
     return np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), n))).astype(np.int64)
 
 
-def make_window(config: str, index: int = 0, n_events: Optional[int] = None) -> Window:
-    """The `index`-th window of workload `config` (c1, c2, c3, c5, c6)."""
+def make_window(config: str, index: int = 0, n_events: Optional[int] = None,
+                subpixel: bool = False) -> Window:
+    """The `index`-th window of workload `config` (c1, c2, c3, c5, c6).
+    subpixel: the same workload with real-valued event coordinates (names
+    get a "/sub" suffix)."""
+    sfx = "/sub" if subpixel else ""
     if config == "c1":
-        return uniform_window(1000 * 1 + index, n_events=n_events or 2000)
+        return uniform_window(1000 * 1 + index, n_events=n_events or 2000, subpixel=subpixel,
+                              name="c1" + sfx)
     if config == "c2":
         return edge_window(1000 * 2 + index, "640x480", n_events or 100_000,
-                           refs=[0.0, 0.5, 1.0], n_segments=50, name="c2")
+                           refs=[0.0, 0.5, 1.0], n_segments=50, name="c2" + sfx,
+                           subpixel=subpixel)
     if config == "c3":
         counts = log_uniform_counts(_rng(1000 * 3 + 999), 64, 5e3, 2e5)
         n = n_events or int(counts[index % 64])
         return edge_window(1000 * 3 + index, "346x260", n, refs=[0.0, 1.0],
-                           n_segments=50, name="c3")
+                           n_segments=50, name="c3" + sfx, subpixel=subpixel)
     if config == "c5":
         return edge_window(1000 * 5 + index, "1280x720", n_events or 2_000_000,
-                           refs=refs_even(8), n_segments=400, name="c5")
+                           refs=refs_even(8), n_segments=400, name="c5" + sfx,
+                           subpixel=subpixel)
     if config == "c6":
-        return bins_window(index)
+        return bins_window(index, subpixel=subpixel).replace(name="c6" + sfx)
     raise ValueError(f"unknown config {config!r}")
 
 
-def make_batch(config: str = "c3", n_windows: int = 64, scale: float = 1.0) -> List[Window]:
+def make_batch(config: str = "c3", n_windows: int = 64, scale: float = 1.0,
+               subpixel: bool = False) -> List[Window]:
     """Workload c3 (or c6): n_windows windows with log-uniform event counts
     (optionally scaled)."""
     if config == "c6":
-        return [bins_window(i) for i in range(n_windows)]
+        return [make_window("c6", i, subpixel=subpixel) for i in range(n_windows)]
     counts = log_uniform_counts(_rng(1000 * 3 + 999), 64, 5e3, 2e5)
     out = []
     for i in range(n_windows):
         n = max(1, int(round(counts[i % 64] * scale)))
-        out.append(make_window(config, i, n_events=n))
+        out.append(make_window(config, i, n_events=n, subpixel=subpixel))
     return out
 
 

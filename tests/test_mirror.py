@@ -10,10 +10,21 @@ import oracle
 from tests.helpers import assert_grads_close, assert_loss_close
 
 
-@pytest.mark.parametrize("case", ["c1", "edge3", "edge8", "ragged"])
+@pytest.mark.parametrize("case", ["c1", "edge3", "edge8", "ragged", "c1/sub", "edge3/sub",
+                                  "edge3 eps=0.25", "c1/sub eps=1e-3"])
 def test_mirror_agrees_with_oracle(case):
     if case == "c1":
         win = eventgen.make_window("c1")
+    elif case == "c1/sub":
+        win = eventgen.make_window("c1", subpixel=True)
+    elif case == "edge3/sub":
+        win = eventgen.edge_window(31, "346x260", 6000, refs=[0.0, 0.5, 1.0], n_segments=20,
+                                   subpixel=True)
+    elif case == "edge3 eps=0.25":
+        win = eventgen.edge_window(31, "346x260", 6000, refs=[0.0, 0.5, 1.0],
+                                   n_segments=20).replace(eps=0.25)
+    elif case == "c1/sub eps=1e-3":
+        win = eventgen.make_window("c1", subpixel=True).replace(eps=1e-3)
     elif case == "edge3":
         win = eventgen.edge_window(31, "346x260", 6000, refs=[0.0, 0.5, 1.0], n_segments=20)
     elif case == "edge8":

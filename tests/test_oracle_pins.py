@@ -350,7 +350,7 @@ def test_depth_scale_invariance_and_gradient_identity():
 # tap distribution or the chain through Eq. 2.
 # ---------------------------------------------------------------------------
 
-def _fd_window(seed, refs, n=40, W=16, H=14, f=12.0):
+def _fd_window(seed, refs, n=40, W=16, H=14, f=12.0, eps=1e-9):
     """Real-valued events, seeded; re-drawn until no visited position lies within
     1e-3 px of a tap boundary or the image border (the loss is smooth there)."""
     for s in range(seed, seed + 200):
@@ -363,7 +363,7 @@ def _fd_window(seed, refs, n=40, W=16, H=14, f=12.0):
         rho = 0.7 + 0.5 * np.exp(-((xs - rng.uniform(0, W)) ** 2 + (ys - rng.uniform(0, H)) ** 2)
                                  / 20.0)
         theta = rng.normal(0, 0.12, 6)
-        win = mkwin(W, H, f, refs, x, y, t, p, rho, theta)
+        win = mkwin(W, H, f, refs, x, y, t, p, rho, theta, eps=eps)
         res = oracle.forward(win, positions=True, valid=True)
         if res["valid"].sum() < n // 2:
             continue
@@ -438,3 +438,100 @@ def test_single_ref_depth_gradient_support_is_event_pixels():
     support[y[ok].astype(int), x[ok].astype(int)] = True
     assert not g["drho"][~support].any()
     assert np.count_nonzero(g["drho"]) > 0
+
+
+# ---------------------------------------------------------------------------
+# Eq. 1's regulariser (Sec. 3.1): where eps sits.  The paper gives no value;
+# the reading is eps in the per-pixel ratio S/(C+eps) and in the active-pixel
+# normaliser N_r+eps.  At eps = 1e-9 a misplaced eps moves the loss by less
+# than 1e-8 relative, so these pins take eps = 0.25 (loss) and 0.05 (gradient),
+# where every placement gives a visibly different number.
+# Catches: eps dropped from N_r, eps dropped from (or added outside) the
+# ratio, (C+eps)^2 or (C+eps)^3 written as C^2 / C^3 in the adjoint seeds.
+# ---------------------------------------------------------------------------
+
+def _static_eps(x, y, t, p, eps, refs=REFS3, W=40, H=30):
+    return mkwin(W, H, 10.0, refs, x, y, t, p, np.ones((H, W)), np.zeros(6), eps=eps)
+
+
+def _bilinear_weights(X, Y):
+    a, b = X - math.floor(X), Y - math.floor(Y)
+    return np.array([(1 - a) * (1 - b), a * (1 - b), (1 - a) * b, a * b])
+
+
+def test_eps_single_event_closed_form():
+    eps = 0.25
+    X, Y, tk = 10.3, 20.6, 0.25
+    w = _bilinear_weights(X, Y)
+    res = oracle.forward(_static_eps([X], [Y], [tk], [1], eps))
+    assert list(res["nact"]) == [4.0, 4.0, 4.0]
+    per_ref = []
+    for r in REFS3:
+        tb = tbar(r, tk)
+        per_ref.append(np.sum((tb * w / (w + eps)) ** 2) / (4.0 + eps))
+        # the numerator alone: sum over the four taps of (tbar w / (w + eps))^2
+    np.testing.assert_allclose(res["num"], [np.sum((tbar(r, tk) * w / (w + eps)) ** 2)
+                                            for r in REFS3], rtol=1e-13)
+    assert res["loss"] == pytest.approx(np.mean(per_ref), rel=1e-13)
+    # on an integer pixel: one active pixel, weight 1
+    res = oracle.forward(_static_eps([7.0], [3.0], [0.75], [-1], eps))
+    assert list(res["nact"]) == [1.0, 1.0, 1.0]
+    expect = np.mean([(tbar(r, 0.75) / (1.0 + eps)) ** 2 / (1.0 + eps) for r in REFS3])
+    assert res["loss"] == pytest.approx(expect, rel=1e-13)
+
+
+def test_eps_two_coincident_events_closed_form():
+    eps = 0.25
+    X, Y, t1, t2 = 10.3, 20.6, 0.1, 0.7
+    w = _bilinear_weights(X, Y)
+    same = oracle.loss(_static_eps([X, X], [Y, Y], [t1, t2], [1, 1], eps))
+    expect = np.mean([np.sum((w * (tbar(r, t1) + tbar(r, t2)) / (2 * w + eps)) ** 2) / (4 + eps)
+                      for r in REFS3])
+    assert same == pytest.approx(expect, rel=1e-13)
+    opp = oracle.loss(_static_eps([X, X], [Y, Y], [t1, t2], [1, -1], eps))
+    expect = np.mean([np.sum((tbar(r, t1) * w / (w + eps)) ** 2
+                             + (tbar(r, t2) * w / (w + eps)) ** 2) / (4 + eps) for r in REFS3])
+    assert opp == pytest.approx(expect, rel=1e-13)
+
+
+def test_eps_moves_the_loss_as_the_reading_says():
+    # the same window at eps = 1e-9 and 0.25: the loss follows the closed form
+    # at both, and the two differ by far more than rounding
+    X, Y, tk = 10.3, 20.6, 0.25
+    w = _bilinear_weights(X, Y)
+    for eps in (1e-9, 1e-3, 0.25, 2.0):
+        e = float(np.float32(eps))       # the descriptor holds eps in FP32
+        L = oracle.loss(_static_eps([X], [Y], [tk], [1], eps))
+        expect = np.mean([np.sum((tbar(r, tk) * w / (w + e)) ** 2) / (4 + e) for r in REFS3])
+        assert L == pytest.approx(expect, rel=1e-12)
+
+
+@pytest.mark.parametrize("refs", [[0.0, 0.4, 1.0], [0.1, 0.3, 0.55, 0.6, 0.9]])
+def test_eps_gradient_matches_central_differences(refs):
+    # with a large eps the seeds' (C+eps)^2 and (C+eps)^3 differ from C^2, C^3
+    # by ~10 % at the typical C of these windows
+    win = _fd_window(500 + len(refs), refs, eps=0.05)
+    g = oracle.backward(win, grad_loss=1.0)
+    h = 1e-6
+
+    def L(rho=None, theta=None):
+        return oracle.loss(win, rho=rho, theta=theta)
+
+    fd_th = np.zeros(6)
+    for k in range(6):
+        tp = win.theta.copy(); tp[k] += h
+        tm = win.theta.copy(); tm[k] -= h
+        fd_th[k] = (L(theta=tp) - L(theta=tm)) / (2 * h)
+    scale_th = np.abs(fd_th).max()
+    assert scale_th > 1e-4
+    np.testing.assert_allclose(g["dtheta"], fd_th, atol=1e-6 * scale_th)
+
+    fd_rho = np.zeros_like(win.rho)
+    for j in range(win.height):
+        for i in range(win.width):
+            rp = win.rho.copy(); rp[j, i] += h
+            rm = win.rho.copy(); rm[j, i] -= h
+            fd_rho[j, i] = (L(rho=rp) - L(rho=rm)) / (2 * h)
+    scale = np.abs(fd_rho).max()
+    assert scale > 1e-5
+    np.testing.assert_allclose(g["drho"], fd_rho, atol=1e-6 * scale)
