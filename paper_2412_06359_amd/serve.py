@@ -3,7 +3,7 @@
 Windows arrive one by one (as in on-device online learning, where every
 freshly accumulated window is a training sample).  A scheduler thread keeps up
 to `n_streams` batches in flight: whenever a stream is free it admits the
-queued windows in arrival order while their HBM footprint fits the budget,
+queued windows in arrival order while their device memory fits the budget,
 packs them into one batched forward + backward (cm_loss_forward_batched /
 cm_loss_backward_batched) on that stream, and retires finished batches by
 polling their completion events.  Requests that arrive while others run are
@@ -11,12 +11,29 @@ admitted as soon as a stream and memory free up, so batches overlap on the
 device.  Each request's Future resolves to its loss (on the host) and its
 gradients (on the device).
 
-Footprint of a window (bytes): its share of the batch state (splat images
-32 R H W, header, tiled workspace: the single-window state size), the events
-(13 N), inverse depth and its gradient (8 F H W for F flow sets) and the small
-per-window vectors; the admitted batches' footprints never sum above the
-budget.  A
-window larger than the whole budget is refused with CM_ERR_BUDGET.
+Memory.  The budget bounds the device memory allocated through torch's
+allocator on the server's device since the server started (torch's
+memory_allocated above its value at start): the stream slots' workspaces
+(inputs, batch state, loss), the gradient buffers of batches in flight and the
+gradients of delivered results the client still holds.  A batch is admitted
+only if that figure plus what the batch will allocate stays within the budget
+(a slot workspace too small for the batch is freed first and reallocated at
+the batch's exact size).  If the head of the queue cannot fit while nothing is
+in flight (held results and workspaces fill the budget), it fails with
+CM_ERR_BUDGET instead of waiting forever; a window larger than the whole
+budget is refused on submission.
+
+Streams.  Delivered gradients are complete when the Future resolves.  They
+were written on a server stream; the server records their use on the stream
+that was current in the submitting thread, so the caching allocator does not
+hand their memory to a later batch while work the client queued on that
+stream may still read them.  A client that reads them on another stream must
+call record_stream for it.
+
+Shutdown and failures.  close() lets the scheduler finish every submitted
+request (queued and in flight) before it stops.  If the scheduler itself fails,
+every request it has not resolved (queued or in flight) fails with the same
+exception, and later submissions raise.
 """
 
 from __future__ import annotations
@@ -25,7 +42,7 @@ import collections
 import threading
 import time
 from concurrent.futures import Future
-from typing import List, Optional
+from typing import List
 
 import numpy as np
 import torch
@@ -36,41 +53,57 @@ from .binding import CMError, WindowDesc
 CM_ERR_BUDGET = -5
 
 
-class Request:
-    __slots__ = ("window", "desc", "n", "footprint", "future", "t_arrival")
+def _align(n: int) -> int:
+    return (n + 255) // 256 * 256
 
-    def __init__(self, window, desc, footprint):
+
+def window_footprint(desc: WindowDesc, n_events: int) -> int:
+    """Device bytes a batch of this window alone allocates: its workspace
+    (events 13 N, inverse depth 4 F H W, ego, the single-window state, loss
+    and grad_loss, each 256-byte aligned) and its gradients (4 F H W + 24 F).
+    A batch of several windows needs about the sum of theirs."""
+    hw = desc.width * desc.height
+    F = desc.F
+    ws = (3 * _align(4 * n_events) + _align(n_events) + _align(4 * F * hw) + _align(24 * F)
+          + _align(binding.state_bytes(desc, n_events)) + 2 * 256)
+    return ws + _align(4 * F * hw) + _align(24 * F)
+
+
+class Request:
+    __slots__ = ("window", "desc", "n", "footprint", "future", "t_arrival", "stream")
+
+    def __init__(self, window, desc, footprint, stream):
         self.window = window
         self.desc = desc
         self.n = int(window.n)
         self.footprint = footprint
         self.future = Future()
         self.t_arrival = time.perf_counter()
-
-
-def window_footprint(desc: WindowDesc, n_events: int) -> int:
-    hw = desc.width * desc.height
-    return binding.state_bytes(desc, n_events) + 13 * n_events + 8 * hw * desc.F + 48 * desc.F + 16
+        self.stream = stream        # the client's current stream at submission
 
 
 class _Staging:
-    """A stream slot's pinned host buffer, reused from batch to batch and grown
-    when a batch needs more (allocating pinned memory per batch costs
-    milliseconds, which showed up in the tail latency).  A slot's buffer is
-    refilled only after its previous batch has retired, so its copies are
-    complete."""
+    """A stream slot's pinned host buffer (reused from batch to batch, grown
+    when a batch needs more: allocating pinned memory per batch costs
+    milliseconds) and its device workspace (inputs, state, loss, grad_loss of
+    its batch; sized exactly, reallocated when a batch needs more).  A slot is
+    refilled only after its previous batch has retired."""
 
     def __init__(self):
         self.buf = None
         self.loss = None
         self.dev = None
 
+    def device_bytes(self) -> int:
+        return 0 if self.dev is None else self.dev.numel()
+
+    def release_device(self):
+        self.dev = None
+
     def device_buffer(self, nbytes, device):
-        """The slot's device workspace (inputs and state of its batch: the
-        caller gets only the gradients, which are allocated per batch)."""
         if self.dev is None or self.dev.numel() < nbytes:
-            cap = max(nbytes, 2 * (self.dev.numel() if self.dev is not None else 0))
-            self.dev = torch.empty(cap, dtype=torch.uint8, device=device)
+            self.dev = None                     # freed before the larger one is allocated
+            self.dev = torch.empty(nbytes, dtype=torch.uint8, device=device)
         return self.dev
 
     def arrays(self, spec):
@@ -98,14 +131,27 @@ class _Staging:
 
 
 class _InFlight:
-    def __init__(self, reqs, batch, stream, event, keep, loss_host, footprint):
+    def __init__(self, reqs, batch, stream, event, keep, loss_host):
         self.reqs = reqs
         self.batch = batch
         self.stream = stream
         self.event = event
         self.keep = keep
         self.loss_host = loss_host
-        self.footprint = footprint
+
+
+def _workspace_sizes(batch, tv) -> List[int]:
+    return [v.numel() * v.element_size() for v in tv.values()] + \
+        [batch.state_bytes, 4 * batch.n, 4 * batch.n]
+
+
+def _batch_need(batch) -> tuple:
+    """(workspace bytes, gradient bytes) a batch allocates on the device."""
+    n = batch.event_offsets[-1]
+    ins = [4 * n, 4 * n, 4 * n, n, 4 * batch.pixel_offsets[-1], 24 * batch.set_offsets[-1]]
+    ws = sum(_align(b) for b in ins + [batch.state_bytes, 4 * batch.n, 4 * batch.n])
+    grads = _align(4 * batch.pixel_offsets[-1]) + _align(24 * batch.set_offsets[-1])
+    return ws, grads
 
 
 class Server:
@@ -124,8 +170,8 @@ class Server:
         self._streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
         self._staging = [_Staging() for _ in range(n_streams)]
         self._busy = [None] * n_streams
-        self._used = 0
-        self._running = True
+        self._closing = False
+        self._failed = None
         self.latencies: List[float] = []
         self.events_done = 0
         self.windows_done = 0
@@ -133,14 +179,26 @@ class Server:
         self.max_used = 0
         self.t_first = None
         self.t_last = None
+        torch.cuda.synchronize(device)
+        self._base = torch.cuda.memory_allocated(device)
+        torch.cuda.reset_peak_memory_stats(device)
         self._thread = threading.Thread(target=self._loop, name="cm-server", daemon=True)
         self._thread.start()
 
     # -- client side ------------------------------------------------------
+    def used_bytes(self) -> int:
+        """Device memory allocated on the server's device since the server
+        started (what the budget bounds)."""
+        return torch.cuda.memory_allocated(self.device) - self._base
+
     def submit(self, window) -> Future:
+        if self._failed is not None:
+            raise RuntimeError("the server's scheduler failed") from self._failed
+        if self._closing:
+            raise RuntimeError("the server is closed")
         desc = WindowDesc.from_window(window, mode=self.mode)
         fp = window_footprint(desc, window.n)
-        req = Request(window, desc, fp)
+        req = Request(window, desc, fp, torch.cuda.current_stream(self.device))
         if fp > self.budget:
             req.future.set_exception(CMError(CM_ERR_BUDGET, "window footprint exceeds the budget"))
             return req.future
@@ -149,14 +207,19 @@ class Server:
         self._wake.set()
         return req.future
 
-    def close(self):
-        self._running = False
+    def close(self, timeout: float = 120.0):
+        """Finish every submitted request, then stop the scheduler."""
+        self._closing = True
         self._wake.set()
-        self._thread.join()
+        self._thread.join(timeout)
+        if self._thread.is_alive():
+            raise TimeoutError("server did not finish its requests")
 
     def drain(self, timeout: float = 60.0):
         t0 = time.perf_counter()
         while time.perf_counter() - t0 < timeout:
+            if self._failed is not None:
+                raise RuntimeError("the server's scheduler failed") from self._failed
             with self._lock:
                 idle = not self._queue and all(b is None for b in self._busy)
             if idle:
@@ -171,11 +234,13 @@ class Server:
             "windows": self.windows_done,
             "events": self.events_done,
             "batches": self.batches,
+            "windows_per_batch": self.windows_done / self.batches if self.batches else None,
             "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
             "mean_ms": float(lat.mean()) if lat.size else None,
             "events_per_s": self.events_done / span if span > 0 else None,
             "max_used_bytes": self.max_used,
+            "peak_allocated_bytes": torch.cuda.max_memory_allocated(self.device) - self._base,
             "budget_bytes": self.budget,
         }
 
@@ -183,20 +248,32 @@ class Server:
     def _loop(self):
         torch.cuda.set_device(self.device)
         try:
-            while self._running:
+            while True:
                 progressed = self._retire()
                 progressed |= self._admit()
+                if self._closing:
+                    with self._lock:
+                        idle = not self._queue and all(b is None for b in self._busy)
+                    if idle:
+                        return
                 if not progressed:
                     self._wake.wait(self.poll_s)
                     self._wake.clear()
-        except Exception as exc:       # fail every pending request loudly
+        except BaseException as exc:       # fail every unresolved request loudly
+            self._failed = exc
             with self._lock:
                 pending = list(self._queue)
                 self._queue.clear()
+            for fl in self._busy:
+                if fl is not None:
+                    pending.extend(fl.reqs)
             for r in pending:
                 if not r.future.done():
                     r.future.set_exception(exc)
             raise
+
+    def _note_usage(self):
+        self.max_used = max(self.max_used, self.used_bytes())
 
     def _retire(self) -> bool:
         done_any = False
@@ -206,7 +283,13 @@ class Server:
             t = time.perf_counter()
             loss = fl.loss_host.numpy()
             g_rho, g_ego = fl.keep["g_rho"], fl.keep["g_ego"]
+            # the client's streams may read the gradients from now on
+            for s in {r.stream for r in fl.reqs}:
+                g_rho.record_stream(s)
+                g_ego.record_stream(s)
             offs, sets = fl.batch.pixel_offsets, fl.batch.set_offsets
+            self._busy[i] = None
+            fl.batch.close()
             for w, r in enumerate(fl.reqs):
                 lead = (r.desc.F,) if r.desc.F > 1 else ()
                 res = {"loss": float(loss[w]),
@@ -219,47 +302,91 @@ class Server:
                 self.windows_done += 1
                 r.future.set_result(res)
             self.t_last = t
-            with self._lock:
-                self._used -= fl.footprint
-            fl.batch.close()
-            self._busy[i] = None
             done_any = True
         return done_any
+
+    def _reclaimable(self, slot) -> int:
+        """Bytes of idle slot workspaces (slots with no batch in flight,
+        `slot` included) that can be freed."""
+        return sum(st.device_bytes() for j, st in enumerate(self._staging)
+                   if j == slot or self._busy[j] is None)
+
+    def _fits(self, slot, ws, grads) -> bool:
+        """Whether a batch needing `ws` workspace and `grads` gradient bytes
+        fits on `slot`.  Frees idle workspaces when that makes the difference:
+        first the other free slots', then the slot's own (a workspace larger
+        than this batch needs, kept from an earlier batch; it is then
+        reallocated at the exact size)."""
+        own = self._staging[slot]
+        extra = max(0, ws - own.device_bytes())
+        if self.used_bytes() + extra + grads <= self.budget:
+            return True
+        for j, st in enumerate(self._staging):
+            if j != slot and self._busy[j] is None and st.device_bytes():
+                st.release_device()
+        if self.used_bytes() + extra + grads <= self.budget:
+            return True
+        own.release_device()
+        return self.used_bytes() + ws + grads <= self.budget
+
+    def _plan(self, slot):
+        """Requests of the next batch for `slot` (removed from the queue) and
+        their plan, or (None, None).  Greedy in arrival order by footprint
+        estimate, then checked against the plan's exact sizes."""
+        with self._lock:
+            avail = self.budget - self.used_bytes() + self._reclaimable(slot)
+            reqs, fp = [], 0
+            for r in self._queue:
+                if len(reqs) >= self.max_batch or fp + r.footprint > avail:
+                    break
+                reqs.append(r)
+                fp += r.footprint
+        while reqs:
+            batch = binding.Batch([r.desc for r in reqs], [r.n for r in reqs],
+                                  device=self.device)
+            if self._fits(slot, *_batch_need(batch)):
+                with self._lock:
+                    for _ in reqs:
+                        self._queue.popleft()
+                return reqs, batch
+            batch.close()
+            reqs.pop()
+        if all(b is None for b in self._busy):
+            # Nothing in flight will free memory: the budget is held by
+            # results the client keeps.  Fail the head instead of waiting.
+            with self._lock:
+                head = self._queue.popleft() if self._queue else None
+            if head is not None:
+                head.future.set_exception(CMError(
+                    CM_ERR_BUDGET, "device memory budget exhausted (results held by the client)"))
+        return None, None
 
     def _admit(self) -> bool:
         try:
             slot = self._busy.index(None)
         except ValueError:
             return False
-        with self._lock:
-            reqs = []
-            fp = 0
-            while self._queue and len(reqs) < self.max_batch:
-                r = self._queue[0]
-                if self._used + fp + r.footprint > self.budget:
-                    break
-                reqs.append(self._queue.popleft())
-                fp += r.footprint
-            self._used += fp
-            self.max_used = max(self.max_used, self._used)
+        if not self._queue:
+            return False
+        reqs, batch = self._plan(slot)
         if not reqs:
             return False
         if self.t_first is None:
             self.t_first = min(r.t_arrival for r in reqs)
         try:
-            self._busy[slot] = self._launch(reqs, self._streams[slot], self._staging[slot], fp)
+            self._busy[slot] = self._launch(reqs, batch, self._streams[slot],
+                                            self._staging[slot])
         except Exception as exc:       # these requests fail; the server keeps serving
-            with self._lock:
-                self._used -= fp
+            batch.close()
             for r in reqs:
                 r.future.set_exception(exc)
             return True
+        self._note_usage()
         self.batches += 1
         return True
 
-    def _launch(self, reqs, stream, staging, fp) -> _InFlight:
+    def _launch(self, reqs, batch, stream, staging) -> _InFlight:
         wins = [r.window for r in reqs]
-        batch = binding.Batch([r.desc for r in reqs], [r.n for r in reqs], device=self.device)
         dev = torch.device("cuda", self.device)
         n = batch.event_offsets[-1]
         spec = [("x", np.float32, n), ("y", np.float32, n), ("t", np.float32, n),
@@ -273,12 +400,11 @@ class Server:
                            out=host[name])
         with torch.cuda.stream(stream):
             # one device workspace per slot: inputs, state, loss, grad_loss
-            sizes = [v.numel() * v.element_size() for v in tv.values()] + \
-                [batch.state_bytes, 4 * batch.n, 4 * batch.n]
+            sizes = _workspace_sizes(batch, tv)
             offs, total = [], 0
             for nb in sizes:
                 offs.append(total)
-                total += (nb + 255) // 256 * 256
+                total += _align(nb)
             dbuf = staging.device_buffer(total, dev)
             d = {}
             for (k, v), o, nb in zip(tv.items(), offs, sizes):
@@ -297,4 +423,4 @@ class Server:
             ev = torch.cuda.Event()
             ev.record(stream)
         keep = dict(d=d, state=state, loss=loss, gl=gl, g_rho=g_rho, g_ego=g_ego)
-        return _InFlight(reqs, batch, stream, ev, keep, loss_host, fp)
+        return _InFlight(reqs, batch, stream, ev, keep, loss_host)

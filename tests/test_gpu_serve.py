@@ -2,6 +2,7 @@
 result alone (bitwise in deterministic mode, within tolerance otherwise), the
 admitted footprint never exceeds the budget, oversize windows are refused."""
 
+import threading
 import time
 
 import numpy as np
@@ -80,19 +81,113 @@ def test_served_equals_alone_atomic(cm):
                                    atol=1e-6 * np.abs(e1).max())
 
 
-def test_budget_is_respected_and_oversize_refused(cm):
-    from paper_2412_06359_amd.serve import window_footprint
+def test_budget_bounds_device_memory_and_oversize_refused(cm):
+    """The budget bounds real device memory: torch's peak allocation while
+    serving (slot workspaces, gradients in flight, results held) stays within
+    it, with the client holding every result until the end."""
+    from paper_2412_06359_amd.serve import Server, window_footprint
     wins = windows(10)
     fps = [window_footprint(cm.WindowDesc.from_window(w), w.n) for w in wins]
     budget = 2 * max(fps) + 1
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
     res, st = serve_all(cm, wins, cm.CM_MODE_ATOMIC, budget=budget, gap_s=0.0)
     assert st["windows"] == len(wins)
     assert 0 < st["max_used_bytes"] <= budget
+    assert 0 < st["peak_allocated_bytes"] <= budget, (st["peak_allocated_bytes"], budget)
+    assert torch.cuda.max_memory_allocated() - base <= budget
     assert st["batches"] >= 3
-    from paper_2412_06359_amd.serve import Server
+    assert st["windows_per_batch"] == len(wins) / st["batches"]
     srv = Server(budget_bytes=max(fps) // 2)
     big = wins[int(np.argmax(fps))]
     with pytest.raises(cm.CMError) as ei:
         srv.submit(big).result(timeout=10)
     assert ei.value.status == -5
     srv.close()
+
+
+def test_held_results_exhaust_the_budget_without_hanging(cm):
+    """Results the client keeps count against the budget; when they fill it
+    and nothing is in flight, the next window fails with CM_ERR_BUDGET instead
+    of waiting forever."""
+    from paper_2412_06359_amd.serve import Server, window_footprint
+    big = eventgen.stream_window("640x480", 20000, 5100)
+    fp = window_footprint(cm.WindowDesc.from_window(big), big.n)
+    srv = Server(budget_bytes=fp + (1 << 20), n_streams=1)
+    held = [srv.submit(big).result(timeout=60)]
+    # one result held (1.2 MB of gradients) plus the idle workspace: a second
+    # window of the same size cannot fit once the workspace is reclaimed
+    held.append(torch.empty(fp, dtype=torch.uint8, device="cuda:0"))   # the client's own use
+    with pytest.raises(cm.CMError) as ei:
+        srv.submit(big).result(timeout=60)
+    assert ei.value.status == -5
+    del held
+    torch.cuda.synchronize()
+    ok = srv.submit(big).result(timeout=60)          # memory freed: served again
+    assert np.isfinite(ok["loss"])
+    srv.close()
+
+
+def test_launch_failure_while_a_batch_is_in_flight(cm):
+    """A launch error (raised from the host) fails only its own batch: the
+    batch already in flight completes, and later requests are served."""
+    from paper_2412_06359_amd.serve import Server
+    wins = windows(3)
+    srv = Server(budget_bytes=8 << 30, n_streams=2, max_batch=1)
+    real = srv._launch
+    calls = {"n": 0}
+
+    def flaky(*a, **k):
+        calls["n"] += 1
+        if calls["n"] == 2:
+            raise RuntimeError("injected launch failure")
+        return real(*a, **k)
+    srv._launch = flaky
+    futs = [srv.submit(w) for w in wins]
+    r0 = futs[0].result(timeout=60)
+    with pytest.raises(RuntimeError, match="injected"):
+        futs[1].result(timeout=60)
+    r2 = futs[2].result(timeout=60)
+    assert np.isfinite(r0["loss"]) and np.isfinite(r2["loss"])
+    srv.close()
+
+
+def test_scheduler_failure_fails_queued_and_in_flight(cm):
+    """If the scheduler itself fails (raised from the host while a batch is in
+    flight and others are queued), every unresolved request fails with that
+    error (none is left pending) and later submissions raise."""
+    from paper_2412_06359_amd.serve import Server
+    wins = windows(6)
+    srv = Server(budget_bytes=8 << 30, n_streams=1, max_batch=1)
+    real_retire, real_admit = srv._retire, srv._admit
+    go = threading.Event()
+
+    def broken():
+        if any(b is not None for b in srv._busy):
+            raise RuntimeError("injected scheduler failure")
+        return real_retire()
+
+    def gated():
+        go.wait(30)                 # admit nothing until every request is queued
+        return real_admit()
+    srv._retire, srv._admit = broken, gated
+    futs = [srv.submit(w) for w in wins]
+    go.set()
+    for f in futs:
+        with pytest.raises(RuntimeError, match="injected"):
+            f.result(timeout=60)
+    with pytest.raises(RuntimeError):
+        srv.submit(wins[0])
+    torch.cuda.synchronize()
+
+
+def test_close_finishes_in_flight_and_queued(cm):
+    from paper_2412_06359_amd.serve import Server
+    wins = windows(8)
+    srv = Server(budget_bytes=8 << 30, n_streams=2, max_batch=2)
+    futs = [srv.submit(w) for w in wins]
+    srv.close()
+    assert all(f.done() for f in futs)
+    assert all(np.isfinite(f.result()["loss"]) for f in futs)
+    with pytest.raises(RuntimeError):
+        srv.submit(wins[0])
