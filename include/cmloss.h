@@ -189,6 +189,27 @@ cm_status cm_loss_backward(cm_handle h, const cm_window_desc* d,
                            void* state, const float* grad_loss,
                            float* grad_inv_depth, float* grad_ego, void* stream);
 
+/* Forward without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments and result as cm_loss_forward, without
+ * `state`: the window's whole forward state lives in a file-scope device array
+ * of the library (CM_NOALLOC_MAX_STATE_BYTES bytes, one per device, held
+ * until the process ends), so the call allocates nothing and no backward can
+ * follow it.  The caller passes the inputs and `loss` (device float32 [1]).
+ * The array is shared by every call on a device and keeps the last call's
+ * contents (the forward clears what it accumulates into): calls that overlap
+ * on one device, on any streams or handles, race and give wrong results.
+ * CM_ERR_BUDGET, with nothing enqueued, if cm_state_bytes(d, n_events)
+ * exceeds CM_NOALLOC_MAX_STATE_BYTES (e.g. 640x480 with 3 references and 100k
+ * events fits; 1280x720 with 8 references does not).  Profiling
+ * (cm_profile_enable) does not record this call. */
+#define CM_NOALLOC_MAX_STATE_BYTES (64u * 1024u * 1024u)
+cm_status cm_loss_forward_noalloc(cm_handle h, const cm_window_desc* d,
+                                  const float* ev_x, const float* ev_y, const float* ev_t,
+                                  const int8_t* ev_p, int64_t n_events,
+                                  const float* inv_depth, const float* ego,
+                                  float* loss, void* stream);
+
 /* Diagnostics of the last forward on `state` (device -> host copy; this call
  * synchronises `stream`).  out[0] = loss (FP64), out[1] = number of valid
  * (unmasked) events, out[2 + r] = numerator of reference r, out[2 + R + r] =

@@ -133,6 +133,8 @@ def load() -> ctypes.CDLL:
         lib.cm_loss_forward.restype = ctypes.c_int
         lib.cm_loss_backward.argtypes = [P, D, P, P, P, P, i64, P, P, P, P, P, P, P]
         lib.cm_loss_backward.restype = ctypes.c_int
+        lib.cm_loss_forward_noalloc.argtypes = [P, D, P, P, P, P, i64, P, P, P, P]
+        lib.cm_loss_forward_noalloc.restype = ctypes.c_int
         lib.cm_state_diagnostics.argtypes = [D, P, P, P]
         lib.cm_state_diagnostics.restype = ctypes.c_int
         lib.cm_batch_create.argtypes = [P, ctypes.c_int32, P, P, ctypes.POINTER(P)]
@@ -276,6 +278,28 @@ def forward(desc: WindowDesc, x, y, t, p, rho, ego, state: Optional[torch.Tensor
                              _stream(dev))
     _check(st, "cm_loss_forward")
     return loss, state
+
+
+NOALLOC_MAX_STATE_BYTES = 64 * 1024 * 1024     # CM_NOALLOC_MAX_STATE_BYTES
+
+
+def forward_noalloc(desc: WindowDesc, x, y, t, p, rho, ego, loss: torch.Tensor):
+    """cm_loss_forward_noalloc on torch's current stream: the loss into `loss`
+    (a float32 [1] GPU tensor the caller owns), with the window's state in the
+    library's own per-device scratch (no allocation; no backward can follow;
+    calls on one device must not overlap).  Raises CMError (CM_ERR_BUDGET) if
+    the window's state exceeds NOALLOC_MAX_STATE_BYTES."""
+    n = _check_events(x, y, t, p)
+    _check_params(desc, rho, ego)
+    if loss.dtype != torch.float32 or loss.numel() < 1 or not loss.is_cuda:
+        raise ValueError("loss: need a float32 GPU tensor of at least 1 element")
+    dev = rho.device
+    lib = load()
+    st = lib.cm_loss_forward_noalloc(handle(dev.index), ctypes.byref(desc), _ptr(x), _ptr(y),
+                                     _ptr(t), _ptr(p), n, _ptr(rho), _ptr(ego), _ptr(loss),
+                                     _stream(dev))
+    _check(st, "cm_loss_forward_noalloc")
+    return loss
 
 
 def backward(desc: WindowDesc, x, y, t, p, rho, ego, state, grad_loss,

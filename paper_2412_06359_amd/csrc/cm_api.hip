@@ -2,6 +2,7 @@
 // state layout, path selection, batch plans and hipGraph replay.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -14,7 +15,43 @@ struct cm_handle_s {
     cm::PlanTuning tune;                    // batch plans' launch shape (atomic mode)
     int64_t tiled_min_records = 1 << 17;    // CM_PATH_AUTO crossover for single windows
     cm::Profiler prof;
+    void* scratch = nullptr;                // this device's address of `scratch` (below)
 };
+
+// Scratch of cm_loss_forward_noalloc: one window's whole forward state
+// (images, sums, reduction partials, metadata, tiled workspace) lives in this
+// file-scope device array, so that call allocates nothing.  Each device the
+// library runs on holds its own copy, at its own address, until the process
+// ends.  Host code never passes the array's name to a kernel or a copy (on
+// the host it is only a stand-in for the device symbol): it uses the address
+// hipGetSymbolAddress returned for the device, kept per device below.
+static __device__ __align__(256) unsigned char scratch[CM_NOALLOC_MAX_STATE_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};  // per-device address of `scratch`, set once
+
+// Looks up (once per device) the device address of `scratch` on `device`,
+// which must be the current device.
+hipError_t scratch_address(int device, void** out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+}  // namespace
 
 namespace {
 
@@ -254,10 +291,17 @@ cm_status cm_create(cm_handle* h, int device)
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess) return CM_ERR_HIP;
     if (device < 0 || device >= count) return CM_ERR_INVALID_ARG;
+    void* scratch_ptr = nullptr;
+    {
+        DeviceGuard g(device);
+        if (!g.ok()) return CM_ERR_HIP;
+        if (scratch_address(device, &scratch_ptr) != hipSuccess) return CM_ERR_HIP;
+    }
     cm_handle_s* hs = new (std::nothrow) cm_handle_s();
     if (!hs) return CM_ERR_OOM;
     hs->device = device;
     hs->path = CM_PATH_AUTO;
+    hs->scratch = scratch_ptr;
     *h = hs;
     return CM_OK;
 }
@@ -316,24 +360,21 @@ cm_status cm_get_tuning(cm_handle h, cm_tuning* out)
     return CM_OK;
 }
 
-cm_status cm_loss_forward(cm_handle h, const cm_window_desc* d, const float* ev_x,
-                          const float* ev_y, const float* ev_t, const int8_t* ev_p,
-                          int64_t n_events, const float* inv_depth, const float* ego, float* loss,
-                          void* state, void* stream)
+}  // extern "C"
+
+namespace {
+
+// The forward of one window on `state` (a caller buffer, or this device's
+// `scratch`), with arguments already validated and L = layout_of(d, n).
+cm_status forward_on_state(cm_handle h, const cm_window_desc* d, const Layout& L,
+                           const float* ev_x, const float* ev_y, const float* ev_t,
+                           const int8_t* ev_p, int64_t n_events, const float* inv_depth,
+                           const float* ego, float* loss, void* state, hipStream_t s,
+                           cm::Profiler* prof)
 {
-    if (!h || !desc_valid(d) || !events_valid(ev_x, ev_y, ev_t, ev_p, n_events) || !inv_depth ||
-        !ego || !loss || !state)
-        return CM_ERR_INVALID_ARG;
-    const Layout L = layout_of(d, n_events);
     const WinParams P = params_of(d);
-    if ((h->path == CM_PATH_TILED || d->mode == CM_MODE_DETERMINISTIC) && !L.tiled && n_events > 0)
-        return CM_ERR_UNSUPPORTED;
-    DeviceGuard g(h->device);
-    if (!g.ok()) return CM_ERR_HIP;
     const cm::EventPtrs ev{ev_x, ev_y, ev_t, ev_p, n_events};
     const StatePtrs sp = state_ptrs(L, state);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    cm::Profiler* prof = h->prof.enabled ? &h->prof : nullptr;
     if (!choose_tiled(h, d, L, P, n_events))
         return status_of(cm::launch_forward(P, ev, inv_depth, ego, loss, sp, s, prof));
     char* base = static_cast<char*>(state);
@@ -345,6 +386,48 @@ cm_status cm_loss_forward(cm_handle h, const cm_window_desc* d, const float* ev_
     return status_of(cm::launch_forward_batch(B, meta, ev, inv_depth, ego, loss,
                                               reinterpret_cast<double2*>(sp.img), sp.hdr,
                                               base + L.ws_off, s, prof));
+}
+
+}  // namespace
+
+extern "C" {
+
+cm_status cm_loss_forward(cm_handle h, const cm_window_desc* d, const float* ev_x,
+                          const float* ev_y, const float* ev_t, const int8_t* ev_p,
+                          int64_t n_events, const float* inv_depth, const float* ego, float* loss,
+                          void* state, void* stream)
+{
+    if (!h || !desc_valid(d) || !events_valid(ev_x, ev_y, ev_t, ev_p, n_events) || !inv_depth ||
+        !ego || !loss || !state)
+        return CM_ERR_INVALID_ARG;
+    const Layout L = layout_of(d, n_events);
+    if ((h->path == CM_PATH_TILED || d->mode == CM_MODE_DETERMINISTIC) && !L.tiled && n_events > 0)
+        return CM_ERR_UNSUPPORTED;
+    DeviceGuard g(h->device);
+    if (!g.ok()) return CM_ERR_HIP;
+    return forward_on_state(h, d, L, ev_x, ev_y, ev_t, ev_p, n_events, inv_depth, ego, loss,
+                            state, static_cast<hipStream_t>(stream),
+                            h->prof.enabled ? &h->prof : nullptr);
+}
+
+cm_status cm_loss_forward_noalloc(cm_handle h, const cm_window_desc* d, const float* ev_x,
+                                  const float* ev_y, const float* ev_t, const int8_t* ev_p,
+                                  int64_t n_events, const float* inv_depth, const float* ego,
+                                  float* loss, void* stream)
+{
+    if (!h || !desc_valid(d) || !events_valid(ev_x, ev_y, ev_t, ev_p, n_events) || !inv_depth ||
+        !ego || !loss)
+        return CM_ERR_INVALID_ARG;
+    const Layout L = layout_of(d, n_events);
+    if (L.total > (size_t)CM_NOALLOC_MAX_STATE_BYTES) return CM_ERR_BUDGET;
+    if ((h->path == CM_PATH_TILED || d->mode == CM_MODE_DETERMINISTIC) && !L.tiled && n_events > 0)
+        return CM_ERR_UNSUPPORTED;
+    if (!h->scratch) return CM_ERR_HIP;
+    DeviceGuard g(h->device);
+    if (!g.ok()) return CM_ERR_HIP;
+    // No profiler: recording its events could create some.
+    return forward_on_state(h, d, L, ev_x, ev_y, ev_t, ev_p, n_events, inv_depth, ego, loss,
+                            h->scratch, static_cast<hipStream_t>(stream), nullptr);
 }
 
 cm_status cm_loss_backward(cm_handle h, const cm_window_desc* d, const float* ev_x,
