@@ -486,14 +486,17 @@ __device__ __forceinline__ int window_of_bbin(const WinMeta* meta, int nw, int64
     return find_window(meta, nw, gbb, [](const WinMeta& m) { return m.bbin_off; });
 }
 
-// The window of every event block, forward bin and backward bin of the
-// batch, one binary search per entry per call instead of one chain of
-// dependent loads at the start of every workgroup.
-// tab = [blocks | forward bins | backward bins].
-// Per-call preparation, one launch: the window of every event block, bin and
-// backward bin; (one thread per window) the first-order motion coefficients
-// of every flow set; cleared per-window headers (hdrs, forward only); zeroed
-// chunk sums.
+// Per-call preparation, one launch: the window of every event block, forward
+// bin and backward bin of the batch (one binary search per entry per call
+// instead of a chain of dependent loads at the start of every workgroup), the
+// forward bins' records; (one thread per window) the first-order motion
+// coefficients of every flow set and cleared per-window headers (hdrs,
+// forward only); zeroed chunk sums.
+// tab = [blocks | forward bins | backward bins].  Each block first copies the
+// windows' first block, bin and backward bin into LDS (batches of up to
+// kTableLdsWindows windows; larger ones search the metadata in memory), so
+// that a search costs one global load instead of one per step.
+constexpr int kTableLdsWindows = 512;
 __global__ __launch_bounds__(256) void window_table_kernel(const WinMeta* __restrict__ meta,
                                                            int nw, int64_t nblk, int64_t nbin,
                                                            int64_t nbb, int* __restrict__ tab,
@@ -503,14 +506,39 @@ __global__ __launch_bounds__(256) void window_table_kernel(const WinMeta* __rest
                                                            uint32_t* __restrict__ csum,
                                                            int64_t ncsum, TileBin* __restrict__ tbin)
 {
+    __shared__ int64_t first[3][kTableLdsWindows];
+    const bool lds = nw <= kTableLdsWindows;
+    if (lds) {
+        for (int w = threadIdx.x; w < nw; w += blockDim.x) {
+            first[0][w] = meta[w].blk_off;
+            first[1][w] = meta[w].bin_off;
+            first[2][w] = meta[w].bbin_off;
+        }
+        __syncthreads();
+    }
+    // largest w with first[kind][w] <= key
+    auto search = [&](int kind, int64_t key) {
+        if (!lds) {
+            if (kind == 0) return window_of_block(meta, nw, key);
+            if (kind == 1) return window_of_bin(meta, nw, key);
+            return window_of_bbin(meta, nw, key);
+        }
+        int lo = 0, hi = nw - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (first[kind][mid] <= key) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    };
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nblk) {
-        tab[i] = window_of_block(meta, nw, i);
+        tab[i] = search(0, i);
         return;
     }
     i -= nblk;
     if (i < nbin) {
-        const int w = window_of_bin(meta, nw, i);
+        const int w = search(1, i);
         tab[nblk + i] = w;
         const WinParams& P = meta[w].P;
         int r, tx, ty;
@@ -530,7 +558,7 @@ __global__ __launch_bounds__(256) void window_table_kernel(const WinMeta* __rest
     }
     i -= nbin;
     if (i < nbb) {
-        tab[nblk + nbin + i] = window_of_bbin(meta, nw, i);
+        tab[nblk + nbin + i] = search(2, i);
         return;
     }
     i -= nbb;
