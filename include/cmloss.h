@@ -203,7 +203,7 @@ cm_status cm_loss_backward(cm_handle h, const cm_window_desc* d,
  * exceeds CM_NOALLOC_MAX_STATE_BYTES (e.g. 640x480 with 3 references and 100k
  * events fits; 1280x720 with 8 references does not).  Profiling
  * (cm_profile_enable) does not record this call. */
-#define CM_NOALLOC_MAX_STATE_BYTES (64u * 1024u * 1024u)
+#define CM_NOALLOC_MAX_STATE_BYTES (128u * 1024u * 1024u)
 cm_status cm_loss_forward_noalloc(cm_handle h, const cm_window_desc* d,
                                   const float* ev_x, const float* ev_y, const float* ev_t,
                                   const int8_t* ev_p, int64_t n_events,

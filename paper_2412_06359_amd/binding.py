@@ -280,7 +280,7 @@ def forward(desc: WindowDesc, x, y, t, p, rho, ego, state: Optional[torch.Tensor
     return loss, state
 
 
-NOALLOC_MAX_STATE_BYTES = 64 * 1024 * 1024     # CM_NOALLOC_MAX_STATE_BYTES
+NOALLOC_MAX_STATE_BYTES = 128 * 1024 * 1024    # CM_NOALLOC_MAX_STATE_BYTES
 
 
 def forward_noalloc(desc: WindowDesc, x, y, t, p, rho, ego, loss: torch.Tensor):

@@ -151,7 +151,7 @@ Layout layout_of(const cm_window_desc* d, int64_t n)
     L.meta_off = L.scratch_off + align_up(cm::scratch_doubles(flows_of(d)) * sizeof(double), kAlign);
     L.ws_off = L.meta_off + align_up(sizeof(WinMeta), kAlign);
     const WinParams P = params_of(d);
-    L.tiled = n > 0 && cm::tiled_supported(P, n);
+    L.tiled = n > 0 && cm::tiled_supported(P, n, d->mode == CM_MODE_DETERMINISTIC);
     L.total = L.ws_off +
               (L.tiled ? cm::plan_batch(&P, &n, 1, d->mode == CM_MODE_DETERMINISTIC).ws.total : 0);
     return L;
@@ -516,10 +516,13 @@ cm_status cm_batch_create(cm_handle h, int32_t n_windows, const cm_window_desc* 
         if (descs[w].mode != descs[0].mode) return CM_ERR_INVALID_ARG;
         if (descs[w].flow_model != descs[0].flow_model) return CM_ERR_INVALID_ARG;
         params[w] = params_of(&descs[w]);
-        if (!cm::tiled_supported(params[w], n_events[w])) return CM_ERR_UNSUPPORTED;
-        total_records += n_events[w] * (int64_t)params[w].R;
+        if (!cm::tiled_supported(params[w], n_events[w], descs[0].mode == CM_MODE_DETERMINISTIC))
+            return CM_ERR_UNSUPPORTED;
+        total_records += n_events[w] * (int64_t)(params[w].R + 1);
     }
-    if (total_records >= ((int64_t)1 << 31)) return CM_ERR_UNSUPPORTED;
+    // record slots are 32-bit; the atomic mode reserves up to four per position
+    if (total_records * (descs[0].mode == CM_MODE_DETERMINISTIC ? 1 : 4) >= ((int64_t)1 << 31))
+        return CM_ERR_UNSUPPORTED;
     DeviceGuard g(h->device);
     if (!g.ok()) return CM_ERR_HIP;
     cm_batch_s* b = new (std::nothrow) cm_batch_s();

@@ -181,24 +181,37 @@ __device__ __forceinline__ void load_ref_table(const WinParams& P, const StateHe
 // spilled registers cost less than the lost latency hiding (the scatter,
 // which holds every visit's position until its records are written, loses
 // more to spills and is left at 2).
-template <int RM, int NT, int FM>
+//
+// Atomic mode (DET false): every tile owns all its pixels, so a position is
+// counted in each tile its taps reach (tiles_reached), and each valid event
+// once more in a source bin: the tile of its own position (with the tiles its
+// taps reach) when the batch's backward samples the flow at the events only
+// (`ae`), else the tile of its reference-0 position.  A block reserves its
+// range in every bin it fills with one returning atomic on the bin's total,
+// and stores the offset it got in its histogram row.  Deterministic mode:
+// reference bins only, the row holds counts, and the chunk sums feed the
+// column scan that orders the blocks.
+template <int RM, int NT, int FM, bool DET>
 __global__ __launch_bounds__(NT, 3) void fwd_count_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const float* __restrict__ ex,
     const float* __restrict__ ey, const float* __restrict__ et, const float* __restrict__ rho,
     const float* __restrict__ ego, const Motion* __restrict__ mtab, uint32_t* __restrict__ hist,
-    uint32_t* __restrict__ csum, StateHeader* __restrict__ hdrs, uint8_t* __restrict__ valid)
+    uint32_t* __restrict__ csum, uint32_t* __restrict__ totals, uint32_t* __restrict__ totals_src,
+    int ae, StateHeader* __restrict__ hdrs, uint8_t* __restrict__ valid)
 {
     extern __shared__ uint32_t lh[];
     __shared__ uint32_t cnt_lds;
-    __shared__ int bins[RM][NT];
+    __shared__ uint32_t bins[RM][NT];
     const int64_t blk = xcd_block();
     const int w = win_of[blk];
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
     const int64_t lb = blk - meta[w].blk_off;
     const int64_t ev0 = meta[w].ev_off, n = meta[w].n;
+    const int nrb = G.nbins;                    // reference bins; source bins follow
+    const int nlb = DET ? nrb : nrb + G.nbins_s;
     __shared__ RefTable rt;
-    for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) lh[i] = 0;
+    for (int i = threadIdx.x; i < nlb; i += blockDim.x) lh[i] = 0;
     if (threadIdx.x == 0) cnt_lds = 0;
     load_ref_table(P, nullptr, rt);
     __shared__ MotionTable mt;
@@ -216,28 +229,55 @@ __global__ __launch_bounds__(NT, 3) void fwd_count_kernel(
         // only the bins are kept, in the thread's LDS column (registers
         // would stay live through the whole warp)
         Visits v;
+        uint32_t t0 = 0;        // tile of the reference-0 position
         const bool ok = warp_visits_v<RM, FM>(P, u, rt, cur.x, cur.y, cur.t, v,
                                               [&](int j, double X, double Y, int r) {
-                                                  bins[j][threadIdx.x] =
-                                                      r * G.ntiles +
-                                                      tile_index(G, make_taps(P, X, Y));
+                                                  const Taps tp = make_taps(P, X, Y);
+                                                  if (DET) {
+                                                      bins[j][threadIdx.x] =
+                                                          r * G.ntiles + tile_index(G, tp);
+                                                  } else {
+                                                      const uint32_t tr = tiles_reached(G, tp);
+                                                      bins[j][threadIdx.x] =
+                                                          tr + (uint32_t)(r * G.ntiles);
+                                                      if (r == 0) t0 = tr & 0xffffu;
+                                                  }
                                               });
         // the mask, for the scatter (which then warps valid events only)
         valid[ev0 + k] = ok ? 1 : 0;
         if (!ok) continue;
         ++cnt;
 #pragma unroll
-        for (int j = 0; j < RM; ++j)
-            if (j < P.R) atomicAdd(&lh[bins[j][threadIdx.x]], 1u);
+        for (int j = 0; j < RM; ++j) {
+            if (j < P.R) {
+                if (DET) atomicAdd(&lh[bins[j][threadIdx.x]], 1u);
+                else for_each_reached(bins[j][threadIdx.x], G.ntx,
+                                      [&](int b) { atomicAdd(&lh[b], 1u); });
+            }
+        }
+        if (!DET) {
+            if (ae) for_each_reached(tiles_reached(G, make_taps(P, cur.x, cur.y)), G.ntx,
+                                     [&](int t) { atomicAdd(&lh[nrb + t], 1u); });
+            else atomicAdd(&lh[nrb + (int)t0], 1u);
+        }
     }
     if (cnt) atomicAdd(&cnt_lds, cnt);
     __syncthreads();
-    uint32_t* row = hist + meta[w].hist_off + lb * G.nbins;
-    uint32_t* cs = csum + meta[w].csum_off + (size_t)(lb / kScanChunk) * G.nbins;
-    for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) {
-        const uint32_t c = lh[i];
-        row[i] = c;
-        if (c) atomicAdd(cs + i, c);       // the chunk's column sums (integer: order-free)
+    uint32_t* row = hist + meta[w].hist_off + lb * nlb;
+    if (DET) {
+        uint32_t* cs = csum + meta[w].csum_off + (size_t)(lb / kScanChunk) * G.nbins;
+        for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) {
+            const uint32_t c = lh[i];
+            row[i] = c;
+            if (c) atomicAdd(cs + i, c);       // the chunk's column sums (integer: order-free)
+        }
+    } else {
+        for (int i = threadIdx.x; i < nlb; i += blockDim.x) {
+            const uint32_t c = lh[i];
+            uint32_t* tot = i < nrb ? totals + (meta[w].bin_off + i)
+                                    : totals_src + (meta[w].sbin_off + (i - nrb));
+            row[i] = c ? atomicAdd(tot, c) : 0u;
+        }
     }
     if (threadIdx.x == 0 && cnt_lds) atomicAdd(&hdrs[w].n_valid, (unsigned long long)cnt_lds);
 }
@@ -291,15 +331,20 @@ __global__ __launch_bounds__(256) void chunk_scan_kernel(const WinMeta* __restri
     totals[gbin] = run;
 }
 
-// start[bin] = exclusive prefix sum of totals over all windows' bins;
-// start[nbins] = total.  One block.
 // Exclusive scan of the bins' totals into start (start[nbins] = the sum), one
-// block: chunks of 8192 totals are loaded coalesced into LDS, each thread sums
-// 8 consecutive ones, the 1024 sums are scanned with in-wave shuffles and the
-// 16 wave totals by one wave, and the results go out coalesced.
-__global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__ totals,
-                                                    int64_t nbins, uint32_t* __restrict__ start)
+// block per bin array (block 0: totals0 -> start0; block 1, if launched:
+// totals1 -> start1): chunks of 8192 totals are loaded coalesced into LDS,
+// each thread sums 8 consecutive ones, the 1024 sums are scanned with in-wave
+// shuffles and the 16 wave totals by one wave, and the results go out
+// coalesced.
+__global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__ totals0,
+                                                    int64_t nbins0, uint32_t* __restrict__ start0,
+                                                    const uint32_t* __restrict__ totals1,
+                                                    int64_t nbins1, uint32_t* __restrict__ start1)
 {
+    const uint32_t* __restrict__ totals = blockIdx.x ? totals1 : totals0;
+    const int64_t nbins = blockIdx.x ? nbins1 : nbins0;
+    uint32_t* __restrict__ start = blockIdx.x ? start1 : start0;
     constexpr int T = 1024, K = 8, CH = T * K, NWV = T / 64;
     __shared__ uint32_t buf[CH];
     __shared__ uint32_t wsum[NWV];
@@ -384,13 +429,21 @@ __global__ __launch_bounds__(256) void offsets_kernel(const WinMeta* __restrict_
     }
 }
 
+// Writes each valid event's records into the slots its block reserved.
+// Atomic mode: a record goes to every tile its taps reach, and each valid
+// event's source record to its source bin(s) (see fwd_count); the block's
+// LDS counters start at the bins' starts plus the block's offsets.
+// Deterministic mode: the offsets kernel made the row absolute; the source
+// record goes where the event's reference-0 record goes, relative to the
+// window's first reference-0 slot.
 template <int RM, int NT, bool DET, int FM>
 __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const float* __restrict__ ex,
     const float* __restrict__ ey, const float* __restrict__ et, const int8_t* __restrict__ ep,
     const float* __restrict__ rho, const float* __restrict__ ego, const Motion* __restrict__ mtab,
     const uint32_t* __restrict__ offs, const uint32_t* __restrict__ start,
-    const uint8_t* __restrict__ valid, SplatRec* __restrict__ rec, SrcRec* __restrict__ src)
+    const uint32_t* __restrict__ start_src, int ae, const uint8_t* __restrict__ valid,
+    SplatRec* __restrict__ rec, SrcRec* __restrict__ src)
 {
     extern __shared__ uint32_t lh[];
     const int64_t blk = xcd_block();
@@ -399,18 +452,24 @@ __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
     const TileGeom G = meta[w].G;
     const int64_t lb = blk - meta[w].blk_off;
     const int64_t ev0 = meta[w].ev_off, n = meta[w].n;
-    const uint32_t* row = offs + meta[w].hist_off + lb * G.nbins;
+    const int nrb = G.nbins;
+    const int nlb = DET ? nrb : nrb + G.nbins_s;
+    const uint32_t* row = offs + meta[w].hist_off + lb * nlb;
     __shared__ RefTable rt;
-    for (int i = threadIdx.x; i < G.nbins; i += blockDim.x) lh[i] = row[i];
+    for (int i = threadIdx.x; i < nlb; i += blockDim.x) {
+        if (DET) lh[i] = row[i];
+        else lh[i] = row[i] + (i < nrb ? start[meta[w].bin_off + i]
+                                        : start_src[meta[w].sbin_off + (i - nrb)]);
+    }
     load_ref_table(P, nullptr, rt);
     __shared__ MotionTable mt;
     const Flows<FM> u = make_flows_tab<FM>(P, rho + meta[w].pix_off, ego + 6 * meta[w].ego_off,
                                            mtab + meta[w].ego_off, &mt);
     __syncthreads();
-    // the window's reference-0 records come first among its records: their
-    // slots minus this offset number its valid events
-    const uint32_t r0 = start[meta[w].bin_off];
-    SrcRec* wsrc = src + ev0;
+    // deterministic mode: the window's reference-0 records come first among
+    // its records, so their slots minus this offset number its valid events
+    const uint32_t r0 = DET ? start[meta[w].bin_off] : 0u;
+    SrcRec* wsrc = DET ? src + ev0 : src;
     const int64_t base = lb * NT * G.ept;
     const uint8_t* wvalid = valid + ev0;
     EventPrefetch nx(ex + ev0, ey + ev0, et + ev0, ep + ev0, base + threadIdx.x, n);
@@ -428,23 +487,32 @@ __global__ __launch_bounds__(NT) void fwd_scatter_kernel(
         if (!vk) continue;
         const float xk = cur.x, yk = cur.y, tk = cur.t;
         const float ts = cur.p > 0 ? fabsf(tk) : -fabsf(tk);   // sign bit = polarity
+        SrcRec o;
+        o.x0 = xk;
+        o.y0 = yk;
+        o.ts = ts;
+        o.k = (uint32_t)k;
+        if (!DET && ae)
+            for_each_reached(tiles_reached(G, make_taps(P, xk, yk)), G.ntx, [&](int t) {
+                store_nt(src + atomicAdd(&lh[nrb + t], 1u), o);
+            });
         Visits v;
         warp_visits_v<RM, FM>(P, u, rt, xk, yk, tk, v, [&](int, double X, double Y, int r) {
-            const int bin = r * G.ntiles + tile_index(G, make_taps(P, X, Y));
-            const uint32_t slot = DET ? stable_slot(lh, bin) : atomicAdd(&lh[bin], 1u);
+            const Taps tp = make_taps(P, X, Y);
             SplatRec q;
             q.X = X;
             q.Y = Y;
             q.ts = ts;
             q.k = (uint32_t)k;
-            rec[slot] = q;
-            if (r == 0) {
-                SrcRec o;
-                o.x0 = xk;
-                o.y0 = yk;
-                o.ts = ts;
-                o.k = (uint32_t)k;
-                wsrc[slot - r0] = o;
+            if (DET) {
+                const uint32_t slot = stable_slot(lh, r * G.ntiles + tile_index(G, tp));
+                rec[slot] = q;
+                if (r == 0) wsrc[slot - r0] = o;
+            } else {
+                const uint32_t tr = tiles_reached(G, tp);
+                for_each_reached(tr + (uint32_t)(r * G.ntiles), G.ntx,
+                                 [&](int b) { rec[atomicAdd(&lh[b], 1u)] = q; });
+                if (r == 0 && !ae) store_nt(src + atomicAdd(&lh[nrb + (int)(tr & 0xffffu)], 1u), o);
             }
         });
     }
@@ -585,13 +653,17 @@ __global__ __launch_bounds__(256) void window_table_kernel(const WinMeta* __rest
 }
 
 // Threads of the forward tile kernel: the deterministic mode keeps 256 (its
-// reduction order is defined on them); the atomic mode uses more, so that the
-// four blocks whose LDS tiles fit a CU keep more wavefronts in flight.
+// reduction order is defined on them); the atomic mode uses more by default
+// (a tuning), so that the blocks whose LDS tiles fit a CU keep more
+// wavefronts in flight.
 constexpr int kTileThreadsDet = 256;
 constexpr int kTileThreads = 512;
 
-template <bool DET>
-__global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile_kernel(const TileBin* __restrict__ tbin,
+// Deterministic mode: one workgroup per (reference, tile) bin accumulates its
+// records in a 33 x 33 LDS tile (the tile and its right column / bottom row
+// halo) in record order; column 0 and row 0 go to a border buffer and the
+// halo to a halo buffer, which the merge combines in a fixed order.
+__global__ __launch_bounds__(kTileThreadsDet) void fwd_tile_det_kernel(const TileBin* __restrict__ tbin,
                                                        const SplatRec* __restrict__ rec,
                                                        const uint32_t* __restrict__ start,
                                                        double2* __restrict__ img_base,
@@ -627,42 +699,7 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
     for (int i = threadIdx.x; i < (2 * TLW * TLH + 31) / 32; i += blockDim.x) zbit[i] = 0u;
     __syncthreads();
     const double ref = bi.ref;
-    if (!DET) {
-        // two records per thread and round, both loads issued before either
-        // is used (a heavy bin takes several rounds); the second load reads
-        // the first record again when there is no second one
-        const uint32_t nt = blockDim.x;
-        for (uint32_t i0 = s0 + threadIdx.x; i0 < s1; i0 += 2 * nt) {
-            const bool two = i0 + nt < s1;
-            SplatRec qq[2];
-            qq[0] = rec[i0];
-            qq[1] = rec[two ? i0 + nt : i0];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                if (u == 1 && !two) break;
-                const SplatRec q = qq[u];
-                const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
-                const double tb = 1.0 - fabs(ref - (double)fabsf(q.ts));
-                const Taps tp = make_taps_wh(bi.W, bi.H, q.X, q.Y);
-                const int lx = tp.x0 - xo, ly = tp.y0 - yo;
-                double2* L = lds + pol * TLW * TLH;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    if (!tap_in(tp, c)) continue;
-                    const double wt = tap_w(tp, c);
-                    const int key = (ly + (c >> 1)) * TLW + lx + (c & 1);
-                    if (wt == 0.0) {
-                        const int zk = pol * TLW * TLH + key;
-                        atomicOr(&zbit[zk >> 5], 1u << (zk & 31));
-                        continue;
-                    }
-                    double2* cell = L + key;
-                    atomicAdd(&cell->x, wt);
-                    atomicAdd(&cell->y, wt * tb);
-                }
-            }
-        }
-    } else if (threadIdx.x < 64) {
+    if (threadIdx.x < 64) {
         // one wavefront walks the records in order, 64 at a time; per tap slot,
         // equal cells are updated in lane order
         for (uint32_t b0 = s0; b0 < s1; b0 += 64) {
@@ -728,6 +765,115 @@ __global__ __launch_bounds__(DET ? kTileThreadsDet : kTileThreads) void fwd_tile
     if (threadIdx.x == 0) {
         part[(gbin * 2 + 0) * 2 + 0] = sc[0];
         part[(gbin * 2 + 0) * 2 + 1] = sc[1];
+    }
+}
+
+// Atomic mode: one workgroup per (reference, tile) bin owns the tile's 32 x 32
+// pixels.  Its bin holds every record whose taps reach the tile (its own
+// positions and the copies from the left, upper and upper-left neighbours),
+// so it accumulates the taps that fall in the tile with FP64 LDS atomics,
+// stores the pixels some tap reached and reduces Eq. 1 over all its pixels:
+// no halo, no merge.  The first records are loaded before the LDS tile is
+// cleared, so their latency overlaps the clear and the barrier.
+template <int NTT>
+__global__ __launch_bounds__(NTT) void fwd_tile_own_kernel(const TileBin* __restrict__ tbin,
+                                                           const SplatRec* __restrict__ rec,
+                                                           const uint32_t* __restrict__ start,
+                                                           double2* __restrict__ img_base,
+                                                           double* __restrict__ part)
+{
+    constexpr int NPIX = TW * TH;
+    __shared__ double2 lds[2 * NPIX];
+    // pixels reached only by zero-weight taps (positions on a pixel row or
+    // column): they hold zeros, but the backward reads them
+    __shared__ uint32_t zbit[2 * NPIX / 32];
+    __shared__ double red[32];
+    const int64_t gbin = blockIdx.x;
+    const uint32_t s0 = start[gbin], s1 = start[gbin + 1];
+    const TileBin bi = tbin[gbin];
+    if (s0 == s1) {
+        // no tap reaches the tile at this reference: nothing reads its pixels
+        if (threadIdx.x == 0) {
+            part[gbin * 4 + 0] = 0.0;
+            part[gbin * 4 + 1] = 0.0;
+            part[gbin * 4 + 2] = 0.0;
+            part[gbin * 4 + 3] = 0.0;
+        }
+        return;
+    }
+    const int xo = bi.xo, yo = bi.yo;
+    const double ref = bi.ref;
+    // the first round's records, in flight during the clear
+    uint32_t i0 = s0 + threadIdx.x;
+    SplatRec qq[2];
+    if (i0 < s1) {
+        qq[0] = rec[i0];
+        qq[1] = rec[i0 + NTT < s1 ? i0 + NTT : i0];
+    }
+    for (int i = threadIdx.x; i < 2 * NPIX; i += NTT) lds[i] = make_double2(0.0, 0.0);
+    for (int i = threadIdx.x; i < 2 * NPIX / 32; i += NTT) zbit[i] = 0u;
+    __syncthreads();
+    while (i0 < s1) {
+        const bool two = i0 + NTT < s1;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (u == 1 && !two) break;
+            const SplatRec q = qq[u];
+            const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
+            const double tb = 1.0 - fabs(ref - (double)fabsf(q.ts));
+            const Taps tp = make_taps_wh(bi.W, bi.H, q.X, q.Y);
+            const int lx = tp.x0 - xo, ly = tp.y0 - yo;
+            double2* L = lds + pol * NPIX;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int cx = lx + (c & 1), cy = ly + (c >> 1);
+                if (!tap_in(tp, c) || (unsigned)cx >= (unsigned)TW || (unsigned)cy >= (unsigned)TH)
+                    continue;
+                const double wt = tap_w(tp, c);
+                const int key = cy * TW + cx;
+                if (wt == 0.0) {
+                    const int zk = pol * NPIX + key;
+                    atomicOr(&zbit[zk >> 5], 1u << (zk & 31));
+                    continue;
+                }
+                atomicAdd(&L[key].x, wt);
+                atomicAdd(&L[key].y, wt * tb);
+            }
+        }
+        i0 += 2 * NTT;
+        if (i0 < s1) {
+            qq[0] = rec[i0];
+            qq[1] = rec[i0 + NTT < s1 ? i0 + NTT : i0];
+        }
+    }
+    __syncthreads();
+    double sum = 0.0, cnt = 0.0;
+    double2* plane0 = img_base + bi.plane;
+    double2* plane1 = plane0 + (size_t)bi.W * bi.H;
+    // The backward reads the image only at the taps of the positions splatted
+    // here, and every such tap reached this tile through its bin: so only the
+    // pixels some tap reached (a non-zero sum, or a zero-weight tap's bit) are
+    // stored, the others are neither written nor read.
+    auto reached = [&](int k, const double2& c) {
+        return c.x != 0.0 || c.y != 0.0 || ((zbit[k >> 5] >> (k & 31)) & 1u);
+    };
+    for (int i = threadIdx.x; i < NPIX; i += NTT) {
+        const int lx = i % TW, ly = i / TW;
+        const int X = xo + lx, Y = yo + ly;
+        if (X >= bi.W || Y >= bi.H) continue;
+        const double2 a = lds[i], b = lds[NPIX + i];
+        const int pix = Y * bi.W + X;
+        if (reached(i, a)) plane0[pix] = a;
+        if (reached(NPIX + i, b)) plane1[pix] = b;
+        reduce_pixel(a, b, bi.eps, sum, cnt);
+    }
+    double sc[2] = {sum, cnt};
+    block_sum_n(sc, red);
+    if (threadIdx.x == 0) {
+        part[gbin * 4 + 0] = sc[0];
+        part[gbin * 4 + 1] = sc[1];
+        part[gbin * 4 + 2] = 0.0;
+        part[gbin * 4 + 3] = 0.0;
     }
 }
 
@@ -867,8 +1013,8 @@ __global__ __launch_bounds__(256) void fwd_finalize_kernel(const WinMeta* __rest
 // batch.
 template <int RM, int FM, typename F>
 __device__ __forceinline__ void for_each_sample(const WinParams& P, const RefTable& rt,
-                                                const Visits& v, const int (&tl)[RM], int tev,
-                                                F&& fn)
+                                                const Visits& v, const uint32_t (&tl)[RM],
+                                                uint32_t tev, F&& fn)
 {
     // tl[j]: tile of visit j's position; tev: tile of the event.  A visit's
     // reference is mb + j in the forward sweep, mb - 1 - (j - nf) backward.
@@ -896,22 +1042,52 @@ __device__ __forceinline__ void for_each_sample(const WinParams& P, const RefTab
 // positions [(e * nblocks + b) * NT, +NT).  The blocks in flight then work on
 // one compact stretch of the source order, that is on neighbouring tiles, and
 // their image and inverse-depth gathers share the L2.
-template <int RM, int NT, int FM>
+//
+// The window's source records: deterministic mode, [ev_off, ev_off + n_valid)
+// of src; atomic mode, the window's source bins.  None (n = 0) if the forward
+// was not the tiled one.
+struct SrcRange {
+    const SrcRec* p;
+    int64_t n;
+};
+
+template <bool DET>
+__device__ __forceinline__ SrcRange src_range(const WinMeta& M, const StateHeader& h,
+                                              const SrcRec* src, const uint32_t* start_src)
+{
+    SrcRange s;
+    if (!(h.flags & kHdrSourceRecords)) {
+        s.p = src;
+        s.n = 0;
+    } else if (DET) {
+        s.p = src + M.ev_off;
+        s.n = (int64_t)h.n_valid;
+    } else {
+        const uint32_t a = start_src[M.sbin_off], b = start_src[M.sbin_off + M.G.nbins_s];
+        s.p = src + a;
+        s.n = (int64_t)(b - a);
+    }
+    return s;
+}
+
+template <int RM, int NT, int FM, bool DET>
 __global__ __launch_bounds__(NT, 3) void bwd_count_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const SrcRec* __restrict__ src,
-    const float* __restrict__ rho, const float* __restrict__ ego, const Motion* __restrict__ mtab,
-    const StateHeader* __restrict__ hdrs, uint32_t* __restrict__ hist, uint32_t* __restrict__ csum)
+    const uint32_t* __restrict__ start_src, const float* __restrict__ rho,
+    const float* __restrict__ ego, const Motion* __restrict__ mtab,
+    const StateHeader* __restrict__ hdrs, uint32_t* __restrict__ hist, uint32_t* __restrict__ csum,
+    uint32_t* __restrict__ totals)
 {
     extern __shared__ uint32_t lh[];
-    __shared__ int tls[RM][NT];
+    __shared__ uint32_t tls[RM][NT];
     const int64_t blk = xcd_block();
     const int w = win_of[blk];
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
     const int64_t lb = blk - meta[w].blk_off;
-    const int64_t nv =
-        (hdrs[w].flags & kHdrSourceRecords) ? (int64_t)hdrs[w].n_valid : 0;
-    const SrcRec* wsrc = src + meta[w].ev_off;
+    const SrcRange sr = src_range<DET>(meta[w], hdrs[w], src, start_src);
+    const int64_t nv = sr.n;
+    const SrcRec* wsrc = sr.p;
     __shared__ RefTable rt;
     for (int i = threadIdx.x; i < G.nbins_b; i += blockDim.x) lh[i] = 0;
     load_ref_table(P, nullptr, rt);
@@ -927,6 +1103,17 @@ __global__ __launch_bounds__(NT, 3) void bwd_count_kernel(
     // events only.
     const bool at_events = !(FM != 0 && P.F > 1) &&
                            (P.R == 1 || (P.R == 2 && rt.t[0] == 0.0 && rt.t[1] == 1.0));
+    // a sampling position's bin (deterministic) or bins (atomic: every tile
+    // its taps reach)
+    auto add = [&](uint32_t t, int set) {
+        if (DET) atomicAdd(&lh[set * G.ntiles + (int)t], 1u);
+        else for_each_reached(t + (uint32_t)(set * G.ntiles), G.ntx,
+                              [&](int b) { atomicAdd(&lh[b], 1u); });
+    };
+    auto tile_of = [&](double X, double Y) -> uint32_t {
+        const Taps tp = make_taps(P, X, Y);
+        return DET ? (uint32_t)tile_index(G, tp) : tiles_reached(G, tp);
+    };
     SrcRec qn;
     int64_t i = (int64_t)lb * NT + threadIdx.x;
     if (i < nv) qn = load_nt(wsrc + i);
@@ -936,39 +1123,55 @@ __global__ __launch_bounds__(NT, 3) void bwd_count_kernel(
         if (e + 1 < G.ept && i + stride < nv) qn = load_nt(wsrc + i + stride);
         const double x0 = q.x0, y0 = q.y0, tk = fabsf(q.ts);
         if (at_events) {
-            if (!(P.R == 1 && rt.t[0] == tk))
-                atomicAdd(&lh[tile_index(G, make_taps(P, x0, y0))], 1u);
+            if (!(P.R == 1 && rt.t[0] == tk)) add(tile_of(x0, y0), 0);
             continue;
         }
         // each visit's tile, in the thread's LDS column (see fwd_count)
         Visits v;
         if (!warp_visits_v<RM, FM>(P, u, rt, x0, y0, tk, v,
                                    [&](int j, double X, double Y, int) {
-                                       tls[j][threadIdx.x] = tile_index(G, make_taps(P, X, Y));
+                                       tls[j][threadIdx.x] = tile_of(X, Y);
                                    }))
             continue;
-        int tl[RM];
+        uint32_t tl[RM];
 #pragma unroll
-        for (int j = 0; j < RM; ++j) tl[j] = j < P.R ? tls[j][threadIdx.x] : 0;
-        for_each_sample<RM, FM>(P, rt, v, tl, tile_index(G, make_taps(P, x0, y0)),
-                                [&](int tile, int set) { atomicAdd(&lh[set * G.ntiles + tile], 1u); });
+        for (int j = 0; j < RM; ++j) tl[j] = j < P.R ? tls[j][threadIdx.x] : 0u;
+        for_each_sample<RM, FM>(P, rt, v, tl, tile_of(x0, y0),
+                                [&](uint32_t tile, int set) { add(tile, set); });
     }
     __syncthreads();
     uint32_t* row = hist + meta[w].hist_off + lb * G.nbins_b;
-    uint32_t* cs = csum + meta[w].csum_off + (size_t)(lb / kScanChunk) * G.nbins_b;
-    for (int i = threadIdx.x; i < G.nbins_b; i += blockDim.x) {
-        const uint32_t c = lh[i];
-        row[i] = c;
-        if (c) atomicAdd(cs + i, c);
+    if (DET) {
+        uint32_t* cs = csum + meta[w].csum_off + (size_t)(lb / kScanChunk) * G.nbins_b;
+        for (int i = threadIdx.x; i < G.nbins_b; i += blockDim.x) {
+            const uint32_t c = lh[i];
+            row[i] = c;
+            if (c) atomicAdd(cs + i, c);
+        }
+    } else {
+        for (int i = threadIdx.x; i < G.nbins_b; i += blockDim.x) {
+            const uint32_t c = lh[i];
+            row[i] = c ? atomicAdd(totals + (meta[w].bbin_off + i), c) : 0u;
+        }
     }
 }
 
-template <int RM, int NT, bool DET, int FM>
+// Re-runs each valid event's warp, gathers the adjoint seeds, runs the
+// reverse sweep and emits one record (sampling position, dt * adjoint) per
+// flow-sampling position.  Deterministic mode: into the position's bin, at
+// the slot stable_slot gives.  Atomic mode: into every tile its taps reach;
+// or, with AE (every warp step of every window starts at its event, and the
+// forward sorted the source records by the tiles their events' taps reach),
+// one record per source record at the source record's own index: the
+// records then come out in bin order, with no count and no scan.
+template <int RM, int NT, bool DET, int FM, bool AE>
 __global__ __launch_bounds__(NT, 3) void bwd_sweep_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const SrcRec* __restrict__ src,
-    const float* __restrict__ rho, const float* __restrict__ ego, const Motion* __restrict__ mtab,
+    const uint32_t* __restrict__ start_src, const float* __restrict__ rho,
+    const float* __restrict__ ego, const Motion* __restrict__ mtab,
     const double2* __restrict__ img_base, const StateHeader* __restrict__ hdrs,
-    const uint32_t* __restrict__ offs, GradRec* __restrict__ rec)
+    const uint32_t* __restrict__ offs, const uint32_t* __restrict__ start,
+    GradRec* __restrict__ rec)
 {
     extern __shared__ uint32_t lh[];
     const int64_t blk = xcd_block();
@@ -976,11 +1179,14 @@ __global__ __launch_bounds__(NT, 3) void bwd_sweep_kernel(
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
     const int64_t lb = blk - meta[w].blk_off;
-    const int64_t nv =
-        (hdrs[w].flags & kHdrSourceRecords) ? (int64_t)hdrs[w].n_valid : 0;
-    const SrcRec* wsrc = src + meta[w].ev_off;
-    const uint32_t* row = offs + meta[w].hist_off + lb * G.nbins_b;
-    for (int i = threadIdx.x; i < G.nbins_b; i += blockDim.x) lh[i] = row[i];
+    const SrcRange sr = src_range<DET>(meta[w], hdrs[w], src, start_src);
+    const int64_t nv = sr.n;
+    const SrcRec* wsrc = sr.p;
+    if (!AE) {
+        const uint32_t* row = offs + meta[w].hist_off + lb * G.nbins_b;
+        for (int i = threadIdx.x; i < G.nbins_b; i += blockDim.x)
+            lh[i] = DET ? row[i] : row[i] + start[meta[w].bbin_off + i];
+    }
     __syncthreads();
     __shared__ RefTable rt;
     load_ref_table(P, hdrs + w, rt);
@@ -992,32 +1198,43 @@ __global__ __launch_bounds__(NT, 3) void bwd_sweep_kernel(
     const bool split = FM != 0 && P.F > 1;    // one record per first step (see for_each_sample)
 
     auto emit = [&](double X, double Y, double gx, double gy, int set) {
-        const int bin = set * G.ntiles + tile_index(G, make_taps(P, X, Y));
-        const uint32_t slot = DET ? stable_slot(lh, bin) : atomicAdd(&lh[bin], 1u);
         GradRec q;
         q.X = X;
         q.Y = Y;
         q.gx = gx;
         q.gy = gy;
-        store_nt(rec + slot, q);
+        const Taps tp = make_taps(P, X, Y);
+        if (DET) {
+            store_nt(rec + stable_slot(lh, set * G.ntiles + tile_index(G, tp)), q);
+        } else {
+            for_each_reached(tiles_reached(G, tp) + (uint32_t)(set * G.ntiles), G.ntx,
+                             [&](int b) { store_nt(rec + atomicAdd(&lh[b], 1u), q); });
+        }
     };
 
+    // (the loop runs until the window's source records are done: with AE a
+    // window has up to four per valid event, more than the block geometry's
+    // events per lane)
     const int64_t stride = (int64_t)G.nblocks * NT;
+    GradRec* const arec = rec + (wsrc - src);     // AE: record of source record i
     SrcRec qn;
     int64_t i = (int64_t)lb * NT + threadIdx.x;
     if (i < nv) qn = load_nt(wsrc + i);
-    for (int e = 0; e < G.ept; ++e, i += stride) {
-        if (i >= nv) break;
+    for (; i < nv; i += stride) {
         const SrcRec q = qn;
-        if (e + 1 < G.ept && i + stride < nv) qn = load_nt(wsrc + i + stride);
+        if (i + stride < nv) qn = load_nt(wsrc + i + stride);
         double vx[RM], vy[RM];
         Visits v;
         const double x0 = q.x0, y0 = q.y0, tk = fabsf(q.ts);
         if (!warp_visits_v<RM, FM>(P, u, rt, x0, y0, tk, v, [&](int j, double X, double Y, int) {
                 vx[j] = X;
                 vy[j] = Y;
-            }))
+            })) {
+            // (a source record's event is valid: the forward's warp of the
+            // same inputs; its slot still gets a record)
+            if (AE) store_nt(arec + i, GradRec{x0, y0, 0.0, 0.0});
             continue;
+        }
         const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
         const double2* planes = img + (size_t)pol * P.HW;
         double g0x = 0.0, g0y = 0.0;     // contributions sampled at the event position
@@ -1052,15 +1269,17 @@ __global__ __launch_bounds__(NT, 3) void bwd_sweep_kernel(
                 }
             }
         }
-        if (!split && P.R - (v.eq ? 1 : 0) > 0) emit(x0, y0, g0x, g0y, 0);
+        if (AE) store_nt(arec + i, GradRec{x0, y0, g0x, g0y});
+        else if (!split && P.R - (v.eq ? 1 : 0) > 0) emit(x0, y0, g0x, g0y, 0);
     }
 }
 
-// Accumulate dL/du = sum over records of w_tap * (dt * adjoint) in LDS; own
-// pixels off the border get d rho and their d theta share here, the border
-// and the halo go to buffers for the merge.
-template <bool DET, bool EXACT>
-__global__ __launch_bounds__(256) void bwd_tile_kernel(
+// Deterministic mode: accumulate dL/du = sum over records of w_tap * (dt *
+// adjoint) in LDS in record order; own pixels off the border get d rho and
+// their d theta share here, the border and the halo go to buffers for the
+// merge.
+template <bool EXACT>
+__global__ __launch_bounds__(256) void bwd_tile_det_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const GradRec* __restrict__ rec,
     const uint32_t* __restrict__ start, const float* __restrict__ rho,
     const float* __restrict__ ego, const float* __restrict__ grad_loss,
@@ -1095,32 +1314,7 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(
     }
     for (int i = threadIdx.x; i < TLW * TLH; i += blockDim.x) lds[i] = make_double2(0.0, 0.0);
     __syncthreads();
-    if (!DET) {
-        // two records per thread and round, loaded together (see fwd_tile)
-        const uint32_t nt = blockDim.x;
-        for (uint32_t i0 = s0 + threadIdx.x; i0 < s1; i0 += 2 * nt) {
-            const bool two = i0 + nt < s1;
-            GradRec qq[2];
-            qq[0] = rec[i0];
-            qq[1] = rec[two ? i0 + nt : i0];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                if (u == 1 && !two) break;
-                const GradRec q = qq[u];
-                const Taps tp = make_taps(P, q.X, q.Y);
-                const int lx = tp.x0 - xo, ly = tp.y0 - yo;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    if (!tap_in(tp, c)) continue;
-                    const double wt = tap_w(tp, c);
-                    if (wt == 0.0) continue;
-                    double2* cell = lds + (ly + (c >> 1)) * TLW + lx + (c & 1);
-                    atomicAdd(&cell->x, wt * q.gx);
-                    atomicAdd(&cell->y, wt * q.gy);
-                }
-            }
-        }
-    } else if (threadIdx.x < 64) {
+    if (threadIdx.x < 64) {
         for (uint32_t b0 = s0; b0 < s1; b0 += 64) {
             const uint32_t i = b0 + threadIdx.x;
             const bool live = i < s1;
@@ -1180,6 +1374,114 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(
     if (threadIdx.x == 0)
 #pragma unroll
         for (int c = 0; c < 6; ++c) part[gtile * 12 + c] = dth[c];
+}
+
+// Atomic mode: one workgroup per backward bin (flow set, tile of a window)
+// owns the tile's 32 x 32 pixels.  Its records are every sampling position
+// whose taps reach the tile (with AE, its source bin's records, indexed like
+// the source records); it accumulates dL/du at the taps inside the tile in
+// LDS, then writes d rho of every pixel and reduces the tile's d theta share.
+// No halo, no merge.
+template <bool EXACT, bool AE>
+__global__ __launch_bounds__(256) void bwd_tile_own_kernel(
+    const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const GradRec* __restrict__ rec,
+    const uint32_t* __restrict__ start, const uint32_t* __restrict__ start_src,
+    const float* __restrict__ rho, const float* __restrict__ ego, const float* __restrict__ grad_loss,
+    float* __restrict__ drho, double* __restrict__ part)
+{
+    constexpr int NT = 256, NPIX = TW * TH;
+    __shared__ double2 lds[NPIX];
+    __shared__ double red[16 * 6];
+    const int64_t gtile = blockIdx.x;       // backward bin: (flow set, tile) of a window
+    const int w = win_of[gtile];
+    const WinParams& P = meta[w].P;
+    const TileGeom G = meta[w].G;
+    const int lbin = (int)(gtile - meta[w].bbin_off);
+    const int set = lbin / G.ntiles, tile = lbin - set * G.ntiles;
+    const int ty = tile / G.ntx, tx = tile - ty * G.ntx;
+    const int xo = tx * TW, yo = ty * TH;
+    const uint32_t s0 = AE ? start_src[meta[w].sbin_off + tile] : start[gtile];
+    const uint32_t s1 = AE ? start_src[meta[w].sbin_off + tile + 1] : start[gtile + 1];
+    float* drho_w = drho + meta[w].pix_off + (size_t)set * P.HW;
+    const double gl = (double)grad_loss[w];
+    if (s0 == s1) {
+        // no records: dL/du is zero on the tile
+        const float z = (float)(gl * 0.0);
+        for (int i = threadIdx.x; i < NPIX; i += NT) {
+            const int X = xo + i % TW, Y = yo + i / TW;
+            if (X < P.W && Y < P.H) drho_w[Y * P.W + X] = z;
+        }
+        if (threadIdx.x < 12) part[gtile * 12 + threadIdx.x] = 0.0;
+        return;
+    }
+    // the first round's records, in flight during the clear
+    uint32_t i0 = s0 + threadIdx.x;
+    GradRec qq[2];
+    if (i0 < s1) {
+        qq[0] = rec[i0];
+        qq[1] = rec[i0 + NT < s1 ? i0 + NT : i0];
+    }
+    for (int i = threadIdx.x; i < NPIX; i += NT) lds[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+    while (i0 < s1) {
+        const bool two = i0 + NT < s1;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (u == 1 && !two) break;
+            const GradRec q = qq[u];
+            const Taps tp = make_taps(P, q.X, q.Y);
+            const int lx = tp.x0 - xo, ly = tp.y0 - yo;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int cx = lx + (c & 1), cy = ly + (c >> 1);
+                if (!tap_in(tp, c) || (unsigned)cx >= (unsigned)TW || (unsigned)cy >= (unsigned)TH)
+                    continue;
+                const double wt = tap_w(tp, c);
+                if (wt == 0.0) continue;
+                double2* cell = lds + cy * TW + cx;
+                atomicAdd(&cell->x, wt * q.gx);
+                atomicAdd(&cell->y, wt * q.gy);
+            }
+        }
+        i0 += 2 * NT;
+        if (i0 < s1) {
+            qq[0] = rec[i0];
+            qq[1] = rec[i0 + NT < s1 ? i0 + NT : i0];
+        }
+    }
+    __syncthreads();
+    const float* ego_s = ego + 6 * (meta[w].ego_off + set);
+    const Motion m = load_motion(P, ego_s);
+    __shared__ MotionXJ mx[1];      // used by the exact model only
+    if (EXACT) {
+        if (threadIdx.x == 0) mx[0] = load_motion_xj(ego_s);
+        __syncthreads();
+    }
+    const float* rho_w = rho + meta[w].pix_off + (size_t)set * P.HW;
+    double dth[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < NPIX; i += NT) {
+        const int X = xo + i % TW, Y = yo + i / TW;
+        if (X >= P.W || Y >= P.H) continue;
+        const double2 g = lds[i];
+        const int pix = Y * P.W + X;
+        if constexpr (EXACT) {
+            double d = 0.0;
+            if (g.x != 0.0 || g.y != 0.0) d = chain_exact(P, mx[0], X, Y, (double)rho_w[pix], g.x, g.y, dth);
+            drho_w[pix] = (float)(gl * d);
+            continue;
+        }
+        double Ax, Ay, Bx, By;
+        flow_parts(P, m, X, Y, Ax, Ay, Bx, By);
+        drho_w[pix] = (float)(gl * (g.x * Bx + g.y * By));
+        if (g.x != 0.0 || g.y != 0.0) dtheta_at_pixel(P, X, Y, (double)rho_w[pix], g.x, g.y, dth);
+    }
+    block_sum_n(dth, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            part[gtile * 12 + c] = dth[c];
+            part[gtile * 12 + 6 + c] = 0.0;
+        }
 }
 
 template <bool EXACT>
@@ -1308,6 +1610,7 @@ TileGeom tile_geom(const WinParams& P, int64_t n, bool det, int min_ept)
     G.ntiles = G.ntx * G.nty;
     G.nbins = P.R * G.ntiles;
     G.nbins_b = P.F * G.ntiles;
+    G.nbins_s = det ? 0 : G.ntiles;
     // enough blocks to fill the chip, few enough to keep the histogram matrix small
     const int nt = bin_threads(det);
     const int64_t ept = std::max<int64_t>(n / ((int64_t)nt * 1024), min_ept);
@@ -1317,10 +1620,20 @@ TileGeom tile_geom(const WinParams& P, int64_t n, bool det, int min_ept)
     return G;
 }
 
-bool tiled_supported(const WinParams& P, int64_t n)
+// The backward of every window samples the flow at its events only (one flow
+// set, and references {0, 1} or a single one): every warp step starts at the
+// event.
+static bool samples_at_events(const WinParams& P)
 {
-    const TileGeom G = tile_geom(P, n, false, 1);
-    return G.nbins <= kMaxBins && G.nbins_b <= kMaxBins && n * (int64_t)P.R < ((int64_t)1 << 31);
+    return P.F == 1 && (P.R == 1 || (P.R == 2 && P.refs[0] == 0.0 && P.refs[1] == 1.0));
+}
+
+bool tiled_supported(const WinParams& P, int64_t n, bool det)
+{
+    const TileGeom G = tile_geom(P, n, det, 1);
+    // record slots are 32-bit: up to four per position in the atomic mode
+    return G.nbins + G.nbins_s <= kMaxBins && G.nbins_b <= kMaxBins &&
+           n * (int64_t)(P.R + 1) < ((int64_t)1 << 29);
 }
 
 BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int nw, bool det,
@@ -1332,11 +1645,12 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     B.tile_threads = det ? kTileThreadsDet : tune.tile_threads;
     const int64_t target_blocks = tune.event_blocks;
     B.meta.resize(nw);
-    int64_t ev = 0, pix = 0, sets = 0, img = 0, hist = 0, csum = 0, bin = 0, bbin = 0, blk = 0;
-    int64_t cf = 0, cb = 0, recs = 0;
+    int64_t ev = 0, pix = 0, sets = 0, img = 0, hist = 0, csum = 0, bin = 0, bbin = 0, sbin = 0;
+    int64_t blk = 0, cf = 0, cb = 0, recs = 0;
     B.max_R = 1;
     B.max_F = 1;
     B.max_lds_bins = 1;
+    B.at_events = !det;
     // Events per lane from the batch's size (the atomic mode only: the
     // deterministic mode's block partition, and with it its operation order,
     // depends on the window alone).
@@ -1363,18 +1677,21 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
         M.csum_off = csum;
         M.bin_off = bin;
         M.bbin_off = bbin;
+        M.sbin_off = sbin;
         M.blk_off = blk;
         M.cell_off_f = cf;
         M.cell_off_b = cb;
-        const int64_t row = std::max(M.G.nbins, M.G.nbins_b);   // forward and backward rows
+        // forward rows (reference and source bins) and backward rows
+        const int64_t row = std::max(M.G.nbins + M.G.nbins_s, M.G.nbins_b);
         ev += M.n;
         pix += (int64_t)M.P.F * M.P.HW;
         sets += M.P.F;
         img += (int64_t)2 * M.P.R * M.P.HW;
         hist += (int64_t)M.G.nblocks * row;
-        csum += (int64_t)M.nchunks * row;
+        if (det) csum += (int64_t)M.nchunks * row;
         bin += M.G.nbins;
         bbin += M.G.nbins_b;
+        sbin += M.G.nbins_s;
         blk += M.G.nblocks;
         cf += (int64_t)M.nchunks * M.G.nbins;
         cb += (int64_t)M.nchunks * M.G.nbins_b;
@@ -1383,6 +1700,7 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
         B.max_F = std::max(B.max_F, M.P.F);
         B.model = M.P.model;      // uniform over a batch (checked when the batch is created)
         B.max_lds_bins = std::max(B.max_lds_bins, (int)row);
+        if (!samples_at_events(M.P)) B.at_events = false;
     }
     B.n_events = ev;
     B.n_pixels = pix;
@@ -1390,6 +1708,7 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     B.img_elems = img;
     B.nbins = bin;
     B.nbins_b = bbin;
+    B.nbins_s = sbin;
     B.nblocks = blk;
     B.cells_f = cf;
     B.cells_b = cb;
@@ -1400,17 +1719,26 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
         off += (bytes + 255) / 256 * 256;
         return o;
     };
-    const int64_t bins = std::max(bin, bbin);
+    // totals and starts: one segment for the reference (forward) or backward
+    // bins, one for the source bins (atomic mode)
+    B.seg = std::max(bin, bbin);
     B.ws.hist = take((size_t)hist * sizeof(uint32_t));
     B.ws.csum = take((size_t)csum * sizeof(uint32_t));
-    B.ws.totals = take((size_t)(bins + 1) * sizeof(uint32_t));
-    B.ws.start = take((size_t)(bins + 1) * sizeof(uint32_t));
+    B.ws.totals = take((size_t)(B.seg + 1 + sbin) * sizeof(uint32_t));
+    B.ws.start = take((size_t)(B.seg + 1 + sbin + 1) * sizeof(uint32_t));
     B.ws.part = take((size_t)std::max(bin * 4, bbin * 12) * sizeof(double));
-    B.ws.halo = take((size_t)std::max<int64_t>(bin * (NHALO + NBORDER) * 2,
-                                               bbin * (NHALO + NBORDER)) *
-                     sizeof(double2));
-    B.ws.records = take((size_t)recs * std::max(sizeof(SplatRec), sizeof(GradRec)));
-    B.ws.src = take((size_t)ev * sizeof(SrcRec));
+    B.ws.halo = take(det ? (size_t)std::max<int64_t>(bin * (NHALO + NBORDER) * 2,
+                                                     bbin * (NHALO + NBORDER)) *
+                               sizeof(double2)
+                         : 0);
+    // Record slots (32 bytes each): the deterministic mode writes one record
+    // per position; the atomic mode one per tile the position's taps reach,
+    // at most four (the capacity is that bound; about 7 % above one record
+    // per position is typical at 32 x 32 tiles)
+    B.ws.records = take((size_t)recs * (det ? 1 : 4) * std::max(sizeof(SplatRec), sizeof(GradRec)));
+    // source records: one per valid event, or (atomic, sampled at the events)
+    // one per tile the event's taps reach
+    B.ws.src = take((size_t)ev * (B.at_events ? 4 : 1) * sizeof(SrcRec));
     B.ws.valid = take((size_t)ev);
     B.ws.win = take((size_t)(blk + bin + bbin) * sizeof(int));
     B.ws.motion = take((size_t)B.n_sets * sizeof(Motion));
@@ -1421,12 +1749,44 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
 
 static void launch_window_table(const BatchPlanHost& B, const WinMeta* meta, int* tab,
                                 const float* ego, Motion* mtab, StateHeader* hdrs,
-                                uint32_t* csum, TileBin* tbin, hipStream_t s)
+                                uint32_t* clear, int64_t nclear, TileBin* tbin, hipStream_t s)
 {
-    const int64_t n = B.nblocks + B.nbins + B.nbins_b + B.nw + B.csum_cells;
+    const int64_t n = B.nblocks + B.nbins + B.nbins_b + B.nw + nclear;
     window_table_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(
-        meta, B.nw, B.nblocks, B.nbins, B.nbins_b, tab, ego, mtab, hdrs, csum, B.csum_cells,
-        tbin);
+        meta, B.nw, B.nblocks, B.nbins, B.nbins_b, tab, ego, mtab, hdrs, clear, nclear, tbin);
+}
+
+// Pointers into a batch's workspace.
+struct WsPtrs {
+    uint32_t *hist, *csum, *totals, *totals_src, *start, *start_src;
+    double* part;
+    double2* halo;
+    char* records;
+    SrcRec* src;
+    uint8_t* valid;
+    int* wtab;
+    Motion* mtab;
+    TileBin* tbin;
+};
+
+static WsPtrs ws_ptrs(const BatchPlanHost& B, char* ws)
+{
+    WsPtrs p;
+    p.hist = reinterpret_cast<uint32_t*>(ws + B.ws.hist);
+    p.csum = reinterpret_cast<uint32_t*>(ws + B.ws.csum);
+    p.totals = reinterpret_cast<uint32_t*>(ws + B.ws.totals);
+    p.totals_src = p.totals + B.seg + 1;
+    p.start = reinterpret_cast<uint32_t*>(ws + B.ws.start);
+    p.start_src = p.start + B.seg + 1;
+    p.part = reinterpret_cast<double*>(ws + B.ws.part);
+    p.halo = reinterpret_cast<double2*>(ws + B.ws.halo);
+    p.records = ws + B.ws.records;
+    p.src = reinterpret_cast<SrcRec*>(ws + B.ws.src);
+    p.valid = reinterpret_cast<uint8_t*>(ws + B.ws.valid);
+    p.wtab = reinterpret_cast<int*>(ws + B.ws.win);
+    p.mtab = reinterpret_cast<Motion*>(ws + B.ws.motion);
+    p.tbin = reinterpret_cast<TileBin*>(ws + B.ws.tbin);
+    return p;
 }
 
 template <int RM, bool DET, int FM>
@@ -1436,59 +1796,64 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
                                    hipStream_t s, Profiler* prof)
 {
     const int nw = B.nw;
-    uint32_t* hist = reinterpret_cast<uint32_t*>(ws + B.ws.hist);
-    uint32_t* csum = reinterpret_cast<uint32_t*>(ws + B.ws.csum);
-    uint32_t* totals = reinterpret_cast<uint32_t*>(ws + B.ws.totals);
-    uint32_t* start = reinterpret_cast<uint32_t*>(ws + B.ws.start);
-    double* part = reinterpret_cast<double*>(ws + B.ws.part);
-    double2* halo = reinterpret_cast<double2*>(ws + B.ws.halo);
-    double2* fborder = halo + B.nbins * NHALO * 2;
-    SplatRec* rec = reinterpret_cast<SplatRec*>(ws + B.ws.records);
-    SrcRec* src = reinterpret_cast<SrcRec*>(ws + B.ws.src);
-    uint8_t* valid = reinterpret_cast<uint8_t*>(ws + B.ws.valid);
-    int* wtab = reinterpret_cast<int*>(ws + B.ws.win);
-    Motion* mtab = reinterpret_cast<Motion*>(ws + B.ws.motion);
-    TileBin* tbin = reinterpret_cast<TileBin*>(ws + B.ws.tbin);
-    const int* win_blk = wtab;
-    const int* win_bin = wtab + B.nblocks;
+    const WsPtrs W = ws_ptrs(B, ws);
+    SplatRec* rec = reinterpret_cast<SplatRec*>(W.records);
+    const int* win_blk = W.wtab;
+    const int* win_bin = W.wtab + B.nblocks;
     const size_t lds = (size_t)B.max_lds_bins * sizeof(uint32_t);
+    constexpr int NT = DET ? 64 : kBinThreads;
+    const int ae = B.at_events ? 1 : 0;
     {
         PhaseScope ph(prof, kPhZero, s);
-        launch_window_table(B, meta, wtab, ego, mtab, hdrs, csum, tbin, s);
+        if (DET)
+            launch_window_table(B, meta, W.wtab, ego, W.mtab, hdrs, W.csum, B.csum_cells, W.tbin, s);
+        else
+            launch_window_table(B, meta, W.wtab, ego, W.mtab, hdrs, W.totals,
+                                B.seg + 1 + B.nbins_s, W.tbin, s);
     }
     {
         PhaseScope ph(prof, kPhCount, s);
-        constexpr int NT = DET ? 64 : kBinThreads;
-        fwd_count_kernel<RM, NT, FM><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, ev.x, ev.y, ev.t, rho, ego,
-                                                            mtab, hist, csum, hdrs, valid);
+        fwd_count_kernel<RM, NT, FM, DET><<<B.nblocks, NT, lds, s>>>(
+            meta, nw, win_blk, ev.x, ev.y, ev.t, rho, ego, W.mtab, W.hist, W.csum, W.totals,
+            W.totals_src, ae, hdrs, W.valid);
     }
     {
         PhaseScope ph(prof, kPhScan, s);
-        const int gc = (int)((B.cells_f + 255) / 256);
-        chunk_scan_kernel<<<(int)((B.nbins + 255) / 256), 256, 0, s>>>(meta, win_bin, B.nbins, 0,
-                                                                        csum, totals);
-        scan_kernel<<<1, 1024, 0, s>>>(totals, B.nbins, start);
-        offsets_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_f, 0, hist, csum, start);
+        if (DET) {
+            const int gc = (int)((B.cells_f + 255) / 256);
+            chunk_scan_kernel<<<(int)((B.nbins + 255) / 256), 256, 0, s>>>(meta, win_bin, B.nbins,
+                                                                            0, W.csum, W.totals);
+            scan_kernel<<<1, 1024, 0, s>>>(W.totals, B.nbins, W.start, nullptr, 0, nullptr);
+            offsets_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_f, 0, W.hist, W.csum, W.start);
+        } else {
+            scan_kernel<<<2, 1024, 0, s>>>(W.totals, B.nbins, W.start, W.totals_src, B.nbins_s,
+                                           W.start_src);
+        }
     }
     {
         PhaseScope ph(prof, kPhScatter, s);
-        constexpr int NT = DET ? 64 : kBinThreads;
         fwd_scatter_kernel<RM, NT, DET, FM><<<B.nblocks, NT, lds, s>>>(
-            meta, nw, win_blk, ev.x, ev.y, ev.t, ev.p, rho, ego, mtab, hist, start, valid, rec, src);
+            meta, nw, win_blk, ev.x, ev.y, ev.t, ev.p, rho, ego, W.mtab, W.hist, W.start,
+            W.start_src, ae, W.valid, rec, W.src);
     }
     {
         PhaseScope ph(prof, kPhSplat, s);
-        fwd_tile_kernel<DET><<<(int)B.nbins, B.tile_threads, 0, s>>>(
-            tbin, rec, start, img, halo, fborder, part);
+        if (DET)
+            fwd_tile_det_kernel<<<(int)B.nbins, kTileThreadsDet, 0, s>>>(
+                W.tbin, rec, W.start, img, W.halo, W.halo + B.nbins * NHALO * 2, W.part);
+        else if (B.tile_threads == 256)
+            fwd_tile_own_kernel<256><<<(int)B.nbins, 256, 0, s>>>(W.tbin, rec, W.start, img, W.part);
+        else
+            fwd_tile_own_kernel<512><<<(int)B.nbins, 512, 0, s>>>(W.tbin, rec, W.start, img, W.part);
     }
-    {
+    if (DET) {
         PhaseScope ph(prof, kPhReduce, s);
         fwd_merge_kernel<<<(int)((B.nbins + kMergeBins - 1) / kMergeBins), 64 * kMergeBins, 0, s>>>(
-            tbin, B.nbins, start, img, halo, fborder, part);
+            W.tbin, B.nbins, W.start, img, W.halo, W.halo + B.nbins * NHALO * 2, W.part);
     }
     {
         PhaseScope ph(prof, kPhFinalize, s);
-        fwd_finalize_kernel<<<nw, 256, 0, s>>>(meta, part, hdrs, loss);
+        fwd_finalize_kernel<<<nw, 256, 0, s>>>(meta, W.part, hdrs, loss);
     }
     return hipGetLastError();
 }
@@ -1516,56 +1881,77 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
                                     char* ws, hipStream_t s, Profiler* prof)
 {
     const int nw = B.nw;
-    uint32_t* hist = reinterpret_cast<uint32_t*>(ws + B.ws.hist);
-    uint32_t* csum = reinterpret_cast<uint32_t*>(ws + B.ws.csum);
-    uint32_t* totals = reinterpret_cast<uint32_t*>(ws + B.ws.totals);
-    uint32_t* start = reinterpret_cast<uint32_t*>(ws + B.ws.start);
-    double* part = reinterpret_cast<double*>(ws + B.ws.part);
-    double2* halo = reinterpret_cast<double2*>(ws + B.ws.halo);
-    double2* border = halo + B.nbins_b * NHALO;
-    GradRec* rec = reinterpret_cast<GradRec*>(ws + B.ws.records);
-    const SrcRec* src = reinterpret_cast<const SrcRec*>(ws + B.ws.src);
-    int* wtab = reinterpret_cast<int*>(ws + B.ws.win);
-    Motion* mtab = reinterpret_cast<Motion*>(ws + B.ws.motion);
-    const int* win_blk = wtab;
-    const int* win_tile = wtab + B.nblocks + B.nbins;
+    const WsPtrs W = ws_ptrs(B, ws);
+    GradRec* rec = reinterpret_cast<GradRec*>(W.records);
+    const int* win_blk = W.wtab;
+    const int* win_tile = W.wtab + B.nblocks + B.nbins;
     const size_t lds = (size_t)B.max_lds_bins * sizeof(uint32_t);
+    constexpr int NT = DET ? 64 : kBinThreads;
+    constexpr bool EX = FM == 2;
+    // sampled at the events only: the forward's source bins are the backward's
+    const bool ae = !DET && B.at_events;
     {
         PhaseScope ph(prof, kPhGradCount, s);
         // rebuilt rather than taken from the forward: a state the direct
         // forward filled has no tables, and the backward must stay in bounds
-        launch_window_table(B, meta, wtab, ego, mtab, nullptr, csum,
-                            reinterpret_cast<TileBin*>(ws + B.ws.tbin), s);
-        constexpr int NT = DET ? 64 : kBinThreads;
-        bwd_count_kernel<RM, NT, FM><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, src, rho, ego,
-                                                                mtab, hdrs, hist, csum);
+        if (DET)
+            launch_window_table(B, meta, W.wtab, ego, W.mtab, nullptr, W.csum, B.csum_cells,
+                                W.tbin, s);
+        else
+            launch_window_table(B, meta, W.wtab, ego, W.mtab, nullptr, W.totals,
+                                ae ? 0 : B.nbins_b, W.tbin, s);
+        if (!ae)
+            bwd_count_kernel<RM, NT, FM, DET><<<B.nblocks, NT, lds, s>>>(
+                meta, nw, win_blk, W.src, W.start_src, rho, ego, W.mtab, hdrs, W.hist, W.csum,
+                W.totals);
     }
-    {
+    if (!ae) {
         PhaseScope ph(prof, kPhGradScan, s);
-        const int gc = (int)((B.cells_b + 255) / 256);
-        chunk_scan_kernel<<<(int)((B.nbins_b + 255) / 256), 256, 0, s>>>(meta, win_tile, B.nbins_b,
-                                                                          1, csum, totals);
-        scan_kernel<<<1, 1024, 0, s>>>(totals, B.nbins_b, start);
-        offsets_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_b, 1, hist, csum, start);
+        if (DET) {
+            const int gc = (int)((B.cells_b + 255) / 256);
+            chunk_scan_kernel<<<(int)((B.nbins_b + 255) / 256), 256, 0, s>>>(
+                meta, win_tile, B.nbins_b, 1, W.csum, W.totals);
+            scan_kernel<<<1, 1024, 0, s>>>(W.totals, B.nbins_b, W.start, nullptr, 0, nullptr);
+            offsets_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_b, 1, W.hist, W.csum, W.start);
+        } else {
+            scan_kernel<<<1, 1024, 0, s>>>(W.totals, B.nbins_b, W.start, nullptr, 0, nullptr);
+        }
     }
     {
         PhaseScope ph(prof, kPhAdjoint, s);
-        constexpr int NT = DET ? 64 : kBinThreads;
-        bwd_sweep_kernel<RM, NT, DET, FM><<<B.nblocks, NT, lds, s>>>(meta, nw, win_blk, src, rho, ego, mtab, img,
-                                                                 hdrs, hist, rec);
+        if (ae)
+            bwd_sweep_kernel<RM, NT, false, FM, true><<<B.nblocks, NT, 0, s>>>(
+                meta, nw, win_blk, W.src, W.start_src, rho, ego, W.mtab, img, hdrs, nullptr,
+                nullptr, rec);
+        else
+            bwd_sweep_kernel<RM, NT, DET, FM, false><<<B.nblocks, NT, lds, s>>>(
+                meta, nw, win_blk, W.src, W.start_src, rho, ego, W.mtab, img, hdrs, W.hist,
+                W.start, rec);
     }
     {
         PhaseScope ph(prof, kPhGradTile, s);
-        constexpr bool EX = FM == 2;
-        bwd_tile_kernel<DET, EX><<<(int)B.nbins_b, 256, 0, s>>>(meta, nw, win_tile, rec, start, rho, ego,
-                                                                grad_loss, grad_rho, halo, border, part);
-        bwd_merge_kernel<EX><<<(int)((B.nbins_b + kMergeBins - 1) / kMergeBins), 64 * kMergeBins, 0,
-                               s>>>(meta, nw, B.nbins_b, win_tile, rho, ego, grad_loss, start,
-                                                           grad_rho, halo, border, part);
+        if (DET) {
+            double2* border = W.halo + B.nbins_b * NHALO;
+            bwd_tile_det_kernel<EX><<<(int)B.nbins_b, 256, 0, s>>>(
+                meta, nw, win_tile, rec, W.start, rho, ego, grad_loss, grad_rho, W.halo, border,
+                W.part);
+            bwd_merge_kernel<EX><<<(int)((B.nbins_b + kMergeBins - 1) / kMergeBins),
+                                   64 * kMergeBins, 0, s>>>(meta, nw, B.nbins_b, win_tile, rho,
+                                                            ego, grad_loss, W.start, grad_rho,
+                                                            W.halo, border, W.part);
+        } else if (ae) {
+            bwd_tile_own_kernel<EX, true><<<(int)B.nbins_b, 256, 0, s>>>(
+                meta, nw, win_tile, rec, W.start, W.start_src, rho, ego, grad_loss, grad_rho,
+                W.part);
+        } else {
+            bwd_tile_own_kernel<EX, false><<<(int)B.nbins_b, 256, 0, s>>>(
+                meta, nw, win_tile, rec, W.start, W.start_src, rho, ego, grad_loss, grad_rho,
+                W.part);
+        }
     }
     {
         PhaseScope ph(prof, kPhGradFinalize, s);
-        bwd_finalize_kernel<<<nw, 256, 0, s>>>(meta, part, hdrs, grad_loss, grad_ego);
+        bwd_finalize_kernel<<<nw, 256, 0, s>>>(meta, W.part, hdrs, grad_loss, grad_ego);
     }
     return hipGetLastError();
 }

@@ -798,6 +798,7 @@ struct TileGeom {
     int ntx, nty, ntiles;   // tiles per row / column / image
     int nbins;              // forward bins: R * ntiles (reference, tile)
     int nbins_b;            // backward bins: F * ntiles (flow set, tile)
+    int nbins_s;            // source-record bins (atomic mode): ntiles; 0 otherwise
     int nblocks;            // count / scatter blocks
     int ept;                // events per thread in the count / scatter kernels
 };
@@ -891,7 +892,36 @@ __device__ __forceinline__ SrcRec load_nt(const SrcRec* p)
 
 __device__ __forceinline__ int tile_index(const TileGeom& G, const Taps& t)
 {
-    return (t.y0 / TH) * G.ntx + t.x0 / TW;
+    return (int)((uint32_t)t.y0 / TH) * G.ntx + (int)((uint32_t)t.x0 / TW);
+}
+
+// The tiles whose pixels the on-sensor taps of a position reach (atomic
+// mode, where each tile owns all its pixels): the tile of tap 0 and, when tap
+// 0 sits on that tile's last column or row, the right, lower and lower-right
+// neighbours.  Packed as the tile index (low 16 bits) and two flags: bit 16,
+// the right neighbour is reached; bit 17, the lower one (both: the
+// lower-right one as well).  A tap of zero weight counts: the backward reads
+// the image at every tap of a position, so its pixel must be stored.
+constexpr uint32_t kReachRight = 1u << 16, kReachDown = 1u << 17;
+
+__device__ __forceinline__ uint32_t tiles_reached(const TileGeom& G, const Taps& t)
+{
+    const uint32_t x0 = (uint32_t)t.x0, y0 = (uint32_t)t.y0;
+    uint32_t v = (uint32_t)((y0 / TH) * G.ntx + x0 / TW);
+    if (t.inx && x0 % TW == TW - 1) v |= kReachRight;
+    if (t.iny && y0 % TH == TH - 1) v |= kReachDown;
+    return v;
+}
+
+// Calls fn(tile) for every tile of a packed tiles_reached value, own tile first.
+template <typename F>
+__device__ __forceinline__ void for_each_reached(uint32_t v, int ntx, F&& fn)
+{
+    const int tile = (int)(v & 0xffffu);
+    fn(tile);
+    if (v & kReachRight) fn(tile + 1);
+    if (v & kReachDown) fn(tile + ntx);
+    if ((v & kReachRight) && (v & kReachDown)) fn(tile + ntx + 1);
 }
 
 }  // namespace cm

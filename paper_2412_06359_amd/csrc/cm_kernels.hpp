@@ -124,6 +124,7 @@ struct WinMeta {
     int64_t csum_off;       // first chunk-sum cell
     int64_t bin_off;        // first forward bin
     int64_t bbin_off;       // first backward bin (flow set, tile)
+    int64_t sbin_off;       // first source-record bin (atomic mode)
     int64_t blk_off;        // first count / scatter / sweep block
     int64_t cell_off_f;     // first forward chunk cell
     int64_t cell_off_b;     // first backward chunk cell
@@ -153,8 +154,11 @@ struct BatchPlanHost {
     bool det = false;       // deterministic mode
     std::vector<WinMeta> meta;
     int64_t n_events = 0, n_pixels = 0, n_sets = 0, img_elems = 0;
-    int64_t nbins = 0, nbins_b = 0, nblocks = 0, cells_f = 0, cells_b = 0, csum_cells = 0;
+    int64_t nbins = 0, nbins_b = 0, nbins_s = 0, nblocks = 0, cells_f = 0, cells_b = 0;
+    int64_t csum_cells = 0;
+    int64_t seg = 0;        // bins of the first totals / start segment: max(nbins, nbins_b)
     int max_R = 1, max_F = 1, max_lds_bins = 1;
+    bool at_events = false; // atomic mode, every window samples the flow at its events only
     int model = 0;          // flow model of the batch's windows
     int tile_threads = 512; // forward tile kernel threads (atomic mode)
     TileWorkspace ws;
@@ -184,7 +188,7 @@ hipError_t launch_backward(const WinParams& P, const EventPtrs& ev, const float*
 // Tiled (owner-computes) path over one or many windows.  `meta` is the device
 // copy of plan.meta; `ws` a device region of plan.ws.total bytes; images of
 // window w start at img + meta[w].img_off; hdrs[w] its sums.
-bool tiled_supported(const WinParams& P, int64_t n);
+bool tiled_supported(const WinParams& P, int64_t n, bool det);
 TileGeom tile_geom(const WinParams& P, int64_t n, bool det, int min_ept);
 // Launch shape of a plan (the atomic mode's tunables; see cm_tuning).
 struct PlanTuning {

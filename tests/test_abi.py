@@ -48,10 +48,18 @@ def test_state_bytes_formula(lib):
     n = cm.state_bytes(d, 0)
     assert n >= 32 * 3 * 64 * 48
     assert n - 32 * 3 * 64 * 48 < 1 << 20
-    # the tiled path's workspace grows with the event count (records of <= 32 R bytes)
+    # the tiled path's workspace grows with the event count: in the atomic
+    # mode up to four 32-byte record slots per position (one per tile its taps
+    # reach) plus a source record per event; one slot per position in the
+    # deterministic mode
     big = cm.state_bytes(d, 1_000_000)
-    assert big > n + 24 * 3 * 1_000_000
-    assert big < n + 32 * 3 * 1_000_000 + (64 << 20)
+    assert big > n + 4 * 32 * 3 * 1_000_000
+    assert big < n + (4 * 32 * 3 + 32) * 1_000_000 + (64 << 20)
+    dd = _desc(mode=cm.CM_MODE_DETERMINISTIC)
+    nd = cm.state_bytes(dd, 0)
+    bigd = cm.state_bytes(dd, 1_000_000)
+    assert bigd > nd + 32 * 3 * 1_000_000
+    assert bigd < nd + (32 * 3 + 32) * 1_000_000 + (64 << 20)
 
 
 @pytest.mark.parametrize("bad", [

@@ -88,7 +88,9 @@ def test_budget_bounds_device_memory_and_oversize_refused(cm):
     from paper_2412_06359_amd.serve import Server, window_footprint
     wins = windows(10)
     fps = [window_footprint(cm.WindowDesc.from_window(w), w.n) for w in wins]
-    budget = 2 * max(fps) + 1
+    # room for the largest window and half of it again: the windows cannot
+    # all share a batch, so the budget has to split them
+    budget = max(fps) + max(fps) // 2 + 1
     torch.cuda.synchronize()
     base = torch.cuda.memory_allocated()
     res, st = serve_all(cm, wins, cm.CM_MODE_ATOMIC, budget=budget, gap_s=0.0)
@@ -96,7 +98,7 @@ def test_budget_bounds_device_memory_and_oversize_refused(cm):
     assert 0 < st["max_used_bytes"] <= budget
     assert 0 < st["peak_allocated_bytes"] <= budget, (st["peak_allocated_bytes"], budget)
     assert torch.cuda.max_memory_allocated() - base <= budget
-    assert st["batches"] >= 3
+    assert st["batches"] >= max(3, -(-sum(fps) // budget))
     assert st["windows_per_batch"] == len(wins) / st["batches"]
     srv = Server(budget_bytes=max(fps) // 2)
     big = wins[int(np.argmax(fps))]
