@@ -49,23 +49,31 @@ def kernel_source_sha() -> str:
     return source_sha()
 
 
+# Bytes of splat state per pixel and reference that the measurement plan
+# counts as algorithmic: C and S of both polarities at FP32 (2 x 2 x 4 B).
+# This build keeps the images in FP64 (32 B per pixel and reference, for the
+# precision of the adjoint seeds); the FP64 figure is reported beside it,
+# labelled, and is not the roofline fraction.
+STATE_BYTES_PLAN = 16.0
+STATE_BYTES_FP64 = 32.0
+
+
 def algorithmic_bytes(phase: str, n: int, HW: int, R: int, tiled: bool, F: int = 1,
-                      active_bytes=None) -> float:
+                      active=None, state_bytes: float = STATE_BYTES_PLAN) -> float:
     """Bytes a phase must move at minimum for one window.
 
     events: 13 B each (x, y, t FP32 + p int8); rho: 4 B per pixel and flow set;
-    d rho 4 B per pixel and flow set; splat images: C and S FP64 per pixel,
-    polarity and reference (32 R B per pixel) on the direct path, which writes
-    every pixel; the tiled path stores only the pixels some tap reached, 32 B
-    at each of the sum over references of N_r (active_bytes, from
-    cm_batch_active_pixels): the others hold zeros that are neither written
-    nor read.  The backward gathers C and S at those pixels only.  The tiled
-    path's records, bin tables and tile borders are not counted: they are the
-    implementation's traffic, not the method's."""
+    d rho 4 B per pixel and flow set; splat state: `state_bytes` per pixel and
+    reference.  The direct path writes every pixel of the images; the tiled
+    path stores only the pixels some tap reached, the sum over references of
+    N_r (`active`, from cm_batch_active_pixels): the others are neither
+    written nor read.  The backward gathers the state at those pixels only.
+    The tiled path's records, bin tables and histograms are not counted:
+    they are the implementation's traffic, not the method's."""
     ev = 13.0 * n
     rho = 4.0 * HW * F
-    img = 32.0 * R * HW
-    act = img if active_bytes is None else active_bytes
+    img = state_bytes * R * HW
+    act = img if active is None else state_bytes * active
     if tiled:
         table = {"zero": 0.0, "count": ev + rho, "scan": 0.0, "scatter": ev + rho,
                  "splat": act, "reduce": 0.0, "finalize": 0.0,
@@ -76,6 +84,35 @@ def algorithmic_bytes(phase: str, n: int, HW: int, R: int, tiled: bool, F: int =
                  "grad_zero": 4.0 * HW * F, "adjoint": ev + rho + act + 4.0 * HW * F,
                  "grad_finalize": 0.0}
     return table.get(phase, 0.0)
+
+
+def roofline_of(phases: dict, steps: int, wins, active, tiled: bool, workload: str):
+    """The dominant phase (by total time) against the HBM roofline: its
+    algorithmic bytes per launch (the measurement plan's byte model) over its
+    average launch time (HIP events on the launch stream)."""
+    per_launch = {k: (ms / max(c, 1), c) for k, (ms, c) in phases.items() if c > 0}
+    dom = max(per_launch, key=lambda k: per_launch[k][0] * per_launch[k][1])
+    dom_ms = per_launch[dom][0]
+    launches_per_step = per_launch[dom][1] / steps
+
+    def alg(sb):
+        return sum(algorithmic_bytes(dom, w.n, w.width * w.height, len(w.refs), tiled,
+                                     w.rho.shape[0] if w.rho.ndim == 3 else 1, a, sb)
+                   for w, a in zip(wins, active)) / launches_per_step
+    a16, a32 = alg(STATE_BYTES_PLAN), alg(STATE_BYTES_FP64)
+    achieved = a16 / (dom_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(workload, dom),
+            "algorithmic_bytes_per_launch": a16, "avg_launch_ms": dom_ms,
+            "byte_model": "events 13 B, rho 4 B/px, splat state 16 B per active pixel and "
+                          "reference (C, S, both polarities, FP32 as the plan counts it)",
+            "fp64_state": {"algorithmic_bytes_per_launch": a32,
+                           "achieved": a32 / (dom_ms * 1e-3) / 1e9,
+                           "frac": a32 / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                           "note": "the same kernel with the state at the 32 B per pixel and "
+                                   "reference this build stores (FP64 images); not the "
+                                   "roofline fraction"}}, per_launch
 
 
 def launches_per_splat(per_launch: dict, steps: int) -> float:
@@ -97,18 +134,15 @@ def splat_atomic_roofline(n_valid: int, R: int, splat_ms: float, launches_per_st
             "peak_source": "LDS FP64 atomic adds, random addresses, measured in this run"}
 
 
-def image_bytes(cm, wins, dev):
-    """Per window, the splat-image bytes of its occupied tiles and of its
-    active pixels (32 B times the sum over references of N_r), from one
-    batched forward of the windows, read back before any backward."""
+def active_pixels(cm, wins, dev):
+    """Per window, the sum over references of N_r (pixels some tap reached),
+    from one batched forward of the windows, read back before any backward."""
     import torch
     d = to_device(wins, dev)
     b = cm.Batch([cm.WindowDesc.from_window(w) for w in wins], [w.n for w in wins])
     try:
         _, st = b.forward(d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"])
-        occ = b.occupied_image_bytes(st)
-        act = [32.0 * sum(nr) for nr in b.active_pixels(st)]
-        return occ, act
+        return [float(sum(nr)) for nr in b.active_pixels(st)]
     finally:
         b.close()
         torch.cuda.synchronize()
@@ -127,6 +161,25 @@ def measured_traffic(workload: str, phase: str):
         return None
     ph = rec.get("phases", {}).get(phase)
     return ph["bytes_per_launch"] if ph else None
+
+
+def host_cpu() -> dict:
+    """The host's logical CPU count and CPU model (from /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+# Host cores a one-GPU job is given on the GPU boxes (their CPU share per
+# GPU); os.cpu_count() there reports the whole machine.
+HOST_CORES_PER_GPU = 16
 
 
 def cpu_baseline(wins, seconds: float, threads: int) -> dict:
@@ -151,9 +204,13 @@ def cpu_baseline(wins, seconds: float, threads: int) -> dict:
             done_events += sum(pool.map(one, chunk))
             done_windows += len(chunk)
     el = time.perf_counter() - t0
-    return {"value": done_events / el, "unit": "events/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done_windows} windows of the workload ({done_events} events), FP64 "
-                      f"oracle forward+backward, {threads} threads (one window each), {el:.1f} s"}
+    out = {"value": done_events / el, "unit": "events/s", "cores": threads, "kind": "oracle",
+           "sample": f"{done_windows} windows of the workload ({done_events} events), FP64 "
+                     f"oracle forward+backward, {threads} threads (one window each), {el:.1f} s"}
+    out.update(host_cpu())
+    out["cores_note"] = (f"{threads} threads: the host cores one GPU's job gets on this machine "
+                         f"(os.cpu_count() reports the whole host)")
+    return out
 
 
 def to_device(wins, dev):
@@ -203,6 +260,42 @@ def plain_step_fn(cm, wins, dev):
     return step
 
 
+def _serve_run(cm, pool, rate: float, seconds: float, budget_gib: float, seed=None):
+    """One Poisson stream of c4 windows into a fresh server; the client consumes
+    each result as it arrives.  Returns the server's stats and the offered rate."""
+    import collections
+    import eventgen
+    from paper_2412_06359_amd.serve import Server
+    trace = (eventgen.poisson_stream(rate_hz=rate, duration_s=seconds) if seed is None else
+             eventgen.poisson_stream(rate_hz=rate, duration_s=seconds, seed=seed))
+    reqs = [eventgen.thin(pool[s][i % 2], n, offset=i) for i, (_, s, n) in enumerate(trace)]
+    srv = Server(budget_bytes=int(budget_gib * (1 << 30)), max_batch=64, n_streams=2)
+    try:
+        # warm-up: one request per sensor (allocator, code objects)
+        for s in pool:
+            srv.submit(eventgen.thin(pool[s][0], 10000)).result(timeout=60)
+        srv.drain()
+        srv.reset_stats()
+        pending = collections.deque()
+        t0 = time.perf_counter()
+        for (ta, _, _), w in zip(trace, reqs):
+            dt = t0 + ta - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            pending.append(srv.submit(w))
+            while pending and pending[0].done():
+                pending.popleft().result()
+        while pending:
+            pending.popleft().result(timeout=300)
+        srv.drain()
+        st = srv.stats()
+    finally:
+        srv.close()
+    st["offered_events_per_s"] = sum(w.n for w in reqs) / seconds
+    st["offered_windows_per_s"] = len(reqs) / seconds
+    return st
+
+
 def serve_stream(cm, seconds: float, rate: float, budget_gib: float) -> dict:
     """Workload c4: Poisson arrivals of windows (sensors 50/50 346x260 / 640x480,
     event counts log-uniform in [1k, 500k], refs {0,1}) into the continuous-
@@ -211,44 +304,86 @@ def serve_stream(cm, seconds: float, rate: float, budget_gib: float) -> dict:
     arrival -> loss on the host and gradients ready on the device, and includes
     the host-to-device copy of the window."""
     import eventgen
-    from paper_2412_06359_amd.serve import Server
     pool = eventgen.stream_pool(2, 500_000)
-    trace = eventgen.poisson_stream(rate_hz=rate, duration_s=seconds)
-    reqs = [eventgen.thin(pool[s][i % 2], n, offset=i) for i, (_, s, n) in enumerate(trace)]
-    srv = Server(budget_bytes=int(budget_gib * (1 << 30)), max_batch=64, n_streams=2)
-    # warm-up: one request per sensor (allocator, code objects)
-    for s in pool:
-        srv.submit(eventgen.thin(pool[s][0], 10000)).result(timeout=60)
-    srv.drain()
-    srv.latencies.clear()
-    srv.events_done = srv.windows_done = srv.batches = 0
-    srv.t_first = srv.t_last = None
-    # the client consumes each result as it arrives (holding every window's
-    # gradients until the end would grow device memory by ~8 GB over the
-    # stream and time the allocator instead of the server)
-    import collections
-    pending = collections.deque()
-    t0 = time.perf_counter()
-    for (ta, _, _), w in zip(trace, reqs):
-        dt = t0 + ta - time.perf_counter()
-        if dt > 0:
-            time.sleep(dt)
-        pending.append(srv.submit(w))
-        while pending and pending[0].done():
-            pending.popleft().result()
-    while pending:
-        pending.popleft().result(timeout=300)
-    srv.drain()
-    st = srv.stats()
-    srv.close()
-    offered = sum(w.n for w in reqs) / seconds
+    st = _serve_run(cm, pool, rate, seconds, budget_gib)
     return {"workload": f"c4: Poisson {rate:.0f} windows/s for {seconds:.0f} s, 346x260/640x480 "
                         f"50/50, log-uniform 1k..500k events, refs {{0,1}}, fwd+bwd",
             "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
-            "events_per_s": st["events_per_s"], "offered_events_per_s": offered,
+            "events_per_s": st["events_per_s"], "offered_events_per_s": st["offered_events_per_s"],
             "windows": st["windows"], "batches": st["batches"],
+            "windows_per_batch": st["windows_per_batch"],
             "budget_GiB": budget_gib, "max_admitted_GiB": st["max_used_bytes"] / (1 << 30),
             "latency_includes": "H2D copy of the window, batching wait, fwd+bwd, loss D2H"}
+
+
+def serve_saturation(cm, budget_gib: float, seconds: float = 2.0, start_rate: float = 500.0,
+                     max_levels: int = 7) -> dict:
+    """The c4 stream at rising Poisson rates (doubling from start_rate), a
+    fresh server per level, until the server no longer keeps up: served
+    events/s below 90 % of the offered rate, or p99 above 100 ms.  Reports
+    every level and the highest rate sustained, with its p50/p99."""
+    import eventgen
+    pool = eventgen.stream_pool(2, 500_000)
+    levels = []
+    rate = start_rate
+    sustained = None
+    for lvl in range(max_levels):
+        st = _serve_run(cm, pool, rate, seconds, budget_gib, seed=100 + lvl)
+        ok = (st["events_per_s"] is not None and
+              st["events_per_s"] >= 0.9 * st["offered_events_per_s"] and
+              st["p99_ms"] is not None and st["p99_ms"] <= 100.0)
+        levels.append({"rate_windows_per_s": rate, "offered_events_per_s": st["offered_events_per_s"],
+                       "events_per_s": st["events_per_s"], "p50_ms": st["p50_ms"],
+                       "p99_ms": st["p99_ms"], "windows": st["windows"],
+                       "windows_per_batch": st["windows_per_batch"], "kept_up": ok})
+        print(f"# serving level {rate:.0f} windows/s: {st['events_per_s'] / 1e6:.1f} Mev/s "
+              f"served of {st['offered_events_per_s'] / 1e6:.1f} offered, p99 {st['p99_ms']:.2f} ms, "
+              f"{st['windows_per_batch']:.2f} windows/batch", file=sys.stderr, flush=True)
+        if not ok:
+            break
+        sustained = levels[-1]
+        rate *= 2.0
+    return {"workload": "c4 windows (346x260/640x480 50/50, log-uniform 1k..500k events, refs "
+                        "{0,1}, fwd+bwd), Poisson arrivals, rate doubled per level, "
+                        f"{seconds:.0f} s per level",
+            "criterion": "served >= 90% of offered events/s and p99 <= 100 ms",
+            "max_sustained": sustained, "levels": levels}
+
+
+def single_window_line(cm, win, mode: int, steps: int, warmup: int, dev, stream,
+                       workload: str, forward_only: bool = False) -> dict:
+    """One window per call through the C ABI (the library picks its path),
+    buffers allocated once: ms per fwd+bwd (or forward only), events/s, and the
+    dominant phase against the HBM roofline."""
+    import torch
+    d = to_device([win], dev)
+    desc = cm.WindowDesc.from_window(win, mode=mode)
+    st = torch.empty(cm.state_bytes(desc, win.n), dtype=torch.uint8, device=dev)
+    loss = torch.empty(1, device=dev)
+    g_rho, g_ego = torch.empty_like(d["rho"]), torch.empty(d["ego"].numel(), device=dev)
+    g = torch.ones(1, device=dev)
+
+    def step():
+        cm.forward(desc, d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"], state=st, loss=loss)
+        if not forward_only:
+            cm.backward(desc, d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"], st, g,
+                        grad_rho=g_rho, grad_ego=g_ego)
+    ms = timed(step, steps, warmup, stream)
+    cm.profile_enable(0, True)
+    cm.profile_read(0)
+    for _ in range(steps):
+        step()
+    phases = cm.profile_read(0)
+    cm.profile_enable(0, False)
+    tiled = phases["count"][1] > 0
+    act = active_pixels(cm, [win], dev) if tiled else [None]
+    roof, per_launch = roofline_of(phases, steps, [win], act, tiled, workload)
+    return {"workload": WORKLOADS.get(workload, workload) if not forward_only else
+            WORKLOADS[workload].replace("fwd+bwd", "forward only"),
+            "mode": "deterministic" if mode == 1 else "atomic",
+            "path": "tiled" if tiled else "direct", "n_events": win.n,
+            "ms_per_step": ms, "events_per_s": win.n / (ms * 1e-3), "roofline": roof,
+            "phases_ms_per_launch": {k: v[0] for k, v in per_launch.items()}}
 
 
 def main():
@@ -260,11 +395,16 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the c6 (flow sets) and single-window c2 lines")
+                    help="skip the c6 (flow sets), c2, c5 and c1 lines")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the served Poisson stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=500.0)
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
+    ap.add_argument("--saturation-seconds", type=float, default=2.0,
+                    help="seconds per level of the rising-rate serving run (0: skip)")
+    ap.add_argument("--tuning", default=None,
+                    help="EVENT_BLOCKS,TILE_THREADS for the batched workload instead of the "
+                         "autotuner's choice (profiled runs pass the timed run's tuning)")
     ap.add_argument("--path", default="auto", choices=["auto", "direct", "tiled"],
                     help="kernel path of the library handle (plain calls)")
     args = ap.parse_args()
@@ -296,11 +436,16 @@ def main():
         from paper_2412_06359_amd import autotune
         d = to_device(wins, dev)
         descs = [cm.WindowDesc.from_window(w) for w in wins]
-        tune_log = []
-        tuning = autotune.tune(descs, [w.n for w in wins], d, steps=3, warmup=1,
-                               log=tune_log)
-        out_extra["tuning"] = {"chosen": tuning, "candidates": [dict(c, ms=ms)
-                                                                for c, ms in tune_log]}
+        if args.tuning:
+            eb, tt = (int(v) for v in args.tuning.split(","))
+            tuning = dict(event_blocks=eb, tile_threads=tt)
+            out_extra["tuning"] = {"chosen": tuning, "source": "--tuning"}
+        else:
+            tune_log = []
+            tuning = autotune.tune(descs, [w.n for w in wins], d, steps=3, warmup=1,
+                                   log=tune_log)
+            out_extra["tuning"] = {"chosen": tuning, "candidates": [dict(c, ms=ms)
+                                                                    for c, ms in tune_log]}
         batch = cm.Batch(descs, [w.n for w in wins], graph=True, tuning=tuning)
         state = batch.new_state()
         loss = torch.empty(batch.n, device=dev)
@@ -338,18 +483,11 @@ def main():
         path_used = "tiled" if phases["count"][1] > 0 else "direct"
         n_valid = None
 
-    per_launch = {k: (ms / max(c, 1), c) for k, (ms, c) in phases.items() if c > 0}
-    dom = max(per_launch, key=lambda k: per_launch[k][0] * per_launch[k][1])
-    dom_ms = per_launch[dom][0]
-    launches_per_step = per_launch[dom][1] / args.steps
-    occ, act = image_bytes(cm, wins, dev)
-    if path_used != "tiled":
-        occ = [None] * len(wins)
-    alg = sum(algorithmic_bytes(dom, w.n, w.width * w.height, len(w.refs), path_used == "tiled",
-                                w.rho.shape[0] if w.rho.ndim == 3 else 1, a)
-              for w, a in zip(wins, act)) / launches_per_step
-    achieved = alg / (dom_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, dom)
+    act = active_pixels(cm, wins, dev)
+    roof, per_launch = roofline_of(phases, args.steps, wins,
+                                   act if path_used == "tiled" else [None] * len(wins),
+                                   path_used == "tiled", args.workload)
+    roof["active_pixel_fraction"] = sum(act) / sum(len(w.refs) * w.width * w.height for w in wins)
 
     if not args.no_extras and args.workload == "c3":
         # the paper's training setting: 10 slices per window, one flow per slice
@@ -393,6 +531,8 @@ def main():
             "geo_algorithmic_bytes": geo_bytes,
             "geo_achieved_gbs": geo_bytes / (ms6g * 1e-3) / 1e9}
         b6.close()
+        del d6, st6, gst6
+        torch.cuda.empty_cache()
 
     if not args.no_extras and args.workload != "c2":
         w2 = eventgen.make_window("c2")
@@ -408,6 +548,26 @@ def main():
         out_extra["c2_single_window_autograd"] = {
             "workload": WORKLOADS["c2"], "ms_per_step": ms2,
             "events_per_s": w2.n / (ms2 * 1e-3)}
+
+    if not args.no_extras and args.workload not in ("c5", "c1"):
+        cm.set_path(0, cm.CM_PATH_AUTO)
+        # the large window, atomic and deterministic (sort-by-pixel) modes
+        w5 = eventgen.make_window("c5")
+        out_extra["c5_atomic"] = single_window_line(cm, w5, cm.CM_MODE_ATOMIC, args.steps,
+                                                    args.warmup, dev, stream, "c5")
+        out_extra["c5_deterministic"] = single_window_line(cm, w5, cm.CM_MODE_DETERMINISTIC,
+                                                           args.steps, args.warmup, dev, stream,
+                                                           "c5")
+        del w5
+        torch.cuda.empty_cache()
+        w1 = eventgen.make_window("c1")
+        out_extra["c1_forward"] = single_window_line(cm, w1, cm.CM_MODE_ATOMIC, args.steps,
+                                                     args.warmup, dev, stream, "c1",
+                                                     forward_only=True)
+        out_extra["c1_fwd_bwd"] = single_window_line(cm, w1, cm.CM_MODE_ATOMIC, args.steps,
+                                                     args.warmup, dev, stream, "c1")
+        cm.set_path(0, {"auto": cm.CM_PATH_AUTO, "direct": cm.CM_PATH_DIRECT,
+                        "tiled": cm.CM_PATH_TILED}[args.path])
 
     R = len(wins[0].refs)
     out = {
@@ -431,14 +591,7 @@ def main():
                    "valid_fraction": (n_valid / n_events) if n_valid is not None else None,
                    "mode": "atomic",
                    "inputs": "FP32 events/rho/ego, FP64 warp and splat images"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": alg, "avg_launch_ms": dom_ms,
-                     "image_occupancy": (sum(occ) / sum(32.0 * len(w.refs) * w.width * w.height
-                                                        for w in wins)
-                                         if occ and occ[0] is not None else None),
-                     "active_pixel_fraction": (sum(act) / sum(32.0 * len(w.refs) * w.width *
-                                                              w.height for w in wins))},
+        "roofline": roof,
         "phases_ms_per_launch": {k: v[0] for k, v in per_launch.items()},
     }
     if batched and "splat" in per_launch and n_valid:
@@ -449,8 +602,13 @@ def main():
         cm.set_path(0, cm.CM_PATH_AUTO)
         out["serving"] = serve_stream(cm, args.serve_seconds, args.serve_rate,
                                       args.serve_budget_gib)
+    if args.saturation_seconds > 0:
+        cm.set_path(0, cm.CM_PATH_AUTO)
+        out["serving_saturation"] = serve_saturation(cm, args.serve_budget_gib,
+                                                     args.saturation_seconds,
+                                                     start_rate=args.serve_rate)
     if not args.no_cpu_baseline:
-        threads = min(os.cpu_count() or 1, 16) if batched else 1
+        threads = min(os.cpu_count() or 1, HOST_CORES_PER_GPU) if batched else 1
         out["cpu_baseline"] = cpu_baseline(wins, args.cpu_seconds, threads)
     print(json.dumps(out), flush=True)
 

@@ -11,7 +11,15 @@
         --copy-mib M --cmd C [--cmd C ...] --out FILE.json
         HBM bytes per dispatch of the largest-grid launches of each kernel,
         each counter scaled by what it reads for the copy kernel; writes the
-        JSON record and a markdown table beside it (FILE.md).
+        JSON record and a markdown table beside it (FILE.md);
+    python -m paper_2412_06359_amd.profsum counters DIR [DIR ...] --kernel NAME:PHASE
+        [...] --title T --cmd C [--cmd C ...] --out FILE.md
+        mean per dispatch of every counter the runs collected, for the
+        largest-grid launches of each kernel, with the wave-state ratios
+        (waiting / wave cycles, busy / wave cycles) where the counters exist.
+
+The profiled runs pass the timed run's launch tuning explicitly, so the
+largest-grid launch of a kernel is the batched launch that was timed.
 
 The traffic summary records the hash of the kernel sources it was taken on;
 the benchmark reports it only while the sources are unchanged.
@@ -115,6 +123,62 @@ def traffic(args) -> dict:
             "fetch_scale": f_scale, "write_scale": w_scale, "phases": kernels}
 
 
+def counter_table(dirs, kernels, title: str, cmds) -> str:
+    """Mean per dispatch of each counter in the runs under `dirs`, for the
+    largest-grid launches of each kernel (NAME:PHASE, NAME a substring of
+    the kernel name)."""
+    rows = []
+    for d in dirs:
+        rows.extend(_csv(d, "counter_collection.csv"))
+    names = sorted({r["Counter_Name"] for r in rows})
+    out = [f"# {title}", "", "Commands (from the repository root, one MI355X):", "", "```"]
+    out += list(cmds)
+    out += ["```", "", "Mean value per dispatch (summed over the GPU's counter instances) of the "
+            "largest-grid launches of each kernel.", ""]
+    derived = []
+    if "SQ_WAVE_CYCLES" in names:
+        if "SQ_WAIT_ANY" in names:
+            derived.append(("wait/wave", "SQ_WAIT_ANY"))
+        if "SQ_BUSY_CYCLES" in names:
+            derived.append(("busy/wave", "SQ_BUSY_CYCLES"))
+        if "SQ_WAIT_INST_LDS" in names:
+            derived.append(("lds-wait/wave", "SQ_WAIT_INST_LDS"))
+    out.append("| phase | kernel | grid | dispatches | " + " | ".join(names) +
+               "".join(f" | {n}" for n, _ in derived) + " |")
+    out.append("|---" * (4 + len(names) + len(derived)) + "|")
+    for spec in kernels:
+        name, phase = spec.split(":")
+        vals = {}
+        grid = None
+        nd = 0
+        for c in names:
+            try:
+                by = _counter_rows(rows, c, name)
+            except ValueError:
+                continue
+            g = max(by)
+            grid = g if grid is None else grid
+            vals[c] = statistics.mean(by[g])
+            nd = max(nd, len(by[g]))
+        cells = [f"{vals[c]:.4g}" if c in vals else "" for c in names]
+        for _, c in derived:
+            cells.append(f"{vals[c] / vals['SQ_WAVE_CYCLES']:.3f}"
+                         if c in vals and vals.get("SQ_WAVE_CYCLES") else "")
+        out.append(f"| {phase} | `{name}` | {grid} | {nd} | " + " | ".join(cells) + " |")
+    return "\n".join(out) + "\n"
+
+
+def _counter_rows(rows, counter: str, match: str):
+    by_grid = collections.defaultdict(list)
+    for r in rows:
+        if r["Counter_Name"] != counter or match not in r["Kernel_Name"]:
+            continue
+        by_grid[_grid(r)].append(float(r["Counter_Value"]))
+    if not by_grid:
+        raise ValueError(f"no {counter} rows for a kernel matching {match!r}")
+    return by_grid
+
+
 def traffic_md(rec: dict) -> str:
     out = [f"# HBM traffic per launch, workload {rec['workload']}", "",
            "Commands (from the repository root, one MI355X):", "", "```"]
@@ -165,9 +229,18 @@ def main(argv=None):
     f.add_argument("--kernel", action="append", required=True, help="NAME:PHASE")
     f.add_argument("--copy-mib", type=int, default=512)
     f.add_argument("--cmd", action="append", default=[])
+    k = sub.add_parser("counters")
+    k.add_argument("dirs", nargs="+")
+    k.add_argument("--kernel", action="append", required=True, help="NAME:PHASE")
+    k.add_argument("--title", required=True)
+    k.add_argument("--cmd", action="append", default=[])
+    k.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     if a.cmd_name == "copy":
         copy_once(a.mib)
+    elif a.cmd_name == "counters":
+        with open(a.out, "w") as fh:
+            fh.write(counter_table(a.dirs, a.kernel, a.title, a.cmd))
     elif a.cmd_name == "trace":
         s = trace_table(a.dir, a.title, a.cmd)
         if a.out:

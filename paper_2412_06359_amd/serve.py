@@ -227,6 +227,14 @@ class Server:
             time.sleep(1e-3)
         raise TimeoutError("server did not drain")
 
+    def reset_stats(self):
+        """Clears the latency and throughput counters (call while idle, e.g.
+        after drain(), to leave a warm-up out of the figures)."""
+        with self._lock:
+            self.latencies.clear()
+            self.events_done = self.windows_done = self.batches = 0
+            self.t_first = self.t_last = None
+
     def stats(self) -> dict:
         lat = np.array(self.latencies) * 1e3
         span = (self.t_last - self.t_first) if self.t_first is not None else 0.0

@@ -43,3 +43,22 @@ def test_traffic_scaling(tmp_path):
     assert ph["grid"] == 900
     assert abs(ph["bytes_per_launch"] - (101.0 * 1024 * 2 + 8.0 * 1024)) < 1e-6
     assert (tmp_path / "t.md").exists()
+
+
+def test_counter_table(tmp_path):
+    # two counters of the same kernel in two runs; the largest grid is summarised
+    _write(tmp_path / "a", "SQ_WAVE_CYCLES", [("cm::fwd_tile_own_kernel<256>", 50, 1.0),
+                                              ("cm::fwd_tile_own_kernel<256>", 500, 1000.0),
+                                              ("cm::fwd_tile_own_kernel<256>", 500, 3000.0)])
+    _write(tmp_path / "b", "SQ_WAIT_ANY", [("cm::fwd_tile_own_kernel<256>", 500, 500.0),
+                                           ("cm::fwd_tile_own_kernel<256>", 500, 1500.0)])
+    out = tmp_path / "c.md"
+    profsum.main(["counters", str(tmp_path / "a"), str(tmp_path / "b"), "--kernel",
+                  "fwd_tile_own_kernel:splat", "--title", "T", "--cmd", "c1", "--out", str(out)])
+    text = out.read_text()
+    row = [l for l in text.splitlines() if l.startswith("| splat")][0]
+    cells = [c.strip() for c in row.strip("|").split("|")]
+    # phase, kernel, grid, dispatches, SQ_WAIT_ANY, SQ_WAVE_CYCLES, wait/wave
+    assert cells[2] == "500" and cells[3] == "2"
+    assert float(cells[4]) == 1000.0 and float(cells[5]) == 2000.0
+    assert abs(float(cells[6]) - 0.5) < 1e-12
