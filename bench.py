@@ -134,12 +134,14 @@ def splat_atomic_roofline(n_valid: int, R: int, splat_ms: float, launches_per_st
             "peak_source": "LDS FP64 atomic adds, random addresses, measured in this run"}
 
 
-def active_pixels(cm, wins, dev):
+def active_pixels(cm, wins, dev, tuning=None):
     """Per window, the sum over references of N_r (pixels some tap reached),
-    from one batched forward of the windows, read back before any backward."""
+    from one batched forward of the windows (at the timed run's tuning, so a
+    profiled run holds no other launch shape), read back before any backward."""
     import torch
     d = to_device(wins, dev)
-    b = cm.Batch([cm.WindowDesc.from_window(w) for w in wins], [w.n for w in wins])
+    b = cm.Batch([cm.WindowDesc.from_window(w) for w in wins], [w.n for w in wins],
+                 tuning=tuning)
     try:
         _, st = b.forward(d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"])
         return [float(sum(nr)) for nr in b.active_pixels(st)]
@@ -483,7 +485,7 @@ def main():
         path_used = "tiled" if phases["count"][1] > 0 else "direct"
         n_valid = None
 
-    act = active_pixels(cm, wins, dev)
+    act = active_pixels(cm, wins, dev, tuning if batched else None)
     roof, per_launch = roofline_of(phases, args.steps, wins,
                                    act if path_used == "tiled" else [None] * len(wins),
                                    path_used == "tiled", args.workload)

@@ -336,20 +336,24 @@ __global__ __launch_bounds__(256) void chunk_scan_kernel(const WinMeta* __restri
 // totals1 -> start1): chunks of 8192 totals are loaded coalesced into LDS,
 // each thread sums 8 consecutive ones, the 1024 sums are scanned with in-wave
 // shuffles and the 16 wave totals by one wave, and the results go out
-// coalesced.
+// coalesced.  With occ0, block 0 also lists its non-empty bins in order
+// (occ0[0 .. occ0_n[0]), by the same scan over the bins' non-empty flags).
 __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__ totals0,
                                                     int64_t nbins0, uint32_t* __restrict__ start0,
                                                     const uint32_t* __restrict__ totals1,
-                                                    int64_t nbins1, uint32_t* __restrict__ start1)
+                                                    int64_t nbins1, uint32_t* __restrict__ start1,
+                                                    uint32_t* __restrict__ occ0 = nullptr,
+                                                    uint32_t* __restrict__ occ0_n = nullptr)
 {
     const uint32_t* __restrict__ totals = blockIdx.x ? totals1 : totals0;
     const int64_t nbins = blockIdx.x ? nbins1 : nbins0;
     uint32_t* __restrict__ start = blockIdx.x ? start1 : start0;
+    uint32_t* __restrict__ occ = blockIdx.x ? nullptr : occ0;
     constexpr int T = 1024, K = 8, CH = T * K, NWV = T / 64;
     __shared__ uint32_t buf[CH];
-    __shared__ uint32_t wsum[NWV];
+    __shared__ uint32_t wsum[2][NWV];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    uint32_t carry = 0;
+    uint32_t carry = 0, fcarry = 0;
     for (int64_t base = 0; base < nbins; base += CH) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -357,37 +361,49 @@ __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__
             buf[k * T + tid] = i < nbins ? totals[i] : 0u;
         }
         __syncthreads();
-        uint32_t v[K], sum = 0;
+        uint32_t v[K], sum = 0, fsum = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             v[k] = buf[tid * K + k];
             sum += v[k];
+            fsum += v[k] ? 1u : 0u;
         }
-        uint32_t x = sum;                                  // inclusive scan within the wave
+        uint32_t x = sum, fx = fsum;                       // inclusive scans within the wave
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
+            const uint32_t fy = __shfl_up(fx, o, 64);
+            if (lane >= o) {
+                x += y;
+                fx += fy;
+            }
         }
-        if (lane == 63) wsum[wid] = x;
+        if (lane == 63) {
+            wsum[0][wid] = x;
+            wsum[1][wid] = fx;
+        }
         __syncthreads();
-        if (wid == 0) {
-            uint32_t t = lane < NWV ? wsum[lane] : 0u;
+        if (wid < 2) {
+            uint32_t t = lane < NWV ? wsum[wid][lane] : 0u;
 #pragma unroll
             for (int o = 1; o < NWV; o <<= 1) {
                 const uint32_t y = __shfl_up(t, o, 64);
                 if (lane >= o) t += y;
             }
-            if (lane < NWV) wsum[lane] = t;
+            if (lane < NWV) wsum[wid][lane] = t;
         }
         __syncthreads();
-        uint32_t run = carry + (wid ? wsum[wid - 1] : 0u) + (x - sum);
+        uint32_t run = carry + (wid ? wsum[0][wid - 1] : 0u) + (x - sum);
+        uint32_t frun = fcarry + (wid ? wsum[1][wid - 1] : 0u) + (fx - fsum);
+        const int64_t i0 = base + (int64_t)tid * K;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             buf[tid * K + k] = run;
             run += v[k];
+            if (occ && v[k]) occ[frun++] = (uint32_t)(i0 + k);
         }
-        carry += wsum[NWV - 1];
+        carry += wsum[0][NWV - 1];
+        fcarry += wsum[1][NWV - 1];
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -396,7 +412,10 @@ __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__
         }
         __syncthreads();
     }
-    if (tid == 0) start[nbins] = carry;
+    if (tid == 0) {
+        start[nbins] = carry;
+        if (occ) occ0_n[0] = fcarry;
+    }
 }
 
 // In place: hist[b][bin] <- start[global bin] + sum_{b' < b} hist[b'][bin].
@@ -572,7 +591,9 @@ __global__ __launch_bounds__(256) void window_table_kernel(const WinMeta* __rest
                                                            Motion* __restrict__ mtab,
                                                            StateHeader* __restrict__ hdrs,
                                                            uint32_t* __restrict__ csum,
-                                                           int64_t ncsum, TileBin* __restrict__ tbin)
+                                                           int64_t ncsum, TileBin* __restrict__ tbin,
+                                                           double* __restrict__ zero2 = nullptr,
+                                                           int64_t nzero2 = 0)
 {
     __shared__ int64_t first[3][kTableLdsWindows];
     const bool lds = nw <= kTableLdsWindows;
@@ -649,7 +670,12 @@ __global__ __launch_bounds__(256) void window_table_kernel(const WinMeta* __rest
         return;
     }
     i -= nw;
-    if (i < ncsum) csum[i] = 0u;
+    if (i < ncsum) {
+        csum[i] = 0u;
+        return;
+    }
+    i -= ncsum;
+    if (i < nzero2) zero2[i] = 0.0;
 }
 
 // Threads of the forward tile kernel: the deterministic mode keeps 256 (its
@@ -768,112 +794,132 @@ __global__ __launch_bounds__(kTileThreadsDet) void fwd_tile_det_kernel(const Til
     }
 }
 
-// Atomic mode: one workgroup per (reference, tile) bin owns the tile's 32 x 32
-// pixels.  Its bin holds every record whose taps reach the tile (its own
-// positions and the copies from the left, upper and upper-left neighbours),
-// so it accumulates the taps that fall in the tile with FP64 LDS atomics,
-// stores the pixels some tap reached and reduces Eq. 1 over all its pixels:
-// no halo, no merge.  The first records are loaded before the LDS tile is
-// cleared, so their latency overlaps the clear and the barrier.
+// Atomic mode: a (reference, tile) bin owns the tile's 32 x 32 pixels.  Its
+// bin holds every record whose taps reach the tile (its own positions and the
+// copies from the left, upper and upper-left neighbours), so its workgroup
+// accumulates the taps that fall in the tile with FP64 LDS atomics, stores the
+// pixels some tap reached and reduces Eq. 1 over all its pixels: no halo, no
+// merge.  Only occupied bins are visited (the scan lists them; the window
+// table kernel zeroed the partial sums of the others): workgroup b
+// takes list entries b, b + grid, b + 2 grid, ..., loading the next entry's
+// index during the current bin's accumulation and its bounds during the
+// current bin's output, so that a bin's chain starts at its record loads.
+// The first records are loaded before the LDS tile is cleared.  C and S
+// accumulate in separate LDS arrays (8-byte stride: half the bank conflicts
+// of interleaved pairs).
 template <int NTT>
 __global__ __launch_bounds__(NTT) void fwd_tile_own_kernel(const TileBin* __restrict__ tbin,
                                                            const SplatRec* __restrict__ rec,
                                                            const uint32_t* __restrict__ start,
+                                                           const uint32_t* __restrict__ occ,
+                                                           const uint32_t* __restrict__ occ_n,
                                                            double2* __restrict__ img_base,
                                                            double* __restrict__ part)
 {
     constexpr int NPIX = TW * TH;
-    __shared__ double2 lds[2 * NPIX];
+    __shared__ double lc[2 * NPIX];       // C by polarity, then pixel
+    __shared__ double ls[2 * NPIX];       // S
     // pixels reached only by zero-weight taps (positions on a pixel row or
     // column): they hold zeros, but the backward reads them
     __shared__ uint32_t zbit[2 * NPIX / 32];
     __shared__ double red[32];
-    const int64_t gbin = blockIdx.x;
-    const uint32_t s0 = start[gbin], s1 = start[gbin + 1];
-    const TileBin bi = tbin[gbin];
-    if (s0 == s1) {
-        // no tap reaches the tile at this reference: nothing reads its pixels
-        if (threadIdx.x == 0) {
-            part[gbin * 4 + 0] = 0.0;
-            part[gbin * 4 + 1] = 0.0;
-            part[gbin * 4 + 2] = 0.0;
-            part[gbin * 4 + 3] = 0.0;
-        }
-        return;
-    }
-    const int xo = bi.xo, yo = bi.yo;
-    const double ref = bi.ref;
-    // the first round's records, in flight during the clear
-    uint32_t i0 = s0 + threadIdx.x;
-    SplatRec qq[2];
-    if (i0 < s1) {
-        qq[0] = rec[i0];
-        qq[1] = rec[i0 + NTT < s1 ? i0 + NTT : i0];
-    }
-    for (int i = threadIdx.x; i < 2 * NPIX; i += NTT) lds[i] = make_double2(0.0, 0.0);
-    for (int i = threadIdx.x; i < 2 * NPIX / 32; i += NTT) zbit[i] = 0u;
-    __syncthreads();
-    while (i0 < s1) {
-        const bool two = i0 + NTT < s1;
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            if (u == 1 && !two) break;
-            const SplatRec q = qq[u];
-            const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
-            const double tb = 1.0 - fabs(ref - (double)fabsf(q.ts));
-            const Taps tp = make_taps_wh(bi.W, bi.H, q.X, q.Y);
-            const int lx = tp.x0 - xo, ly = tp.y0 - yo;
-            double2* L = lds + pol * NPIX;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int cx = lx + (c & 1), cy = ly + (c >> 1);
-                if (!tap_in(tp, c) || (unsigned)cx >= (unsigned)TW || (unsigned)cy >= (unsigned)TH)
-                    continue;
-                const double wt = tap_w(tp, c);
-                const int key = cy * TW + cx;
-                if (wt == 0.0) {
-                    const int zk = pol * NPIX + key;
-                    atomicOr(&zbit[zk >> 5], 1u << (zk & 31));
-                    continue;
-                }
-                atomicAdd(&L[key].x, wt);
-                atomicAdd(&L[key].y, wt * tb);
-            }
-        }
-        i0 += 2 * NTT;
+    const uint32_t nocc = occ_n[0];
+    uint32_t k = blockIdx.x;
+    if (k >= nocc) return;
+    uint32_t gbin = occ[k];
+    uint32_t s0 = start[gbin], s1 = start[gbin + 1];
+    TileBin bi = tbin[gbin];
+    for (;;) {
+        const uint32_t kn = k + gridDim.x;
+        const uint32_t gn = kn < nocc ? occ[kn] : gbin;     // the next bin, in flight
+        const int xo = bi.xo, yo = bi.yo;
+        const double ref = bi.ref;
+        // the first round's records, in flight during the clear
+        uint32_t i0 = s0 + threadIdx.x;
+        SplatRec qq[2];
         if (i0 < s1) {
             qq[0] = rec[i0];
             qq[1] = rec[i0 + NTT < s1 ? i0 + NTT : i0];
         }
-    }
-    __syncthreads();
-    double sum = 0.0, cnt = 0.0;
-    double2* plane0 = img_base + bi.plane;
-    double2* plane1 = plane0 + (size_t)bi.W * bi.H;
-    // The backward reads the image only at the taps of the positions splatted
-    // here, and every such tap reached this tile through its bin: so only the
-    // pixels some tap reached (a non-zero sum, or a zero-weight tap's bit) are
-    // stored, the others are neither written nor read.
-    auto reached = [&](int k, const double2& c) {
-        return c.x != 0.0 || c.y != 0.0 || ((zbit[k >> 5] >> (k & 31)) & 1u);
-    };
-    for (int i = threadIdx.x; i < NPIX; i += NTT) {
-        const int lx = i % TW, ly = i / TW;
-        const int X = xo + lx, Y = yo + ly;
-        if (X >= bi.W || Y >= bi.H) continue;
-        const double2 a = lds[i], b = lds[NPIX + i];
-        const int pix = Y * bi.W + X;
-        if (reached(i, a)) plane0[pix] = a;
-        if (reached(NPIX + i, b)) plane1[pix] = b;
-        reduce_pixel(a, b, bi.eps, sum, cnt);
-    }
-    double sc[2] = {sum, cnt};
-    block_sum_n(sc, red);
-    if (threadIdx.x == 0) {
-        part[gbin * 4 + 0] = sc[0];
-        part[gbin * 4 + 1] = sc[1];
-        part[gbin * 4 + 2] = 0.0;
-        part[gbin * 4 + 3] = 0.0;
+        for (int i = threadIdx.x; i < 2 * NPIX; i += NTT) {
+            lc[i] = 0.0;
+            ls[i] = 0.0;
+        }
+        for (int i = threadIdx.x; i < 2 * NPIX / 32; i += NTT) zbit[i] = 0u;
+        __syncthreads();
+        while (i0 < s1) {
+            const bool two = i0 + NTT < s1;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (u == 1 && !two) break;
+                const SplatRec q = qq[u];
+                const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
+                const double tb = 1.0 - fabs(ref - (double)fabsf(q.ts));
+                const Taps tp = make_taps_wh(bi.W, bi.H, q.X, q.Y);
+                const int lx = tp.x0 - xo, ly = tp.y0 - yo;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int cx = lx + (c & 1), cy = ly + (c >> 1);
+                    if (!tap_in(tp, c) || (unsigned)cx >= (unsigned)TW ||
+                        (unsigned)cy >= (unsigned)TH)
+                        continue;
+                    const double wt = tap_w(tp, c);
+                    const int key = pol * NPIX + cy * TW + cx;
+                    if (wt == 0.0) {
+                        atomicOr(&zbit[key >> 5], 1u << (key & 31));
+                        continue;
+                    }
+                    atomicAdd(&lc[key], wt);
+                    atomicAdd(&ls[key], wt * tb);
+                }
+            }
+            i0 += 2 * NTT;
+            if (i0 < s1) {
+                qq[0] = rec[i0];
+                qq[1] = rec[i0 + NTT < s1 ? i0 + NTT : i0];
+            }
+        }
+        __syncthreads();
+        // the next bin's bounds and record, in flight during the output
+        const uint32_t s0n = start[gn], s1n = start[gn + 1];
+        const TileBin bin_n = tbin[gn];
+        double sum = 0.0, cnt = 0.0;
+        double2* plane0 = img_base + bi.plane;
+        double2* plane1 = plane0 + (size_t)bi.W * bi.H;
+        // The backward reads the image only at the taps of the positions
+        // splatted here, and every such tap reached this tile through its
+        // bin: so only the pixels some tap reached (a non-zero sum, or a
+        // zero-weight tap's bit) are stored, the others are neither written
+        // nor read.
+        auto reached = [&](int kk, const double2& c) {
+            return c.x != 0.0 || c.y != 0.0 || ((zbit[kk >> 5] >> (kk & 31)) & 1u);
+        };
+        for (int i = threadIdx.x; i < NPIX; i += NTT) {
+            const int X = xo + (i % TW), Y = yo + (i / TW);
+            if (X >= bi.W || Y >= bi.H) continue;
+            const double2 a = make_double2(lc[i], ls[i]);
+            const double2 b = make_double2(lc[NPIX + i], ls[NPIX + i]);
+            const int pix = Y * bi.W + X;
+            if (reached(i, a)) plane0[pix] = a;
+            if (reached(NPIX + i, b)) plane1[pix] = b;
+            reduce_pixel(a, b, bi.eps, sum, cnt);
+        }
+        double sc[2] = {sum, cnt};
+        block_sum_n(sc, red);
+        if (threadIdx.x == 0) {
+            part[(size_t)gbin * 4 + 0] = sc[0];
+            part[(size_t)gbin * 4 + 1] = sc[1];
+            part[(size_t)gbin * 4 + 2] = 0.0;
+            part[(size_t)gbin * 4 + 3] = 0.0;
+        }
+        if (kn >= nocc) break;
+        // (block_sum_n's barriers order every thread's LDS reads above
+        // before the next bin's clear)
+        k = kn;
+        gbin = gn;
+        s0 = s0n;
+        s1 = s1n;
+        bi = bin_n;
     }
 }
 
@@ -968,7 +1014,7 @@ __global__ __launch_bounds__(256) void fwd_finalize_kernel(const WinMeta* __rest
                                                            StateHeader* __restrict__ hdrs,
                                                            float* __restrict__ loss)
 {
-    __shared__ double red[16];
+    __shared__ double red[16 * 2];
     const int w = blockIdx.x;
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
@@ -976,17 +1022,16 @@ __global__ __launch_bounds__(256) void fwd_finalize_kernel(const WinMeta* __rest
     StateHeader* hdr = hdrs + w;
     double L = 0.0;
     for (int r = 0; r < P.R; ++r) {
-        double s = 0.0, c = 0.0;
+        double sc[2] = {0.0, 0.0};
         for (int j = threadIdx.x; j < 2 * G.ntiles; j += blockDim.x) {
-            s += pw[((size_t)r * 2 * G.ntiles + j) * 2 + 0];
-            c += pw[((size_t)r * 2 * G.ntiles + j) * 2 + 1];
+            sc[0] += pw[((size_t)r * 2 * G.ntiles + j) * 2 + 0];
+            sc[1] += pw[((size_t)r * 2 * G.ntiles + j) * 2 + 1];
         }
-        s = block_sum(s, red);
-        c = block_sum(c, red);
+        block_sum_n(sc, red);
         if (threadIdx.x == 0) {
-            hdr->num[r] = s;
-            hdr->nact[r] = c;
-            L += s / (c + P.eps);
+            hdr->num[r] = sc[0];
+            hdr->nact[r] = sc[1];
+            L += sc[0] / (sc[1] + P.eps);
         }
     }
     if (threadIdx.x == 0) {
@@ -1562,25 +1607,31 @@ __global__ __launch_bounds__(64 * kMergeBins) void bwd_merge_kernel(
 }
 
 // One block per window: fixed-order sum of its tiles' d theta partials, per
-// flow set.
+// flow set (the six components through one block reduction, each in
+// block_sum's order).
 __global__ __launch_bounds__(256) void bwd_finalize_kernel(const WinMeta* __restrict__ meta,
                                                            const double* __restrict__ part,
                                                            const StateHeader* __restrict__ hdrs,
                                                            const float* __restrict__ grad_loss,
                                                            float* __restrict__ grad_ego)
 {
-    __shared__ double red[16];
+    __shared__ double red[16 * 6];
     const int w = blockIdx.x;
     const int ntiles = meta[w].G.ntiles;
     const double gl = (hdrs[w].flags & kHdrSourceRecords) ? (double)grad_loss[w] : (double)NAN;
     for (int f = 0; f < meta[w].P.F; ++f) {
         const double* pw = part + (meta[w].bbin_off + (int64_t)f * ntiles) * 12;
+        double v[6];
+#pragma unroll
         for (int c = 0; c < 6; ++c) {
             double s = 0.0;
             for (int j = threadIdx.x; j < 2 * ntiles; j += blockDim.x) s += pw[(size_t)j * 6 + c];
-            s = block_sum(s, red);
-            if (threadIdx.x == 0) grad_ego[(meta[w].ego_off + f) * 6 + c] = (float)(gl * s);
+            v[c] = s;
         }
+        block_sum_n(v, red);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) grad_ego[(meta[w].ego_off + f) * 6 + c] = (float)(gl * v[c]);
     }
 }
 
@@ -1726,6 +1777,8 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     B.ws.csum = take((size_t)csum * sizeof(uint32_t));
     B.ws.totals = take((size_t)(B.seg + 1 + sbin) * sizeof(uint32_t));
     B.ws.start = take((size_t)(B.seg + 1 + sbin + 1) * sizeof(uint32_t));
+    // the occupied forward bins, listed by the scan, and their count
+    B.ws.occ = take((size_t)(bin + 2) * sizeof(uint32_t));
     B.ws.part = take((size_t)std::max(bin * 4, bbin * 12) * sizeof(double));
     B.ws.halo = take(det ? (size_t)std::max<int64_t>(bin * (NHALO + NBORDER) * 2,
                                                      bbin * (NHALO + NBORDER)) *
@@ -1747,18 +1800,28 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     return B;
 }
 
+// Workgroups of the atomic mode's forward tile kernel: each walks the list of
+// occupied bins with the grid as stride; twice the workgroups whose LDS tiles
+// fit the chip at once, so that those freed early take the remaining ones.
+static int tile_grid(const BatchPlanHost& B)
+{
+    return (int)std::max<int64_t>(1, std::min<int64_t>(B.nbins, 2048));
+}
+
 static void launch_window_table(const BatchPlanHost& B, const WinMeta* meta, int* tab,
                                 const float* ego, Motion* mtab, StateHeader* hdrs,
-                                uint32_t* clear, int64_t nclear, TileBin* tbin, hipStream_t s)
+                                uint32_t* clear, int64_t nclear, TileBin* tbin, hipStream_t s,
+                                double* zero2 = nullptr, int64_t nzero2 = 0)
 {
-    const int64_t n = B.nblocks + B.nbins + B.nbins_b + B.nw + nclear;
+    const int64_t n = B.nblocks + B.nbins + B.nbins_b + B.nw + nclear + nzero2;
     window_table_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(
-        meta, B.nw, B.nblocks, B.nbins, B.nbins_b, tab, ego, mtab, hdrs, clear, nclear, tbin);
+        meta, B.nw, B.nblocks, B.nbins, B.nbins_b, tab, ego, mtab, hdrs, clear, nclear, tbin,
+        zero2, nzero2);
 }
 
 // Pointers into a batch's workspace.
 struct WsPtrs {
-    uint32_t *hist, *csum, *totals, *totals_src, *start, *start_src;
+    uint32_t *hist, *csum, *totals, *totals_src, *start, *start_src, *occ, *occ_n;
     double* part;
     double2* halo;
     char* records;
@@ -1778,6 +1841,8 @@ static WsPtrs ws_ptrs(const BatchPlanHost& B, char* ws)
     p.totals_src = p.totals + B.seg + 1;
     p.start = reinterpret_cast<uint32_t*>(ws + B.ws.start);
     p.start_src = p.start + B.seg + 1;
+    p.occ = reinterpret_cast<uint32_t*>(ws + B.ws.occ);
+    p.occ_n = p.occ + B.nbins;
     p.part = reinterpret_cast<double*>(ws + B.ws.part);
     p.halo = reinterpret_cast<double2*>(ws + B.ws.halo);
     p.records = ws + B.ws.records;
@@ -1808,8 +1873,9 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
         if (DET)
             launch_window_table(B, meta, W.wtab, ego, W.mtab, hdrs, W.csum, B.csum_cells, W.tbin, s);
         else
+            // (and the partial sums: the tile kernel writes those of occupied bins only)
             launch_window_table(B, meta, W.wtab, ego, W.mtab, hdrs, W.totals,
-                                B.seg + 1 + B.nbins_s, W.tbin, s);
+                                B.seg + 1 + B.nbins_s, W.tbin, s, W.part, B.nbins * 4);
     }
     {
         PhaseScope ph(prof, kPhCount, s);
@@ -1827,7 +1893,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
             offsets_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_f, 0, W.hist, W.csum, W.start);
         } else {
             scan_kernel<<<2, 1024, 0, s>>>(W.totals, B.nbins, W.start, W.totals_src, B.nbins_s,
-                                           W.start_src);
+                                           W.start_src, W.occ, W.occ_n);
         }
     }
     {
@@ -1842,9 +1908,11 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
             fwd_tile_det_kernel<<<(int)B.nbins, kTileThreadsDet, 0, s>>>(
                 W.tbin, rec, W.start, img, W.halo, W.halo + B.nbins * NHALO * 2, W.part);
         else if (B.tile_threads == 256)
-            fwd_tile_own_kernel<256><<<(int)B.nbins, 256, 0, s>>>(W.tbin, rec, W.start, img, W.part);
+            fwd_tile_own_kernel<256><<<tile_grid(B), 256, 0, s>>>(W.tbin, rec, W.start, W.occ,
+                                                                  W.occ_n, img, W.part);
         else
-            fwd_tile_own_kernel<512><<<(int)B.nbins, 512, 0, s>>>(W.tbin, rec, W.start, img, W.part);
+            fwd_tile_own_kernel<512><<<tile_grid(B), 512, 0, s>>>(W.tbin, rec, W.start, W.occ,
+                                                                  W.occ_n, img, W.part);
     }
     if (DET) {
         PhaseScope ph(prof, kPhReduce, s);

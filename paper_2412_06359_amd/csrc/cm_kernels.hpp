@@ -134,7 +134,7 @@ constexpr int kScanChunk = 16;  // histogram rows per chunk of the column scan
 
 // Byte offsets of the tiled path's buffers inside the workspace region.
 struct TileWorkspace {
-    size_t hist, csum, totals, start, part, halo, records, src, valid, win, motion, tbin, total;
+    size_t hist, csum, totals, start, occ, part, halo, records, src, valid, win, motion, tbin, total;
 };
 
 // What the forward tile kernel needs of its bin, in one record written with

@@ -278,7 +278,10 @@ class Server:
             for r in pending:
                 if not r.future.done():
                     r.future.set_exception(exc)
-            raise
+            # every client sees the failure (its future, submit(), drain());
+            # only an interpreter exit propagates further
+            if not isinstance(exc, Exception):
+                raise
 
     def _note_usage(self):
         self.max_used = max(self.max_used, self.used_bytes())
