@@ -689,7 +689,18 @@ constexpr int kTileThreads = 512;
 // records in a 33 x 33 LDS tile (the tile and its right column / bottom row
 // halo) in record order; column 0 and row 0 go to a border buffer and the
 // halo to a halo buffer, which the merge combines in a fixed order.
-__global__ __launch_bounds__(kTileThreadsDet) void fwd_tile_det_kernel(const TileBin* __restrict__ tbin,
+//
+// The order is per pixel: the bin's records 64 at a time, then tap slot 0..3,
+// then lane.  kDetAccWaves wavefronts walk the records in that order
+// together, each adding only the contributions to the LDS cells it owns
+// (cell index mod kDetAccWaves): every cell is updated by one wavefront in
+// the canonical order, so the bits are those of a single wavefront walking
+// all of them, and the serial part (one pass per distinct cell of a slot)
+// splits over the wavefronts.  The output and its reduction run on the first
+// kTileThreadsDet threads, in the order the reduction is defined on.
+constexpr int kDetAccWaves = 16;
+
+__global__ __launch_bounds__(64 * kDetAccWaves) void fwd_tile_det_kernel(const TileBin* __restrict__ tbin,
                                                        const SplatRec* __restrict__ rec,
                                                        const uint32_t* __restrict__ start,
                                                        double2* __restrict__ img_base,
@@ -725,11 +736,12 @@ __global__ __launch_bounds__(kTileThreadsDet) void fwd_tile_det_kernel(const Til
     for (int i = threadIdx.x; i < (2 * TLW * TLH + 31) / 32; i += blockDim.x) zbit[i] = 0u;
     __syncthreads();
     const double ref = bi.ref;
-    if (threadIdx.x < 64) {
-        // one wavefront walks the records in order, 64 at a time; per tap slot,
-        // equal cells are updated in lane order
+    {
+        // every wavefront walks the records in order, 64 at a time; per tap
+        // slot, equal cells among its own are updated in lane order
+        const int wave = (int)(threadIdx.x >> 6);
         for (uint32_t b0 = s0; b0 < s1; b0 += 64) {
-            const uint32_t i = b0 + threadIdx.x;
+            const uint32_t i = b0 + __lane_id();
             const bool live = i < s1;
             SplatRec q;
             if (live) q = rec[i];
@@ -741,10 +753,10 @@ __global__ __launch_bounds__(kTileThreadsDet) void fwd_tile_det_kernel(const Til
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const double wt = tap_w(tp, c);
-                const bool act = live && tap_in(tp, c) && wt != 0.0;
                 const int key = pol * TLW * TLH + (ly + (c >> 1)) * TLW + lx + (c & 1);
-                if (live && tap_in(tp, c) && wt == 0.0) atomicOr(&zbit[key >> 5], 1u << (key & 31));
-                ordered_add(lds, act, key, wt, wt * tb);
+                const bool mine = live && tap_in(tp, c) && key % kDetAccWaves == wave;
+                if (mine && wt == 0.0) atomicOr(&zbit[key >> 5], 1u << (key & 31));
+                ordered_add(lds, mine && wt != 0.0, key, wt, wt * tb);
             }
         }
     }
@@ -763,7 +775,7 @@ __global__ __launch_bounds__(kTileThreadsDet) void fwd_tile_det_kernel(const Til
     auto reached = [&](int k, const double2& c) {
         return c.x != 0.0 || c.y != 0.0 || ((zbit[k >> 5] >> (k & 31)) & 1u);
     };
-    for (int i = threadIdx.x; i < TW * TH; i += blockDim.x) {
+    for (int i = threadIdx.x; i < TW * TH && threadIdx.x < kTileThreadsDet; i += kTileThreadsDet) {
         const int lx = i % TW, ly = i / TW;
         const int X = xo + lx, Y = yo + ly;
         if (X >= bi.W || Y >= bi.H) continue;
@@ -787,7 +799,7 @@ __global__ __launch_bounds__(kTileThreadsDet) void fwd_tile_det_kernel(const Til
         hb[j * 2 + 1] = lds[TLW * TLH + idx];
     }
     double sc[2] = {sum, cnt};
-    block_sum_n(sc, red);
+    block_sum_n(sc, red, kTileThreadsDet / 64);
     if (threadIdx.x == 0) {
         part[(gbin * 2 + 0) * 2 + 0] = sc[0];
         part[(gbin * 2 + 0) * 2 + 1] = sc[1];
@@ -1323,8 +1335,11 @@ __global__ __launch_bounds__(NT, 3) void bwd_sweep_kernel(
 // adjoint) in LDS in record order; own pixels off the border get d rho and
 // their d theta share here, the border and the halo go to buffers for the
 // merge.
+// (the accumulation splits the cells over kDetAccWaves wavefronts as in
+// fwd_tile_det_kernel; the output and its reduction run on the first 256
+// threads)
 template <bool EXACT>
-__global__ __launch_bounds__(256) void bwd_tile_det_kernel(
+__global__ __launch_bounds__(64 * kDetAccWaves) void bwd_tile_det_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const GradRec* __restrict__ rec,
     const uint32_t* __restrict__ start, const float* __restrict__ rho,
     const float* __restrict__ ego, const float* __restrict__ grad_loss,
@@ -1359,9 +1374,10 @@ __global__ __launch_bounds__(256) void bwd_tile_det_kernel(
     }
     for (int i = threadIdx.x; i < TLW * TLH; i += blockDim.x) lds[i] = make_double2(0.0, 0.0);
     __syncthreads();
-    if (threadIdx.x < 64) {
+    {
+        const int wave = (int)(threadIdx.x >> 6);
         for (uint32_t b0 = s0; b0 < s1; b0 += 64) {
-            const uint32_t i = b0 + threadIdx.x;
+            const uint32_t i = b0 + __lane_id();
             const bool live = i < s1;
             GradRec q;
             if (live) q = rec[i];
@@ -1371,8 +1387,8 @@ __global__ __launch_bounds__(256) void bwd_tile_det_kernel(
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const double wt = tap_w(tp, c);
-                const bool act = live && tap_in(tp, c) && wt != 0.0;
                 const int key = (ly + (c >> 1)) * TLW + lx + (c & 1);
+                const bool act = live && tap_in(tp, c) && wt != 0.0 && key % kDetAccWaves == wave;
                 ordered_add(lds, act, key, wt * q.gx, wt * q.gy);
             }
         }
@@ -1389,7 +1405,7 @@ __global__ __launch_bounds__(256) void bwd_tile_det_kernel(
     float* drho_w = drho + meta[w].pix_off + (size_t)set * P.HW;
     const double gl = (double)grad_loss[w];
     double dth[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < TW * TH; i += blockDim.x) {
+    for (int i = threadIdx.x; i < TW * TH && threadIdx.x < 256; i += 256) {
         const int lx = i % TW, ly = i / TW;
         const int X = xo + lx, Y = yo + ly;
         if (X >= P.W || Y >= P.H) continue;
@@ -1415,7 +1431,7 @@ __global__ __launch_bounds__(256) void bwd_tile_det_kernel(
         const int idx = (j <= TH) ? j * TLW + TW : TH * TLW + (j - (TH + 1));
         hb[j] = lds[idx];
     }
-    block_sum_n(dth, red);
+    block_sum_n(dth, red, 256 / 64);
     if (threadIdx.x == 0)
 #pragma unroll
         for (int c = 0; c < 6; ++c) part[gtile * 12 + c] = dth[c];
@@ -1905,7 +1921,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     {
         PhaseScope ph(prof, kPhSplat, s);
         if (DET)
-            fwd_tile_det_kernel<<<(int)B.nbins, kTileThreadsDet, 0, s>>>(
+            fwd_tile_det_kernel<<<(int)B.nbins, 64 * kDetAccWaves, 0, s>>>(
                 W.tbin, rec, W.start, img, W.halo, W.halo + B.nbins * NHALO * 2, W.part);
         else if (B.tile_threads == 256)
             fwd_tile_own_kernel<256><<<tile_grid(B), 256, 0, s>>>(W.tbin, rec, W.start, W.occ,
@@ -2000,7 +2016,7 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
         PhaseScope ph(prof, kPhGradTile, s);
         if (DET) {
             double2* border = W.halo + B.nbins_b * NHALO;
-            bwd_tile_det_kernel<EX><<<(int)B.nbins_b, 256, 0, s>>>(
+            bwd_tile_det_kernel<EX><<<(int)B.nbins_b, 64 * kDetAccWaves, 0, s>>>(
                 meta, nw, win_tile, rec, W.start, rho, ego, grad_loss, grad_rho, W.halo, border,
                 W.part);
             bwd_merge_kernel<EX><<<(int)((B.nbins_b + kMergeBins - 1) / kMergeBins),

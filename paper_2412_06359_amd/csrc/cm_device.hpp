@@ -752,8 +752,11 @@ __device__ __forceinline__ double block_sum(double v, double* lds /* >= 16 */)
 
 // K block_sum reductions in one pass: each value is added up in block_sum's
 // order, with one pair of barriers for all of them.  Results in thread 0.
+// nwaves (default: all of the block's) is the number of leading wavefronts
+// whose values count, as if the block had only those.
 template <int K>
-__device__ __forceinline__ void block_sum_n(double (&v)[K], double* lds /* >= 16 K */)
+__device__ __forceinline__ void block_sum_n(double (&v)[K], double* lds /* >= 16 K */,
+                                            int nwaves = 0)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
@@ -766,7 +769,7 @@ __device__ __forceinline__ void block_sum_n(double (&v)[K], double* lds /* >= 16
         for (int k = 0; k < K; ++k) lds[16 * k + wid] = v[k];
     __syncthreads();
     if (threadIdx.x == 0) {
-        const int nw = blockDim.x >> 6;
+        const int nw = nwaves > 0 ? nwaves : (int)(blockDim.x >> 6);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             double s = 0.0;

@@ -2,8 +2,9 @@
 //
 //   fill_zero          clears the splat images and per-window sums
 //   splat_kernel       per event: iterative warp (FP64) + bilinear splat into
-//                      the per-polarity images C and S with FP32 atomics
-//                      (paper Sec. 3.1, Fig. 2; Sec. 3.3 per-event forward)
+//                      the per-polarity images C and S with FP64 global
+//                      atomics (paper Sec. 3.1, Fig. 2; Sec. 3.3 per-event
+//                      forward)
 //   reduce_kernel      per reference: sum_x sum_p (S_p/(C_p+eps))^2 and the
 //                      active-pixel count (Eq. 1), FP64 block partials
 //   finalize_forward   fixed-order sum of the partials, mean over references
