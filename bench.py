@@ -318,12 +318,13 @@ def serve_stream(cm, seconds: float, rate: float, budget_gib: float) -> dict:
             "latency_includes": "H2D copy of the window, batching wait, fwd+bwd, loss D2H"}
 
 
-def serve_saturation(cm, budget_gib: float, seconds: float = 2.0, start_rate: float = 500.0,
+def serve_saturation(cm, budget_gib: float, seconds: float = 3.0, start_rate: float = 500.0,
                      max_levels: int = 7) -> dict:
     """The c4 stream at rising Poisson rates (doubling from start_rate), a
     fresh server per level, until the server no longer keeps up: served
-    events/s below 90 % of the offered rate, or p99 above 100 ms.  Reports
-    every level and the highest rate sustained, with its p50/p99."""
+    events/s below 95 % of the offered rate.  Reports every level (p50/p99
+    included: latency grows with the queue as the rate nears saturation) and
+    the highest rate sustained."""
     import eventgen
     pool = eventgen.stream_pool(2, 500_000)
     levels = []
@@ -332,8 +333,7 @@ def serve_saturation(cm, budget_gib: float, seconds: float = 2.0, start_rate: fl
     for lvl in range(max_levels):
         st = _serve_run(cm, pool, rate, seconds, budget_gib, seed=100 + lvl)
         ok = (st["events_per_s"] is not None and
-              st["events_per_s"] >= 0.9 * st["offered_events_per_s"] and
-              st["p99_ms"] is not None and st["p99_ms"] <= 100.0)
+              st["events_per_s"] >= 0.95 * st["offered_events_per_s"])
         levels.append({"rate_windows_per_s": rate, "offered_events_per_s": st["offered_events_per_s"],
                        "events_per_s": st["events_per_s"], "p50_ms": st["p50_ms"],
                        "p99_ms": st["p99_ms"], "windows": st["windows"],
@@ -348,7 +348,7 @@ def serve_saturation(cm, budget_gib: float, seconds: float = 2.0, start_rate: fl
     return {"workload": "c4 windows (346x260/640x480 50/50, log-uniform 1k..500k events, refs "
                         "{0,1}, fwd+bwd), Poisson arrivals, rate doubled per level, "
                         f"{seconds:.0f} s per level",
-            "criterion": "served >= 90% of offered events/s and p99 <= 100 ms",
+            "criterion": "served >= 95% of offered events/s",
             "max_sustained": sustained, "levels": levels}
 
 
@@ -402,7 +402,7 @@ def main():
                     help="length of the served Poisson stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=500.0)
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
-    ap.add_argument("--saturation-seconds", type=float, default=2.0,
+    ap.add_argument("--saturation-seconds", type=float, default=3.0,
                     help="seconds per level of the rising-rate serving run (0: skip)")
     ap.add_argument("--tuning", default=None,
                     help="EVENT_BLOCKS,TILE_THREADS for the batched workload instead of the "

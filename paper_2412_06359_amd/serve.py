@@ -180,7 +180,8 @@ class Server:
         self.t_first = None
         self.t_last = None
         torch.cuda.synchronize(device)
-        self._base = torch.cuda.memory_allocated(device)
+        self._base = torch.cuda.memory_stats_as_nested_dict(device)["allocated_bytes"]["all"][
+            "current"]
         torch.cuda.reset_peak_memory_stats(device)
         self._thread = threading.Thread(target=self._loop, name="cm-server", daemon=True)
         self._thread.start()
@@ -188,8 +189,12 @@ class Server:
     # -- client side ------------------------------------------------------
     def used_bytes(self) -> int:
         """Device memory allocated on the server's device since the server
-        started (what the budget bounds)."""
-        return torch.cuda.memory_allocated(self.device) - self._base
+        started (what the budget bounds).  Read from the allocator's nested
+        statistics: torch.cuda.memory_allocated() flattens the whole
+        statistics dictionary on every call, which cost the scheduler a
+        quarter of its time."""
+        st = torch.cuda.memory_stats_as_nested_dict(self.device)
+        return st["allocated_bytes"]["all"]["current"] - self._base
 
     def submit(self, window) -> Future:
         if self._failed is not None:
@@ -404,11 +409,13 @@ class Server:
                 ("p", np.int8, n), ("rho", np.float32, batch.pixel_offsets[-1]),
                 ("ego", np.float32, 6 * batch.set_offsets[-1])]
         host, tv = staging.arrays(spec)
+        # one copy per field into the pinned buffer (strided event arrays go in
+        # as they are; concatenate casts to the buffer's dtype)
         for name, field in (("x", "x"), ("y", "y"), ("t", "t"), ("p", "p"), ("rho", "rho"),
                             ("ego", "theta")):
-            dt = host[name].dtype
-            np.concatenate([np.asarray(getattr(w, field), dtype=dt).ravel() for w in wins],
-                           out=host[name])
+            parts = [np.asarray(getattr(w, field)) for w in wins]
+            np.concatenate([a if a.ndim == 1 else a.reshape(-1) for a in parts],
+                           out=host[name], casting="same_kind")
         with torch.cuda.stream(stream):
             # one device workspace per slot: inputs, state, loss, grad_loss
             sizes = _workspace_sizes(batch, tv)
