@@ -41,7 +41,7 @@ from __future__ import annotations
 import collections
 import threading
 import time
-from concurrent.futures import Future
+from concurrent.futures import Future, ThreadPoolExecutor
 from typing import List
 
 import numpy as np
@@ -158,8 +158,13 @@ class Server:
     """Continuous-batching server for CM loss + gradient requests on one GPU."""
 
     def __init__(self, budget_bytes: int, max_batch: int = 64, n_streams: int = 2,
-                 device: int = 0, mode: int = binding.CM_MODE_ATOMIC, poll_s: float = 50e-6):
+                 device: int = 0, mode: int = binding.CM_MODE_ATOMIC, poll_s: float = 50e-6,
+                 copy_threads: int = 6, parallel_copy_bytes: int = 8 << 20):
         self.budget = int(budget_bytes)
+        # host threads for the staging copies of large batches
+        self.parallel_copy_bytes = parallel_copy_bytes
+        self._copier = ThreadPoolExecutor(max_workers=max(1, copy_threads),
+                                          thread_name_prefix="cm-copy")
         self.max_batch = max_batch
         self.device = device
         self.mode = mode
@@ -219,6 +224,7 @@ class Server:
         self._thread.join(timeout)
         if self._thread.is_alive():
             raise TimeoutError("server did not finish its requests")
+        self._copier.shutdown(wait=True)
 
     def drain(self, timeout: float = 60.0):
         t0 = time.perf_counter()
@@ -409,13 +415,35 @@ class Server:
                 ("p", np.int8, n), ("rho", np.float32, batch.pixel_offsets[-1]),
                 ("ego", np.float32, 6 * batch.set_offsets[-1])]
         host, tv = staging.arrays(spec)
-        # one copy per field into the pinned buffer (strided event arrays go in
-        # as they are; concatenate casts to the buffer's dtype)
+        # every window's fields into the pinned buffer (strided event arrays go
+        # in as they are, cast to the buffer's dtype); large batches split the
+        # copies over a few host threads (numpy releases the GIL in them)
+        # (a job: one field of a run of consecutive windows, one concatenation)
+        jobs = []
+        split = 4 if len(wins) >= 8 else 1
         for name, field in (("x", "x"), ("y", "y"), ("t", "t"), ("p", "p"), ("rho", "rho"),
                             ("ego", "theta")):
             parts = [np.asarray(getattr(w, field)) for w in wins]
-            np.concatenate([a if a.ndim == 1 else a.reshape(-1) for a in parts],
-                           out=host[name], casting="same_kind")
+            parts = [a if a.ndim == 1 else a.reshape(-1) for a in parts]
+            k = split if name in ("rho", "x", "y", "t") else 1
+            bounds = [len(parts) * i // k for i in range(k + 1)]
+            o = 0
+            for i in range(k):
+                chunk = parts[bounds[i]:bounds[i + 1]]
+                sz = sum(a.size for a in chunk)
+                if sz:
+                    jobs.append((host[name][o:o + sz], chunk))
+                o += sz
+        total = sum(sum(a.nbytes for a in c) for _, c in jobs)
+
+        def run(job):
+            dst, chunk = job
+            np.concatenate(chunk, out=dst, casting="same_kind")
+        if total >= self.parallel_copy_bytes and len(jobs) > 1:
+            list(self._copier.map(run, jobs))
+        else:
+            for job in jobs:
+                run(job)
         with torch.cuda.stream(stream):
             # one device workspace per slot: inputs, state, loss, grad_loss
             sizes = _workspace_sizes(batch, tv)
