@@ -144,16 +144,22 @@ cm_status cm_set_path(cm_handle h, int path);
  *   tiled_min_records : CM_PATH_AUTO takes the tiled path for single windows
  *                       with at least this many event-reference records,
  *                       >= 1, default 131072
- * event_blocks and tile_threads apply to batch plans created after the call,
- * in the atomic mode only (the deterministic mode's launch geometry defines
- * its operation order and is fixed); single-window calls keep the default
- * geometry, which cm_state_bytes sizes.  Results in the atomic mode agree
- * across tunings within rounding.  CM_ERR_INVALID_ARG for values out of
- * range, with the handle unchanged. */
+ *   tile_w, tile_h    : the tiled path's tile size, 32 x 32 (default),
+ *                       64 x 32, 32 x 16 or 16 x 16; a plan whose windows
+ *                       would need more than 16384 bins at that size takes
+ *                       32 x 32
+ * event_blocks, tile_threads and the tile size apply to batch plans created
+ * after the call, in the atomic mode only (the deterministic mode's launch
+ * geometry and 32 x 32 tiles define its operation order and are fixed);
+ * single-window calls keep the default geometry, which cm_state_bytes sizes.
+ * Results in the atomic mode agree across tunings within rounding.
+ * CM_ERR_INVALID_ARG for values out of range, with the handle unchanged. */
 typedef struct {
     int32_t event_blocks;
     int32_t tile_threads;
     int64_t tiled_min_records;
+    int32_t tile_w;
+    int32_t tile_h;
 } cm_tuning;
 cm_status cm_set_tuning(cm_handle h, const cm_tuning* t);
 cm_status cm_get_tuning(cm_handle h, cm_tuning* out);

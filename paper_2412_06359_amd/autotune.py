@@ -1,14 +1,16 @@
 """Autotuner for batched launches.
 
-A batch's launch shape in the atomic mode has two tunables (cm_tuning): the
-number of event blocks the count / scatter / sweep kernels aim for (which sets
-events per lane) and the forward tile kernel's thread count.  `tune` times
-each candidate on a real batch -- forward + backward, replayed from a
-hipGraph, between HIP events on the current stream -- and returns the
-fastest.  Results are cached per shape class (mode, flow model, references,
-flow sets, sensor size, total events and window count, the last three
-rounded to powers of two) in a JSON file, so that a serving loop or a
-training run tunes once per class:
+A batch's launch shape in the atomic mode has three tunables (cm_tuning):
+the number of event blocks the count / scatter / sweep kernels aim for
+(which sets events per lane), the forward tile kernel's thread count, and
+the tile size of the owner-computes splat and backward (32 x 32, 64 x 32,
+32 x 16 or 16 x 16).  `tune` times candidates on a real batch -- forward +
+backward, replayed from a hipGraph, between HIP events on the current stream
+-- and returns the fastest: by default event blocks x tile threads at 32 x 32
+tiles first, then the other tile sizes at the best pair.  Results are cached
+per shape class (mode, flow model, references, flow sets, sensor size, total
+events and window count, the last three rounded to powers of two) in a JSON
+file, so that a serving loop or a training run tunes once per class:
 
     from paper_2412_06359_amd import autotune
     tuning = autotune.tune(descs, counts, inputs, cache_path="tune.json")
@@ -28,9 +30,17 @@ import torch
 
 from . import binding as cm
 
-DEFAULT = dict(event_blocks=4096, tile_threads=512)
-CANDIDATES = [dict(event_blocks=e, tile_threads=t)
+DEFAULT = dict(event_blocks=4096, tile_threads=512, tile_w=32, tile_h=32)
+# first stage: launch geometry at 32 x 32 tiles; second stage: tile sizes
+CANDIDATES = [dict(event_blocks=e, tile_threads=t, tile_w=32, tile_h=32)
               for e in (1024, 2048, 4096, 8192, 16384) for t in (256, 512)]
+TILE_SIZES = [(32, 32), (64, 32), (32, 16), (16, 16)]
+
+
+def _tuning(d: dict) -> dict:
+    """A cached or given tuning with every field (older caches lack the tile size)."""
+    return dict(event_blocks=int(d["event_blocks"]), tile_threads=int(d["tile_threads"]),
+                tile_w=int(d.get("tile_w", 32)), tile_h=int(d.get("tile_h", 32)))
 
 
 def _pow2(v: float) -> int:
@@ -105,21 +115,29 @@ def tune(descs: Sequence[cm.WindowDesc], n_events: Sequence[int], inputs: Option
     key = shape_class(descs, n_events)
     cache = load_cache(path)
     if key in cache:
-        hit = cache[key]
-        return dict(event_blocks=int(hit["event_blocks"]), tile_threads=int(hit["tile_threads"]))
+        return _tuning(cache[key])
     if inputs is None:
         return dict(DEFAULT)
     best, best_ms = None, float("inf")
-    for cand in candidates or CANDIDATES:
-        b = cm.Batch(descs, n_events, device=device, graph=True, tuning=cand)
-        try:
-            ms = time_step(b, inputs, steps, warmup)
-        finally:
-            b.close()
-        if log is not None:
-            log.append((dict(cand), ms))
-        if ms < best_ms:
-            best, best_ms = dict(cand), ms
+
+    def run(cands):
+        nonlocal best, best_ms
+        for cand in cands:
+            b = cm.Batch(descs, n_events, device=device, graph=True, tuning=cand)
+            try:
+                ms = time_step(b, inputs, steps, warmup)
+            finally:
+                b.close()
+            if log is not None:
+                log.append((dict(cand), ms))
+            if ms < best_ms:
+                best, best_ms = _tuning(cand), ms
+    if candidates is not None:
+        run(candidates)
+    else:
+        run(CANDIDATES)
+        run([dict(best, tile_w=w, tile_h=h) for w, h in TILE_SIZES
+             if (w, h) != (best["tile_w"], best["tile_h"])])
     if path:
         cache = load_cache(path)
         cache[key] = dict(best, ms=best_ms)

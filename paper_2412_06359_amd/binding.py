@@ -88,11 +88,13 @@ class Tuning(ctypes.Structure):
     tiled crossover of single windows; zero fields keep the defaults."""
 
     _fields_ = [("event_blocks", ctypes.c_int32), ("tile_threads", ctypes.c_int32),
-                ("tiled_min_records", ctypes.c_int64)]
+                ("tiled_min_records", ctypes.c_int64), ("tile_w", ctypes.c_int32),
+                ("tile_h", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return dict(event_blocks=int(self.event_blocks), tile_threads=int(self.tile_threads),
-                    tiled_min_records=int(self.tiled_min_records))
+                    tiled_min_records=int(self.tiled_min_records), tile_w=int(self.tile_w),
+                    tile_h=int(self.tile_h))
 
 
 _lib = None
@@ -221,10 +223,11 @@ def get_tuning(device: int = 0) -> dict:
 
 
 def set_tuning(device: int = 0, event_blocks: int = 0, tile_threads: int = 0,
-               tiled_min_records: int = 0) -> dict:
+               tiled_min_records: int = 0, tile_w: int = 0, tile_h: int = 0) -> dict:
     """cm_set_tuning on this device's handle (0 keeps a field's default);
     returns the tuning now in effect."""
-    t = Tuning(int(event_blocks), int(tile_threads), int(tiled_min_records))
+    t = Tuning(int(event_blocks), int(tile_threads), int(tiled_min_records), int(tile_w),
+               int(tile_h))
     _check(load().cm_set_tuning(handle(device), ctypes.byref(t)), "cm_set_tuning")
     return get_tuning(device)
 
@@ -401,8 +404,9 @@ class Batch:
 
     def __init__(self, descs: Sequence[WindowDesc], n_events: Sequence[int], device: int = 0,
                  graph: bool = False, tuning: Optional[dict] = None):
-        """tuning: dict(event_blocks=, tile_threads=) for this plan (atomic
-        mode), e.g. from autotune.tune; None takes the handle's current one."""
+        """tuning: dict(event_blocks=, tile_threads=, tile_w=, tile_h=) for this
+        plan (atomic mode), e.g. from autotune.tune; absent fields take the
+        defaults; None takes the handle's current tuning."""
         lib = load()
         n = len(descs)
         self.device = device
@@ -416,7 +420,8 @@ class Batch:
             _check(lib.cm_get_tuning(h, ctypes.byref(prev)), "cm_get_tuning")
             if tuning is not None:
                 t = Tuning(int(tuning.get("event_blocks", 0)), int(tuning.get("tile_threads", 0)),
-                           int(prev.tiled_min_records))
+                           int(prev.tiled_min_records), int(tuning.get("tile_w", 0)),
+                           int(tuning.get("tile_h", 0)))
                 _check(lib.cm_set_tuning(h, ctypes.byref(t)), "cm_set_tuning")
             try:
                 st = lib.cm_batch_create(h, n, arr, cnt, ctypes.byref(self._b))

@@ -344,9 +344,16 @@ cm_status cm_set_tuning(cm_handle h, const cm_tuning* t)
     const int eb = t->event_blocks ? t->event_blocks : 4096;
     const int tt = t->tile_threads ? t->tile_threads : 512;
     const int64_t tm = t->tiled_min_records ? t->tiled_min_records : kTiledMinRecords;
-    if (eb < 256 || eb > 65536 || (tt != 256 && tt != 512) || tm < 1) return CM_ERR_INVALID_ARG;
+    const int tw = t->tile_w ? t->tile_w : 32;
+    const int th = t->tile_h ? t->tile_h : 32;
+    const bool tile_ok = (tw == 32 && th == 32) || (tw == 64 && th == 32) ||
+                         (tw == 32 && th == 16) || (tw == 16 && th == 16);
+    if (eb < 256 || eb > 65536 || (tt != 256 && tt != 512) || tm < 1 || !tile_ok)
+        return CM_ERR_INVALID_ARG;
     h->tune.event_blocks = eb;
     h->tune.tile_threads = tt;
+    h->tune.tile_w = tw;
+    h->tune.tile_h = th;
     h->tiled_min_records = tm;
     return CM_OK;
 }
@@ -357,6 +364,8 @@ cm_status cm_get_tuning(cm_handle h, cm_tuning* out)
     out->event_blocks = h->tune.event_blocks;
     out->tile_threads = h->tune.tile_threads;
     out->tiled_min_records = h->tiled_min_records;
+    out->tile_w = h->tune.tile_w;
+    out->tile_h = h->tune.tile_h;
     return CM_OK;
 }
 
@@ -716,8 +725,8 @@ cm_status cm_batch_occupied_image_bytes(cm_batch b, const void* state, double* o
             if (start[gb + 1] == start[gb]) continue;
             const int tile = bin % M.G.ntiles;
             const int tx = tile % M.G.ntx, ty = tile / M.G.ntx;
-            const int pw = std::min(cm::TW, M.P.W - tx * cm::TW);
-            const int ph = std::min(cm::TH, M.P.H - ty * cm::TH);
+            const int pw = std::min(M.G.tw, M.P.W - tx * M.G.tw);
+            const int ph = std::min(M.G.th, M.P.H - ty * M.G.th);
             bytes += 2.0 * 16.0 * pw * ph;      // C and S, FP64, both polarities
         }
         out[w] = bytes;

@@ -28,6 +28,8 @@
 // over prefix offsets), the motion coefficients of every flow set and, per
 // forward bin, the few values its tile and merge kernels need.  A single
 // window is a batch of one.
+#include <type_traits>
+
 #include "cm_kernels.hpp"
 
 namespace cm {
@@ -638,8 +640,8 @@ __global__ __launch_bounds__(256) void window_table_kernel(const WinMeta* __rest
         b.plane = meta[w].img_off + (int64_t)r * 2 * P.HW;
         b.W = P.W;
         b.H = P.H;
-        b.xo = tx * TW;
-        b.yo = ty * TH;
+        b.xo = tx * meta[w].G.tw;
+        b.yo = ty * meta[w].G.th;
         b.ntx = meta[w].G.ntx;
         b.pad = 0;
         tbin[i] = b;
@@ -806,7 +808,8 @@ __global__ __launch_bounds__(64 * kDetAccWaves) void fwd_tile_det_kernel(const T
     }
 }
 
-// Atomic mode: a (reference, tile) bin owns the tile's 32 x 32 pixels.  Its
+// Atomic mode: a (reference, tile) bin owns the tile's pixels (TWX x THX, the
+// plan's tile size; 32 x 32 by default).  Its
 // bin holds every record whose taps reach the tile (its own positions and the
 // copies from the left, upper and upper-left neighbours), so its workgroup
 // accumulates the taps that fall in the tile with FP64 LDS atomics, stores the
@@ -819,7 +822,7 @@ __global__ __launch_bounds__(64 * kDetAccWaves) void fwd_tile_det_kernel(const T
 // The first records are loaded before the LDS tile is cleared.  C and S
 // accumulate in separate LDS arrays (8-byte stride: half the bank conflicts
 // of interleaved pairs).
-template <int NTT>
+template <int NTT, int TWX, int THX>
 __global__ __launch_bounds__(NTT) void fwd_tile_own_kernel(const TileBin* __restrict__ tbin,
                                                            const SplatRec* __restrict__ rec,
                                                            const uint32_t* __restrict__ start,
@@ -828,7 +831,7 @@ __global__ __launch_bounds__(NTT) void fwd_tile_own_kernel(const TileBin* __rest
                                                            double2* __restrict__ img_base,
                                                            double* __restrict__ part)
 {
-    constexpr int NPIX = TW * TH;
+    constexpr int NPIX = TWX * THX;
     __shared__ double lc[2 * NPIX];       // C by polarity, then pixel
     __shared__ double ls[2 * NPIX];       // S
     // pixels reached only by zero-weight taps (positions on a pixel row or
@@ -872,11 +875,11 @@ __global__ __launch_bounds__(NTT) void fwd_tile_own_kernel(const TileBin* __rest
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const int cx = lx + (c & 1), cy = ly + (c >> 1);
-                    if (!tap_in(tp, c) || (unsigned)cx >= (unsigned)TW ||
-                        (unsigned)cy >= (unsigned)TH)
+                    if (!tap_in(tp, c) || (unsigned)cx >= (unsigned)TWX ||
+                        (unsigned)cy >= (unsigned)THX)
                         continue;
                     const double wt = tap_w(tp, c);
-                    const int key = pol * NPIX + cy * TW + cx;
+                    const int key = pol * NPIX + cy * TWX + cx;
                     if (wt == 0.0) {
                         atomicOr(&zbit[key >> 5], 1u << (key & 31));
                         continue;
@@ -907,7 +910,7 @@ __global__ __launch_bounds__(NTT) void fwd_tile_own_kernel(const TileBin* __rest
             return c.x != 0.0 || c.y != 0.0 || ((zbit[kk >> 5] >> (kk & 31)) & 1u);
         };
         for (int i = threadIdx.x; i < NPIX; i += NTT) {
-            const int X = xo + (i % TW), Y = yo + (i / TW);
+            const int X = xo + (i % TWX), Y = yo + (i / TWX);
             if (X >= bi.W || Y >= bi.H) continue;
             const double2 a = make_double2(lc[i], ls[i]);
             const double2 b = make_double2(lc[NPIX + i], ls[NPIX + i]);
@@ -1438,19 +1441,19 @@ __global__ __launch_bounds__(64 * kDetAccWaves) void bwd_tile_det_kernel(
 }
 
 // Atomic mode: one workgroup per backward bin (flow set, tile of a window)
-// owns the tile's 32 x 32 pixels.  Its records are every sampling position
+// owns the tile's TWX x THX pixels.  Its records are every sampling position
 // whose taps reach the tile (with AE, its source bin's records, indexed like
 // the source records); it accumulates dL/du at the taps inside the tile in
 // LDS, then writes d rho of every pixel and reduces the tile's d theta share.
 // No halo, no merge.
-template <bool EXACT, bool AE>
+template <bool EXACT, bool AE, int TWX, int THX>
 __global__ __launch_bounds__(256) void bwd_tile_own_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const GradRec* __restrict__ rec,
     const uint32_t* __restrict__ start, const uint32_t* __restrict__ start_src,
     const float* __restrict__ rho, const float* __restrict__ ego, const float* __restrict__ grad_loss,
     float* __restrict__ drho, double* __restrict__ part)
 {
-    constexpr int NT = 256, NPIX = TW * TH;
+    constexpr int NT = 256, NPIX = TWX * THX;
     __shared__ double2 lds[NPIX];
     __shared__ double red[16 * 6];
     const int64_t gtile = blockIdx.x;       // backward bin: (flow set, tile) of a window
@@ -1460,7 +1463,7 @@ __global__ __launch_bounds__(256) void bwd_tile_own_kernel(
     const int lbin = (int)(gtile - meta[w].bbin_off);
     const int set = lbin / G.ntiles, tile = lbin - set * G.ntiles;
     const int ty = tile / G.ntx, tx = tile - ty * G.ntx;
-    const int xo = tx * TW, yo = ty * TH;
+    const int xo = tx * TWX, yo = ty * THX;
     const uint32_t s0 = AE ? start_src[meta[w].sbin_off + tile] : start[gtile];
     const uint32_t s1 = AE ? start_src[meta[w].sbin_off + tile + 1] : start[gtile + 1];
     float* drho_w = drho + meta[w].pix_off + (size_t)set * P.HW;
@@ -1469,7 +1472,7 @@ __global__ __launch_bounds__(256) void bwd_tile_own_kernel(
         // no records: dL/du is zero on the tile
         const float z = (float)(gl * 0.0);
         for (int i = threadIdx.x; i < NPIX; i += NT) {
-            const int X = xo + i % TW, Y = yo + i / TW;
+            const int X = xo + i % TWX, Y = yo + i / TWX;
             if (X < P.W && Y < P.H) drho_w[Y * P.W + X] = z;
         }
         if (threadIdx.x < 12) part[gtile * 12 + threadIdx.x] = 0.0;
@@ -1495,11 +1498,11 @@ __global__ __launch_bounds__(256) void bwd_tile_own_kernel(
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int cx = lx + (c & 1), cy = ly + (c >> 1);
-                if (!tap_in(tp, c) || (unsigned)cx >= (unsigned)TW || (unsigned)cy >= (unsigned)TH)
+                if (!tap_in(tp, c) || (unsigned)cx >= (unsigned)TWX || (unsigned)cy >= (unsigned)THX)
                     continue;
                 const double wt = tap_w(tp, c);
                 if (wt == 0.0) continue;
-                double2* cell = lds + cy * TW + cx;
+                double2* cell = lds + cy * TWX + cx;
                 atomicAdd(&cell->x, wt * q.gx);
                 atomicAdd(&cell->y, wt * q.gy);
             }
@@ -1521,7 +1524,7 @@ __global__ __launch_bounds__(256) void bwd_tile_own_kernel(
     const float* rho_w = rho + meta[w].pix_off + (size_t)set * P.HW;
     double dth[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int i = threadIdx.x; i < NPIX; i += NT) {
-        const int X = xo + i % TW, Y = yo + i / TW;
+        const int X = xo + i % TWX, Y = yo + i / TWX;
         if (X >= P.W || Y >= P.H) continue;
         const double2 g = lds[i];
         const int pix = Y * P.W + X;
@@ -1669,11 +1672,22 @@ static int bin_threads(bool det) { return det ? 64 : kBinThreads; }
 // 4096): a few waves of the 256 CUs, so that every block warps several events
 // per lane and the next event's loads overlap the current one's gathers.
 
-TileGeom tile_geom(const WinParams& P, int64_t n, bool det, int min_ept)
+static int log2_of(int v)
+{
+    int s = 0;
+    while ((1 << s) < v) ++s;
+    return s;
+}
+
+TileGeom tile_geom(const WinParams& P, int64_t n, bool det, int min_ept, int tw, int th)
 {
     TileGeom G;
-    G.ntx = (P.W + TW - 1) / TW;
-    G.nty = (P.H + TH - 1) / TH;
+    G.tw = det ? TW : tw;
+    G.th = det ? TH : th;
+    G.tws = log2_of(G.tw);
+    G.ths = log2_of(G.th);
+    G.ntx = (P.W + G.tw - 1) / G.tw;
+    G.nty = (P.H + G.th - 1) / G.th;
     G.ntiles = G.ntx * G.nty;
     G.nbins = P.R * G.ntiles;
     G.nbins_b = P.F * G.ntiles;
@@ -1697,7 +1711,7 @@ static bool samples_at_events(const WinParams& P)
 
 bool tiled_supported(const WinParams& P, int64_t n, bool det)
 {
-    const TileGeom G = tile_geom(P, n, det, 1);
+    const TileGeom G = tile_geom(P, n, det, 1, TW, TH);
     // record slots are 32-bit: up to four per position in the atomic mode
     return G.nbins + G.nbins_s <= kMaxBins && G.nbins_b <= kMaxBins &&
            n * (int64_t)(P.R + 1) < ((int64_t)1 << 29);
@@ -1711,6 +1725,18 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     B.det = det;
     B.tile_threads = det ? kTileThreadsDet : tune.tile_threads;
     const int64_t target_blocks = tune.event_blocks;
+    // the tile size (atomic mode): the tuning's, unless a window would then
+    // need more bins than the LDS histograms hold
+    B.tile_w = det ? TW : tune.tile_w;
+    B.tile_h = det ? TH : tune.tile_h;
+    for (int w = 0; w < nw && !det; ++w) {
+        const TileGeom g = tile_geom(params[w], n_events[w], false, 1, B.tile_w, B.tile_h);
+        if (g.nbins + g.nbins_s > kMaxBins || g.nbins_b > kMaxBins) {
+            B.tile_w = TW;
+            B.tile_h = TH;
+            break;
+        }
+    }
     B.meta.resize(nw);
     int64_t ev = 0, pix = 0, sets = 0, img = 0, hist = 0, csum = 0, bin = 0, bbin = 0, sbin = 0;
     int64_t blk = 0, cf = 0, cb = 0, recs = 0;
@@ -1733,7 +1759,7 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
         WinMeta& M = B.meta[w];
         std::memset(&M, 0, sizeof M);
         M.P = params[w];
-        M.G = tile_geom(M.P, n_events[w], det, min_ept);
+        M.G = tile_geom(M.P, n_events[w], det, min_ept, B.tile_w, B.tile_h);
         M.nchunks = (M.G.nblocks + kScanChunk - 1) / kScanChunk;
         M.ev_off = ev;
         M.n = n_events[w];
@@ -1821,7 +1847,32 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
 // fit the chip at once, so that those freed early take the remaining ones.
 static int tile_grid(const BatchPlanHost& B)
 {
-    return (int)std::max<int64_t>(1, std::min<int64_t>(B.nbins, 2048));
+    const int64_t lds = 2LL * B.tile_w * B.tile_h * 16 + 1024;
+    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(160 * 1024 / lds,
+                                                                   32 / (B.tile_threads / 64)));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(B.nbins, 2 * 256 * per_cu));
+}
+
+template <int NTT, int TWX, int THX>
+static void launch_fwd_tile_own(const BatchPlanHost& B, const TileBin* tbin, const SplatRec* rec,
+                                const uint32_t* start, const uint32_t* occ, const uint32_t* occ_n,
+                                double2* img, double* part, hipStream_t s)
+{
+    fwd_tile_own_kernel<NTT, TWX, THX><<<tile_grid(B), NTT, 0, s>>>(tbin, rec, start, occ, occ_n,
+                                                                    img, part);
+}
+
+// The atomic mode's tile sizes (the tuning's choice; 32 x 32 by default).
+template <typename F>
+static void with_tile(const BatchPlanHost& B, F&& f)
+{
+    using I64 = std::integral_constant<int, 64>;
+    using I32 = std::integral_constant<int, 32>;
+    using I16 = std::integral_constant<int, 16>;
+    if (B.tile_w == 64 && B.tile_h == 32) f(I64(), I32());
+    else if (B.tile_w == 32 && B.tile_h == 16) f(I32(), I16());
+    else if (B.tile_w == 16 && B.tile_h == 16) f(I16(), I16());
+    else f(I32(), I32());
 }
 
 static void launch_window_table(const BatchPlanHost& B, const WinMeta* meta, int* tab,
@@ -1923,12 +1974,16 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
         if (DET)
             fwd_tile_det_kernel<<<(int)B.nbins, 64 * kDetAccWaves, 0, s>>>(
                 W.tbin, rec, W.start, img, W.halo, W.halo + B.nbins * NHALO * 2, W.part);
-        else if (B.tile_threads == 256)
-            fwd_tile_own_kernel<256><<<tile_grid(B), 256, 0, s>>>(W.tbin, rec, W.start, W.occ,
-                                                                  W.occ_n, img, W.part);
         else
-            fwd_tile_own_kernel<512><<<tile_grid(B), 512, 0, s>>>(W.tbin, rec, W.start, W.occ,
-                                                                  W.occ_n, img, W.part);
+            with_tile(B, [&](auto twc, auto thc) {
+                constexpr int TWX = decltype(twc)::value, THX = decltype(thc)::value;
+                if (B.tile_threads == 256)
+                    launch_fwd_tile_own<256, TWX, THX>(B, W.tbin, rec, W.start, W.occ, W.occ_n,
+                                                       img, W.part, s);
+                else
+                    launch_fwd_tile_own<512, TWX, THX>(B, W.tbin, rec, W.start, W.occ, W.occ_n,
+                                                       img, W.part, s);
+            });
     }
     if (DET) {
         PhaseScope ph(prof, kPhReduce, s);
@@ -2023,14 +2078,18 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
                                    64 * kMergeBins, 0, s>>>(meta, nw, B.nbins_b, win_tile, rho,
                                                             ego, grad_loss, W.start, grad_rho,
                                                             W.halo, border, W.part);
-        } else if (ae) {
-            bwd_tile_own_kernel<EX, true><<<(int)B.nbins_b, 256, 0, s>>>(
-                meta, nw, win_tile, rec, W.start, W.start_src, rho, ego, grad_loss, grad_rho,
-                W.part);
         } else {
-            bwd_tile_own_kernel<EX, false><<<(int)B.nbins_b, 256, 0, s>>>(
-                meta, nw, win_tile, rec, W.start, W.start_src, rho, ego, grad_loss, grad_rho,
-                W.part);
+            with_tile(B, [&](auto twc, auto thc) {
+                constexpr int TWX = decltype(twc)::value, THX = decltype(thc)::value;
+                if (ae)
+                    bwd_tile_own_kernel<EX, true, TWX, THX><<<(int)B.nbins_b, 256, 0, s>>>(
+                        meta, nw, win_tile, rec, W.start, W.start_src, rho, ego, grad_loss,
+                        grad_rho, W.part);
+                else
+                    bwd_tile_own_kernel<EX, false, TWX, THX><<<(int)B.nbins_b, 256, 0, s>>>(
+                        meta, nw, win_tile, rec, W.start, W.start_src, rho, ego, grad_loss,
+                        grad_rho, W.part);
+            });
         }
     }
     {

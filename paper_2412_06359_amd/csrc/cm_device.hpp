@@ -798,6 +798,8 @@ constexpr int kMaxEventsPerThread = 16;
 
 
 struct TileGeom {
+    int tw, th;             // tile size (powers of two; 32 x 32 in the deterministic mode)
+    int tws, ths;           // their base-2 logarithms
     int ntx, nty, ntiles;   // tiles per row / column / image
     int nbins;              // forward bins: R * ntiles (reference, tile)
     int nbins_b;            // backward bins: F * ntiles (flow set, tile)
@@ -895,7 +897,7 @@ __device__ __forceinline__ SrcRec load_nt(const SrcRec* p)
 
 __device__ __forceinline__ int tile_index(const TileGeom& G, const Taps& t)
 {
-    return (int)((uint32_t)t.y0 / TH) * G.ntx + (int)((uint32_t)t.x0 / TW);
+    return (int)((uint32_t)t.y0 >> G.ths) * G.ntx + (int)((uint32_t)t.x0 >> G.tws);
 }
 
 // The tiles whose pixels the on-sensor taps of a position reach (atomic
@@ -910,9 +912,9 @@ constexpr uint32_t kReachRight = 1u << 16, kReachDown = 1u << 17;
 __device__ __forceinline__ uint32_t tiles_reached(const TileGeom& G, const Taps& t)
 {
     const uint32_t x0 = (uint32_t)t.x0, y0 = (uint32_t)t.y0;
-    uint32_t v = (uint32_t)((y0 / TH) * G.ntx + x0 / TW);
-    if (t.inx && x0 % TW == TW - 1) v |= kReachRight;
-    if (t.iny && y0 % TH == TH - 1) v |= kReachDown;
+    uint32_t v = (uint32_t)((y0 >> G.ths) * G.ntx + (x0 >> G.tws));
+    if (t.inx && (x0 & (G.tw - 1)) == (uint32_t)G.tw - 1) v |= kReachRight;
+    if (t.iny && (y0 & (G.th - 1)) == (uint32_t)G.th - 1) v |= kReachDown;
     return v;
 }
 

@@ -161,6 +161,7 @@ struct BatchPlanHost {
     bool at_events = false; // atomic mode, every window samples the flow at its events only
     int model = 0;          // flow model of the batch's windows
     int tile_threads = 512; // forward tile kernel threads (atomic mode)
+    int tile_w = 32, tile_h = 32;   // tile size (atomic mode: the tuning's; 32 x 32 otherwise)
     TileWorkspace ws;
 };
 
@@ -189,11 +190,12 @@ hipError_t launch_backward(const WinParams& P, const EventPtrs& ev, const float*
 // copy of plan.meta; `ws` a device region of plan.ws.total bytes; images of
 // window w start at img + meta[w].img_off; hdrs[w] its sums.
 bool tiled_supported(const WinParams& P, int64_t n, bool det);
-TileGeom tile_geom(const WinParams& P, int64_t n, bool det, int min_ept);
+TileGeom tile_geom(const WinParams& P, int64_t n, bool det, int min_ept, int tw, int th);
 // Launch shape of a plan (the atomic mode's tunables; see cm_tuning).
 struct PlanTuning {
     int event_blocks = 4096;
     int tile_threads = 512;
+    int tile_w = 32, tile_h = 32;
 };
 BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int nw, bool det,
                          const PlanTuning& tune = PlanTuning());

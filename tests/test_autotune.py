@@ -29,7 +29,11 @@ def test_cache_roundtrip_and_hit(tmp_path):
     assert json.load(open(path))[key]["event_blocks"] == 2048
     # a cache hit needs no inputs and no GPU
     assert autotune.tune(descs, counts, cache_path=path) == dict(event_blocks=2048,
-                                                                tile_threads=256)
+                                                                tile_threads=256, tile_w=32,
+                                                                tile_h=32)
+    autotune.save_cache(path, {key: dict(event_blocks=2048, tile_threads=256, tile_w=64,
+                                         tile_h=32, ms=1.0)})
+    assert autotune.tune(descs, counts, cache_path=path)["tile_w"] == 64
     # a miss without inputs gives the defaults
     assert autotune.tune(_descs(3), [5] * 3, cache_path=path) == autotune.DEFAULT
     # the deterministic mode is not tuned
@@ -39,4 +43,6 @@ def test_cache_roundtrip_and_hit(tmp_path):
 def test_candidates_are_valid_tunings():
     for c in autotune.CANDIDATES:
         assert 256 <= c["event_blocks"] <= 65536 and c["tile_threads"] in (256, 512)
+        assert (c["tile_w"], c["tile_h"]) == (32, 32)
     assert autotune.DEFAULT in autotune.CANDIDATES
+    assert set(autotune.TILE_SIZES) == {(32, 32), (64, 32), (32, 16), (16, 16)}
