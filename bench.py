@@ -471,6 +471,14 @@ def main():
         phases = cm.profile_read(0)
         cm.profile_enable(0, False)
         path_used = "tiled"
+        # the single-window direct / tiled crossover on windows spanning the
+        # workload's sizes (measured, not applied to the handle)
+        by_size = sorted(wins, key=lambda w: w.n)
+        sample = [by_size[i * (len(by_size) - 1) // 7] for i in range(8)]
+        cross_log = []
+        cross = autotune.tune_crossover(sample, steps=3, warmup=1, log=cross_log, apply=False)
+        out_extra["crossover"] = {"tiled_min_records": cross, "handle_default": 1 << 17,
+                                  "windows": cross_log}
         out_extra["plain_events_per_s"] = n_events / (ms_plain * 1e-3)
         out_extra["plain_ms_per_step"] = ms_plain
         out_extra["batched_over_plain"] = ms_plain / ms_per_step
@@ -495,7 +503,13 @@ def main():
         # the paper's training setting: 10 slices per window, one flow per slice
         w6 = eventgen.make_batch("c6", 64)
         d6 = to_device(w6, dev)
-        b6 = cm.Batch([cm.WindowDesc.from_window(w) for w in w6], [w.n for w in w6], graph=True)
+        descs6 = [cm.WindowDesc.from_window(w) for w in w6]
+        if args.tuning:
+            tuning6 = tuning
+        else:
+            from paper_2412_06359_amd import autotune
+            tuning6 = autotune.tune(descs6, [w.n for w in w6], d6, steps=2, warmup=1)
+        b6 = cm.Batch(descs6, [w.n for w in w6], graph=True, tuning=tuning6)
         st6 = b6.new_state()
         l6 = torch.empty(b6.n, device=dev)
         gr6, ge6 = torch.empty_like(d6["rho"]), torch.empty_like(d6["ego"])
@@ -509,7 +523,8 @@ def main():
         ms6 = timed(step6, args.steps, args.warmup, stream)
         n6 = sum(w.n for w in w6)
         out_extra["c6_batched"] = {"workload": WORKLOADS["c6"], "n_events": n6,
-                                   "ms_per_step": ms6, "events_per_s": n6 / (ms6 * 1e-3)}
+                                   "ms_per_step": ms6, "events_per_s": n6 / (ms6 * 1e-3),
+                                   "tuning": tuning6}
         # the full training loss of Eq. 4: L_CM + 0.05 L_geo over consecutive slices
         gst6 = torch.empty(b6.geo_state_bytes(), dtype=torch.uint8, device=dev)
 

@@ -143,3 +143,72 @@ def tune(descs: Sequence[cm.WindowDesc], n_events: Sequence[int], inputs: Option
         cache[key] = dict(best, ms=best_ms)
         save_cache(path, cache)
     return best
+
+
+def _time_window(desc, win, path: int, device: int, steps: int, warmup: int) -> float:
+    """ms per forward + backward of one window through the single-window calls
+    on the given path, HIP events on the current stream."""
+    dev = torch.device("cuda", device)
+    f32 = lambda a: torch.as_tensor(a, dtype=torch.float32).reshape(-1).contiguous().to(dev)
+    x, y, t = f32(win.x), f32(win.y), f32(win.t)
+    p = torch.as_tensor(win.p, dtype=torch.int8).to(dev)
+    rho, ego = f32(win.rho), f32(win.theta)
+    prev = cm.get_path(device)
+    cm.set_path(device, path)
+    try:
+        st = torch.empty(cm.state_bytes(desc, win.n), dtype=torch.uint8, device=dev)
+        loss = torch.empty(1, device=dev)
+        g_rho, g_ego = torch.empty_like(rho), torch.empty_like(ego)
+        g = torch.ones(1, device=dev)
+
+        def step():
+            cm.forward(desc, x, y, t, p, rho, ego, state=st, loss=loss)
+            cm.backward(desc, x, y, t, p, rho, ego, st, g, grad_rho=g_rho, grad_ego=g_ego)
+        for _ in range(warmup):
+            step()
+        stream = torch.cuda.current_stream(dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / steps
+    finally:
+        cm.set_path(device, prev)
+
+
+def tune_crossover(windows, device: int = 0, steps: int = 5, warmup: int = 2,
+                   log: Optional[list] = None, apply: bool = True) -> int:
+    """The single-window direct / tiled crossover (cm_tuning.tiled_min_records):
+    times each window (ascending event-reference records) on both paths and
+    returns the record count from which the tiled path is faster -- the
+    geometric mean of the largest window the direct path wins and the smallest
+    the tiled path wins from there on (the first or last window's count when
+    one path wins everywhere).  apply: set it on the device's handle."""
+    rows = []
+    for win in sorted(windows, key=lambda w: w.n * len(w.refs)):
+        desc = cm.WindowDesc.from_window(win)
+        recs = int(win.n) * len(win.refs)
+        md = _time_window(desc, win, cm.CM_PATH_DIRECT, device, steps, warmup)
+        mt = _time_window(desc, win, cm.CM_PATH_TILED, device, steps, warmup)
+        rows.append((recs, md, mt))
+        if log is not None:
+            log.append(dict(records=recs, direct_ms=md, tiled_ms=mt))
+    # the smallest index from which the tiled path wins every larger window
+    k = len(rows)
+    while k > 0 and rows[k - 1][2] < rows[k - 1][1]:
+        k -= 1
+    if k == len(rows):
+        cross = rows[-1][0] + 1                 # the direct path wins everywhere measured
+    elif k == 0:
+        cross = rows[0][0]
+    else:
+        cross = int(round(math.sqrt(rows[k - 1][0] * rows[k][0])))
+    cross = max(1, cross)
+    if apply:
+        cur = cm.get_tuning(device)
+        cur["tiled_min_records"] = cross
+        cm.set_tuning(device, **cur)
+    return cross

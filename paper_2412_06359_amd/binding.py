@@ -211,9 +211,19 @@ def state_bytes(desc: WindowDesc, n_events: int) -> int:
     return int(n)
 
 
+_path_of: dict = {}
+
+
 def set_path(device: int, path: int):
     """Kernel path of this device's handle: CM_PATH_AUTO, _DIRECT or _TILED."""
     _check(load().cm_set_path(handle(device), int(path)), "cm_set_path")
+    _path_of[device] = int(path)
+
+
+def get_path(device: int = 0) -> int:
+    """The path set_path last gave this device's handle (CM_PATH_AUTO before
+    any call)."""
+    return _path_of.get(device, CM_PATH_AUTO)
 
 
 def get_tuning(device: int = 0) -> dict:

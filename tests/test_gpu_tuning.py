@@ -107,3 +107,25 @@ def test_tuned_event_sampled_batches_match_oracle(cm, tile):
         pr = g_rho[batch.pixel_offsets[w]:batch.pixel_offsets[w + 1]]
         pe = g_ego[6 * batch.set_offsets[w]:6 * batch.set_offsets[w + 1]]
         assert_grads_close(pr, pe, ob["drho"].ravel(), ob["dtheta"], what=f"{tile} {win.name}")
+
+
+def test_crossover_tuning(cm):
+    """The direct / tiled crossover search: a threshold from the measured
+    windows, set on the handle with the rest of the tuning kept."""
+    import eventgen
+    from paper_2412_06359_amd import autotune
+    cm.set_tuning(0, event_blocks=2048)
+    wins = [eventgen.edge_window(800 + i, "346x260", n, refs=[0.0, 1.0], n_segments=30,
+                                 name=f"x{i}") for i, n in enumerate([500, 5000, 60000])]
+    log = []
+    try:
+        cross = autotune.tune_crossover(wins, steps=2, warmup=1, log=log)
+        print(f"[gpu] crossover {cross} from {log}", flush=True)
+        recs = [r["records"] for r in log]
+        assert len(log) == 3 and recs == sorted(recs)
+        assert 1 <= cross <= recs[-1] + 1
+        t = cm.get_tuning(0)
+        assert t["tiled_min_records"] == cross and t["event_blocks"] == 2048
+        assert cm.get_path(0) == cm.CM_PATH_AUTO          # the path is restored
+    finally:
+        cm.set_tuning(0)
