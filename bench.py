@@ -405,8 +405,9 @@ def main():
     ap.add_argument("--saturation-seconds", type=float, default=3.0,
                     help="seconds per level of the rising-rate serving run (0: skip)")
     ap.add_argument("--tuning", default=None,
-                    help="EVENT_BLOCKS,TILE_THREADS for the batched workload instead of the "
-                         "autotuner's choice (profiled runs pass the timed run's tuning)")
+                    help="EVENT_BLOCKS,TILE_THREADS[,TILE_W,TILE_H] for the batched workload "
+                         "instead of the autotuner's choice (profiled runs pass the timed run's "
+                         "tuning)")
     ap.add_argument("--path", default="auto", choices=["auto", "direct", "tiled"],
                     help="kernel path of the library handle (plain calls)")
     args = ap.parse_args()
@@ -439,8 +440,12 @@ def main():
         d = to_device(wins, dev)
         descs = [cm.WindowDesc.from_window(w) for w in wins]
         if args.tuning:
-            eb, tt = (int(v) for v in args.tuning.split(","))
-            tuning = dict(event_blocks=eb, tile_threads=tt)
+            vals = [int(v) for v in args.tuning.split(",")]
+            if len(vals) not in (2, 4):
+                ap.error("--tuning takes EVENT_BLOCKS,TILE_THREADS[,TILE_W,TILE_H]")
+            tuning = dict(event_blocks=vals[0], tile_threads=vals[1])
+            if len(vals) == 4:
+                tuning.update(tile_w=vals[2], tile_h=vals[3])
             out_extra["tuning"] = {"chosen": tuning, "source": "--tuning"}
         else:
             tune_log = []
