@@ -338,8 +338,17 @@ __global__ __launch_bounds__(256) void chunk_scan_kernel(const WinMeta* __restri
 // totals1 -> start1): chunks of 8192 totals are loaded coalesced into LDS,
 // each thread sums 8 consecutive ones, the 1024 sums are scanned with in-wave
 // shuffles and the 16 wave totals by one wave, and the results go out
-// coalesced.  With occ0, block 0 also lists its non-empty bins in order
-// (occ0[0 .. occ0_n[0]), by the same scan over the bins' non-empty flags).
+// coalesced.  With occ0, block 0 also lists its non-empty bins
+// (occ0[0 .. occ0_n[0])), heaviest first by the binary order of magnitude of
+// their totals (in any order within one magnitude): the splat workgroups take
+// the list round-robin, so the longest bins start first.
+constexpr int kOccBuckets = 24;
+__device__ __forceinline__ int occ_bucket(uint32_t c)
+{
+    const int b = 31 - __clz((int)c);
+    return b < kOccBuckets ? b : kOccBuckets - 1;
+}
+
 __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__ totals0,
                                                     int64_t nbins0, uint32_t* __restrict__ start0,
                                                     const uint32_t* __restrict__ totals1,
@@ -354,7 +363,9 @@ __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__
     constexpr int T = 1024, K = 8, CH = T * K, NWV = T / 64;
     __shared__ uint32_t buf[CH];
     __shared__ uint32_t wsum[2][NWV];
+    __shared__ uint32_t bkt[kOccBuckets];     // non-empty bins per magnitude, then list offsets
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (tid < kOccBuckets) bkt[tid] = 0u;
     uint32_t carry = 0, fcarry = 0;
     for (int64_t base = 0; base < nbins; base += CH) {
 #pragma unroll
@@ -396,13 +407,12 @@ __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__
         }
         __syncthreads();
         uint32_t run = carry + (wid ? wsum[0][wid - 1] : 0u) + (x - sum);
-        uint32_t frun = fcarry + (wid ? wsum[1][wid - 1] : 0u) + (fx - fsum);
         const int64_t i0 = base + (int64_t)tid * K;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             buf[tid * K + k] = run;
             run += v[k];
-            if (occ && v[k]) occ[frun++] = (uint32_t)(i0 + k);
+            if (occ && v[k]) atomicAdd(&bkt[occ_bucket(v[k])], 1u);
         }
         carry += wsum[0][NWV - 1];
         fcarry += wsum[1][NWV - 1];
@@ -417,6 +427,21 @@ __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__
     if (tid == 0) {
         start[nbins] = carry;
         if (occ) occ0_n[0] = fcarry;
+    }
+    if (!occ) return;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t at = 0;
+        for (int b = kOccBuckets - 1; b >= 0; --b) {
+            const uint32_t c = bkt[b];
+            bkt[b] = at;
+            at += c;
+        }
+    }
+    __syncthreads();
+    for (int64_t i = tid; i < nbins; i += T) {
+        const uint32_t c = totals[i];
+        if (c) occ[atomicAdd(&bkt[occ_bucket(c)], 1u)] = (uint32_t)i;
     }
 }
 
@@ -808,20 +833,57 @@ __global__ __launch_bounds__(64 * kDetAccWaves) void fwd_tile_det_kernel(const T
     }
 }
 
+// One wavefront's sum (lanes in the shuffle-down tree of block_sum; the
+// result, valid in lane 0, is 0.0 + the tree's value as block_sum gives it
+// for a one-wavefront block).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return 0.0 + v;
+}
+
+// Partial sums of Eq. 1 per forward bin in the atomic mode: one (sum, count)
+// pair per wavefront of the splat workgroup (at most 8), so that a bin needs
+// no cross-wavefront reduction; the finalize adds them.
+constexpr int kPartOwn = 16;
+
+// A splat workgroup's table of its bins (list entry, bounds, table entry),
+// loaded kBinTable at a time.
+constexpr int kBinTable = 64;
+struct OwnBin {
+    TileBin b;
+    uint32_t g, s0, s1, pad;
+};
+
 // Atomic mode: a (reference, tile) bin owns the tile's pixels (TWX x THX, the
-// plan's tile size; 32 x 32 by default).  Its
-// bin holds every record whose taps reach the tile (its own positions and the
-// copies from the left, upper and upper-left neighbours), so its workgroup
-// accumulates the taps that fall in the tile with FP64 LDS atomics, stores the
-// pixels some tap reached and reduces Eq. 1 over all its pixels: no halo, no
-// merge.  Only occupied bins are visited (the scan lists them; the window
-// table kernel zeroed the partial sums of the others): workgroup b
-// takes list entries b, b + grid, b + 2 grid, ..., loading the next entry's
-// index during the current bin's accumulation and its bounds during the
-// current bin's output, so that a bin's chain starts at its record loads.
-// The first records are loaded before the LDS tile is cleared.  C and S
-// accumulate in separate LDS arrays (8-byte stride: half the bank conflicts
-// of interleaved pairs).
+// plan's tile size; 32 x 32 by default).  Its bin holds every record whose
+// taps reach the tile (its own positions and the copies from the left, upper
+// and upper-left neighbours), so its workgroup accumulates the taps that fall
+// in the tile with FP64 LDS atomics, stores the pixels some tap reached and
+// reduces Eq. 1 over all its pixels: no halo, no merge.  Only occupied bins
+// are visited (the scan lists them; the window table kernel zeroed the
+// partial sums of the others).  The list runs heaviest first and the grid is
+// what fits the chip at once, ncu CUs x per_cu workgroups, workgroup b on CU
+// b mod ncu (the dispatcher's order).  The list is dealt out in passes of one
+// bin per CU, alternating direction (pass p gives entry p ncu + c, or
+// p ncu + ncu - 1 - c on odd passes, to CU c), and the CU's workgroup b / ncu
+// takes passes b / ncu, b / ncu + per_cu, ...: the longest bins start at
+// once, on different CUs, and the CUs' sums even out.  Per bin the chain is:
+// accumulate, barrier, output, barrier.
+// - The workgroup's list entries, bin bounds and table entries are loaded
+//   into LDS up front (kBinTable bins at a time), so that no scalar load is
+//   in flight in the loop: scalar loads share the LDS operations' counter,
+//   and the next LDS wait would wait for them.
+// - The next bin's records are loaded right after the accumulation barrier,
+//   in flight during the output.
+// - The output loop reads, stores and clears only the cells some tap reached
+//   (a byte per cell marks them), so the next bin starts on a clear tile
+//   with no clearing pass (the tile is cleared once, up front).
+// - Each wavefront reduces its pixels' Eq. 1 terms and writes its own pair
+//   of partial sums: no block reduction and its two barriers.
+// C and S accumulate in separate LDS arrays (8-byte stride: half the bank
+// conflicts of interleaved pairs).
 template <int NTT, int TWX, int THX>
 __global__ __launch_bounds__(NTT) void fwd_tile_own_kernel(const TileBin* __restrict__ tbin,
                                                            const SplatRec* __restrict__ rec,
@@ -829,40 +891,67 @@ __global__ __launch_bounds__(NTT) void fwd_tile_own_kernel(const TileBin* __rest
                                                            const uint32_t* __restrict__ occ,
                                                            const uint32_t* __restrict__ occ_n,
                                                            double2* __restrict__ img_base,
-                                                           double* __restrict__ part)
+                                                           double* __restrict__ part, int ncu)
 {
+    static_assert(NTT / 64 * 2 <= kPartOwn, "one partial pair per wavefront");
+    static_assert(NTT >= kBinTable, "one table entry per thread");
     constexpr int NPIX = TWX * THX;
     __shared__ double lc[2 * NPIX];       // C by polarity, then pixel
     __shared__ double ls[2 * NPIX];       // S
-    // pixels reached only by zero-weight taps (positions on a pixel row or
-    // column): they hold zeros, but the backward reads them
-    __shared__ uint32_t zbit[2 * NPIX / 32];
-    __shared__ double red[32];
+    // cells some tap reached (positive or zero weight: a position on a pixel
+    // row or column gives zero-weight taps, whose pixels hold zeros but are
+    // read by the backward)
+    __shared__ uint8_t tch[2 * NPIX];
+    __shared__ OwnBin tab[kBinTable];
     const uint32_t nocc = occ_n[0];
-    uint32_t k = blockIdx.x;
-    if (k >= nocc) return;
-    uint32_t gbin = occ[k];
-    uint32_t s0 = start[gbin], s1 = start[gbin + 1];
-    TileBin bi = tbin[gbin];
-    for (;;) {
-        const uint32_t kn = k + gridDim.x;
-        const uint32_t gn = kn < nocc ? occ[kn] : gbin;     // the next bin, in flight
+    const uint32_t G = gridDim.x;
+    if (nocc == 0) return;
+    const uint32_t nc = (uint32_t)ncu, per = G / nc;
+    const uint32_t slot = blockIdx.x / nc, cu = blockIdx.x - slot * nc;
+    // list entry of pass p for this CU
+    auto entry = [&](uint32_t p) { return p * nc + ((p & 1) ? nc - 1 - cu : cu); };
+    // this workgroup's bins: its passes among the full ones, and the partial
+    // last pass if it is one of its passes and reaches its CU
+    const uint32_t pf = nocc / nc;
+    uint32_t nb = pf > slot ? (pf - slot - 1) / per + 1 : 0u;
+    if (pf % per == slot && entry(pf) < nocc) ++nb;
+    if (nb == 0) return;
+    auto load_table = [&](uint32_t j0) {
+        const uint32_t j = j0 + threadIdx.x;
+        if (threadIdx.x < kBinTable && j < nb) {
+            OwnBin e;
+            const uint32_t kk = entry(j * per + slot);
+            e.g = kk < nocc ? occ[kk] : 0u;
+            e.s0 = start[e.g];
+            e.s1 = start[e.g + 1];
+            e.b = tbin[e.g];
+            e.pad = 0;
+            tab[threadIdx.x] = e;
+        }
+    };
+    load_table(0);
+    for (int i = threadIdx.x; i < 2 * NPIX; i += NTT) {
+        lc[i] = 0.0;
+        ls[i] = 0.0;
+        tch[i] = 0;
+    }
+    __syncthreads();
+    SplatRec qq[2];
+    auto load_first = [&](uint32_t a0, uint32_t a1) {
+        const uint32_t i0 = a0 + threadIdx.x;
+        if (i0 < a1) {
+            qq[0] = rec[i0];
+            qq[1] = rec[i0 + NTT < a1 ? i0 + NTT : i0];
+        }
+    };
+    load_first(tab[0].s0, tab[0].s1);
+    for (uint32_t j = 0;;) {
+        const OwnBin& e = tab[j % kBinTable];
+        const uint32_t gbin = e.g, s0 = e.s0, s1 = e.s1;
+        const TileBin bi = e.b;
         const int xo = bi.xo, yo = bi.yo;
         const double ref = bi.ref;
-        // the first round's records, in flight during the clear
-        uint32_t i0 = s0 + threadIdx.x;
-        SplatRec qq[2];
-        if (i0 < s1) {
-            qq[0] = rec[i0];
-            qq[1] = rec[i0 + NTT < s1 ? i0 + NTT : i0];
-        }
-        for (int i = threadIdx.x; i < 2 * NPIX; i += NTT) {
-            lc[i] = 0.0;
-            ls[i] = 0.0;
-        }
-        for (int i = threadIdx.x; i < 2 * NPIX / 32; i += NTT) zbit[i] = 0u;
-        __syncthreads();
-        while (i0 < s1) {
+        for (uint32_t i0 = s0 + threadIdx.x; i0 < s1;) {
             const bool two = i0 + NTT < s1;
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
@@ -880,10 +969,8 @@ __global__ __launch_bounds__(NTT) void fwd_tile_own_kernel(const TileBin* __rest
                         continue;
                     const double wt = tap_w(tp, c);
                     const int key = pol * NPIX + cy * TWX + cx;
-                    if (wt == 0.0) {
-                        atomicOr(&zbit[key >> 5], 1u << (key & 31));
-                        continue;
-                    }
+                    tch[key] = 1;
+                    if (wt == 0.0) continue;
                     atomicAdd(&lc[key], wt);
                     atomicAdd(&ls[key], wt * tb);
                 }
@@ -895,61 +982,61 @@ __global__ __launch_bounds__(NTT) void fwd_tile_own_kernel(const TileBin* __rest
             }
         }
         __syncthreads();
-        // the next bin's bounds and record, in flight during the output
-        const uint32_t s0n = start[gn], s1n = start[gn + 1];
-        const TileBin bin_n = tbin[gn];
+        const uint32_t jn = j + 1;
+        // the next bin's first records, in flight during the output (at a
+        // table boundary they wait for the next table)
+        if (jn < nb && jn % kBinTable != 0) load_first(tab[jn % kBinTable].s0, tab[jn % kBinTable].s1);
         double sum = 0.0, cnt = 0.0;
         double2* plane0 = img_base + bi.plane;
         double2* plane1 = plane0 + (size_t)bi.W * bi.H;
         // The backward reads the image only at the taps of the positions
         // splatted here, and every such tap reached this tile through its
-        // bin: so only the pixels some tap reached (a non-zero sum, or a
-        // zero-weight tap's bit) are stored, the others are neither written
-        // nor read.
-        auto reached = [&](int kk, const double2& c) {
-            return c.x != 0.0 || c.y != 0.0 || ((zbit[kk >> 5] >> (kk & 31)) & 1u);
-        };
+        // bin: so only the pixels some tap reached are stored, the others are
+        // neither written nor read.  Untouched cells hold zeros and add
+        // nothing to Eq. 1: they are skipped.
         for (int i = threadIdx.x; i < NPIX; i += NTT) {
-            const int X = xo + (i % TWX), Y = yo + (i / TWX);
-            if (X >= bi.W || Y >= bi.H) continue;
-            const double2 a = make_double2(lc[i], ls[i]);
-            const double2 b = make_double2(lc[NPIX + i], ls[NPIX + i]);
-            const int pix = Y * bi.W + X;
-            if (reached(i, a)) plane0[pix] = a;
-            if (reached(NPIX + i, b)) plane1[pix] = b;
+            const bool ta = tch[i] != 0, tb2 = tch[NPIX + i] != 0;
+            if (!ta && !tb2) continue;
+            double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+            if (ta) {
+                a = make_double2(lc[i], ls[i]);
+                lc[i] = 0.0;
+                ls[i] = 0.0;
+                tch[i] = 0;
+            }
+            if (tb2) {
+                b = make_double2(lc[NPIX + i], ls[NPIX + i]);
+                lc[NPIX + i] = 0.0;
+                ls[NPIX + i] = 0.0;
+                tch[NPIX + i] = 0;
+            }
+            // (taps off the sensor are never made: a touched cell is on it)
+            const int pix = (yo + i / TWX) * bi.W + xo + (i % TWX);
+            if (ta) plane0[pix] = a;
+            if (tb2) plane1[pix] = b;
             reduce_pixel(a, b, bi.eps, sum, cnt);
         }
-        double sc[2] = {sum, cnt};
-        block_sum_n(sc, red);
-        if (threadIdx.x == 0) {
-            part[(size_t)gbin * 4 + 0] = sc[0];
-            part[(size_t)gbin * 4 + 1] = sc[1];
-            part[(size_t)gbin * 4 + 2] = 0.0;
-            part[(size_t)gbin * 4 + 3] = 0.0;
+        sum = wave_sum(sum);
+        cnt = wave_sum(cnt);
+        if ((threadIdx.x & 63) == 0) {
+            double* pp = part + (size_t)gbin * kPartOwn + (threadIdx.x >> 6) * 2;
+            pp[0] = sum;
+            pp[1] = cnt;
         }
-        if (kn >= nocc) break;
-        // (block_sum_n's barriers order every thread's LDS reads above
-        // before the next bin's clear)
-        k = kn;
-        gbin = gn;
-        s0 = s0n;
-        s1 = s1n;
-        bi = bin_n;
+        if (jn >= nb) break;
+        __syncthreads();        // the cleared tile (and the read table), for the next bin
+        j = jn;
+        if (j % kBinTable == 0) {
+            load_table(j);
+            __syncthreads();
+            load_first(tab[0].s0, tab[0].s1);
+        }
     }
 }
 
 // Column 0 and row 0 of each tile: the tile's own values (border buffer) plus
 // the halos of the left, top and top-left tiles (in that order); store and
 // reduce those pixels.
-// One wavefront's sum (lanes in the shuffle-down tree of block_sum; the
-// result, valid in lane 0, is 0.0 + the tree's value as block_sum gives it
-// for a one-wavefront block).
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    return 0.0 + v;
-}
 
 // One wavefront per bin, kMergeBins bins per block (the bins are
 // independent: no barrier).
@@ -1026,6 +1113,7 @@ __global__ __launch_bounds__(64 * kMergeBins) void fwd_merge_kernel(const TileBi
 // reference, then Eq. 1.
 __global__ __launch_bounds__(256) void fwd_finalize_kernel(const WinMeta* __restrict__ meta,
                                                            const double* __restrict__ part,
+                                                           int pstride,
                                                            StateHeader* __restrict__ hdrs,
                                                            float* __restrict__ loss)
 {
@@ -1033,14 +1121,16 @@ __global__ __launch_bounds__(256) void fwd_finalize_kernel(const WinMeta* __rest
     const int w = blockIdx.x;
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
-    const double* pw = part + meta[w].bin_off * 4;
+    // pstride doubles per bin: (sum, count) pairs
+    const double* pw = part + meta[w].bin_off * pstride;
+    const int npair = G.ntiles * pstride / 2;
     StateHeader* hdr = hdrs + w;
     double L = 0.0;
     for (int r = 0; r < P.R; ++r) {
         double sc[2] = {0.0, 0.0};
-        for (int j = threadIdx.x; j < 2 * G.ntiles; j += blockDim.x) {
-            sc[0] += pw[((size_t)r * 2 * G.ntiles + j) * 2 + 0];
-            sc[1] += pw[((size_t)r * 2 * G.ntiles + j) * 2 + 1];
+        for (int j = threadIdx.x; j < npair; j += blockDim.x) {
+            sc[0] += pw[((size_t)r * npair + j) * 2 + 0];
+            sc[1] += pw[((size_t)r * npair + j) * 2 + 1];
         }
         block_sum_n(sc, red);
         if (threadIdx.x == 0) {
@@ -1821,7 +1911,7 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     B.ws.start = take((size_t)(B.seg + 1 + sbin + 1) * sizeof(uint32_t));
     // the occupied forward bins, listed by the scan, and their count
     B.ws.occ = take((size_t)(bin + 2) * sizeof(uint32_t));
-    B.ws.part = take((size_t)std::max(bin * 4, bbin * 12) * sizeof(double));
+    B.ws.part = take((size_t)std::max(bin * (det ? 4 : kPartOwn), bbin * 12) * sizeof(double));
     B.ws.halo = take(det ? (size_t)std::max<int64_t>(bin * (NHALO + NBORDER) * 2,
                                                      bbin * (NHALO + NBORDER)) *
                                sizeof(double2)
@@ -1842,15 +1932,31 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     return B;
 }
 
-// Workgroups of the atomic mode's forward tile kernel: each walks the list of
-// occupied bins with the grid as stride; twice the workgroups whose LDS tiles
-// fit the chip at once, so that those freed early take the remaining ones.
-static int tile_grid(const BatchPlanHost& B)
+// Compute units of the current device (queried once per device).
+static int device_cus()
 {
-    const int64_t lds = 2LL * B.tile_w * B.tile_h * 16 + 1024;
-    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(160 * 1024 / lds,
-                                                                   32 / (B.tile_threads / 64)));
-    return (int)std::max<int64_t>(1, std::min<int64_t>(B.nbins, 2 * 256 * per_cu));
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cus[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            v <= 0)
+            v = 256;
+        cus[dev] = v;
+    }
+    return cus[dev];
+}
+
+// Workgroups per CU of the atomic mode's forward tile kernel: as many as fit
+// at once (every workgroup starts at once; each takes its share of the
+// heaviest-first list of occupied bins pass by pass).
+static int tile_per_cu(const BatchPlanHost& B)
+{
+    // C and S of both polarities, the touched bytes, the bin table
+    const int64_t lds = 2LL * B.tile_w * B.tile_h * (16 + 1) + kBinTable * (int64_t)sizeof(OwnBin);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(160 * 1024 / lds,
+                                                       32 / (B.tile_threads / 64)));
 }
 
 template <int NTT, int TWX, int THX>
@@ -1858,8 +1964,12 @@ static void launch_fwd_tile_own(const BatchPlanHost& B, const TileBin* tbin, con
                                 const uint32_t* start, const uint32_t* occ, const uint32_t* occ_n,
                                 double2* img, double* part, hipStream_t s)
 {
-    fwd_tile_own_kernel<NTT, TWX, THX><<<tile_grid(B), NTT, 0, s>>>(tbin, rec, start, occ, occ_n,
-                                                                    img, part);
+    // (no more workgroups than bins: a small plan takes fewer CUs or slots)
+    const int nc = (int)std::max<int64_t>(1, std::min<int64_t>(device_cus(), B.nbins));
+    const int per = (int)std::max<int64_t>(
+        1, std::min<int64_t>(tile_per_cu(B), (B.nbins + nc - 1) / nc));
+    fwd_tile_own_kernel<NTT, TWX, THX><<<nc * per, NTT, 0, s>>>(tbin, rec, start, occ, occ_n,
+                                                                img, part, nc);
 }
 
 // The atomic mode's tile sizes (the tuning's choice; 32 x 32 by default).
@@ -1942,7 +2052,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
         else
             // (and the partial sums: the tile kernel writes those of occupied bins only)
             launch_window_table(B, meta, W.wtab, ego, W.mtab, hdrs, W.totals,
-                                B.seg + 1 + B.nbins_s, W.tbin, s, W.part, B.nbins * 4);
+                                B.seg + 1 + B.nbins_s, W.tbin, s, W.part, B.nbins * kPartOwn);
     }
     {
         PhaseScope ph(prof, kPhCount, s);
@@ -1992,7 +2102,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     }
     {
         PhaseScope ph(prof, kPhFinalize, s);
-        fwd_finalize_kernel<<<nw, 256, 0, s>>>(meta, W.part, hdrs, loss);
+        fwd_finalize_kernel<<<nw, 256, 0, s>>>(meta, W.part, DET ? 4 : kPartOwn, hdrs, loss);
     }
     return hipGetLastError();
 }
