@@ -341,11 +341,14 @@ __global__ __launch_bounds__(256) void chunk_scan_kernel(const WinMeta* __restri
 // coalesced.  With occ0, block 0 also lists its non-empty bins
 // (occ0[0 .. occ0_n[0])), heaviest first by the binary order of magnitude of
 // their totals (in any order within one magnitude): the splat workgroups take
-// the list round-robin, so the longest bins start first.
-constexpr int kOccBuckets = 24;
+// the list in passes, so the longest bins start first.  With occ1, block 1
+// lists all its bins the same way, the empty ones last (the order in which a
+// one-workgroup-per-bin kernel over them is launched).
+constexpr int kOccBuckets = 25;     // empty, then magnitudes 0 .. 23 (and above)
 __device__ __forceinline__ int occ_bucket(uint32_t c)
 {
-    const int b = 31 - __clz((int)c);
+    if (c == 0) return 0;
+    const int b = 32 - __clz((int)c);
     return b < kOccBuckets ? b : kOccBuckets - 1;
 }
 
@@ -354,12 +357,14 @@ __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__
                                                     const uint32_t* __restrict__ totals1,
                                                     int64_t nbins1, uint32_t* __restrict__ start1,
                                                     uint32_t* __restrict__ occ0 = nullptr,
-                                                    uint32_t* __restrict__ occ0_n = nullptr)
+                                                    uint32_t* __restrict__ occ0_n = nullptr,
+                                                    uint32_t* __restrict__ occ1 = nullptr)
 {
     const uint32_t* __restrict__ totals = blockIdx.x ? totals1 : totals0;
     const int64_t nbins = blockIdx.x ? nbins1 : nbins0;
     uint32_t* __restrict__ start = blockIdx.x ? start1 : start0;
-    uint32_t* __restrict__ occ = blockIdx.x ? nullptr : occ0;
+    uint32_t* __restrict__ occ = blockIdx.x ? occ1 : occ0;
+    const bool empties = blockIdx.x != 0;       // occ1 lists the empty bins too
     constexpr int T = 1024, K = 8, CH = T * K, NWV = T / 64;
     __shared__ uint32_t buf[CH];
     __shared__ uint32_t wsum[2][NWV];
@@ -412,7 +417,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__
         for (int k = 0; k < K; ++k) {
             buf[tid * K + k] = run;
             run += v[k];
-            if (occ && v[k]) atomicAdd(&bkt[occ_bucket(v[k])], 1u);
+            if (occ && (v[k] || empties)) atomicAdd(&bkt[occ_bucket(v[k])], 1u);
         }
         carry += wsum[0][NWV - 1];
         fcarry += wsum[1][NWV - 1];
@@ -426,7 +431,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__
     }
     if (tid == 0) {
         start[nbins] = carry;
-        if (occ) occ0_n[0] = fcarry;
+        if (occ && !empties) occ0_n[0] = fcarry;
     }
     if (!occ) return;
     __syncthreads();
@@ -441,7 +446,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__
     __syncthreads();
     for (int64_t i = tid; i < nbins; i += T) {
         const uint32_t c = totals[i];
-        if (c) occ[atomicAdd(&bkt[occ_bucket(c)], 1u)] = (uint32_t)i;
+        if (c || empties) occ[atomicAdd(&bkt[occ_bucket(c)], 1u)] = (uint32_t)i;
     }
 }
 
@@ -843,6 +848,32 @@ __device__ __forceinline__ double wave_sum(double v)
     return 0.0 + v;
 }
 
+// A double moved across lanes by a DPP control (both halves; lanes with no
+// source lane get 0).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// One wavefront's sum by DPP moves (no LDS round trips), valid in lane 63:
+// prefix sums within each row of 16 lanes (row_shr 1, 2, 4, 8), then row
+// 15's value broadcast into the next row (row_bcast:15) and lane 31's into
+// the upper half (row_bcast:31).  Where the additions fall differs from
+// wave_sum (any order: the atomic mode's sums are not order-fixed).
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v += dpp_f64<0x111, 0xf>(v);     // row_shr:1
+    v += dpp_f64<0x112, 0xf>(v);     // row_shr:2
+    v += dpp_f64<0x114, 0xf>(v);     // row_shr:4
+    v += dpp_f64<0x118, 0xf>(v);     // row_shr:8
+    v += dpp_f64<0x142, 0xa>(v);     // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xc>(v);     // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // Partial sums of Eq. 1 per forward bin in the atomic mode: one (sum, count)
 // pair per wavefront of the splat workgroup (at most 8), so that a bin needs
 // no cross-wavefront reduction; the finalize adds them.
@@ -1016,9 +1047,9 @@ __global__ __launch_bounds__(NTT) void fwd_tile_own_kernel(const TileBin* __rest
             if (tb2) plane1[pix] = b;
             reduce_pixel(a, b, bi.eps, sum, cnt);
         }
-        sum = wave_sum(sum);
-        cnt = wave_sum(cnt);
-        if ((threadIdx.x & 63) == 0) {
+        sum = wave_sum_dpp(sum);
+        cnt = wave_sum_dpp(cnt);
+        if ((threadIdx.x & 63) == 63) {
             double* pp = part + (size_t)gbin * kPartOwn + (threadIdx.x >> 6) * 2;
             pp[0] = sum;
             pp[1] = cnt;
@@ -1540,13 +1571,17 @@ template <bool EXACT, bool AE, int TWX, int THX>
 __global__ __launch_bounds__(256) void bwd_tile_own_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const GradRec* __restrict__ rec,
     const uint32_t* __restrict__ start, const uint32_t* __restrict__ start_src,
-    const float* __restrict__ rho, const float* __restrict__ ego, const float* __restrict__ grad_loss,
+    const uint32_t* __restrict__ order, const float* __restrict__ rho,
+    const float* __restrict__ ego, const float* __restrict__ grad_loss,
     float* __restrict__ drho, double* __restrict__ part)
 {
     constexpr int NT = 256, NPIX = TWX * THX;
     __shared__ double2 lds[NPIX];
     __shared__ double red[16 * 6];
-    const int64_t gtile = blockIdx.x;       // backward bin: (flow set, tile) of a window
+    // backward bin: (flow set, tile) of a window; with AE the source bins'
+    // heaviest-first order (one source bin per backward bin), so that the
+    // longest bins are launched first
+    const int64_t gtile = AE ? (int64_t)order[blockIdx.x] : (int64_t)blockIdx.x;
     const int w = win_of[gtile];
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
@@ -1910,7 +1945,8 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     B.ws.totals = take((size_t)(B.seg + 1 + sbin) * sizeof(uint32_t));
     B.ws.start = take((size_t)(B.seg + 1 + sbin + 1) * sizeof(uint32_t));
     // the occupied forward bins, listed by the scan, and their count
-    B.ws.occ = take((size_t)(bin + 2) * sizeof(uint32_t));
+    // and (source bins) all of them, heaviest first, for the backward tiles
+    B.ws.occ = take((size_t)(bin + 2 + sbin) * sizeof(uint32_t));
     B.ws.part = take((size_t)std::max(bin * (det ? 4 : kPartOwn), bbin * 12) * sizeof(double));
     B.ws.halo = take(det ? (size_t)std::max<int64_t>(bin * (NHALO + NBORDER) * 2,
                                                      bbin * (NHALO + NBORDER)) *
@@ -1998,7 +2034,7 @@ static void launch_window_table(const BatchPlanHost& B, const WinMeta* meta, int
 
 // Pointers into a batch's workspace.
 struct WsPtrs {
-    uint32_t *hist, *csum, *totals, *totals_src, *start, *start_src, *occ, *occ_n;
+    uint32_t *hist, *csum, *totals, *totals_src, *start, *start_src, *occ, *occ_n, *occ_src;
     double* part;
     double2* halo;
     char* records;
@@ -2020,6 +2056,7 @@ static WsPtrs ws_ptrs(const BatchPlanHost& B, char* ws)
     p.start_src = p.start + B.seg + 1;
     p.occ = reinterpret_cast<uint32_t*>(ws + B.ws.occ);
     p.occ_n = p.occ + B.nbins;
+    p.occ_src = p.occ + B.nbins + 2;
     p.part = reinterpret_cast<double*>(ws + B.ws.part);
     p.halo = reinterpret_cast<double2*>(ws + B.ws.halo);
     p.records = ws + B.ws.records;
@@ -2070,7 +2107,7 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
             offsets_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_f, 0, W.hist, W.csum, W.start);
         } else {
             scan_kernel<<<2, 1024, 0, s>>>(W.totals, B.nbins, W.start, W.totals_src, B.nbins_s,
-                                           W.start_src, W.occ, W.occ_n);
+                                           W.start_src, W.occ, W.occ_n, W.occ_src);
         }
     }
     {
@@ -2193,12 +2230,12 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
                 constexpr int TWX = decltype(twc)::value, THX = decltype(thc)::value;
                 if (ae)
                     bwd_tile_own_kernel<EX, true, TWX, THX><<<(int)B.nbins_b, 256, 0, s>>>(
-                        meta, nw, win_tile, rec, W.start, W.start_src, rho, ego, grad_loss,
-                        grad_rho, W.part);
+                        meta, nw, win_tile, rec, W.start, W.start_src, W.occ_src, rho, ego,
+                        grad_loss, grad_rho, W.part);
                 else
                     bwd_tile_own_kernel<EX, false, TWX, THX><<<(int)B.nbins_b, 256, 0, s>>>(
-                        meta, nw, win_tile, rec, W.start, W.start_src, rho, ego, grad_loss,
-                        grad_rho, W.part);
+                        meta, nw, win_tile, rec, W.start, W.start_src, nullptr, rho, ego,
+                        grad_loss, grad_rho, W.part);
             });
         }
     }
