@@ -338,40 +338,20 @@ __global__ __launch_bounds__(256) void chunk_scan_kernel(const WinMeta* __restri
 // totals1 -> start1): chunks of 8192 totals are loaded coalesced into LDS,
 // each thread sums 8 consecutive ones, the 1024 sums are scanned with in-wave
 // shuffles and the 16 wave totals by one wave, and the results go out
-// coalesced.  With occ0, block 0 also lists its non-empty bins
-// (occ0[0 .. occ0_n[0])), heaviest first by the binary order of magnitude of
-// their totals (in any order within one magnitude): the splat workgroups take
-// the list in passes, so the longest bins start first.  With occ1, block 1
-// lists all its bins the same way, the empty ones last (the order in which a
-// one-workgroup-per-bin kernel over them is launched).
-constexpr int kOccBuckets = 25;     // empty, then magnitudes 0 .. 23 (and above)
-__device__ __forceinline__ int occ_bucket(uint32_t c)
-{
-    if (c == 0) return 0;
-    const int b = 32 - __clz((int)c);
-    return b < kOccBuckets ? b : kOccBuckets - 1;
-}
-
+// coalesced.
 __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__ totals0,
                                                     int64_t nbins0, uint32_t* __restrict__ start0,
                                                     const uint32_t* __restrict__ totals1,
-                                                    int64_t nbins1, uint32_t* __restrict__ start1,
-                                                    uint32_t* __restrict__ occ0 = nullptr,
-                                                    uint32_t* __restrict__ occ0_n = nullptr,
-                                                    uint32_t* __restrict__ occ1 = nullptr)
+                                                    int64_t nbins1, uint32_t* __restrict__ start1)
 {
     const uint32_t* __restrict__ totals = blockIdx.x ? totals1 : totals0;
     const int64_t nbins = blockIdx.x ? nbins1 : nbins0;
     uint32_t* __restrict__ start = blockIdx.x ? start1 : start0;
-    uint32_t* __restrict__ occ = blockIdx.x ? occ1 : occ0;
-    const bool empties = blockIdx.x != 0;       // occ1 lists the empty bins too
     constexpr int T = 1024, K = 8, CH = T * K, NWV = T / 64;
     __shared__ uint32_t buf[CH];
-    __shared__ uint32_t wsum[2][NWV];
-    __shared__ uint32_t bkt[kOccBuckets];     // non-empty bins per magnitude, then list offsets
+    __shared__ uint32_t wsum[NWV];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    if (tid < kOccBuckets) bkt[tid] = 0u;
-    uint32_t carry = 0, fcarry = 0;
+    uint32_t carry = 0;
     for (int64_t base = 0; base < nbins; base += CH) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -379,48 +359,37 @@ __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__
             buf[k * T + tid] = i < nbins ? totals[i] : 0u;
         }
         __syncthreads();
-        uint32_t v[K], sum = 0, fsum = 0;
+        uint32_t v[K], sum = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             v[k] = buf[tid * K + k];
             sum += v[k];
-            fsum += v[k] ? 1u : 0u;
         }
-        uint32_t x = sum, fx = fsum;                       // inclusive scans within the wave
+        uint32_t x = sum;                       // inclusive scan within the wave
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t y = __shfl_up(x, o, 64);
-            const uint32_t fy = __shfl_up(fx, o, 64);
-            if (lane >= o) {
-                x += y;
-                fx += fy;
-            }
+            if (lane >= o) x += y;
         }
-        if (lane == 63) {
-            wsum[0][wid] = x;
-            wsum[1][wid] = fx;
-        }
+        if (lane == 63) wsum[wid] = x;
         __syncthreads();
-        if (wid < 2) {
-            uint32_t t = lane < NWV ? wsum[wid][lane] : 0u;
+        if (wid == 0) {
+            uint32_t t = lane < NWV ? wsum[lane] : 0u;
 #pragma unroll
             for (int o = 1; o < NWV; o <<= 1) {
                 const uint32_t y = __shfl_up(t, o, 64);
                 if (lane >= o) t += y;
             }
-            if (lane < NWV) wsum[wid][lane] = t;
+            if (lane < NWV) wsum[lane] = t;
         }
         __syncthreads();
-        uint32_t run = carry + (wid ? wsum[0][wid - 1] : 0u) + (x - sum);
-        const int64_t i0 = base + (int64_t)tid * K;
+        uint32_t run = carry + (wid ? wsum[wid - 1] : 0u) + (x - sum);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             buf[tid * K + k] = run;
             run += v[k];
-            if (occ && (v[k] || empties)) atomicAdd(&bkt[occ_bucket(v[k])], 1u);
         }
-        carry += wsum[0][NWV - 1];
-        fcarry += wsum[1][NWV - 1];
+        carry += wsum[NWV - 1];
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -429,24 +398,185 @@ __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__
         }
         __syncthreads();
     }
-    if (tid == 0) {
-        start[nbins] = carry;
-        if (occ && !empties) occ0_n[0] = fcarry;
-    }
-    if (!occ) return;
+    if (tid == 0) start[nbins] = carry;
+}
+
+// Atomic mode: the forward's scan, one workgroup per chunk of 8192 bins of
+// either array (blocks [0, nc0): the reference bins' chunks, then the source
+// bins'): a chunk's first slot is the sum of the totals before it, which its
+// workgroup adds up itself (all final when this kernel runs), so the chunks
+// scan independently, with no workgroup waiting on another (past
+// kScanChunksMax chunks, chunk_sums_kernel first writes each chunk's total,
+// and the workgroups add those up instead of the bins before them).
+// Each workgroup also lists its chunk's bins, heaviest first: those of at
+// least kVeryHeavyBin records, then those of at least kHeavyBin (each class
+// in any order), then the rest; the reference list takes the non-empty bins
+// (the splat workgroups take it in passes, so the longest bins start first),
+// the source list all of them (the order in which a one-workgroup-per-bin
+// kernel over them is launched).  A list of capacity cap (the array's bins)
+// keeps each class in a region of its own: the rest at [0, cap), the heavy
+// bins at [cap, 2 cap), the very heavy ones at [2 cap, 3 cap); its counters,
+// cleared by the window table kernel, are the entry count, the very heavy
+// and the heavy bins' counts, cap, and the rest's count.  A workgroup
+// reserves its entries of each class with one returning atomic.
+constexpr uint32_t kHeavyBin = 1024, kVeryHeavyBin = 4096;
+constexpr int kListCounters = 8;
+constexpr int kScanChunk8k = 8192, kScanChunksMax = 16;
+
+// Entry e of such a list.
+__device__ __forceinline__ uint32_t occ_entry(const uint32_t* __restrict__ occ,
+                                              const uint32_t* __restrict__ occ_n, uint32_t e)
+{
+    const uint32_t n2 = occ_n[1], n1 = occ_n[2], cap = occ_n[3];
+    if (e < n2) return occ[2 * cap + e];
+    if (e < n2 + n1) return occ[cap + (e - n2)];
+    return occ[e - n2 - n1];
+}
+
+// Each chunk's total (blocks as in scan_chunks_kernel).
+__global__ __launch_bounds__(1024) void chunk_sums_kernel(const uint32_t* __restrict__ totals0,
+                                                          int64_t nbins0,
+                                                          const uint32_t* __restrict__ totals1,
+                                                          int64_t nbins1,
+                                                          uint32_t* __restrict__ chunk_tot)
+{
+    constexpr int T = 1024, CH = kScanChunk8k;
+    __shared__ uint32_t ws[T / 64];
+    const int64_t nc0 = (nbins0 + CH - 1) / CH;
+    const int arr = (int64_t)blockIdx.x < nc0 ? 0 : 1;
+    const int64_t base = (arr ? (int64_t)blockIdx.x - nc0 : (int64_t)blockIdx.x) * CH;
+    const uint32_t* __restrict__ totals = arr ? totals1 : totals0;
+    const int64_t nbins = arr ? nbins1 : nbins0;
+    uint32_t v = 0;
+    for (int64_t i = base + threadIdx.x; i < base + CH && i < nbins; i += T) v += totals[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (tid == 0) {
-        uint32_t at = 0;
-        for (int b = kOccBuckets - 1; b >= 0; --b) {
-            const uint32_t c = bkt[b];
-            bkt[b] = at;
-            at += c;
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int i = 0; i < T / 64; ++i) t += ws[i];
+        chunk_tot[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(1024) void scan_chunks_kernel(
+    const uint32_t* __restrict__ totals0, int64_t nbins0, uint32_t* __restrict__ start0,
+    uint32_t* __restrict__ occ0, uint32_t* __restrict__ occ0_n,
+    const uint32_t* __restrict__ totals1, int64_t nbins1, uint32_t* __restrict__ start1,
+    uint32_t* __restrict__ occ1, uint32_t* __restrict__ occ1_n,
+    const uint32_t* __restrict__ chunk_tot)
+{
+    constexpr int T = 1024, K = 8, CH = kScanChunk8k, NWV = T / 64;
+    static_assert(T * K == CH, "one chunk per workgroup");
+    __shared__ uint32_t buf[CH];
+    __shared__ uint32_t wsum[4][NWV];
+    __shared__ uint32_t res[4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t nc0 = (nbins0 + CH - 1) / CH;
+    const int arr = (int64_t)blockIdx.x < nc0 ? 0 : 1;
+    const int64_t chunk = arr ? (int64_t)blockIdx.x - nc0 : (int64_t)blockIdx.x;
+    const uint32_t* __restrict__ totals = arr ? totals1 : totals0;
+    const int64_t nbins = arr ? nbins1 : nbins0;
+    uint32_t* __restrict__ start = arr ? start1 : start0;
+    uint32_t* __restrict__ list = arr ? occ1 : occ0;
+    uint32_t* __restrict__ ln = arr ? occ1_n : occ0_n;
+    const uint32_t cap = (uint32_t)nbins;
+    const bool empties = arr != 0;
+    const int64_t base = chunk * CH;
+    // the chunk's own totals, and the sum of those before it
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t i = base + k * T + tid;
+        buf[k * T + tid] = i < nbins ? totals[i] : 0u;
+    }
+    uint32_t before = 0;
+    if (chunk_tot) {
+        const int64_t c0 = arr ? nc0 : 0;
+        for (int64_t c = tid; c < chunk; c += T) before += chunk_tot[c0 + c];
+    } else {
+        for (int64_t i = tid; i < base; i += T) before += totals[i];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) before += __shfl_down(before, o, 64);
+    if (lane == 0) wsum[0][wid] = before;
+    if (tid == 0 && chunk == 0) ln[3] = cap;
+    __syncthreads();
+    uint32_t carry = 0;
+#pragma unroll
+    for (int i = 0; i < NWV; ++i) carry += wsum[0][i];
+    const int64_t i0 = base + (int64_t)tid * K;
+    // per thread: the sum, its listed light bins, and its heavy bins packed
+    // (very heavy in the low 16 bits, heavy in the high 16: at most 512 of
+    // either in a wavefront)
+    uint32_t v[K], sum = 0, fsum = 0, h = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        v[k] = buf[tid * K + k];
+        sum += v[k];
+        if (v[k] >= kVeryHeavyBin) h += 1u;
+        else if (v[k] >= kHeavyBin) h += 1u << 16;
+        else if (i0 + k < nbins && (v[k] || empties)) ++fsum;
+    }
+    uint32_t x = sum, fx = fsum, hx = h;               // inclusive scans within the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        const uint32_t fy = __shfl_up(fx, o, 64);
+        const uint32_t hy = __shfl_up(hx, o, 64);
+        if (lane >= o) {
+            x += y;
+            fx += fy;
+            hx += hy;
+        }
+    }
+    __syncthreads();        // (wsum[0] read above)
+    if (lane == 63) {
+        wsum[0][wid] = x;
+        wsum[1][wid] = fx;
+        wsum[2][wid] = hx & 0xffffu;
+        wsum[3][wid] = hx >> 16;
+    }
+    __syncthreads();
+    if (tid < 4) {
+        // exclusive prefix over the wavefronts, and the chunk's entries of
+        // each listed class reserved in the list
+        uint32_t t = 0;
+#pragma unroll
+        for (int i = 0; i < NWV; ++i) {
+            const uint32_t c = wsum[tid][i];
+            wsum[tid][i] = t;
+            t += c;
+        }
+        uint32_t r = 0;
+        if (tid == 1 && t) r = atomicAdd(&ln[4], t);
+        if (tid == 2 && t) r = atomicAdd(&ln[1], t);
+        if (tid == 3 && t) r = atomicAdd(&ln[2], t);
+        res[tid] = r;
+        if (tid >= 1 && t) atomicAdd(&ln[0], t);
+        if (tid == 0 && base + CH >= nbins) start[nbins] = carry + t;     // the array's end
+    }
+    __syncthreads();
+    uint32_t run = carry + wsum[0][wid] + (x - sum);
+    uint32_t frun = res[1] + wsum[1][wid] + (fx - fsum);
+    uint32_t o2 = res[2] + wsum[2][wid] + ((hx - h) & 0xffffu);
+    uint32_t o1 = res[3] + wsum[3][wid] + ((hx - h) >> 16);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        buf[tid * K + k] = run;
+        run += v[k];
+        if (i0 + k < nbins) {
+            const uint32_t bin = (uint32_t)(i0 + k);
+            if (v[k] >= kVeryHeavyBin) list[2 * cap + o2++] = bin;
+            else if (v[k] >= kHeavyBin) list[cap + o1++] = bin;
+            else if (v[k] || empties) list[frun++] = bin;
         }
     }
     __syncthreads();
-    for (int64_t i = tid; i < nbins; i += T) {
-        const uint32_t c = totals[i];
-        if (c || empties) occ[atomicAdd(&bkt[occ_bucket(c)], 1u)] = (uint32_t)i;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t i = base + k * T + tid;
+        if (i < nbins) start[i] = buf[k * T + tid];
     }
 }
 
@@ -952,7 +1082,7 @@ __global__ __launch_bounds__(NTT) void fwd_tile_own_kernel(const TileBin* __rest
         if (threadIdx.x < kBinTable && j < nb) {
             OwnBin e;
             const uint32_t kk = entry(j * per + slot);
-            e.g = kk < nocc ? occ[kk] : 0u;
+            e.g = kk < nocc ? occ_entry(occ, occ_n, kk) : 0u;
             e.s0 = start[e.g];
             e.s1 = start[e.g + 1];
             e.b = tbin[e.g];
@@ -1571,7 +1701,8 @@ template <bool EXACT, bool AE, int TWX, int THX>
 __global__ __launch_bounds__(256) void bwd_tile_own_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const GradRec* __restrict__ rec,
     const uint32_t* __restrict__ start, const uint32_t* __restrict__ start_src,
-    const uint32_t* __restrict__ order, const float* __restrict__ rho,
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ order_n,
+    const float* __restrict__ rho,
     const float* __restrict__ ego, const float* __restrict__ grad_loss,
     float* __restrict__ drho, double* __restrict__ part)
 {
@@ -1581,7 +1712,7 @@ __global__ __launch_bounds__(256) void bwd_tile_own_kernel(
     // backward bin: (flow set, tile) of a window; with AE the source bins'
     // heaviest-first order (one source bin per backward bin), so that the
     // longest bins are launched first
-    const int64_t gtile = AE ? (int64_t)order[blockIdx.x] : (int64_t)blockIdx.x;
+    const int64_t gtile = AE ? (int64_t)occ_entry(order, order_n, blockIdx.x) : (int64_t)blockIdx.x;
     const int w = win_of[gtile];
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
@@ -1942,11 +2073,16 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     B.seg = std::max(bin, bbin);
     B.ws.hist = take((size_t)hist * sizeof(uint32_t));
     B.ws.csum = take((size_t)csum * sizeof(uint32_t));
-    B.ws.totals = take((size_t)(B.seg + 1 + sbin) * sizeof(uint32_t));
+    // (then, atomic mode: the counters of the heaviest-first bin lists, and
+    // the scan chunks' totals)
+    const int64_t nchunks = (bin + kScanChunk8k - 1) / kScanChunk8k +
+                            (sbin + kScanChunk8k - 1) / kScanChunk8k;
+    B.ws.totals =
+        take((size_t)(B.seg + 1 + sbin + 2 * kListCounters + nchunks) * sizeof(uint32_t));
     B.ws.start = take((size_t)(B.seg + 1 + sbin + 1) * sizeof(uint32_t));
     // the occupied forward bins, listed by the scan, and their count
     // and (source bins) all of them, heaviest first, for the backward tiles
-    B.ws.occ = take((size_t)(bin + 2 + sbin) * sizeof(uint32_t));
+    B.ws.occ = take((size_t)(3 * bin + 3 * sbin) * sizeof(uint32_t));
     B.ws.part = take((size_t)std::max(bin * (det ? 4 : kPartOwn), bbin * 12) * sizeof(double));
     B.ws.halo = take(det ? (size_t)std::max<int64_t>(bin * (NHALO + NBORDER) * 2,
                                                      bbin * (NHALO + NBORDER)) *
@@ -2034,7 +2170,9 @@ static void launch_window_table(const BatchPlanHost& B, const WinMeta* meta, int
 
 // Pointers into a batch's workspace.
 struct WsPtrs {
-    uint32_t *hist, *csum, *totals, *totals_src, *start, *start_src, *occ, *occ_n, *occ_src;
+    uint32_t *hist, *csum, *totals, *totals_src, *start, *start_src;
+    uint32_t *occ, *occ_n, *occ_src, *occ_src_n;   // heaviest-first bin lists and counters
+    uint32_t* chunk_tot;                           // scan chunks' totals
     double* part;
     double2* halo;
     char* records;
@@ -2055,8 +2193,10 @@ static WsPtrs ws_ptrs(const BatchPlanHost& B, char* ws)
     p.start = reinterpret_cast<uint32_t*>(ws + B.ws.start);
     p.start_src = p.start + B.seg + 1;
     p.occ = reinterpret_cast<uint32_t*>(ws + B.ws.occ);
-    p.occ_n = p.occ + B.nbins;
-    p.occ_src = p.occ + B.nbins + 2;
+    p.occ_src = p.occ + 3 * B.nbins;
+    p.occ_n = p.totals_src + B.nbins_s;
+    p.occ_src_n = p.occ_n + kListCounters;
+    p.chunk_tot = p.occ_src_n + kListCounters;
     p.part = reinterpret_cast<double*>(ws + B.ws.part);
     p.halo = reinterpret_cast<double2*>(ws + B.ws.halo);
     p.records = ws + B.ws.records;
@@ -2089,7 +2229,8 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
         else
             // (and the partial sums: the tile kernel writes those of occupied bins only)
             launch_window_table(B, meta, W.wtab, ego, W.mtab, hdrs, W.totals,
-                                B.seg + 1 + B.nbins_s, W.tbin, s, W.part, B.nbins * kPartOwn);
+                                B.seg + 1 + B.nbins_s + 2 * kListCounters, W.tbin, s,
+                                W.part, B.nbins * kPartOwn);
     }
     {
         PhaseScope ph(prof, kPhCount, s);
@@ -2106,8 +2247,16 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
             scan_kernel<<<1, 1024, 0, s>>>(W.totals, B.nbins, W.start, nullptr, 0, nullptr);
             offsets_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_f, 0, W.hist, W.csum, W.start);
         } else {
-            scan_kernel<<<2, 1024, 0, s>>>(W.totals, B.nbins, W.start, W.totals_src, B.nbins_s,
-                                           W.start_src, W.occ, W.occ_n, W.occ_src);
+            const int64_t nc0 = (B.nbins + kScanChunk8k - 1) / kScanChunk8k;
+            const int64_t nc1 = (B.nbins_s + kScanChunk8k - 1) / kScanChunk8k;
+            const bool sums = nc0 > kScanChunksMax || nc1 > kScanChunksMax;
+            if (sums)
+                chunk_sums_kernel<<<(int)(nc0 + nc1), 1024, 0, s>>>(W.totals, B.nbins,
+                                                                    W.totals_src, B.nbins_s,
+                                                                    W.chunk_tot);
+            scan_chunks_kernel<<<(int)(nc0 + nc1), 1024, 0, s>>>(
+                W.totals, B.nbins, W.start, W.occ, W.occ_n, W.totals_src, B.nbins_s,
+                W.start_src, W.occ_src, W.occ_src_n, sums ? W.chunk_tot : nullptr);
         }
     }
     {
@@ -2230,11 +2379,13 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
                 constexpr int TWX = decltype(twc)::value, THX = decltype(thc)::value;
                 if (ae)
                     bwd_tile_own_kernel<EX, true, TWX, THX><<<(int)B.nbins_b, 256, 0, s>>>(
-                        meta, nw, win_tile, rec, W.start, W.start_src, W.occ_src, rho, ego,
+                        meta, nw, win_tile, rec, W.start, W.start_src, W.occ_src, W.occ_src_n,
+                        rho, ego,
                         grad_loss, grad_rho, W.part);
                 else
                     bwd_tile_own_kernel<EX, false, TWX, THX><<<(int)B.nbins_b, 256, 0, s>>>(
-                        meta, nw, win_tile, rec, W.start, W.start_src, nullptr, rho, ego,
+                        meta, nw, win_tile, rec, W.start, W.start_src, nullptr, nullptr, rho,
+                        ego,
                         grad_loss, grad_rho, W.part);
             });
         }
