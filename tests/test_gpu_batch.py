@@ -76,6 +76,30 @@ def test_batch_matches_oracle_per_window(cm):
         assert_grads_close(g_rho[a:b], g_ego[w], ob["drho"].ravel(), ob["dtheta"], what=win.name)
 
 
+def test_batch_of_many_bins_matches_oracle(cm):
+    """A batch with more forward bins than the scan's one-pass limit (20 windows of
+    1280x720 with 8 references: 147,200 bins, 18 chunks of 8192), so that the scan
+    takes per-chunk totals first; every window's loss and the last windows'
+    gradients against the oracle (a wrong chunk prefix misplaces every later
+    window's records)."""
+    refs = list(eventgen.refs_even(8))
+    wins = [eventgen.edge_window(900 + i, "1280x720", 3000, refs=refs, n_segments=20,
+                                 name=f"m{i}") for i in range(20)]
+    batch = make_batch(cm, wins)
+    print(f"[gpu] batch of {batch.n} windows, {batch.event_offsets[-1]} events, 8 refs",
+          flush=True)
+    loss, g_rho, g_ego, diag = run_batch(cm, batch, pack(wins))
+    for w, win in enumerate(wins):
+        o = oracle.forward(win, valid=True)
+        assert_loss_close(loss[w], o["loss"], what=win.name)
+        assert diag[w][1] == int(o["valid"].sum())
+    for w in (0, 10, 19):
+        ob = oracle.backward(wins[w])
+        a, b = batch.pixel_offsets[w], batch.pixel_offsets[w + 1]
+        assert_grads_close(g_rho[a:b], g_ego[w], ob["drho"].ravel(), ob["dtheta"],
+                           what=wins[w].name)
+
+
 def test_batch_equals_single_window_calls(cm):
     wins = mixed_windows()
     batch = make_batch(cm, wins)
