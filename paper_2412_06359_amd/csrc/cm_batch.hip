@@ -1272,26 +1272,49 @@ __global__ __launch_bounds__(64 * kMergeBins) void fwd_merge_kernel(const TileBi
 
 // One block per window: fixed-order sums of the tile and merge partials per
 // reference, then Eq. 1.
-__global__ __launch_bounds__(256) void fwd_finalize_kernel(const WinMeta* __restrict__ meta,
-                                                           const double* __restrict__ part,
-                                                           int pstride,
-                                                           StateHeader* __restrict__ hdrs,
-                                                           float* __restrict__ loss)
+// One workgroup per window: Eq. 1 per reference from its bins' partial sums
+// (pstride doubles per bin, of which the first pused (sum, count) pairs are
+// written: one per wavefront of the atomic mode's splat workgroup, two in the
+// deterministic mode), then the loss.  1024 threads in the atomic mode: a
+// window with many bins (c5: 7,360 bins of 8 pairs) has them read by many
+// lanes at once; 256 in the deterministic mode (its fixed addition order).
+constexpr int kFinalizeThreads = 1024;
+__global__ __launch_bounds__(kFinalizeThreads) void fwd_finalize_kernel(
+    const WinMeta* __restrict__ meta, const double* __restrict__ part, int pstride, int pused,
+    StateHeader* __restrict__ hdrs, float* __restrict__ loss)
 {
     __shared__ double red[16 * 2];
     const int w = blockIdx.x;
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
-    // pstride doubles per bin: (sum, count) pairs
     const double* pw = part + meta[w].bin_off * pstride;
-    const int npair = G.ntiles * pstride / 2;
+    const int nt = G.ntiles * pused;
     StateHeader* hdr = hdrs + w;
     double L = 0.0;
     for (int r = 0; r < P.R; ++r) {
         double sc[2] = {0.0, 0.0};
-        for (int j = threadIdx.x; j < npair; j += blockDim.x) {
-            sc[0] += pw[((size_t)r * npair + j) * 2 + 0];
-            sc[1] += pw[((size_t)r * npair + j) * 2 + 1];
+        // four items per round, loaded before they are added (in item order:
+        // the same additions as one item at a time)
+        const int nthr = (int)blockDim.x;
+        for (int t0 = threadIdx.x; t0 < nt; t0 += 4 * nthr) {
+            double2 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u * nthr;
+                v[u] = make_double2(0.0, 0.0);
+                if (t < nt) {
+                    const int tile = t / pused, q = t - tile * pused;
+                    const double* pp = pw + ((size_t)r * G.ntiles + tile) * pstride + 2 * q;
+                    v[u] = make_double2(pp[0], pp[1]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (t0 + u * nthr < nt) {
+                    sc[0] += v[u].x;
+                    sc[1] += v[u].y;
+                }
+            }
         }
         block_sum_n(sc, red);
         if (threadIdx.x == 0) {
@@ -2288,7 +2311,10 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     }
     {
         PhaseScope ph(prof, kPhFinalize, s);
-        fwd_finalize_kernel<<<nw, 256, 0, s>>>(meta, W.part, DET ? 4 : kPartOwn, hdrs, loss);
+        // (the deterministic mode keeps 256 threads: its addition order, which
+        // the mirror follows)
+        fwd_finalize_kernel<<<nw, DET ? 256 : kFinalizeThreads, 0, s>>>(
+            meta, W.part, DET ? 4 : kPartOwn, DET ? 2 : B.tile_threads / 64, hdrs, loss);
     }
     return hipGetLastError();
 }
