@@ -1720,6 +1720,10 @@ __global__ __launch_bounds__(64 * kDetAccWaves) void bwd_tile_det_kernel(
 // the source records); it accumulates dL/du at the taps inside the tile in
 // LDS, then writes d rho of every pixel and reduces the tile's d theta share.
 // No halo, no merge.
+// Partial d theta per backward bin in the atomic mode: six per wavefront of
+// the tile workgroup (four); the finalize adds them.
+constexpr int kBwdPartOwn = 24;
+
 template <bool EXACT, bool AE, int TWX, int THX>
 __global__ __launch_bounds__(256) void bwd_tile_own_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const GradRec* __restrict__ rec,
@@ -1731,7 +1735,6 @@ __global__ __launch_bounds__(256) void bwd_tile_own_kernel(
 {
     constexpr int NT = 256, NPIX = TWX * THX;
     __shared__ double2 lds[NPIX];
-    __shared__ double red[16 * 6];
     // backward bin: (flow set, tile) of a window; with AE the source bins'
     // heaviest-first order (one source bin per backward bin), so that the
     // longest bins are launched first
@@ -1754,7 +1757,7 @@ __global__ __launch_bounds__(256) void bwd_tile_own_kernel(
             const int X = xo + i % TWX, Y = yo + i / TWX;
             if (X < P.W && Y < P.H) drho_w[Y * P.W + X] = z;
         }
-        if (threadIdx.x < 12) part[gtile * 12 + threadIdx.x] = 0.0;
+        if (threadIdx.x < kBwdPartOwn) part[gtile * kBwdPartOwn + threadIdx.x] = 0.0;
         return;
     }
     // the first round's records, in flight during the clear
@@ -1818,13 +1821,12 @@ __global__ __launch_bounds__(256) void bwd_tile_own_kernel(
         drho_w[pix] = (float)(gl * (g.x * Bx + g.y * By));
         if (g.x != 0.0 || g.y != 0.0) dtheta_at_pixel(P, X, Y, (double)rho_w[pix], g.x, g.y, dth);
     }
-    block_sum_n(dth, red);
-    if (threadIdx.x == 0)
+    // each wavefront's d theta share (DPP sums, no block reduction)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            part[gtile * 12 + c] = dth[c];
-            part[gtile * 12 + 6 + c] = 0.0;
-        }
+    for (int c = 0; c < 6; ++c) dth[c] = wave_sum_dpp(dth[c]);
+    if ((threadIdx.x & 63) == 63)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) part[gtile * kBwdPartOwn + (threadIdx.x >> 6) * 6 + c] = dth[c];
 }
 
 template <bool EXACT>
@@ -1907,8 +1909,11 @@ __global__ __launch_bounds__(64 * kMergeBins) void bwd_merge_kernel(
 // One block per window: fixed-order sum of its tiles' d theta partials, per
 // flow set (the six components through one block reduction, each in
 // block_sum's order).
+// (pstride doubles per backward bin: groups of six, two in the deterministic
+// mode (tile and merge), one per wavefront in the atomic mode)
 __global__ __launch_bounds__(256) void bwd_finalize_kernel(const WinMeta* __restrict__ meta,
                                                            const double* __restrict__ part,
+                                                           int pstride,
                                                            const StateHeader* __restrict__ hdrs,
                                                            const float* __restrict__ grad_loss,
                                                            float* __restrict__ grad_ego)
@@ -1916,15 +1921,17 @@ __global__ __launch_bounds__(256) void bwd_finalize_kernel(const WinMeta* __rest
     __shared__ double red[16 * 6];
     const int w = blockIdx.x;
     const int ntiles = meta[w].G.ntiles;
+    const int ng = ntiles * (pstride / 6);
     const double gl = (hdrs[w].flags & kHdrSourceRecords) ? (double)grad_loss[w] : (double)NAN;
     for (int f = 0; f < meta[w].P.F; ++f) {
-        const double* pw = part + (meta[w].bbin_off + (int64_t)f * ntiles) * 12;
-        double v[6];
+        const double* pw = part + (meta[w].bbin_off + (int64_t)f * ntiles) * pstride;
+        // (each group's six values read together; every sum still adds the
+        // groups in order)
+        double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int j = threadIdx.x; j < ng; j += blockDim.x) {
+            const double* q = pw + (size_t)j * 6;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            double s = 0.0;
-            for (int j = threadIdx.x; j < 2 * ntiles; j += blockDim.x) s += pw[(size_t)j * 6 + c];
-            v[c] = s;
+            for (int c = 0; c < 6; ++c) v[c] += q[c];
         }
         block_sum_n(v, red);
         if (threadIdx.x == 0)
@@ -2106,7 +2113,8 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     // the occupied forward bins, listed by the scan, and their count
     // and (source bins) all of them, heaviest first, for the backward tiles
     B.ws.occ = take((size_t)(3 * bin + 3 * sbin) * sizeof(uint32_t));
-    B.ws.part = take((size_t)std::max(bin * (det ? 4 : kPartOwn), bbin * 12) * sizeof(double));
+    B.ws.part = take((size_t)std::max(bin * (det ? 4 : kPartOwn), bbin * (det ? 12 : kBwdPartOwn)) *
+                     sizeof(double));
     B.ws.halo = take(det ? (size_t)std::max<int64_t>(bin * (NHALO + NBORDER) * 2,
                                                      bbin * (NHALO + NBORDER)) *
                                sizeof(double2)
@@ -2312,9 +2320,14 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     {
         PhaseScope ph(prof, kPhFinalize, s);
         // (the deterministic mode keeps 256 threads: its addition order, which
-        // the mirror follows)
-        fwd_finalize_kernel<<<nw, DET ? 256 : kFinalizeThreads, 0, s>>>(
-            meta, W.part, DET ? 4 : kPartOwn, DET ? 2 : B.tile_threads / 64, hdrs, loss);
+        // the mirror follows; the atomic mode takes 1024 for windows of many
+        // partial sums)
+        int64_t items = 0;
+        for (const WinMeta& m : B.meta)
+            items = std::max<int64_t>(items, (int64_t)m.G.ntiles * m.P.R * (B.tile_threads / 64));
+        const int nthr = DET || items <= 4 * 1024 ? 256 : kFinalizeThreads;
+        fwd_finalize_kernel<<<nw, nthr, 0, s>>>(meta, W.part, DET ? 4 : kPartOwn,
+                                                 DET ? 2 : B.tile_threads / 64, hdrs, loss);
     }
     return hipGetLastError();
 }
@@ -2418,7 +2431,8 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
     }
     {
         PhaseScope ph(prof, kPhGradFinalize, s);
-        bwd_finalize_kernel<<<nw, 256, 0, s>>>(meta, W.part, hdrs, grad_loss, grad_ego);
+        bwd_finalize_kernel<<<nw, 256, 0, s>>>(meta, W.part, DET ? 12 : kBwdPartOwn, hdrs,
+                                               grad_loss, grad_ego);
     }
     return hipGetLastError();
 }
