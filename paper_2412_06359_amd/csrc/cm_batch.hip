@@ -1735,10 +1735,10 @@ __global__ __launch_bounds__(256) void bwd_tile_own_kernel(
 {
     constexpr int NT = 256, NPIX = TWX * THX;
     __shared__ double2 lds[NPIX];
-    // backward bin: (flow set, tile) of a window; with AE the source bins'
-    // heaviest-first order (one source bin per backward bin), so that the
-    // longest bins are launched first
-    const int64_t gtile = AE ? (int64_t)occ_entry(order, order_n, blockIdx.x) : (int64_t)blockIdx.x;
+    // backward bin: (flow set, tile) of a window, in the order of a
+    // heaviest-first list (the source bins' with AE, one per backward bin;
+    // else the backward scan's), so that the longest bins are launched first
+    const int64_t gtile = order ? (int64_t)occ_entry(order, order_n, blockIdx.x) : (int64_t)blockIdx.x;
     const int w = win_of[gtile];
     const WinParams& P = meta[w].P;
     const TileGeom G = meta[w].G;
@@ -2105,14 +2105,16 @@ BatchPlanHost plan_batch(const WinParams* params, const int64_t* n_events, int n
     B.ws.csum = take((size_t)csum * sizeof(uint32_t));
     // (then, atomic mode: the counters of the heaviest-first bin lists, and
     // the scan chunks' totals)
-    const int64_t nchunks = (bin + kScanChunk8k - 1) / kScanChunk8k +
+    const int64_t nchunks = (std::max(bin, bbin) + kScanChunk8k - 1) / kScanChunk8k +
                             (sbin + kScanChunk8k - 1) / kScanChunk8k;
     B.ws.totals =
         take((size_t)(B.seg + 1 + sbin + 2 * kListCounters + nchunks) * sizeof(uint32_t));
     B.ws.start = take((size_t)(B.seg + 1 + sbin + 1) * sizeof(uint32_t));
     // the occupied forward bins, listed by the scan, and their count
     // and (source bins) all of them, heaviest first, for the backward tiles
-    B.ws.occ = take((size_t)(3 * bin + 3 * sbin) * sizeof(uint32_t));
+    // (the forward's bins, then the backward's in the same list, and the
+    // source bins)
+    B.ws.occ = take((size_t)(3 * std::max(bin, bbin) + 3 * sbin) * sizeof(uint32_t));
     B.ws.part = take((size_t)std::max(bin * (det ? 4 : kPartOwn), bbin * (det ? 12 : kBwdPartOwn)) *
                      sizeof(double));
     B.ws.halo = take(det ? (size_t)std::max<int64_t>(bin * (NHALO + NBORDER) * 2,
@@ -2224,7 +2226,7 @@ static WsPtrs ws_ptrs(const BatchPlanHost& B, char* ws)
     p.start = reinterpret_cast<uint32_t*>(ws + B.ws.start);
     p.start_src = p.start + B.seg + 1;
     p.occ = reinterpret_cast<uint32_t*>(ws + B.ws.occ);
-    p.occ_src = p.occ + 3 * B.nbins;
+    p.occ_src = p.occ + 3 * std::max(B.nbins, B.nbins_b);
     p.occ_n = p.totals_src + B.nbins_s;
     p.occ_src_n = p.occ_n + kListCounters;
     p.chunk_tot = p.occ_src_n + kListCounters;
@@ -2372,8 +2374,10 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
             launch_window_table(B, meta, W.wtab, ego, W.mtab, nullptr, W.csum, B.csum_cells,
                                 W.tbin, s);
         else
+            // (and, after the backward bins' totals, the counters of their
+            // heaviest-first list: forward-only data lies there)
             launch_window_table(B, meta, W.wtab, ego, W.mtab, nullptr, W.totals,
-                                ae ? 0 : B.nbins_b, W.tbin, s);
+                                ae ? 0 : B.nbins_b + kListCounters, W.tbin, s);
         if (!ae)
             bwd_count_kernel<RM, NT, FM, DET><<<B.nblocks, NT, lds, s>>>(
                 meta, nw, win_blk, W.src, W.start_src, rho, ego, W.mtab, hdrs, W.hist, W.csum,
@@ -2388,7 +2392,15 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
             scan_kernel<<<1, 1024, 0, s>>>(W.totals, B.nbins_b, W.start, nullptr, 0, nullptr);
             offsets_kernel<<<gc, 256, 0, s>>>(meta, nw, B.cells_b, 1, W.hist, W.csum, W.start);
         } else {
-            scan_kernel<<<1, 1024, 0, s>>>(W.totals, B.nbins_b, W.start, nullptr, 0, nullptr);
+            // one array, its list holding the empty bins too (one workgroup per bin)
+            const int64_t nc = (B.nbins_b + kScanChunk8k - 1) / kScanChunk8k;
+            const bool sums = nc > kScanChunksMax;
+            if (sums)
+                chunk_sums_kernel<<<(int)nc, 1024, 0, s>>>(nullptr, 0, W.totals, B.nbins_b,
+                                                           W.chunk_tot);
+            scan_chunks_kernel<<<(int)nc, 1024, 0, s>>>(
+                nullptr, 0, nullptr, nullptr, nullptr, W.totals, B.nbins_b, W.start, W.occ,
+                W.totals + B.nbins_b, sums ? W.chunk_tot : nullptr);
         }
     }
     {
@@ -2423,8 +2435,8 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
                         grad_loss, grad_rho, W.part);
                 else
                     bwd_tile_own_kernel<EX, false, TWX, THX><<<(int)B.nbins_b, 256, 0, s>>>(
-                        meta, nw, win_tile, rec, W.start, W.start_src, nullptr, nullptr, rho,
-                        ego,
+                        meta, nw, win_tile, rec, W.start, W.start_src, W.occ,
+                        W.totals + B.nbins_b, rho, ego,
                         grad_loss, grad_rho, W.part);
             });
         }
