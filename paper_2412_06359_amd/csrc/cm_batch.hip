@@ -1550,7 +1550,9 @@ __global__ __launch_bounds__(NT, 3) void bwd_sweep_kernel(
     // window has up to four per valid event, more than the block geometry's
     // events per lane)
     const int64_t stride = (int64_t)G.nblocks * NT;
-    GradRec* const arec = rec + (wsrc - src);     // AE: record of source record i
+    // AE: the record of source record i (its event's dt * adjoint; the
+    // position is the source record's)
+    double2* const arec = reinterpret_cast<double2*>(rec) + (wsrc - src);
     SrcRec qn;
     int64_t i = (int64_t)lb * NT + threadIdx.x;
     if (i < nv) qn = load_nt(wsrc + i);
@@ -1566,7 +1568,7 @@ __global__ __launch_bounds__(NT, 3) void bwd_sweep_kernel(
             })) {
             // (a source record's event is valid: the forward's warp of the
             // same inputs; its slot still gets a record)
-            if (AE) store_nt(arec + i, GradRec{x0, y0, 0.0, 0.0});
+            if (AE) store_nt(arec + i, 0.0, 0.0);
             continue;
         }
         const int pol = (__float_as_uint(q.ts) >> 31) ? 1 : 0;
@@ -1603,7 +1605,7 @@ __global__ __launch_bounds__(NT, 3) void bwd_sweep_kernel(
                 }
             }
         }
-        if (AE) store_nt(arec + i, GradRec{x0, y0, g0x, g0y});
+        if (AE) store_nt(arec + i, g0x, g0y);
         else if (!split && P.R - (v.eq ? 1 : 0) > 0) emit(x0, y0, g0x, g0y, 0);
     }
 }
@@ -1727,7 +1729,8 @@ constexpr int kBwdPartOwn = 24;
 template <bool EXACT, bool AE, int TWX, int THX>
 __global__ __launch_bounds__(256) void bwd_tile_own_kernel(
     const WinMeta* __restrict__ meta, int nw, const int* __restrict__ win_of, const GradRec* __restrict__ rec,
-    const uint32_t* __restrict__ start, const uint32_t* __restrict__ start_src,
+    const SrcRec* __restrict__ src, const uint32_t* __restrict__ start,
+    const uint32_t* __restrict__ start_src,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ order_n,
     const float* __restrict__ rho,
     const float* __restrict__ ego, const float* __restrict__ grad_loss,
@@ -1760,12 +1763,24 @@ __global__ __launch_bounds__(256) void bwd_tile_own_kernel(
         if (threadIdx.x < kBwdPartOwn) part[gtile * kBwdPartOwn + threadIdx.x] = 0.0;
         return;
     }
+    // a record: with AE, the event's position from its source record and
+    // dt * adjoint from the sweep's 16-byte record at the same index
+    const double2* __restrict__ arec = reinterpret_cast<const double2*>(rec);
+    auto load_rec = [&](uint32_t i) {
+        if constexpr (AE) {
+            const SrcRec qs = load_nt(src + i);
+            const double2 g = load_nt(arec + i);
+            return GradRec{(double)qs.x0, (double)qs.y0, g.x, g.y};
+        } else {
+            return rec[i];
+        }
+    };
     // the first round's records, in flight during the clear
     uint32_t i0 = s0 + threadIdx.x;
     GradRec qq[2];
     if (i0 < s1) {
-        qq[0] = rec[i0];
-        qq[1] = rec[i0 + NT < s1 ? i0 + NT : i0];
+        qq[0] = load_rec(i0);
+        qq[1] = load_rec(i0 + NT < s1 ? i0 + NT : i0);
     }
     for (int i = threadIdx.x; i < NPIX; i += NT) lds[i] = make_double2(0.0, 0.0);
     __syncthreads();
@@ -1791,8 +1806,8 @@ __global__ __launch_bounds__(256) void bwd_tile_own_kernel(
         }
         i0 += 2 * NT;
         if (i0 < s1) {
-            qq[0] = rec[i0];
-            qq[1] = rec[i0 + NT < s1 ? i0 + NT : i0];
+            qq[0] = load_rec(i0);
+            qq[1] = load_rec(i0 + NT < s1 ? i0 + NT : i0);
         }
     }
     __syncthreads();
@@ -2430,12 +2445,13 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
                 constexpr int TWX = decltype(twc)::value, THX = decltype(thc)::value;
                 if (ae)
                     bwd_tile_own_kernel<EX, true, TWX, THX><<<(int)B.nbins_b, 256, 0, s>>>(
-                        meta, nw, win_tile, rec, W.start, W.start_src, W.occ_src, W.occ_src_n,
+                        meta, nw, win_tile, rec, W.src, W.start, W.start_src, W.occ_src,
+                        W.occ_src_n,
                         rho, ego,
                         grad_loss, grad_rho, W.part);
                 else
                     bwd_tile_own_kernel<EX, false, TWX, THX><<<(int)B.nbins_b, 256, 0, s>>>(
-                        meta, nw, win_tile, rec, W.start, W.start_src, W.occ,
+                        meta, nw, win_tile, rec, W.src, W.start, W.start_src, W.occ,
                         W.totals + B.nbins_b, rho, ego,
                         grad_loss, grad_rho, W.part);
             });

@@ -859,6 +859,20 @@ __device__ __forceinline__ SplatRec load_nt(const SplatRec* p)
     return q;
 }
 
+// An event-sampled backward record: dt * adjoint at the event, whose
+// position its source record holds (16 bytes at the source record's index).
+__device__ __forceinline__ void store_nt(double2* p, double gx, double gy)
+{
+    const nt_d2 a = {gx, gy};
+    __builtin_nontemporal_store(a, reinterpret_cast<nt_d2*>(p));
+}
+
+__device__ __forceinline__ double2 load_nt(const double2* p)
+{
+    const nt_d2 a = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+    return make_double2(a.x, a.y);
+}
+
 __device__ __forceinline__ void store_nt(GradRec* p, const GradRec& q)
 {
     const nt_d2 a = {q.X, q.Y}, b = {q.gx, q.gy};
