@@ -1275,13 +1275,13 @@ __global__ __launch_bounds__(64 * kMergeBins) void fwd_merge_kernel(const TileBi
 // One workgroup per window: Eq. 1 per reference from its bins' partial sums
 // (pstride doubles per bin, of which the first pused (sum, count) pairs are
 // written: one per wavefront of the atomic mode's splat workgroup, two in the
-// deterministic mode), then the loss.  1024 threads in the atomic mode: a
-// window with many bins (c5: 7,360 bins of 8 pairs) has them read by many
-// lanes at once; 256 in the deterministic mode (its fixed addition order).
+// deterministic mode), then the loss.  The atomic mode gives each reference
+// a wavefront of its own (per_wave; 64 R threads); the deterministic mode
+// takes the references in turn over 256 threads (its fixed addition order).
 constexpr int kFinalizeThreads = 1024;
 __global__ __launch_bounds__(kFinalizeThreads) void fwd_finalize_kernel(
     const WinMeta* __restrict__ meta, const double* __restrict__ part, int pstride, int pused,
-    StateHeader* __restrict__ hdrs, float* __restrict__ loss)
+    int per_wave, StateHeader* __restrict__ hdrs, float* __restrict__ loss)
 {
     __shared__ double red[16 * 2];
     const int w = blockIdx.x;
@@ -1291,6 +1291,53 @@ __global__ __launch_bounds__(kFinalizeThreads) void fwd_finalize_kernel(
     const int nt = G.ntiles * pused;
     StateHeader* hdr = hdrs + w;
     double L = 0.0;
+    if (per_wave) {
+        // atomic mode: wavefront r sums reference r's partials (R <= 16
+        // wavefronts), one barrier for all
+        const int lane = threadIdx.x & 63, r = threadIdx.x >> 6;
+        double a = 0.0, b = 0.0;
+        if (r < P.R) {
+            const double* pr = pw + (size_t)r * G.ntiles * pstride;
+            // eight items per lane and round, loaded before they are added
+            for (int t0 = lane; t0 < nt; t0 += 8 * 64) {
+                double2 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int t = t0 + u * 64;
+                    v[u] = make_double2(0.0, 0.0);
+                    if (t < nt) {
+                        const int tile = t / pused, q = t - tile * pused;
+                        const double* pp = pr + (size_t)tile * pstride + 2 * q;
+                        v[u] = make_double2(pp[0], pp[1]);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    a += v[u].x;
+                    b += v[u].y;
+                }
+            }
+        }
+        a = wave_sum_dpp(a);
+        b = wave_sum_dpp(b);
+        if (lane == 63) {
+            red[2 * r] = a;
+            red[2 * r + 1] = b;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int q = 0; q < P.R; ++q) {
+                hdr->num[q] = red[2 * q];
+                hdr->nact[q] = red[2 * q + 1];
+                L += red[2 * q] / (red[2 * q + 1] + P.eps);
+            }
+            L = L / (double)P.R;
+            hdr->loss = L;
+            hdr->flags = kHdrSourceRecords;
+            loss[w] = (float)L;
+        }
+        return;
+    }
     for (int r = 0; r < P.R; ++r) {
         double sc[2] = {0.0, 0.0};
         // four items per round, loaded before they are added (in item order:
@@ -1928,17 +1975,19 @@ __global__ __launch_bounds__(64 * kMergeBins) void bwd_merge_kernel(
 // mode (tile and merge), one per wavefront in the atomic mode)
 __global__ __launch_bounds__(256) void bwd_finalize_kernel(const WinMeta* __restrict__ meta,
                                                            const double* __restrict__ part,
-                                                           int pstride,
+                                                           int pstride, int max_F,
                                                            const StateHeader* __restrict__ hdrs,
                                                            const float* __restrict__ grad_loss,
                                                            float* __restrict__ grad_ego)
 {
     __shared__ double red[16 * 6];
-    const int w = blockIdx.x;
+    // one workgroup per (window, flow set): blockIdx.x = w * max_F + f
+    const int w = (int)blockIdx.x / max_F, f = (int)blockIdx.x - w * max_F;
+    if (f >= meta[w].P.F) return;
     const int ntiles = meta[w].G.ntiles;
     const int ng = ntiles * (pstride / 6);
     const double gl = (hdrs[w].flags & kHdrSourceRecords) ? (double)grad_loss[w] : (double)NAN;
-    for (int f = 0; f < meta[w].P.F; ++f) {
+    {
         const double* pw = part + (meta[w].bbin_off + (int64_t)f * ntiles) * pstride;
         // (each group's six values read together; every sum still adds the
         // groups in order)
@@ -2336,15 +2385,14 @@ static hipError_t batch_forward_rm(const BatchPlanHost& B, const WinMeta* meta,
     }
     {
         PhaseScope ph(prof, kPhFinalize, s);
-        // (the deterministic mode keeps 256 threads: its addition order, which
-        // the mirror follows; the atomic mode takes 1024 for windows of many
-        // partial sums)
-        int64_t items = 0;
-        for (const WinMeta& m : B.meta)
-            items = std::max<int64_t>(items, (int64_t)m.G.ntiles * m.P.R * (B.tile_threads / 64));
-        const int nthr = DET || items <= 4 * 1024 ? 256 : kFinalizeThreads;
-        fwd_finalize_kernel<<<nw, nthr, 0, s>>>(meta, W.part, DET ? 4 : kPartOwn,
-                                                 DET ? 2 : B.tile_threads / 64, hdrs, loss);
+        // (the deterministic mode keeps 256 threads and its references in
+        // turn: its addition order, which the mirror follows; the atomic
+        // mode sums every reference at once, a wavefront each)
+        if (DET)
+            fwd_finalize_kernel<<<nw, 256, 0, s>>>(meta, W.part, 4, 2, 0, hdrs, loss);
+        else
+            fwd_finalize_kernel<<<nw, 64 * B.max_R, 0, s>>>(meta, W.part, kPartOwn,
+                                                            B.tile_threads / 64, 1, hdrs, loss);
     }
     return hipGetLastError();
 }
@@ -2459,8 +2507,8 @@ static hipError_t batch_backward_rm(const BatchPlanHost& B, const WinMeta* meta,
     }
     {
         PhaseScope ph(prof, kPhGradFinalize, s);
-        bwd_finalize_kernel<<<nw, 256, 0, s>>>(meta, W.part, DET ? 12 : kBwdPartOwn, hdrs,
-                                               grad_loss, grad_ego);
+        bwd_finalize_kernel<<<nw * B.max_F, 256, 0, s>>>(meta, W.part, DET ? 12 : kBwdPartOwn,
+                                                         B.max_F, hdrs, grad_loss, grad_ego);
     }
     return hipGetLastError();
 }
