@@ -184,6 +184,66 @@ def test_c3_batch_full_size(cm):
                            what=f"c3[{w}]")
 
 
+@pytest.fixture(scope="module")
+def c3_reference():
+    """The 64 c3 windows and the oracle's loss and gradients for each (computed once)."""
+    wins = eventgen.make_batch("c3", 64)
+    with cf.ThreadPoolExecutor(8) as ex:
+        ref = list(ex.map(lambda w: (oracle.forward(w, valid=True), oracle.backward(w)), wins))
+    return wins, ref
+
+
+@pytest.mark.parametrize("tuning", [(8192, 512, 32, 32), (4096, 256, 32, 32),
+                                    (16384, 512, 64, 32), (8192, 512, 16, 16)])
+def test_c3_batch_full_size_tunings(cm, c3_reference, tuning):
+    """All 64 c3 windows at the launch shapes the autotuner chooses between (the first
+    is the one the bench times), graph replay, each against the oracle."""
+    wins, ref = c3_reference
+    eb, tt, tw, th = tuning
+    descs = [cm.WindowDesc.from_window(w) for w in wins]
+    batch = cm.Batch(descs, [w.n for w in wins], graph=True,
+                     tuning=dict(event_blocks=eb, tile_threads=tt, tile_w=tw, tile_h=th))
+    print(f"[gpu] c3 batch at tuning {tuning}", flush=True)
+    loss, g_rho, g_ego, diag = run_batch(cm, batch, pack(wins))
+    for w, (o, ob) in enumerate(ref):
+        assert_loss_close(loss[w], o["loss"], what=f"c3[{w}] {tuning}")
+        assert diag[w][1] == int(o["valid"].sum()), w
+        a, b = batch.pixel_offsets[w], batch.pixel_offsets[w + 1]
+        assert_grads_close(g_rho[a:b], g_ego[w], ob["drho"].ravel(), ob["dtheta"],
+                           what=f"c3[{w}] {tuning}")
+
+
+def test_c6_batch_full_size(cm):
+    """All 64 c6 windows (10 flow sets, references at the 11 slice edges) at the launch
+    shape the bench times for them (64x32 tiles, 16384 event blocks), each flow set's
+    gradients against the oracle."""
+    wins = eventgen.make_batch("c6", 64)
+    descs = [cm.WindowDesc.from_window(w) for w in wins]
+    batch = cm.Batch(descs, [w.n for w in wins], graph=True,
+                     tuning=dict(event_blocks=16384, tile_threads=512, tile_w=64, tile_h=32))
+    d = pack(wins)
+    print(f"[gpu] c6 batch {batch.event_offsets[-1]} events, {batch.set_offsets[-1]} sets",
+          flush=True)
+    loss, state = batch.forward(d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"])
+    g_rho, g_ego = batch.backward(d["x"], d["y"], d["t"], d["p"], d["rho"], d["ego"], state,
+                                  torch.ones(batch.n, device="cuda:0"))
+    torch.cuda.synchronize()
+    loss = loss.double().cpu().numpy()
+    g_rho = g_rho.double().cpu().numpy()
+    g_ego = g_ego.double().cpu().numpy()
+    with cf.ThreadPoolExecutor(8) as ex:
+        ref = list(ex.map(lambda w: (oracle.forward(w), oracle.backward(w)), wins))
+    for w, (win, (o, ob)) in enumerate(zip(wins, ref)):
+        assert_loss_close(loss[w], o["loss"], what=f"c6[{w}]")
+        F = win.rho.shape[0]
+        pr = g_rho[batch.pixel_offsets[w]:batch.pixel_offsets[w + 1]].reshape(F, win.height,
+                                                                               win.width)
+        pe = g_ego[6 * batch.set_offsets[w]:6 * batch.set_offsets[w + 1]].reshape(F, 6)
+        for f in range(F):
+            assert_grads_close(pr[f], pe[f], ob["drho"][f], ob["dtheta"][f],
+                               what=f"c6[{w}] set {f}")
+
+
 @pytest.mark.parametrize("case", ["c1", "edges_R3"])
 def test_reused_state_zero_flow_reads_no_stale_pixels(cm, case):
     """The tiled splat stores only the image pixels some tap reached.  With
