@@ -100,6 +100,48 @@ def test_batch_of_many_bins_matches_oracle(cm):
                            what=wins[w].name)
 
 
+def _masked(win):
+    """Every event's time outside [0, 1]: every event masked (Sec. 3.1's validity)."""
+    return win.replace(t=np.full(win.n, 2.0, np.float32))
+
+
+@pytest.mark.parametrize("refs", [[0.0, 1.0], [0.0, 0.5, 1.0]], ids=["at_events", "three_refs"])
+def test_batch_with_masked_windows(cm, refs):
+    """Windows whose events are all masked, in a batch with ordinary ones (their bins
+    stay empty and no source record names them) and in a batch of nothing else (no
+    occupied bin at all: the splat's list and the backward's are empty).  A masked
+    window has loss 0 and zero gradients, as in the oracle; the others match the
+    oracle.  Both backward paths: sampled at the events (refs {0, 1}) and binned."""
+    mk = lambda i, n: eventgen.edge_window(700 + i, "346x260", n, refs=refs, n_segments=30,
+                                           name=f"k{i}")
+    wins = [mk(0, 20000), _masked(mk(1, 8000)), mk(2, 5000), mk(3, 1), _masked(mk(4, 300))]
+    fwd, bwd = {}, {}
+    for group in (wins, [_masked(mk(5, 4000)), _masked(mk(6, 1)), _masked(mk(7, 9000))]):
+        for graph in (False, True):
+            batch = make_batch(cm, group, graph=graph)
+            print(f"[gpu] masked windows: {batch.n} windows, refs {refs}, graph {graph}",
+                  flush=True)
+            d = pack(group)
+            for _ in range(2 if graph else 1):     # (a replay after the capture)
+                loss, g_rho, g_ego, diag = run_batch(cm, batch, d)
+            for w, win in enumerate(group):
+                a, b = batch.pixel_offsets[w], batch.pixel_offsets[w + 1]
+                if win.name not in fwd:
+                    fwd[win.name] = oracle.forward(win, valid=True)
+                o = fwd[win.name]
+                if not o["valid"].any():
+                    assert loss[w] == 0.0 and diag[w][1] == 0, win.name
+                    assert not g_rho[a:b].any() and not g_ego[w].any(), win.name
+                    continue
+                assert_loss_close(loss[w], o["loss"], what=win.name)
+                assert diag[w][1] == int(o["valid"].sum())
+                if win.name not in bwd:
+                    bwd[win.name] = oracle.backward(win)
+                ob = bwd[win.name]
+                assert_grads_close(g_rho[a:b], g_ego[w], ob["drho"].ravel(), ob["dtheta"],
+                                   what=win.name)
+
+
 def test_batch_equals_single_window_calls(cm):
     wins = mixed_windows()
     batch = make_batch(cm, wins)
