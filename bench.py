@@ -51,7 +51,7 @@ def kernel_source_sha() -> str:
 
 # Bytes of splat state per pixel and reference that the measurement plan
 # counts as algorithmic: C and S of both polarities at FP32 (2 x 2 x 4 B).
-# This build keeps the images in FP64 (32 B per pixel and reference, for the
+# The library keeps the images in FP64 (32 B per pixel and reference, for the
 # precision of the adjoint seeds); the FP64 figure is reported beside it,
 # labelled, and is not the roofline fraction.
 STATE_BYTES_PLAN = 16.0
@@ -111,7 +111,7 @@ def roofline_of(phases: dict, steps: int, wins, active, tiled: bool, workload: s
                            "achieved": a32 / (dom_ms * 1e-3) / 1e9,
                            "frac": a32 / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                            "note": "the same kernel with the state at the 32 B per pixel and "
-                                   "reference this build stores (FP64 images); not the "
+                                   "reference the library stores (FP64 images); not the "
                                    "roofline fraction"}}, per_launch
 
 
@@ -179,8 +179,8 @@ def host_cpu() -> dict:
     return {"nproc": os.cpu_count(), "cpu_model": model}
 
 
-# Host cores a one-GPU job is given on the GPU machines (their CPU share per
-# GPU); os.cpu_count() there reports the whole machine.
+# Host cores a one-GPU job is given on the MI355X hosts this is measured on
+# (their CPU share per GPU); os.cpu_count() there reports the whole machine.
 HOST_CORES_PER_GPU = 16
 
 

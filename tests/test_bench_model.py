@@ -14,7 +14,7 @@ def _win(n, W, H, R, F=1):
 
 def test_splat_bytes_follow_the_plan_at_active_pixels():
     # tiled splat: 16 B of state (C, S of both polarities at FP32) per active
-    # pixel and reference; the FP64 images of this build are twice that
+    # pixel and reference; the library's FP64 images are twice that
     assert bench.algorithmic_bytes("splat", 1000, 100, 2, True, 1, 37.0) == 16.0 * 37
     assert bench.algorithmic_bytes("splat", 1000, 100, 2, True, 1, 37.0,
                                    bench.STATE_BYTES_FP64) == 32.0 * 37
